@@ -1,0 +1,504 @@
+"""Pins of the FP64 oracle against facts the paper and mathematics fix.
+
+None of these tests re-types the oracle's own formulas: each compares the
+oracle against a closed form, an invariant, a special case, a brute-force
+minimisation or a published reference sequence (see the table of pins in
+the design notes).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1206_6409_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# independent dense helpers (numpy), used only as yardsticks
+# --------------------------------------------------------------------------
+
+def dense_objective(A, y, kind, lam, w):
+    t = A @ w
+    if kind == O.SQUARED:
+        L = 0.5 * (y - t) ** 2
+    else:
+        L = np.logaddexp(0.0, -y * t)
+    return L.mean() + lam * np.abs(w).sum()
+
+
+def dense_smooth(A, y, kind, w):
+    t = A @ w
+    if kind == O.SQUARED:
+        return (0.5 * (y - t) ** 2).mean()
+    return np.logaddexp(0.0, -y * t).mean()
+
+
+def soft(x, tau):
+    return math.copysign(max(abs(x) - tau, 0.0), x) if x != 0 else 0.0
+
+
+def small_problem(n, k, kind, seed, density=0.6):
+    P = synth.dense_small(n, k, kind, seed, density=density)
+    X = O.Matrix.of(P)
+    return P, X, X.dense(), P.y.astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# selection machinery
+# --------------------------------------------------------------------------
+
+def test_splitmix64_reference_sequence():
+    """The mixing function reproduces the published SplitMix64 outputs."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 6
+    for seed, idx, out in rows:
+        state = (int(seed) + int(idx) * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+        assert O.mix64(state) == int(out, 16)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 17, 64, 1000, 4097])
+def test_epoch_permutation_is_a_bijection(m):
+    seen = set()
+    for e in range(3):
+        p = O.perm(m, 12345, e)
+        assert sorted(p.tolist()) == list(range(m))
+        seen.add(tuple(p.tolist()))
+    if m >= 5:
+        assert len(seen) == 3  # epochs reshuffle
+
+
+def test_permutation_windows_look_uniform():
+    # each position's image should be spread over the range (chi-square-ish)
+    m, reps = 97, 400
+    counts = np.zeros((m, m))
+    for e in range(reps):
+        p = O.perm(m, 7, e)
+        counts[np.arange(m), p] += 1
+    first = counts[0]
+    assert first.max() < 20 and (first > 0).sum() > 80
+
+
+# --------------------------------------------------------------------------
+# Eq. 4 / Eq. 7 / Eq. 9
+# --------------------------------------------------------------------------
+
+def test_P1_clip_step_equals_soft_threshold():
+    """-psi(w; (g-l)/c, (g+l)/c) == s_{l/c}(w - g/c) - w (section 3.1)."""
+    rng = np.random.default_rng(0)
+    cases = []
+    for _ in range(3000):
+        cases.append((rng.normal() * 3, rng.uniform(0.01, 4), rng.normal() * 2, rng.uniform(0, 2)))
+    # exactly on the clip boundaries and at zero
+    for c in (0.5, 1.0, 2.0):
+        for lam in (0.0, 0.3):
+            for g in (-1.0, 0.0, 0.7):
+                a, b = (g - lam) / c, (g + lam) / c
+                for w in (a, b, 0.0, a - 1e-9, b + 1e-9):
+                    cases.append((g, c, w, lam))
+    for g, c, w, lam in cases:
+        d, _ = O.propose(g, c, w, lam)
+        ref = soft(w - g / c, lam / c) - w
+        assert d == pytest.approx(ref, abs=1e-12, rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_P2_squared_loss_step_is_exact_coordinate_minimiser(seed):
+    """For squared loss the step of Eq. 4 minimises Eq. 2 exactly: compare with
+    a golden-section search on the true 1-D objective."""
+    P, X, A, y = small_problem(40, 6, O.SQUARED, seed)
+    rng = np.random.default_rng(seed)
+    w = rng.normal(size=6) * (rng.random(6) < 0.5)
+    z = A @ w
+    lam = 0.05
+    for j in range(6):
+        res = O.step(X, y, O.SQUARED, lam, [j], w.copy(), z.copy())
+        d = res.delta[0]
+
+        def f(t):
+            w2 = w.copy()
+            w2[j] += t
+            return dense_objective(A, y, O.SQUARED, lam, w2)
+
+        lo, hi = d - 5.0, d + 5.0
+        gr = (math.sqrt(5) - 1) / 2
+        for _ in range(200):
+            m1, m2 = hi - gr * (hi - lo), lo + gr * (hi - lo)
+            if f(m1) < f(m2):
+                hi = m2
+            else:
+                lo = m1
+        t_star = 0.5 * (lo + hi)
+        assert d == pytest.approx(t_star, abs=1e-7)
+        assert f(d) <= f(t_star) + 1e-13
+
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_P4_proxy_is_the_bound_decrease(kind):
+    """phi (Eq. 9) equals F~(w + d e_j) - F~(w) built from Eq. 5 with the
+    gradient of the smooth part, is <= 0, and vanishes iff d = 0."""
+    P, X, A, y = small_problem(50, 8, kind, 11)
+    rng = np.random.default_rng(5)
+    w = rng.normal(size=8) * (rng.random(8) < 0.5)
+    lam = 0.02
+    c = (0.25 if kind == O.LOGISTIC else 1.0) * (A ** 2).sum(0) / A.shape[0]
+    # gradient of the smooth part by central differences (independent of the oracle)
+    h = 1e-6
+    for j in range(8):
+        e = np.zeros(8)
+        e[j] = h
+        gfd = (dense_smooth(A, y, kind, w + e) - dense_smooth(A, y, kind, w - e)) / (2 * h)
+        res = O.step(X, y, kind, lam, [j], w.copy(), A @ w)
+        assert res.g[0] == pytest.approx(gfd, abs=1e-7)
+        d, phi = res.delta[0], res.phi[0]
+        g = res.g[0]
+        bound_change = (g * d + 0.5 * c[j] * d * d) + lam * (abs(w[j] + d) - abs(w[j]))
+        assert phi == pytest.approx(bound_change, abs=1e-14)
+        assert phi <= 1e-15
+        assert (phi == 0.0) == (d == 0.0)
+        # the bound is an upper bound (Eq. 6): true change <= phi
+        w2 = w.copy()
+        w2[j] += d
+        true_change = dense_objective(A, y, kind, lam, w2) - dense_objective(A, y, kind, lam, w)
+        assert true_change <= phi + 1e-12
+
+
+# --------------------------------------------------------------------------
+# monotone decrease (Eq. 6) and reductions between rules (Table 2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_P3_ccd_never_increases_objective(kind):
+    P, X, A, y = small_problem(60, 12, kind, 21, density=0.4)
+    lam = 0.01
+    w, z = np.zeros(12), np.zeros(60)
+    prev = dense_objective(A, y, kind, lam, w)
+    for sweep in range(20):
+        for j in range(12):
+            O.step(X, y, kind, lam, [j], w, z)
+            cur = dense_objective(A, y, kind, lam, w)
+            assert cur <= prev * (1 + 1e-15) + 1e-15
+            prev = cur
+
+
+def test_P12_reductions_between_rules():
+    P, X, A, y = small_problem(80, 20, O.LOGISTIC, 31, density=0.3)
+    lam = 0.005
+    rng = np.random.default_rng(3)
+    w0 = rng.normal(size=20) * (rng.random(20) < 0.4)
+    J = rng.permutation(20)[:12].astype(np.int32)
+    # Thread-Greedy with B = 1 accepts everything, like Shotgun
+    w1, z1 = w0.copy(), A @ w0
+    w2, z2 = w0.copy(), A @ w0
+    O.step(X, y, O.LOGISTIC, lam, J, w1, z1, block=0)
+    O.step(X, y, O.LOGISTIC, lam, J, w2, z2, block=1)
+    assert np.array_equal(w1, w2) and np.array_equal(z1, z2)
+    # Thread-Greedy with B = |J| is Greedy on J: exactly the best single proposal
+    w3, z3 = w0.copy(), A @ w0
+    res = O.step(X, y, O.LOGISTIC, lam, J, w3, z3, block=J.size)
+    best = int(np.argmin(res.phi))
+    assert res.accepted.sum() == 1 and res.accepted[best] == 1
+    changed = np.nonzero(w3 != w0)[0]
+    assert set(changed.tolist()) <= {int(J[best])}
+    # Shotgun with |J| = 1 is a single coordinate step (SCD / CCD)
+    w4, z4 = w0.copy(), A @ w0
+    O.step(X, y, O.LOGISTIC, lam, J[:1], w4, z4)
+    w5, z5 = w0.copy(), A @ w0
+    O.step(X, y, O.LOGISTIC, lam, J[:1], w5, z5, block=1)
+    assert np.array_equal(w4, w5)
+
+
+def test_P11_colour_class_step_equals_sequential_ccd():
+    """Columns with disjoint rows: one Jacobi step over the class equals
+    updating them one after another, in any order (section 4.1)."""
+    P = synth.orthogonal_design(90, 15, O.LOGISTIC, 4)
+    X = O.Matrix.of(P)
+    A, y = X.dense(), P.y.astype(np.float64)
+    lam = 0.003
+    rng = np.random.default_rng(1)
+    w0 = rng.normal(size=15) * 0.3
+    J = np.arange(15, dtype=np.int32)
+    wa, za = w0.copy(), A @ w0
+    O.step(X, y, O.LOGISTIC, lam, J, wa, za)
+    for order in (J, J[::-1], rng.permutation(J)):
+        wb, zb = w0.copy(), A @ w0
+        for j in order:
+            O.step(X, y, O.LOGISTIC, lam, [j], wb, zb)
+        np.testing.assert_allclose(wb, wa, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(zb, za, rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# closed forms and special cases of the optimum
+# --------------------------------------------------------------------------
+
+def test_P6_orthogonal_design_lasso_closed_form():
+    """Disjoint columns decouple Eq. 1: w_j = S_lam(X_j^T y / n) / (||X_j||^2/n)."""
+    P = synth.orthogonal_design(200, 30, O.SQUARED, 9)
+    X = O.Matrix.of(P)
+    A, y = X.dense(), P.y.astype(np.float64)
+    n = A.shape[0]
+    lam = 0.05
+    expect = np.array([soft(A[:, j] @ y / n, lam) / ((A[:, j] ** 2).sum() / n) for j in range(30)])
+    r = O.solve(X, y, O.SQUARED, lam, O.CYCLIC, tol=1e-12, max_epochs=1)
+    np.testing.assert_allclose(r.w, expect, rtol=1e-13, atol=1e-15)
+    r2 = O.solve(X, y, O.SQUARED, lam, O.SHOTGUN, select_size=30, seed=3, tol=1e-12, max_epochs=1)
+    np.testing.assert_allclose(r2.w, expect, rtol=1e-13, atol=1e-15)
+    colors = np.zeros(30, dtype=np.int32)
+    r3 = O.solve(X, y, O.SQUARED, lam, O.COLORING, colors=colors, seed=3, tol=1e-12, max_epochs=1)
+    np.testing.assert_allclose(r3.w, expect, rtol=1e-13, atol=1e-15)
+    assert r.converged and r2.converged and r3.converged
+
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_P5_lambda_max_gives_zero_solution(kind):
+    P, X, A, y = small_problem(70, 25, kind, 41, density=0.3)
+    n = A.shape[0]
+    lm = O.lambda_max(X, y, kind)
+    # at w = 0 the only nonzero KKT violations are |g_j| - lam
+    r = O.solve(X, y, kind, lm * 1.0000001, O.CYCLIC, tol=1e-12, max_epochs=5)
+    assert np.all(r.w == 0.0) and r.converged
+    r2 = O.solve(X, y, kind, lm * 0.9, O.CYCLIC, tol=1e-10, max_epochs=5000)
+    assert np.count_nonzero(r2.w) >= 1
+    # lambda_max is attained: the column with the largest |gradient at 0|
+    d0 = (y * -1.0) if kind == O.SQUARED else (-y * 0.5)
+    g0 = np.abs(A.T @ d0) / n
+    assert lm == pytest.approx(g0.max(), rel=1e-13)
+
+
+def dense_kkt(A, y, kind, lam, w):
+    n = A.shape[0]
+    t = A @ w
+    if kind == O.SQUARED:
+        d = t - y
+    else:
+        d = -y / (1.0 + np.exp(y * t))
+    g = A.T @ d / n
+    v = np.where(w != 0, np.abs(g + lam * np.sign(w)), np.maximum(np.abs(g) - lam, 0))
+    return v.max()
+
+
+@pytest.mark.parametrize("rule", [O.CYCLIC, O.STOCHASTIC, O.SHOTGUN, O.THREAD_GREEDY, O.GREEDY])
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_P7_final_point_satisfies_kkt(rule, kind):
+    P, X, A, y = small_problem(120, 40, kind, 51, density=0.2)
+    lam = 0.2 * O.lambda_max(X, y, kind)
+    r = O.solve(X, y, kind, lam, rule, select_size=8, block=4, seed=5, tol=1e-8,
+                max_epochs=200000, check_every=1 if rule != O.GREEDY else 20)
+    assert r.converged
+    assert dense_kkt(A, y, kind, lam, r.w) <= 1e-8 * 1.01
+    assert r.objective == pytest.approx(dense_objective(A, y, kind, lam, r.w), rel=1e-13)
+
+
+def _newton_reduced(A, y, kind, lam, s, iters=100):
+    """Minimise the smooth reduced objective F(w_A) + lam s^T w_A."""
+    n, m = A.shape
+    if kind == O.SQUARED:
+        G = A.T @ A / n
+        try:
+            return np.linalg.solve(G, (A.T @ y / n) - lam * s)
+        except np.linalg.LinAlgError:
+            return None
+    w = np.zeros(m)
+
+    def f(w):
+        return np.logaddexp(0, -y * (A @ w)).mean() + lam * s @ w
+
+    for _ in range(iters):
+        t = A @ w
+        p = 1.0 / (1.0 + np.exp(y * t))
+        grad = A.T @ (-y * p) / n + lam * s
+        H = (A * (p * (1 - p))[:, None]).T @ A / n + 1e-14 * np.eye(m)
+        try:
+            step = np.linalg.solve(H, grad)
+        except np.linalg.LinAlgError:
+            return None
+        a = 1.0
+        f0 = f(w)
+        while f(w - a * step) > f0 - 1e-4 * a * grad @ step and a > 1e-12:
+            a *= 0.5
+        w = w - a * step
+        if np.abs(grad).max() < 1e-14 or np.abs(w).max() > 1e6:
+            break
+    return w if np.abs(w).max() < 1e6 else None
+
+
+@pytest.mark.parametrize("kind,seed", [(O.SQUARED, 61), (O.SQUARED, 62), (O.LOGISTIC, 63), (O.LOGISTIC, 64)])
+def test_P8_brute_force_optimum_small_k(kind, seed):
+    """Enumerate all 3^k sign patterns (k = 6); each self-consistent pattern
+    gives a feasible point; the minimum over them is the optimum of Eq. 1."""
+    import itertools
+    k = 6
+    P, X, A, y = small_problem(30, k, kind, seed, density=0.7)
+    lam = 0.15 * O.lambda_max(X, y, kind)
+    best = dense_objective(A, y, kind, lam, np.zeros(k))
+    for s in itertools.product((-1, 0, 1), repeat=k):
+        s = np.array(s, dtype=float)
+        act = np.nonzero(s)[0]
+        if act.size == 0:
+            continue
+        wa = _newton_reduced(A[:, act], y, kind, lam, s[act])
+        if wa is None or np.any(np.sign(wa) != s[act]):
+            continue
+        w = np.zeros(k)
+        w[act] = wa
+        best = min(best, dense_objective(A, y, kind, lam, w))
+    r = O.solve(X, y, kind, lam, O.CYCLIC, tol=1e-12, max_epochs=200000)
+    assert r.converged
+    assert r.objective == pytest.approx(best, rel=1e-10, abs=1e-12)
+
+
+def test_P13_single_feature_logistic_by_bisection():
+    P, X, A, y = small_problem(200, 1, O.LOGISTIC, 71, density=0.8)
+    lam = 0.3 * O.lambda_max(X, y, O.LOGISTIC)
+    a = A[:, 0]
+    n = a.size
+
+    def dF(t):
+        return (a * (-y / (1.0 + np.exp(y * a * t)))).sum() / n
+
+    # optimum w* > 0 or < 0 solves dF(w) + lam*sign(w) = 0
+    sgn = -np.sign(dF(0.0))
+    lo, hi = (0.0, 100.0) if sgn > 0 else (-100.0, 0.0)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        val = dF(mid) + lam * sgn
+        if (val > 0) == (sgn > 0):
+            hi = mid
+        else:
+            lo = mid
+    wstar = 0.5 * (lo + hi)
+    r = O.solve(X, y, O.LOGISTIC, lam, O.CYCLIC, tol=1e-13, max_epochs=100000)
+    assert r.w[0] == pytest.approx(wstar, rel=1e-9)
+
+
+def test_objective_is_unique_across_rules():
+    """z* and the optimal value are unique (strict convexity in t): all rules
+    agree on them even with k > n."""
+    P = synth.c1_ccd_logistic(scale=0.2)
+    X = O.Matrix.of(P)
+    y = P.y.astype(np.float64)
+    lam = 0.1 * O.lambda_max(X, y, P.loss)
+    res = [O.solve(X, y, P.loss, lam, O.CYCLIC, tol=1e-10, max_epochs=100000)]
+    res.append(O.solve(X, y, P.loss, lam, O.SHOTGUN, select_size=16, seed=2, tol=1e-10, max_epochs=100000))
+    res.append(O.solve(X, y, P.loss, lam, O.THREAD_GREEDY, select_size=64, block=8, seed=2, tol=1e-10,
+                       max_epochs=100000))
+    for r in res:
+        assert r.converged
+    for r in res[1:]:
+        assert r.objective == pytest.approx(res[0].objective, rel=1e-9)
+        np.testing.assert_allclose(r.z, res[0].z, atol=1e-5)
+
+
+# --------------------------------------------------------------------------
+# colouring (section 4.1, partial distance-2 colouring)
+# --------------------------------------------------------------------------
+
+def check_colouring(n, k, col_ptr, row_idx, color, order):
+    rows_of = [set(row_idx[col_ptr[j]:col_ptr[j + 1]].tolist()) for j in range(k)]
+    # valid: no two columns of one colour share a row
+    for i in range(n):
+        pass
+    by_row = {}
+    for j in range(k):
+        for i in rows_of[j]:
+            by_row.setdefault(i, []).append(j)
+    for i, cols in by_row.items():
+        cs = [color[j] for j in cols]
+        assert len(cs) == len(set(cs)), f"row {i} has a repeated colour"
+    # greedy: colour = mex over earlier neighbours in the visit order
+    pos = np.empty(k, dtype=np.int64)
+    pos[order] = np.arange(k)
+    for j in range(k):
+        earlier = set()
+        for i in rows_of[j]:
+            for j2 in by_row[i]:
+                if pos[j2] < pos[j]:
+                    earlier.add(color[j2])
+        mex = 0
+        while mex in earlier:
+            mex += 1
+        assert color[j] == mex
+
+
+def _pattern(n, k, pairs):
+    rows = np.array([p[0] for p in pairs], dtype=np.int64)
+    cols = np.array([p[1] for p in pairs], dtype=np.int64)
+    cp, ri, _ = synth.coo_to_csc(n, k, rows, cols, np.ones(len(pairs), np.float32))
+    return cp, ri
+
+
+def test_P10_colouring_random_matrix():
+    P = synth.c3_zipf_lasso(scale=0.002)
+    color, nc, order = O.color(P.n, P.k, P.col_ptr, P.row_idx)
+    check_colouring(P.n, P.k, P.col_ptr, P.row_idx, color, order)
+    nnz = np.diff(P.col_ptr)
+    # visit order: decreasing nnz, ties by index
+    assert all((nnz[a] > nnz[b]) or (nnz[a] == nnz[b] and a < b) for a, b in zip(order[:-1], order[1:]))
+    assert nc == color.max() + 1
+
+
+def test_P10_colouring_adversarial_graphs():
+    # clique: one row holding every column -> all colours distinct
+    cp, ri = _pattern(1, 6, [(0, j) for j in range(6)])
+    c, nc, o = O.color(1, 6, cp, ri)
+    assert nc == 6 and sorted(c.tolist()) == list(range(6))
+    # star: column 0 shares a row with each other column, which are independent
+    pairs = [(i, 0) for i in range(5)] + [(i, i + 1) for i in range(5)]
+    cp, ri = _pattern(5, 6, pairs)
+    c, nc, o = O.color(5, 6, cp, ri)
+    assert c[0] == 0 and np.all(c[1:] == 1) and nc == 2
+    # empty columns take colour 0
+    cp, ri = _pattern(3, 5, [(0, 1), (1, 1), (1, 3)])
+    c, nc, o = O.color(3, 5, cp, ri)
+    assert c[0] == 0 and c[2] == 0 and c[4] == 0 and c[1] != c[3]
+    check_colouring(3, 5, cp, ri, c, o)
+    # natural order option
+    P = synth.c1_ccd_logistic(scale=0.05)
+    c, nc, o = O.color(P.n, P.k, P.col_ptr, P.row_idx, order_mode=1)
+    assert np.array_equal(o, np.arange(P.k))
+    check_colouring(P.n, P.k, P.col_ptr, P.row_idx, c, o)
+
+
+def test_coloring_solve_matches_ccd_optimum():
+    P = synth.c3_zipf_lasso(scale=0.002)
+    X = O.Matrix.of(P)
+    y = P.y.astype(np.float64)
+    lam = 0.1 * O.lambda_max(X, y, P.loss)
+    color, nc, _ = O.color(P.n, P.k, P.col_ptr, P.row_idx)
+    a = O.solve(X, y, P.loss, lam, O.COLORING, colors=color, seed=1, tol=1e-9, max_epochs=100000)
+    b = O.solve(X, y, P.loss, lam, O.CYCLIC, tol=1e-9, max_epochs=100000)
+    assert a.converged and b.converged
+    assert a.objective == pytest.approx(b.objective, rel=1e-9)
+
+
+def test_thread_greedy_ties_go_to_the_first_position():
+    """Exact ties (duplicate columns give identical phi) are resolved towards
+    the lowest position of the block (the reading of "best" for equal
+    proxies)."""
+    n = 40
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal(n)
+    b = rng.standard_normal(n)
+    rows = np.concatenate([np.arange(n)] * 4)
+    cols = np.repeat([0, 1, 2, 3], n)
+    vals = np.concatenate([a, a, a, a]).astype(np.float32)
+    cp, ri, va = synth.coo_to_csc(n, 4, rows, cols, vals)
+    X = O.Matrix(n, 4, cp, ri, va)
+    y = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    for J in ([0, 2, 1, 3], [0, 3, 2, 1], [0, 1, 3, 2]):
+        w, z = np.zeros(4), np.zeros(n)
+        res = O.step(X, y, O.LOGISTIC, 1e-4, J, w, z, block=4)
+        tied = [t for t in range(4) if res.phi[t] == res.phi.min()]
+        assert len(tied) == 4 and res.phi.min() < 0
+        assert res.accepted[tied[0]] == 1 and res.accepted.sum() == 1
+        w2, z2 = np.zeros(4), np.zeros(n)
+        res2 = O.step(X, y, O.LOGISTIC, 1e-4, J, w2, z2, block=2)
+        for blk in range(2):
+            ph = res2.phi[2 * blk:2 * blk + 2]
+            first = 2 * blk + int(np.argmin(ph))
+            assert res2.accepted[first] == 1
