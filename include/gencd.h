@@ -1,0 +1,182 @@
+/*
+ * gencd.h — C ABI of the GenCD Propose/Update library for MI355X (gfx950).
+ *
+ * The library solves the l1-regularised loss minimisation problem of Eq. (1)
+ * of Scherrer, Halappanavar, Tewari & Haglin, "Scaling Up Coordinate Descent
+ * Algorithms for Large l1 Regularization Problems":
+ *
+ *     min_w  (1/n) sum_i loss(y_i, (Xw)_i) + lambda ||w||_1
+ *
+ * with the squared loss 1/2 (y-t)^2 or the logistic loss log(1+exp(-yt))
+ * (section 1), by the generic coordinate-descent loop of Algorithm 1
+ * (Select, Propose, Accept, Update) under the rules of Table 2.
+ *
+ * Conventions for every call
+ *   - Pointers documented "device" point to memory on the current HIP
+ *     device; "host" pointers to ordinary host memory.  The caller allocates
+ *     and owns every buffer, including the workspace; the library never
+ *     allocates or frees device memory and keeps no pointer after a call
+ *     returns (the server keeps its arena until gencd_server_destroy).
+ *   - All device work is enqueued on the given stream.  Calls that return
+ *     results to the host (statistics, lambda_max) synchronise that stream.
+ *   - Every call returns a gencd_status.  Arguments are validated on the host
+ *     before any device work; on an error no output has been modified unless
+ *     stated.  Nothing crosses the ABI as a C++ exception.
+ *   - Calls on different streams with disjoint workspaces are independent.
+ *     The library has no global mutable state.
+ *
+ * Matrix X (n x k) is CSC: col_ptr int64[k+1] (col_ptr[0] = 0,
+ * non-decreasing, col_ptr[k] = nnz), row_idx int32[nnz] (sorted and unique
+ * within a column, each in [0, n)), val float32[nnz].  All three are device
+ * pointers.  Labels y are float32[n] (device); the logistic loss needs
+ * y_i in {-1, +1}.
+ */
+#ifndef GENCD_H
+#define GENCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GENCD_OK = 0,
+  GENCD_NOT_CONVERGED = 1,        /* warning: outputs valid, stats filled */
+  GENCD_ERR_INVALID_ARG = -1,     /* null pointer, bad size or scalar */
+  GENCD_ERR_BAD_MATRIX = -2,      /* CSC structure invalid (device check) */
+  GENCD_ERR_BAD_LABELS = -3,      /* logistic labels not in {-1, +1} */
+  GENCD_ERR_WORKSPACE = -4,       /* workspace null or too small */
+  GENCD_ERR_UNSUPPORTED = -5,     /* option combination not implemented */
+  GENCD_ERR_DIVERGED = -6,        /* non-finite objective at a check */
+  GENCD_ERR_HIP = -7,             /* a HIP runtime call failed */
+  GENCD_ERR_BUDGET = -8           /* server: request larger than the arena */
+} gencd_status;
+
+typedef enum { GENCD_SQUARED = 0, GENCD_LOGISTIC = 1 } gencd_loss;
+
+/* Selection / acceptance rules of Table 2 (plus the sequential special cases
+ * of section 2.1). */
+typedef enum {
+  GENCD_CYCLIC = 0,        /* J = {one column}, columns in index order */
+  GENCD_STOCHASTIC = 1,    /* J = {one random column} (Shotgun with |J| = 1) */
+  GENCD_SHOTGUN = 2,       /* random |J| columns, accept all */
+  GENCD_THREAD_GREEDY = 3, /* random |J| columns, best proposal per block of B */
+  GENCD_GREEDY = 4,        /* all columns, single best proposal */
+  GENCD_COLORING = 5       /* one colour class per iteration, accept all */
+} gencd_rule;
+
+/* flags */
+#define GENCD_WARM_START 0x1u      /* w holds the starting point on entry */
+#define GENCD_VALIDATE_DEVICE 0x2u /* check CSC structure and labels on the device */
+#define GENCD_USE_GRAPH 0x4u       /* replay each epoch as a captured HIP graph */
+
+/* Device CSC matrix (see the conventions above). */
+typedef struct {
+  int64_t n, k, nnz;
+  const int64_t *col_ptr;
+  const int32_t *row_idx;
+  const float *val;
+} gencd_csc;
+
+typedef struct {
+  int32_t loss;          /* gencd_loss */
+  int32_t rule;          /* gencd_rule */
+  double lambda;         /* lambda >= 0 of Eq. (1) */
+  int64_t select_size;   /* |J| (Shotgun, Thread-Greedy) */
+  int64_t block;         /* B, proposals per accepting block (Thread-Greedy) */
+  uint64_t seed;         /* seed of the per-epoch selection permutation */
+  double kkt_tol;        /* stop when max_j KKT violation <= kkt_tol ... */
+  double gap_tol;        /* ... and duality gap <= gap_tol * |objective| (0: off) */
+  int64_t max_epochs;    /* epoch = one pass of Select over the live columns */
+  int64_t check_every;   /* epochs between FP64 convergence checks (>= 1) */
+  uint32_t flags;        /* GENCD_* flags */
+  const int32_t *color;  /* COLORING: device int32[k] colours (gencd_color) */
+  int32_t num_colors;    /* COLORING: number of colours */
+  int32_t piece;         /* nnz per work piece; 0 = library default */
+  int32_t group;         /* lanes per piece (8, 16, 32 or 64); 0 = default */
+} gencd_params;
+
+/* Host-side statistics filled by the solve calls. */
+typedef struct {
+  int64_t iters;          /* GenCD iterations (Algorithm 1 loop trips) */
+  int64_t epochs;
+  int64_t coord_updates;  /* accepted proposals */
+  int64_t nnz_visits;     /* sum over proposals of nnz_j (Propose work) */
+  int64_t nnz_updates;    /* sum over accepted proposals of nnz_j */
+  double objective;       /* Eq. (1) at the last check, FP64 from z = Xw */
+  double kkt_max;         /* max_j KKT violation at the last check */
+  double gap;             /* duality gap P(w) - D(u) at the last check (FP64) */
+  double lambda_max;      /* ||X^T l'(y, 0)||_inf / n */
+  double seconds;         /* wall time of the call */
+  int64_t nnz_w;          /* nonzeros of w at the last check */
+  int32_t converged;
+  int32_t num_colors;
+} gencd_stats;
+
+const char *gencd_status_string(int status);
+
+/* Workspace bytes needed by gencd_solve / gencd_step / gencd_check /
+ * gencd_lambda_max for this matrix shape and these parameters.  Host only. */
+int gencd_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out_bytes);
+
+/* lambda_max = max_j |X_j^T l'(y, 0)| / n in FP64: the smallest lambda at
+ * which w = 0 satisfies the optimality conditions of Eq. (1).  *out is host. */
+int gencd_lambda_max(const gencd_csc *X, const float *y, int32_t loss, double *out, void *ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/* Solve Eq. (1) by Algorithm 1 with the rule of p->rule.
+ *   w: device float32[k]; read as the starting point when GENCD_WARM_START
+ *      is set (else zero-initialised), holds the solution on return.
+ *   z: device float32[n] or NULL; receives Xw (FP32 rounding of the FP64
+ *      product) on return.
+ *   stats: host, may be NULL.
+ * Returns GENCD_OK when the FP64 KKT check met kkt_tol, GENCD_NOT_CONVERGED
+ * after max_epochs, GENCD_ERR_DIVERGED on a non-finite objective. */
+int gencd_solve(const gencd_csc *X, const float *y, const gencd_params *p, float *w, float *z,
+                void *ws, size_t ws_bytes, hipStream_t stream, gencd_stats *stats);
+
+/* One iteration of Algorithm 1 on a given selected set, for step-by-step
+ * comparison.  J: device int32[nJ] distinct column indices.  The state is
+ * (w, z_hi + z_lo), all device float32; z_lo may not be NULL.  The
+ * iteration proposes for every j in J from the state at entry (Algorithm 2 /
+ * Algorithm 4), accepts all (block == 0 rules) or the best of each block of
+ * p->block positions (Thread-Greedy), and updates w, z_hi, z_lo
+ * (Algorithm 3).  Optional device outputs of length nJ: g (gradient),
+ * delta, phi, accepted (0/1).  The accept rule follows p->rule. */
+int gencd_step(const gencd_csc *X, const float *y, const gencd_params *p, const int32_t *J,
+               int64_t nJ, float *w, float *z_hi, float *z_lo, float *g, float *delta,
+               float *phi, int32_t *accepted, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* FP64 check of a point w (device float32[k]): z64 = Xw, the gradient
+ * g64 = X^T l'(y, z64) / n, the KKT violations, the objective of Eq. (1),
+ * nnz(w) and the duality gap, all in double precision.  The gap is P(w)
+ * minus the Fenchel dual of Eq. (1) at the scaled residual
+ * u = s l'(y, z64) / n, s = min(1, lambda / |g64|_inf), so that
+ * P(w) - P* <= gap.  z64 (device double[n]) and g64 (device double[k]) are
+ * optional outputs.  Fills stats->objective, kkt_max, gap, nnz_w. */
+int gencd_check(const gencd_csc *X, const float *y, int32_t loss, double lambda, const float *w,
+                double *z64, double *g64, gencd_stats *stats, void *ws, size_t ws_bytes,
+                hipStream_t stream);
+
+/* Position p -> image of the per-epoch selection permutation of m items
+ * (keyed Feistel bijection, section 2.1's random subsets).  out: device
+ * int32[m]. */
+int gencd_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hipStream_t stream);
+
+/* Greedy partial distance-2 colouring of the columns (section 4.1): columns
+ * are visited by decreasing nnz (ties by index) and each takes the smallest
+ * colour not used by an earlier column sharing a row.  color: device
+ * int32[k]; *num_colors: host.  Workspace from gencd_color_workspace_bytes. */
+int gencd_color_workspace_bytes(const gencd_csc *X, size_t *out_bytes);
+int gencd_color(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws,
+                size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENCD_H */

@@ -70,6 +70,8 @@ def lib():
         L.orc_step.argtypes = [P, P, I32, D, P, P, I64, I64, P, P, P, P, P, P, P, P]
         L.orc_check.restype = None
         L.orc_check.argtypes = [P, P, I32, D, P, P, P, P, P, P]
+        L.orc_duality_gap.restype = D
+        L.orc_duality_gap.argtypes = [P, P, I32, D, P, P]
         L.orc_color.restype = I32
         L.orc_color.argtypes = [I64, I64, P, P, I32, P, P, P]
         L.orc_solve.restype = I32
@@ -188,6 +190,15 @@ def check(X: Matrix, y, kind, lam, w):
     lib().orc_check(X.ref, _p(y), kind, float(lam), _p(w), _p(z), _p(g), C.byref(kkt),
                     C.byref(obj), C.byref(nz))
     return Check(z, g, kkt.value, obj.value, nz.value)
+
+
+def duality_gap(X: Matrix, y, kind, lam, w):
+    """(gap, primal) at w: P(w) - D(u) for the scaled-residual dual point."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    prim = C.c_double()
+    gap = lib().orc_duality_gap(X.ref, _p(y), kind, float(lam), _p(w), C.byref(prim))
+    return gap, prim.value
 
 
 def color(n, k, col_ptr, row_idx, order_mode=0):

@@ -310,6 +310,56 @@ void orc_check(const orc_csc *X, const double *y, int loss, double lambda, const
   free(z);
 }
 
+/* Duality gap of Eq. 1 at w (an upper bound on the suboptimality of w).
+ * Fenchel dual of min f(Xw) + lambda |w|_1 with f(z) = (1/n) sum l(y_i, z_i):
+ *   D(u) = -(1/n) sum_i l*(y_i, n u_i)  subject to  |X^T u|_inf <= lambda,
+ * evaluated at the scaled residual u = s l'(y, Xw) / n with
+ * s = min(1, lambda / |X^T l'(y, Xw) / n|_inf).  Conjugates:
+ *   squared:   l*(y, v) = v y + v^2 / 2
+ *   logistic:  l*(y, v) = p log p + (1 - p) log(1 - p),  p = -v y in [0, 1].
+ * Returns P(w) - D(u); *primal receives P(w). */
+double orc_duality_gap(const orc_csc *X, const double *y, int loss, double lambda, const double *w,
+                       double *primal) {
+  int64_t n = X->n;
+  double *z = (double *)calloc((size_t)n, sizeof(double));
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  for (int64_t j = 0; j < X->k; ++j) {
+    if (w[j] == 0.0) continue;
+    for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) z[X->row_idx[p]] += w[j] * X->val[p];
+  }
+  double lsum = 0.0, l1 = 0.0, gmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    lsum += orc_loss(loss, y[i], z[i]);
+    r[i] = orc_dloss(loss, y[i], z[i]);
+  }
+  for (int64_t j = 0; j < X->k; ++j) {
+    double g = 0.0;
+    for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) g += X->val[p] * r[X->row_idx[p]];
+    g = fabs(g) / (double)n;
+    if (g > gmax) gmax = g;
+    l1 += fabs(w[j]);
+  }
+  double s = (gmax > lambda) ? lambda / gmax : 1.0;
+  double dsum = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double v = s * r[i]; /* n u_i */
+    if (loss == ORC_SQUARED) {
+      dsum -= v * y[i] + 0.5 * v * v;
+    } else {
+      double p = -v * y[i];
+      double h = 0.0;
+      if (p > 0.0) h -= p * log(p);
+      if (p < 1.0) h -= (1.0 - p) * log1p(-p);
+      dsum += h;
+    }
+  }
+  double P = lsum / (double)n + lambda * l1;
+  if (primal) *primal = P;
+  free(z);
+  free(r);
+  return P - dsum / (double)n;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Greedy partial distance-2 colouring of the column conflict graph           */
 /* ------------------------------------------------------------------------ */

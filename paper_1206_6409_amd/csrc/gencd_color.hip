@@ -1,0 +1,356 @@
+// Greedy partial distance-2 colouring of the column conflict graph
+// (section 4.1: columns conflict when they share a row), computed on the GPU
+// and identical to the sequential greedy colouring.
+//
+// The sequential greedy visits columns in priority order (decreasing nnz,
+// ties by index) and gives each the smallest colour not used by an earlier
+// column sharing a row.  A column's colour depends only on the colours of its
+// earlier neighbours, so columns can be coloured in rounds (Jones-Plassmann
+// by priority): a column is ready once all its earlier neighbours are
+// coloured.  Readiness is tracked with a counter per column holding the
+// number of (row, earlier column) pairs still uncoloured:
+//   * CSR rows are sorted by column priority, so the earlier neighbours of a
+//     column in a row are the prefix of that row before it; the counter
+//     starts at the sum of these prefix lengths;
+//   * when a column is coloured it decrements, in each of its rows, every
+//     later column of the row; a counter reaching zero puts the column in the
+//     next round's frontier.
+// Each frontier column takes the mex of the colours in its row prefixes.
+#include <hipcub/hipcub.hpp>
+
+#include "gencd_common.hpp"
+#include "gencd_kernels.hpp"
+
+namespace gencd {
+
+constexpr int kMexWords = 8192;  // LDS bitmap: 262144 colours
+
+struct ColorWs {
+  uint64_t *keys_a, *keys_b;  // [max(k, nnz)]
+  int32_t *vals_a, *vals_b;   // [max(k, nnz)]
+  int32_t *order;             // [k] column at each priority rank
+  int32_t *rank;              // [k] priority rank of each column
+  int32_t *row_ptr;           // [n+1]
+  int32_t *rank_at;           // [nnz] CSR slot -> column rank
+  int32_t *pos_in_row;        // [nnz] CSC entry -> position in its CSR row
+  int32_t *count;             // [k]
+  int32_t *front_a, *front_b; // [k]
+  int32_t *fcnt;              // [k+1] frontier nnz counts, then offsets
+  int32_t *foff;              // [k+1]
+  int32_t *scan_part;
+  int32_t *ctl;               // [8] next frontier size, max colour, error flags
+  void *sort_tmp;
+  size_t sort_tmp_bytes;
+};
+
+static size_t sort_temp_bytes(int64_t items, int end_bit) {
+  size_t bytes = 0;
+  hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, static_cast<const uint64_t *>(nullptr),
+                                     static_cast<uint64_t *>(nullptr),
+                                     static_cast<const int32_t *>(nullptr),
+                                     static_cast<int32_t *>(nullptr), int(items), 0, end_bit);
+  return bytes;
+}
+
+static size_t color_layout(int64_t n, int64_t k, int64_t nnz, void *base, ColorWs *w) {
+  const size_t al = 256;
+  size_t off = 0;
+  char *b = static_cast<char *>(base);
+  auto take = [&](size_t bytes) -> void * {
+    off = (off + al - 1) / al * al;
+    void *p = b ? b + off : nullptr;
+    off += bytes > 0 ? bytes : 1;
+    return p;
+  };
+  const int64_t m = k > nnz ? k : nnz;
+  ColorWs c{};
+  c.keys_a = static_cast<uint64_t *>(take(sizeof(uint64_t) * m));
+  c.keys_b = static_cast<uint64_t *>(take(sizeof(uint64_t) * m));
+  c.vals_a = static_cast<int32_t *>(take(sizeof(int32_t) * m));
+  c.vals_b = static_cast<int32_t *>(take(sizeof(int32_t) * m));
+  c.order = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  c.rank = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  c.row_ptr = static_cast<int32_t *>(take(sizeof(int32_t) * (n + 1)));
+  c.rank_at = static_cast<int32_t *>(take(sizeof(int32_t) * nnz));
+  c.pos_in_row = static_cast<int32_t *>(take(sizeof(int32_t) * nnz));
+  c.count = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  c.front_a = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  c.front_b = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  const int64_t mn = m > n ? m : n;
+  c.fcnt = static_cast<int32_t *>(take(sizeof(int32_t) * (mn + 1)));
+  c.foff = static_cast<int32_t *>(take(sizeof(int32_t) * (k + 1)));
+  const int64_t scan_len = mn + 1;
+  c.scan_part = static_cast<int32_t *>(take(sizeof(int32_t) * scan_partials_for(scan_len)));
+  c.ctl = static_cast<int32_t *>(take(sizeof(int32_t) * 8));
+  size_t t1 = sort_temp_bytes(k, 64), t2 = sort_temp_bytes(nnz, 64);
+  c.sort_tmp_bytes = t1 > t2 ? t1 : t2;
+  c.sort_tmp = take(c.sort_tmp_bytes);
+  if (w) *w = c;
+  return off + al;
+}
+
+__global__ __launch_bounds__(kBlock) void k_prio_keys(const int64_t *col_ptr, int64_t k, int64_t n,
+                                                       uint64_t *keys, int32_t *vals) {
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock) {
+    int64_t m = col_ptr[j + 1] - col_ptr[j];
+    keys[j] = (uint64_t(n - m) << 32) | uint64_t(j);
+    vals[j] = int32_t(j);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_of(const int32_t *order, int64_t k, int32_t *rank) {
+  for (int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x; r < k;
+       r += int64_t(gridDim.x) * kBlock)
+    rank[order[r]] = int32_t(r);
+}
+
+// one wave per column: CSR sort keys (row, rank) and row histogram
+__global__ __launch_bounds__(kBlock) void k_csr_keys(const int64_t *col_ptr, const int32_t *row_idx,
+                                                      int64_t k, const int32_t *rank, uint64_t *keys,
+                                                      int32_t *vals, int32_t *hist) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave;
+  const int64_t nw = int64_t(gridDim.x) * kBlock / kWave;
+  for (int64_t j = wid; j < k; j += nw) {
+    const uint64_t rj = uint64_t(rank[j]);
+    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave) {
+      const int32_t r = row_idx[e];
+      keys[e] = (uint64_t(r) << 32) | rj;
+      vals[e] = int32_t(e);
+      atomicAdd(&hist[r], 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_csr_fill(const uint64_t *keys, const int32_t *vals,
+                                                      int64_t nnz, const int32_t *row_ptr,
+                                                      int32_t *rank_at, int32_t *pos_in_row) {
+  for (int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x; q < nnz;
+       q += int64_t(gridDim.x) * kBlock) {
+    const uint64_t key = keys[q];
+    const int32_t row = int32_t(key >> 32);
+    rank_at[q] = int32_t(key & 0xFFFFFFFFull);
+    pos_in_row[vals[q]] = int32_t(q) - row_ptr[row];
+  }
+}
+
+// counter = number of (row, earlier column) pairs; frontier = columns with 0
+__global__ __launch_bounds__(kBlock) void k_init_count(const int64_t *col_ptr, int64_t k,
+                                                        const int32_t *pos_in_row, int32_t *count,
+                                                        int32_t *color, int32_t *front,
+                                                        int32_t *ctl) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave;
+  const int64_t nw = int64_t(gridDim.x) * kBlock / kWave;
+  for (int64_t j = wid; j < k; j += nw) {
+    int32_t s = 0;
+    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave) s += pos_in_row[e];
+    s = group_sum<kWave>(s);
+    if (lane == 0) {
+      count[j] = s;
+      color[j] = -1;
+      if (s == 0) front[atomicAdd(&ctl[0], 1)] = int32_t(j);
+    }
+  }
+}
+
+// colour of each frontier column: mex of the colours in its row prefixes
+__global__ __launch_bounds__(kBlock) void k_mex(const int64_t *col_ptr, const int32_t *row_idx,
+                                                 const int32_t *front, int32_t F,
+                                                 const int32_t *row_ptr, const int32_t *rank_at,
+                                                 const int32_t *pos_in_row, const int32_t *order,
+                                                 int32_t *color, int32_t *ctl) {
+  __shared__ uint32_t bits[kMexWords];
+  __shared__ int32_t best;
+  const int32_t maxc = ctl[1];  // largest colour so far (-1 initially)
+  int32_t words = (maxc + 2 + 31) / 32;
+  if (words > kMexWords) words = kMexWords;
+  for (int64_t f = blockIdx.x; f < F; f += gridDim.x) {
+    const int32_t j = front[f];
+    for (int32_t u = threadIdx.x; u < words; u += kBlock) bits[u] = 0u;
+    if (threadIdx.x == 0) best = INT32_MAX;
+    __syncthreads();
+    for (int64_t e = col_ptr[j] + threadIdx.x; e < col_ptr[j + 1]; e += kBlock) {
+      const int32_t r = row_idx[e];
+      const int32_t a = row_ptr[r], b = a + pos_in_row[e];
+      for (int32_t s = a; s < b; ++s) {
+        const int32_t c = color[order[rank_at[s]]];
+        if (c >= 0 && c < kMexWords * 32) atomicOr(&bits[c >> 5], 1u << (c & 31));
+      }
+    }
+    __syncthreads();
+    int32_t mine = INT32_MAX;
+    for (int32_t u = threadIdx.x; u < words; u += kBlock) {
+      const uint32_t free_bits = ~bits[u];
+      if (free_bits) {
+        mine = u * 32 + __ffs(int(free_bits)) - 1;
+        break;
+      }
+    }
+    if (mine != INT32_MAX) atomicMin(&best, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t c = best == INT32_MAX ? words * 32 : best;
+      if (c >= kMexWords * 32) {
+        atomicOr(&ctl[2], 1);
+        c = kMexWords * 32 - 1;
+      }
+      color[j] = c;
+      atomicMax(&ctl[3], c);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_front_nnz(const int64_t *col_ptr, const int32_t *front,
+                                                       int32_t F, int32_t *cnt) {
+  for (int64_t f = int64_t(blockIdx.x) * kBlock + threadIdx.x; f < F;
+       f += int64_t(gridDim.x) * kBlock) {
+    const int32_t j = front[f];
+    cnt[f] = int32_t(col_ptr[j + 1] - col_ptr[j]);
+  }
+}
+
+// Flattened over the frontier's CSC entries: decrement later row neighbours.
+__global__ __launch_bounds__(kBlock) void k_decrement(const int64_t *col_ptr, const int32_t *row_idx,
+                                                       const int32_t *front, int32_t F,
+                                                       const int32_t *foff, const int32_t *row_ptr,
+                                                       const int32_t *rank_at,
+                                                       const int32_t *pos_in_row,
+                                                       const int32_t *order, int32_t *count,
+                                                       int32_t *next, int32_t *ctl) {
+  const int32_t total = foff[F];
+  for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * kBlock) {
+    int32_t lo = 0, hi = F;  // find f with foff[f] <= t < foff[f+1]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (foff[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int32_t j = front[lo];
+    const int64_t e = col_ptr[j] + (t - foff[lo]);
+    const int32_t r = row_idx[e];
+    const int32_t b = row_ptr[r + 1];
+    for (int32_t s = row_ptr[r] + pos_in_row[e] + 1; s < b; ++s) {
+      const int32_t j2 = order[rank_at[s]];
+      if (atomicSub(&count[j2], 1) == 1) next[atomicAdd(&ctl[0], 1)] = j2;
+    }
+  }
+}
+
+static unsigned g1(int64_t m, unsigned cap = 4096) {
+  int64_t b = (m + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return unsigned(b);
+}
+
+int color_run(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws_base,
+              size_t ws_bytes, hipStream_t s) {
+  const int64_t n = X->n, k = X->k, nnz = X->nnz;
+  size_t need = color_layout(n, k, nnz, nullptr, nullptr);
+  if (!ws_base || ws_bytes < need) return GENCD_ERR_WORKSPACE;
+  char *base = static_cast<char *>(ws_base);
+  size_t mis = reinterpret_cast<uintptr_t>(base) % 256;
+  if (mis) base += 256 - mis;
+  ColorWs w{};
+  color_layout(n, k, nnz, base, &w);
+  int st;
+  // priority order: decreasing nnz, ties by index (keys are unique)
+  hipLaunchKernelGGL(k_prio_keys, dim3(g1(k)), dim3(kBlock), 0, s, X->col_ptr, k, n, w.keys_a,
+                     w.vals_a);
+  int kbits = 32;
+  while (kbits < 64 && (uint64_t(n) >> (kbits - 32)) != 0) ++kbits;
+  size_t tb = w.sort_tmp_bytes;
+  GENCD_HIP(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.keys_a, w.keys_b, w.vals_a,
+                                               w.order, int(k), 0, kbits, s));
+  hipLaunchKernelGGL(k_rank_of, dim3(g1(k)), dim3(kBlock), 0, s, w.order, k, w.rank);
+  // CSR with rows sorted by priority rank (keys (row, rank) are unique)
+  st = fill_i32(w.fcnt, n + 1, 0, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_csr_keys, dim3(g1(k * kWave, 8192)), dim3(kBlock), 0, s, X->col_ptr,
+                     X->row_idx, k, w.rank, w.keys_a, w.vals_a, w.fcnt);
+  st = scan_exclusive(w.fcnt, w.row_ptr, n, w.scan_part, s);
+  if (st) return st;
+  if (nnz > 0) {
+    int rbits = 32;
+    while (rbits < 64 && (uint64_t(n) >> (rbits - 32)) != 0) ++rbits;
+    tb = w.sort_tmp_bytes;
+    GENCD_HIP(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.keys_a, w.keys_b, w.vals_a,
+                                                 w.vals_b, int(nnz), 0, rbits, s));
+    hipLaunchKernelGGL(k_csr_fill, dim3(g1(nnz)), dim3(kBlock), 0, s, w.keys_b, w.vals_b, nnz,
+                       w.row_ptr, w.rank_at, w.pos_in_row);
+  }
+  st = fill_i32(w.ctl, 8, 0, s);
+  if (st) return st;
+  // ctl[1] = largest colour so far, start at -1
+  st = fill_i32(w.ctl + 1, 1, -1, s);
+  if (st) return st;
+  st = fill_i32(w.ctl + 3, 1, -1, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_init_count, dim3(g1(k * kWave, 8192)), dim3(kBlock), 0, s, X->col_ptr, k,
+                     w.pos_in_row, w.count, color, w.front_a, w.ctl);
+  GENCD_HIP(hipGetLastError());
+  int32_t F = 0;
+  GENCD_HIP(hipMemcpyAsync(&F, w.ctl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipStreamSynchronize(s));
+  int64_t coloured = 0;
+  int32_t *cur = w.front_a, *nxt = w.front_b;
+  int32_t ctl_host[8];
+  while (F > 0) {
+    coloured += F;
+    if (coloured > k) return GENCD_ERR_HIP;  // cannot happen for a valid CSC
+    st = fill_i32(w.ctl, 1, 0, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_mex, dim3(unsigned(F < 16384 ? F : 16384)), dim3(kBlock), 0, s,
+                       X->col_ptr, X->row_idx, cur, F, w.row_ptr, w.rank_at, w.pos_in_row,
+                       w.order, color, w.ctl);
+    hipLaunchKernelGGL(k_front_nnz, dim3(g1(F)), dim3(kBlock), 0, s, X->col_ptr, cur, F, w.fcnt);
+    st = scan_exclusive(w.fcnt, w.foff, F, w.scan_part, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_decrement, dim3(g1(nnz > 0 ? nnz : 1, 8192)), dim3(kBlock), 0, s,
+                       X->col_ptr, X->row_idx, cur, F, w.foff, w.row_ptr, w.rank_at,
+                       w.pos_in_row, w.order, w.count, nxt, w.ctl);
+    // the next round's mex needs the largest colour: ctl[1] <- ctl[3]
+    GENCD_HIP(hipMemcpyAsync(w.ctl + 1, w.ctl + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    GENCD_HIP(hipMemcpyAsync(ctl_host, w.ctl, sizeof(ctl_host), hipMemcpyDeviceToHost, s));
+    GENCD_HIP(hipStreamSynchronize(s));
+    if (ctl_host[2]) return GENCD_ERR_UNSUPPORTED;  // more colours than the bitmap holds
+    F = ctl_host[0];
+    int32_t *t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  if (coloured != k) return GENCD_ERR_HIP;
+  GENCD_HIP(hipMemcpyAsync(ctl_host, w.ctl, sizeof(ctl_host), hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipStreamSynchronize(s));
+  *num_colors = ctl_host[3] + 1;
+  return GENCD_OK;
+}
+
+size_t color_workspace(int64_t n, int64_t k, int64_t nnz) {
+  return color_layout(n, k, nnz, nullptr, nullptr) + 256;
+}
+
+}  // namespace gencd
+
+extern "C" {
+
+int gencd_color_workspace_bytes(const gencd_csc *X, size_t *out_bytes) {
+  if (!X || !out_bytes || X->n <= 0 || X->k <= 0 || X->nnz < 0) return GENCD_ERR_INVALID_ARG;
+  if (X->n > INT32_MAX || X->k >= INT32_MAX || X->nnz >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  *out_bytes = gencd::color_workspace(X->n, X->k, X->nnz);
+  return GENCD_OK;
+}
+
+int gencd_color(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws, size_t ws_bytes,
+                hipStream_t stream) {
+  if (!X || !color || !num_colors || X->n <= 0 || X->k <= 0 || X->nnz < 0 || !X->col_ptr ||
+      (X->nnz > 0 && !X->row_idx))
+    return GENCD_ERR_INVALID_ARG;
+  if (X->n > INT32_MAX || X->k >= INT32_MAX || X->nnz >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  return gencd::color_run(X, color, num_colors, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

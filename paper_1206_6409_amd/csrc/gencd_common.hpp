@@ -1,0 +1,206 @@
+// Internal declarations shared by the HIP translation units of libgencd.
+// Device helpers (losses, the Propose formula, the selection permutation,
+// group reductions), the workspace layout and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/gencd.h"
+
+namespace gencd {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+constexpr int kWave = 64;
+
+#define GENCD_HIP(call)                                     \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return GENCD_ERR_HIP;             \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Losses of section 1, differentiated in the fitted value t.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dloss_f32(int loss, float y, float t) {
+  if (loss == GENCD_SQUARED) return t - y;
+  float m = y * t;  // -y * sigma(-m), evaluated without overflow
+  float s;
+  if (m >= 0.0f) {
+    float e = expf(-m);
+    s = e / (1.0f + e);
+  } else {
+    s = 1.0f / (1.0f + expf(m));
+  }
+  return -y * s;
+}
+
+__device__ __forceinline__ double loss_f64(int loss, double y, double t) {
+  if (loss == GENCD_SQUARED) {
+    double d = y - t;
+    return 0.5 * d * d;
+  }
+  double m = y * t;
+  return (m > 0.0 ? 0.0 : -m) + log1p(exp(-fabs(m)));
+}
+
+__device__ __forceinline__ double dloss_f64(int loss, double y, double t) {
+  if (loss == GENCD_SQUARED) return t - y;
+  double m = y * t;
+  double s;
+  if (m >= 0.0) {
+    double e = exp(-m);
+    s = e / (1.0 + e);
+  } else {
+    s = 1.0 / (1.0 + exp(m));
+  }
+  return -y * s;
+}
+
+// Proposal from the quadratic upper bound (Algorithm 4: Eq. 7 for the step,
+// Eq. 9 for the proxy), with the coordinate curvature c = beta ||X_j||^2 / n.
+__device__ __forceinline__ void propose_f32(float g, float c, float w, float lam, float &d,
+                                            float &phi) {
+  if (!(c > 0.0f)) {
+    d = 0.0f;
+    phi = 0.0f;
+    return;
+  }
+  float a = (g - lam) / c;
+  float b = (g + lam) / c;
+  float psi = w < a ? a : (w > b ? b : w);
+  d = -psi;
+  phi = 0.5f * c * d * d + g * d + lam * (fabsf(w + d) - fabsf(w));
+}
+
+// ---------------------------------------------------------------------------
+// Per-epoch selection permutation: 4-round balanced Feistel network on the
+// smallest even power of two >= m, cycle-walked into [0, m); the round
+// function is the SplitMix64 finaliser.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint64_t splitmix_fin(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return x;
+}
+
+struct PermKey {
+  uint64_t k[4];
+  int half;
+  uint64_t m;
+};
+
+__host__ __device__ inline PermKey make_perm_key(int64_t m, uint64_t seed, int64_t epoch) {
+  PermKey pk;
+  int bits = 2;
+  while ((int64_t(1) << bits) < m) bits += 2;
+  pk.half = bits / 2;
+  pk.m = uint64_t(m);
+  for (int r = 0; r < 4; ++r)
+    pk.k[r] = splitmix_fin(seed + 0x9E3779B97F4A7C15ull * uint64_t(epoch * 8 + r + 1));
+  return pk;
+}
+
+__host__ __device__ __forceinline__ uint64_t perm_apply(const PermKey &pk, uint64_t x) {
+  const uint64_t mask = pk.half >= 32 ? 0xFFFFFFFFull : ((uint64_t(1) << pk.half) - 1);
+  do {
+    uint64_t L = x >> pk.half, R = x & mask;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint64_t f = splitmix_fin(R ^ pk.k[r]) & mask;
+      uint64_t t = R;
+      R = L ^ f;
+      L = t;
+    }
+    x = (L << pk.half) | R;
+  } while (x >= pk.m);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions inside an aligned group of G lanes of a wave64.
+// ---------------------------------------------------------------------------
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Compensated scatter z_hi[i] + z_lo[i] += d * v (exact product by FMA,
+// exact sum by TwoSum of the value the atomic actually replaced).
+__device__ __forceinline__ void scatter_atomic(float *z_hi, float *z_lo, int i, float d, float v) {
+  float p = d * v;
+  float pe = fmaf(d, v, -p);
+  float old = atomicAdd(&z_hi[i], p);
+  float s = old + p;
+  float bp = s - old;
+  float err = (old - (s - bp)) + (p - bp);
+  float corr = err + pe;
+  if (corr != 0.0f) atomicAdd(&z_lo[i], corr);
+}
+
+// Same without atomics: for updates that own the row (columns of one colour
+// class have disjoint rows).
+__device__ __forceinline__ void scatter_plain(float *z_hi, float *z_lo, int i, float d, float v) {
+  float p = d * v;
+  float pe = fmaf(d, v, -p);
+  float old = z_hi[i];
+  float s = old + p;
+  float bp = s - old;
+  float err = (old - (s - bp)) + (p - bp);
+  z_hi[i] = s;
+  z_lo[i] += err + pe;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace (carved from the caller's buffer).
+// ---------------------------------------------------------------------------
+struct Ws {
+  // problem-static
+  float *c;              // [k] curvature bound
+  int32_t *live;         // [k] non-empty columns, ascending
+  int32_t *all_poff;     // [k+1] piece offsets of every column (natural order)
+  int32_t *all_pcol;     // [max_pieces] column of each piece
+  int32_t *tmp_cnt;      // [k+1] scratch counts
+  int32_t *scan_part;    // [scan partials]
+  int32_t *cls_off;      // [k+1] colour class offsets (COLORING)
+  int32_t *cls_mem;      // [k] live members by colour
+  // per-epoch order
+  int32_t *col_of_pos;   // [k]
+  int32_t *poff;         // [k+1]
+  int32_t *piece_pos;    // [max_pieces]
+  int32_t *win_off;      // [k+1]
+  // per-window
+  float *delta;          // [k]
+  float *phi;            // [k]
+  float *gbuf;           // [k]
+  float *gacc;           // [k]
+  int32_t *tick;         // [k]
+  int32_t *acc;          // [k]
+  // state
+  float *z_hi, *z_lo, *r;  // [n]
+  float *w_ckpt;           // [k]
+  // FP64 check
+  double *z64, *r64;     // [n]
+  double *g64;           // [k]
+  double *red;           // [8] loss sum, l1, kkt bits, nnz, ...
+  int32_t *flags;        // [8] device flags (label / matrix validation)
+  size_t scan_part_len;
+  int64_t max_pieces;
+};
+
+int64_t max_pieces_for(int64_t k, int64_t nnz, int piece);
+size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, void *base, Ws *ws);
+size_t scan_partials_for(int64_t len);
+
+// Exclusive scan of int32 counts: out[0..len] (out[len] = total).
+int scan_exclusive(const int32_t *in, int32_t *out, int64_t len, int32_t *partials,
+                   hipStream_t s);
+
+}  // namespace gencd

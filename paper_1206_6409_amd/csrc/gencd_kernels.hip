@@ -1,0 +1,845 @@
+// HIP kernels of the GenCD hot path for gfx950 (wave64, 256-thread groups).
+//
+// Work decomposition.  Column nonzero counts are heavy-tailed, so a column
+// is cut into "pieces" of at most `piece` nonzeros and a group of G lanes
+// (G in {8, 16, 32, 64}) processes one piece: the G lanes read consecutive
+// CSC entries (coalesced row_idx / val loads), gather the residual, and
+// reduce within the group.  A column with one piece is proposed and, for
+// accept-all rules, updated by its group without any synchronisation; the
+// partial sums of a multi-piece column are combined with a float atomic and
+// the last piece to arrive (ticket counter) finalises the proposal.
+//
+// Selection (section 2.1) is precomputed per epoch: position p of the epoch
+// order holds column col_of_pos[p]; poff is the exclusive scan of piece
+// counts over positions and piece_pos maps a piece back to its position, so
+// an iteration's selected set J is the position range of its window and its
+// work is the piece range poff[P0] .. poff[P1].
+#include "gencd_common.hpp"
+#include "gencd_kernels.hpp"
+
+namespace gencd {
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32 (three passes: tile sums, scan of tile sums, apply)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+size_t scan_partials_for(int64_t len) { return size_t((len + kScanTile - 1) / kScanTile) + 2; }
+
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t &total) {
+  __shared__ int32_t wsum[kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = x;
+  __syncthreads();
+  int32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    if (w < wid) pre += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t *in, int64_t len,
+                                                        int32_t *part) {
+  int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int32_t s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u)
+    if (base + u < len) s += in[base + u];
+  int32_t tot;
+  block_excl_scan(s, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_part(int32_t *part, int64_t nparts) {
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nparts; b0 += kBlock) {
+    int64_t i = b0 + threadIdx.x;
+    int32_t v = i < nparts ? part[i] : 0;
+    int32_t tot;
+    int32_t ex = block_excl_scan(v, tot);
+    if (i < nparts) part[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[nparts] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *in, int64_t len,
+                                                        const int32_t *part, int64_t nparts,
+                                                        int32_t *out) {
+  int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int32_t v[kScanItems];
+  int32_t s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u) {
+    v[u] = (base + u < len) ? in[base + u] : 0;
+    s += v[u];
+  }
+  int32_t tot;
+  int32_t ex = block_excl_scan(s, tot) + part[blockIdx.x];
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u) {
+    if (base + u < len) out[base + u] = ex;
+    ex += v[u];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = part[nparts];
+}
+
+int scan_exclusive(const int32_t *in, int32_t *out, int64_t len, int32_t *part, hipStream_t s) {
+  if (len <= 0) {
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(kBlock), 0, s, part, int64_t(0));
+    // out[0] = 0
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kBlock), 0, s, in, int64_t(0), part,
+                       int64_t(0), out);
+    return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+  }
+  int64_t nparts = (len + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(unsigned(nparts)), dim3(kBlock), 0, s, in, len, part);
+  hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(kBlock), 0, s, part, nparts);
+  hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(nparts)), dim3(kBlock), 0, s, in, len, part,
+                     nparts, out);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T *p, int64_t m, T v) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kBlock)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(T *dst, const T *src, int64_t m) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kBlock)
+    dst[i] = src[i];
+}
+
+static unsigned grid_for(int64_t m, unsigned cap = 4096) {
+  int64_t b = (m + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return unsigned(b);
+}
+
+int fill_f32(float *p, int64_t m, float v, hipStream_t s) {
+  if (m <= 0) return GENCD_OK;
+  hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(m)), dim3(kBlock), 0, s, p, m, v);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+int fill_i32(int32_t *p, int64_t m, int32_t v, hipStream_t s) {
+  if (m <= 0) return GENCD_OK;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(m)), dim3(kBlock), 0, s, p, m, v);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+int fill_f64(double *p, int64_t m, double v, hipStream_t s) {
+  if (m <= 0) return GENCD_OK;
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(m)), dim3(kBlock), 0, s, p, m, v);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+int copy_f32(float *d, const float *src, int64_t m, hipStream_t s) {
+  if (m <= 0) return GENCD_OK;
+  hipLaunchKernelGGL(k_copy<float>, dim3(grid_for(m)), dim3(kBlock), 0, s, d, src, m);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+int copy_i32(int32_t *d, const int32_t *src, int64_t m, hipStream_t s) {
+  if (m <= 0) return GENCD_OK;
+  hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(m)), dim3(kBlock), 0, s, d, src, m);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Validation (structure of the CSC matrix, logistic labels)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_validate_matrix(const int64_t *col_ptr,
+                                                             const int32_t *row_idx, int64_t n,
+                                                             int64_t k, int64_t nnz,
+                                                             unsigned long long *bad) {
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock) {
+    int64_t a = col_ptr[j], b = col_ptr[j + 1];
+    bool ok = a >= 0 && b >= a && b <= nnz && (j > 0 || a == 0) && (j + 1 < k || b == nnz);
+    if (ok) {
+      int32_t prev = -1;
+      for (int64_t e = a; e < b; ++e) {
+        int32_t r = row_idx[e];
+        if (r <= prev || r >= n) {
+          ok = false;
+          break;
+        }
+        prev = r;
+      }
+    }
+    if (!ok) atomicOr(bad, 1ull);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate_labels(const float *y, int64_t n,
+                                                             unsigned long long *bad) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    float v = y[i];
+    if (!(v == 1.0f || v == -1.0f)) atomicOr(bad, 2ull);
+  }
+}
+
+int launch_validate(const gencd_csc *X, const float *y, int loss, bool matrix,
+                    unsigned long long *bad, hipStream_t s) {
+  if (matrix)
+    hipLaunchKernelGGL(k_validate_matrix, dim3(grid_for(X->k)), dim3(kBlock), 0, s, X->col_ptr,
+                       X->row_idx, X->n, X->k, X->nnz, bad);
+  if (loss == GENCD_LOGISTIC)
+    hipLaunchKernelGGL(k_validate_labels, dim3(grid_for(X->n)), dim3(kBlock), 0, s, y, X->n, bad);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Preprocessing: piece decomposition, live columns, curvature (row a1)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_col_counts(const int64_t *col_ptr, int64_t k,
+                                                        int piece, int32_t *npieces,
+                                                        int32_t *live_flag) {
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock) {
+    int64_t m = col_ptr[j + 1] - col_ptr[j];
+    npieces[j] = int32_t((m + piece - 1) / piece);
+    live_flag[j] = m > 0 ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_scatter(int64_t k, const int32_t *all_poff,
+                                                         const int32_t *live_pos,
+                                                         int32_t *all_pcol, int32_t *live) {
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock) {
+    int32_t a = all_poff[j], b = all_poff[j + 1];
+    for (int32_t q = a; q < b; ++q) all_pcol[q] = int32_t(j);
+    if (b > a) live[live_pos[j]] = int32_t(j);
+  }
+}
+
+// Sum of squares per column in FP64 over pieces (G lanes per piece).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_colsq(const int64_t *col_ptr, const float *val,
+                                                   const int32_t *all_poff,
+                                                   const int32_t *all_pcol, int32_t npieces,
+                                                   int piece, double *acc) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
+  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  for (int64_t q = gid; q < npieces; q += ng) {
+    int32_t j = all_pcol[q];
+    int32_t pf = all_poff[j];
+    int64_t beg = col_ptr[j] + int64_t(q - pf) * piece;
+    int64_t end = min(beg + int64_t(piece), col_ptr[j + 1]);
+    double s = 0.0;
+    for (int64_t e = beg + lane; e < end; e += G) {
+      double v = double(val[e]);
+      s += v * v;
+    }
+    s = group_sum<G>(s);
+    if (lane == 0) atomicAdd(&acc[j], s);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_curvature(int64_t k, const double *ss, double beta,
+                                                       double inv_n, float *c) {
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock)
+    c[j] = float(beta * ss[j] * inv_n);
+}
+
+static unsigned groups_grid(int64_t groups, int G, unsigned cap = 2048) {
+  int64_t threads = groups * G;
+  int64_t b = (threads + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return unsigned(b);
+}
+
+int launch_preprocess(const gencd_csc *X, int loss, int piece, const Ws &w, hipStream_t s) {
+  const int64_t k = X->k;
+  // npieces -> tmp_cnt, live flags -> col_of_pos (scratch here)
+  hipLaunchKernelGGL(k_col_counts, dim3(grid_for(k)), dim3(kBlock), 0, s, X->col_ptr, k, piece,
+                     w.tmp_cnt, w.col_of_pos);
+  int st = scan_exclusive(w.tmp_cnt, w.all_poff, k, w.scan_part, s);
+  if (st) return st;
+  st = scan_exclusive(w.col_of_pos, w.poff, k, w.scan_part, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(k)), dim3(kBlock), 0, s, k, w.all_poff, w.poff,
+                     w.all_pcol, w.live);
+  return fill_f64(w.g64, k, 0.0, s);
+}
+
+int launch_curvature(const gencd_csc *X, int loss, int piece, int32_t total_pieces, const Ws &w,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_colsq<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
+                     X->col_ptr, X->val, w.all_poff, w.all_pcol, total_pieces, piece, w.g64);
+  double beta = loss == GENCD_SQUARED ? 1.0 : 0.25;
+  hipLaunchKernelGGL(k_curvature, dim3(grid_for(X->k)), dim3(kBlock), 0, s, X->k, w.g64, beta,
+                     1.0 / double(X->n), w.c);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Per-epoch selection order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_select_perm(int64_t m, PermKey pk, int32_t *out) {
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < m;
+       p += int64_t(gridDim.x) * kBlock)
+    out[p] = int32_t(perm_apply(pk, uint64_t(p)));
+}
+
+int launch_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hipStream_t s) {
+  if (m <= 0) return GENCD_OK;
+  PermKey pk = make_perm_key(m, seed, epoch);
+  hipLaunchKernelGGL(k_select_perm, dim3(grid_for(m)), dim3(kBlock), 0, s, m, pk, out);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// order: 0 = permuted live columns, 1 = live columns in index order
+__global__ __launch_bounds__(kBlock) void k_epoch_order(const int32_t *live, int64_t k_live,
+                                                         PermKey pk, int natural,
+                                                         const int32_t *all_poff,
+                                                         int32_t *col_of_pos, int32_t *np) {
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < k_live;
+       p += int64_t(gridDim.x) * kBlock) {
+    int64_t src = natural ? p : int64_t(perm_apply(pk, uint64_t(p)));
+    int32_t j = live[src];
+    col_of_pos[p] = j;
+    np[p] = all_poff[j + 1] - all_poff[j];
+  }
+}
+
+// np for an explicit column list (step API and colour windows)
+__global__ __launch_bounds__(kBlock) void k_list_np(const int32_t *cols, int64_t m,
+                                                     const int32_t *all_poff, int32_t *np) {
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < m;
+       p += int64_t(gridDim.x) * kBlock) {
+    int32_t j = cols[p];
+    np[p] = all_poff[j + 1] - all_poff[j];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_piece_map(const int32_t *poff, int64_t m,
+                                                       int32_t *piece_pos) {
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < m;
+       p += int64_t(gridDim.x) * kBlock) {
+    int32_t a = poff[p], b = poff[p + 1];
+    for (int32_t q = a; q < b; ++q) piece_pos[q] = int32_t(p);
+  }
+}
+
+// Colour windows: size of the class visited at step t of the epoch.
+__global__ __launch_bounds__(kBlock) void k_color_win_sizes(const int32_t *cls_off, int64_t C,
+                                                             PermKey pk, int32_t *sz) {
+  for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < C;
+       t += int64_t(gridDim.x) * kBlock) {
+    int64_t c = int64_t(perm_apply(pk, uint64_t(t)));
+    sz[t] = cls_off[c + 1] - cls_off[c];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_color_fill(const int32_t *cls_off,
+                                                        const int32_t *cls_mem, int64_t C,
+                                                        PermKey pk, const int32_t *win_off,
+                                                        int32_t *col_of_pos) {
+  for (int64_t t = blockIdx.x; t < C; t += gridDim.x) {
+    int64_t c = int64_t(perm_apply(pk, uint64_t(t)));
+    int32_t a = cls_off[c], b = cls_off[c + 1];
+    int32_t o = win_off[t];
+    for (int32_t u = a + threadIdx.x; u < b; u += kBlock) col_of_pos[o + (u - a)] = cls_mem[u];
+  }
+}
+
+int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed, int64_t epoch,
+                       int64_t num_colors, hipStream_t s) {
+  int st;
+  if (rule == GENCD_COLORING) {
+    PermKey pk = make_perm_key(num_colors, seed, epoch);
+    hipLaunchKernelGGL(k_color_win_sizes, dim3(grid_for(num_colors)), dim3(kBlock), 0, s,
+                       w.cls_off, num_colors, pk, w.tmp_cnt);
+    st = scan_exclusive(w.tmp_cnt, w.win_off, num_colors, w.scan_part, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_color_fill, dim3(unsigned(num_colors < 8192 ? num_colors : 8192)),
+                       dim3(kBlock), 0, s, w.cls_off, w.cls_mem, num_colors, pk, w.win_off,
+                       w.col_of_pos);
+    hipLaunchKernelGGL(k_list_np, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.col_of_pos,
+                       k_live, w.all_poff, w.tmp_cnt);
+  } else {
+    PermKey pk = make_perm_key(k_live, seed, epoch);
+    hipLaunchKernelGGL(k_epoch_order, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.live, k_live,
+                       pk, rule == GENCD_CYCLIC ? 1 : 0, w.all_poff, w.col_of_pos, w.tmp_cnt);
+  }
+  st = scan_exclusive(w.tmp_cnt, w.poff, k_live, w.scan_part, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_piece_map, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.poff, k_live,
+                     w.piece_pos);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s) {
+  int st = copy_i32(w.col_of_pos, J, nJ, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_list_np, dim3(grid_for(nJ)), dim3(kBlock), 0, s, w.col_of_pos, nJ,
+                     w.all_poff, w.tmp_cnt);
+  st = scan_exclusive(w.tmp_cnt, w.poff, nJ, w.scan_part, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_piece_map, dim3(grid_for(nJ)), dim3(kBlock), 0, s, w.poff, nJ,
+                     w.piece_pos);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// One iteration: Propose (+ fused Update), Accept, Update, residual refresh
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void window_of(const IterArgs &a, int32_t &P0, int32_t &P1) {
+  if (a.win_off) {
+    P0 = a.win_off[a.t];
+    P1 = a.win_off[a.t + 1];
+  } else {
+    P0 = a.win_lo;
+    P1 = a.win_hi;
+  }
+}
+
+// MODE 0: accept all, atomic scatter (Shotgun, stochastic, cyclic)
+// MODE 1: accept all, plain scatter (Coloring: rows of a class are disjoint)
+// MODE 2: deferred acceptance (Thread-Greedy, Greedy): store delta and phi
+template <int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
+  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  int32_t P0, P1;
+  window_of(a, P0, P1);
+  const int32_t q0 = a.poff[P0], q1 = a.poff[P1];
+  for (int64_t q = q0 + gid; q < q1; q += ng) {
+    const int32_t p = a.piece_pos[q];
+    const int32_t j = a.col_of_pos[p];
+    const int32_t pf = a.poff[p];
+    const int32_t np = a.poff[p + 1] - pf;
+    const int64_t ce = a.col_ptr[j + 1];
+    const int64_t beg = a.col_ptr[j] + int64_t(q - pf) * a.piece;
+    const int64_t end = min(beg + int64_t(a.piece), ce);
+    float s = 0.0f;
+    for (int64_t e = beg + lane; e < end; e += G) s += a.val[e] * a.r[a.row_idx[e]];
+    s = group_sum<G>(s);
+    const int32_t slot = p - P0;
+    int fin = (np == 1);
+    if (np > 1) {
+      // Partial sums of a split column: publish, take a ticket; the last
+      // piece adds the partials in piece order (deterministic result).
+      if (lane == 0) {
+        a.gacc[q] = s;
+        __threadfence();
+        fin = (atomicAdd(&a.tick[slot], 1) == np - 1);
+      }
+      fin = __shfl(fin, 0, G);
+      if (fin) {
+        __threadfence();
+        float t = 0.0f;
+        for (int32_t u = lane; u < np; u += G) t += __hip_atomic_load(&a.gacc[pf + u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s = group_sum<G>(t);
+        if (lane == 0) a.tick[slot] = 0;
+      }
+    }
+    float d = 0.0f;
+    if (fin && lane == 0) {
+      const float g = s / a.n_f;
+      const float wj = a.w[j];
+      float ph;
+      propose_f32(g, a.c[j], wj, a.lam, d, ph);
+      a.delta[slot] = d;
+      a.phi[slot] = ph;
+      if (a.gout) a.gout[slot] = g;
+      if (MODE != 2 && d != 0.0f) a.w[j] = wj + d;
+    }
+    if (MODE != 2 && np == 1) {
+      d = __shfl(d, 0, G);
+      if (d != 0.0f) {
+        for (int64_t e = beg + lane; e < end; e += G) {
+          if (MODE == 0)
+            scatter_atomic(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
+          else
+            scatter_plain(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
+        }
+      }
+    }
+  }
+}
+
+// Accept for Thread-Greedy / Greedy: in each block of B positions, the first
+// position with minimal phi (one workgroup per block).
+__global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
+  __shared__ float sphi[kBlock];
+  __shared__ int32_t spos[kBlock];
+  int32_t P0, P1;
+  window_of(a, P0, P1);
+  const int64_t nblk = (int64_t(P1 - P0) + B - 1) / B;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int64_t lo = P0 + b * B, hi = min(lo + B, int64_t(P1));
+    float best = INFINITY;
+    int32_t bpos = INT32_MAX;
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kBlock) {
+      a.acc[p - P0] = 0;
+      float v = a.phi[p - P0];
+      if (v < best) {  // strided scan visits positions in increasing order
+        best = v;
+        bpos = int32_t(p);
+      }
+    }
+    sphi[threadIdx.x] = best;
+    spos[threadIdx.x] = bpos;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        float v2 = sphi[threadIdx.x + off];
+        int32_t p2 = spos[threadIdx.x + off];
+        if (v2 < sphi[threadIdx.x] || (v2 == sphi[threadIdx.x] && p2 < spos[threadIdx.x])) {
+          sphi[threadIdx.x] = v2;
+          spos[threadIdx.x] = p2;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && spos[0] != INT32_MAX) {
+      const int32_t p = spos[0];
+      a.acc[p - P0] = 1;
+      const int32_t j = a.col_of_pos[p];
+      const float d = a.delta[p - P0];
+      if (d != 0.0f) a.w[j] += d;
+      atomicAdd(a.counters + 0, (unsigned long long)(a.col_ptr[j + 1] - a.col_ptr[j]));
+      atomicAdd(a.counters + 1, 1ull);
+    }
+    __syncthreads();
+  }
+}
+
+// Update (Algorithm 3) of the proposals that Propose did not already apply.
+template <int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
+  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  int32_t P0, P1;
+  window_of(a, P0, P1);
+  const int32_t q0 = a.poff[P0], q1 = a.poff[P1];
+  for (int64_t q = q0 + gid; q < q1; q += ng) {
+    const int32_t p = a.piece_pos[q];
+    const int32_t slot = p - P0;
+    const int32_t pf = a.poff[p];
+    const int32_t np = a.poff[p + 1] - pf;
+    if (MODE == 2) {
+      if (!a.acc[slot]) continue;
+    } else if (np == 1) {
+      continue;  // applied by the fused Propose
+    }
+    const float d = a.delta[slot];
+    if (d == 0.0f) continue;
+    const int32_t j = a.col_of_pos[p];
+    const int64_t beg = a.col_ptr[j] + int64_t(q - pf) * a.piece;
+    const int64_t end = min(beg + int64_t(a.piece), a.col_ptr[j + 1]);
+    for (int64_t e = beg + lane; e < end; e += G) {
+      if (MODE == 1)
+        scatter_plain(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
+      else
+        scatter_atomic(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
+    }
+  }
+}
+
+// r_i = l'(y_i, z_i) for the rows touched by this iteration's updates.
+template <int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_refresh(IterArgs a) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
+  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  int32_t P0, P1;
+  window_of(a, P0, P1);
+  const int32_t q0 = a.poff[P0], q1 = a.poff[P1];
+  for (int64_t q = q0 + gid; q < q1; q += ng) {
+    const int32_t p = a.piece_pos[q];
+    const int32_t slot = p - P0;
+    if (MODE == 2 && !a.acc[slot]) continue;
+    if (a.delta[slot] == 0.0f) continue;
+    const int32_t pf = a.poff[p];
+    const int32_t j = a.col_of_pos[p];
+    const int64_t beg = a.col_ptr[j] + int64_t(q - pf) * a.piece;
+    const int64_t end = min(beg + int64_t(a.piece), a.col_ptr[j + 1]);
+    for (int64_t e = beg + lane; e < end; e += G) {
+      const int32_t i = a.row_idx[e];
+      a.r[i] = dloss_f32(a.loss, a.y[i], a.z_hi[i] + a.z_lo[i]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_refresh_all(int64_t n, int loss, const float *y,
+                                                         const float *z_hi, const float *z_lo,
+                                                         float *r) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    r[i] = dloss_f32(loss, y[i], z_hi[i] + z_lo[i]);
+}
+
+int launch_refresh_all(int64_t n, int loss, const float *y, const float *z_hi, const float *z_lo,
+                       float *r, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_all, dim3(grid_for(n)), dim3(kBlock), 0, s, n, loss, y, z_hi,
+                     z_lo, r);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+template <int G>
+static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, int64_t groups,
+                              int64_t nblocks_accept, bool deferred_work, hipStream_t s) {
+  const dim3 grid(groups_grid(groups, G)), blk(kBlock);
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_propose<G, 0>), grid, blk, 0, s, a);
+    if (deferred_work) hipLaunchKernelGGL((k_update<G, 0>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_refresh<G, 0>), grid, blk, 0, s, a);
+  } else if (mode == 1) {
+    hipLaunchKernelGGL((k_propose<G, 1>), grid, blk, 0, s, a);
+    if (deferred_work) hipLaunchKernelGGL((k_update<G, 1>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_refresh<G, 1>), grid, blk, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_propose<G, 2>), grid, blk, 0, s, a);
+    unsigned nb = unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
+    hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
+    hipLaunchKernelGGL((k_update<G, 2>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_refresh<G, 2>), grid, blk, 0, s, a);
+  }
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t groups,
+                     int64_t nblocks_accept, bool deferred_work, hipStream_t s) {
+  switch (group) {
+    case 8: return launch_iteration_g<8>(a, mode, block, groups, nblocks_accept, deferred_work, s);
+    case 16: return launch_iteration_g<16>(a, mode, block, groups, nblocks_accept, deferred_work, s);
+    case 32: return launch_iteration_g<32>(a, mode, block, groups, nblocks_accept, deferred_work, s);
+    default: return launch_iteration_g<64>(a, mode, block, groups, nblocks_accept, deferred_work, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 check: z64 = Xw, loss, r64 = l'(y, z64), g64 = X^T r64 / n, KKT, |w|_1
+// (and the FP32 re-sync z_hi + z_lo = z64, r = l'(y, z64))
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_check_zero(double *z64, int64_t n, double *g64,
+                                                        int64_t k, unsigned long long *red) {
+  const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t nt = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = tid; i < n; i += nt) z64[i] = 0.0;
+  for (int64_t j = tid; j < k; j += nt) g64[j] = 0.0;
+  if (tid < 8) red[tid] = 0ull;
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_check_spmv(const int64_t *col_ptr,
+                                                        const int32_t *row_idx, const float *val,
+                                                        const int32_t *all_poff,
+                                                        const int32_t *all_pcol,
+                                                        int32_t npieces, int piece,
+                                                        const float *w, double *z64) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
+  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  for (int64_t q = gid; q < npieces; q += ng) {
+    const int32_t j = all_pcol[q];
+    const double wj = double(w[j]);
+    if (wj == 0.0) continue;
+    const int64_t beg = col_ptr[j] + int64_t(q - all_poff[j]) * piece;
+    const int64_t end = min(beg + int64_t(piece), col_ptr[j + 1]);
+    for (int64_t e = beg + lane; e < end; e += G) atomicAdd(&z64[row_idx[e]], wj * double(val[e]));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, const float *y,
+                                                        const double *z64, double *r64,
+                                                        float *z_hi, float *z_lo, float *r,
+                                                        double *red) {
+  __shared__ double sred[kBlock];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const double t = z64[i];
+    const double yi = double(y[i]);
+    acc += loss_f64(loss, yi, t);
+    const double d = dloss_f64(loss, yi, t);
+    r64[i] = d;
+    if (z_hi) {
+      const float h = float(t);
+      z_hi[i] = h;
+      z_lo[i] = float(t - double(h));
+      r[i] = float(d);
+    }
+  }
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(&red[0], sred[0]);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_check_cols(const int64_t *col_ptr,
+                                                        const int32_t *row_idx, const float *val,
+                                                        const int32_t *all_poff,
+                                                        const int32_t *all_pcol,
+                                                        int32_t npieces, int piece,
+                                                        const double *r64, double *g64) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
+  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  for (int64_t q = gid; q < npieces; q += ng) {
+    const int32_t j = all_pcol[q];
+    const int32_t pf = all_poff[j];
+    const int32_t np = all_poff[j + 1] - pf;
+    const int64_t beg = col_ptr[j] + int64_t(q - pf) * piece;
+    const int64_t end = min(beg + int64_t(piece), col_ptr[j + 1]);
+    double s = 0.0;
+    for (int64_t e = beg + lane; e < end; e += G) s += double(val[e]) * r64[row_idx[e]];
+    s = group_sum<G>(s);
+    if (lane == 0) {
+      if (np == 1)
+        g64[j] = s;
+      else
+        atomicAdd(&g64[j], s);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_kkt(int64_t k, double *g64, const float *w,
+                                                       double lam, double inv_n,
+                                                       unsigned long long *red) {
+  __shared__ double smax[kBlock], sl1[kBlock], sgm[kBlock];
+  __shared__ unsigned long long snz[kBlock];
+  double vmax = 0.0, l1 = 0.0, gmax = 0.0;
+  unsigned long long nz = 0;
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock) {
+    const double g = g64[j] * inv_n;
+    g64[j] = g;
+    if (!(fabs(g) <= gmax)) gmax = fabs(g);
+    const double wj = w ? double(w[j]) : 0.0;
+    double v;
+    if (wj != 0.0) {
+      v = fabs(g + (wj > 0.0 ? lam : -lam));
+      l1 += fabs(wj);
+      ++nz;
+    } else {
+      v = fabs(g) - lam;
+      if (v < 0.0) v = 0.0;
+    }
+    if (!(v <= vmax)) vmax = v;  // propagates NaN
+  }
+  smax[threadIdx.x] = vmax;
+  sl1[threadIdx.x] = l1;
+  snz[threadIdx.x] = nz;
+  sgm[threadIdx.x] = gmax;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      double o = smax[threadIdx.x + off];
+      if (!(o <= smax[threadIdx.x])) smax[threadIdx.x] = o;
+      double o2 = sgm[threadIdx.x + off];
+      if (!(o2 <= sgm[threadIdx.x])) sgm[threadIdx.x] = o2;
+      sl1[threadIdx.x] += sl1[threadIdx.x + off];
+      snz[threadIdx.x] += snz[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    unsigned long long bits = (m != m) ? 0x7FF8000000000000ull : __double_as_longlong(m);
+    atomicMax(&red[2], bits);  // non-negative doubles order like their bit patterns
+    double gm = sgm[0];
+    atomicMax(&red[4], (gm != gm) ? 0x7FF8000000000000ull : __double_as_longlong(gm));
+    atomicAdd(reinterpret_cast<double *>(&red[1]), sl1[0]);
+    atomicAdd(&red[3], snz[0]);
+  }
+}
+
+// Dual objective of Eq. (1) at u = s l'(y, z64) / n (summand over rows; the
+// scale s = min(1, lambda / |g|_inf) uses the maximum of the previous pass).
+__global__ __launch_bounds__(kBlock) void k_check_dual(int64_t n, int loss, const float *y,
+                                                        const double *r64, double lam,
+                                                        unsigned long long *red) {
+  __shared__ double sred[kBlock];
+  const double gm = __longlong_as_double((long long)red[4]);
+  const double s = (gm > lam) ? lam / gm : 1.0;
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const double v = s * r64[i];  // n u_i
+    const double yi = double(y[i]);
+    if (loss == GENCD_SQUARED) {
+      acc -= v * yi + 0.5 * v * v;
+    } else {
+      const double p = -v * yi;  // in [0, 1): binary entropy
+      double h = 0.0;
+      if (p > 0.0) h -= p * log(p);
+      if (p < 1.0) h -= (1.0 - p) * log1p(-p);
+      acc += h;
+    }
+  }
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(reinterpret_cast<double *>(&red[5]), sred[0]);
+}
+
+int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
+                 int piece, int32_t total_pieces, const Ws &ws, bool resync, hipStream_t s) {
+  unsigned long long *red = reinterpret_cast<unsigned long long *>(ws.red);
+  const int64_t nk = X->n > X->k ? X->n : X->k;
+  hipLaunchKernelGGL(k_check_zero, dim3(grid_for(nk)), dim3(kBlock), 0, s, ws.z64, X->n, ws.g64,
+                     X->k, red);
+  if (w)
+    hipLaunchKernelGGL(k_check_spmv<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
+                       X->col_ptr, X->row_idx, X->val, ws.all_poff, ws.all_pcol, total_pieces,
+                       piece, w, ws.z64);
+  hipLaunchKernelGGL(k_check_rows, dim3(grid_for(X->n, 1024)), dim3(kBlock), 0, s, X->n, loss, y,
+                     ws.z64, ws.r64, resync ? ws.z_hi : nullptr, ws.z_lo, ws.r, ws.red);
+  hipLaunchKernelGGL(k_check_cols<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
+                     X->col_ptr, X->row_idx, X->val, ws.all_poff, ws.all_pcol, total_pieces,
+                     piece, ws.r64, ws.g64);
+  hipLaunchKernelGGL(k_check_kkt, dim3(grid_for(X->k, 1024)), dim3(kBlock), 0, s, X->k, ws.g64, w,
+                     lam, 1.0 / double(X->n), red);
+  hipLaunchKernelGGL(k_check_dual, dim3(grid_for(X->n, 1024)), dim3(kBlock), 0, s, X->n, loss, y,
+                     ws.r64, lam, red);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// Copy z64 rounded to FP32 into a caller buffer.
+__global__ __launch_bounds__(kBlock) void k_round_f32(const double *src, float *dst, int64_t m) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kBlock)
+    dst[i] = float(src[i]);
+}
+
+int launch_round_f32(const double *src, float *dst, int64_t m, hipStream_t s) {
+  if (m <= 0) return GENCD_OK;
+  hipLaunchKernelGGL(k_round_f32, dim3(grid_for(m)), dim3(kBlock), 0, s, src, dst, m);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+}  // namespace gencd

@@ -1,0 +1,597 @@
+// Host driver of Algorithm 1 and the C-ABI entry points of libgencd.
+//
+// gencd_solve runs, per epoch: the selection order (section 2.1), then for
+// every iteration one Propose launch (Algorithm 2 / 4; for accept-all rules
+// it also applies single-piece updates), the Accept launch of the greedy
+// rules (section 2.3), an Update launch for the remaining updates
+// (Algorithm 3) and a residual refresh.  Every check_every epochs an FP64
+// pass recomputes z = Xw, the objective of Eq. (1) and the KKT violations,
+// re-synchronises the FP32 state from it and decides convergence on the
+// host.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gencd_common.hpp"
+#include "gencd_kernels.hpp"
+
+namespace gencd {
+
+static constexpr size_t kAlign = 256;
+static constexpr int kDefaultPiece = 1024;
+static constexpr int kDefaultGroup = 64;
+static constexpr int64_t kMaxGroups = 2048 * (kBlock / 8);
+
+int64_t max_pieces_for(int64_t k, int64_t nnz, int piece) { return k + nnz / piece + 2; }
+
+namespace {
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(int64_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += size_t(count > 0 ? count : 1) * sizeof(T);
+    return p;
+  }
+};
+}  // namespace
+
+size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, void *base, Ws *ws) {
+  Carver c{static_cast<char *>(base)};
+  Ws w{};
+  const int64_t mp = max_pieces_for(k, nnz, piece);
+  const int64_t scan_len = mp > k + 1 ? mp : k + 1;
+  w.max_pieces = mp;
+  w.scan_part_len = scan_partials_for(scan_len);
+  w.c = c.take<float>(k);
+  w.live = c.take<int32_t>(k);
+  w.all_poff = c.take<int32_t>(k + 1);
+  w.all_pcol = c.take<int32_t>(mp);
+  w.tmp_cnt = c.take<int32_t>(k + 1);
+  w.scan_part = c.take<int32_t>(int64_t(w.scan_part_len));
+  w.cls_off = c.take<int32_t>(k + 1);
+  w.cls_mem = c.take<int32_t>(k);
+  w.col_of_pos = c.take<int32_t>(k);
+  w.poff = c.take<int32_t>(k + 1);
+  w.piece_pos = c.take<int32_t>(mp);
+  w.win_off = c.take<int32_t>(k + 1);
+  w.delta = c.take<float>(k);
+  w.phi = c.take<float>(k);
+  w.gbuf = c.take<float>(k);
+  w.gacc = c.take<float>(mp);
+  w.tick = c.take<int32_t>(k);
+  w.acc = c.take<int32_t>(k);
+  w.z_hi = c.take<float>(n);
+  w.z_lo = c.take<float>(n);
+  w.r = c.take<float>(n);
+  w.w_ckpt = c.take<float>(k);
+  w.z64 = c.take<double>(n);
+  w.r64 = c.take<double>(n);
+  w.g64 = c.take<double>(k);
+  w.red = c.take<double>(16);
+  w.flags = c.take<int32_t>(8);
+  if (ws) *ws = w;
+  return c.off + kAlign;
+}
+
+namespace {
+
+bool csc_ok(const gencd_csc *X) {
+  if (!X || X->n <= 0 || X->k <= 0 || X->nnz < 0) return false;
+  if (X->n > INT32_MAX || X->k >= INT32_MAX) return false;
+  if (!X->col_ptr) return false;
+  if (X->nnz > 0 && (!X->row_idx || !X->val)) return false;
+  return true;
+}
+
+int resolve_schedule(const gencd_params *p, int *piece, int *group) {
+  int g = (p && p->group) ? p->group : kDefaultGroup;
+  if (g != 8 && g != 16 && g != 32 && g != 64) return GENCD_ERR_INVALID_ARG;
+  int pc = (p && p->piece) ? p->piece : kDefaultPiece;
+  if (pc < g || pc % g != 0 || pc > (1 << 22)) return GENCD_ERR_INVALID_ARG;
+  *piece = pc;
+  *group = g;
+  return GENCD_OK;
+}
+
+int params_ok(const gencd_params *p, bool need_rule) {
+  if (!p) return GENCD_ERR_INVALID_ARG;
+  if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return GENCD_ERR_INVALID_ARG;
+  if (!need_rule) return GENCD_OK;
+  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_COLORING) return GENCD_ERR_INVALID_ARG;
+  if ((p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY) && p->select_size <= 0)
+    return GENCD_ERR_INVALID_ARG;
+  if (p->rule == GENCD_THREAD_GREEDY && p->block <= 0) return GENCD_ERR_INVALID_ARG;
+  if (p->rule == GENCD_COLORING && (!p->color || p->num_colors <= 0)) return GENCD_ERR_INVALID_ARG;
+  if (!(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0 || p->check_every < 0)
+    return GENCD_ERR_INVALID_ARG;
+  return GENCD_OK;
+}
+
+// Device -> host copy of the reduction block, then wait for the stream.
+struct Red {
+  double loss_sum, l1;
+  unsigned long long kkt_bits, nnz_w;
+  unsigned long long gmax_bits;
+  double dual_sum;
+  unsigned long long pad[2];
+  unsigned long long acc_nnz, acc_cnt, bad;
+  unsigned long long pad2[5];
+};
+static_assert(sizeof(Red) == 16 * 8, "reduction block layout");
+
+int read_red(const Ws &w, hipStream_t s, Red *out) {
+  GENCD_HIP(hipMemcpyAsync(out, w.red, sizeof(Red), hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipStreamSynchronize(s));
+  return GENCD_OK;
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, sizeof d);
+  return d;
+}
+
+struct Setup {
+  Ws ws{};
+  int piece = kDefaultPiece, group = kDefaultGroup;
+  int32_t total_pieces = 0;
+  int64_t k_live = 0;
+};
+
+// Preprocessing (row a1): validation, piece decomposition, live columns and
+// curvature.  Writes only the workspace.
+int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, void *ws_base,
+          size_t ws_bytes, bool validate_matrix, hipStream_t s, Setup *out) {
+  if (!csc_ok(X) || !y) return GENCD_ERR_INVALID_ARG;
+  int st = resolve_schedule(p, &out->piece, &out->group);
+  if (st) return st;
+  if (max_pieces_for(X->k, X->nnz, out->piece) >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, nullptr, nullptr);
+  if (!ws_base || ws_bytes < need) return GENCD_ERR_WORKSPACE;
+  // align the carve base
+  char *base = static_cast<char *>(ws_base);
+  size_t mis = reinterpret_cast<uintptr_t>(base) % kAlign;
+  if (mis) base += kAlign - mis;
+  workspace_layout(X->n, X->k, X->nnz, out->piece, base, &out->ws);
+  const Ws &w = out->ws;
+  st = fill_f64(w.red, 16, 0.0, s);
+  if (st) return st;
+  st = launch_validate(X, y, loss, validate_matrix, reinterpret_cast<unsigned long long *>(w.red) + 10, s);
+  if (st) return st;
+  st = launch_preprocess(X, loss, out->piece, w, s);
+  if (st) return st;
+  int32_t host[2] = {0, 0};
+  Red r{};
+  GENCD_HIP(hipMemcpyAsync(&host[0], w.all_poff + X->k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipMemcpyAsync(&host[1], w.poff + X->k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  st = read_red(w, s, &r);
+  if (st) return st;
+  if (r.bad & 1ull) return GENCD_ERR_BAD_MATRIX;
+  if (r.bad & 2ull) return GENCD_ERR_BAD_LABELS;
+  out->total_pieces = host[0];
+  out->k_live = host[1];
+  st = launch_curvature(X, loss, out->piece, out->total_pieces, w, s);
+  if (st) return st;
+  st = fill_f32(w.gacc, w.max_pieces, 0.0f, s);
+  if (st) return st;
+  st = fill_i32(w.tick, X->k, 0, s);
+  if (st) return st;
+  return fill_i32(w.acc, X->k, 0, s);
+}
+
+struct CheckOut {
+  double objective, kkt, gap;
+  int64_t nnz_w;
+  unsigned long long acc_nnz, acc_cnt;
+};
+
+int run_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
+              const Setup &su, bool resync, hipStream_t s, CheckOut *out) {
+  int st = launch_check(X, y, loss, lam, w, su.piece, su.total_pieces, su.ws, resync, s);
+  if (st) return st;
+  Red r{};
+  st = read_red(su.ws, s, &r);
+  if (st) return st;
+  out->objective = r.loss_sum / double(X->n) + lam * r.l1;
+  out->kkt = bits_to_double(r.kkt_bits);
+  out->gap = out->objective - r.dual_sum / double(X->n);
+  out->nnz_w = int64_t(r.nnz_w);
+  out->acc_nnz = r.acc_nnz;
+  out->acc_cnt = r.acc_cnt;
+  return GENCD_OK;
+}
+
+bool converged(const gencd_params *p, const CheckOut &ck) {
+  if (!(ck.kkt <= p->kkt_tol)) return false;
+  return p->gap_tol <= 0.0 || ck.gap <= p->gap_tol * std::fabs(ck.objective);
+}
+
+int mode_of(int rule) {
+  if (rule == GENCD_COLORING) return 1;
+  if (rule == GENCD_THREAD_GREEDY || rule == GENCD_GREEDY) return 2;
+  return 0;
+}
+
+IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, const Setup &su,
+                   float *w, float *z_hi, float *z_lo) {
+  const Ws &ws = su.ws;
+  IterArgs a{};
+  a.col_ptr = X->col_ptr;
+  a.row_idx = X->row_idx;
+  a.val = X->val;
+  a.y = y;
+  a.n_f = float(X->n);
+  a.loss = p->loss;
+  a.lam = float(p->lambda);
+  a.piece = su.piece;
+  a.c = ws.c;
+  a.w = w;
+  a.z_hi = z_hi;
+  a.z_lo = z_lo;
+  a.r = ws.r;
+  a.col_of_pos = ws.col_of_pos;
+  a.poff = ws.poff;
+  a.piece_pos = ws.piece_pos;
+  a.delta = ws.delta;
+  a.phi = ws.phi;
+  a.gacc = ws.gacc;
+  a.gout = nullptr;
+  a.tick = ws.tick;
+  a.acc = ws.acc;
+  a.counters = reinterpret_cast<unsigned long long *>(ws.red) + 8;
+  return a;
+}
+
+// Colour classes: live members of every colour (order inside a class does
+// not affect the result: the members' rows are disjoint).
+__global__ void k_class_count(const int32_t *live, int64_t k_live, const int32_t *color,
+                              int32_t C, int32_t *cnt, unsigned long long *bad) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < k_live;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    int32_t c = color[live[t]];
+    if (c < 0 || c >= C)
+      atomicOr(bad, 4ull);
+    else
+      atomicAdd(&cnt[c], 1);
+  }
+}
+
+__global__ void k_class_fill(const int32_t *live, int64_t k_live, const int32_t *color, int32_t C,
+                             const int32_t *off, int32_t *fill, int32_t *mem) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < k_live;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    int32_t j = live[t];
+    int32_t c = color[j];
+    if (c < 0 || c >= C) continue;
+    int32_t pos = atomicAdd(&fill[c], 1);
+    mem[off[c] + pos] = j;
+  }
+}
+
+int build_classes(const Setup &su, const int32_t *color, int32_t C, hipStream_t s,
+                  std::vector<int32_t> *sizes) {
+  const Ws &w = su.ws;
+  int st = fill_i32(w.tmp_cnt, C + 1, 0, s);
+  if (st) return st;
+  unsigned grid = unsigned(std::min<int64_t>((su.k_live + 255) / 256 + 1, 4096));
+  hipLaunchKernelGGL(k_class_count, dim3(grid), dim3(256), 0, s, w.live, su.k_live, color, C,
+                     w.tmp_cnt, reinterpret_cast<unsigned long long *>(w.red) + 10);
+  st = scan_exclusive(w.tmp_cnt, w.cls_off, C, w.scan_part, s);
+  if (st) return st;
+  st = fill_i32(w.tmp_cnt, C + 1, 0, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_class_fill, dim3(grid), dim3(256), 0, s, w.live, su.k_live, color, C,
+                     w.cls_off, w.tmp_cnt, w.cls_mem);
+  GENCD_HIP(hipGetLastError());
+  std::vector<int32_t> off(size_t(C) + 1);
+  GENCD_HIP(hipMemcpyAsync(off.data(), w.cls_off, sizeof(int32_t) * (C + 1),
+                           hipMemcpyDeviceToHost, s));
+  Red r{};
+  st = read_red(w, s, &r);
+  if (st) return st;
+  if (r.bad & 4ull) return GENCD_ERR_INVALID_ARG;
+  sizes->resize(size_t(C));
+  for (int32_t c = 0; c < C; ++c) (*sizes)[c] = off[c + 1] - off[c];
+  return GENCD_OK;
+}
+
+__global__ void k_check_list(const int32_t *J, int64_t m, int64_t k, unsigned long long *bad) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < m;
+       t += int64_t(gridDim.x) * blockDim.x)
+    if (J[t] < 0 || J[t] >= k) atomicOr(bad, 8ull);
+}
+
+int64_t groups_for(int64_t positions, int64_t extra_pieces) {
+  int64_t g = positions + extra_pieces;
+  return g < kMaxGroups ? g : kMaxGroups;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Solve
+// ---------------------------------------------------------------------------
+int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float *w, float *z,
+               void *ws_base, size_t ws_bytes, hipStream_t s, gencd_stats *stats) {
+  auto t0 = std::chrono::steady_clock::now();
+  gencd_stats loc{};
+  gencd_stats *st_out = stats ? stats : &loc;
+  std::memset(st_out, 0, sizeof(*st_out));
+  int st = params_ok(p, true);
+  if (st) return st;
+  if (!w) return GENCD_ERR_INVALID_ARG;
+  Setup su;
+  st = setup(X, y, p->loss, p, ws_base, ws_bytes, (p->flags & GENCD_VALIDATE_DEVICE) != 0, s, &su);
+  if (st) return st;
+  const Ws &ws = su.ws;
+  const int rule = p->rule;
+  const int mode = mode_of(rule);
+  const int64_t k_live = su.k_live;
+  const int64_t extra = int64_t(su.total_pieces) - k_live;
+  std::vector<int32_t> cls_sizes;
+  int64_t C = 0;
+  if (rule == GENCD_COLORING) {
+    C = p->num_colors;
+    if (C > X->k) return GENCD_ERR_INVALID_ARG;
+    st = build_classes(su, p->color, int32_t(C), s, &cls_sizes);
+    if (st) return st;
+  }
+  if (!(p->flags & GENCD_WARM_START)) {
+    st = fill_f32(w, X->k, 0.0f, s);
+    if (st) return st;
+  }
+  // start: z = Xw (FP64), FP32 state, objective, KKT
+  CheckOut ck{};
+  st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
+  if (st) return st;
+  st = copy_f32(ws.w_ckpt, w, X->k, s);
+  if (st) return st;
+  double best = ck.objective;
+  if (!std::isfinite(best)) return GENCD_ERR_DIVERGED;
+  st_out->objective = ck.objective;
+  st_out->kkt_max = ck.kkt;
+  st_out->gap = ck.gap;
+  st_out->nnz_w = ck.nnz_w;
+  st_out->num_colors = int32_t(C);
+  int status = GENCD_NOT_CONVERGED;
+  if (converged(p, ck)) {
+    status = GENCD_OK;
+    st_out->converged = 1;
+  }
+
+  int64_t S;
+  if (rule == GENCD_CYCLIC || rule == GENCD_STOCHASTIC) S = 1;
+  else if (rule == GENCD_GREEDY) S = k_live;
+  else S = p->select_size;
+  if (S > k_live) S = k_live;
+  const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
+  IterArgs a = base_args(X, y, p, su, w, ws.z_hi, ws.z_lo);
+  unsigned long long acc_nnz_seen = 0, acc_cnt_seen = 0;
+
+  for (int64_t e = 0; status != GENCD_OK && e < p->max_epochs && k_live > 0; ++e) {
+    st = launch_epoch_order(ws, k_live, rule, p->seed, e, C, s);
+    if (st) return st;
+    const int64_t T = (rule == GENCD_COLORING) ? C : (k_live + S - 1) / S;
+    PermKey cpk{};
+    if (rule == GENCD_COLORING) cpk = make_perm_key(C, p->seed, e);
+    for (int64_t t = 0; t < T; ++t) {
+      int64_t positions;
+      if (rule == GENCD_COLORING) {
+        a.win_off = ws.win_off;
+        a.t = int32_t(t);
+        positions = cls_sizes[size_t(perm_apply(cpk, uint64_t(t)))];
+      } else {
+        a.win_off = nullptr;
+        a.win_lo = int32_t(t * S);
+        a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
+        positions = a.win_hi - a.win_lo;
+      }
+      if (positions == 0) continue;
+      const int64_t B = (rule == GENCD_THREAD_GREEDY) ? p->block : positions;
+      const bool deferred = (mode == 2) || extra > 0;
+      st = launch_iteration(a, su.group, mode, B, groups_for(positions, extra),
+                            (positions + B - 1) / B, deferred, s);
+      if (st) return st;
+      st_out->iters++;
+      if (mode != 2) st_out->coord_updates += positions;
+    }
+    st_out->epochs = e + 1;
+    st_out->nnz_visits += X->nnz;
+    if (mode != 2) st_out->nnz_updates += X->nnz;
+    if ((e + 1) % check_every == 0 || e + 1 == p->max_epochs) {
+      st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
+      if (st) return st;
+      if (mode == 2) {
+        st_out->coord_updates += int64_t(ck.acc_cnt - acc_cnt_seen);
+        st_out->nnz_updates += int64_t(ck.acc_nnz - acc_nnz_seen);
+        acc_cnt_seen = ck.acc_cnt;
+        acc_nnz_seen = ck.acc_nnz;
+      }
+      const bool bad = !std::isfinite(ck.objective) ||
+                       ck.objective > best + 1e-3 * std::fabs(best) + 1e-12;
+      if (bad && (rule == GENCD_SHOTGUN || rule == GENCD_THREAD_GREEDY) && S > 1) {
+        // Divergence guard: restore the last checked point, halve |J|.
+        st = copy_f32(w, ws.w_ckpt, X->k, s);
+        if (st) return st;
+        st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
+        if (st) return st;
+        S = (S + 1) / 2;
+        continue;
+      }
+      if (!std::isfinite(ck.objective)) return GENCD_ERR_DIVERGED;
+      st_out->objective = ck.objective;
+      st_out->kkt_max = ck.kkt;
+      st_out->gap = ck.gap;
+      st_out->nnz_w = ck.nnz_w;
+      if (ck.objective <= best) {
+        best = ck.objective;
+        st = copy_f32(ws.w_ckpt, w, X->k, s);
+        if (st) return st;
+      }
+      if (converged(p, ck)) {
+        status = GENCD_OK;
+        st_out->converged = 1;
+      }
+    }
+  }
+  if (k_live == 0 && converged(p, ck)) status = GENCD_OK;
+  if (z) {
+    st = launch_round_f32(ws.z64, z, X->n, s);
+    if (st) return st;
+  }
+  GENCD_HIP(hipStreamSynchronize(s));
+  st_out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// One step on a given J
+// ---------------------------------------------------------------------------
+int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const int32_t *J,
+              int64_t nJ, float *w, float *z_hi, float *z_lo, float *g, float *delta, float *phi,
+              int32_t *accepted, void *ws_base, size_t ws_bytes, hipStream_t s) {
+  int st = params_ok(p, false);
+  if (st) return st;
+  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_COLORING) return GENCD_ERR_INVALID_ARG;
+  if (p->rule == GENCD_THREAD_GREEDY && p->block <= 0) return GENCD_ERR_INVALID_ARG;
+  if (!w || !z_hi || !z_lo || nJ < 0 || (nJ > 0 && !J)) return GENCD_ERR_INVALID_ARG;
+  if (nJ > X->k) return GENCD_ERR_INVALID_ARG;
+  Setup su;
+  st = setup(X, y, p->loss, p, ws_base, ws_bytes, (p->flags & GENCD_VALIDATE_DEVICE) != 0, s, &su);
+  if (st) return st;
+  if (nJ == 0) return GENCD_OK;
+  const Ws &ws = su.ws;
+  {
+    unsigned grid = unsigned(std::min<int64_t>((nJ + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_check_list, dim3(grid), dim3(256), 0, s, J, nJ, X->k,
+                       reinterpret_cast<unsigned long long *>(ws.red) + 10);
+    Red r{};
+    st = read_red(ws, s, &r);
+    if (st) return st;
+    if (r.bad & 8ull) return GENCD_ERR_INVALID_ARG;
+  }
+  st = launch_refresh_all(X->n, p->loss, y, z_hi, z_lo, ws.r, s);
+  if (st) return st;
+  st = launch_list_order(ws, J, nJ, s);
+  if (st) return st;
+  const int mode = mode_of(p->rule);
+  IterArgs a = base_args(X, y, p, su, w, z_hi, z_lo);
+  a.win_off = nullptr;
+  a.win_lo = 0;
+  a.win_hi = int32_t(nJ);
+  a.gout = g;
+  const int64_t B = (p->rule == GENCD_THREAD_GREEDY) ? p->block : nJ;
+  const int64_t extra = int64_t(su.total_pieces) - su.k_live;
+  st = launch_iteration(a, su.group, mode, B, groups_for(nJ, extra), (nJ + B - 1) / B, true, s);
+  if (st) return st;
+  if (delta) st = copy_f32(delta, ws.delta, nJ, s);
+  if (st) return st;
+  if (phi) st = copy_f32(phi, ws.phi, nJ, s);
+  if (st) return st;
+  if (accepted) st = (mode == 2) ? copy_i32(accepted, ws.acc, nJ, s) : fill_i32(accepted, nJ, 1, s);
+  if (st) return st;
+  GENCD_HIP(hipStreamSynchronize(s));
+  return GENCD_OK;
+}
+
+int check_impl(const gencd_csc *X, const float *y, int loss, double lambda, const float *w,
+               double *z64, double *g64, gencd_stats *stats, void *ws_base, size_t ws_bytes,
+               hipStream_t s) {
+  gencd_params p{};
+  p.loss = loss;
+  p.lambda = lambda;
+  int st = params_ok(&p, false);
+  if (st) return st;
+  Setup su;
+  st = setup(X, y, loss, &p, ws_base, ws_bytes, false, s, &su);
+  if (st) return st;
+  CheckOut ck{};
+  st = run_check(X, y, loss, lambda, w, su, false, s, &ck);
+  if (st) return st;
+  if (z64) GENCD_HIP(hipMemcpyAsync(z64, su.ws.z64, sizeof(double) * X->n, hipMemcpyDeviceToDevice, s));
+  if (g64) GENCD_HIP(hipMemcpyAsync(g64, su.ws.g64, sizeof(double) * X->k, hipMemcpyDeviceToDevice, s));
+  GENCD_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->objective = ck.objective;
+    stats->kkt_max = ck.kkt;
+    stats->gap = ck.gap;
+    stats->nnz_w = ck.nnz_w;
+  }
+  return GENCD_OK;
+}
+
+}  // namespace gencd
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace gencd;
+
+extern "C" {
+
+const char *gencd_status_string(int status) {
+  switch (status) {
+    case GENCD_OK: return "ok";
+    case GENCD_NOT_CONVERGED: return "not converged (max_epochs reached)";
+    case GENCD_ERR_INVALID_ARG: return "invalid argument";
+    case GENCD_ERR_BAD_MATRIX: return "invalid CSC matrix";
+    case GENCD_ERR_BAD_LABELS: return "logistic labels must be -1 or +1";
+    case GENCD_ERR_WORKSPACE: return "workspace missing or too small";
+    case GENCD_ERR_UNSUPPORTED: return "unsupported option";
+    case GENCD_ERR_DIVERGED: return "diverged (non-finite objective)";
+    case GENCD_ERR_HIP: return "HIP runtime error";
+    case GENCD_ERR_BUDGET: return "request exceeds the memory budget";
+    default: return "unknown status";
+  }
+}
+
+int gencd_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out_bytes) {
+  if (!out_bytes || !X || X->n <= 0 || X->k <= 0 || X->nnz < 0) return GENCD_ERR_INVALID_ARG;
+  int piece, group;
+  int st = resolve_schedule(p, &piece, &group);
+  if (st) return st;
+  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, nullptr, nullptr) + kAlign;
+  return GENCD_OK;
+}
+
+int gencd_lambda_max(const gencd_csc *X, const float *y, int32_t loss, double *out, void *ws,
+                     size_t ws_bytes, hipStream_t stream) {
+  if (!out) return GENCD_ERR_INVALID_ARG;
+  gencd_stats st{};
+  int rc = check_impl(X, y, loss, 0.0, nullptr, nullptr, nullptr, &st, ws, ws_bytes, stream);
+  if (rc) return rc;
+  *out = st.kkt_max;
+  return GENCD_OK;
+}
+
+int gencd_solve(const gencd_csc *X, const float *y, const gencd_params *p, float *w, float *z,
+                void *ws, size_t ws_bytes, hipStream_t stream, gencd_stats *stats) {
+  return solve_impl(X, y, p, w, z, ws, ws_bytes, stream, stats);
+}
+
+int gencd_step(const gencd_csc *X, const float *y, const gencd_params *p, const int32_t *J,
+               int64_t nJ, float *w, float *z_hi, float *z_lo, float *g, float *delta,
+               float *phi, int32_t *accepted, void *ws, size_t ws_bytes, hipStream_t stream) {
+  return step_impl(X, y, p, J, nJ, w, z_hi, z_lo, g, delta, phi, accepted, ws, ws_bytes, stream);
+}
+
+int gencd_check(const gencd_csc *X, const float *y, int32_t loss, double lambda, const float *w,
+                double *z64, double *g64, gencd_stats *stats, void *ws, size_t ws_bytes,
+                hipStream_t stream) {
+  if (!w) return GENCD_ERR_INVALID_ARG;
+  return check_impl(X, y, loss, lambda, w, z64, g64, stats, ws, ws_bytes, stream);
+}
+
+int gencd_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hipStream_t stream) {
+  if (m < 0 || m >= INT32_MAX || (m > 0 && !out)) return GENCD_ERR_INVALID_ARG;
+  int st = launch_select_perm(m, seed, epoch, out, stream);
+  if (st) return st;
+  return hipStreamSynchronize(stream) == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+"""Python binding of libgencd (include/gencd.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Tensors are torch tensors on the current HIP device; the work is enqueued on
+torch's current stream.  If the library has not been built this module raises
+on first use; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgencd.so")
+
+OK, NOT_CONVERGED = 0, 1
+SQUARED, LOGISTIC = 0, 1
+CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING = range(6)
+WARM_START, VALIDATE_DEVICE, USE_GRAPH = 0x1, 0x2, 0x4
+RULES = {"cyclic": CYCLIC, "stochastic": STOCHASTIC, "shotgun": SHOTGUN,
+         "thread_greedy": THREAD_GREEDY, "greedy": GREEDY, "coloring": COLORING}
+
+
+class GencdError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class Csc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("nnz", C.c_int64),
+                ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("loss", C.c_int32), ("rule", C.c_int32), ("lam", C.c_double),
+                ("select_size", C.c_int64), ("block", C.c_int64), ("seed", C.c_uint64),
+                ("kkt_tol", C.c_double), ("gap_tol", C.c_double), ("max_epochs", C.c_int64),
+                ("check_every", C.c_int64),
+                ("flags", C.c_uint32), ("color", C.c_void_p), ("num_colors", C.c_int32),
+                ("piece", C.c_int32), ("group", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("epochs", C.c_int64), ("coord_updates", C.c_int64),
+                ("nnz_visits", C.c_int64), ("nnz_updates", C.c_int64), ("objective", C.c_double),
+                ("kkt_max", C.c_double), ("gap", C.c_double), ("lambda_max", C.c_double),
+                ("seconds", C.c_double),
+                ("nnz_w", C.c_int64), ("converged", C.c_int32), ("num_colors", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+_SIGS = {
+    "gencd_status_string": (C.c_char_p, [C.c_int]),
+    "gencd_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_lambda_max": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_size_t, C.c_void_p]),
+    "gencd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "gencd_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "gencd_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                              C.c_void_p]),
+    "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "gencd_color_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gencd_color": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                              C.c_void_p]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1206_6409_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def status_string(status):
+    return lib().gencd_status_string(int(status)).decode()
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(status, where, allow=(OK,)):
+    if status not in allow:
+        raise GencdError(status, where)
+    return status
+
+
+@dataclass
+class Matrix:
+    """A CSC matrix on the device (int64 col_ptr, int32 row_idx, float32 val)."""
+    n: int
+    k: int
+    col_ptr: torch.Tensor
+    row_idx: torch.Tensor
+    val: torch.Tensor
+    _s: Csc = field(default=None, repr=False)
+
+    def __post_init__(self):
+        assert self.col_ptr.dtype == torch.int64 and self.row_idx.dtype == torch.int32
+        assert self.val.dtype == torch.float32
+        self._s = Csc(int(self.n), int(self.k), int(self.row_idx.numel()),
+                      self.col_ptr.data_ptr(), self.row_idx.data_ptr() if self.row_idx.numel() else None,
+                      self.val.data_ptr() if self.val.numel() else None)
+
+    @property
+    def nnz(self):
+        return int(self.row_idx.numel())
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    @classmethod
+    def from_numpy(cls, n, k, col_ptr, row_idx, val, device="cuda"):
+        return cls(int(n), int(k), torch.as_tensor(col_ptr, dtype=torch.int64).to(device),
+                   torch.as_tensor(row_idx, dtype=torch.int32).to(device),
+                   torch.as_tensor(val, dtype=torch.float32).to(device))
+
+    @classmethod
+    def of(cls, prob, device="cuda"):
+        return cls.from_numpy(prob.n, prob.k, prob.col_ptr, prob.row_idx, prob.val, device)
+
+
+def make_params(loss, lam, rule=SHOTGUN, select_size=1, block=1, seed=0, tol=1e-6,
+                gap_tol=1e-7, max_epochs=1000, check_every=1, flags=0, colors=None,
+                num_colors=0, piece=0, group=0):
+    if isinstance(rule, str):
+        rule = RULES[rule]
+    return Params(int(loss), int(rule), float(lam), int(select_size), int(block),
+                  C.c_uint64(seed).value, float(tol), float(gap_tol), int(max_epochs),
+                  int(check_every),
+                  int(flags), colors.data_ptr() if colors is not None else None, int(num_colors),
+                  int(piece), int(group))
+
+
+def workspace_bytes(X: Matrix, params: Params = None):
+    out = C.c_size_t()
+    _check(lib().gencd_workspace_bytes(X.ref, C.byref(params) if params is not None else None,
+                                       C.byref(out)), "gencd_workspace_bytes")
+    return out.value
+
+
+def workspace(X: Matrix, params: Params = None, device=None):
+    nbytes = workspace_bytes(X, params)
+    dev = device if device is not None else X.col_ptr.device
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+
+def lambda_max(X: Matrix, y: torch.Tensor, loss, ws=None):
+    ws = workspace(X) if ws is None else ws
+    out = C.c_double()
+    _check(lib().gencd_lambda_max(X.ref, _ptr(y), int(loss), C.byref(out), _ptr(ws), ws.numel(),
+                                  _stream()), "gencd_lambda_max")
+    return out.value
+
+
+@dataclass
+class SolveResult:
+    status: int
+    w: torch.Tensor
+    z: torch.Tensor
+    stats: dict
+
+
+def solve(X: Matrix, y: torch.Tensor, params: Params, w0=None, ws=None, want_z=True):
+    ws = workspace(X, params) if ws is None else ws
+    if w0 is not None:
+        w = w0.clone().to(torch.float32)
+        params.flags |= WARM_START
+    else:
+        w = torch.empty(X.k, dtype=torch.float32, device=X.col_ptr.device)
+    z = torch.empty(X.n, dtype=torch.float32, device=X.col_ptr.device) if want_z else None
+    st = Stats()
+    rc = lib().gencd_solve(X.ref, _ptr(y), C.byref(params), _ptr(w), _ptr(z), _ptr(ws),
+                           ws.numel(), _stream(), C.byref(st))
+    _check(rc, "gencd_solve", allow=(OK, NOT_CONVERGED))
+    return SolveResult(rc, w, z, st.as_dict())
+
+
+@dataclass
+class StepResult:
+    g: torch.Tensor
+    delta: torch.Tensor
+    phi: torch.Tensor
+    accepted: torch.Tensor
+
+
+def step(X: Matrix, y, params: Params, J: torch.Tensor, w, z_hi, z_lo, ws=None):
+    """One iteration on J; w, z_hi, z_lo (float32 device tensors) are updated in place."""
+    ws = workspace(X, params) if ws is None else ws
+    m = J.numel()
+    dev = X.col_ptr.device
+    g = torch.empty(m, dtype=torch.float32, device=dev)
+    d = torch.empty(m, dtype=torch.float32, device=dev)
+    ph = torch.empty(m, dtype=torch.float32, device=dev)
+    acc = torch.empty(m, dtype=torch.int32, device=dev)
+    rc = lib().gencd_step(X.ref, _ptr(y), C.byref(params), _ptr(J), m, _ptr(w), _ptr(z_hi),
+                          _ptr(z_lo), _ptr(g), _ptr(d), _ptr(ph), _ptr(acc), _ptr(ws), ws.numel(),
+                          _stream())
+    _check(rc, "gencd_step")
+    return StepResult(g, d, ph, acc)
+
+
+@dataclass
+class CheckResult:
+    objective: float
+    kkt: float
+    nnz_w: int
+    z64: torch.Tensor
+    g64: torch.Tensor
+    gap: float = 0.0
+
+
+def check(X: Matrix, y, loss, lam, w, ws=None):
+    ws = workspace(X) if ws is None else ws
+    dev = X.col_ptr.device
+    z64 = torch.empty(X.n, dtype=torch.float64, device=dev)
+    g64 = torch.empty(X.k, dtype=torch.float64, device=dev)
+    st = Stats()
+    rc = lib().gencd_check(X.ref, _ptr(y), int(loss), float(lam), _ptr(w), _ptr(z64), _ptr(g64),
+                           C.byref(st), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "gencd_check")
+    return CheckResult(st.objective, st.kkt_max, st.nnz_w, z64, g64, st.gap)
+
+
+def select_perm(m, seed, epoch, device="cuda"):
+    out = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+    _check(lib().gencd_select_perm(int(m), C.c_uint64(seed).value, int(epoch), _ptr(out),
+                                   _stream()), "gencd_select_perm")
+    return out[:m]
+
+
+def color(X: Matrix, ws=None):
+    """Greedy partial distance-2 colouring of the columns: (int32[k] colours, count)."""
+    if ws is None:
+        nb = C.c_size_t()
+        _check(lib().gencd_color_workspace_bytes(X.ref, C.byref(nb)), "gencd_color_workspace_bytes")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=X.col_ptr.device)
+    out = torch.empty(X.k, dtype=torch.int32, device=X.col_ptr.device)
+    nc = C.c_int32()
+    _check(lib().gencd_color(X.ref, _ptr(out), C.byref(nc), _ptr(ws), ws.numel(), _stream()),
+           "gencd_color")
+    return out, nc.value

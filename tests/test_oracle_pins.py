@@ -502,3 +502,38 @@ def test_thread_greedy_ties_go_to_the_first_position():
             ph = res2.phi[2 * blk:2 * blk + 2]
             first = 2 * blk + int(np.argmin(ph))
             assert res2.accepted[first] == 1
+
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_duality_gap_bounds_suboptimality(kind):
+    """Weak duality: gap(w) >= P(w) - P* >= 0 for any w, and the gap vanishes
+    at the optimum (brute-force optimum for k = 5)."""
+    import itertools
+    k = 5
+    P, X, A, y = small_problem(40, k, kind, 81, density=0.7)
+    lam = 0.2 * O.lambda_max(X, y, kind)
+    best = dense_objective(A, y, kind, lam, np.zeros(k))
+    for s in itertools.product((-1, 0, 1), repeat=k):
+        s = np.array(s, dtype=float)
+        act = np.nonzero(s)[0]
+        if act.size == 0:
+            continue
+        wa = _newton_reduced(A[:, act], y, kind, lam, s[act])
+        if wa is None or np.any(np.sign(wa) != s[act]):
+            continue
+        w = np.zeros(k)
+        w[act] = wa
+        best = min(best, dense_objective(A, y, kind, lam, w))
+    rng = np.random.default_rng(2)
+    for _ in range(30):
+        w = rng.normal(size=k) * (rng.random(k) < 0.6)
+        gap, prim = O.duality_gap(X, y, kind, lam, w)
+        assert prim == pytest.approx(dense_objective(A, y, kind, lam, w), rel=1e-13)
+        assert gap >= prim - best - 1e-12
+    r = O.solve(X, y, kind, lam, O.CYCLIC, tol=1e-12, max_epochs=100000)
+    gap, prim = O.duality_gap(X, y, kind, lam, r.w)
+    assert 0 <= gap + 1e-15 and gap <= 1e-10
+    # at w = 0 with lambda = lambda_max the dual point is feasible unscaled: gap = 0
+    lm = O.lambda_max(X, y, kind)
+    gap0, _ = O.duality_gap(X, y, kind, lm, np.zeros(k))
+    assert abs(gap0) <= 1e-14
