@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of GenCD solves on one MI355X.
+
+Workload: the tf-idf-like logistic problem (n = 100,000 samples, k = 500,000
+features, Zipf(1.1) column popularity, ~50 nonzeros per row, lognormal values,
+rows L2-normalised, labels from a 500-sparse w*), lambda = 0.05 lambda_max,
+Shotgun with |J| = 4096.  One step = one full solve from w = 0 to FP64
+KKT <= 1e-6 (inputs already resident in HBM).
+
+Printed value: nnz-updates/s = sum over accepted proposals of nnz_j, divided
+by the wall time of the timed solves.  Also reported: solves/s, coordinate
+updates/s, the Thread-Greedy variant, the roofline of the dominant kernel
+(Propose, timed with HIP events on the solve's stream) and the FP64 oracle
+timed on the host as the CPU baseline.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink n and k (tests only)")
+    ap.add_argument("--select", type=int, default=4096)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-thread-greedy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "row-sharded design is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1206_6409_amd import gencd as G
+    from paper_1206_6409_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    G.lib()  # fail loudly if the HIP library is missing
+    torch.cuda.set_device(0)
+
+    t = time.time()
+    P = synth.c2_zipf_logistic(scale=args.scale)
+    log(f"generated {P.name}: nnz={P.nnz} in {time.time() - t:.1f}s")
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device="cuda")
+    lam_max = G.lambda_max(X, y, P.loss)
+    lam = 0.05 * lam_max
+    base = dict(loss=P.loss, lam=lam, rule=G.SHOTGUN, select_size=args.select, seed=7,
+                tol=args.tol, max_epochs=100000, check_every=1)
+    ws = G.workspace(X, G.make_params(**base))
+
+    def run(rule, steps, warmup, flags=0, **kw):
+        pr = dict(base, rule=rule, **kw)
+        for _ in range(warmup):
+            G.solve(X, y, G.make_params(**pr), ws=ws)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = G.solve(X, y, G.make_params(flags=flags, **pr), ws=ws)
+            stats.append(res.stats)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert all(s["converged"] == 1 for s in stats), stats[-1]
+        return dt, stats, res
+
+    log("timing Shotgun solves")
+    dt, stats, res = run(G.SHOTGUN, args.steps, args.warmup, flags=G.PROFILE)
+    nnz_upd = sum(s["nnz_updates"] for s in stats)
+    coord_upd = sum(s["coord_updates"] for s in stats)
+    value = nnz_upd / dt
+    last = stats[-1]
+    prof_ms = sum(s["prof_kernel_ms"] for s in stats)
+    prof_launch = sum(s["prof_launches"] for s in stats)
+    prof_bytes = sum(s["prof_bytes"] for s in stats)
+    achieved = prof_bytes / (prof_ms * 1e-3) / 1e9 if prof_ms > 0 else 0.0
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_propose (fused Propose + single-piece Update)",
+        "achieved": round(achieved, 3),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 6),
+        "traffic": None,
+        "avg_launch_us": round(prof_ms * 1e3 / max(prof_launch, 1), 3),
+        "bytes_per_launch": round(prof_bytes / max(prof_launch, 1), 1),
+        "launches": prof_launch,
+    }
+    out = {
+        "metric": "nnz-updates/s of Shotgun solves to FP64 KKT 1e-6",
+        "value": value,
+        "unit": "nnz-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{P.name}: Zipf(1.1) ~50 nnz/row, lognormal row-normalised values, "
+                        f"logistic, lambda=0.05*lambda_max, Shotgun |J|={args.select}",
+            "n": P.n, "k": P.k, "nnz": P.nnz, "lambda": lam, "lambda_max": lam_max,
+            "kkt_tol": args.tol, "path": "plain (per-iteration launches)",
+        },
+        "solves_per_s": args.steps / dt,
+        "coord_updates_per_s": coord_upd / dt,
+        "epochs_per_solve": last["epochs"],
+        "iters_per_solve": last["iters"],
+        "objective": last["objective"],
+        "kkt_max": last["kkt_max"],
+        "duality_gap": last["gap"],
+        "nnz_w": last["nnz_w"],
+        "roofline": roofline,
+    }
+
+    if not args.no_thread_greedy:
+        log("timing Thread-Greedy solves")
+        dt2, st2, _ = run(G.THREAD_GREEDY, 1, 0, block=64)
+        out["thread_greedy"] = {
+            "nnz_updates_per_s": st2[-1]["nnz_updates"] / dt2,
+            "solves_per_s": 1.0 / dt2,
+            "epochs": st2[-1]["epochs"], "objective": st2[-1]["objective"],
+            "kkt_max": st2[-1]["kkt_max"], "block": 64,
+        }
+
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        log("timing the FP64 oracle on the host")
+        Xo = O.Matrix.of(P)
+        yo = P.y.astype(np.float64)
+        lam_o = 0.05 * O.lambda_max(Xo, yo, P.loss)
+        t0 = time.perf_counter()
+        r = O.solve(Xo, yo, P.loss, lam_o, O.SHOTGUN, select_size=args.select, seed=7,
+                    tol=args.tol, max_epochs=100000)
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": r.nnz_updates / tc,
+            "unit": "nnz-updates/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"one full Shotgun solve of the same workload to KKT {args.tol} "
+                      f"({r.epochs} epochs, {tc:.1f} s) on 1 thread of {cpu_model()}",
+            "objective": r.objective,
+        }
+        out["objective_rel_diff_vs_oracle"] = abs(last["objective"] - r.objective) / abs(r.objective)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

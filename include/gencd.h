@@ -73,6 +73,7 @@ typedef enum {
 #define GENCD_WARM_START 0x1u      /* w holds the starting point on entry */
 #define GENCD_VALIDATE_DEVICE 0x2u /* check CSC structure and labels on the device */
 #define GENCD_USE_GRAPH 0x4u       /* replay each epoch as a captured HIP graph */
+#define GENCD_PROFILE 0x8u         /* time every Propose launch with HIP events */
 
 /* Device CSC matrix (see the conventions above). */
 typedef struct {
@@ -115,6 +116,14 @@ typedef struct {
   int64_t nnz_w;          /* nonzeros of w at the last check */
   int32_t converged;
   int32_t num_colors;
+  /* GENCD_PROFILE: Propose launches, their summed duration (HIP events on
+   * the solve's stream) and the algorithmic bytes they moved: 12 B per
+   * proposed nonzero (row index, value, residual), 20 B per proposed column
+   * (column pointers, w, c, delta/phi), and 16 B per nonzero of a fused
+   * update (z_hi, z_lo read and written). */
+  int64_t prof_launches;
+  double prof_kernel_ms;
+  double prof_bytes;
 } gencd_stats;
 
 const char *gencd_status_string(int status);

@@ -72,7 +72,16 @@ __device__ __forceinline__ void propose_f32(float g, float c, float w, float lam
   float b = (g + lam) / c;
   float psi = w < a ? a : (w > b ? b : w);
   d = -psi;
-  phi = 0.5f * c * d * d + g * d + lam * (fabsf(w + d) - fabsf(w));
+  // Eq. 9.  When w and w + d have the same sign, lam (|w + d| - |w|) is
+  // +-lam d exactly; factoring it out avoids the cancellation of two FP32
+  // magnitudes when |d| << |w| (phi is then tiny and decides the Accept).
+  const float wd = w + d;
+  if (w > 0.0f && wd >= 0.0f)
+    phi = d * (0.5f * c * d + (g + lam));
+  else if (w < 0.0f && wd <= 0.0f)
+    phi = d * (0.5f * c * d + (g - lam));
+  else
+    phi = 0.5f * c * d * d + g * d + lam * (fabsf(wd) - fabsf(w));
 }
 
 // ---------------------------------------------------------------------------
@@ -180,7 +189,7 @@ struct Ws {
   float *delta;          // [k]
   float *phi;            // [k]
   float *gbuf;           // [k]
-  float *gacc;           // [k]
+  float *gacc;           // [max_pieces] partial sums of split columns
   int32_t *tick;         // [k]
   int32_t *acc;          // [k]
   // state

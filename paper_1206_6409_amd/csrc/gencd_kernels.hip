@@ -466,7 +466,10 @@ __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
       a.delta[slot] = d;
       a.phi[slot] = ph;
       if (a.gout) a.gout[slot] = g;
-      if (MODE != 2 && d != 0.0f) a.w[j] = wj + d;
+      if (MODE != 2 && d != 0.0f) {
+        a.w[j] = wj + d;
+        if (np == 1) atomicAdd(a.counters + 3, (unsigned long long)(end - beg));
+      }
     }
     if (MODE != 2 && np == 1) {
       d = __shfl(d, 0, G);
@@ -604,18 +607,24 @@ int launch_refresh_all(int64_t n, int loss, const float *y, const float *z_hi, c
 
 template <int G>
 static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, int64_t groups,
-                              int64_t nblocks_accept, bool deferred_work, hipStream_t s) {
+                              int64_t nblocks_accept, bool deferred_work, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 grid(groups_grid(groups, G)), blk(kBlock);
-  if (mode == 0) {
+  if (ev0) hipEventRecord(ev0, s);
+  if (mode == 0)
     hipLaunchKernelGGL((k_propose<G, 0>), grid, blk, 0, s, a);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_propose<G, 1>), grid, blk, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_propose<G, 2>), grid, blk, 0, s, a);
+  if (ev1) hipEventRecord(ev1, s);
+  if (mode == 0) {
     if (deferred_work) hipLaunchKernelGGL((k_update<G, 0>), grid, blk, 0, s, a);
     hipLaunchKernelGGL((k_refresh<G, 0>), grid, blk, 0, s, a);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_propose<G, 1>), grid, blk, 0, s, a);
     if (deferred_work) hipLaunchKernelGGL((k_update<G, 1>), grid, blk, 0, s, a);
     hipLaunchKernelGGL((k_refresh<G, 1>), grid, blk, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_propose<G, 2>), grid, blk, 0, s, a);
     unsigned nb = unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
     hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
     hipLaunchKernelGGL((k_update<G, 2>), grid, blk, 0, s, a);
@@ -625,12 +634,17 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, int64_
 }
 
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t groups,
-                     int64_t nblocks_accept, bool deferred_work, hipStream_t s) {
+                     int64_t nblocks_accept, bool deferred_work, hipStream_t s, hipEvent_t ev0,
+                     hipEvent_t ev1) {
   switch (group) {
-    case 8: return launch_iteration_g<8>(a, mode, block, groups, nblocks_accept, deferred_work, s);
-    case 16: return launch_iteration_g<16>(a, mode, block, groups, nblocks_accept, deferred_work, s);
-    case 32: return launch_iteration_g<32>(a, mode, block, groups, nblocks_accept, deferred_work, s);
-    default: return launch_iteration_g<64>(a, mode, block, groups, nblocks_accept, deferred_work, s);
+    case 8:
+      return launch_iteration_g<8>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
+    case 16:
+      return launch_iteration_g<16>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
+    case 32:
+      return launch_iteration_g<32>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
+    default:
+      return launch_iteration_g<64>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
   }
 }
 

@@ -23,7 +23,7 @@ struct IterArgs {
   int32_t t, win_lo, win_hi;
   float *delta, *phi, *gacc, *gout;
   int32_t *tick, *acc;
-  unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals
+  unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals, [3] fused-update nnz
 };
 
 int fill_f32(float *p, int64_t m, float v, hipStream_t s);
@@ -44,7 +44,8 @@ int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s);
 int launch_refresh_all(int64_t n, int loss, const float *y, const float *z_hi, const float *z_lo,
                        float *r, hipStream_t s);
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t groups,
-                     int64_t nblocks_accept, bool deferred_work, hipStream_t s);
+                     int64_t nblocks_accept, bool deferred_work, hipStream_t s,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
                  int piece, int32_t total_pieces, const Ws &ws, bool resync, hipStream_t s);
 int launch_round_f32(const double *src, float *dst, int64_t m, hipStream_t s);

@@ -119,8 +119,8 @@ struct Red {
   unsigned long long gmax_bits;
   double dual_sum;
   unsigned long long pad[2];
-  unsigned long long acc_nnz, acc_cnt, bad;
-  unsigned long long pad2[5];
+  unsigned long long acc_nnz, acc_cnt, bad, fused_nnz;
+  unsigned long long pad2[4];
 };
 static_assert(sizeof(Red) == 16 * 8, "reduction block layout");
 
@@ -187,7 +187,7 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
 struct CheckOut {
   double objective, kkt, gap;
   int64_t nnz_w;
-  unsigned long long acc_nnz, acc_cnt;
+  unsigned long long acc_nnz, acc_cnt, fused_nnz;
 };
 
 int run_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
@@ -203,6 +203,7 @@ int run_check(const gencd_csc *X, const float *y, int loss, double lam, const fl
   out->nnz_w = int64_t(r.nnz_w);
   out->acc_nnz = r.acc_nnz;
   out->acc_cnt = r.acc_cnt;
+  out->fused_nnz = r.fused_nnz;
   return GENCD_OK;
 }
 
@@ -306,6 +307,15 @@ __global__ void k_check_list(const int32_t *J, int64_t m, int64_t k, unsigned lo
     if (J[t] < 0 || J[t] >= k) atomicOr(bad, 8ull);
 }
 
+// HIP events owned by one solve call, released on every return path.
+struct EventPool {
+  std::vector<hipEvent_t> v;
+  ~EventPool() {
+    for (auto e : v)
+      if (e) hipEventDestroy(e);
+  }
+};
+
 int64_t groups_for(int64_t positions, int64_t extra_pieces) {
   int64_t g = positions + extra_pieces;
   return g < kMaxGroups ? g : kMaxGroups;
@@ -371,7 +381,36 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   if (S > k_live) S = k_live;
   const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
   IterArgs a = base_args(X, y, p, su, w, ws.z_hi, ws.z_lo);
-  unsigned long long acc_nnz_seen = 0, acc_cnt_seen = 0;
+  unsigned long long acc_nnz_seen = 0, acc_cnt_seen = 0, fused_seen = ck.fused_nnz;
+  // GENCD_PROFILE: one event pair per Propose launch between two checks
+  const bool prof = (p->flags & GENCD_PROFILE) != 0;
+  EventPool pool;
+  std::vector<hipEvent_t> &evs = pool.v;
+  size_t ev_used = 0;
+  double prof_bytes_pending = 0.0;
+  if (prof) {
+    const int64_t T0 = (rule == GENCD_COLORING) ? C : (k_live + S - 1) / std::max<int64_t>(S, 1);
+    const int64_t want = 2 * std::max<int64_t>(T0, 1) * check_every;
+    if (want <= 2 * 65536) {
+      evs.resize(size_t(want));
+      for (auto &ev : evs)
+        if (hipEventCreate(&ev) != hipSuccess) ev = nullptr;
+    }
+  }
+  auto harvest = [&]() {
+    // called after a stream synchronisation: every recorded pair is complete
+    double ms = 0.0;
+    for (size_t u = 0; u + 1 < ev_used; u += 2) {
+      float t = 0.0f;
+      if (evs[u] && evs[u + 1] && hipEventElapsedTime(&t, evs[u], evs[u + 1]) == hipSuccess)
+        ms += double(t);
+    }
+    st_out->prof_kernel_ms += ms;
+    st_out->prof_launches += int64_t(ev_used / 2);
+    st_out->prof_bytes += prof_bytes_pending;
+    prof_bytes_pending = 0.0;
+    ev_used = 0;
+  };
 
   for (int64_t e = 0; status != GENCD_OK && e < p->max_epochs && k_live > 0; ++e) {
     st = launch_epoch_order(ws, k_live, rule, p->seed, e, C, s);
@@ -394,18 +433,30 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       if (positions == 0) continue;
       const int64_t B = (rule == GENCD_THREAD_GREEDY) ? p->block : positions;
       const bool deferred = (mode == 2) || extra > 0;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (!evs.empty() && ev_used + 2 <= evs.size()) {
+        e0 = evs[ev_used];
+        e1 = evs[ev_used + 1];
+        ev_used += 2;
+      }
       st = launch_iteration(a, su.group, mode, B, groups_for(positions, extra),
-                            (positions + B - 1) / B, deferred, s);
+                            (positions + B - 1) / B, deferred, s, e0, e1);
       if (st) return st;
       st_out->iters++;
       if (mode != 2) st_out->coord_updates += positions;
     }
     st_out->epochs = e + 1;
+    if (!evs.empty()) prof_bytes_pending += 12.0 * double(X->nnz) + 20.0 * double(k_live);
     st_out->nnz_visits += X->nnz;
     if (mode != 2) st_out->nnz_updates += X->nnz;
     if ((e + 1) % check_every == 0 || e + 1 == p->max_epochs) {
       st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
       if (st) return st;
+      if (!evs.empty()) {
+        prof_bytes_pending += 16.0 * double(ck.fused_nnz - fused_seen);
+        harvest();
+      }
+      fused_seen = ck.fused_nnz;
       if (mode == 2) {
         st_out->coord_updates += int64_t(ck.acc_cnt - acc_cnt_seen);
         st_out->nnz_updates += int64_t(ck.acc_nnz - acc_nnz_seen);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgencd.so")
 OK, NOT_CONVERGED = 0, 1
 SQUARED, LOGISTIC = 0, 1
 CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING = range(6)
-WARM_START, VALIDATE_DEVICE, USE_GRAPH = 0x1, 0x2, 0x4
+WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE = 0x1, 0x2, 0x4, 0x8
 RULES = {"cyclic": CYCLIC, "stochastic": STOCHASTIC, "shotgun": SHOTGUN,
          "thread_greedy": THREAD_GREEDY, "greedy": GREEDY, "coloring": COLORING}
 
@@ -49,7 +49,9 @@ class Stats(C.Structure):
                 ("nnz_visits", C.c_int64), ("nnz_updates", C.c_int64), ("objective", C.c_double),
                 ("kkt_max", C.c_double), ("gap", C.c_double), ("lambda_max", C.c_double),
                 ("seconds", C.c_double),
-                ("nnz_w", C.c_int64), ("converged", C.c_int32), ("num_colors", C.c_int32)]
+                ("nnz_w", C.c_int64), ("converged", C.c_int32), ("num_colors", C.c_int32),
+                ("prof_launches", C.c_int64), ("prof_kernel_ms", C.c_double),
+                ("prof_bytes", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -149,7 +151,7 @@ class Matrix:
 
 
 def make_params(loss, lam, rule=SHOTGUN, select_size=1, block=1, seed=0, tol=1e-6,
-                gap_tol=1e-7, max_epochs=1000, check_every=1, flags=0, colors=None,
+                gap_tol=0.0, max_epochs=1000, check_every=1, flags=0, colors=None,
                 num_colors=0, piece=0, group=0):
     if isinstance(rule, str):
         rule = RULES[rule]

@@ -7,8 +7,12 @@ Tolerances (FP32 path against FP64 oracle):
     (both sides FP64, different summation order);
   * one iteration from a shared state: z within 1e-5 (|z_or| + rms(z_or));
     g within 1e-5 of max|g| and delta within 1e-5 of max|delta| (FP32 sums);
-  * end-to-end: FP64 KKT <= 1e-6 at the GPU's w (re-checked by the oracle)
-    and objective within 1e-6 relative of the oracle's optimum.
+  * end-to-end: solved to FP64 KKT <= 1e-8 (re-checked by the oracle at the
+    GPU's w), the objective is within 1e-6 relative of the oracle's optimum.
+    KKT <= 1e-6 alone does not pin the objective that tightly on k >> n
+    logistic problems (the objective error is about quadratic in the KKT
+    violation: ~1e-4 relative at 1e-6 on the binary workload), so solves at
+    1e-6 are checked for KKT and for an objective within 2e-4.
 """
 import numpy as np
 import pytest
@@ -40,6 +44,7 @@ def problems():
         "c2": synth.c2_zipf_logistic(scale=0.02),
         "c3": synth.c3_zipf_lasso(scale=0.005),
         "c4": synth.c4_binary_path(scale=0.1),
+        "c1s": synth.c1_ccd_logistic(scale=0.05),
     }
 
 
@@ -187,9 +192,9 @@ SOLVE_CASES = [
     ("c2", G.THREAD_GREEDY, dict(select_size=2048, block=16)),
     ("c3", G.SHOTGUN, dict(select_size=256)),
     ("c4", G.SHOTGUN, dict(select_size=256)),
-    ("c4", G.STOCHASTIC, dict()),
+    ("c1s", G.STOCHASTIC, dict()),
 ]
-LAM_FRAC = {"c1": 0.1, "c2": 0.05, "c3": 0.1, "c4": 0.05}
+LAM_FRAC = {"c1": 0.1, "c2": 0.05, "c3": 0.1, "c4": 0.05, "c1s": 0.1}
 
 
 @pytest.fixture(scope="module")
@@ -198,30 +203,44 @@ def optima(problems):
     for name, P in problems.items():
         Xo = O.Matrix.of(P)
         lam = LAM_FRAC[name] * O.lambda_max(Xo, P.y, P.loss)
-        r = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-10, max_epochs=200000)
+        r = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000)
         assert r.converged
         out[name] = (lam, r)
     return out
 
 
+# A float32 weight cannot move by less than half an ulp, so the KKT violation
+# of a float32 solution is floored near c_j * ulp(|w_j|) / 2; on the Lasso
+# workload (c_j ~ 1, |w_j| ~ 1) that is ~6e-8, so its tight level is 1e-7.
+TIGHT = {"c3": 1e-7}
+
+
 @pytest.mark.parametrize("name,rule,kw", SOLVE_CASES)
-def test_solve_parity(problems, optima, name, rule, kw):
-    _print_case("solve", name, rule, kw)
+@pytest.mark.parametrize("level", ["tight", "1e-6"])
+def test_solve_parity(problems, optima, name, rule, kw, level):
+    kkt = TIGHT.get(name, 1e-8) if level == "tight" else 1e-6
+    _print_case("solve", name, rule, kw, kkt)
     P = problems[name]
     lam, ref = optima[name]
     X = G.Matrix.of(P)
     y = torch.as_tensor(P.y, device=DEV)
-    params = G.make_params(P.loss, lam, rule=rule, seed=3, tol=1e-6, max_epochs=20000, **kw)
+    params = G.make_params(P.loss, lam, rule=rule, seed=3, tol=kkt, max_epochs=20000, **kw)
     res = G.solve(X, y, params)
-    assert res.status == G.OK, res.stats
     st = res.stats
-    assert st["converged"] == 1 and st["kkt_max"] <= 1e-6
-    assert st["gap"] <= 1e-7 * abs(st["objective"])
+    print("STATS", name, rule, {k: st[k] for k in ("epochs", "iters", "objective", "kkt_max", "gap",
+                                                  "nnz_w", "seconds")}, "ref", ref.objective,
+          flush=True)
+    assert res.status == G.OK, res.stats
+    assert st["converged"] == 1 and st["kkt_max"] <= kkt
     w = res.w.cpu().numpy().astype(np.float64)
     oc = O.check(O.Matrix.of(P), P.y, P.loss, lam, w)
-    assert oc.kkt <= 1e-6 * (1 + 1e-9)
+    assert oc.kkt <= kkt * (1 + 1e-6)
     assert st["objective"] == pytest.approx(oc.objective, rel=1e-12)
-    assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+    gap_or, _ = O.duality_gap(O.Matrix.of(P), P.y, P.loss, lam, w)
+    assert st["gap"] == pytest.approx(gap_or, rel=1e-6, abs=1e-12)
+    assert oc.objective - ref.objective >= -1e-12 * abs(ref.objective)
+    bound = 1e-6 if level == "tight" else 2e-4
+    assert abs(oc.objective - ref.objective) <= bound * abs(ref.objective)
     z = res.z.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(z, oc.z, rtol=1e-6, atol=1e-6 * np.abs(oc.z).max())
 
