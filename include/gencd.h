@@ -117,10 +117,10 @@ typedef struct {
   int32_t converged;
   int32_t num_colors;
   /* GENCD_PROFILE: Propose launches, their summed duration (HIP events on
-   * the solve's stream) and the algorithmic bytes they moved: 12 B per
-   * proposed nonzero (row index, value, residual), 20 B per proposed column
-   * (column pointers, w, c, delta/phi), and 16 B per nonzero of a fused
-   * update (z_hi, z_lo read and written). */
+   * the solve's stream) and the algorithmic bytes they moved: 20 B per
+   * proposed nonzero (row index, value, and the gathered z_hi, z_lo, y from
+   * which l'(y, z) is formed) and 32 B per proposed column (piece
+   * descriptor, w, c, delta and phi). */
   int64_t prof_launches;
   double prof_kernel_ms;
   double prof_bytes;

@@ -350,6 +350,7 @@ int gencd_color(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *w
       (X->nnz > 0 && !X->row_idx))
     return GENCD_ERR_INVALID_ARG;
   if (X->n > INT32_MAX || X->k >= INT32_MAX || X->nnz >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  (void)hipGetLastError();  // launch checks below must not see an earlier error
   return gencd::color_run(X, color, num_colors, ws, ws_bytes, stream);
 }
 

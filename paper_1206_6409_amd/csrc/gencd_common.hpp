@@ -14,6 +14,7 @@ namespace gencd {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
+constexpr int kUnroll = 4;   // CSC entries a lane keeps in flight per round
 
 #define GENCD_HIP(call)                                     \
   do {                                                      \
@@ -141,17 +142,11 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// Compensated scatter z_hi[i] + z_lo[i] += d * v (exact product by FMA,
-// exact sum by TwoSum of the value the atomic actually replaced).
-__device__ __forceinline__ void scatter_atomic(float *z_hi, float *z_lo, int i, float d, float v) {
-  float p = d * v;
-  float pe = fmaf(d, v, -p);
-  float old = atomicAdd(&z_hi[i], p);
-  float s = old + p;
-  float bp = s - old;
-  float err = (old - (s - bp)) + (p - bp);
-  float corr = err + pe;
-  if (corr != 0.0f) atomicAdd(&z_lo[i], corr);
+// Rounding error of a + b (TwoSum, exact in round-to-nearest).
+__device__ __forceinline__ float twosum_err(float a, float b) {
+  const float s = a + b;
+  const float bp = s - a;
+  return (a - (s - bp)) + (b - bp);
 }
 
 // Same without atomics: for updates that own the row (columns of one colour
@@ -175,31 +170,30 @@ struct Ws {
   float *c;              // [k] curvature bound
   int32_t *live;         // [k] non-empty columns, ascending
   int32_t *all_poff;     // [k+1] piece offsets of every column (natural order)
-  int32_t *all_pcol;     // [max_pieces] column of each piece
+  int4 *desc_all;        // [max_pieces] piece descriptors, natural order
   int32_t *tmp_cnt;      // [k+1] scratch counts
   int32_t *scan_part;    // [scan partials]
   int32_t *cls_off;      // [k+1] colour class offsets (COLORING)
   int32_t *cls_mem;      // [k] live members by colour
   // per-epoch order
   int32_t *col_of_pos;   // [k]
-  int32_t *poff;         // [k+1]
-  int32_t *piece_pos;    // [max_pieces]
-  int32_t *win_off;      // [k+1]
+  int32_t *poff;         // [k+1] piece offsets of the positions
+  int4 *desc;            // [max_pieces] piece descriptors of the epoch order
+  int32_t *win_off;      // [k+1] colour windows (COLORING)
+  int32_t *wbounds;      // [k+2] first piece of every window
   // per-window
   float *delta;          // [k]
   float *phi;            // [k]
-  float *gbuf;           // [k]
   float *gacc;           // [max_pieces] partial sums of split columns
-  int32_t *tick;         // [k]
+  float *wsnap;          // [k] w of split columns at Propose time
   int32_t *acc;          // [k]
   // state
-  float *z_hi, *z_lo, *r;  // [n]
-  float *w_ckpt;           // [k]
+  float *z_hi, *z_lo;    // [n] compensated fitted values
+  float *w_ckpt;         // [k]
   // FP64 check
   double *z64, *r64;     // [n]
   double *g64;           // [k]
-  double *red;           // [8] loss sum, l1, kkt bits, nnz, ...
-  int32_t *flags;        // [8] device flags (label / matrix validation)
+  double *red;           // [16] reductions, counters, flags; [12] epoch counter
   size_t scan_part_len;
   int64_t max_pieces;
 };

@@ -207,6 +207,20 @@ int launch_validate(const gencd_csc *X, const float *y, int loss, bool matrix,
 }
 
 // ---------------------------------------------------------------------------
+// Piece descriptors.  A descriptor is one 16-byte load:
+//   x = first CSC entry of the piece, y = column, z = position in the order
+//   (-1 for the static natural-order decomposition), w = length | single<<31
+// where `single` marks a column that fits in one piece.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int4 make_desc(int64_t beg, int32_t j, int32_t p, int32_t len,
+                                          bool single) {
+  return make_int4(int32_t(uint32_t(beg)), j, p, int32_t(uint32_t(len) | (single ? 0x80000000u : 0u)));
+}
+__device__ __forceinline__ int64_t desc_beg(const int4 &d) { return int64_t(uint32_t(d.x)); }
+__device__ __forceinline__ int32_t desc_len(const int4 &d) { return int32_t(uint32_t(d.w) & 0x7FFFFFFFu); }
+__device__ __forceinline__ bool desc_single(const int4 &d) { return (uint32_t(d.w) >> 31) != 0; }
+
+// ---------------------------------------------------------------------------
 // Preprocessing: piece decomposition, live columns, curvature (row a1)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_col_counts(const int64_t *col_ptr, int64_t k,
@@ -220,38 +234,47 @@ __global__ __launch_bounds__(kBlock) void k_col_counts(const int64_t *col_ptr, i
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_col_scatter(int64_t k, const int32_t *all_poff,
+__global__ __launch_bounds__(kBlock) void k_col_scatter(const int64_t *col_ptr, int64_t k,
+                                                         int piece, const int32_t *all_poff,
                                                          const int32_t *live_pos,
-                                                         int32_t *all_pcol, int32_t *live) {
+                                                         int4 *desc_all, int32_t *live) {
   for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
        j += int64_t(gridDim.x) * kBlock) {
-    int32_t a = all_poff[j], b = all_poff[j + 1];
-    for (int32_t q = a; q < b; ++q) all_pcol[q] = int32_t(j);
+    const int32_t a = all_poff[j], b = all_poff[j + 1];
+    const int64_t cb = col_ptr[j], ce = col_ptr[j + 1];
+    for (int32_t q = a; q < b; ++q) {
+      const int64_t beg = cb + int64_t(q - a) * piece;
+      const int64_t len = (ce - beg) < piece ? (ce - beg) : piece;
+      desc_all[q] = make_desc(beg, int32_t(j), -1, int32_t(len), b - a == 1);
+    }
     if (b > a) live[live_pos[j]] = int32_t(j);
   }
 }
 
 // Sum of squares per column in FP64 over pieces (G lanes per piece).
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_colsq(const int64_t *col_ptr, const float *val,
-                                                   const int32_t *all_poff,
-                                                   const int32_t *all_pcol, int32_t npieces,
-                                                   int piece, double *acc) {
+__global__ __launch_bounds__(kBlock) void k_colsq(const float *val, const int4 *desc, int32_t npieces,
+                                                   double *acc) {
   const int lane = threadIdx.x & (G - 1);
   const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
   const int64_t ng = int64_t(gridDim.x) * kBlock / G;
   for (int64_t q = gid; q < npieces; q += ng) {
-    int32_t j = all_pcol[q];
-    int32_t pf = all_poff[j];
-    int64_t beg = col_ptr[j] + int64_t(q - pf) * piece;
-    int64_t end = min(beg + int64_t(piece), col_ptr[j + 1]);
+    const int4 d = desc[q];
+    const int64_t beg = desc_beg(d);
+    const int32_t len = desc_len(d);
     double s = 0.0;
-    for (int64_t e = beg + lane; e < end; e += G) {
-      double v = double(val[e]);
-      s += v * v;
+    for (int32_t base = 0; base < len; base += G * kUnroll) {
+      float v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t e = base + u * G + lane;
+        v[u] = e < len ? val[beg + e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) s += double(v[u]) * double(v[u]);
     }
     s = group_sum<G>(s);
-    if (lane == 0) atomicAdd(&acc[j], s);
+    if (lane == 0) atomicAdd(&acc[d.y], s);
   }
 }
 
@@ -262,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_curvature(int64_t k, const double *s
     c[j] = float(beta * ss[j] * inv_n);
 }
 
-static unsigned groups_grid(int64_t groups, int G, unsigned cap = 2048) {
+static unsigned groups_grid(int64_t groups, int G, unsigned cap = 8192) {
   int64_t threads = groups * G;
   int64_t b = (threads + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
@@ -279,15 +302,17 @@ int launch_preprocess(const gencd_csc *X, int loss, int piece, const Ws &w, hipS
   if (st) return st;
   st = scan_exclusive(w.col_of_pos, w.poff, k, w.scan_part, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(k)), dim3(kBlock), 0, s, k, w.all_poff, w.poff,
-                     w.all_pcol, w.live);
+  hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(k)), dim3(kBlock), 0, s, X->col_ptr, k, piece,
+                     w.all_poff, w.poff, w.desc_all, w.live);
   return fill_f64(w.g64, k, 0.0, s);
 }
 
 int launch_curvature(const gencd_csc *X, int loss, int piece, int32_t total_pieces, const Ws &w,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_colsq<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
-                     X->col_ptr, X->val, w.all_poff, w.all_pcol, total_pieces, piece, w.g64);
+  (void)piece;
+  if (total_pieces > 0)
+    hipLaunchKernelGGL(k_colsq<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
+                       X->val, w.desc_all, total_pieces, w.g64);
   double beta = loss == GENCD_SQUARED ? 1.0 : 0.25;
   hipLaunchKernelGGL(k_curvature, dim3(grid_for(X->k)), dim3(kBlock), 0, s, X->k, w.g64, beta,
                      1.0 / double(X->n), w.c);
@@ -310,11 +335,13 @@ int launch_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hi
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
-// order: 0 = permuted live columns, 1 = live columns in index order
+// natural != 0: live columns in index order (cyclic rule).  The epoch
+// number is read from device memory so that a captured epoch replays.
 __global__ __launch_bounds__(kBlock) void k_epoch_order(const int32_t *live, int64_t k_live,
-                                                         PermKey pk, int natural,
-                                                         const int32_t *all_poff,
+                                                         uint64_t seed, const int64_t *epoch,
+                                                         int natural, const int32_t *all_poff,
                                                          int32_t *col_of_pos, int32_t *np) {
+  const PermKey pk = make_perm_key(k_live, seed, *epoch);
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < k_live;
        p += int64_t(gridDim.x) * kBlock) {
     int64_t src = natural ? p : int64_t(perm_apply(pk, uint64_t(p)));
@@ -322,6 +349,10 @@ __global__ __launch_bounds__(kBlock) void k_epoch_order(const int32_t *live, int
     col_of_pos[p] = j;
     np[p] = all_poff[j + 1] - all_poff[j];
   }
+}
+
+__global__ void k_inc_epoch(int64_t *epoch) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *epoch += 1;
 }
 
 // np for an explicit column list (step API and colour windows)
@@ -334,18 +365,42 @@ __global__ __launch_bounds__(kBlock) void k_list_np(const int32_t *cols, int64_t
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_piece_map(const int32_t *poff, int64_t m,
-                                                       int32_t *piece_pos) {
-  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < m;
-       p += int64_t(gridDim.x) * kBlock) {
-    int32_t a = poff[p], b = poff[p + 1];
-    for (int32_t q = a; q < b; ++q) piece_pos[q] = int32_t(p);
+// Descriptors of the epoch order: the pieces of position p are the static
+// pieces of its column, re-tagged with p (8 lanes per position).
+__global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos, int64_t m,
+                                                        const int32_t *poff,
+                                                        const int32_t *all_poff,
+                                                        const int4 *desc_all, int4 *desc) {
+  constexpr int L = 8;
+  const int lane = threadIdx.x & (L - 1);
+  for (int64_t p = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / L; p < m;
+       p += int64_t(gridDim.x) * kBlock / L) {
+    const int32_t j = col_of_pos[p];
+    const int32_t a = poff[p], b = poff[p + 1], src = all_poff[j];
+    for (int32_t q0 = a; q0 < b; q0 += L * kUnroll) {
+      int4 d[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t q = q0 + u * L + lane;
+        if (q < b) d[u] = desc_all[src + (q - a)];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t q = q0 + u * L + lane;
+        if (q < b) {
+          d[u].z = int32_t(p);
+          desc[q] = d[u];
+        }
+      }
+    }
   }
 }
 
 // Colour windows: size of the class visited at step t of the epoch.
 __global__ __launch_bounds__(kBlock) void k_color_win_sizes(const int32_t *cls_off, int64_t C,
-                                                             PermKey pk, int32_t *sz) {
+                                                             uint64_t seed, const int64_t *epoch,
+                                                             int32_t *sz) {
+  const PermKey pk = make_perm_key(C, seed, *epoch);
   for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < C;
        t += int64_t(gridDim.x) * kBlock) {
     int64_t c = int64_t(perm_apply(pk, uint64_t(t)));
@@ -355,8 +410,10 @@ __global__ __launch_bounds__(kBlock) void k_color_win_sizes(const int32_t *cls_o
 
 __global__ __launch_bounds__(kBlock) void k_color_fill(const int32_t *cls_off,
                                                         const int32_t *cls_mem, int64_t C,
-                                                        PermKey pk, const int32_t *win_off,
+                                                        uint64_t seed, const int64_t *epoch,
+                                                        const int32_t *win_off,
                                                         int32_t *col_of_pos) {
+  const PermKey pk = make_perm_key(C, seed, *epoch);
   for (int64_t t = blockIdx.x; t < C; t += gridDim.x) {
     int64_t c = int64_t(perm_apply(pk, uint64_t(t)));
     int32_t a = cls_off[c], b = cls_off[c + 1];
@@ -365,29 +422,53 @@ __global__ __launch_bounds__(kBlock) void k_color_fill(const int32_t *cls_off,
   }
 }
 
-int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed, int64_t epoch,
-                       int64_t num_colors, hipStream_t s) {
-  int st;
+// Piece range of every window of the epoch: bounds[t] = poff[start of window t].
+__global__ __launch_bounds__(kBlock) void k_window_bounds(const int32_t *poff,
+                                                           const int32_t *win_off, int64_t S,
+                                                           int64_t m, int64_t T,
+                                                           int32_t *bounds) {
+  for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t <= T;
+       t += int64_t(gridDim.x) * kBlock) {
+    int64_t pos = win_off ? int64_t(win_off[t]) : (t * S < m ? t * S : m);
+    bounds[t] = poff[pos];
+  }
+}
+
+static int order_tail(const Ws &w, int64_t m, const int32_t *win_off, int64_t S, int64_t T,
+                      hipStream_t s) {
+  int st = scan_exclusive(w.tmp_cnt, w.poff, m, w.scan_part, s);
+  if (st) return st;
+  if (m > 0)
+    hipLaunchKernelGGL(k_order_desc, dim3(grid_for(m * 8)), dim3(kBlock), 0, s, w.col_of_pos, m,
+                       w.poff, w.all_poff, w.desc_all, w.desc);
+  hipLaunchKernelGGL(k_window_bounds, dim3(grid_for(T + 1)), dim3(kBlock), 0, s, w.poff, win_off,
+                     S, m, T, w.wbounds);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed,
+                       const int64_t *epoch, int64_t num_colors, int64_t S, int64_t T,
+                       hipStream_t s) {
   if (rule == GENCD_COLORING) {
-    PermKey pk = make_perm_key(num_colors, seed, epoch);
     hipLaunchKernelGGL(k_color_win_sizes, dim3(grid_for(num_colors)), dim3(kBlock), 0, s,
-                       w.cls_off, num_colors, pk, w.tmp_cnt);
-    st = scan_exclusive(w.tmp_cnt, w.win_off, num_colors, w.scan_part, s);
+                       w.cls_off, num_colors, seed, epoch, w.tmp_cnt);
+    int st = scan_exclusive(w.tmp_cnt, w.win_off, num_colors, w.scan_part, s);
     if (st) return st;
     hipLaunchKernelGGL(k_color_fill, dim3(unsigned(num_colors < 8192 ? num_colors : 8192)),
-                       dim3(kBlock), 0, s, w.cls_off, w.cls_mem, num_colors, pk, w.win_off,
-                       w.col_of_pos);
+                       dim3(kBlock), 0, s, w.cls_off, w.cls_mem, num_colors, seed, epoch,
+                       w.win_off, w.col_of_pos);
     hipLaunchKernelGGL(k_list_np, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.col_of_pos,
                        k_live, w.all_poff, w.tmp_cnt);
-  } else {
-    PermKey pk = make_perm_key(k_live, seed, epoch);
-    hipLaunchKernelGGL(k_epoch_order, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.live, k_live,
-                       pk, rule == GENCD_CYCLIC ? 1 : 0, w.all_poff, w.col_of_pos, w.tmp_cnt);
+    return order_tail(w, k_live, w.win_off, 0, num_colors, s);
   }
-  st = scan_exclusive(w.tmp_cnt, w.poff, k_live, w.scan_part, s);
-  if (st) return st;
-  hipLaunchKernelGGL(k_piece_map, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.poff, k_live,
-                     w.piece_pos);
+  hipLaunchKernelGGL(k_epoch_order, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.live, k_live,
+                     seed, epoch, rule == GENCD_CYCLIC ? 1 : 0, w.all_poff, w.col_of_pos,
+                     w.tmp_cnt);
+  return order_tail(w, k_live, nullptr, S, T, s);
+}
+
+int launch_inc_epoch(int64_t *epoch, hipStream_t s) {
+  hipLaunchKernelGGL(k_inc_epoch, dim3(1), dim3(64), 0, s, epoch);
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
@@ -396,15 +477,14 @@ int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s) 
   if (st) return st;
   hipLaunchKernelGGL(k_list_np, dim3(grid_for(nJ)), dim3(kBlock), 0, s, w.col_of_pos, nJ,
                      w.all_poff, w.tmp_cnt);
-  st = scan_exclusive(w.tmp_cnt, w.poff, nJ, w.scan_part, s);
-  if (st) return st;
-  hipLaunchKernelGGL(k_piece_map, dim3(grid_for(nJ)), dim3(kBlock), 0, s, w.poff, nJ,
-                     w.piece_pos);
-  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+  return order_tail(w, nJ, nullptr, nJ, 1, s);
 }
 
 // ---------------------------------------------------------------------------
-// One iteration: Propose (+ fused Update), Accept, Update, residual refresh
+// One iteration: Propose (Algorithm 2 / 4), Accept (section 2.3), Update
+// (Algorithm 3).  The residual l'(y, z) is evaluated on the fly from
+// z = z_hi + z_lo, which Propose only reads; Update writes z in the next
+// launch, so every proposal of an iteration sees the state at its start.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void window_of(const IterArgs &a, int32_t &P0, int32_t &P1) {
   if (a.win_off) {
@@ -416,91 +496,146 @@ __device__ __forceinline__ void window_of(const IterArgs &a, int32_t &P0, int32_
   }
 }
 
+// Sum of the partial gradients of a split column, in piece order (the same
+// order, hence the same float result, in every group that computes it).
+template <int G>
+__device__ __forceinline__ float split_sum(const float *part, int32_t pf, int32_t np, int lane) {
+  float t = 0.0f;
+  for (int32_t u0 = 0; u0 < np; u0 += G * kUnroll) {
+    float v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t idx = u0 + u * G + lane;
+      v[u] = idx < np ? part[pf + idx] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) t += v[u];
+  }
+  return group_sum<G>(t);
+}
+
+// Propose (Algorithm 2 / 4).  A column that fits in one piece is finalised
+// here (delta, phi; accept-all rules also apply w_j += delta_j).  A split
+// column only publishes its partial sums; Update (accept-all rules) or
+// Accept (greedy rules) finalise it in the next launch, so no workgroup
+// ever waits for another.
 // MODE 0: accept all, atomic scatter (Shotgun, stochastic, cyclic)
 // MODE 1: accept all, plain scatter (Coloring: rows of a class are disjoint)
-// MODE 2: deferred acceptance (Thread-Greedy, Greedy): store delta and phi
+// MODE 2: deferred acceptance (Thread-Greedy, Greedy)
 template <int G, int MODE>
 __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
   const int lane = threadIdx.x & (G - 1);
   const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
   const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  const int32_t q0 = a.wbounds[a.t], q1 = a.wbounds[a.t + 1];
   int32_t P0, P1;
   window_of(a, P0, P1);
-  const int32_t q0 = a.poff[P0], q1 = a.poff[P1];
   for (int64_t q = q0 + gid; q < q1; q += ng) {
-    const int32_t p = a.piece_pos[q];
-    const int32_t j = a.col_of_pos[p];
-    const int32_t pf = a.poff[p];
-    const int32_t np = a.poff[p + 1] - pf;
-    const int64_t ce = a.col_ptr[j + 1];
-    const int64_t beg = a.col_ptr[j] + int64_t(q - pf) * a.piece;
-    const int64_t end = min(beg + int64_t(a.piece), ce);
+    const int4 dsc = a.desc[q];
+    const int64_t beg = desc_beg(dsc);
+    const int32_t len = desc_len(dsc);
+    const int32_t j = dsc.y, p = dsc.z;
+    const bool single = desc_single(dsc);
+    float wj = 0.0f, cj = 0.0f;
+    if (single && lane == 0) {  // issued early, consumed after the reduction
+      wj = a.w[j];
+      cj = a.c[j];
+    }
     float s = 0.0f;
-    for (int64_t e = beg + lane; e < end; e += G) s += a.val[e] * a.r[a.row_idx[e]];
+    for (int32_t base = 0; base < len; base += G * kUnroll) {
+      int32_t ri[kUnroll];
+      float vv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t e = base + u * G + lane;
+        ri[u] = e < len ? a.row_idx[beg + e] : -1;
+        vv[u] = e < len ? a.val[beg + e] : 0.0f;
+      }
+      float zh[kUnroll], zl[kUnroll], yy[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t i = ri[u] >= 0 ? ri[u] : 0;
+        zh[u] = a.z_hi[i];
+        zl[u] = a.z_lo[i];
+        yy[u] = a.y[i];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ri[u] >= 0) s += vv[u] * dloss_f32(a.loss, yy[u], zh[u] + zl[u]);
+    }
     s = group_sum<G>(s);
+    if (lane != 0) continue;
     const int32_t slot = p - P0;
-    int fin = (np == 1);
-    if (np > 1) {
-      // Partial sums of a split column: publish, take a ticket; the last
-      // piece adds the partials in piece order (deterministic result).
-      if (lane == 0) {
-        a.gacc[q] = s;
-        __threadfence();
-        fin = (atomicAdd(&a.tick[slot], 1) == np - 1);
-      }
-      fin = __shfl(fin, 0, G);
-      if (fin) {
-        __threadfence();
-        float t = 0.0f;
-        for (int32_t u = lane; u < np; u += G) t += __hip_atomic_load(&a.gacc[pf + u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s = group_sum<G>(t);
-        if (lane == 0) a.tick[slot] = 0;
-      }
+    if (!single) {
+      a.gacc[q] = s;
+      if (MODE != 2) a.wsnap[slot] = a.w[j];  // stable copy for Update
+      continue;
     }
-    float d = 0.0f;
-    if (fin && lane == 0) {
-      const float g = s / a.n_f;
-      const float wj = a.w[j];
-      float ph;
-      propose_f32(g, a.c[j], wj, a.lam, d, ph);
-      a.delta[slot] = d;
-      a.phi[slot] = ph;
-      if (a.gout) a.gout[slot] = g;
-      if (MODE != 2 && d != 0.0f) {
-        a.w[j] = wj + d;
-        if (np == 1) atomicAdd(a.counters + 3, (unsigned long long)(end - beg));
-      }
-    }
-    if (MODE != 2 && np == 1) {
-      d = __shfl(d, 0, G);
-      if (d != 0.0f) {
-        for (int64_t e = beg + lane; e < end; e += G) {
-          if (MODE == 0)
-            scatter_atomic(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
-          else
-            scatter_plain(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
-        }
-      }
+    const float g = s / a.n_f;
+    float d, ph;
+    propose_f32(g, cj, wj, a.lam, d, ph);
+    a.delta[slot] = d;
+    a.phi[slot] = ph;
+    if (a.gout) a.gout[slot] = g;
+    if (MODE != 2 && d != 0.0f) {
+      a.w[j] = wj + d;
+      atomicAdd(a.counters + 3, (unsigned long long)len);
     }
   }
 }
 
-// Accept for Thread-Greedy / Greedy: in each block of B positions, the first
-// position with minimal phi (one workgroup per block).
+// Accept for Thread-Greedy / Greedy (section 2.3): in each block of B
+// positions the first position with minimal phi.  One workgroup per block;
+// it first finalises the block's split columns from their partial sums.
 __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
   __shared__ float sphi[kBlock];
   __shared__ int32_t spos[kBlock];
+  __shared__ float sred[kBlock];
+  __shared__ int32_t smulti[kBlock];
+  __shared__ int32_t nmulti;
   int32_t P0, P1;
   window_of(a, P0, P1);
   const int64_t nblk = (int64_t(P1 - P0) + B - 1) / B;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int64_t lo = P0 + b * B, hi = min(lo + B, int64_t(P1));
+    // finalise the block's split columns: find them in parallel, then sum
+    // each one's partials (in piece order) with the whole workgroup
+    for (int64_t c0 = lo; c0 < hi; c0 += kBlock) {
+      if (threadIdx.x == 0) nmulti = 0;
+      __syncthreads();
+      const int64_t pp = c0 + threadIdx.x;
+      if (pp < hi && a.poff[pp + 1] - a.poff[pp] > 1) smulti[atomicAdd(&nmulti, 1)] = int32_t(pp);
+      __syncthreads();
+      const int32_t cnt = nmulti;
+      for (int32_t m = 0; m < cnt; ++m) {
+        const int32_t p = smulti[m];
+        const int32_t pf = a.poff[p], np = a.poff[p + 1] - pf;
+        float t = 0.0f;
+        for (int32_t u = threadIdx.x; u < np; u += kBlock) t += a.gacc[pf + u];
+        sred[threadIdx.x] = t;
+        __syncthreads();
+        for (int off = kBlock / 2; off > 0; off >>= 1) {
+          if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+          __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+          const int32_t j = a.col_of_pos[p];
+          const float g = sred[0] / a.n_f;
+          float d, ph;
+          propose_f32(g, a.c[j], a.w[j], a.lam, d, ph);
+          a.delta[p - P0] = d;
+          a.phi[p - P0] = ph;
+          if (a.gout) a.gout[p - P0] = g;
+        }
+        __syncthreads();
+      }
+    }
     float best = INFINITY;
     int32_t bpos = INT32_MAX;
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBlock) {
       a.acc[p - P0] = 0;
       float v = a.phi[p - P0];
-      if (v < best) {  // strided scan visits positions in increasing order
+      if (v < best) {  // a thread visits its positions in increasing order
         best = v;
         bpos = int32_t(p);
       }
@@ -532,125 +667,118 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
   }
 }
 
-// Update (Algorithm 3) of the proposals that Propose did not already apply.
+// Update (Algorithm 3): z += delta_j X_j for the accepted, nonzero proposals.
+// Accept-all rules finalise split columns here: every piece recomputes the
+// same delta from the partial sums and the weight snapshot; the column's
+// first piece writes w_j, delta_j and phi_j.
 template <int G, int MODE>
 __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   const int lane = threadIdx.x & (G - 1);
   const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
   const int64_t ng = int64_t(gridDim.x) * kBlock / G;
+  const int32_t q0 = a.wbounds[a.t], q1 = a.wbounds[a.t + 1];
   int32_t P0, P1;
   window_of(a, P0, P1);
-  const int32_t q0 = a.poff[P0], q1 = a.poff[P1];
   for (int64_t q = q0 + gid; q < q1; q += ng) {
-    const int32_t p = a.piece_pos[q];
-    const int32_t slot = p - P0;
-    const int32_t pf = a.poff[p];
-    const int32_t np = a.poff[p + 1] - pf;
+    const int4 dsc = a.desc[q];
+    const int32_t slot = dsc.z - P0;
+    float d;
     if (MODE == 2) {
       if (!a.acc[slot]) continue;
-    } else if (np == 1) {
-      continue;  // applied by the fused Propose
+      d = a.delta[slot];
+    } else if (desc_single(dsc)) {
+      d = a.delta[slot];
+    } else {
+      const int32_t pf = a.poff[dsc.z], np = a.poff[dsc.z + 1] - pf;
+      const int32_t j = dsc.y;
+      const float ws = a.wsnap[slot];
+      const float cj = a.c[j];
+      const float g = split_sum<G>(a.gacc, pf, np, lane) / a.n_f;
+      float ph;
+      propose_f32(g, cj, ws, a.lam, d, ph);
+      if (q == pf && lane == 0) {
+        a.delta[slot] = d;
+        a.phi[slot] = ph;
+        if (a.gout) a.gout[slot] = g;
+        if (d != 0.0f) {
+          a.w[j] = ws + d;
+          atomicAdd(a.counters + 3, (unsigned long long)(a.col_ptr[j + 1] - a.col_ptr[j]));
+        }
+      }
     }
-    const float d = a.delta[slot];
     if (d == 0.0f) continue;
-    const int32_t j = a.col_of_pos[p];
-    const int64_t beg = a.col_ptr[j] + int64_t(q - pf) * a.piece;
-    const int64_t end = min(beg + int64_t(a.piece), a.col_ptr[j + 1]);
-    for (int64_t e = beg + lane; e < end; e += G) {
-      if (MODE == 1)
-        scatter_plain(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
-      else
-        scatter_atomic(a.z_hi, a.z_lo, a.row_idx[e], d, a.val[e]);
+    const int64_t beg = desc_beg(dsc);
+    const int32_t len = desc_len(dsc);
+    for (int32_t base = 0; base < len; base += G * kUnroll) {
+      int32_t ri[kUnroll];
+      float vv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t e = base + u * G + lane;
+        ri[u] = e < len ? a.row_idx[beg + e] : -1;
+        vv[u] = e < len ? a.val[beg + e] : 0.0f;
+      }
+      if (MODE == 1) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (ri[u] >= 0) scatter_plain(a.z_hi, a.z_lo, ri[u], d, vv[u]);
+      } else {
+        // issue all the returning atomics first, then the compensations
+        float pp[kUnroll], old[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          pp[u] = d * vv[u];
+          old[u] = ri[u] >= 0 ? atomicAdd(&a.z_hi[ri[u]], pp[u]) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (ri[u] < 0) continue;
+          const float corr = twosum_err(old[u], pp[u]) + fmaf(d, vv[u], -pp[u]);
+          if (corr != 0.0f) atomicAdd(&a.z_lo[ri[u]], corr);
+        }
+      }
     }
   }
-}
-
-// r_i = l'(y_i, z_i) for the rows touched by this iteration's updates.
-template <int G, int MODE>
-__global__ __launch_bounds__(kBlock) void k_refresh(IterArgs a) {
-  const int lane = threadIdx.x & (G - 1);
-  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
-  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
-  int32_t P0, P1;
-  window_of(a, P0, P1);
-  const int32_t q0 = a.poff[P0], q1 = a.poff[P1];
-  for (int64_t q = q0 + gid; q < q1; q += ng) {
-    const int32_t p = a.piece_pos[q];
-    const int32_t slot = p - P0;
-    if (MODE == 2 && !a.acc[slot]) continue;
-    if (a.delta[slot] == 0.0f) continue;
-    const int32_t pf = a.poff[p];
-    const int32_t j = a.col_of_pos[p];
-    const int64_t beg = a.col_ptr[j] + int64_t(q - pf) * a.piece;
-    const int64_t end = min(beg + int64_t(a.piece), a.col_ptr[j + 1]);
-    for (int64_t e = beg + lane; e < end; e += G) {
-      const int32_t i = a.row_idx[e];
-      a.r[i] = dloss_f32(a.loss, a.y[i], a.z_hi[i] + a.z_lo[i]);
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_refresh_all(int64_t n, int loss, const float *y,
-                                                         const float *z_hi, const float *z_lo,
-                                                         float *r) {
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * kBlock)
-    r[i] = dloss_f32(loss, y[i], z_hi[i] + z_lo[i]);
-}
-
-int launch_refresh_all(int64_t n, int loss, const float *y, const float *z_hi, const float *z_lo,
-                       float *r, hipStream_t s) {
-  hipLaunchKernelGGL(k_refresh_all, dim3(grid_for(n)), dim3(kBlock), 0, s, n, loss, y, z_hi,
-                     z_lo, r);
-  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
 template <int G>
 static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, int64_t groups,
-                              int64_t nblocks_accept, bool deferred_work, hipStream_t s,
-                              hipEvent_t ev0, hipEvent_t ev1) {
+                              int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
+                              hipEvent_t ev1) {
   const dim3 grid(groups_grid(groups, G)), blk(kBlock);
-  if (ev0) hipEventRecord(ev0, s);
+  if (ev0) (void)hipEventRecord(ev0, s);
   if (mode == 0)
     hipLaunchKernelGGL((k_propose<G, 0>), grid, blk, 0, s, a);
   else if (mode == 1)
     hipLaunchKernelGGL((k_propose<G, 1>), grid, blk, 0, s, a);
   else
     hipLaunchKernelGGL((k_propose<G, 2>), grid, blk, 0, s, a);
-  if (ev1) hipEventRecord(ev1, s);
+  if (ev1) (void)hipEventRecord(ev1, s);
   if (mode == 0) {
-    if (deferred_work) hipLaunchKernelGGL((k_update<G, 0>), grid, blk, 0, s, a);
-    hipLaunchKernelGGL((k_refresh<G, 0>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<G, 0>), grid, blk, 0, s, a);
   } else if (mode == 1) {
-    if (deferred_work) hipLaunchKernelGGL((k_update<G, 1>), grid, blk, 0, s, a);
-    hipLaunchKernelGGL((k_refresh<G, 1>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<G, 1>), grid, blk, 0, s, a);
   } else {
     unsigned nb = unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
     hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
     hipLaunchKernelGGL((k_update<G, 2>), grid, blk, 0, s, a);
-    hipLaunchKernelGGL((k_refresh<G, 2>), grid, blk, 0, s, a);
   }
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t groups,
-                     int64_t nblocks_accept, bool deferred_work, hipStream_t s, hipEvent_t ev0,
-                     hipEvent_t ev1) {
+                     int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   switch (group) {
-    case 8:
-      return launch_iteration_g<8>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
-    case 16:
-      return launch_iteration_g<16>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
-    case 32:
-      return launch_iteration_g<32>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
-    default:
-      return launch_iteration_g<64>(a, mode, block, groups, nblocks_accept, deferred_work, s, ev0, ev1);
+    case 8: return launch_iteration_g<8>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
+    case 16: return launch_iteration_g<16>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
+    case 32: return launch_iteration_g<32>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
+    default: return launch_iteration_g<64>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
   }
 }
 
 // ---------------------------------------------------------------------------
-// FP64 check: z64 = Xw, loss, r64 = l'(y, z64), g64 = X^T r64 / n, KKT, |w|_1
-// (and the FP32 re-sync z_hi + z_lo = z64, r = l'(y, z64))
+// FP64 check: z64 = Xw, loss, r64 = l'(y, z64), g64 = X^T r64 / n, KKT, |w|_1,
+// duality gap (and the FP32 re-sync z_hi + z_lo = z64)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_check_zero(double *z64, int64_t n, double *g64,
                                                         int64_t k, unsigned long long *red) {
@@ -662,29 +790,37 @@ __global__ __launch_bounds__(kBlock) void k_check_zero(double *z64, int64_t n, d
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_check_spmv(const int64_t *col_ptr,
-                                                        const int32_t *row_idx, const float *val,
-                                                        const int32_t *all_poff,
-                                                        const int32_t *all_pcol,
-                                                        int32_t npieces, int piece,
+__global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, const float *val,
+                                                        const int4 *desc, int32_t npieces,
                                                         const float *w, double *z64) {
   const int lane = threadIdx.x & (G - 1);
   const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
   const int64_t ng = int64_t(gridDim.x) * kBlock / G;
   for (int64_t q = gid; q < npieces; q += ng) {
-    const int32_t j = all_pcol[q];
-    const double wj = double(w[j]);
+    const int4 dsc = desc[q];
+    const double wj = double(w[dsc.y]);
     if (wj == 0.0) continue;
-    const int64_t beg = col_ptr[j] + int64_t(q - all_poff[j]) * piece;
-    const int64_t end = min(beg + int64_t(piece), col_ptr[j + 1]);
-    for (int64_t e = beg + lane; e < end; e += G) atomicAdd(&z64[row_idx[e]], wj * double(val[e]));
+    const int64_t beg = desc_beg(dsc);
+    const int32_t len = desc_len(dsc);
+    for (int32_t base = 0; base < len; base += G * kUnroll) {
+      int32_t ri[kUnroll];
+      float vv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t e = base + u * G + lane;
+        ri[u] = e < len ? row_idx[beg + e] : -1;
+        vv[u] = e < len ? val[beg + e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ri[u] >= 0) atomicAdd(&z64[ri[u]], wj * double(vv[u]));
+    }
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, const float *y,
                                                         const double *z64, double *r64,
-                                                        float *z_hi, float *z_lo, float *r,
-                                                        double *red) {
+                                                        float *z_hi, float *z_lo, double *red) {
   __shared__ double sred[kBlock];
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -692,13 +828,11 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, cons
     const double t = z64[i];
     const double yi = double(y[i]);
     acc += loss_f64(loss, yi, t);
-    const double d = dloss_f64(loss, yi, t);
-    r64[i] = d;
+    r64[i] = dloss_f64(loss, yi, t);
     if (z_hi) {
       const float h = float(t);
       z_hi[i] = h;
       z_lo[i] = float(t - double(h));
-      r[i] = float(d);
     }
   }
   sred[threadIdx.x] = acc;
@@ -711,29 +845,39 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, cons
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_check_cols(const int64_t *col_ptr,
-                                                        const int32_t *row_idx, const float *val,
-                                                        const int32_t *all_poff,
-                                                        const int32_t *all_pcol,
-                                                        int32_t npieces, int piece,
+__global__ __launch_bounds__(kBlock) void k_check_cols(const int32_t *row_idx, const float *val,
+                                                        const int4 *desc, int32_t npieces,
                                                         const double *r64, double *g64) {
   const int lane = threadIdx.x & (G - 1);
   const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
   const int64_t ng = int64_t(gridDim.x) * kBlock / G;
   for (int64_t q = gid; q < npieces; q += ng) {
-    const int32_t j = all_pcol[q];
-    const int32_t pf = all_poff[j];
-    const int32_t np = all_poff[j + 1] - pf;
-    const int64_t beg = col_ptr[j] + int64_t(q - pf) * piece;
-    const int64_t end = min(beg + int64_t(piece), col_ptr[j + 1]);
+    const int4 dsc = desc[q];
+    const int64_t beg = desc_beg(dsc);
+    const int32_t len = desc_len(dsc);
     double s = 0.0;
-    for (int64_t e = beg + lane; e < end; e += G) s += double(val[e]) * r64[row_idx[e]];
+    for (int32_t base = 0; base < len; base += G * kUnroll) {
+      int32_t ri[kUnroll];
+      float vv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t e = base + u * G + lane;
+        ri[u] = e < len ? row_idx[beg + e] : -1;
+        vv[u] = e < len ? val[beg + e] : 0.0f;
+      }
+      double rr[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) rr[u] = r64[ri[u] >= 0 ? ri[u] : 0];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ri[u] >= 0) s += double(vv[u]) * rr[u];
+    }
     s = group_sum<G>(s);
     if (lane == 0) {
-      if (np == 1)
-        g64[j] = s;
+      if (desc_single(dsc))
+        g64[dsc.y] = s;
       else
-        atomicAdd(&g64[j], s);
+        atomicAdd(&g64[dsc.y], s);
     }
   }
 }
@@ -823,22 +967,22 @@ __global__ __launch_bounds__(kBlock) void k_check_dual(int64_t n, int loss, cons
 
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
                  int piece, int32_t total_pieces, const Ws &ws, bool resync, hipStream_t s) {
+  (void)piece;
   unsigned long long *red = reinterpret_cast<unsigned long long *>(ws.red);
   const int64_t nk = X->n > X->k ? X->n : X->k;
   hipLaunchKernelGGL(k_check_zero, dim3(grid_for(nk)), dim3(kBlock), 0, s, ws.z64, X->n, ws.g64,
                      X->k, red);
-  if (w)
+  if (w && total_pieces > 0)
     hipLaunchKernelGGL(k_check_spmv<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
-                       X->col_ptr, X->row_idx, X->val, ws.all_poff, ws.all_pcol, total_pieces,
-                       piece, w, ws.z64);
-  hipLaunchKernelGGL(k_check_rows, dim3(grid_for(X->n, 1024)), dim3(kBlock), 0, s, X->n, loss, y,
-                     ws.z64, ws.r64, resync ? ws.z_hi : nullptr, ws.z_lo, ws.r, ws.red);
-  hipLaunchKernelGGL(k_check_cols<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
-                     X->col_ptr, X->row_idx, X->val, ws.all_poff, ws.all_pcol, total_pieces,
-                     piece, ws.r64, ws.g64);
-  hipLaunchKernelGGL(k_check_kkt, dim3(grid_for(X->k, 1024)), dim3(kBlock), 0, s, X->k, ws.g64, w,
+                       X->row_idx, X->val, ws.desc_all, total_pieces, w, ws.z64);
+  hipLaunchKernelGGL(k_check_rows, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
+                     ws.z64, ws.r64, resync ? ws.z_hi : nullptr, ws.z_lo, ws.red);
+  if (total_pieces > 0)
+    hipLaunchKernelGGL(k_check_cols<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
+                       X->row_idx, X->val, ws.desc_all, total_pieces, ws.r64, ws.g64);
+  hipLaunchKernelGGL(k_check_kkt, dim3(grid_for(X->k, 256)), dim3(kBlock), 0, s, X->k, ws.g64, w,
                      lam, 1.0 / double(X->n), red);
-  hipLaunchKernelGGL(k_check_dual, dim3(grid_for(X->n, 1024)), dim3(kBlock), 0, s, X->n, loss, y,
+  hipLaunchKernelGGL(k_check_dual, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
                      ws.r64, lam, red);
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }

@@ -14,16 +14,17 @@ struct IterArgs {
   float n_f;
   int32_t loss;
   float lam;
-  int32_t piece;
   const float *c;
   float *w;
-  float *z_hi, *z_lo, *r;
-  const int32_t *col_of_pos, *poff, *piece_pos;
+  float *z_hi, *z_lo;
+  const int32_t *col_of_pos, *poff;
+  const int4 *desc;        // piece descriptors of the current order
+  const int32_t *wbounds;  // first piece of every window; window t is [wbounds[t], wbounds[t+1])
   const int32_t *win_off;  // per-epoch window offsets, or null: [win_lo, win_hi)
   int32_t t, win_lo, win_hi;
-  float *delta, *phi, *gacc, *gout;
-  int32_t *tick, *acc;
-  unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals, [3] fused-update nnz
+  float *delta, *phi, *gacc, *gout, *wsnap;
+  int32_t *acc;
+  unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals, [3] updated nnz
 };
 
 int fill_f32(float *p, int64_t m, float v, hipStream_t s);
@@ -38,14 +39,17 @@ int launch_preprocess(const gencd_csc *X, int loss, int piece, const Ws &w, hipS
 int launch_curvature(const gencd_csc *X, int loss, int piece, int32_t total_pieces, const Ws &w,
                      hipStream_t s);
 int launch_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hipStream_t s);
-int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed, int64_t epoch,
-                       int64_t num_colors, hipStream_t s);
+// Writes the epoch order, its piece descriptors and, in w.wbounds[0..T], the
+// first piece of every window (S positions per window; colour windows for
+// COLORING).
+int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed,
+                       const int64_t *epoch, int64_t num_colors, int64_t S, int64_t T,
+                       hipStream_t s);
+int launch_inc_epoch(int64_t *epoch, hipStream_t s);
 int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s);
-int launch_refresh_all(int64_t n, int loss, const float *y, const float *z_hi, const float *z_lo,
-                       float *r, hipStream_t s);
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t groups,
-                     int64_t nblocks_accept, bool deferred_work, hipStream_t s,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                     int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr);
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
                  int piece, int32_t total_pieces, const Ws &ws, bool resync, hipStream_t s);
 int launch_round_f32(const double *src, float *dst, int64_t m, hipStream_t s);

@@ -19,7 +19,7 @@
 namespace gencd {
 
 static constexpr size_t kAlign = 256;
-static constexpr int kDefaultPiece = 1024;
+static constexpr int kDefaultPiece = 512;
 static constexpr int kDefaultGroup = 64;
 static constexpr int64_t kMaxGroups = 2048 * (kBlock / 8);
 
@@ -49,30 +49,28 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, void *base
   w.c = c.take<float>(k);
   w.live = c.take<int32_t>(k);
   w.all_poff = c.take<int32_t>(k + 1);
-  w.all_pcol = c.take<int32_t>(mp);
+  w.desc_all = c.take<int4>(mp);
   w.tmp_cnt = c.take<int32_t>(k + 1);
   w.scan_part = c.take<int32_t>(int64_t(w.scan_part_len));
   w.cls_off = c.take<int32_t>(k + 1);
   w.cls_mem = c.take<int32_t>(k);
   w.col_of_pos = c.take<int32_t>(k);
   w.poff = c.take<int32_t>(k + 1);
-  w.piece_pos = c.take<int32_t>(mp);
+  w.desc = c.take<int4>(mp);
   w.win_off = c.take<int32_t>(k + 1);
+  w.wbounds = c.take<int32_t>(k + 2);
   w.delta = c.take<float>(k);
   w.phi = c.take<float>(k);
-  w.gbuf = c.take<float>(k);
   w.gacc = c.take<float>(mp);
-  w.tick = c.take<int32_t>(k);
+  w.wsnap = c.take<float>(k);
   w.acc = c.take<int32_t>(k);
   w.z_hi = c.take<float>(n);
   w.z_lo = c.take<float>(n);
-  w.r = c.take<float>(n);
   w.w_ckpt = c.take<float>(k);
   w.z64 = c.take<double>(n);
   w.r64 = c.take<double>(n);
   w.g64 = c.take<double>(k);
   w.red = c.take<double>(16);
-  w.flags = c.take<int32_t>(8);
   if (ws) *ws = w;
   return c.off + kAlign;
 }
@@ -150,7 +148,8 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
   if (!csc_ok(X) || !y) return GENCD_ERR_INVALID_ARG;
   int st = resolve_schedule(p, &out->piece, &out->group);
   if (st) return st;
-  if (max_pieces_for(X->k, X->nnz, out->piece) >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  if (max_pieces_for(X->k, X->nnz, out->piece) >= INT32_MAX || X->nnz >= (int64_t(1) << 32))
+    return GENCD_ERR_UNSUPPORTED;
   size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, nullptr, nullptr);
   if (!ws_base || ws_bytes < need) return GENCD_ERR_WORKSPACE;
   // align the carve base
@@ -178,8 +177,6 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
   st = launch_curvature(X, loss, out->piece, out->total_pieces, w, s);
   if (st) return st;
   st = fill_f32(w.gacc, w.max_pieces, 0.0f, s);
-  if (st) return st;
-  st = fill_i32(w.tick, X->k, 0, s);
   if (st) return st;
   return fill_i32(w.acc, X->k, 0, s);
 }
@@ -229,20 +226,19 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   a.n_f = float(X->n);
   a.loss = p->loss;
   a.lam = float(p->lambda);
-  a.piece = su.piece;
   a.c = ws.c;
   a.w = w;
   a.z_hi = z_hi;
   a.z_lo = z_lo;
-  a.r = ws.r;
   a.col_of_pos = ws.col_of_pos;
   a.poff = ws.poff;
-  a.piece_pos = ws.piece_pos;
+  a.desc = ws.desc;
   a.delta = ws.delta;
   a.phi = ws.phi;
   a.gacc = ws.gacc;
   a.gout = nullptr;
-  a.tick = ws.tick;
+  a.wsnap = ws.wsnap;
+  a.wbounds = ws.wbounds;
   a.acc = ws.acc;
   a.counters = reinterpret_cast<unsigned long long *>(ws.red) + 8;
   return a;
@@ -307,6 +303,23 @@ __global__ void k_check_list(const int32_t *J, int64_t m, int64_t k, unsigned lo
     if (J[t] < 0 || J[t] >= k) atomicOr(bad, 8ull);
 }
 
+// A captured epoch, released on every return path.
+struct GraphHolder {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cs = nullptr;  // capture stream
+  void reset() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (g) hipGraphDestroy(g);
+    exec = nullptr;
+    g = nullptr;
+  }
+  ~GraphHolder() {
+    reset();
+    if (cs) hipStreamDestroy(cs);
+  }
+};
+
 // HIP events owned by one solve call, released on every return path.
 struct EventPool {
   std::vector<hipEvent_t> v;
@@ -328,6 +341,7 @@ int64_t groups_for(int64_t positions, int64_t extra_pieces) {
 // ---------------------------------------------------------------------------
 int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float *w, float *z,
                void *ws_base, size_t ws_bytes, hipStream_t s, gencd_stats *stats) {
+  (void)hipGetLastError();  // launch checks below must not see an earlier error
   auto t0 = std::chrono::steady_clock::now();
   gencd_stats loc{};
   gencd_stats *st_out = stats ? stats : &loc;
@@ -342,7 +356,6 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   const int rule = p->rule;
   const int mode = mode_of(rule);
   const int64_t k_live = su.k_live;
-  const int64_t extra = int64_t(su.total_pieces) - k_live;
   std::vector<int32_t> cls_sizes;
   int64_t C = 0;
   if (rule == GENCD_COLORING) {
@@ -379,24 +392,23 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   else if (rule == GENCD_GREEDY) S = k_live;
   else S = p->select_size;
   if (S > k_live) S = k_live;
+  if (S < 1) S = 1;
   const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
+  const int64_t extra = int64_t(su.total_pieces) - k_live;  // pieces beyond one per column
+  int64_t max_class = 0;
+  for (int32_t sz : cls_sizes) max_class = std::max<int64_t>(max_class, sz);
+  int64_t *epoch_dev = reinterpret_cast<int64_t *>(ws.red + 12);
+  st = fill_f64(ws.red + 12, 1, 0.0, s);  // epoch counter = 0
+  if (st) return st;
   IterArgs a = base_args(X, y, p, su, w, ws.z_hi, ws.z_lo);
-  unsigned long long acc_nnz_seen = 0, acc_cnt_seen = 0, fused_seen = ck.fused_nnz;
+  unsigned long long acc_nnz_seen = 0, acc_cnt_seen = 0;
   // GENCD_PROFILE: one event pair per Propose launch between two checks
-  const bool prof = (p->flags & GENCD_PROFILE) != 0;
+  const bool use_graph = (p->flags & GENCD_USE_GRAPH) != 0;
+  const bool prof = (p->flags & GENCD_PROFILE) != 0 && !use_graph;
   EventPool pool;
   std::vector<hipEvent_t> &evs = pool.v;
   size_t ev_used = 0;
   double prof_bytes_pending = 0.0;
-  if (prof) {
-    const int64_t T0 = (rule == GENCD_COLORING) ? C : (k_live + S - 1) / std::max<int64_t>(S, 1);
-    const int64_t want = 2 * std::max<int64_t>(T0, 1) * check_every;
-    if (want <= 2 * 65536) {
-      evs.resize(size_t(want));
-      for (auto &ev : evs)
-        if (hipEventCreate(&ev) != hipSuccess) ev = nullptr;
-    }
-  }
   auto harvest = [&]() {
     // called after a stream synchronisation: every recorded pair is complete
     double ms = 0.0;
@@ -411,52 +423,95 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
     prof_bytes_pending = 0.0;
     ev_used = 0;
   };
+  GraphHolder graph;
+  int64_t graph_S = -1;
 
-  for (int64_t e = 0; status != GENCD_OK && e < p->max_epochs && k_live > 0; ++e) {
-    st = launch_epoch_order(ws, k_live, rule, p->seed, e, C, s);
-    if (st) return st;
-    const int64_t T = (rule == GENCD_COLORING) ? C : (k_live + S - 1) / S;
+  // Enqueue one epoch: selection order (section 2.1), then every iteration
+  // of Algorithm 1, then the epoch counter increment.  Every argument is
+  // independent of the epoch number, so the sequence can be captured once.
+  auto enqueue_epoch = [&](int64_t T, int64_t e_host, bool record, hipStream_t es) -> int {
+    int rc = launch_epoch_order(ws, k_live, rule, p->seed, epoch_dev, C, S, T, es);
+    if (rc) return rc;
     PermKey cpk{};
-    if (rule == GENCD_COLORING) cpk = make_perm_key(C, p->seed, e);
+    if (rule == GENCD_COLORING && !use_graph) cpk = make_perm_key(C, p->seed, e_host);
     for (int64_t t = 0; t < T; ++t) {
-      int64_t positions;
+      int64_t positions, bound;
       if (rule == GENCD_COLORING) {
         a.win_off = ws.win_off;
-        a.t = int32_t(t);
-        positions = cls_sizes[size_t(perm_apply(cpk, uint64_t(t)))];
+        positions = use_graph ? max_class : cls_sizes[size_t(perm_apply(cpk, uint64_t(t)))];
+        bound = max_class + extra;
       } else {
         a.win_off = nullptr;
         a.win_lo = int32_t(t * S);
         a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
         positions = a.win_hi - a.win_lo;
+        bound = positions + extra;
       }
       if (positions == 0) continue;
+      a.t = int32_t(t);
       const int64_t B = (rule == GENCD_THREAD_GREEDY) ? p->block : positions;
-      const bool deferred = (mode == 2) || extra > 0;
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (!evs.empty() && ev_used + 2 <= evs.size()) {
+      if (record && !evs.empty() && ev_used + 2 <= evs.size()) {
         e0 = evs[ev_used];
         e1 = evs[ev_used + 1];
         ev_used += 2;
       }
-      st = launch_iteration(a, su.group, mode, B, groups_for(positions, extra),
-                            (positions + B - 1) / B, deferred, s, e0, e1);
-      if (st) return st;
-      st_out->iters++;
-      if (mode != 2) st_out->coord_updates += positions;
+      rc = launch_iteration(a, su.group, mode, B, groups_for(bound, 0), (positions + B - 1) / B,
+                            es, e0, e1);
+      if (rc) return rc;
     }
+    return launch_inc_epoch(epoch_dev, es);
+  };
+
+  for (int64_t e = 0; status != GENCD_OK && e < p->max_epochs && k_live > 0; ++e) {
+    const int64_t T = (rule == GENCD_COLORING) ? C : (k_live + S - 1) / S;
+    if (prof && evs.empty()) {
+      const int64_t want = 2 * std::max<int64_t>(T, 1) * check_every;
+      if (want <= 2 * 65536) {
+        evs.resize(size_t(want));
+        for (auto &ev : evs)
+          if (hipEventCreate(&ev) != hipSuccess) ev = nullptr;
+      }
+    }
+    if (use_graph) {
+      if (graph_S != S) {
+        // capture on a private stream (the caller's may be the legacy
+        // default stream, which cannot be captured); replay on the caller's
+        graph.reset();
+        if (!graph.cs) GENCD_HIP(hipStreamCreateWithFlags(&graph.cs, hipStreamNonBlocking));
+        GENCD_HIP(hipStreamBeginCapture(graph.cs, hipStreamCaptureModeRelaxed));
+        st = enqueue_epoch(T, e, false, graph.cs);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(graph.cs, &g);
+        if (st) {
+          if (g) hipGraphDestroy(g);
+          return st;
+        }
+        if (ce != hipSuccess) return GENCD_ERR_HIP;
+        graph.g = g;
+        GENCD_HIP(hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0));
+        graph_S = S;
+      }
+      GENCD_HIP(hipGraphLaunch(graph.exec, s));
+    } else {
+      st = enqueue_epoch(T, e, true, s);
+      if (st) return st;
+    }
+    int64_t iters = T;
+    if (rule == GENCD_COLORING) {
+      iters = 0;
+      for (int32_t sz : cls_sizes) iters += sz > 0;
+    }
+    st_out->iters += iters;
+    if (mode != 2) st_out->coord_updates += k_live;
     st_out->epochs = e + 1;
-    if (!evs.empty()) prof_bytes_pending += 12.0 * double(X->nnz) + 20.0 * double(k_live);
+    if (!evs.empty()) prof_bytes_pending += 20.0 * double(X->nnz) + 32.0 * double(k_live);
     st_out->nnz_visits += X->nnz;
     if (mode != 2) st_out->nnz_updates += X->nnz;
     if ((e + 1) % check_every == 0 || e + 1 == p->max_epochs) {
       st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
       if (st) return st;
-      if (!evs.empty()) {
-        prof_bytes_pending += 16.0 * double(ck.fused_nnz - fused_seen);
-        harvest();
-      }
-      fused_seen = ck.fused_nnz;
+      if (!evs.empty()) harvest();
       if (mode == 2) {
         st_out->coord_updates += int64_t(ck.acc_cnt - acc_cnt_seen);
         st_out->nnz_updates += int64_t(ck.acc_nnz - acc_nnz_seen);
@@ -506,6 +561,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
 int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const int32_t *J,
               int64_t nJ, float *w, float *z_hi, float *z_lo, float *g, float *delta, float *phi,
               int32_t *accepted, void *ws_base, size_t ws_bytes, hipStream_t s) {
+  (void)hipGetLastError();  // launch checks below must not see an earlier error
   int st = params_ok(p, false);
   if (st) return st;
   if (p->rule < GENCD_CYCLIC || p->rule > GENCD_COLORING) return GENCD_ERR_INVALID_ARG;
@@ -526,8 +582,6 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
     if (st) return st;
     if (r.bad & 8ull) return GENCD_ERR_INVALID_ARG;
   }
-  st = launch_refresh_all(X->n, p->loss, y, z_hi, z_lo, ws.r, s);
-  if (st) return st;
   st = launch_list_order(ws, J, nJ, s);
   if (st) return st;
   const int mode = mode_of(p->rule);
@@ -535,10 +589,11 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
   a.win_off = nullptr;
   a.win_lo = 0;
   a.win_hi = int32_t(nJ);
+  a.t = 0;
   a.gout = g;
   const int64_t B = (p->rule == GENCD_THREAD_GREEDY) ? p->block : nJ;
   const int64_t extra = int64_t(su.total_pieces) - su.k_live;
-  st = launch_iteration(a, su.group, mode, B, groups_for(nJ, extra), (nJ + B - 1) / B, true, s);
+  st = launch_iteration(a, su.group, mode, B, groups_for(nJ + extra, 0), (nJ + B - 1) / B, s);
   if (st) return st;
   if (delta) st = copy_f32(delta, ws.delta, nJ, s);
   if (st) return st;
@@ -553,6 +608,7 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
 int check_impl(const gencd_csc *X, const float *y, int loss, double lambda, const float *w,
                double *z64, double *g64, gencd_stats *stats, void *ws_base, size_t ws_bytes,
                hipStream_t s) {
+  (void)hipGetLastError();  // launch checks below must not see an earlier error
   gencd_params p{};
   p.loss = loss;
   p.lambda = lambda;

@@ -124,3 +124,22 @@ def test_coloring_step_matches_sequential_ccd():
     assert np.sqrt(np.mean(zo ** 2)) > 0
     assert np.all(np.abs(zg - zo) <= 1e-5 * scale)
     np.testing.assert_allclose(wd.cpu().numpy(), wo, rtol=1e-5, atol=1e-7)
+
+
+def test_coloring_graph_replays_bit_identical():
+    """Coloring uses no atomics: the captured-epoch path must reproduce the
+    plain path bit for bit over many replays."""
+    P = synth.c3_zipf_lasso(scale=0.01)
+    Xo = O.Matrix.of(P)
+    lam = 0.1 * O.lambda_max(Xo, P.y, P.loss)
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    colors, nc = G.color(X)
+    ws = []
+    for flags in (0, G.USE_GRAPH, G.USE_GRAPH):
+        params = G.make_params(P.loss, lam, rule=G.COLORING, colors=colors, num_colors=nc,
+                               seed=5, tol=1e-7, max_epochs=5000, piece=64, flags=flags)
+        res = G.solve(X, y, params)
+        assert res.status == G.OK and res.stats["epochs"] > 2
+        ws.append(res.w.cpu().numpy())
+    assert np.array_equal(ws[0], ws[1]) and np.array_equal(ws[1], ws[2])

@@ -300,3 +300,29 @@ def test_error_paths():
         G.solve(Xb, y, G.make_params(P.loss, 0.01, rule=G.SHOTGUN, select_size=8,
                                      flags=G.VALIDATE_DEVICE))
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("name,rule,kw", [("c2", G.SHOTGUN, dict(select_size=512)),
+                                          ("c2", G.THREAD_GREEDY, dict(select_size=2048, block=16)),
+                                          ("c4", G.SHOTGUN, dict(select_size=256))])
+def test_graph_path_matches_plain(problems, optima, name, rule, kw):
+    """The captured epoch is replayed once per epoch, with the eager FP64
+    check and host synchronisations between replays; every replay must give
+    the plain path's result (same objective and KKT level)."""
+    _print_case("graph", name, rule, kw)
+    P = problems[name]
+    lam, ref = optima[name]
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    out = {}
+    for flags in (0, G.USE_GRAPH):
+        params = G.make_params(P.loss, lam, rule=rule, seed=3, tol=1e-8, max_epochs=20000,
+                               flags=flags, **kw)
+        res = G.solve(X, y, params)
+        assert res.status == G.OK, res.stats
+        out[flags] = res
+    a, b = out[0], out[G.USE_GRAPH]
+    assert b.stats["epochs"] > 3
+    assert abs(a.stats["objective"] - b.stats["objective"]) <= 1e-9 * abs(ref.objective)
+    assert abs(b.stats["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
+    assert b.stats["kkt_max"] <= 1e-8
