@@ -74,6 +74,7 @@ typedef enum {
 #define GENCD_VALIDATE_DEVICE 0x2u /* check CSC structure and labels on the device */
 #define GENCD_USE_GRAPH 0x4u       /* replay each epoch as a captured HIP graph */
 #define GENCD_PROFILE 0x8u         /* time every Propose launch with HIP events */
+#define GENCD_EXACT_ACCUM 0x10u    /* TwoSum-compensate every atomic update of z */
 
 /* Device CSC matrix (see the conventions above). */
 typedef struct {

@@ -149,17 +149,14 @@ __device__ __forceinline__ float twosum_err(float a, float b) {
   return (a - (s - bp)) + (b - bp);
 }
 
-// Same without atomics: for updates that own the row (columns of one colour
-// class have disjoint rows).
+// Compensated update of a row the caller owns (columns of one colour class
+// have disjoint rows): exact product error by FMA, exact sum error by TwoSum.
 __device__ __forceinline__ void scatter_plain(float *z_hi, float *z_lo, int i, float d, float v) {
-  float p = d * v;
-  float pe = fmaf(d, v, -p);
-  float old = z_hi[i];
-  float s = old + p;
-  float bp = s - old;
-  float err = (old - (s - bp)) + (p - bp);
-  z_hi[i] = s;
-  z_lo[i] += err + pe;
+  const float p = d * v;
+  const float pe = fmaf(d, v, -p);
+  const float old = z_hi[i];
+  z_hi[i] = old + p;
+  z_lo[i] += twosum_err(old, p) + pe;
 }
 
 // ---------------------------------------------------------------------------

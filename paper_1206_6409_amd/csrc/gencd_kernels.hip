@@ -722,6 +722,12 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
           if (ri[u] >= 0) scatter_plain(a.z_hi, a.z_lo, ri[u], d, vv[u]);
+      } else if (!a.exact_accum) {
+        // increments accumulate in the low word (non-returning atomics); the
+        // pair is renormalised exactly at the end of the epoch
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (ri[u] >= 0) atomicAdd(&a.z_lo[ri[u]], d * vv[u]);
       } else {
         // issue all the returning atomics first, then the compensations
         float pp[kUnroll], old[kUnroll];
@@ -739,6 +745,22 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       }
     }
   }
+}
+
+// Exact renormalisation of the fitted values: (z_hi, z_lo) <- TwoSum.
+__global__ __launch_bounds__(kBlock) void k_renorm(int64_t n, float *z_hi, float *z_lo) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const float h = z_hi[i], l = z_lo[i];
+    const float s = h + l;
+    z_lo[i] = twosum_err(h, l);
+    z_hi[i] = s;
+  }
+}
+
+int launch_renorm(int64_t n, float *z_hi, float *z_lo, hipStream_t s) {
+  hipLaunchKernelGGL(k_renorm, dim3(grid_for(n, 2048)), dim3(kBlock), 0, s, n, z_hi, z_lo);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
 template <int G>

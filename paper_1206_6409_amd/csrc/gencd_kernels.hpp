@@ -24,6 +24,7 @@ struct IterArgs {
   int32_t t, win_lo, win_hi;
   float *delta, *phi, *gacc, *gout, *wsnap;
   int32_t *acc;
+  int32_t exact_accum;     // 1: TwoSum per update (returning atomics); 0: low-word accumulation
   unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals, [3] updated nnz
 };
 
@@ -52,6 +53,7 @@ int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int6
                      hipEvent_t ev1 = nullptr);
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
                  int piece, int32_t total_pieces, const Ws &ws, bool resync, hipStream_t s);
+int launch_renorm(int64_t n, float *z_hi, float *z_lo, hipStream_t s);
 int launch_round_f32(const double *src, float *dst, int64_t m, hipStream_t s);
 
 }  // namespace gencd

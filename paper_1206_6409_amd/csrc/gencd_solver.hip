@@ -241,6 +241,7 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   a.wbounds = ws.wbounds;
   a.acc = ws.acc;
   a.counters = reinterpret_cast<unsigned long long *>(ws.red) + 8;
+  a.exact_accum = (p->flags & GENCD_EXACT_ACCUM) ? 1 : 0;
   return a;
 }
 
@@ -460,6 +461,10 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
                             es, e0, e1);
       if (rc) return rc;
     }
+    if (mode != 1 && !a.exact_accum) {
+      rc = launch_renorm(X->n, ws.z_hi, ws.z_lo, es);
+      if (rc) return rc;
+    }
     return launch_inc_epoch(epoch_dev, es);
   };
 
@@ -469,8 +474,10 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       const int64_t want = 2 * std::max<int64_t>(T, 1) * check_every;
       if (want <= 2 * 65536) {
         evs.resize(size_t(want));
+        // no system-scope fence at the markers: the pair then brackets the
+        // kernel without an extra cache flush
         for (auto &ev : evs)
-          if (hipEventCreate(&ev) != hipSuccess) ev = nullptr;
+          if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) ev = nullptr;
       }
     }
     if (use_graph) {

@@ -118,12 +118,15 @@ STEP_CASES = [
     ("c2", G.THREAD_GREEDY, 64, 64, 256), ("c2", G.THREAD_GREEDY, 7, 16, 64),
     ("c2", G.GREEDY, 0, 64, 1024),
     ("c3", G.SHOTGUN, 0, 64, 64), ("c4", G.SHOTGUN, 0, 64, 64), ("c4", G.THREAD_GREEDY, 16, 64, 64),
+    ("c2", G.SHOTGUN, 0, 64, 256, G.EXACT_ACCUM), ("c2", G.THREAD_GREEDY, 64, 64, 256, G.EXACT_ACCUM),
 ]
 
 
-@pytest.mark.parametrize("name,rule,block,group,piece", STEP_CASES)
-def test_step_parity(problems, name, rule, block, group, piece):
-    _print_case("step", name, rule, block, group, piece)
+@pytest.mark.parametrize("case", STEP_CASES)
+def test_step_parity(problems, case):
+    name, rule, block, group, piece = case[:5]
+    flags = case[5] if len(case) > 5 else 0
+    _print_case("step", name, rule, block, group, piece, flags)
     P = problems[name]
     X = G.Matrix.of(P)
     Xo = O.Matrix.of(P)
@@ -141,7 +144,7 @@ def test_step_parity(problems, name, rule, block, group, piece):
     if heavy not in J:
         J[0] = heavy
     params = G.make_params(P.loss, lam, rule=rule, select_size=m, block=block, group=group,
-                           piece=piece)
+                           piece=piece, flags=flags)
     w_d = torch.as_tensor(w, device=DEV)
     zh_d = torch.as_tensor(z_hi, device=DEV)
     zl_d = torch.as_tensor(z_lo, device=DEV)
@@ -315,7 +318,7 @@ def test_graph_path_matches_plain(problems, optima, name, rule, kw):
     X = G.Matrix.of(P)
     y = torch.as_tensor(P.y, device=DEV)
     out = {}
-    for flags in (0, G.USE_GRAPH):
+    for flags in (0, G.USE_GRAPH, G.USE_GRAPH | G.EXACT_ACCUM):
         params = G.make_params(P.loss, lam, rule=rule, seed=3, tol=1e-8, max_epochs=20000,
                                flags=flags, **kw)
         res = G.solve(X, y, params)
@@ -323,6 +326,8 @@ def test_graph_path_matches_plain(problems, optima, name, rule, kw):
         out[flags] = res
     a, b = out[0], out[G.USE_GRAPH]
     assert b.stats["epochs"] > 3
+    c = out[G.USE_GRAPH | G.EXACT_ACCUM]
+    assert abs(c.stats["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
     assert abs(a.stats["objective"] - b.stats["objective"]) <= 1e-9 * abs(ref.objective)
     assert abs(b.stats["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
     assert b.stats["kkt_max"] <= 1e-8
