@@ -185,6 +185,23 @@ int gencd_color_workspace_bytes(const gencd_csc *X, size_t *out_bytes);
 int gencd_color(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws,
                 size_t ws_bytes, hipStream_t stream);
 
+/* Regularisation path: solve Eq. (1) for L values of lambda (any order;
+ * decreasing order makes the warm starts effective) on one matrix, B of them
+ * at a time in one batched launch sequence (B in {16, 32, 64}).  All slots
+ * share the selected sets of the Shotgun rule (p->rule must be
+ * GENCD_SHOTGUN, |J| = p->select_size); each slot has its own lambda, its
+ * own FP64 KKT test and stops independently.  When a slot finishes, the next
+ * lambda takes it, starting from the latest iterate of the previous lambda
+ * (section 4.1 mentions starting from a large lambda and decreasing it).
+ *   lambdas: host double[L];  W: device float32[L][k] (row t = solution for
+ *   lambdas[t]);  stats: host gencd_stats[L].
+ * Workspace bytes from gencd_path_workspace_bytes. */
+int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_t B,
+                               size_t *out_bytes);
+int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
+                     const double *lambdas, int32_t L, int32_t B, float *W, void *ws,
+                     size_t ws_bytes, hipStream_t stream, gencd_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,624 @@
+// Batched regularisation path: many lambda values of Eq. (1) on one matrix.
+//
+// B "slots" (B in {16, 32, 64}) are solved together with a shared selected
+// set J (Shotgun windows of the per-epoch permutation, section 2.1): a group
+// of B lanes owns one column of J and lane s works for slot s, so every read
+// of the slot-interleaved state W[k][B], Z[n][B] is one coalesced B-wide row
+// and the CSC entries of X are read once for all slots.  Propose (Algorithm
+// 4) and Update (Algorithm 3) are the single-problem ones applied per lane
+// with the lane's own lambda; the FP64 check (objective, KKT, re-sync) runs
+// per slot.  A slot whose KKT test passes is retired on the host and the
+// next lambda (decreasing order) is admitted into it, warm-started from the
+// latest iterate of its predecessor.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gencd_common.hpp"
+#include "gencd_kernels.hpp"
+
+namespace gencd {
+
+struct PathWs {
+  float *W;              // [k][B]
+  float *zh, *zl;        // [n][B]
+  float *lam;            // [B] lambda of each slot for the FP32 Propose arithmetic
+  double *lam64;         // [B] the same lambda in FP64 for the check
+  int32_t *active;       // [B]
+  float *delta;          // [S][B] deltas of the current window
+  double *z64, *r64;     // [n][B]
+  double *g64;           // [k][B]
+  double *red;           // [B][8]: loss, l1, kkt bits, nnz, gmax bits, dual
+};
+
+static size_t path_layout(int64_t n, int64_t k, int64_t S, int B, void *base, PathWs *o) {
+  const size_t al = 256;
+  size_t off = 0;
+  char *b = static_cast<char *>(base);
+  auto take = [&](size_t bytes) -> void * {
+    off = (off + al - 1) / al * al;
+    void *p = b ? b + off : nullptr;
+    off += bytes > 0 ? bytes : 1;
+    return p;
+  };
+  PathWs w{};
+  w.W = static_cast<float *>(take(sizeof(float) * k * B));
+  w.zh = static_cast<float *>(take(sizeof(float) * n * B));
+  w.zl = static_cast<float *>(take(sizeof(float) * n * B));
+  w.lam = static_cast<float *>(take(sizeof(float) * B));
+  w.lam64 = static_cast<double *>(take(sizeof(double) * B));
+  w.active = static_cast<int32_t *>(take(sizeof(int32_t) * B));
+  w.delta = static_cast<float *>(take(sizeof(float) * S * B));
+  w.z64 = static_cast<double *>(take(sizeof(double) * n * B));
+  w.r64 = static_cast<double *>(take(sizeof(double) * n * B));
+  w.g64 = static_cast<double *>(take(sizeof(double) * k * B));
+  w.red = static_cast<double *>(take(sizeof(double) * 8 * B));
+  if (o) *o = w;
+  return off + al;
+}
+
+// ---------------------------------------------------------------------------
+// Batched Propose / Update over one window of shared J
+// ---------------------------------------------------------------------------
+struct PathArgs {
+  const int64_t *col_ptr;
+  const int32_t *row_idx;
+  const float *val;
+  const float *y;
+  const float *c;
+  const int32_t *col_of_pos;
+  int32_t win_lo, win_hi;
+  float n_f;
+  int32_t loss;
+  float *W, *zh, *zl;
+  const float *lam;
+  const int32_t *active;
+  float *delta;
+};
+
+// One group of B lanes per column; the column's entries are staged in LDS
+// (B at a time) and broadcast to the lanes.
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
+  constexpr int GPB = kBlock / B;  // groups per block
+  __shared__ int32_t srow[GPB][B];
+  __shared__ float sval[GPB][B];
+  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  const int64_t npos = a.win_hi - a.win_lo;
+  const bool on = a.active[s] != 0;
+  for (int64_t p0 = int64_t(blockIdx.x) * GPB; p0 < npos; p0 += int64_t(gridDim.x) * GPB) {
+    const int64_t p = p0 + grp;
+    const bool have = p < npos;
+    int32_t j = 0;
+    int64_t cb = 0, ce = 0;
+    if (have) {
+      j = a.col_of_pos[a.win_lo + p];
+      cb = a.col_ptr[j];
+      ce = a.col_ptr[j + 1];
+    }
+    float acc = 0.0f;
+    for (int64_t base = cb; base < ce; base += B) {
+      const int64_t e = base + s;
+      srow[grp][s] = e < ce ? a.row_idx[e] : -1;
+      sval[grp][s] = e < ce ? a.val[e] : 0.0f;
+      __builtin_amdgcn_wave_barrier();
+      const int cnt = int(ce - base < B ? ce - base : B);
+      int u = 0;
+      for (; u + kUnroll <= cnt; u += kUnroll) {
+        float zh[kUnroll], zl[kUnroll], yy[kUnroll], vv[kUnroll];
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+          const int32_t i = srow[grp][u + q];
+          vv[q] = sval[grp][u + q];
+          zh[q] = a.zh[int64_t(i) * B + s];
+          zl[q] = a.zl[int64_t(i) * B + s];
+          yy[q] = a.y[i];
+        }
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) acc += vv[q] * dloss_f32(a.loss, yy[q], zh[q] + zl[q]);
+      }
+      for (; u < cnt; ++u) {
+        const int32_t i = srow[grp][u];
+        acc += sval[grp][u] *
+               dloss_f32(a.loss, a.y[i], a.zh[int64_t(i) * B + s] + a.zl[int64_t(i) * B + s]);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (have) {
+      float d = 0.0f;
+      if (on) {
+        const float g = acc / a.n_f;
+        const float wj = a.W[int64_t(j) * B + s];
+        float ph;
+        propose_f32(g, a.c[j], wj, a.lam[s], d, ph);
+        if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
+      }
+      a.delta[p * B + s] = d;
+    }
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_update(PathArgs a) {
+  constexpr int GPB = kBlock / B;
+  __shared__ int32_t srow[GPB][B];
+  __shared__ float sval[GPB][B];
+  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  const int64_t npos = a.win_hi - a.win_lo;
+  for (int64_t p0 = int64_t(blockIdx.x) * GPB; p0 < npos; p0 += int64_t(gridDim.x) * GPB) {
+    const int64_t p = p0 + grp;
+    const bool have = p < npos;
+    int64_t cb = 0, ce = 0;
+    float d = 0.0f;
+    if (have) {
+      const int32_t j = a.col_of_pos[a.win_lo + p];
+      cb = a.col_ptr[j];
+      ce = a.col_ptr[j + 1];
+      d = a.delta[p * B + s];
+    }
+    for (int64_t base = cb; base < ce; base += B) {
+      const int64_t e = base + s;
+      srow[grp][s] = e < ce ? a.row_idx[e] : -1;
+      sval[grp][s] = e < ce ? a.val[e] : 0.0f;
+      __builtin_amdgcn_wave_barrier();
+      const int cnt = int(ce - base < B ? ce - base : B);
+      if (d != 0.0f)
+        for (int u = 0; u < cnt; ++u)
+          atomicAdd(&a.zl[int64_t(srow[grp][u]) * B + s], d * sval[grp][u]);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP64 check (per slot): z64 = X W, loss, r64, g64, KKT, |w|_1, dual
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_zero(double *z64, int64_t n, double *g64, int64_t k,
+                                                      double *red) {
+  const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t nt = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = tid; i < n * B; i += nt) z64[i] = 0.0;
+  for (int64_t j = tid; j < k * B; j += nt) g64[j] = 0.0;
+  if (tid < 8 * B) red[tid] = 0.0;
+}
+
+// one group of B lanes per column: z64[i][s] += W[j][s] * x_ij
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_spmv(const int64_t *col_ptr, const int32_t *row_idx,
+                                                      const float *val, int64_t k, const float *W,
+                                                      double *z64) {
+  constexpr int GPB = kBlock / B;
+  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  for (int64_t j = int64_t(blockIdx.x) * GPB + grp; j < k; j += int64_t(gridDim.x) * GPB) {
+    const double wj = double(W[j * B + s]);
+    if (wj == 0.0) continue;
+    for (int64_t e = col_ptr[j]; e < col_ptr[j + 1]; ++e)
+      atomicAdd(&z64[int64_t(row_idx[e]) * B + s], wj * double(val[e]));
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_rows(int64_t n, int loss, const float *y,
+                                                      const double *z64, double *r64, float *zh,
+                                                      float *zl, double *red) {
+  constexpr int GPB = kBlock / B;
+  __shared__ double sacc[kBlock];
+  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * GPB + grp; i < n; i += int64_t(gridDim.x) * GPB) {
+    const double t = z64[i * B + s];
+    const double yi = double(y[i]);
+    acc += loss_f64(loss, yi, t);
+    r64[i * B + s] = dloss_f64(loss, yi, t);
+    const float h = float(t);
+    zh[i * B + s] = h;
+    zl[i * B + s] = float(t - double(h));
+  }
+  sacc[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < B) {
+    double t = 0.0;
+    for (int g = 0; g < GPB; ++g) t += sacc[g * B + threadIdx.x];
+    atomicAdd(&red[threadIdx.x * 8 + 0], t);
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_cols(const int64_t *col_ptr, const int32_t *row_idx,
+                                                      const float *val, int64_t k,
+                                                      const double *r64, double *g64) {
+  constexpr int GPB = kBlock / B;
+  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  for (int64_t j = int64_t(blockIdx.x) * GPB + grp; j < k; j += int64_t(gridDim.x) * GPB) {
+    double acc = 0.0;
+    int64_t e = col_ptr[j];
+    const int64_t ce = col_ptr[j + 1];
+    for (; e + kUnroll <= ce; e += kUnroll) {
+      double r[kUnroll];
+      float v[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        v[q] = val[e + q];
+        r[q] = r64[int64_t(row_idx[e + q]) * B + s];
+      }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) acc += double(v[q]) * r[q];
+    }
+    for (; e < ce; ++e) acc += double(val[e]) * r64[int64_t(row_idx[e]) * B + s];
+    g64[j * B + s] = acc;
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_kkt(int64_t k, double *g64, const float *W,
+                                                     const double *lam, double inv_n, double *red) {
+  constexpr int GPB = kBlock / B;
+  __shared__ double smax[kBlock], sl1[kBlock], sgm[kBlock], snz[kBlock];
+  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  const double l = lam[s];
+  double vmax = 0.0, l1 = 0.0, gmax = 0.0, nz = 0.0;
+  for (int64_t j = int64_t(blockIdx.x) * GPB + grp; j < k; j += int64_t(gridDim.x) * GPB) {
+    const double g = g64[j * B + s] * inv_n;
+    g64[j * B + s] = g;
+    if (!(fabs(g) <= gmax)) gmax = fabs(g);
+    const double wj = double(W[j * B + s]);
+    double v;
+    if (wj != 0.0) {
+      v = fabs(g + (wj > 0.0 ? l : -l));
+      l1 += fabs(wj);
+      nz += 1.0;
+    } else {
+      v = fabs(g) - l;
+      if (v < 0.0) v = 0.0;
+    }
+    if (!(v <= vmax)) vmax = v;
+  }
+  smax[threadIdx.x] = vmax;
+  sl1[threadIdx.x] = l1;
+  sgm[threadIdx.x] = gmax;
+  snz[threadIdx.x] = nz;
+  __syncthreads();
+  if (threadIdx.x < B) {
+    double m = 0.0, a1 = 0.0, gm = 0.0, z = 0.0;
+    for (int g = 0; g < GPB; ++g) {
+      const int t = g * B + threadIdx.x;
+      if (!(smax[t] <= m)) m = smax[t];
+      if (!(sgm[t] <= gm)) gm = sgm[t];
+      a1 += sl1[t];
+      z += snz[t];
+    }
+    unsigned long long *rb = reinterpret_cast<unsigned long long *>(red + threadIdx.x * 8);
+    atomicMax(rb + 2, (m != m) ? 0x7FF8000000000000ull : (unsigned long long)__double_as_longlong(m));
+    atomicMax(rb + 4, (gm != gm) ? 0x7FF8000000000000ull : (unsigned long long)__double_as_longlong(gm));
+    atomicAdd(&red[threadIdx.x * 8 + 1], a1);
+    atomicAdd(&red[threadIdx.x * 8 + 3], z);
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_dual(int64_t n, int loss, const float *y,
+                                                      const double *r64, const double *lam,
+                                                      double *red) {
+  constexpr int GPB = kBlock / B;
+  __shared__ double sacc[kBlock];
+  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  const double l = lam[s];
+  const double gm = __longlong_as_double(reinterpret_cast<long long *>(red + s * 8)[4]);
+  const double sc = (gm > l) ? l / gm : 1.0;
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * GPB + grp; i < n; i += int64_t(gridDim.x) * GPB) {
+    const double v = sc * r64[i * B + s];
+    const double yi = double(y[i]);
+    if (loss == GENCD_SQUARED) {
+      acc -= v * yi + 0.5 * v * v;
+    } else {
+      const double pp = -v * yi;
+      double h = 0.0;
+      if (pp > 0.0) h -= pp * log(pp);
+      if (pp < 1.0) h -= (1.0 - pp) * log1p(-pp);
+      acc += h;
+    }
+  }
+  sacc[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < B) {
+    double t = 0.0;
+    for (int g = 0; g < GPB; ++g) t += sacc[g * B + threadIdx.x];
+    atomicAdd(&red[threadIdx.x * 8 + 5], t);
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_renorm(int64_t m, float *zh, float *zl) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kBlock) {
+    const float h = zh[i], l = zl[i];
+    zh[i] = h + l;
+    zl[i] = twosum_err(h, l);
+  }
+}
+
+// copy slot columns: dst[j*ds + so] = src[j*ss + si] for j < k
+__global__ __launch_bounds__(kBlock) void k_strided_copy(int64_t k, const float *src, int64_t ss,
+                                                         int64_t si, float *dst, int64_t ds,
+                                                         int64_t so) {
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock)
+    dst[j * ds + so] = src ? src[j * ss + si] : 0.0f;
+}
+
+static unsigned g1(int64_t m, unsigned cap = 4096) {
+  int64_t b = (m + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return unsigned(b);
+}
+
+template <int B>
+static int path_check(const gencd_csc *X, const float *y, int loss, const PathWs &w, hipStream_t s,
+                      std::vector<double> *red) {
+  constexpr int GPB = kBlock / B;
+  const int64_t n = X->n, k = X->k;
+  hipLaunchKernelGGL(k_path_zero<B>, dim3(g1((n > k ? n : k) * B)), dim3(kBlock), 0, s, w.z64, n,
+                     w.g64, k, w.red);
+  const unsigned gk = unsigned(std::min<int64_t>((k + GPB - 1) / GPB, 16384));
+  const unsigned gn = unsigned(std::min<int64_t>((n + GPB - 1) / GPB, 2048));
+  hipLaunchKernelGGL(k_path_spmv<B>, dim3(gk), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
+                     k, w.W, w.z64);
+  hipLaunchKernelGGL(k_path_rows<B>, dim3(gn), dim3(kBlock), 0, s, n, loss, y, w.z64, w.r64, w.zh,
+                     w.zl, w.red);
+  hipLaunchKernelGGL(k_path_cols<B>, dim3(gk), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
+                     k, w.r64, w.g64);
+  hipLaunchKernelGGL(k_path_kkt<B>, dim3(std::min<unsigned>(gk, 512)), dim3(kBlock), 0, s, k,
+                     w.g64, w.W, w.lam64, 1.0 / double(n), w.red);
+  hipLaunchKernelGGL(k_path_dual<B>, dim3(std::min<unsigned>(gn, 512)), dim3(kBlock), 0, s, n,
+                     loss, y, w.r64, w.lam64, w.red);
+  GENCD_HIP(hipGetLastError());
+  red->resize(size_t(8) * B);
+  GENCD_HIP(hipMemcpyAsync(red->data(), w.red, sizeof(double) * 8 * B, hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipStreamSynchronize(s));
+  return GENCD_OK;
+}
+
+struct PathSetup {
+  Ws base;
+  int piece;
+  int32_t total_pieces;
+  int64_t k_live;
+};
+
+int path_setup(const gencd_csc *X, const float *y, const gencd_params *p, void *ws, size_t bytes,
+               hipStream_t s, PathSetup *out, size_t *used);
+
+size_t path_workspace_bytes(int64_t n, int64_t k, int64_t nnz, int64_t S, int B, int piece) {
+  return workspace_layout(n, k, nnz, piece, nullptr, nullptr) + 256 +
+         path_layout(n, k, S, B, nullptr, nullptr) + 256;
+}
+
+template <int B>
+int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const double *lambdas,
+             int32_t L, float *W_out, char *path_base, const PathSetup &su, hipStream_t s,
+             gencd_stats *stats) {
+  constexpr int GPB = kBlock / B;
+  const int64_t n = X->n, k = X->k, k_live = su.k_live;
+  int64_t S = std::min<int64_t>(p->select_size, std::max<int64_t>(k_live, 1));
+  PathWs w{};
+  path_layout(n, k, S, B, path_base, &w);
+  const Ws &ws = su.base;
+  // slots
+  std::vector<int32_t> slot_lambda(B, -1);   // lambda index held by each slot
+  std::vector<int32_t> lambda_slot(L, -1);
+  std::vector<int32_t> done(L, 0);
+  std::vector<int64_t> start_epoch(L, 0);
+  std::vector<float> lam_host(B, 0.0f);
+  std::vector<double> lam64_host(B, 0.0);
+  std::vector<int32_t> act_host(B, 0);
+  int32_t next = 0;
+  int st = fill_f32(w.W, k * B, 0.0f, s);
+  if (st) return st;
+  auto admit = [&](int slot, int64_t epoch) -> int {
+    const int32_t t = next++;
+    slot_lambda[slot] = t;
+    lambda_slot[t] = slot;
+    lam_host[slot] = float(lambdas[t]);
+    lam64_host[slot] = lambdas[t];
+    act_host[slot] = 1;
+    start_epoch[t] = epoch;
+    // warm start from the latest iterate of the predecessor (decreasing lambdas)
+    const float *src = nullptr;
+    int64_t ss = 0, si = 0;
+    if (t > 0 && lambda_slot[t - 1] >= 0 && !done[t - 1]) {
+      src = w.W;
+      ss = B;
+      si = lambda_slot[t - 1];
+    } else if (t > 0 && done[t - 1]) {
+      src = W_out + int64_t(t - 1) * k;
+      ss = 1;
+      si = 0;
+    }
+    if (src == w.W && si == slot) return GENCD_OK;
+    hipLaunchKernelGGL(k_strided_copy, dim3(g1(k)), dim3(kBlock), 0, s, k, src, ss, si, w.W,
+                       int64_t(B), int64_t(slot));
+    return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+  };
+  for (int slot = 0; slot < B && next < L; ++slot) {
+    st = admit(slot, 0);
+    if (st) return st;
+  }
+  auto push_slots = [&]() -> int {
+    GENCD_HIP(hipMemcpyAsync(w.lam, lam_host.data(), sizeof(float) * B, hipMemcpyHostToDevice, s));
+    GENCD_HIP(hipMemcpyAsync(w.lam64, lam64_host.data(), sizeof(double) * B,
+                             hipMemcpyHostToDevice, s));
+    GENCD_HIP(hipMemcpyAsync(w.active, act_host.data(), sizeof(int32_t) * B,
+                             hipMemcpyHostToDevice, s));
+    return GENCD_OK;
+  };
+  st = push_slots();
+  if (st) return st;
+
+  int64_t *epoch_dev = reinterpret_cast<int64_t *>(ws.red + 12);
+  st = fill_f64(ws.red + 12, 1, 0.0, s);
+  if (st) return st;
+  PathArgs a{};
+  a.col_ptr = X->col_ptr;
+  a.row_idx = X->row_idx;
+  a.val = X->val;
+  a.y = y;
+  a.c = ws.c;
+  a.col_of_pos = ws.col_of_pos;
+  a.n_f = float(n);
+  a.loss = p->loss;
+  a.W = w.W;
+  a.zh = w.zh;
+  a.zl = w.zl;
+  a.lam = w.lam;
+  a.active = w.active;
+  a.delta = w.delta;
+  const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
+  std::vector<double> red;
+  const int64_t T = (k_live + S - 1) / S;
+  int64_t e = 0;
+  bool resync = true;
+  int remaining = L;
+  while (remaining > 0) {
+    if (resync || e % check_every == 0) {
+      st = path_check<B>(X, y, p->loss, w, s, &red);
+      if (st) return st;
+      resync = false;
+      bool admitted = false;
+      for (int slot = 0; slot < B; ++slot) {
+        const int32_t t = slot_lambda[slot];
+        if (t < 0 || done[t]) continue;
+        const double lsum = red[slot * 8 + 0], l1 = red[slot * 8 + 1], dsum = red[slot * 8 + 5];
+        unsigned long long kb;
+        std::memcpy(&kb, &red[slot * 8 + 2], 8);
+        double kkt;
+        std::memcpy(&kkt, &kb, 8);
+        const double obj = lsum / double(n) + lam64_host[slot] * l1;
+        gencd_stats &so = stats[t];
+        so.objective = obj;
+        so.kkt_max = kkt;
+        so.gap = obj - dsum / double(n);
+        so.nnz_w = int64_t(red[slot * 8 + 3]);
+        so.epochs = e - start_epoch[t];
+        so.lambda_max = 0.0;
+        if (!std::isfinite(obj)) return GENCD_ERR_DIVERGED;
+        const bool conv = kkt <= p->kkt_tol &&
+                          (p->gap_tol <= 0.0 || so.gap <= p->gap_tol * std::fabs(obj));
+        const bool out_of_epochs = so.epochs >= p->max_epochs;
+        if (conv || out_of_epochs) {
+          so.converged = conv ? 1 : 0;
+          hipLaunchKernelGGL(k_strided_copy, dim3(g1(k)), dim3(kBlock), 0, s, k, w.W, int64_t(B),
+                             int64_t(slot), W_out + int64_t(t) * k, int64_t(1), int64_t(0));
+          GENCD_HIP(hipGetLastError());
+          done[t] = 1;
+          --remaining;
+          slot_lambda[slot] = -1;
+          act_host[slot] = 0;
+          lam_host[slot] = 0.0f;
+          lam64_host[slot] = 0.0;
+          if (next < L) {
+            st = admit(slot, e);
+            if (st) return st;
+            admitted = true;
+          }
+        }
+      }
+      st = push_slots();
+      if (st) return st;
+      if (remaining == 0) break;
+      if (admitted) {
+        resync = true;  // z of the admitted slots must be recomputed from W
+        continue;
+      }
+    }
+    // one epoch over the live columns with shared windows
+    st = launch_epoch_order(ws, k_live, GENCD_SHOTGUN, p->seed, epoch_dev, 0, S, T, s);
+    if (st) return st;
+    for (int64_t t = 0; t < T; ++t) {
+      a.win_lo = int32_t(t * S);
+      a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
+      const int64_t npos = a.win_hi - a.win_lo;
+      const unsigned grid = unsigned(std::min<int64_t>((npos + GPB - 1) / GPB, 16384));
+      hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(k_path_update<B>, dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_path_renorm<B>, dim3(g1(n * B)), dim3(kBlock), 0, s, n * B, w.zh, w.zl);
+    st = launch_inc_epoch(epoch_dev, s);
+    if (st) return st;
+    GENCD_HIP(hipGetLastError());
+    for (int slot = 0; slot < B; ++slot) {
+      const int32_t t = slot_lambda[slot];
+      if (t >= 0 && !done[t]) {
+        stats[t].iters += T;
+        stats[t].coord_updates += k_live;
+        stats[t].nnz_visits += X->nnz;
+        stats[t].nnz_updates += X->nnz;
+      }
+    }
+    ++e;
+  }
+  GENCD_HIP(hipStreamSynchronize(s));
+  return GENCD_OK;
+}
+
+}  // namespace gencd
+
+using namespace gencd;
+
+extern "C" {
+
+int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_t B,
+                               size_t *out_bytes) {
+  if (!X || !p || !out_bytes || X->n <= 0 || X->k <= 0 || X->nnz < 0) return GENCD_ERR_INVALID_ARG;
+  if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
+  if (p->select_size <= 0) return GENCD_ERR_INVALID_ARG;
+  const int piece = p->piece ? p->piece : 512;
+  *out_bytes = path_workspace_bytes(X->n, X->k, X->nnz, std::min<int64_t>(p->select_size, X->k), B,
+                                    piece) + 256;
+  return GENCD_OK;
+}
+
+int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
+                     const double *lambdas, int32_t L, int32_t B, float *W, void *ws,
+                     size_t ws_bytes, hipStream_t stream, gencd_stats *stats) {
+  (void)hipGetLastError();
+  auto t0 = std::chrono::steady_clock::now();
+  if (!X || !p || !lambdas || L <= 0 || !W || !stats) return GENCD_ERR_INVALID_ARG;
+  if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
+  if (p->rule != GENCD_SHOTGUN) return GENCD_ERR_UNSUPPORTED;
+  if (p->select_size <= 0 || !(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0)
+    return GENCD_ERR_INVALID_ARG;
+  if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;
+  for (int32_t t = 0; t < L; ++t)
+    if (!(lambdas[t] >= 0.0) || !std::isfinite(lambdas[t])) return GENCD_ERR_INVALID_ARG;
+  std::memset(stats, 0, sizeof(gencd_stats) * size_t(L));
+  size_t need = 0;
+  int st = gencd_path_workspace_bytes(X, p, B, &need);
+  if (st) return st;
+  if (!ws || ws_bytes < need) return GENCD_ERR_WORKSPACE;
+  PathSetup su{};
+  size_t used = 0;
+  st = path_setup(X, y, p, ws, ws_bytes, stream, &su, &used);
+  if (st) return st;
+  char *pb = static_cast<char *>(ws) + used;
+  size_t mis = reinterpret_cast<uintptr_t>(pb) % 256;
+  if (mis) pb += 256 - mis;
+  switch (B) {
+    case 16: st = path_run<16>(X, y, p, lambdas, L, W, pb, su, stream, stats); break;
+    case 32: st = path_run<32>(X, y, p, lambdas, L, W, pb, su, stream, stats); break;
+    default: st = path_run<64>(X, y, p, lambdas, L, W, pb, su, stream, stats); break;
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int all = 1;
+  for (int32_t t = 0; t < L; ++t) {
+    stats[t].seconds = secs;
+    all &= stats[t].converged;
+  }
+  if (st) return st;
+  return all ? GENCD_OK : GENCD_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -337,6 +337,30 @@ int64_t groups_for(int64_t positions, int64_t extra_pieces) {
 
 }  // namespace
 
+struct PathSetup {
+  Ws base;
+  int piece;
+  int32_t total_pieces;
+  int64_t k_live;
+};
+
+// Preprocessing shared with the batched path: the single-problem workspace
+// occupies the front of `ws`; *used is its size.
+int path_setup(const gencd_csc *X, const float *y, const gencd_params *p, void *ws, size_t bytes,
+               hipStream_t s, PathSetup *out, size_t *used) {
+  int st = params_ok(p, false);
+  if (st) return st;
+  Setup su;
+  st = setup(X, y, p->loss, p, ws, bytes, (p->flags & GENCD_VALIDATE_DEVICE) != 0, s, &su);
+  if (st) return st;
+  out->base = su.ws;
+  out->piece = su.piece;
+  out->total_pieces = su.total_pieces;
+  out->k_live = su.k_live;
+  *used = workspace_layout(X->n, X->k, X->nnz, su.piece, nullptr, nullptr) + kAlign;
+  return GENCD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Solve
 // ---------------------------------------------------------------------------

@@ -74,6 +74,10 @@ _SIGS = {
                               C.c_void_p]),
     "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "gencd_color_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gencd_path_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "gencd_solve_path": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                   C.c_void_p]),
     "gencd_color": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                               C.c_void_p]),
 }
@@ -270,3 +274,29 @@ def color(X: Matrix, ws=None):
     _check(lib().gencd_color(X.ref, _ptr(out), C.byref(nc), _ptr(ws), ws.numel(), _stream()),
            "gencd_color")
     return out, nc.value
+
+
+@dataclass
+class PathResult:
+    status: int
+    W: torch.Tensor      # [L, k]
+    stats: list
+
+
+def solve_path(X: Matrix, y, params: Params, lambdas, B=32, ws=None):
+    """Batched regularisation path (B lambda slots per launch sequence)."""
+    import numpy as _np
+    lam = _np.ascontiguousarray(_np.asarray(lambdas, dtype=_np.float64))
+    L = int(lam.size)
+    if ws is None:
+        nb = C.c_size_t()
+        _check(lib().gencd_path_workspace_bytes(X.ref, C.byref(params), int(B), C.byref(nb)),
+               "gencd_path_workspace_bytes")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=X.col_ptr.device)
+    W = torch.empty((L, X.k), dtype=torch.float32, device=X.col_ptr.device)
+    st = (Stats * L)()
+    rc = lib().gencd_solve_path(X.ref, _ptr(y), C.byref(params),
+                                lam.ctypes.data_as(C.c_void_p), L, int(B), _ptr(W), _ptr(ws),
+                                ws.numel(), _stream(), st)
+    _check(rc, "gencd_solve_path", allow=(OK, NOT_CONVERGED))
+    return PathResult(rc, W, [s.as_dict() for s in st])

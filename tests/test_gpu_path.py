@@ -1,0 +1,67 @@
+"""Batched regularisation path on the GPU against independent oracle solves."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1206_6409_amd import gencd as G
+from paper_1206_6409_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def binary_problem():
+    P = synth.c4_binary_path(scale=0.05)
+    Xo = O.Matrix.of(P)
+    lm = O.lambda_max(Xo, P.y, P.loss)
+    return P, Xo, lm
+
+
+@pytest.mark.parametrize("B,L", [(16, 20), (32, 12), (64, 6)])
+def test_path_matches_independent_solves(binary_problem, B, L):
+    print("CASE path", B, L, flush=True)
+    P, Xo, lm = binary_problem
+    lams = synth.lambda_grid(lm, count=L, ratio=0.1)
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-8,
+                           max_epochs=20000)
+    res = G.solve_path(X, y, params, lams, B=B)
+    assert res.status == G.OK
+    W = res.W.cpu().numpy().astype(np.float64)
+    for t, lam in enumerate(lams):
+        st = res.stats[t]
+        assert st["converged"] == 1 and st["kkt_max"] <= 1e-8, (t, st)
+        oc = O.check(Xo, P.y, P.loss, lam, W[t])
+        assert oc.kkt <= 1e-8 * (1 + 1e-6)
+        assert st["objective"] == pytest.approx(oc.objective, rel=1e-12)
+        ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000,
+                      w0=W[t - 1] if t > 0 else None)
+        assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective), t
+
+
+def test_path_single_lambda_equals_solve(binary_problem):
+    P, Xo, lm = binary_problem
+    lam = 0.1 * lm
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    params = G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-8,
+                           max_epochs=20000)
+    single = G.solve(X, y, params)
+    path = G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4,
+                                            tol=1e-8, max_epochs=20000), [lam], B=16)
+    assert path.status == G.OK
+    assert abs(path.stats[0]["objective"] - single.stats["objective"]) <= 1e-7 * single.stats["objective"]
+
+
+def test_path_rejects_bad_args(binary_problem):
+    P, Xo, lm = binary_problem
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    with pytest.raises(G.GencdError):
+        G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.THREAD_GREEDY, select_size=64, block=8),
+                     [0.1 * lm], B=16)
+    with pytest.raises(G.GencdError):
+        G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=64), [0.1 * lm], B=24)
