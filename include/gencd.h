@@ -202,6 +202,57 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
                      const double *lambdas, int32_t L, int32_t B, float *W, void *ws,
                      size_t ws_bytes, hipStream_t stream, gencd_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching server.  Requests are whole solves of Eq. (1); they
+ * are admitted in arrival order while a slot is free and their workspace
+ * (gencd_workspace_bytes) fits in the caller's device arena.  Admitted
+ * requests run concurrently, each on a worker thread with its own stream;
+ * their state stays in the arena until they finish.  A request larger than
+ * the whole arena is rejected with GENCD_ERR_BUDGET.
+ * ------------------------------------------------------------------------ */
+typedef struct gencd_server gencd_server;
+
+typedef struct {
+  gencd_csc X;          /* device matrix, caller owned, valid until polled */
+  const float *y;       /* device labels, idem */
+  gencd_params params;  /* loss, lambda, rule, ... (colour array for COLORING) */
+  float *w;             /* device float32[k] solution (read first with WARM_START) */
+  float *z;             /* device float32[n] fitted values or NULL */
+  int64_t user_tag;     /* returned unchanged in the result */
+} gencd_request;
+
+typedef struct {
+  int64_t ticket, user_tag;
+  int32_t status;       /* gencd_solve's status for this request */
+  gencd_stats stats;
+  double submit_s, start_s, finish_s;  /* seconds since gencd_server_create */
+} gencd_result;
+
+typedef struct {
+  int32_t running, waiting, finished_unpolled;
+  size_t arena_used, arena_bytes;
+} gencd_server_status;
+
+/* arena: device memory owned by the caller for the server's lifetime;
+ * max_slots: concurrent solves (1..256).  The device current at creation is
+ * used by every worker. */
+int gencd_server_create(void *arena, size_t arena_bytes, int32_t max_slots, gencd_server **out);
+/* Non-blocking; *ticket identifies the request in its result. */
+int gencd_server_submit(gencd_server *sv, const gencd_request *req, int64_t *ticket);
+/* Moves up to max finished results to out (host).  wait_for > 0 first
+ * blocks until that many results are available (or all in flight ended). */
+int gencd_server_poll(gencd_server *sv, gencd_result *out, int32_t max, int32_t wait_for,
+                      int32_t *n_out);
+int gencd_server_info(gencd_server *sv, gencd_server_status *out);
+/* Waits for every submitted request, then releases the server. */
+int gencd_server_destroy(gencd_server *sv);
+/* Host-only replay of the admission policy (capacity planning, tests):
+ * request i arrives at arrival[i] (non-decreasing), needs bytes[i] of arena
+ * and holds its slot for service[i] seconds; start[i] receives its start time
+ * or -1 if it can never fit. */
+int gencd_server_plan(size_t arena_bytes, int32_t max_slots, int32_t n, const size_t *bytes,
+                      const double *arrival, const double *service, double *start);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgencd.so")
-SOURCES = ["gencd_kernels.hip", "gencd_solver.hip", "gencd_color.hip", "gencd_path.hip"]
+SOURCES = ["gencd_kernels.hip", "gencd_solver.hip", "gencd_color.hip", "gencd_path.hip",
+           "gencd_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -75,6 +75,13 @@ _SIGS = {
     "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "gencd_color_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gencd_path_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "gencd_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]),
+    "gencd_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_server_poll": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "gencd_server_info": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gencd_server_destroy": (C.c_int, [C.c_void_p]),
+    "gencd_server_plan": (C.c_int, [C.c_size_t, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
     "gencd_solve_path": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                    C.c_void_p]),
@@ -300,3 +307,85 @@ def solve_path(X: Matrix, y, params: Params, lambdas, B=32, ws=None):
                                 ws.numel(), _stream(), st)
     _check(rc, "gencd_solve_path", allow=(OK, NOT_CONVERGED))
     return PathResult(rc, W, [s.as_dict() for s in st])
+
+
+class Request(C.Structure):
+    _fields_ = [("X", Csc), ("y", C.c_void_p), ("params", Params), ("w", C.c_void_p),
+                ("z", C.c_void_p), ("user_tag", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("user_tag", C.c_int64), ("status", C.c_int32),
+                ("stats", Stats), ("submit_s", C.c_double), ("start_s", C.c_double),
+                ("finish_s", C.c_double)]
+
+    def as_dict(self):
+        return {"ticket": self.ticket, "user_tag": self.user_tag, "status": self.status,
+                "stats": self.stats.as_dict(), "submit_s": self.submit_s,
+                "start_s": self.start_s, "finish_s": self.finish_s}
+
+
+class ServerStatus(C.Structure):
+    _fields_ = [("running", C.c_int32), ("waiting", C.c_int32), ("finished_unpolled", C.c_int32),
+                ("arena_used", C.c_size_t), ("arena_bytes", C.c_size_t)]
+
+
+class Server:
+    """Continuous-batching solve server over a torch-owned device arena."""
+
+    def __init__(self, arena_bytes, max_slots=8, device=None):
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=dev)
+        self._h = C.c_void_p()
+        self._keep = {}
+        _check(lib().gencd_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots),
+                                         C.byref(self._h)), "gencd_server_create")
+
+    def submit(self, X: Matrix, y, params: Params, w, z=None, tag=0):
+        """Non-blocking; X, y, w (and z) must stay alive until the result is polled."""
+        req = Request(X._s, y.data_ptr(), params, w.data_ptr(),
+                      z.data_ptr() if z is not None else None, int(tag))
+        t = C.c_int64()
+        _check(lib().gencd_server_submit(self._h, C.byref(req), C.byref(t)), "gencd_server_submit")
+        self._keep[t.value] = (X, y, w, z)
+        return t.value
+
+    def poll(self, max_results=1024, wait_for=0):
+        buf = (Result * max(1, max_results))()
+        n = C.c_int32()
+        _check(lib().gencd_server_poll(self._h, buf, int(max_results), int(wait_for), C.byref(n)),
+               "gencd_server_poll")
+        out = [buf[i].as_dict() for i in range(n.value)]
+        for r in out:
+            self._keep.pop(r["ticket"], None)
+        return out
+
+    def info(self):
+        s = ServerStatus()
+        _check(lib().gencd_server_info(self._h, C.byref(s)), "gencd_server_info")
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def close(self):
+        if self._h:
+            lib().gencd_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_plan(arena_bytes, max_slots, bytes_, arrival, service):
+    """Start times under the server's admission policy (host-only replay)."""
+    import numpy as _np
+    b = _np.ascontiguousarray(bytes_, dtype=_np.uint64)
+    a = _np.ascontiguousarray(arrival, dtype=_np.float64)
+    sv = _np.ascontiguousarray(service, dtype=_np.float64)
+    out = _np.zeros(b.size, dtype=_np.float64)
+    _check(lib().gencd_server_plan(int(arena_bytes), int(max_slots), int(b.size),
+                                   b.ctypes.data_as(C.c_void_p), a.ctypes.data_as(C.c_void_p),
+                                   sv.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)),
+           "gencd_server_plan")
+    return out
