@@ -42,6 +42,9 @@ def cpu_model():
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="shotgun",
+                    choices=["shotgun", "coloring", "path", "serve", "all"],
+                    help="shotgun (default, the headline line) or an extra workload")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -51,6 +54,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-thread-greedy", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time only the plain launch path")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
+    ap.add_argument("--req-scale", type=float, default=0.25,
+                    help="serve: scale of the n and k ranges of the request distribution")
+    ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -68,6 +75,11 @@ def main():
         sys.exit(1)
     G.lib()  # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
+    if args.workload != "shotgun":
+        names = ["coloring", "path", "serve"] if args.workload == "all" else [args.workload]
+        for name in names:
+            print(json.dumps(WORKLOADS[name](args)), flush=True)
+        return
 
     t = time.time()
     P = synth.c2_zipf_logistic(scale=args.scale)
@@ -194,6 +206,246 @@ def main():
         out["objective_rel_diff_vs_oracle"] = abs(last["objective"] - r.objective) / abs(r.objective)
 
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Extra workloads (one JSON line each; not part of the default run)
+# ---------------------------------------------------------------------------
+
+def _timed(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def bench_coloring(args):
+    """Lasso workload (n=2e5, k=1e6, Zipf(1.2), ~30 nnz/row): GPU colouring
+    (bit-exact against the oracle) and Coloring solves to KKT 1e-6."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1206_6409_amd import gencd as G
+    from paper_1206_6409_amd import synth
+
+    t = time.time()
+    P = synth.c3_zipf_lasso(scale=args.scale)
+    log(f"generated {P.name}: nnz={P.nnz} in {time.time() - t:.1f}s")
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device="cuda")
+    G.color(X)  # warm-up
+    t_col, (colors, nc) = _timed(lambda: G.color(X), reps=3)
+    t0 = time.perf_counter()
+    ocol, onc, _ = O.color(P.n, P.k, P.col_ptr, P.row_idx)
+    t_ocol = time.perf_counter() - t0
+    exact = bool(onc == nc and np.array_equal(colors.cpu().numpy(), ocol))
+    sizes = np.bincount(colors.cpu().numpy()[np.diff(P.col_ptr) > 0], minlength=nc)
+    lam = 0.1 * G.lambda_max(X, y, P.loss)
+    params = dict(loss=P.loss, lam=lam, rule=G.COLORING, colors=colors, num_colors=nc, seed=3,
+                  tol=args.tol, max_epochs=100000)
+    G.solve(X, y, G.make_params(**params))
+    t_plain, res = _timed(lambda: G.solve(X, y, G.make_params(**params)), reps=args.steps)
+    t_graph, resg = _timed(lambda: G.solve(X, y, G.make_params(flags=G.USE_GRAPH, **params)),
+                           reps=args.steps)
+    best = min(t_plain, t_graph)
+    st = (resg if t_graph <= t_plain else res).stats
+    Xo = O.Matrix.of(P)
+    t0 = time.perf_counter()
+    r = O.solve(Xo, P.y.astype(np.float64), P.loss, lam, O.COLORING, colors=ocol, seed=3,
+                tol=args.tol, max_epochs=100000)
+    t_or = time.perf_counter() - t0
+    return {
+        "metric": "nnz-updates/s of Coloring solves to FP64 KKT 1e-6; colouring time",
+        "value": st["nnz_updates"] / best, "unit": "nnz-updates/s", "n_gpus": 1,
+        "steps": args.steps, "ms_per_step": best * 1e3, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": P.name + ": Zipf(1.2) ~30 nnz/row, N(0,1), Lasso, lambda=0.1*lambda_max",
+                   "n": P.n, "k": P.k, "nnz": P.nnz},
+        "colouring": {"gpu_ms": t_col * 1e3, "oracle_cpu_ms": t_ocol * 1e3, "colors": int(nc),
+                      "bit_exact": exact, "mean_class_size": float(sizes[sizes > 0].mean()),
+                      "max_class_size": int(sizes.max())},
+        "solves_per_s": 1.0 / best, "plain_path_ms": t_plain * 1e3, "graph_path_ms": t_graph * 1e3,
+        "epochs": st["epochs"], "iters": st["iters"], "objective": st["objective"],
+        "kkt_max": st["kkt_max"],
+        "objective_rel_diff_vs_oracle": abs(st["objective"] - r.objective) / abs(r.objective),
+        "cpu_baseline": {"value": r.nnz_updates / t_or, "unit": "nnz-updates/s", "cores": 1,
+                         "kind": "oracle", "sample": f"one full Coloring solve ({r.epochs} epochs, "
+                                                     f"{t_or:.1f} s) on 1 thread of {cpu_model()}"},
+    }
+
+
+def bench_path(args):
+    """64-lambda regularisation path (binary, n=5e4, k=2e5, density 0.05%),
+    lambda geometric from lambda_max to 1e-3 lambda_max, KKT 1e-6: batched
+    slots vs the plain path (one warm-started gencd_solve per lambda)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1206_6409_amd import gencd as G
+    from paper_1206_6409_amd import synth
+
+    t = time.time()
+    P = synth.c4_binary_path(scale=args.scale)
+    log(f"generated {P.name}: nnz={P.nnz} in {time.time() - t:.1f}s")
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device="cuda")
+    lm = G.lambda_max(X, y, P.loss)
+    lams = synth.lambda_grid(lm, count=args.lambdas, ratio=1e-3)
+    base = dict(loss=P.loss, lam=0.0, rule=G.SHOTGUN, select_size=1024, seed=5, tol=args.tol,
+                max_epochs=200000)
+    batched = {}
+    for B in (16, 32, 64):
+        dt, res = _timed(lambda: G.solve_path(X, y, G.make_params(**base), lams, B=B))
+        assert all(s["converged"] for s in res.stats)
+        batched[B] = (dt, res)
+        log(f"path B={B}: {dt:.2f}s")
+    # plain path: one solve per lambda, warm-started from the previous solution
+    ws = G.workspace(X, G.make_params(**base))
+
+    def plain():
+        w0, objs, epochs = None, [], 0
+        for lam in lams:
+            r = G.solve(X, y, G.make_params(**dict(base, lam=float(lam))), w0=w0, ws=ws)
+            assert r.stats["converged"]
+            w0, epochs = r.w, epochs + r.stats["epochs"]
+            objs.append(r.stats["objective"])
+        return objs, epochs
+
+    t_plain, (objs_plain, ep_plain) = _timed(plain)
+    Bbest = min(batched, key=lambda b: batched[b][0])
+    t_b, res = batched[Bbest]
+    objs = [s["objective"] for s in res.stats]
+    rel = max(abs(a - b) / abs(b) for a, b in zip(objs, objs_plain))
+    nnz_upd = sum(s["nnz_updates"] for s in res.stats)
+    # oracle on the first lambdas (bounded sample), warm-started like the plain path
+    Xo = O.Matrix.of(P)
+    yo = P.y.astype(np.float64)
+    t0 = time.perf_counter()
+    w0, oupd, ocnt = None, 0, 0
+    for lam in lams:
+        r = O.solve(Xo, yo, P.loss, float(lam), O.SHOTGUN, select_size=1024, seed=5, tol=args.tol,
+                    max_epochs=200000, w0=w0)
+        w0, oupd, ocnt = r.w, oupd + r.nnz_updates, ocnt + 1
+        if time.perf_counter() - t0 > 20.0:
+            break
+    t_or = time.perf_counter() - t0
+    return {
+        "metric": "solves/s of a 64-lambda path to FP64 KKT 1e-6, batched vs plain GPU path",
+        "value": len(lams) / t_b, "unit": "solves/s", "n_gpus": 1, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": P.name + ": binary, logistic, 64 lambdas geometric to 1e-3 lambda_max",
+                   "n": P.n, "k": P.k, "nnz": P.nnz, "select_size": 1024},
+        "batched": {str(B): {"seconds": batched[B][0], "solves_per_s": len(lams) / batched[B][0]}
+                    for B in batched},
+        "best_B": Bbest, "plain_path": {"seconds": t_plain, "solves_per_s": len(lams) / t_plain,
+                                        "epochs_total": ep_plain},
+        "speedup_vs_plain": t_plain / t_b,
+        "nnz_updates_per_s": nnz_upd / t_b,
+        "max_objective_rel_diff_batched_vs_plain": rel,
+        "epochs_per_lambda": [s["epochs"] for s in res.stats],
+        "cpu_baseline": {"value": oupd / t_or, "unit": "nnz-updates/s", "cores": 1, "kind": "oracle",
+                         "sample": f"the first {ocnt} lambdas of the path, warm-started "
+                                   f"({t_or:.1f} s) on 1 thread of {cpu_model()}"},
+    }
+
+
+def bench_serve(args):
+    """Serving: a Poisson stream of L1 solves, 50/50 Lasso and logistic,
+    n ~ U{1k..50k}*s, k ~ U{1k..200k}*s (s = --req-scale), density
+    U[0.1%, 2%], lambda/lambda_max log-uniform [1e-3, 0.5]; matrices drawn
+    from a pool of distinct generated problems.  Reports p50/p99 latency and
+    solves/s for the continuous-batching server and for one-at-a-time
+    (plain) service of the same stream."""
+    import numpy as np
+    import torch
+
+    from paper_1206_6409_amd import gencd as G
+    from paper_1206_6409_amd import synth
+
+    sc = args.req_scale
+    pool_n = 24
+    stream = synth.c5_request_stream(count=args.requests, rate=1.0,
+                                     n_range=(int(1000 * sc), int(50000 * sc)),
+                                     k_range=(int(1000 * sc), int(200000 * sc)))
+    t = time.time()
+    pool = []
+    for i in range(pool_n):
+        r = stream[i]
+        P = synth.request_problem(r)
+        X = G.Matrix.of(P)
+        y = torch.as_tensor(P.y, device="cuda")
+        lm = G.lambda_max(X, y, P.loss)
+        pool.append((P, X, y, lm))
+    log(f"generated a pool of {pool_n} request problems in {time.time() - t:.1f}s, "
+        f"mean nnz {np.mean([p[0].nnz for p in pool]):.0f}")
+    reqs = []
+    for r in stream:
+        P, X, y, lm = pool[r.ticket % pool_n]
+        reqs.append((P, X, y, r.lambda_ratio * lm))
+
+    def params(P, lam):
+        return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=512, seed=11, tol=1e-6,
+                             max_epochs=20000, flags=G.USE_GRAPH)
+
+    need = max(G.workspace_bytes(X, params(P, 1.0)) for P, X, y, lm in pool)
+    slots = 8
+    srv = G.Server(arena_bytes=slots * need + (64 << 20), max_slots=slots)
+
+    def run_stream(server, arrivals):
+        outs = [torch.empty(P.k, dtype=torch.float32, device="cuda") for P, X, y, lam in reqs]
+        t0 = time.perf_counter()
+        base = None
+        for i, ((P, X, y, lam), at) in enumerate(zip(reqs, arrivals)):
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            server.submit(X, y, params(P, lam), outs[i], tag=i)
+        res = []
+        while len(res) < len(reqs):
+            res += server.poll(wait_for=1)
+        return res
+
+    # saturated throughput: everything arrives at once
+    res = run_stream(srv, np.zeros(len(reqs)))
+    span = max(r["finish_s"] for r in res) - min(r["submit_s"] for r in res)
+    sat = len(reqs) / span
+    assert all(r["status"] == G.OK for r in res)
+    rate = 0.7 * sat
+    gaps = np.random.default_rng(1050).exponential(1.0 / rate, size=len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    res = run_stream(srv, arrivals)
+    srv.close()
+    lat = np.array([r["finish_s"] - r["submit_s"] for r in res])
+    span = max(r["finish_s"] for r in res) - min(r["submit_s"] for r in res)
+    # plain: one request at a time, same arrivals
+    srv1 = G.Server(arena_bytes=need + (64 << 20), max_slots=1)
+    res1 = run_stream(srv1, arrivals)
+    srv1.close()
+    lat1 = np.array([r["finish_s"] - r["submit_s"] for r in res1])
+    span1 = max(r["finish_s"] for r in res1) - min(r["submit_s"] for r in res1)
+    nnz = sum(r["stats"]["nnz_updates"] for r in res)
+    return {
+        "metric": "serving: solves/s and p50/p99 latency at 0.7x saturated rate",
+        "value": len(reqs) / span, "unit": "solves/s", "n_gpus": 1, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} Poisson requests, 50/50 Lasso/logistic, n,k ranges x{sc}, "
+                               f"density 0.1-2%, lambda/lambda_max logU[1e-3,0.5], pool of {pool_n}",
+                   "slots": slots, "rate_per_s": rate, "mean_nnz": float(np.mean([r[0].nnz for r in reqs]))},
+        "saturated_solves_per_s": sat,
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "nnz_updates_per_s": nnz / span,
+        "plain_one_at_a_time": {"solves_per_s": len(reqs) / span1,
+                                "latency_p50_s": float(np.percentile(lat1, 50)),
+                                "latency_p99_s": float(np.percentile(lat1, 99))},
+        "all_converged": bool(all(r["stats"]["converged"] for r in res)),
+    }
+
+
+WORKLOADS = {"coloring": bench_coloring, "path": bench_path, "serve": bench_serve}
 
 
 if __name__ == "__main__":

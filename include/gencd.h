@@ -202,6 +202,26 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
                      const double *lambdas, int32_t L, int32_t B, float *W, void *ws,
                      size_t ws_bytes, hipStream_t stream, gencd_stats *stats);
 
+/* Schedule autotuner.  Times every candidate schedule (lanes per piece in
+ * {16, 32, 64} x nonzeros per piece in {256, 512, 1024} x captured-epoch
+ * graph on/off) on `epochs` epochs of the real solve from w = 0 and returns
+ * the fastest in *out; copy out->group, out->piece and out->flags into
+ * gencd_params to use it.  Results are cached (JSON lines) in cache_path, or
+ * in $GENCD_TUNE_CACHE when cache_path is NULL, under a key made of the
+ * device, the problem shape and rule, and the histogram of column lengths;
+ * a cached key is answered without timing.  w_scratch: device float32[k];
+ * the workspace must be at least gencd_workspace_bytes for piece = 256. */
+typedef struct {
+  int32_t group, piece;
+  uint32_t flags;            /* GENCD_USE_GRAPH or 0 */
+  double seconds_per_epoch;  /* measured on the tuning run */
+  int32_t from_cache;
+} gencd_schedule;
+
+int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, int32_t epochs,
+                   const char *cache_path, float *w_scratch, void *ws, size_t ws_bytes,
+                   hipStream_t stream, gencd_schedule *out);
+
 /* ------------------------------------------------------------------------
  * Continuous-batching server.  Requests are whole solves of Eq. (1); they
  * are admitted in arrival order while a slot is free and their workspace

@@ -1,0 +1,166 @@
+// Schedule autotuner for gencd_solve.
+//
+// A schedule is (lanes per piece, nonzeros per piece, captured-epoch graph
+// on/off).  The tuner times each candidate on a short run of the real solve
+// (a few epochs from w = 0, no convergence test in between) and keeps the
+// fastest.  Results are cached on disk, one JSON object per line, keyed by a
+// problem signature: device architecture and CU count, n, k, nnz, loss,
+// rule, |J|, B, and the histogram of column lengths in powers of two (which
+// is what the piece and group sizes respond to).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/gencd.h"
+
+namespace gencd {
+
+int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float *w, float *z,
+               void *ws_base, size_t ws_bytes, hipStream_t s, gencd_stats *stats);
+
+__global__ void k_zero_u64(unsigned long long *p, int m) {
+  if (int(threadIdx.x) < m) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_len_hist(const int64_t *col_ptr, int64_t k, unsigned long long *hist) {
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    int64_t m = col_ptr[j + 1] - col_ptr[j];
+    int b = 0;
+    while (b < 31 && (int64_t(1) << b) <= m) ++b;  // b = bit length of m
+    atomicAdd(&hist[b], 1ull);
+  }
+}
+
+static std::mutex g_cache_mu;  // serialises cache-file access within the process
+
+static std::string signature(const gencd_csc *X, const gencd_params *p, const unsigned long long *h) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  std::ostringstream os;
+  os << prop.gcnArchName << "/" << prop.multiProcessorCount << "|n" << X->n << "|k" << X->k
+     << "|nnz" << X->nnz << "|loss" << p->loss << "|rule" << p->rule << "|J" << p->select_size
+     << "|B" << p->block << "|h";
+  for (int b = 0; b < 32; ++b) os << (b ? "," : "") << h[b];
+  return os.str();
+}
+
+static bool cache_lookup(const char *path, const std::string &key, gencd_schedule *out) {
+  if (!path || !*path) return false;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  const std::string pat = "\"key\": \"" + key + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(pat) == std::string::npos) continue;
+    int g = 0, pc = 0;
+    unsigned fl = 0;
+    double sec = 0;
+    const char *q = std::strstr(line.c_str(), "\"group\":");
+    const char *r = std::strstr(line.c_str(), "\"piece\":");
+    const char *t = std::strstr(line.c_str(), "\"flags\":");
+    const char *u = std::strstr(line.c_str(), "\"seconds_per_epoch\":");
+    if (q && r && t && u && std::sscanf(q, "\"group\": %d", &g) == 1 &&
+        std::sscanf(r, "\"piece\": %d", &pc) == 1 && std::sscanf(t, "\"flags\": %u", &fl) == 1 &&
+        std::sscanf(u, "\"seconds_per_epoch\": %lf", &sec) == 1) {
+      out->group = g;
+      out->piece = pc;
+      out->flags = fl;
+      out->seconds_per_epoch = sec;
+      out->from_cache = 1;
+      found = true;  // last entry for the key wins
+    }
+  }
+  return found;
+}
+
+static void cache_store(const char *path, const std::string &key, const gencd_schedule &s) {
+  if (!path || !*path) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  std::ofstream f(path, std::ios::app);
+  f << "{\"key\": \"" << key << "\", \"group\": " << s.group << ", \"piece\": " << s.piece
+    << ", \"flags\": " << s.flags << ", \"seconds_per_epoch\": " << s.seconds_per_epoch << "}\n";
+}
+
+}  // namespace gencd
+
+using namespace gencd;
+
+extern "C" {
+
+int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, int32_t epochs,
+                   const char *cache_path, float *w_scratch, void *ws, size_t ws_bytes,
+                   hipStream_t stream, gencd_schedule *out) {
+  (void)hipGetLastError();
+  if (!X || !y || !p || !out || !w_scratch || epochs <= 0 || X->k <= 0 || !X->col_ptr)
+    return GENCD_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  if (!cache_path) cache_path = std::getenv("GENCD_TUNE_CACHE");
+  // signature: column-length histogram (device pass, 32 counters in the workspace)
+  if (!ws || ws_bytes < 256) return GENCD_ERR_WORKSPACE;
+  unsigned long long *hd = static_cast<unsigned long long *>(ws);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, hd, 32);
+  const unsigned grid = unsigned(std::min<int64_t>((X->k + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_len_hist, dim3(grid), dim3(256), 0, stream, X->col_ptr, X->k, hd);
+  unsigned long long h[32];
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(h, hd, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return GENCD_ERR_HIP;
+  const std::string key = signature(X, p, h);
+  if (cache_lookup(cache_path, key, out)) return GENCD_OK;
+
+  const int groups[] = {16, 32, 64};
+  const int pieces[] = {256, 512, 1024};
+  const unsigned gflags[] = {0u, GENCD_USE_GRAPH};
+  double best = 1e300;
+  for (int g : groups)
+    for (int pc : pieces)
+      for (unsigned gf : gflags) {
+        if (pc < g) continue;
+        gencd_params q = *p;
+        q.group = g;
+        q.piece = pc;
+        q.flags = (p->flags & ~(GENCD_WARM_START | GENCD_USE_GRAPH | GENCD_PROFILE)) | gf;
+        q.kkt_tol = 0.0;  // run exactly `epochs` epochs
+        q.gap_tol = 0.0;
+        q.max_epochs = epochs;
+        q.check_every = epochs;
+        size_t need = 0;
+        if (gencd_workspace_bytes(X, &q, &need) != GENCD_OK || need > ws_bytes) continue;
+        gencd_stats st{};
+        // first run warms caches and (for graphs) pays the capture once
+        int rc = solve_impl(X, y, &q, w_scratch, nullptr, ws, ws_bytes, stream, &st);
+        if (rc < 0) continue;
+        auto t0 = std::chrono::steady_clock::now();
+        rc = solve_impl(X, y, &q, w_scratch, nullptr, ws, ws_bytes, stream, &st);
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rc < 0 || st.epochs <= 0) continue;
+        const double per = sec / double(st.epochs);
+        if (per < best) {
+          best = per;
+          out->group = g;
+          out->piece = pc;
+          out->flags = gf;
+          out->seconds_per_epoch = per;
+        }
+      }
+  if (best == 1e300) return GENCD_ERR_WORKSPACE;
+  out->from_cache = 0;
+  cache_store(cache_path, key, *out);
+  return GENCD_OK;
+}
+
+}  // extern "C"

@@ -75,6 +75,8 @@ _SIGS = {
     "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "gencd_color_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gencd_path_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "gencd_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_char_p,
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "gencd_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]),
     "gencd_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gencd_server_poll": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
@@ -389,3 +391,31 @@ def server_plan(arena_bytes, max_slots, bytes_, arrival, service):
                                    sv.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)),
            "gencd_server_plan")
     return out
+
+
+class Schedule(C.Structure):
+    _fields_ = [("group", C.c_int32), ("piece", C.c_int32), ("flags", C.c_uint32),
+                ("seconds_per_epoch", C.c_double), ("from_cache", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def autotune(X: Matrix, y, params: Params, epochs=2, cache_path=None):
+    """Fastest (group, piece, graph) schedule for this problem; apply with apply_schedule."""
+    p256 = Params.from_buffer_copy(params)
+    p256.piece, p256.group = 256, 16
+    ws = workspace(X, p256)
+    w = torch.empty(X.k, dtype=torch.float32, device=X.col_ptr.device)
+    out = Schedule()
+    _check(lib().gencd_autotune(X.ref, _ptr(y), C.byref(params), int(epochs),
+                                cache_path.encode() if cache_path else None, _ptr(w), _ptr(ws),
+                                ws.numel(), _stream(), C.byref(out)), "gencd_autotune")
+    return out.as_dict()
+
+
+def apply_schedule(params: Params, sched: dict):
+    params.group = int(sched["group"])
+    params.piece = int(sched["piece"])
+    params.flags = (params.flags & ~USE_GRAPH) | int(sched["flags"])
+    return params
