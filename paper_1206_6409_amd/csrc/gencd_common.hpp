@@ -166,22 +166,26 @@ struct Ws {
   // problem-static
   float *c;              // [k] curvature bound
   int32_t *live;         // [k] non-empty columns, ascending
-  int32_t *all_poff;     // [k+1] piece offsets of every column (natural order)
-  int4 *desc_all;        // [max_pieces] piece descriptors, natural order
+  int32_t *all_soff;     // [k+1] short-column index of every column (natural order)
+  int32_t *all_loff;     // [k+1] long-piece offsets of every column
+  int4 *desc_all_s;      // [k] short-column descriptors, natural order
+  int4 *desc_all_l;      // [max_lpieces] long-piece descriptors, natural order
   int32_t *tmp_cnt;      // [k+1] scratch counts
+  int32_t *tmp_cnt2;     // [k+1] scratch counts
   int32_t *scan_part;    // [scan partials]
   int32_t *cls_off;      // [k+1] colour class offsets (COLORING)
   int32_t *cls_mem;      // [k] live members by colour
   // per-epoch order
   int32_t *col_of_pos;   // [k]
-  int32_t *poff;         // [k+1] piece offsets of the positions
-  int4 *desc;            // [max_pieces] piece descriptors of the epoch order
+  int32_t *soff, *loff;  // [k+1] short-column / long-piece offsets of the positions
+  int4 *desc_s;          // [k] short descriptors of the epoch order
+  int4 *desc_l;          // [max_lpieces] long descriptors of the epoch order
   int32_t *win_off;      // [k+1] colour windows (COLORING)
-  int32_t *wbounds;      // [k+2] first piece of every window
+  int32_t *wbs, *wbl;    // [k+2] first short column / long piece of every window
   // per-window
   float *delta;          // [k]
   float *phi;            // [k]
-  float *gacc;           // [max_pieces] partial sums of split columns
+  float *gacc;           // [max_lpieces] partial sums of split columns
   float *wsnap;          // [k] w of split columns at Propose time
   int32_t *acc;          // [k]
   // state
@@ -192,11 +196,12 @@ struct Ws {
   double *g64;           // [k]
   double *red;           // [16] reductions, counters, flags; [12] epoch counter
   size_t scan_part_len;
-  int64_t max_pieces;
+  int64_t max_lpieces;
 };
 
-int64_t max_pieces_for(int64_t k, int64_t nnz, int piece);
-size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, void *base, Ws *ws);
+int64_t max_lpieces_for(int64_t k, int64_t nnz, int piece, int short_max);
+size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, void *base,
+                        Ws *ws);
 size_t scan_partials_for(int64_t len);
 
 // Exclusive scan of int32 counts: out[0..len] (out[len] = total).

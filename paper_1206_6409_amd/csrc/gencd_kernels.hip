@@ -1,19 +1,23 @@
 // HIP kernels of the GenCD hot path for gfx950 (wave64, 256-thread groups).
 //
-// Work decomposition.  Column nonzero counts are heavy-tailed, so a column
-// is cut into "pieces" of at most `piece` nonzeros and a group of G lanes
-// (G in {8, 16, 32, 64}) processes one piece: the G lanes read consecutive
-// CSC entries (coalesced row_idx / val loads), gather the residual, and
-// reduce within the group.  A column with one piece is proposed and, for
-// accept-all rules, updated by its group without any synchronisation; the
-// partial sums of a multi-piece column are combined with a float atomic and
-// the last piece to arrive (ticket counter) finalises the proposal.
+// Work decomposition.  Column nonzero counts are heavy-tailed (most columns
+// hold a handful of nonzeros, a few hold nearly n), so columns come in two
+// classes, each with its own list of 16-byte piece descriptors:
+//   * short columns (at most GS * kUnroll nonzeros) are one piece each and a
+//     group of GS lanes (GS in {4, 8, 16, 32}) proposes / updates a column, so
+//     one wave serves 64 / GS columns at once;
+//   * long columns are cut into pieces of at most `piece` nonzeros, one
+//     wave64 per piece; the partial sums of a split column are published and
+//     combined, in piece order, by the next launch.
+// Inside a group the lanes read consecutive CSC entries (coalesced row_idx /
+// val loads), keep kUnroll of them in flight, gather the state and reduce.
 //
 // Selection (section 2.1) is precomputed per epoch: position p of the epoch
-// order holds column col_of_pos[p]; poff is the exclusive scan of piece
-// counts over positions and piece_pos maps a piece back to its position, so
-// an iteration's selected set J is the position range of its window and its
-// work is the piece range poff[P0] .. poff[P1].
+// order holds column col_of_pos[p]; soff / loff are the exclusive scans of
+// short columns / long pieces over positions, so an iteration's selected set
+// J (a position range) maps to one short-descriptor range and one
+// long-descriptor range, whose bounds sit in device memory (a captured
+// epoch replays without host involvement).
 #include "gencd_common.hpp"
 #include "gencd_kernels.hpp"
 
@@ -209,7 +213,7 @@ int launch_validate(const gencd_csc *X, const float *y, int loss, bool matrix,
 // ---------------------------------------------------------------------------
 // Piece descriptors.  A descriptor is one 16-byte load:
 //   x = first CSC entry of the piece, y = column, z = position in the order
-//   (-1 for the static natural-order decomposition), w = length | single<<31
+//   (-1 for the static natural-order lists), w = length | single<<31
 // where `single` marks a column that fits in one piece.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int4 make_desc(int64_t beg, int32_t j, int32_t p, int32_t len,
@@ -220,46 +224,76 @@ __device__ __forceinline__ int64_t desc_beg(const int4 &d) { return int64_t(uint
 __device__ __forceinline__ int32_t desc_len(const int4 &d) { return int32_t(uint32_t(d.w) & 0x7FFFFFFFu); }
 __device__ __forceinline__ bool desc_single(const int4 &d) { return (uint32_t(d.w) >> 31) != 0; }
 
+// Role of a wave in a two-class launch: the first `nl` waves walk the long
+// pieces (one piece per wave), the others walk the short columns (64/GS per
+// wave).  At least one wave is kept for each role.
+struct Roles {
+  int64_t wave, nwaves, nl;
+  int wl;
+};
+__device__ __forceinline__ Roles roles(int32_t nl_req) {
+  Roles r;
+  r.wave = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave;
+  r.nwaves = int64_t(gridDim.x) * (kBlock / kWave);
+  int64_t nl = nl_req < 1 ? 1 : nl_req;
+  if (nl > r.nwaves - 1) nl = r.nwaves - 1;
+  r.nl = nl;
+  r.wl = threadIdx.x & (kWave - 1);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Preprocessing: piece decomposition, live columns, curvature (row a1)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_col_counts(const int64_t *col_ptr, int64_t k,
-                                                        int piece, int32_t *npieces,
+                                                        int piece, int short_max,
+                                                        int32_t *scnt, int32_t *lcnt,
                                                         int32_t *live_flag) {
   for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
        j += int64_t(gridDim.x) * kBlock) {
-    int64_t m = col_ptr[j + 1] - col_ptr[j];
-    npieces[j] = int32_t((m + piece - 1) / piece);
+    const int64_t m = col_ptr[j + 1] - col_ptr[j];
+    scnt[j] = (m > 0 && m <= short_max) ? 1 : 0;
+    lcnt[j] = m > short_max ? int32_t((m + piece - 1) / piece) : 0;
     live_flag[j] = m > 0 ? 1 : 0;
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_col_scatter(const int64_t *col_ptr, int64_t k,
-                                                         int piece, const int32_t *all_poff,
+                                                         int piece, const int32_t *all_soff,
+                                                         const int32_t *all_loff,
                                                          const int32_t *live_pos,
-                                                         int4 *desc_all, int32_t *live) {
+                                                         int4 *desc_all_s, int4 *desc_all_l,
+                                                         int32_t *live) {
   for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
        j += int64_t(gridDim.x) * kBlock) {
-    const int32_t a = all_poff[j], b = all_poff[j + 1];
     const int64_t cb = col_ptr[j], ce = col_ptr[j + 1];
+    if (all_soff[j + 1] > all_soff[j])
+      desc_all_s[all_soff[j]] = make_desc(cb, int32_t(j), -1, int32_t(ce - cb), true);
+    const int32_t a = all_loff[j], b = all_loff[j + 1];
     for (int32_t q = a; q < b; ++q) {
       const int64_t beg = cb + int64_t(q - a) * piece;
       const int64_t len = (ce - beg) < piece ? (ce - beg) : piece;
-      desc_all[q] = make_desc(beg, int32_t(j), -1, int32_t(len), b - a == 1);
+      desc_all_l[q] = make_desc(beg, int32_t(j), -1, int32_t(len), b - a == 1);
     }
-    if (b > a) live[live_pos[j]] = int32_t(j);
+    if (ce > cb) live[live_pos[j]] = int32_t(j);
   }
 }
 
-// Sum of squares per column in FP64 over pieces (G lanes per piece).
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_colsq(const float *val, const int4 *desc, int32_t npieces,
+// Sum of squares per column in FP64 (both piece classes).
+template <int GS>
+__global__ __launch_bounds__(kBlock) void k_colsq(const float *val, const int4 *ds, int32_t ns,
+                                                   const int4 *dl, int32_t nlp, int32_t nl_req,
                                                    double *acc) {
-  const int lane = threadIdx.x & (G - 1);
-  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
-  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
-  for (int64_t q = gid; q < npieces; q += ng) {
-    const int4 d = desc[q];
+  const Roles r = roles(nl_req);
+  const bool lng = r.wave < r.nl;
+  const int G = lng ? kWave : GS;
+  const int lane = lng ? r.wl : (r.wl & (GS - 1));
+  const int64_t first = lng ? r.wave : (r.wave - r.nl) * (kWave / GS) + r.wl / GS;
+  const int64_t step = lng ? r.nl : (r.nwaves - r.nl) * (kWave / GS);
+  const int64_t cnt = lng ? nlp : ns;
+  const int4 *dd = lng ? dl : ds;
+  for (int64_t q = first; q < cnt; q += step) {
+    const int4 d = dd[q];
     const int64_t beg = desc_beg(d);
     const int32_t len = desc_len(d);
     double s = 0.0;
@@ -273,8 +307,13 @@ __global__ __launch_bounds__(kBlock) void k_colsq(const float *val, const int4 *
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) s += double(v[u]) * double(v[u]);
     }
-    s = group_sum<G>(s);
-    if (lane == 0) atomicAdd(&acc[d.y], s);
+    s = lng ? group_sum<kWave>(s) : group_sum<GS>(s);
+    if (lane == 0) {
+      if (desc_single(d))
+        acc[d.y] = s;
+      else
+        atomicAdd(&acc[d.y], s);
+    }
   }
 }
 
@@ -285,34 +324,50 @@ __global__ __launch_bounds__(kBlock) void k_curvature(int64_t k, const double *s
     c[j] = float(beta * ss[j] * inv_n);
 }
 
-static unsigned groups_grid(int64_t groups, int G, unsigned cap = 8192) {
-  int64_t threads = groups * G;
-  int64_t b = (threads + kBlock - 1) / kBlock;
+static unsigned waves_grid(int64_t waves, unsigned cap = 8192) {
+  int64_t b = (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return unsigned(b);
 }
 
-int launch_preprocess(const gencd_csc *X, int loss, int piece, const Ws &w, hipStream_t s) {
+int launch_preprocess(const gencd_csc *X, int loss, int piece, int short_max, const Ws &w,
+                      hipStream_t s) {
+  (void)loss;
   const int64_t k = X->k;
-  // npieces -> tmp_cnt, live flags -> col_of_pos (scratch here)
+  // counts: short -> tmp_cnt, long pieces -> tmp_cnt2, live flags -> col_of_pos (scratch)
   hipLaunchKernelGGL(k_col_counts, dim3(grid_for(k)), dim3(kBlock), 0, s, X->col_ptr, k, piece,
-                     w.tmp_cnt, w.col_of_pos);
-  int st = scan_exclusive(w.tmp_cnt, w.all_poff, k, w.scan_part, s);
+                     short_max, w.tmp_cnt, w.tmp_cnt2, w.col_of_pos);
+  int st = scan_exclusive(w.tmp_cnt, w.all_soff, k, w.scan_part, s);
   if (st) return st;
-  st = scan_exclusive(w.col_of_pos, w.poff, k, w.scan_part, s);
+  st = scan_exclusive(w.tmp_cnt2, w.all_loff, k, w.scan_part, s);
+  if (st) return st;
+  st = scan_exclusive(w.col_of_pos, w.soff, k, w.scan_part, s);  // live positions
   if (st) return st;
   hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(k)), dim3(kBlock), 0, s, X->col_ptr, k, piece,
-                     w.all_poff, w.poff, w.desc_all, w.live);
+                     w.all_soff, w.all_loff, w.soff, w.desc_all_s, w.desc_all_l, w.live);
   return fill_f64(w.g64, k, 0.0, s);
 }
 
-int launch_curvature(const gencd_csc *X, int loss, int piece, int32_t total_pieces, const Ws &w,
-                     hipStream_t s) {
-  (void)piece;
-  if (total_pieces > 0)
-    hipLaunchKernelGGL(k_colsq<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
-                       X->val, w.desc_all, total_pieces, w.g64);
+// grid for a two-class pass over ns short columns and nlp long pieces
+static void two_class_grid(int64_t ns, int64_t nlp, int gs, unsigned *blocks, int32_t *nl) {
+  int64_t lw = nlp < 4096 ? nlp : 4096;
+  int64_t sw = (ns + (kWave / gs) - 1) / (kWave / gs);
+  if (sw > 28672) sw = 28672;
+  if (lw < 1) lw = 1;
+  if (sw < 1) sw = 1;
+  *nl = int32_t(lw);
+  *blocks = waves_grid(lw + sw);
+}
+
+int launch_curvature(const gencd_csc *X, int loss, int32_t n_short, int32_t n_lpieces,
+                     const Ws &w, hipStream_t s) {
+  unsigned blocks;
+  int32_t nl;
+  two_class_grid(n_short, n_lpieces, 8, &blocks, &nl);
+  if (n_short + n_lpieces > 0)
+    hipLaunchKernelGGL(k_colsq<8>, dim3(blocks), dim3(kBlock), 0, s, X->val, w.desc_all_s,
+                       n_short, w.desc_all_l, n_lpieces, nl, w.g64);
   double beta = loss == GENCD_SQUARED ? 1.0 : 0.25;
   hipLaunchKernelGGL(k_curvature, dim3(grid_for(X->k)), dim3(kBlock), 0, s, X->k, w.g64, beta,
                      1.0 / double(X->n), w.c);
@@ -335,19 +390,28 @@ int launch_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hi
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
+// Class counts of the columns at the positions of an order.
+__device__ __forceinline__ void pos_counts(int32_t j, const int32_t *all_soff,
+                                           const int32_t *all_loff, int32_t &sc, int32_t &lc) {
+  sc = all_soff[j + 1] - all_soff[j];
+  lc = all_loff[j + 1] - all_loff[j];
+}
+
 // natural != 0: live columns in index order (cyclic rule).  The epoch
 // number is read from device memory so that a captured epoch replays.
 __global__ __launch_bounds__(kBlock) void k_epoch_order(const int32_t *live, int64_t k_live,
                                                          uint64_t seed, const int64_t *epoch,
-                                                         int natural, const int32_t *all_poff,
-                                                         int32_t *col_of_pos, int32_t *np) {
+                                                         int natural, const int32_t *all_soff,
+                                                         const int32_t *all_loff,
+                                                         int32_t *col_of_pos, int32_t *sc,
+                                                         int32_t *lc) {
   const PermKey pk = make_perm_key(k_live, seed, *epoch);
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < k_live;
        p += int64_t(gridDim.x) * kBlock) {
     int64_t src = natural ? p : int64_t(perm_apply(pk, uint64_t(p)));
     int32_t j = live[src];
     col_of_pos[p] = j;
-    np[p] = all_poff[j + 1] - all_poff[j];
+    pos_counts(j, all_soff, all_loff, sc[p], lc[p]);
   }
 }
 
@@ -355,41 +419,52 @@ __global__ void k_inc_epoch(int64_t *epoch) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *epoch += 1;
 }
 
-// np for an explicit column list (step API and colour windows)
-__global__ __launch_bounds__(kBlock) void k_list_np(const int32_t *cols, int64_t m,
-                                                     const int32_t *all_poff, int32_t *np) {
+// class counts for an explicit column list (step API and colour windows)
+__global__ __launch_bounds__(kBlock) void k_list_counts(const int32_t *cols, int64_t m,
+                                                         const int32_t *all_soff,
+                                                         const int32_t *all_loff, int32_t *sc,
+                                                         int32_t *lc) {
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < m;
-       p += int64_t(gridDim.x) * kBlock) {
-    int32_t j = cols[p];
-    np[p] = all_poff[j + 1] - all_poff[j];
-  }
+       p += int64_t(gridDim.x) * kBlock)
+    pos_counts(cols[p], all_soff, all_loff, sc[p], lc[p]);
 }
 
-// Descriptors of the epoch order: the pieces of position p are the static
-// pieces of its column, re-tagged with p (8 lanes per position).
+// Descriptors of the order: each position's static descriptors, re-tagged
+// with the position (8 lanes per position for long columns).
 __global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos, int64_t m,
-                                                        const int32_t *poff,
-                                                        const int32_t *all_poff,
-                                                        const int4 *desc_all, int4 *desc) {
+                                                        const int32_t *soff, const int32_t *loff,
+                                                        const int32_t *all_soff,
+                                                        const int32_t *all_loff,
+                                                        const int4 *desc_all_s,
+                                                        const int4 *desc_all_l, int4 *desc_s,
+                                                        int4 *desc_l) {
   constexpr int L = 8;
   const int lane = threadIdx.x & (L - 1);
   for (int64_t p = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / L; p < m;
        p += int64_t(gridDim.x) * kBlock / L) {
     const int32_t j = col_of_pos[p];
-    const int32_t a = poff[p], b = poff[p + 1], src = all_poff[j];
+    if (soff[p + 1] > soff[p]) {
+      if (lane == 0) {
+        int4 d = desc_all_s[all_soff[j]];
+        d.z = int32_t(p);
+        desc_s[soff[p]] = d;
+      }
+      continue;
+    }
+    const int32_t a = loff[p], b = loff[p + 1], src = all_loff[j];
     for (int32_t q0 = a; q0 < b; q0 += L * kUnroll) {
       int4 d[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int32_t q = q0 + u * L + lane;
-        if (q < b) d[u] = desc_all[src + (q - a)];
+        if (q < b) d[u] = desc_all_l[src + (q - a)];
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int32_t q = q0 + u * L + lane;
         if (q < b) {
           d[u].z = int32_t(p);
-          desc[q] = d[u];
+          desc_l[q] = d[u];
         }
       }
     }
@@ -422,27 +497,32 @@ __global__ __launch_bounds__(kBlock) void k_color_fill(const int32_t *cls_off,
   }
 }
 
-// Piece range of every window of the epoch: bounds[t] = poff[start of window t].
-__global__ __launch_bounds__(kBlock) void k_window_bounds(const int32_t *poff,
+// Descriptor ranges of every window: wbs[t] / wbl[t] = first short column /
+// long piece of window t.
+__global__ __launch_bounds__(kBlock) void k_window_bounds(const int32_t *soff, const int32_t *loff,
                                                            const int32_t *win_off, int64_t S,
-                                                           int64_t m, int64_t T,
-                                                           int32_t *bounds) {
+                                                           int64_t m, int64_t T, int32_t *wbs,
+                                                           int32_t *wbl) {
   for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t <= T;
        t += int64_t(gridDim.x) * kBlock) {
     int64_t pos = win_off ? int64_t(win_off[t]) : (t * S < m ? t * S : m);
-    bounds[t] = poff[pos];
+    wbs[t] = soff[pos];
+    wbl[t] = loff[pos];
   }
 }
 
 static int order_tail(const Ws &w, int64_t m, const int32_t *win_off, int64_t S, int64_t T,
                       hipStream_t s) {
-  int st = scan_exclusive(w.tmp_cnt, w.poff, m, w.scan_part, s);
+  int st = scan_exclusive(w.tmp_cnt, w.soff, m, w.scan_part, s);
+  if (st) return st;
+  st = scan_exclusive(w.tmp_cnt2, w.loff, m, w.scan_part, s);
   if (st) return st;
   if (m > 0)
     hipLaunchKernelGGL(k_order_desc, dim3(grid_for(m * 8)), dim3(kBlock), 0, s, w.col_of_pos, m,
-                       w.poff, w.all_poff, w.desc_all, w.desc);
-  hipLaunchKernelGGL(k_window_bounds, dim3(grid_for(T + 1)), dim3(kBlock), 0, s, w.poff, win_off,
-                     S, m, T, w.wbounds);
+                       w.soff, w.loff, w.all_soff, w.all_loff, w.desc_all_s, w.desc_all_l,
+                       w.desc_s, w.desc_l);
+  hipLaunchKernelGGL(k_window_bounds, dim3(grid_for(T + 1)), dim3(kBlock), 0, s, w.soff, w.loff,
+                     win_off, S, m, T, w.wbs, w.wbl);
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
@@ -457,13 +537,13 @@ int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed,
     hipLaunchKernelGGL(k_color_fill, dim3(unsigned(num_colors < 8192 ? num_colors : 8192)),
                        dim3(kBlock), 0, s, w.cls_off, w.cls_mem, num_colors, seed, epoch,
                        w.win_off, w.col_of_pos);
-    hipLaunchKernelGGL(k_list_np, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.col_of_pos,
-                       k_live, w.all_poff, w.tmp_cnt);
+    hipLaunchKernelGGL(k_list_counts, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.col_of_pos,
+                       k_live, w.all_soff, w.all_loff, w.tmp_cnt, w.tmp_cnt2);
     return order_tail(w, k_live, w.win_off, 0, num_colors, s);
   }
   hipLaunchKernelGGL(k_epoch_order, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.live, k_live,
-                     seed, epoch, rule == GENCD_CYCLIC ? 1 : 0, w.all_poff, w.col_of_pos,
-                     w.tmp_cnt);
+                     seed, epoch, rule == GENCD_CYCLIC ? 1 : 0, w.all_soff, w.all_loff,
+                     w.col_of_pos, w.tmp_cnt, w.tmp_cnt2);
   return order_tail(w, k_live, nullptr, S, T, s);
 }
 
@@ -475,8 +555,8 @@ int launch_inc_epoch(int64_t *epoch, hipStream_t s) {
 int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s) {
   int st = copy_i32(w.col_of_pos, J, nJ, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_list_np, dim3(grid_for(nJ)), dim3(kBlock), 0, s, w.col_of_pos, nJ,
-                     w.all_poff, w.tmp_cnt);
+  hipLaunchKernelGGL(k_list_counts, dim3(grid_for(nJ)), dim3(kBlock), 0, s, w.col_of_pos, nJ,
+                     w.all_soff, w.all_loff, w.tmp_cnt, w.tmp_cnt2);
   return order_tail(w, nJ, nullptr, nJ, 1, s);
 }
 
@@ -497,21 +577,75 @@ __device__ __forceinline__ void window_of(const IterArgs &a, int32_t &P0, int32_
 }
 
 // Sum of the partial gradients of a split column, in piece order (the same
-// order, hence the same float result, in every group that computes it).
-template <int G>
+// order, hence the same float result, in every wave that computes it).
 __device__ __forceinline__ float split_sum(const float *part, int32_t pf, int32_t np, int lane) {
   float t = 0.0f;
-  for (int32_t u0 = 0; u0 < np; u0 += G * kUnroll) {
+  for (int32_t u0 = 0; u0 < np; u0 += kWave * kUnroll) {
     float v[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int32_t idx = u0 + u * G + lane;
+      const int32_t idx = u0 + u * kWave + lane;
       v[u] = idx < np ? part[pf + idx] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) t += v[u];
   }
-  return group_sum<G>(t);
+  return group_sum<kWave>(t);
+}
+
+// Propose of one piece by a group of G lanes.
+template <int G, int MODE>
+__device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc, int64_t q,
+                                              int lane, int32_t P0) {
+  const int64_t beg = desc_beg(dsc);
+  const int32_t len = desc_len(dsc);
+  const int32_t j = dsc.y, p = dsc.z;
+  const bool single = desc_single(dsc);
+  float wj = 0.0f, cj = 0.0f;
+  if (single && lane == 0) {  // issued early, consumed after the reduction
+    wj = a.w[j];
+    cj = a.c[j];
+  }
+  float s = 0.0f;
+  for (int32_t base = 0; base < len; base += G * kUnroll) {
+    int32_t ri[kUnroll];
+    float vv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t e = base + u * G + lane;
+      ri[u] = e < len ? a.row_idx[beg + e] : -1;
+      vv[u] = e < len ? a.val[beg + e] : 0.0f;
+    }
+    float zh[kUnroll], zl[kUnroll], yy[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t i = ri[u] >= 0 ? ri[u] : 0;
+      zh[u] = a.z_hi[i];
+      zl[u] = a.z_lo[i];
+      yy[u] = a.y[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (ri[u] >= 0) s += vv[u] * dloss_f32(a.loss, yy[u], zh[u] + zl[u]);
+  }
+  s = group_sum<G>(s);
+  if (lane != 0) return;
+  const int32_t slot = p - P0;
+  if (!single) {
+    a.gacc[q] = s;
+    if (MODE != 2) a.wsnap[slot] = a.w[j];  // stable copy for Update
+    return;
+  }
+  const float g = s / a.n_f;
+  float d, ph;
+  propose_f32(g, cj, wj, a.lam, d, ph);
+  a.delta[slot] = d;
+  a.phi[slot] = ph;
+  if (a.gout) a.gout[slot] = g;
+  if (MODE != 2 && d != 0.0f) {
+    a.w[j] = wj + d;
+    atomicAdd(a.counters + 3, (unsigned long long)len);
+  }
 }
 
 // Propose (Algorithm 2 / 4).  A column that fits in one piece is finalised
@@ -522,65 +656,20 @@ __device__ __forceinline__ float split_sum(const float *part, int32_t pf, int32_
 // MODE 0: accept all, atomic scatter (Shotgun, stochastic, cyclic)
 // MODE 1: accept all, plain scatter (Coloring: rows of a class are disjoint)
 // MODE 2: deferred acceptance (Thread-Greedy, Greedy)
-template <int G, int MODE>
+template <int GS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
-  const int lane = threadIdx.x & (G - 1);
-  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
-  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
-  const int32_t q0 = a.wbounds[a.t], q1 = a.wbounds[a.t + 1];
+  const Roles r = roles(a.nl);
   int32_t P0, P1;
   window_of(a, P0, P1);
-  for (int64_t q = q0 + gid; q < q1; q += ng) {
-    const int4 dsc = a.desc[q];
-    const int64_t beg = desc_beg(dsc);
-    const int32_t len = desc_len(dsc);
-    const int32_t j = dsc.y, p = dsc.z;
-    const bool single = desc_single(dsc);
-    float wj = 0.0f, cj = 0.0f;
-    if (single && lane == 0) {  // issued early, consumed after the reduction
-      wj = a.w[j];
-      cj = a.c[j];
-    }
-    float s = 0.0f;
-    for (int32_t base = 0; base < len; base += G * kUnroll) {
-      int32_t ri[kUnroll];
-      float vv[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t e = base + u * G + lane;
-        ri[u] = e < len ? a.row_idx[beg + e] : -1;
-        vv[u] = e < len ? a.val[beg + e] : 0.0f;
-      }
-      float zh[kUnroll], zl[kUnroll], yy[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t i = ri[u] >= 0 ? ri[u] : 0;
-        zh[u] = a.z_hi[i];
-        zl[u] = a.z_lo[i];
-        yy[u] = a.y[i];
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (ri[u] >= 0) s += vv[u] * dloss_f32(a.loss, yy[u], zh[u] + zl[u]);
-    }
-    s = group_sum<G>(s);
-    if (lane != 0) continue;
-    const int32_t slot = p - P0;
-    if (!single) {
-      a.gacc[q] = s;
-      if (MODE != 2) a.wsnap[slot] = a.w[j];  // stable copy for Update
-      continue;
-    }
-    const float g = s / a.n_f;
-    float d, ph;
-    propose_f32(g, cj, wj, a.lam, d, ph);
-    a.delta[slot] = d;
-    a.phi[slot] = ph;
-    if (a.gout) a.gout[slot] = g;
-    if (MODE != 2 && d != 0.0f) {
-      a.w[j] = wj + d;
-      atomicAdd(a.counters + 3, (unsigned long long)len);
-    }
+  if (r.wave < r.nl) {
+    const int32_t q1 = a.wbl[a.t + 1];
+    for (int64_t q = a.wbl[a.t] + r.wave; q < q1; q += r.nl)
+      propose_piece<kWave, MODE>(a, a.desc_l[q], q, r.wl, P0);
+  } else {
+    const int32_t q1 = a.wbs[a.t + 1];
+    const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
+    for (int64_t q = a.wbs[a.t] + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < q1; q += step)
+      propose_piece<GS, MODE>(a, a.desc_s[q], q, r.wl & (GS - 1), P0);
   }
 }
 
@@ -604,12 +693,12 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
       if (threadIdx.x == 0) nmulti = 0;
       __syncthreads();
       const int64_t pp = c0 + threadIdx.x;
-      if (pp < hi && a.poff[pp + 1] - a.poff[pp] > 1) smulti[atomicAdd(&nmulti, 1)] = int32_t(pp);
+      if (pp < hi && a.loff[pp + 1] - a.loff[pp] > 1) smulti[atomicAdd(&nmulti, 1)] = int32_t(pp);
       __syncthreads();
       const int32_t cnt = nmulti;
       for (int32_t m = 0; m < cnt; ++m) {
         const int32_t p = smulti[m];
-        const int32_t pf = a.poff[p], np = a.poff[p + 1] - pf;
+        const int32_t pf = a.loff[p], np = a.loff[p + 1] - pf;
         float t = 0.0f;
         for (int32_t u = threadIdx.x; u < np; u += kBlock) t += a.gacc[pf + u];
         sred[threadIdx.x] = t;
@@ -667,82 +756,99 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
   }
 }
 
+// Scatter z += d x over one piece (G lanes).
+template <int G, int MODE>
+__device__ __forceinline__ void scatter_piece(const IterArgs &a, int64_t beg, int32_t len, float d,
+                                              int lane) {
+  for (int32_t base = 0; base < len; base += G * kUnroll) {
+    int32_t ri[kUnroll];
+    float vv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t e = base + u * G + lane;
+      ri[u] = e < len ? a.row_idx[beg + e] : -1;
+      vv[u] = e < len ? a.val[beg + e] : 0.0f;
+    }
+    if (MODE == 1) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ri[u] >= 0) scatter_plain(a.z_hi, a.z_lo, ri[u], d, vv[u]);
+    } else if (!a.exact_accum) {
+      // increments accumulate in the low word (non-returning atomics); the
+      // pair is renormalised exactly at the end of the epoch
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ri[u] >= 0) atomicAdd(&a.z_lo[ri[u]], d * vv[u]);
+    } else {
+      // issue all the returning atomics first, then the compensations
+      float pp[kUnroll], old[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        pp[u] = d * vv[u];
+        old[u] = ri[u] >= 0 ? atomicAdd(&a.z_hi[ri[u]], pp[u]) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (ri[u] < 0) continue;
+        const float corr = twosum_err(old[u], pp[u]) + fmaf(d, vv[u], -pp[u]);
+        if (corr != 0.0f) atomicAdd(&a.z_lo[ri[u]], corr);
+      }
+    }
+  }
+}
+
 // Update (Algorithm 3): z += delta_j X_j for the accepted, nonzero proposals.
 // Accept-all rules finalise split columns here: every piece recomputes the
 // same delta from the partial sums and the weight snapshot; the column's
 // first piece writes w_j, delta_j and phi_j.
-template <int G, int MODE>
+template <int GS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
-  const int lane = threadIdx.x & (G - 1);
-  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
-  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
-  const int32_t q0 = a.wbounds[a.t], q1 = a.wbounds[a.t + 1];
+  const Roles r = roles(a.nl);
   int32_t P0, P1;
   window_of(a, P0, P1);
-  for (int64_t q = q0 + gid; q < q1; q += ng) {
-    const int4 dsc = a.desc[q];
-    const int32_t slot = dsc.z - P0;
-    float d;
-    if (MODE == 2) {
-      if (!a.acc[slot]) continue;
-      d = a.delta[slot];
-    } else if (desc_single(dsc)) {
-      d = a.delta[slot];
-    } else {
-      const int32_t pf = a.poff[dsc.z], np = a.poff[dsc.z + 1] - pf;
-      const int32_t j = dsc.y;
-      const float ws = a.wsnap[slot];
-      const float cj = a.c[j];
-      const float g = split_sum<G>(a.gacc, pf, np, lane) / a.n_f;
-      float ph;
-      propose_f32(g, cj, ws, a.lam, d, ph);
-      if (q == pf && lane == 0) {
-        a.delta[slot] = d;
-        a.phi[slot] = ph;
-        if (a.gout) a.gout[slot] = g;
-        if (d != 0.0f) {
-          a.w[j] = ws + d;
-          atomicAdd(a.counters + 3, (unsigned long long)(a.col_ptr[j + 1] - a.col_ptr[j]));
-        }
-      }
-    }
-    if (d == 0.0f) continue;
-    const int64_t beg = desc_beg(dsc);
-    const int32_t len = desc_len(dsc);
-    for (int32_t base = 0; base < len; base += G * kUnroll) {
-      int32_t ri[kUnroll];
-      float vv[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t e = base + u * G + lane;
-        ri[u] = e < len ? a.row_idx[beg + e] : -1;
-        vv[u] = e < len ? a.val[beg + e] : 0.0f;
-      }
-      if (MODE == 1) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          if (ri[u] >= 0) scatter_plain(a.z_hi, a.z_lo, ri[u], d, vv[u]);
-      } else if (!a.exact_accum) {
-        // increments accumulate in the low word (non-returning atomics); the
-        // pair is renormalised exactly at the end of the epoch
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          if (ri[u] >= 0) atomicAdd(&a.z_lo[ri[u]], d * vv[u]);
+  if (r.wave < r.nl) {
+    const int32_t q1 = a.wbl[a.t + 1];
+    for (int64_t q = a.wbl[a.t] + r.wave; q < q1; q += r.nl) {
+      const int4 dsc = a.desc_l[q];
+      const int32_t slot = dsc.z - P0;
+      float d;
+      if (MODE == 2) {
+        if (!a.acc[slot]) continue;
+        d = a.delta[slot];
+      } else if (desc_single(dsc)) {
+        d = a.delta[slot];
       } else {
-        // issue all the returning atomics first, then the compensations
-        float pp[kUnroll], old[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          pp[u] = d * vv[u];
-          old[u] = ri[u] >= 0 ? atomicAdd(&a.z_hi[ri[u]], pp[u]) : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          if (ri[u] < 0) continue;
-          const float corr = twosum_err(old[u], pp[u]) + fmaf(d, vv[u], -pp[u]);
-          if (corr != 0.0f) atomicAdd(&a.z_lo[ri[u]], corr);
+        const int32_t pf = a.loff[dsc.z], np = a.loff[dsc.z + 1] - pf;
+        const int32_t j = dsc.y;
+        const float ws = a.wsnap[slot];
+        const float cj = a.c[j];
+        const float g = split_sum(a.gacc, pf, np, r.wl) / a.n_f;
+        float ph;
+        propose_f32(g, cj, ws, a.lam, d, ph);
+        if (q == pf && r.wl == 0) {
+          a.delta[slot] = d;
+          a.phi[slot] = ph;
+          if (a.gout) a.gout[slot] = g;
+          if (d != 0.0f) {
+            a.w[j] = ws + d;
+            atomicAdd(a.counters + 3, (unsigned long long)(a.col_ptr[j + 1] - a.col_ptr[j]));
+          }
         }
       }
+      if (d == 0.0f) continue;
+      scatter_piece<kWave, MODE>(a, desc_beg(dsc), desc_len(dsc), d, r.wl);
+    }
+  } else {
+    const int32_t q1 = a.wbs[a.t + 1];
+    const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
+    const int lane = r.wl & (GS - 1);
+    for (int64_t q = a.wbs[a.t] + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < q1; q += step) {
+      const int4 dsc = a.desc_s[q];
+      const int32_t slot = dsc.z - P0;
+      if (MODE == 2 && !a.acc[slot]) continue;
+      const float d = a.delta[slot];
+      if (d == 0.0f) continue;
+      scatter_piece<GS, MODE>(a, desc_beg(dsc), desc_len(dsc), d, lane);
     }
   }
 }
@@ -763,38 +869,44 @@ int launch_renorm(int64_t n, float *z_hi, float *z_lo, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
-template <int G>
-static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, int64_t groups,
+template <int GS>
+static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsigned blocks,
                               int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
                               hipEvent_t ev1) {
-  const dim3 grid(groups_grid(groups, G)), blk(kBlock);
+  const dim3 grid(blocks), blk(kBlock);
   if (ev0) (void)hipEventRecord(ev0, s);
   if (mode == 0)
-    hipLaunchKernelGGL((k_propose<G, 0>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_propose<GS, 0>), grid, blk, 0, s, a);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_propose<G, 1>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_propose<GS, 1>), grid, blk, 0, s, a);
   else
-    hipLaunchKernelGGL((k_propose<G, 2>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_propose<GS, 2>), grid, blk, 0, s, a);
   if (ev1) (void)hipEventRecord(ev1, s);
   if (mode == 0) {
-    hipLaunchKernelGGL((k_update<G, 0>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<GS, 0>), grid, blk, 0, s, a);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_update<G, 1>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<GS, 1>), grid, blk, 0, s, a);
   } else {
     unsigned nb = unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
     hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
-    hipLaunchKernelGGL((k_update<G, 2>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<GS, 2>), grid, blk, 0, s, a);
   }
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
-int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t groups,
-                     int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
+                     int64_t long_bound, int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
+                     hipEvent_t ev1) {
+  IterArgs b = a;
+  unsigned blocks;
+  int32_t nl;
+  two_class_grid(short_bound, long_bound, group, &blocks, &nl);
+  b.nl = nl;
   switch (group) {
-    case 8: return launch_iteration_g<8>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
-    case 16: return launch_iteration_g<16>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
-    case 32: return launch_iteration_g<32>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
-    default: return launch_iteration_g<64>(a, mode, block, groups, nblocks_accept, s, ev0, ev1);
+    case 4: return launch_iteration_g<4>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    case 8: return launch_iteration_g<8>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    case 16: return launch_iteration_g<16>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    default: return launch_iteration_g<32>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
   }
 }
 
@@ -812,31 +924,39 @@ __global__ __launch_bounds__(kBlock) void k_check_zero(double *z64, int64_t n, d
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, const float *val,
-                                                        const int4 *desc, int32_t npieces,
-                                                        const float *w, double *z64) {
-  const int lane = threadIdx.x & (G - 1);
-  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
-  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
-  for (int64_t q = gid; q < npieces; q += ng) {
-    const int4 dsc = desc[q];
-    const double wj = double(w[dsc.y]);
-    if (wj == 0.0) continue;
-    const int64_t beg = desc_beg(dsc);
-    const int32_t len = desc_len(dsc);
-    for (int32_t base = 0; base < len; base += G * kUnroll) {
-      int32_t ri[kUnroll];
-      float vv[kUnroll];
+__device__ __forceinline__ void spmv_piece(const int32_t *row_idx, const float *val, const int4 d,
+                                           const float *w, double *z64, int lane) {
+  const double wj = double(w[d.y]);
+  if (wj == 0.0) return;
+  const int64_t beg = desc_beg(d);
+  const int32_t len = desc_len(d);
+  for (int32_t base = 0; base < len; base += G * kUnroll) {
+    int32_t ri[kUnroll];
+    float vv[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t e = base + u * G + lane;
-        ri[u] = e < len ? row_idx[beg + e] : -1;
-        vv[u] = e < len ? val[beg + e] : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (ri[u] >= 0) atomicAdd(&z64[ri[u]], wj * double(vv[u]));
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t e = base + u * G + lane;
+      ri[u] = e < len ? row_idx[beg + e] : -1;
+      vv[u] = e < len ? val[beg + e] : 0.0f;
     }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (ri[u] >= 0) atomicAdd(&z64[ri[u]], wj * double(vv[u]));
+  }
+}
+
+template <int GS>
+__global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, const float *val,
+                                                        const int4 *ds, int32_t ns,
+                                                        const int4 *dl, int32_t nlp, int32_t nl_req,
+                                                        const float *w, double *z64) {
+  const Roles r = roles(nl_req);
+  if (r.wave < r.nl) {
+    for (int64_t q = r.wave; q < nlp; q += r.nl) spmv_piece<kWave>(row_idx, val, dl[q], w, z64, r.wl);
+  } else {
+    const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
+    for (int64_t q = (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < ns; q += step)
+      spmv_piece<GS>(row_idx, val, ds[q], w, z64, r.wl & (GS - 1));
   }
 }
 
@@ -867,40 +987,48 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, cons
 }
 
 template <int G>
+__device__ __forceinline__ void cols_piece(const int32_t *row_idx, const float *val, const int4 d,
+                                           const double *r64, double *g64, int lane) {
+  const int64_t beg = desc_beg(d);
+  const int32_t len = desc_len(d);
+  double s = 0.0;
+  for (int32_t base = 0; base < len; base += G * kUnroll) {
+    int32_t ri[kUnroll];
+    float vv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t e = base + u * G + lane;
+      ri[u] = e < len ? row_idx[beg + e] : -1;
+      vv[u] = e < len ? val[beg + e] : 0.0f;
+    }
+    double rr[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) rr[u] = r64[ri[u] >= 0 ? ri[u] : 0];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (ri[u] >= 0) s += double(vv[u]) * rr[u];
+  }
+  s = group_sum<G>(s);
+  if (lane == 0) {
+    if (desc_single(d))
+      g64[d.y] = s;
+    else
+      atomicAdd(&g64[d.y], s);
+  }
+}
+
+template <int GS>
 __global__ __launch_bounds__(kBlock) void k_check_cols(const int32_t *row_idx, const float *val,
-                                                        const int4 *desc, int32_t npieces,
+                                                        const int4 *ds, int32_t ns,
+                                                        const int4 *dl, int32_t nlp, int32_t nl_req,
                                                         const double *r64, double *g64) {
-  const int lane = threadIdx.x & (G - 1);
-  const int64_t gid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G;
-  const int64_t ng = int64_t(gridDim.x) * kBlock / G;
-  for (int64_t q = gid; q < npieces; q += ng) {
-    const int4 dsc = desc[q];
-    const int64_t beg = desc_beg(dsc);
-    const int32_t len = desc_len(dsc);
-    double s = 0.0;
-    for (int32_t base = 0; base < len; base += G * kUnroll) {
-      int32_t ri[kUnroll];
-      float vv[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t e = base + u * G + lane;
-        ri[u] = e < len ? row_idx[beg + e] : -1;
-        vv[u] = e < len ? val[beg + e] : 0.0f;
-      }
-      double rr[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) rr[u] = r64[ri[u] >= 0 ? ri[u] : 0];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (ri[u] >= 0) s += double(vv[u]) * rr[u];
-    }
-    s = group_sum<G>(s);
-    if (lane == 0) {
-      if (desc_single(dsc))
-        g64[dsc.y] = s;
-      else
-        atomicAdd(&g64[dsc.y], s);
-    }
+  const Roles r = roles(nl_req);
+  if (r.wave < r.nl) {
+    for (int64_t q = r.wave; q < nlp; q += r.nl) cols_piece<kWave>(row_idx, val, dl[q], r64, g64, r.wl);
+  } else {
+    const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
+    for (int64_t q = (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < ns; q += step)
+      cols_piece<GS>(row_idx, val, ds[q], r64, g64, r.wl & (GS - 1));
   }
 }
 
@@ -988,20 +1116,22 @@ __global__ __launch_bounds__(kBlock) void k_check_dual(int64_t n, int loss, cons
 }
 
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
-                 int piece, int32_t total_pieces, const Ws &ws, bool resync, hipStream_t s) {
-  (void)piece;
+                 int32_t n_short, int32_t n_lpieces, const Ws &ws, bool resync, hipStream_t s) {
   unsigned long long *red = reinterpret_cast<unsigned long long *>(ws.red);
   const int64_t nk = X->n > X->k ? X->n : X->k;
+  unsigned blocks;
+  int32_t nl;
+  two_class_grid(n_short, n_lpieces, 8, &blocks, &nl);
   hipLaunchKernelGGL(k_check_zero, dim3(grid_for(nk)), dim3(kBlock), 0, s, ws.z64, X->n, ws.g64,
                      X->k, red);
-  if (w && total_pieces > 0)
-    hipLaunchKernelGGL(k_check_spmv<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
-                       X->row_idx, X->val, ws.desc_all, total_pieces, w, ws.z64);
+  if (w && n_short + n_lpieces > 0)
+    hipLaunchKernelGGL(k_check_spmv<8>, dim3(blocks), dim3(kBlock), 0, s, X->row_idx, X->val,
+                       ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, w, ws.z64);
   hipLaunchKernelGGL(k_check_rows, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
                      ws.z64, ws.r64, resync ? ws.z_hi : nullptr, ws.z_lo, ws.red);
-  if (total_pieces > 0)
-    hipLaunchKernelGGL(k_check_cols<64>, dim3(groups_grid(total_pieces, 64)), dim3(kBlock), 0, s,
-                       X->row_idx, X->val, ws.desc_all, total_pieces, ws.r64, ws.g64);
+  if (n_short + n_lpieces > 0)
+    hipLaunchKernelGGL(k_check_cols<8>, dim3(blocks), dim3(kBlock), 0, s, X->row_idx, X->val,
+                       ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, ws.r64, ws.g64);
   hipLaunchKernelGGL(k_check_kkt, dim3(grid_for(X->k, 256)), dim3(kBlock), 0, s, X->k, ws.g64, w,
                      lam, 1.0 / double(X->n), red);
   hipLaunchKernelGGL(k_check_dual, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,

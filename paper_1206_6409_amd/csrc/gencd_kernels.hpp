@@ -17,9 +17,11 @@ struct IterArgs {
   const float *c;
   float *w;
   float *z_hi, *z_lo;
-  const int32_t *col_of_pos, *poff;
-  const int4 *desc;        // piece descriptors of the current order
-  const int32_t *wbounds;  // first piece of every window; window t is [wbounds[t], wbounds[t+1])
+  const int32_t *col_of_pos;
+  const int32_t *loff;             // long-piece offsets of the positions
+  const int4 *desc_s, *desc_l;     // descriptors of the current order
+  const int32_t *wbs, *wbl;        // window t: short [wbs[t], wbs[t+1]), long [wbl[t], wbl[t+1])
+  int32_t nl;                      // waves walking long pieces (set by the launcher)
   const int32_t *win_off;  // per-epoch window offsets, or null: [win_lo, win_hi)
   int32_t t, win_lo, win_hi;
   float *delta, *phi, *gacc, *gout, *wsnap;
@@ -36,9 +38,10 @@ int copy_i32(int32_t *d, const int32_t *src, int64_t m, hipStream_t s);
 
 int launch_validate(const gencd_csc *X, const float *y, int loss, bool matrix,
                     unsigned long long *bad, hipStream_t s);
-int launch_preprocess(const gencd_csc *X, int loss, int piece, const Ws &w, hipStream_t s);
-int launch_curvature(const gencd_csc *X, int loss, int piece, int32_t total_pieces, const Ws &w,
-                     hipStream_t s);
+int launch_preprocess(const gencd_csc *X, int loss, int piece, int short_max, const Ws &w,
+                      hipStream_t s);
+int launch_curvature(const gencd_csc *X, int loss, int32_t n_short, int32_t n_lpieces,
+                     const Ws &w, hipStream_t s);
 int launch_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hipStream_t s);
 // Writes the epoch order, its piece descriptors and, in w.wbounds[0..T], the
 // first piece of every window (S positions per window; colour windows for
@@ -48,11 +51,14 @@ int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed,
                        hipStream_t s);
 int launch_inc_epoch(int64_t *epoch, hipStream_t s);
 int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s);
-int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t groups,
-                     int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0 = nullptr,
-                     hipEvent_t ev1 = nullptr);
+// group: lanes per short column (4, 8, 16 or 32); short_bound / long_bound:
+// expected short columns / long pieces of a window (they size the grid; the
+// kernels stride over whatever the window holds).
+int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
+                     int64_t long_bound, int64_t nblocks_accept, hipStream_t s,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
-                 int piece, int32_t total_pieces, const Ws &ws, bool resync, hipStream_t s);
+                 int32_t n_short, int32_t n_lpieces, const Ws &ws, bool resync, hipStream_t s);
 int launch_renorm(int64_t n, float *z_hi, float *z_lo, hipStream_t s);
 int launch_round_f32(const double *src, float *dst, int64_t m, hipStream_t s);
 

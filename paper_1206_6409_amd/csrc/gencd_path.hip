@@ -385,15 +385,16 @@ static int path_check(const gencd_csc *X, const float *y, int loss, const PathWs
 struct PathSetup {
   Ws base;
   int piece;
-  int32_t total_pieces;
+  int32_t n_short, n_lpieces;
   int64_t k_live;
 };
 
 int path_setup(const gencd_csc *X, const float *y, const gencd_params *p, void *ws, size_t bytes,
                hipStream_t s, PathSetup *out, size_t *used);
 
-size_t path_workspace_bytes(int64_t n, int64_t k, int64_t nnz, int64_t S, int B, int piece) {
-  return workspace_layout(n, k, nnz, piece, nullptr, nullptr) + 256 +
+size_t path_workspace_bytes(int64_t n, int64_t k, int64_t nnz, int64_t S, int B, int piece,
+                            int short_max) {
+  return workspace_layout(n, k, nnz, piece, short_max, nullptr, nullptr) + 256 +
          path_layout(n, k, S, B, nullptr, nullptr) + 256;
 }
 
@@ -576,8 +577,9 @@ int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_
   if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
   if (p->select_size <= 0) return GENCD_ERR_INVALID_ARG;
   const int piece = p->piece ? p->piece : 512;
+  const int group = p->group ? p->group : 8;
   *out_bytes = path_workspace_bytes(X->n, X->k, X->nnz, std::min<int64_t>(p->select_size, X->k), B,
-                                    piece) + 256;
+                                    piece, group * kUnroll) + 256;
   return GENCD_OK;
 }
 

@@ -20,10 +20,16 @@ namespace gencd {
 
 static constexpr size_t kAlign = 256;
 static constexpr int kDefaultPiece = 512;
-static constexpr int kDefaultGroup = 64;
-static constexpr int64_t kMaxGroups = 2048 * (kBlock / 8);
+static constexpr int kDefaultGroup = 8;
 
-int64_t max_pieces_for(int64_t k, int64_t nnz, int piece) { return k + nnz / piece + 2; }
+// long pieces: a long column has more than short_max nonzeros, so there are
+// at most nnz / (short_max + 1) of them, each with at most one partial piece
+int64_t max_lpieces_for(int64_t k, int64_t nnz, int piece, int short_max) {
+  (void)k;
+  return nnz / piece + nnz / (short_max + 1) + 2;
+}
+
+static int short_max_of(int group) { return group * kUnroll; }
 
 namespace {
 struct Carver {
@@ -39,29 +45,36 @@ struct Carver {
 };
 }  // namespace
 
-size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, void *base, Ws *ws) {
+size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, void *base,
+                        Ws *ws) {
   Carver c{static_cast<char *>(base)};
   Ws w{};
-  const int64_t mp = max_pieces_for(k, nnz, piece);
-  const int64_t scan_len = mp > k + 1 ? mp : k + 1;
-  w.max_pieces = mp;
+  const int64_t ml = max_lpieces_for(k, nnz, piece, short_max);
+  const int64_t scan_len = ml > k + 1 ? ml : k + 1;
+  w.max_lpieces = ml;
   w.scan_part_len = scan_partials_for(scan_len);
   w.c = c.take<float>(k);
   w.live = c.take<int32_t>(k);
-  w.all_poff = c.take<int32_t>(k + 1);
-  w.desc_all = c.take<int4>(mp);
+  w.all_soff = c.take<int32_t>(k + 1);
+  w.all_loff = c.take<int32_t>(k + 1);
+  w.desc_all_s = c.take<int4>(k);
+  w.desc_all_l = c.take<int4>(ml);
   w.tmp_cnt = c.take<int32_t>(k + 1);
+  w.tmp_cnt2 = c.take<int32_t>(k + 1);
   w.scan_part = c.take<int32_t>(int64_t(w.scan_part_len));
   w.cls_off = c.take<int32_t>(k + 1);
   w.cls_mem = c.take<int32_t>(k);
   w.col_of_pos = c.take<int32_t>(k);
-  w.poff = c.take<int32_t>(k + 1);
-  w.desc = c.take<int4>(mp);
+  w.soff = c.take<int32_t>(k + 1);
+  w.loff = c.take<int32_t>(k + 1);
+  w.desc_s = c.take<int4>(k);
+  w.desc_l = c.take<int4>(ml);
   w.win_off = c.take<int32_t>(k + 1);
-  w.wbounds = c.take<int32_t>(k + 2);
+  w.wbs = c.take<int32_t>(k + 2);
+  w.wbl = c.take<int32_t>(k + 2);
   w.delta = c.take<float>(k);
   w.phi = c.take<float>(k);
-  w.gacc = c.take<float>(mp);
+  w.gacc = c.take<float>(ml);
   w.wsnap = c.take<float>(k);
   w.acc = c.take<int32_t>(k);
   w.z_hi = c.take<float>(n);
@@ -87,9 +100,9 @@ bool csc_ok(const gencd_csc *X) {
 
 int resolve_schedule(const gencd_params *p, int *piece, int *group) {
   int g = (p && p->group) ? p->group : kDefaultGroup;
-  if (g != 8 && g != 16 && g != 32 && g != 64) return GENCD_ERR_INVALID_ARG;
+  if (g != 4 && g != 8 && g != 16 && g != 32) return GENCD_ERR_INVALID_ARG;
   int pc = (p && p->piece) ? p->piece : kDefaultPiece;
-  if (pc < g || pc % g != 0 || pc > (1 << 22)) return GENCD_ERR_INVALID_ARG;
+  if (pc < 64 || pc % 64 != 0 || pc > (1 << 22)) return GENCD_ERR_INVALID_ARG;
   *piece = pc;
   *group = g;
   return GENCD_OK;
@@ -137,7 +150,7 @@ double bits_to_double(unsigned long long b) {
 struct Setup {
   Ws ws{};
   int piece = kDefaultPiece, group = kDefaultGroup;
-  int32_t total_pieces = 0;
+  int32_t n_short = 0, n_lpieces = 0;
   int64_t k_live = 0;
 };
 
@@ -148,35 +161,39 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
   if (!csc_ok(X) || !y) return GENCD_ERR_INVALID_ARG;
   int st = resolve_schedule(p, &out->piece, &out->group);
   if (st) return st;
-  if (max_pieces_for(X->k, X->nnz, out->piece) >= INT32_MAX || X->nnz >= (int64_t(1) << 32))
+  const int smax = short_max_of(out->group);
+  if (max_lpieces_for(X->k, X->nnz, out->piece, smax) >= INT32_MAX ||
+      X->nnz >= (int64_t(1) << 32))
     return GENCD_ERR_UNSUPPORTED;
-  size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, nullptr, nullptr);
+  size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, smax, nullptr, nullptr);
   if (!ws_base || ws_bytes < need) return GENCD_ERR_WORKSPACE;
   // align the carve base
   char *base = static_cast<char *>(ws_base);
   size_t mis = reinterpret_cast<uintptr_t>(base) % kAlign;
   if (mis) base += kAlign - mis;
-  workspace_layout(X->n, X->k, X->nnz, out->piece, base, &out->ws);
+  workspace_layout(X->n, X->k, X->nnz, out->piece, smax, base, &out->ws);
   const Ws &w = out->ws;
   st = fill_f64(w.red, 16, 0.0, s);
   if (st) return st;
   st = launch_validate(X, y, loss, validate_matrix, reinterpret_cast<unsigned long long *>(w.red) + 10, s);
   if (st) return st;
-  st = launch_preprocess(X, loss, out->piece, w, s);
+  st = launch_preprocess(X, loss, out->piece, smax, w, s);
   if (st) return st;
-  int32_t host[2] = {0, 0};
+  int32_t host[3] = {0, 0, 0};
   Red r{};
-  GENCD_HIP(hipMemcpyAsync(&host[0], w.all_poff + X->k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GENCD_HIP(hipMemcpyAsync(&host[1], w.poff + X->k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipMemcpyAsync(&host[0], w.all_soff + X->k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipMemcpyAsync(&host[1], w.soff + X->k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipMemcpyAsync(&host[2], w.all_loff + X->k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   st = read_red(w, s, &r);
   if (st) return st;
   if (r.bad & 1ull) return GENCD_ERR_BAD_MATRIX;
   if (r.bad & 2ull) return GENCD_ERR_BAD_LABELS;
-  out->total_pieces = host[0];
+  out->n_short = host[0];
   out->k_live = host[1];
-  st = launch_curvature(X, loss, out->piece, out->total_pieces, w, s);
+  out->n_lpieces = host[2];
+  st = launch_curvature(X, loss, out->n_short, out->n_lpieces, w, s);
   if (st) return st;
-  st = fill_f32(w.gacc, w.max_pieces, 0.0f, s);
+  st = fill_f32(w.gacc, w.max_lpieces, 0.0f, s);
   if (st) return st;
   return fill_i32(w.acc, X->k, 0, s);
 }
@@ -189,7 +206,7 @@ struct CheckOut {
 
 int run_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
               const Setup &su, bool resync, hipStream_t s, CheckOut *out) {
-  int st = launch_check(X, y, loss, lam, w, su.piece, su.total_pieces, su.ws, resync, s);
+  int st = launch_check(X, y, loss, lam, w, su.n_short, su.n_lpieces, su.ws, resync, s);
   if (st) return st;
   Red r{};
   st = read_red(su.ws, s, &r);
@@ -231,14 +248,16 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   a.z_hi = z_hi;
   a.z_lo = z_lo;
   a.col_of_pos = ws.col_of_pos;
-  a.poff = ws.poff;
-  a.desc = ws.desc;
+  a.loff = ws.loff;
+  a.desc_s = ws.desc_s;
+  a.desc_l = ws.desc_l;
   a.delta = ws.delta;
   a.phi = ws.phi;
   a.gacc = ws.gacc;
   a.gout = nullptr;
   a.wsnap = ws.wsnap;
-  a.wbounds = ws.wbounds;
+  a.wbs = ws.wbs;
+  a.wbl = ws.wbl;
   a.acc = ws.acc;
   a.counters = reinterpret_cast<unsigned long long *>(ws.red) + 8;
   a.exact_accum = (p->flags & GENCD_EXACT_ACCUM) ? 1 : 0;
@@ -330,9 +349,13 @@ struct EventPool {
   }
 };
 
-int64_t groups_for(int64_t positions, int64_t extra_pieces) {
-  int64_t g = positions + extra_pieces;
-  return g < kMaxGroups ? g : kMaxGroups;
+// Expected long pieces in a window of `positions` columns (sizes the grid;
+// the kernels stride over the actual count).
+int64_t long_bound_for(const Setup &su, int64_t positions) {
+  if (su.n_lpieces <= 0 || su.k_live <= 0) return 0;
+  const double per = double(su.n_lpieces) * double(positions) / double(su.k_live);
+  int64_t b = int64_t(2.0 * per) + 32;
+  return b < su.n_lpieces ? b : su.n_lpieces;
 }
 
 }  // namespace
@@ -340,7 +363,7 @@ int64_t groups_for(int64_t positions, int64_t extra_pieces) {
 struct PathSetup {
   Ws base;
   int piece;
-  int32_t total_pieces;
+  int32_t n_short, n_lpieces;
   int64_t k_live;
 };
 
@@ -355,9 +378,11 @@ int path_setup(const gencd_csc *X, const float *y, const gencd_params *p, void *
   if (st) return st;
   out->base = su.ws;
   out->piece = su.piece;
-  out->total_pieces = su.total_pieces;
+  out->n_short = su.n_short;
+  out->n_lpieces = su.n_lpieces;
   out->k_live = su.k_live;
-  *used = workspace_layout(X->n, X->k, X->nnz, su.piece, nullptr, nullptr) + kAlign;
+  *used = workspace_layout(X->n, X->k, X->nnz, su.piece, short_max_of(su.group), nullptr, nullptr) +
+          kAlign;
   return GENCD_OK;
 }
 
@@ -419,7 +444,6 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   if (S > k_live) S = k_live;
   if (S < 1) S = 1;
   const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
-  const int64_t extra = int64_t(su.total_pieces) - k_live;  // pieces beyond one per column
   int64_t max_class = 0;
   for (int32_t sz : cls_sizes) max_class = std::max<int64_t>(max_class, sz);
   int64_t *epoch_dev = reinterpret_cast<int64_t *>(ws.red + 12);
@@ -460,17 +484,15 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
     PermKey cpk{};
     if (rule == GENCD_COLORING && !use_graph) cpk = make_perm_key(C, p->seed, e_host);
     for (int64_t t = 0; t < T; ++t) {
-      int64_t positions, bound;
+      int64_t positions;
       if (rule == GENCD_COLORING) {
         a.win_off = ws.win_off;
         positions = use_graph ? max_class : cls_sizes[size_t(perm_apply(cpk, uint64_t(t)))];
-        bound = max_class + extra;
       } else {
         a.win_off = nullptr;
         a.win_lo = int32_t(t * S);
         a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
         positions = a.win_hi - a.win_lo;
-        bound = positions + extra;
       }
       if (positions == 0) continue;
       a.t = int32_t(t);
@@ -481,8 +503,8 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
         e1 = evs[ev_used + 1];
         ev_used += 2;
       }
-      rc = launch_iteration(a, su.group, mode, B, groups_for(bound, 0), (positions + B - 1) / B,
-                            es, e0, e1);
+      rc = launch_iteration(a, su.group, mode, B, positions, long_bound_for(su, positions),
+                            (positions + B - 1) / B, es, e0, e1);
       if (rc) return rc;
     }
     if (mode != 1 && !a.exact_accum) {
@@ -623,8 +645,8 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
   a.t = 0;
   a.gout = g;
   const int64_t B = (p->rule == GENCD_THREAD_GREEDY) ? p->block : nJ;
-  const int64_t extra = int64_t(su.total_pieces) - su.k_live;
-  st = launch_iteration(a, su.group, mode, B, groups_for(nJ + extra, 0), (nJ + B - 1) / B, s);
+  st = launch_iteration(a, su.group, mode, B, nJ, std::max<int64_t>(long_bound_for(su, nJ), 1),
+                        (nJ + B - 1) / B, s);
   if (st) return st;
   if (delta) st = copy_f32(delta, ws.delta, nJ, s);
   if (st) return st;
@@ -693,7 +715,8 @@ int gencd_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out
   int piece, group;
   int st = resolve_schedule(p, &piece, &group);
   if (st) return st;
-  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, nullptr, nullptr) + kAlign;
+  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), nullptr, nullptr) +
+               kAlign;
   return GENCD_OK;
 }
 

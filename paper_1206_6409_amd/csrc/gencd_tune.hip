@@ -122,14 +122,13 @@ int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, in
   const std::string key = signature(X, p, h);
   if (cache_lookup(cache_path, key, out)) return GENCD_OK;
 
-  const int groups[] = {16, 32, 64};
+  const int groups[] = {4, 8, 16};
   const int pieces[] = {256, 512, 1024};
   const unsigned gflags[] = {0u, GENCD_USE_GRAPH};
   double best = 1e300;
   for (int g : groups)
     for (int pc : pieces)
       for (unsigned gf : gflags) {
-        if (pc < g) continue;
         gencd_params q = *p;
         q.group = g;
         q.piece = pc;

@@ -113,12 +113,12 @@ def _split(z64):
 
 
 STEP_CASES = [
-    ("c1", G.SHOTGUN, 0, 64, 64), ("c1", G.SHOTGUN, 0, 16, 64),
-    ("c2", G.SHOTGUN, 0, 64, 1024), ("c2", G.SHOTGUN, 0, 8, 64), ("c2", G.SHOTGUN, 0, 32, 128),
-    ("c2", G.THREAD_GREEDY, 64, 64, 256), ("c2", G.THREAD_GREEDY, 7, 16, 64),
-    ("c2", G.GREEDY, 0, 64, 1024),
-    ("c3", G.SHOTGUN, 0, 64, 64), ("c4", G.SHOTGUN, 0, 64, 64), ("c4", G.THREAD_GREEDY, 16, 64, 64),
-    ("c2", G.SHOTGUN, 0, 64, 256, G.EXACT_ACCUM), ("c2", G.THREAD_GREEDY, 64, 64, 256, G.EXACT_ACCUM),
+    ("c1", G.SHOTGUN, 0, 8, 64), ("c1", G.SHOTGUN, 0, 16, 64),
+    ("c2", G.SHOTGUN, 0, 8, 1024), ("c2", G.SHOTGUN, 0, 4, 64), ("c2", G.SHOTGUN, 0, 32, 128),
+    ("c2", G.THREAD_GREEDY, 64, 8, 256), ("c2", G.THREAD_GREEDY, 7, 16, 64),
+    ("c2", G.GREEDY, 0, 8, 1024), ("c2", G.GREEDY, 0, 4, 64),
+    ("c3", G.SHOTGUN, 0, 8, 64), ("c4", G.SHOTGUN, 0, 4, 64), ("c4", G.THREAD_GREEDY, 16, 8, 64),
+    ("c2", G.SHOTGUN, 0, 8, 256, G.EXACT_ACCUM), ("c2", G.THREAD_GREEDY, 64, 8, 256, G.EXACT_ACCUM),
 ]
 
 
