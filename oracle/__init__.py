@@ -73,6 +73,10 @@ def lib():
         L.orc_duality_gap.restype = D
         L.orc_duality_gap.argtypes = [P, P, I32, D, P, P]
         L.orc_color.restype = I32
+        L.orc_rho.restype = D
+        L.orc_rho.argtypes = [P, I32, P, P]
+        L.orc_pstar.restype = I64
+        L.orc_pstar.argtypes = [I64, D, I64]
         L.orc_color.argtypes = [I64, I64, P, P, I32, P, P, P]
         L.orc_solve.restype = I32
         L.orc_solve.argtypes = [P, P, P, P, P, P]
@@ -199,6 +203,20 @@ def duality_gap(X: Matrix, y, kind, lam, w):
     prim = C.c_double()
     gap = lib().orc_duality_gap(X.ref, _p(y), kind, float(lam), _p(w), C.byref(prim))
     return gap, prim.value
+
+
+def rho(X: Matrix, iters=20):
+    """(rho, history, k_live): power-iteration estimate of the spectral radius
+    of the column-normalised Gram matrix (section 4.1)."""
+    hist = np.zeros(max(int(iters), 1), dtype=np.float64)
+    kl = C.c_int64()
+    r = lib().orc_rho(X.ref, int(iters), _p(hist), C.byref(kl))
+    return r, hist[:int(iters)], kl.value
+
+
+def pstar(k_live, rho_est, cap=1024):
+    """Selection size floor(k_live / (2 rho)) clamped to [1, cap]."""
+    return int(lib().orc_pstar(int(k_live), float(rho_est), int(cap)))
 
 
 def color(n, k, col_ptr, row_idx, order_mode=0):

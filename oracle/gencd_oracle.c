@@ -361,6 +361,73 @@ double orc_duality_gap(const orc_csc *X, const double *y, int loss, double lambd
 }
 
 /* ------------------------------------------------------------------------ */
+/* Spectral radius of the column-normalised Gram matrix (section 4.1)         */
+/* ------------------------------------------------------------------------ */
+
+/* Shotgun is guaranteed to converge when it selects at most P* = k/(2 rho)
+ * coordinates, rho the largest eigenvalue of X^T X for columns scaled to unit
+ * norm (section 4.1, after Bradley et al. 2011).  Here
+ *   G = D^{-1/2} X^T X D^{-1/2},  D = diag(X^T X),
+ * restricted to the non-empty columns, and rho is estimated by power
+ * iteration from the unit vector with equal entries on those columns:
+ *   u = G v,  rho_t = ||u||_2,  v <- u / rho_t,   t = 1..iters.
+ * Returns rho_iters (0 if every column is empty); hist[t-1] = rho_t when hist
+ * is non-null; *k_live receives the number of non-empty columns. */
+double orc_rho(const orc_csc *X, int32_t iters, double *hist, int64_t *k_live) {
+  int64_t n = X->n, k = X->k, kl = 0;
+  double *dinv = (double *)calloc((size_t)k, sizeof(double)); /* D^{-1/2}, 0 on empty columns */
+  double *v = (double *)calloc((size_t)k, sizeof(double));
+  double *s = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int64_t j = 0; j < k; ++j) {
+    double q = 0.0;
+    for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) q += X->val[p] * X->val[p];
+    if (q > 0.0) {
+      dinv[j] = 1.0 / sqrt(q);
+      ++kl;
+    }
+  }
+  if (k_live) *k_live = kl;
+  double rho = 0.0;
+  if (kl > 0) {
+    for (int64_t j = 0; j < k; ++j) v[j] = dinv[j] > 0.0 ? 1.0 / sqrt((double)kl) : 0.0;
+    for (int32_t t = 0; t < iters; ++t) {
+      /* s = X D^{-1/2} v */
+      for (int64_t i = 0; i < n; ++i) s[i] = 0.0;
+      for (int64_t j = 0; j < k; ++j) {
+        double xj = dinv[j] * v[j];
+        for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) s[X->row_idx[p]] += X->val[p] * xj;
+      }
+      /* u = D^{-1/2} X^T s (stored in v), rho = ||u|| */
+      double nrm = 0.0;
+      for (int64_t j = 0; j < k; ++j) {
+        double u = 0.0;
+        for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) u += X->val[p] * s[X->row_idx[p]];
+        v[j] = dinv[j] * u;
+        nrm += v[j] * v[j];
+      }
+      rho = sqrt(nrm);
+      if (hist) hist[t] = rho;
+      if (rho == 0.0) break;
+      for (int64_t j = 0; j < k; ++j) v[j] /= rho;
+    }
+  }
+  free(dinv);
+  free(v);
+  free(s);
+  return rho;
+}
+
+/* Selection size from the estimate: floor(k_live / (2 rho)), clamped to
+ * [1, cap]. */
+int64_t orc_pstar(int64_t k_live, double rho, int64_t cap) {
+  if (!(rho > 0.0)) return 1;
+  double q = floor((double)k_live / (2.0 * rho));
+  if (q < 1.0) return 1;
+  if (q > (double)cap) return cap;
+  return (int64_t)q;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Greedy partial distance-2 colouring of the column conflict graph           */
 /* ------------------------------------------------------------------------ */
 

@@ -537,3 +537,96 @@ def test_duality_gap_bounds_suboptimality(kind):
     lm = O.lambda_max(X, y, kind)
     gap0, _ = O.duality_gap(X, y, kind, lm, np.zeros(k))
     assert abs(gap0) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# Spectral radius estimate behind P* = k / (2 rho) (section 4.1)
+# --------------------------------------------------------------------------
+
+def _csc_matrix(A):
+    """Oracle matrix from a dense array (column-major nonzeros)."""
+    k = A.shape[1]
+    col_ptr = [0]
+    rows, vals = [], []
+    for j in range(k):
+        nz = np.nonzero(A[:, j])[0]
+        rows.extend(nz.tolist())
+        vals.extend(A[nz, j].tolist())
+        col_ptr.append(len(rows))
+    return O.Matrix(A.shape[0], k, np.array(col_ptr, np.int64), np.array(rows, np.int32),
+                    np.array(vals, np.float64))
+
+
+def _normalised_gram_rho(A):
+    live = np.linalg.norm(A, axis=0) > 0
+    B = A[:, live] / np.linalg.norm(A[:, live], axis=0)
+    return float(np.linalg.eigvalsh(B.T @ B)[-1])
+
+
+def test_rho_disjoint_columns_is_one():
+    # one nonzero per row: the normalised Gram matrix is the identity
+    rng = np.random.default_rng(3)
+    A = np.zeros((40, 12))
+    for i in range(40):
+        A[i, rng.integers(12)] = rng.normal()
+    r, hist, kl = O.rho(_csc_matrix(A), 5)
+    assert kl == int((np.abs(A).sum(0) > 0).sum())
+    np.testing.assert_allclose(hist, 1.0, rtol=1e-15)
+
+
+def test_rho_rescaled_copies_of_one_column_is_k():
+    # positive multiples of one column: G = 1 1^T, rho = k after one step
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=30)
+    A = np.outer(x, rng.uniform(0.1, 5.0, size=9))
+    r, hist, kl = O.rho(_csc_matrix(A), 3)
+    assert kl == 9
+    np.testing.assert_allclose(hist, 9.0, rtol=1e-13)
+
+
+def test_rho_duplicate_blocks_converges_to_largest_block():
+    # blocks of 3, 5 and 2 copies on disjoint rows: eigenvalues 3, 5, 2
+    rng = np.random.default_rng(5)
+    A = np.zeros((30, 10))
+    for rows, cols in ((slice(0, 10), range(0, 3)), (slice(10, 20), range(3, 8)),
+                       (slice(20, 30), range(8, 10))):
+        x = rng.normal(size=10)
+        for j in cols:
+            A[rows, j] = x * rng.uniform(0.5, 2.0)
+    r, hist, _ = O.rho(_csc_matrix(A), 200)
+    assert abs(r - 5.0) < 1e-12
+    assert hist[0] < 5.0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rho_matches_symmetric_eigensolver(seed):
+    # positive tf-idf-like values: a Perron root with a wide gap, so the
+    # iteration converges to the library eigenvalue
+    rng = np.random.default_rng(seed)
+    A = np.exp(rng.normal(size=(25, 15))) * (rng.random((25, 15)) < 0.5)
+    r, _, _ = O.rho(_csc_matrix(A), 400)
+    assert abs(r - _normalised_gram_rho(A)) <= 1e-10 * r
+
+
+def test_rho_history_is_a_monotone_lower_bound():
+    # for a symmetric PSD G the ratios ||G^t v|| / ||G^(t-1) v|| never
+    # decrease and never exceed the largest eigenvalue
+    rng = np.random.default_rng(7)
+    A = rng.normal(size=(20, 30)) * (rng.random((20, 30)) < 0.3)
+    _, hist, _ = O.rho(_csc_matrix(A), 60)
+    top = _normalised_gram_rho(A)
+    assert np.all(np.diff(hist) >= -1e-12 * top)
+    assert np.all(hist <= top * (1 + 1e-12))
+    assert hist[-1] > 0.99 * top
+
+
+def test_rho_ignores_empty_columns_and_pstar_clamps():
+    rng = np.random.default_rng(8)
+    A = np.exp(rng.normal(size=(25, 15))) * (rng.random((25, 15)) < 0.5)
+    A[:, [2, 7]] = 0.0
+    Z = np.concatenate([A, np.zeros((25, 6))], axis=1)
+    r1, h1, k1 = O.rho(_csc_matrix(A), 20)
+    r2, h2, k2 = O.rho(_csc_matrix(Z), 20)
+    assert k1 == k2 == 13 and r1 == r2
+    assert O.pstar(1000, 2.0) == 250 and O.pstar(1000, 3.0) == 166
+    assert O.pstar(10, 100.0) == 1 and O.pstar(10**7, 1.0) == 1024 and O.pstar(5, 0.0) == 1
