@@ -388,7 +388,9 @@ def bench_serve(args):
         reqs.append((P, X, y, r.lambda_ratio * lm))
 
     def params(P, lam):
-        return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=512, seed=11, tol=1e-6,
+        # |J| = floor(k_live / (2 rho)) clamped to [1, 1024], rho from 20 power
+        # iterations on the normalised Gram matrix (section 4.1's P*)
+        return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=0, seed=11, tol=1e-6,
                              max_epochs=20000, flags=G.USE_GRAPH)
 
     need = max(G.workspace_bytes(X, params(P, 1.0)) for P, X, y, lm in pool)
@@ -442,6 +444,9 @@ def bench_serve(args):
                                 "latency_p50_s": float(np.percentile(lat1, 50)),
                                 "latency_p99_s": float(np.percentile(lat1, 99))},
         "all_converged": bool(all(r["stats"]["converged"] for r in res)),
+        "select_size_from_rho": {"min": int(min(r["stats"]["select_size"] for r in res)),
+                                 "median": float(np.median([r["stats"]["select_size"] for r in res])),
+                                 "max": int(max(r["stats"]["select_size"] for r in res))},
     }
 
 

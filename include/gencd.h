@@ -88,7 +88,9 @@ typedef struct {
   int32_t loss;          /* gencd_loss */
   int32_t rule;          /* gencd_rule */
   double lambda;         /* lambda >= 0 of Eq. (1) */
-  int64_t select_size;   /* |J| (Shotgun, Thread-Greedy) */
+  int64_t select_size;   /* |J| (Shotgun, Thread-Greedy); 0: floor(k_live / (2 rho))
+                            clamped to [1, 1024], rho estimated by 20 power
+                            iterations (gencd_estimate_rho; section 4.1) */
   int64_t block;         /* B, proposals per accepting block (Thread-Greedy) */
   uint64_t seed;         /* seed of the per-epoch selection permutation */
   double kkt_tol;        /* stop when max_j KKT violation <= kkt_tol ... */
@@ -98,8 +100,10 @@ typedef struct {
   uint32_t flags;        /* GENCD_* flags */
   const int32_t *color;  /* COLORING: device int32[k] colours (gencd_color) */
   int32_t num_colors;    /* COLORING: number of colours */
-  int32_t piece;         /* nnz per work piece; 0 = library default */
-  int32_t group;         /* lanes per piece (8, 16, 32 or 64); 0 = default */
+  int32_t piece;         /* nonzeros per piece of a long column (multiple of 64,
+                            64..2^22); 0 = library default */
+  int32_t group;         /* lanes per short column (4, 8, 16 or 32); columns of
+                            at most 4 * group nonzeros are short; 0 = default */
 } gencd_params;
 
 /* Host-side statistics filled by the solve calls. */
@@ -125,6 +129,8 @@ typedef struct {
   int64_t prof_launches;
   double prof_kernel_ms;
   double prof_bytes;
+  double rho;             /* spectral-radius estimate when |J| came from it, else 0 */
+  int64_t select_size;    /* |J| used by the solve */
 } gencd_stats;
 
 const char *gencd_status_string(int status);
@@ -221,6 +227,34 @@ typedef struct {
 int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, int32_t epochs,
                    const char *cache_path, float *w_scratch, void *ws, size_t ws_bytes,
                    hipStream_t stream, gencd_schedule *out);
+
+/* ------------------------------------------------------------------------
+ * Spectral radius of the column-normalised Gram matrix (section 4.1: Shotgun
+ * is guaranteed to converge with at most P* = k / (2 rho) coordinates per
+ * iteration, rho the largest eigenvalue of X^T X for unit-norm columns).
+ *
+ * rho is estimated by power iteration on G = D^{-1/2} X^T X D^{-1/2},
+ * D = diag(X^T X), restricted to the non-empty columns, starting from the
+ * unit vector with equal entries on those columns: u = G v, rho_t = ||u||,
+ * v = u / rho_t.  FP64 on the device.  Each rho_t is a lower bound of rho and
+ * the sequence does not decrease.
+ *
+ *   p            schedule (piece, group) and flags (GENCD_VALIDATE_DEVICE)
+ *                are read; loss, lambda and rule are ignored.  May be NULL.
+ *   iters        1..1024
+ *   rho_hist     host double[iters]: rho_t after iteration t (0 from the
+ *                first iteration with G v = 0 on)
+ *   k_live       host, may be NULL: number of non-empty columns
+ *   select_size  host, may be NULL: floor(k_live / (2 rho_iters)) clamped to
+ *                [1, 1024], the |J| gencd_solve takes for select_size 0
+ *   ws           device workspace of gencd_rho_workspace_bytes bytes
+ * Synchronises the stream.  Errors: INVALID_ARG, BAD_MATRIX (with
+ * VALIDATE_DEVICE), WORKSPACE, UNSUPPORTED, HIP.
+ * ------------------------------------------------------------------------ */
+int gencd_rho_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out_bytes);
+int gencd_estimate_rho(const gencd_csc *X, const gencd_params *p, int32_t iters, double *rho_hist,
+                       int64_t *k_live, int64_t *select_size, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Continuous-batching server.  Requests are whole solves of Eq. (1); they

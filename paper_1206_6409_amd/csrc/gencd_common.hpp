@@ -195,13 +195,20 @@ struct Ws {
   double *z64, *r64;     // [n]
   double *g64;           // [k]
   double *red;           // [16] reductions, counters, flags; [12] epoch counter
+  // spectral-radius estimate (only when |J| is chosen from it)
+  double *rho_dinv;      // [k] 1/||X_j|| (0 for empty columns)
+  double *rho_x;         // [k] D^{-1/2} v, the scaled iterate
+  double *rho_hist;      // [kRhoMaxIters] ||G v||^2 per iteration
   size_t scan_part_len;
   int64_t max_lpieces;
 };
 
 int64_t max_lpieces_for(int64_t k, int64_t nnz, int piece, int short_max);
-size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, void *base,
-                        Ws *ws);
+constexpr int kRhoIters = 20;       // power iterations behind an automatic |J|
+constexpr int kRhoMaxIters = 1024;  // cap for the standalone estimate
+constexpr int64_t kRhoSelectCap = 1024;  // automatic |J| is clamped to [1, this]
+size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, bool rho,
+                        void *base, Ws *ws);
 size_t scan_partials_for(int64_t len);
 
 // Exclusive scan of int32 counts: out[0..len] (out[len] = total).

@@ -923,9 +923,9 @@ __global__ __launch_bounds__(kBlock) void k_check_zero(double *z64, int64_t n, d
   if (tid < 8) red[tid] = 0ull;
 }
 
-template <int G>
+template <int G, typename WT>
 __device__ __forceinline__ void spmv_piece(const int32_t *row_idx, const float *val, const int4 d,
-                                           const float *w, double *z64, int lane) {
+                                           const WT *w, double *z64, int lane) {
   const double wj = double(w[d.y]);
   if (wj == 0.0) return;
   const int64_t beg = desc_beg(d);
@@ -945,18 +945,21 @@ __device__ __forceinline__ void spmv_piece(const int32_t *row_idx, const float *
   }
 }
 
-template <int GS>
+// z64 += X w over all pieces (w float for the check, double for the
+// spectral-radius iteration)
+template <int GS, typename WT>
 __global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, const float *val,
                                                         const int4 *ds, int32_t ns,
                                                         const int4 *dl, int32_t nlp, int32_t nl_req,
-                                                        const float *w, double *z64) {
+                                                        const WT *w, double *z64) {
   const Roles r = roles(nl_req);
   if (r.wave < r.nl) {
-    for (int64_t q = r.wave; q < nlp; q += r.nl) spmv_piece<kWave>(row_idx, val, dl[q], w, z64, r.wl);
+    for (int64_t q = r.wave; q < nlp; q += r.nl)
+      spmv_piece<kWave, WT>(row_idx, val, dl[q], w, z64, r.wl);
   } else {
     const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
     for (int64_t q = (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < ns; q += step)
-      spmv_piece<GS>(row_idx, val, ds[q], w, z64, r.wl & (GS - 1));
+      spmv_piece<GS, WT>(row_idx, val, ds[q], w, z64, r.wl & (GS - 1));
   }
 }
 
@@ -1125,8 +1128,8 @@ int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const
   hipLaunchKernelGGL(k_check_zero, dim3(grid_for(nk)), dim3(kBlock), 0, s, ws.z64, X->n, ws.g64,
                      X->k, red);
   if (w && n_short + n_lpieces > 0)
-    hipLaunchKernelGGL(k_check_spmv<8>, dim3(blocks), dim3(kBlock), 0, s, X->row_idx, X->val,
-                       ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, w, ws.z64);
+    hipLaunchKernelGGL((k_check_spmv<8, float>), dim3(blocks), dim3(kBlock), 0, s, X->row_idx,
+                       X->val, ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, w, ws.z64);
   hipLaunchKernelGGL(k_check_rows, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
                      ws.z64, ws.r64, resync ? ws.z_hi : nullptr, ws.z_lo, ws.red);
   if (n_short + n_lpieces > 0)
@@ -1136,6 +1139,89 @@ int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const
                      lam, 1.0 / double(X->n), red);
   hipLaunchKernelGGL(k_check_dual, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
                      ws.r64, lam, red);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Spectral radius of G = D^{-1/2} X^T X D^{-1/2} (D = diag(X^T X), non-empty
+// columns) by power iteration from the unit vector with equal entries on the
+// non-empty columns (section 4.1: Shotgun is safe up to k / (2 rho) columns
+// per iteration).  FP64 throughout.  Per iteration:
+//   s = X x,  x = D^{-1/2} v          (k_check_spmv<8, double>, into z64)
+//   U = X^T s                          (k_check_cols<8>, into g64)
+//   hist[t] = ||D^{-1/2} U||^2         (k_rho_norm)
+//   x = D^{-1/2} (D^{-1/2} U / rho_t), U = 0, s = 0   (k_rho_scale)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_rho_init(int64_t k, int64_t n, double *ss_u,
+                                                      double *dinv, double *x, double v0,
+                                                      double *s64, double *hist, int iters) {
+  const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t nt = int64_t(gridDim.x) * kBlock;
+  for (int64_t j = tid; j < k; j += nt) {
+    const double q = ss_u[j];  // sum of squares of column j
+    const double d = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    dinv[j] = d;
+    x[j] = d * v0;
+    ss_u[j] = 0.0;
+  }
+  for (int64_t i = tid; i < n; i += nt) s64[i] = 0.0;
+  for (int64_t t = tid; t < iters; t += nt) hist[t] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rho_norm(int64_t k, const double *dinv, const double *u,
+                                                      double *hist_t) {
+  __shared__ double sred[kBlock];
+  double acc = 0.0;
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock) {
+    const double v = dinv[j] * u[j];
+    acc += v * v;
+  }
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(hist_t, sred[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rho_scale(int64_t k, int64_t n, const double *dinv,
+                                                       double *u, double *x, double *s64,
+                                                       const double *hist_t) {
+  const double rho = sqrt(*hist_t);
+  const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t nt = int64_t(gridDim.x) * kBlock;
+  for (int64_t j = tid; j < k; j += nt) {
+    const double v = dinv[j] * u[j];
+    x[j] = rho > 0.0 ? dinv[j] * (v / rho) : 0.0;
+    u[j] = 0.0;
+  }
+  for (int64_t i = tid; i < n; i += nt) s64[i] = 0.0;
+}
+
+int launch_rho(const gencd_csc *X, int32_t n_short, int32_t n_lpieces, const Ws &ws, int64_t k_live,
+               int iters, hipStream_t s) {
+  if (!ws.rho_dinv || iters < 1 || iters > kRhoMaxIters || k_live <= 0) return GENCD_ERR_INVALID_ARG;
+  const int64_t nk = X->n > X->k ? X->n : X->k;
+  unsigned blocks;
+  int32_t nl;
+  two_class_grid(n_short, n_lpieces, 8, &blocks, &nl);
+  hipLaunchKernelGGL(k_rho_init, dim3(grid_for(nk)), dim3(kBlock), 0, s, X->k, X->n, ws.g64,
+                     ws.rho_dinv, ws.rho_x, 1.0 / sqrt(double(k_live)), ws.z64, ws.rho_hist, iters);
+  for (int t = 0; t < iters; ++t) {
+    if (n_short + n_lpieces > 0) {
+      hipLaunchKernelGGL((k_check_spmv<8, double>), dim3(blocks), dim3(kBlock), 0, s, X->row_idx,
+                         X->val, ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, ws.rho_x,
+                         ws.z64);
+      hipLaunchKernelGGL(k_check_cols<8>, dim3(blocks), dim3(kBlock), 0, s, X->row_idx, X->val,
+                         ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, ws.z64, ws.g64);
+    }
+    hipLaunchKernelGGL(k_rho_norm, dim3(grid_for(X->k, 256)), dim3(kBlock), 0, s, X->k, ws.rho_dinv,
+                       ws.g64, ws.rho_hist + t);
+    hipLaunchKernelGGL(k_rho_scale, dim3(grid_for(nk)), dim3(kBlock), 0, s, X->k, X->n, ws.rho_dinv,
+                       ws.g64, ws.rho_x, ws.z64, ws.rho_hist + t);
+  }
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 

@@ -57,6 +57,11 @@ int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s);
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
                      int64_t long_bound, int64_t nblocks_accept, hipStream_t s,
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Power-iteration estimate of the normalised Gram spectral radius; needs the
+// column sums of squares in ws.g64 (left there by launch_curvature) and the
+// rho arrays of the workspace.  Squared norms land in ws.rho_hist[0..iters).
+int launch_rho(const gencd_csc *X, int32_t n_short, int32_t n_lpieces, const Ws &ws, int64_t k_live,
+               int iters, hipStream_t s);
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
                  int32_t n_short, int32_t n_lpieces, const Ws &ws, bool resync, hipStream_t s);
 int launch_renorm(int64_t n, float *z_hi, float *z_lo, hipStream_t s);

@@ -45,8 +45,8 @@ struct Carver {
 };
 }  // namespace
 
-size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, void *base,
-                        Ws *ws) {
+size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, bool rho,
+                        void *base, Ws *ws) {
   Carver c{static_cast<char *>(base)};
   Ws w{};
   const int64_t ml = max_lpieces_for(k, nnz, piece, short_max);
@@ -84,6 +84,11 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.r64 = c.take<double>(n);
   w.g64 = c.take<double>(k);
   w.red = c.take<double>(16);
+  if (rho) {
+    w.rho_dinv = c.take<double>(k);
+    w.rho_x = c.take<double>(k);
+    w.rho_hist = c.take<double>(kRhoMaxIters);
+  }
   if (ws) *ws = w;
   return c.off + kAlign;
 }
@@ -96,6 +101,11 @@ bool csc_ok(const gencd_csc *X) {
   if (!X->col_ptr) return false;
   if (X->nnz > 0 && (!X->row_idx || !X->val)) return false;
   return true;
+}
+
+// Shotgun and Thread-Greedy with select_size 0 take |J| from the estimate.
+bool wants_rho(const gencd_params *p) {
+  return p && (p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY) && p->select_size == 0;
 }
 
 int resolve_schedule(const gencd_params *p, int *piece, int *group) {
@@ -114,7 +124,7 @@ int params_ok(const gencd_params *p, bool need_rule) {
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return GENCD_ERR_INVALID_ARG;
   if (!need_rule) return GENCD_OK;
   if (p->rule < GENCD_CYCLIC || p->rule > GENCD_COLORING) return GENCD_ERR_INVALID_ARG;
-  if ((p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY) && p->select_size <= 0)
+  if ((p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY) && p->select_size < 0)
     return GENCD_ERR_INVALID_ARG;
   if (p->rule == GENCD_THREAD_GREEDY && p->block <= 0) return GENCD_ERR_INVALID_ARG;
   if (p->rule == GENCD_COLORING && (!p->color || p->num_colors <= 0)) return GENCD_ERR_INVALID_ARG;
@@ -152,26 +162,40 @@ struct Setup {
   int piece = kDefaultPiece, group = kDefaultGroup;
   int32_t n_short = 0, n_lpieces = 0;
   int64_t k_live = 0;
+  std::vector<double> rho_hist;  // spectral-radius estimate after each power iteration
+  double rho = 0.0;
 };
 
-// Preprocessing (row a1): validation, piece decomposition, live columns and
-// curvature.  Writes only the workspace.
+// |J| = floor(k_live / (2 rho)) clamped to [1, kRhoSelectCap] (section 4.1).
+int64_t pstar_of(int64_t k_live, double rho) {
+  if (!(rho > 0.0)) return 1;
+  const double q = std::floor(double(k_live) / (2.0 * rho));
+  if (q < 1.0) return 1;
+  if (q > double(kRhoSelectCap)) return kRhoSelectCap;
+  return int64_t(q);
+}
+
+// Preprocessing: validation, piece decomposition, live columns, curvature
+// and (rho_iters > 0) the spectral-radius estimate.  Writes only the
+// workspace.  y may be null only when need_y is false (no label check).
 int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, void *ws_base,
-          size_t ws_bytes, bool validate_matrix, hipStream_t s, Setup *out) {
-  if (!csc_ok(X) || !y) return GENCD_ERR_INVALID_ARG;
+          size_t ws_bytes, bool validate_matrix, hipStream_t s, Setup *out, int rho_iters = 0,
+          bool need_y = true) {
+  if (!csc_ok(X) || (need_y && !y)) return GENCD_ERR_INVALID_ARG;
+  if (rho_iters < 0 || rho_iters > kRhoMaxIters) return GENCD_ERR_INVALID_ARG;
   int st = resolve_schedule(p, &out->piece, &out->group);
   if (st) return st;
   const int smax = short_max_of(out->group);
   if (max_lpieces_for(X->k, X->nnz, out->piece, smax) >= INT32_MAX ||
       X->nnz >= (int64_t(1) << 32))
     return GENCD_ERR_UNSUPPORTED;
-  size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, smax, nullptr, nullptr);
+  size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, smax, rho_iters > 0, nullptr, nullptr);
   if (!ws_base || ws_bytes < need) return GENCD_ERR_WORKSPACE;
   // align the carve base
   char *base = static_cast<char *>(ws_base);
   size_t mis = reinterpret_cast<uintptr_t>(base) % kAlign;
   if (mis) base += kAlign - mis;
-  workspace_layout(X->n, X->k, X->nnz, out->piece, smax, base, &out->ws);
+  workspace_layout(X->n, X->k, X->nnz, out->piece, smax, rho_iters > 0, base, &out->ws);
   const Ws &w = out->ws;
   st = fill_f64(w.red, 16, 0.0, s);
   if (st) return st;
@@ -193,6 +217,20 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
   out->n_lpieces = host[2];
   st = launch_curvature(X, loss, out->n_short, out->n_lpieces, w, s);
   if (st) return st;
+  if (rho_iters > 0) {
+    // power iteration; reads the column sums of squares that the curvature
+    // pass left in g64
+    out->rho_hist.assign(size_t(rho_iters), 0.0);
+    if (out->k_live > 0) {
+      st = launch_rho(X, out->n_short, out->n_lpieces, w, out->k_live, rho_iters, s);
+      if (st) return st;
+      GENCD_HIP(hipMemcpyAsync(out->rho_hist.data(), w.rho_hist, sizeof(double) * size_t(rho_iters),
+                               hipMemcpyDeviceToHost, s));
+      GENCD_HIP(hipStreamSynchronize(s));
+      for (double &h : out->rho_hist) h = std::sqrt(h);
+    }
+    out->rho = out->rho_hist.back();
+  }
   st = fill_f32(w.gacc, w.max_lpieces, 0.0f, s);
   if (st) return st;
   return fill_i32(w.acc, X->k, 0, s);
@@ -381,7 +419,8 @@ int path_setup(const gencd_csc *X, const float *y, const gencd_params *p, void *
   out->n_short = su.n_short;
   out->n_lpieces = su.n_lpieces;
   out->k_live = su.k_live;
-  *used = workspace_layout(X->n, X->k, X->nnz, su.piece, short_max_of(su.group), nullptr, nullptr) +
+  *used = workspace_layout(X->n, X->k, X->nnz, su.piece, short_max_of(su.group), false, nullptr,
+                           nullptr) +
           kAlign;
   return GENCD_OK;
 }
@@ -400,7 +439,8 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   if (st) return st;
   if (!w) return GENCD_ERR_INVALID_ARG;
   Setup su;
-  st = setup(X, y, p->loss, p, ws_base, ws_bytes, (p->flags & GENCD_VALIDATE_DEVICE) != 0, s, &su);
+  st = setup(X, y, p->loss, p, ws_base, ws_bytes, (p->flags & GENCD_VALIDATE_DEVICE) != 0, s, &su,
+             wants_rho(p) ? kRhoIters : 0);
   if (st) return st;
   const Ws &ws = su.ws;
   const int rule = p->rule;
@@ -440,9 +480,12 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   int64_t S;
   if (rule == GENCD_CYCLIC || rule == GENCD_STOCHASTIC) S = 1;
   else if (rule == GENCD_GREEDY) S = k_live;
+  else if (p->select_size == 0) S = pstar_of(k_live, su.rho);
   else S = p->select_size;
   if (S > k_live) S = k_live;
   if (S < 1) S = 1;
+  st_out->rho = su.rho;
+  st_out->select_size = S;
   const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
   int64_t max_class = 0;
   for (int32_t sz : cls_sizes) max_class = std::max<int64_t>(max_class, sz);
@@ -715,7 +758,8 @@ int gencd_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out
   int piece, group;
   int st = resolve_schedule(p, &piece, &group);
   if (st) return st;
-  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), nullptr, nullptr) +
+  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), wants_rho(p),
+                               nullptr, nullptr) +
                kAlign;
   return GENCD_OK;
 }
@@ -746,6 +790,35 @@ int gencd_check(const gencd_csc *X, const float *y, int32_t loss, double lambda,
                 hipStream_t stream) {
   if (!w) return GENCD_ERR_INVALID_ARG;
   return check_impl(X, y, loss, lambda, w, z64, g64, stats, ws, ws_bytes, stream);
+}
+
+int gencd_rho_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out_bytes) {
+  if (!out_bytes || !X || X->n <= 0 || X->k <= 0 || X->nnz < 0) return GENCD_ERR_INVALID_ARG;
+  int piece, group;
+  int st = resolve_schedule(p, &piece, &group);
+  if (st) return st;
+  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), true, nullptr,
+                                nullptr) +
+               kAlign;
+  return GENCD_OK;
+}
+
+int gencd_estimate_rho(const gencd_csc *X, const gencd_params *p, int32_t iters, double *rho_hist,
+                       int64_t *k_live, int64_t *select_size, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  (void)hipGetLastError();
+  if (!rho_hist || iters < 1 || iters > kRhoMaxIters) return GENCD_ERR_INVALID_ARG;
+  gencd_params q{};
+  if (p) q = *p;
+  q.loss = GENCD_SQUARED;  // no labels: nothing to validate
+  Setup su;
+  int st = setup(X, nullptr, GENCD_SQUARED, &q, ws, ws_bytes, (q.flags & GENCD_VALIDATE_DEVICE) != 0,
+                 stream, &su, iters, false);
+  if (st) return st;
+  for (int32_t t = 0; t < iters; ++t) rho_hist[t] = su.rho_hist[size_t(t)];
+  if (k_live) *k_live = su.k_live;
+  if (select_size) *select_size = pstar_of(su.k_live, su.rho);
+  return GENCD_OK;
 }
 
 int gencd_select_perm(int64_t m, uint64_t seed, int64_t epoch, int32_t *out, hipStream_t stream) {

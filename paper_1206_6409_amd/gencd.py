@@ -51,7 +51,7 @@ class Stats(C.Structure):
                 ("seconds", C.c_double),
                 ("nnz_w", C.c_int64), ("converged", C.c_int32), ("num_colors", C.c_int32),
                 ("prof_launches", C.c_int64), ("prof_kernel_ms", C.c_double),
-                ("prof_bytes", C.c_double)]
+                ("prof_bytes", C.c_double), ("rho", C.c_double), ("select_size", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,6 +73,9 @@ _SIGS = {
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                               C.c_void_p]),
     "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "gencd_rho_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_estimate_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "gencd_color_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gencd_path_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "gencd_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_char_p,
@@ -194,6 +197,29 @@ def lambda_max(X: Matrix, y: torch.Tensor, loss, ws=None):
     _check(lib().gencd_lambda_max(X.ref, _ptr(y), int(loss), C.byref(out), _ptr(ws), ws.numel(),
                                   _stream()), "gencd_lambda_max")
     return out.value
+
+
+@dataclass
+class RhoResult:
+    rho: float            # estimate after the last iteration
+    history: list         # estimate after each iteration
+    k_live: int
+    select_size: int      # floor(k_live / (2 rho)) clamped to [1, 1024]
+
+
+def estimate_rho(X: Matrix, iters=20, params=None):
+    """Power-iteration estimate of the largest eigenvalue of the
+    column-normalised Gram matrix (section 4.1's P* = k / (2 rho))."""
+    pp = C.byref(params) if params is not None else None
+    nb = C.c_size_t()
+    _check(lib().gencd_rho_workspace_bytes(X.ref, pp, C.byref(nb)), "gencd_rho_workspace_bytes")
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=X.col_ptr.device)
+    hist = (C.c_double * int(iters))()
+    kl, sel = C.c_int64(), C.c_int64()
+    _check(lib().gencd_estimate_rho(X.ref, pp, int(iters), hist, C.byref(kl), C.byref(sel),
+                                    _ptr(ws), ws.numel(), _stream()), "gencd_estimate_rho")
+    h = list(hist)
+    return RhoResult(h[-1], h, kl.value, sel.value)
 
 
 @dataclass

@@ -64,7 +64,7 @@ def test_workspace_bytes_host_only():
 
 @pytest.mark.parametrize("field,value", [
     ("loss", 7), ("lam", -1.0), ("lam", float("nan")), ("rule", 9),
-    ("select_size", 0), ("max_epochs", -1),
+    ("select_size", -1), ("max_epochs", -1),
 ])
 def test_solve_rejects_bad_params_before_device_work(field, value):
     X = _fake_matrix()
@@ -102,3 +102,24 @@ def test_solve_rejects_null_and_bad_shapes():
 def test_select_perm_rejects_bad_sizes():
     assert G.lib().gencd_select_perm(-1, 0, 0, None, None) == -1
     assert G.lib().gencd_select_perm(5, 0, 0, None, None) == -1
+
+
+def test_rho_host_validation():
+    X = _fake_matrix(1000, 500, 4000)
+    out = C.c_size_t()
+    base = C.c_size_t()
+    assert G.lib().gencd_rho_workspace_bytes(C.byref(X), None, C.byref(out)) == 0
+    assert G.lib().gencd_workspace_bytes(C.byref(X), None, C.byref(base)) == 0
+    assert out.value >= base.value + 2 * 8 * 500  # 1/||X_j|| and the iterate
+    # automatic |J| needs the same extra arrays in the solve workspace
+    p = G.make_params(1, 0.1, rule=G.SHOTGUN, select_size=0)
+    auto = C.c_size_t()
+    assert G.lib().gencd_workspace_bytes(C.byref(X), C.byref(p), C.byref(auto)) == 0
+    assert auto.value == out.value
+    hist = (C.c_double * 4)()
+    for iters in (0, 1025, -3):
+        assert G.lib().gencd_estimate_rho(C.byref(X), None, iters, hist, None, None, None, 0,
+                                          None) == -1
+    assert G.lib().gencd_estimate_rho(C.byref(X), None, 4, None, None, None, None, 0, None) == -1
+    bad = _fake_matrix(0, 5, 0)
+    assert G.lib().gencd_rho_workspace_bytes(C.byref(bad), None, C.byref(out)) == -1
