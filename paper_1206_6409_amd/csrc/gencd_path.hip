@@ -77,58 +77,65 @@ struct PathArgs {
   float *delta;
 };
 
-// One group of B lanes per column; the column's entries are staged in LDS
-// (B at a time) and broadcast to the lanes.
+// One 256-thread block per column of the window: thread (r, s) = (row lane,
+// slot), s = threadIdx % B, r = threadIdx / B, R = 256 / B row lanes.  Row
+// lane r takes the column entries r, r + R, ...; for each it reads the
+// B-wide row Z[row][0..B) (one coalesced segment per row lane) and the
+// entry itself (the same address for all B slot lanes).  Loads are issued in
+// batches of R * PU entries so that a short column costs one round of
+// dependent loads.  Partial sums are reduced across row lanes in a fixed
+// order (shuffles inside a wave, then LDS across the waves), so the result
+// does not depend on scheduling.
+template <int B>
+struct PathShape {
+  static constexpr int R = kBlock / B;   // row lanes per column
+  static constexpr int PU = 32 / R > 1 ? 32 / R : 2;  // entries per row lane per batch
+  static constexpr int NW = kBlock / kWave;
+};
+
 template <int B>
 __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
-  constexpr int GPB = kBlock / B;  // groups per block
-  __shared__ int32_t srow[GPB][B];
-  __shared__ float sval[GPB][B];
-  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  using SH = PathShape<B>;
+  constexpr int R = SH::R, PU = SH::PU, NW = SH::NW;
+  __shared__ float sred[NW][B];
+  const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
   const int64_t npos = a.win_hi - a.win_lo;
-  const bool on = a.active[s] != 0;
-  for (int64_t p0 = int64_t(blockIdx.x) * GPB; p0 < npos; p0 += int64_t(gridDim.x) * GPB) {
-    const int64_t p = p0 + grp;
-    const bool have = p < npos;
-    int32_t j = 0;
-    int64_t cb = 0, ce = 0;
-    if (have) {
-      j = a.col_of_pos[a.win_lo + p];
-      cb = a.col_ptr[j];
-      ce = a.col_ptr[j + 1];
-    }
+  for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
+    const int32_t j = a.col_of_pos[a.win_lo + p];
+    const int64_t cb = a.col_ptr[j], ce = a.col_ptr[j + 1];
     float acc = 0.0f;
-    for (int64_t base = cb; base < ce; base += B) {
-      const int64_t e = base + s;
-      srow[grp][s] = e < ce ? a.row_idx[e] : -1;
-      sval[grp][s] = e < ce ? a.val[e] : 0.0f;
-      __builtin_amdgcn_wave_barrier();
-      const int cnt = int(ce - base < B ? ce - base : B);
-      int u = 0;
-      for (; u + kUnroll <= cnt; u += kUnroll) {
-        float zh[kUnroll], zl[kUnroll], yy[kUnroll], vv[kUnroll];
+    for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
+      int32_t ri[PU];
+      float vv[PU];
 #pragma unroll
-        for (int q = 0; q < kUnroll; ++q) {
-          const int32_t i = srow[grp][u + q];
-          vv[q] = sval[grp][u + q];
-          zh[q] = a.zh[int64_t(i) * B + s];
-          zl[q] = a.zl[int64_t(i) * B + s];
-          yy[q] = a.y[i];
-        }
+      for (int q = 0; q < PU; ++q) {
+        const int64_t e = base + int64_t(q) * R + r;
+        ri[q] = e < ce ? a.row_idx[e] : -1;
+        vv[q] = e < ce ? a.val[e] : 0.0f;
+      }
+      float zh[PU], zl[PU], yy[PU];
 #pragma unroll
-        for (int q = 0; q < kUnroll; ++q) acc += vv[q] * dloss_f32(a.loss, yy[q], zh[q] + zl[q]);
+      for (int q = 0; q < PU; ++q) {
+        const int64_t i = ri[q] >= 0 ? ri[q] : 0;  // row 0 stands in for padding
+        zh[q] = a.zh[i * B + s];
+        zl[q] = a.zl[i * B + s];
+        yy[q] = a.y[i];
       }
-      for (; u < cnt; ++u) {
-        const int32_t i = srow[grp][u];
-        acc += sval[grp][u] *
-               dloss_f32(a.loss, a.y[i], a.zh[int64_t(i) * B + s] + a.zl[int64_t(i) * B + s]);
-      }
-      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int q = 0; q < PU; ++q)
+        if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yy[q], zh[q] + zl[q]);
     }
-    if (have) {
+#pragma unroll
+    for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
+    if (int(threadIdx.x) % kWave < B) sred[threadIdx.x / kWave][s] = acc;
+    __syncthreads();
+    if (int(threadIdx.x) < B) {
+      float g = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) g += sred[w][s];
       float d = 0.0f;
-      if (on) {
-        const float g = acc / a.n_f;
+      if (a.active[s] != 0) {
+        g /= a.n_f;
         const float wj = a.W[int64_t(j) * B + s];
         float ph;
         propose_f32(g, a.c[j], wj, a.lam[s], d, ph);
@@ -136,37 +143,37 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
       }
       a.delta[p * B + s] = d;
     }
+    __syncthreads();  // sred is reused by the next column
   }
 }
 
+// Same thread shape: row lane r scatters delta_s * x_ij of its entries into
+// the low words Z_lo[row][s] (non-returning float atomics; the high words
+// absorb them at the end of the epoch).
 template <int B>
 __global__ __launch_bounds__(kBlock) void k_path_update(PathArgs a) {
-  constexpr int GPB = kBlock / B;
-  __shared__ int32_t srow[GPB][B];
-  __shared__ float sval[GPB][B];
-  const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  using SH = PathShape<B>;
+  constexpr int R = SH::R, PU = SH::PU;
+  const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
   const int64_t npos = a.win_hi - a.win_lo;
-  for (int64_t p0 = int64_t(blockIdx.x) * GPB; p0 < npos; p0 += int64_t(gridDim.x) * GPB) {
-    const int64_t p = p0 + grp;
-    const bool have = p < npos;
-    int64_t cb = 0, ce = 0;
-    float d = 0.0f;
-    if (have) {
-      const int32_t j = a.col_of_pos[a.win_lo + p];
-      cb = a.col_ptr[j];
-      ce = a.col_ptr[j + 1];
-      d = a.delta[p * B + s];
-    }
-    for (int64_t base = cb; base < ce; base += B) {
-      const int64_t e = base + s;
-      srow[grp][s] = e < ce ? a.row_idx[e] : -1;
-      sval[grp][s] = e < ce ? a.val[e] : 0.0f;
-      __builtin_amdgcn_wave_barrier();
-      const int cnt = int(ce - base < B ? ce - base : B);
-      if (d != 0.0f)
-        for (int u = 0; u < cnt; ++u)
-          atomicAdd(&a.zl[int64_t(srow[grp][u]) * B + s], d * sval[grp][u]);
-      __builtin_amdgcn_wave_barrier();
+  for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
+    const float d = a.delta[p * B + s];
+    const int32_t j = a.col_of_pos[a.win_lo + p];
+    const int64_t cb = a.col_ptr[j], ce = a.col_ptr[j + 1];
+    for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
+      int32_t ri[PU];
+      float vv[PU];
+#pragma unroll
+      for (int q = 0; q < PU; ++q) {
+        const int64_t e = base + int64_t(q) * R + r;
+        ri[q] = e < ce ? a.row_idx[e] : -1;
+        vv[q] = e < ce ? a.val[e] : 0.0f;
+      }
+      if (d != 0.0f) {
+#pragma unroll
+        for (int q = 0; q < PU; ++q)
+          if (ri[q] >= 0) atomicAdd(&a.zl[int64_t(ri[q]) * B + s], d * vv[q]);
+      }
     }
   }
 }
@@ -402,7 +409,6 @@ template <int B>
 int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const double *lambdas,
              int32_t L, float *W_out, char *path_base, const PathSetup &su, hipStream_t s,
              gencd_stats *stats) {
-  constexpr int GPB = kBlock / B;
   const int64_t n = X->n, k = X->k, k_live = su.k_live;
   int64_t S = std::min<int64_t>(p->select_size, std::max<int64_t>(k_live, 1));
   PathWs w{};
@@ -542,7 +548,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       a.win_lo = int32_t(t * S);
       a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
       const int64_t npos = a.win_hi - a.win_lo;
-      const unsigned grid = unsigned(std::min<int64_t>((npos + GPB - 1) / GPB, 16384));
+      const unsigned grid = unsigned(std::min<int64_t>(npos > 0 ? npos : 1, 65536));
       hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, s, a);
       hipLaunchKernelGGL(k_path_update<B>, dim3(grid), dim3(kBlock), 0, s, a);
     }
