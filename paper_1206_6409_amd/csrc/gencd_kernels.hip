@@ -594,7 +594,9 @@ __device__ __forceinline__ float split_sum(const float *part, int32_t pf, int32_
 }
 
 // Propose of one piece by a group of G lanes.
-template <int G, int MODE>
+// U entries per lane per batch: long pieces (G = 64) take 8 so that a
+// 512-entry piece is one round of dependent loads; short groups take 4.
+template <int G, int MODE, int U = kUnroll>
 __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc, int64_t q,
                                               int lane, int32_t P0) {
   const int64_t beg = desc_beg(dsc);
@@ -607,25 +609,25 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
     cj = a.c[j];
   }
   float s = 0.0f;
-  for (int32_t base = 0; base < len; base += G * kUnroll) {
-    int32_t ri[kUnroll];
-    float vv[kUnroll];
+  for (int32_t base = 0; base < len; base += G * U) {
+    int32_t ri[U];
+    float vv[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int32_t e = base + u * G + lane;
       ri[u] = e < len ? a.row_idx[beg + e] : -1;
       vv[u] = e < len ? a.val[beg + e] : 0.0f;
     }
-    float zh[kUnroll], zl[kUnroll], yy[kUnroll];
+    float zh[U], zl[U], yy[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int32_t i = ri[u] >= 0 ? ri[u] : 0;
       zh[u] = a.z_hi[i];
       zl[u] = a.z_lo[i];
       yy[u] = a.y[i];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < U; ++u)
       if (ri[u] >= 0) s += vv[u] * dloss_f32(a.loss, yy[u], zh[u] + zl[u]);
   }
   s = group_sum<G>(s);
@@ -642,10 +644,7 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
   a.delta[slot] = d;
   a.phi[slot] = ph;
   if (a.gout) a.gout[slot] = g;
-  if (MODE != 2 && d != 0.0f) {
-    a.w[j] = wj + d;
-    atomicAdd(a.counters + 3, (unsigned long long)len);
-  }
+  if (MODE != 2 && d != 0.0f) a.w[j] = wj + d;
 }
 
 // Propose (Algorithm 2 / 4).  A column that fits in one piece is finalised
@@ -664,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
   if (r.wave < r.nl) {
     const int32_t q1 = a.wbl[a.t + 1];
     for (int64_t q = a.wbl[a.t] + r.wave; q < q1; q += r.nl)
-      propose_piece<kWave, MODE>(a, a.desc_l[q], q, r.wl, P0);
+      propose_piece<kWave, MODE, 2 * kUnroll>(a, a.desc_l[q], q, r.wl, P0);
   } else {
     const int32_t q1 = a.wbs[a.t + 1];
     const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
@@ -757,38 +756,38 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
 }
 
 // Scatter z += d x over one piece (G lanes).
-template <int G, int MODE>
+template <int G, int MODE, int U = kUnroll>
 __device__ __forceinline__ void scatter_piece(const IterArgs &a, int64_t beg, int32_t len, float d,
                                               int lane) {
-  for (int32_t base = 0; base < len; base += G * kUnroll) {
-    int32_t ri[kUnroll];
-    float vv[kUnroll];
+  for (int32_t base = 0; base < len; base += G * U) {
+    int32_t ri[U];
+    float vv[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int32_t e = base + u * G + lane;
       ri[u] = e < len ? a.row_idx[beg + e] : -1;
       vv[u] = e < len ? a.val[beg + e] : 0.0f;
     }
     if (MODE == 1) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < U; ++u)
         if (ri[u] >= 0) scatter_plain(a.z_hi, a.z_lo, ri[u], d, vv[u]);
     } else if (!a.exact_accum) {
       // increments accumulate in the low word (non-returning atomics); the
       // pair is renormalised exactly at the end of the epoch
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < U; ++u)
         if (ri[u] >= 0) atomicAdd(&a.z_lo[ri[u]], d * vv[u]);
     } else {
       // issue all the returning atomics first, then the compensations
-      float pp[kUnroll], old[kUnroll];
+      float pp[U], old[U];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         pp[u] = d * vv[u];
         old[u] = ri[u] >= 0 ? atomicAdd(&a.z_hi[ri[u]], pp[u]) : 0.0f;
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         if (ri[u] < 0) continue;
         const float corr = twosum_err(old[u], pp[u]) + fmaf(d, vv[u], -pp[u]);
         if (corr != 0.0f) atomicAdd(&a.z_lo[ri[u]], corr);
@@ -829,14 +828,11 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
           a.delta[slot] = d;
           a.phi[slot] = ph;
           if (a.gout) a.gout[slot] = g;
-          if (d != 0.0f) {
-            a.w[j] = ws + d;
-            atomicAdd(a.counters + 3, (unsigned long long)(a.col_ptr[j + 1] - a.col_ptr[j]));
-          }
+          if (d != 0.0f) a.w[j] = ws + d;
         }
       }
       if (d == 0.0f) continue;
-      scatter_piece<kWave, MODE>(a, desc_beg(dsc), desc_len(dsc), d, r.wl);
+      scatter_piece<kWave, MODE, 2 * kUnroll>(a, desc_beg(dsc), desc_len(dsc), d, r.wl);
     }
   } else {
     const int32_t q1 = a.wbs[a.t + 1];

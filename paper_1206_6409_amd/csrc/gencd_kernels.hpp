@@ -27,7 +27,7 @@ struct IterArgs {
   float *delta, *phi, *gacc, *gout, *wsnap;
   int32_t *acc;
   int32_t exact_accum;     // 1: TwoSum per update (returning atomics); 0: low-word accumulation
-  unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals, [3] updated nnz
+  unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals (greedy rules)
 };
 
 int fill_f32(float *p, int64_t m, float v, hipStream_t s);

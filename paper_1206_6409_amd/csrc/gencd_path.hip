@@ -68,6 +68,7 @@ struct PathArgs {
   const float *y;
   const float *c;
   const int32_t *col_of_pos;
+  const int4 *pdesc;  // per position of the epoch order: {first entry, column, length, 0}
   int32_t win_lo, win_hi;
   float n_f;
   int32_t loss;
@@ -101,8 +102,9 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
   const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
   const int64_t npos = a.win_hi - a.win_lo;
   for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
-    const int32_t j = a.col_of_pos[a.win_lo + p];
-    const int64_t cb = a.col_ptr[j], ce = a.col_ptr[j + 1];
+    const int4 pd = a.pdesc[a.win_lo + p];
+    const int32_t j = pd.y;
+    const int64_t cb = int64_t(uint32_t(pd.x)), ce = cb + pd.z;
     float acc = 0.0f;
     for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
       int32_t ri[PU];
@@ -158,8 +160,8 @@ __global__ __launch_bounds__(kBlock) void k_path_update(PathArgs a) {
   const int64_t npos = a.win_hi - a.win_lo;
   for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
     const float d = a.delta[p * B + s];
-    const int32_t j = a.col_of_pos[a.win_lo + p];
-    const int64_t cb = a.col_ptr[j], ce = a.col_ptr[j + 1];
+    const int4 pd = a.pdesc[a.win_lo + p];
+    const int64_t cb = int64_t(uint32_t(pd.x)), ce = cb + pd.z;
     for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
       int32_t ri[PU];
       float vv[PU];
@@ -175,6 +177,51 @@ __global__ __launch_bounds__(kBlock) void k_path_update(PathArgs a) {
           if (ri[q] >= 0) atomicAdd(&a.zl[int64_t(ri[q]) * B + s], d * vv[q]);
       }
     }
+  }
+}
+
+// Staged form (used at B = 64): one group of B lanes per column, GPB = 256 / B columns per block;
+// the group stages B entries at a time in LDS and issues one B-wide atomic
+// row per entry.
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_update_staged(PathArgs a) {
+  constexpr int GPB = kBlock / B;
+  __shared__ int32_t srow[GPB][B];
+  __shared__ float sval[GPB][B];
+  const int grp = int(threadIdx.x) / B, s = int(threadIdx.x) % B;
+  const int64_t npos = a.win_hi - a.win_lo;
+  for (int64_t p0 = int64_t(blockIdx.x) * GPB; p0 < npos; p0 += int64_t(gridDim.x) * GPB) {
+    const int64_t p = p0 + grp;
+    int64_t cb = 0, ce = 0;
+    float d = 0.0f;
+    if (p < npos) {
+      const int4 pd = a.pdesc[a.win_lo + p];
+      cb = int64_t(uint32_t(pd.x));
+      ce = cb + pd.z;
+      d = a.delta[p * B + s];
+    }
+    for (int64_t base = cb; base < ce; base += B) {
+      const int64_t e = base + s;
+      srow[grp][s] = e < ce ? a.row_idx[e] : -1;
+      sval[grp][s] = e < ce ? a.val[e] : 0.0f;
+      __builtin_amdgcn_wave_barrier();
+      const int cnt = int(ce - base < B ? ce - base : B);
+      if (d != 0.0f)
+        for (int u = 0; u < cnt; ++u)
+          atomicAdd(&a.zl[int64_t(srow[grp][u]) * B + s], d * sval[grp][u]);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// Position descriptors of the epoch order.
+__global__ __launch_bounds__(kBlock) void k_path_desc(int64_t m, const int32_t *col_of_pos,
+                                                       const int64_t *col_ptr, int4 *pdesc) {
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < m;
+       p += int64_t(gridDim.x) * kBlock) {
+    const int32_t j = col_of_pos[p];
+    const int64_t b = col_ptr[j];
+    pdesc[p] = make_int4(int32_t(uint32_t(b)), j, int32_t(col_ptr[j + 1] - b), 0);
   }
 }
 
@@ -475,6 +522,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   a.y = y;
   a.c = ws.c;
   a.col_of_pos = ws.col_of_pos;
+  a.pdesc = ws.desc_s;  // the single-problem descriptors are not used here
   a.n_f = float(n);
   a.loss = p->loss;
   a.W = w.W;
@@ -484,6 +532,9 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   a.active = w.active;
   a.delta = w.delta;
   const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
+  // measured on the 64-lambda binary workload: the staged update wins at
+  // B = 64 (one full wave per column row), the block update below that
+  constexpr bool upd_staged = B == 64;
   std::vector<double> red;
   const int64_t T = (k_live + S - 1) / S;
   int64_t e = 0;
@@ -544,13 +595,20 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
     // one epoch over the live columns with shared windows
     st = launch_epoch_order(ws, k_live, GENCD_SHOTGUN, p->seed, epoch_dev, 0, S, T, s);
     if (st) return st;
+    hipLaunchKernelGGL(k_path_desc, dim3(g1(k_live)), dim3(kBlock), 0, s, k_live, ws.col_of_pos,
+                       X->col_ptr, ws.desc_s);
     for (int64_t t = 0; t < T; ++t) {
       a.win_lo = int32_t(t * S);
       a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
       const int64_t npos = a.win_hi - a.win_lo;
       const unsigned grid = unsigned(std::min<int64_t>(npos > 0 ? npos : 1, 65536));
       hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, s, a);
-      hipLaunchKernelGGL(k_path_update<B>, dim3(grid), dim3(kBlock), 0, s, a);
+      if constexpr (upd_staged)
+        hipLaunchKernelGGL(k_path_update_staged<B>,
+                           dim3(unsigned(std::min<int64_t>((npos + kBlock / B - 1) / (kBlock / B), 16384))),
+                           dim3(kBlock), 0, s, a);
+      else
+        hipLaunchKernelGGL(k_path_update<B>, dim3(grid), dim3(kBlock), 0, s, a);
     }
     hipLaunchKernelGGL(k_path_renorm<B>, dim3(g1(n * B)), dim3(kBlock), 0, s, n * B, w.zh, w.zl);
     st = launch_inc_epoch(epoch_dev, s);

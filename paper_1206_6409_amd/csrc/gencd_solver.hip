@@ -140,7 +140,7 @@ struct Red {
   unsigned long long gmax_bits;
   double dual_sum;
   unsigned long long pad[2];
-  unsigned long long acc_nnz, acc_cnt, bad, fused_nnz;
+  unsigned long long acc_nnz, acc_cnt, bad, spare;
   unsigned long long pad2[4];
 };
 static_assert(sizeof(Red) == 16 * 8, "reduction block layout");
@@ -239,7 +239,7 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
 struct CheckOut {
   double objective, kkt, gap;
   int64_t nnz_w;
-  unsigned long long acc_nnz, acc_cnt, fused_nnz;
+  unsigned long long acc_nnz, acc_cnt;
 };
 
 int run_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
@@ -255,7 +255,6 @@ int run_check(const gencd_csc *X, const float *y, int loss, double lam, const fl
   out->nnz_w = int64_t(r.nnz_w);
   out->acc_nnz = r.acc_nnz;
   out->acc_cnt = r.acc_cnt;
-  out->fused_nnz = r.fused_nnz;
   return GENCD_OK;
 }
 
