@@ -151,12 +151,13 @@ __device__ __forceinline__ float twosum_err(float a, float b) {
 
 // Compensated update of a row the caller owns (columns of one colour class
 // have disjoint rows): exact product error by FMA, exact sum error by TwoSum.
-__device__ __forceinline__ void scatter_plain(float *z_hi, float *z_lo, int i, float d, float v) {
+__device__ __forceinline__ void scatter_plain(float4 *zs, int i, float d, float v) {
   const float p = d * v;
   const float pe = fmaf(d, v, -p);
-  const float old = z_hi[i];
-  z_hi[i] = old + p;
-  z_lo[i] += twosum_err(old, p) + pe;
+  float *q = reinterpret_cast<float *>(zs + i);
+  const float old = q[0];
+  q[0] = old + p;
+  q[1] += twosum_err(old, p) + pe;
 }
 
 // ---------------------------------------------------------------------------
@@ -177,11 +178,12 @@ struct Ws {
   int32_t *cls_mem;      // [k] live members by colour
   // per-epoch order
   int32_t *col_of_pos;   // [k]
-  int32_t *soff, *loff;  // [k+1] short-column / long-piece offsets of the positions
-  int4 *desc_s;          // [k] short descriptors of the epoch order
+  int32_t *soff;         // [k+1] scratch (live-column scan at set-up)
+  int32_t *loff;         // [k+1] long-piece offsets of the positions
+  int4 *desc_s;          // [k] descriptor of every position (length 0: long column)
   int4 *desc_l;          // [max_lpieces] long descriptors of the epoch order
   int32_t *win_off;      // [k+1] colour windows (COLORING)
-  int32_t *wbs, *wbl;    // [k+2] first short column / long piece of every window
+  int32_t *wbl;          // [k+2] first long piece of every window
   // per-window
   float *delta;          // [k]
   float *phi;            // [k]
@@ -189,7 +191,8 @@ struct Ws {
   float *wsnap;          // [k] w of split columns at Propose time
   int32_t *acc;          // [k]
   // state
-  float *z_hi, *z_lo;    // [n] compensated fitted values
+  float4 *zs;            // [n] {z_hi, z_lo, y, 0}: compensated fitted value and label
+                         // of a row in one 16-byte record (one gather per entry)
   float *w_ckpt;         // [k]
   // FP64 check
   double *z64, *r64;     // [n]
@@ -204,6 +207,9 @@ struct Ws {
 };
 
 int64_t max_lpieces_for(int64_t k, int64_t nnz, int piece, int short_max);
+// Default schedule: lanes per short column and nonzeros per long piece.
+constexpr int kDefaultGroup = 8;
+constexpr int kDefaultPiece = 256;
 constexpr int kRhoIters = 20;       // power iterations behind an automatic |J|
 constexpr int kRhoMaxIters = 1024;  // cap for the standalone estimate
 constexpr int64_t kRhoSelectCap = 1024;  // automatic |J| is clamped to [1, this]

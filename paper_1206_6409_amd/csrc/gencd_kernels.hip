@@ -13,11 +13,12 @@
 // val loads), keep kUnroll of them in flight, gather the state and reduce.
 //
 // Selection (section 2.1) is precomputed per epoch: position p of the epoch
-// order holds column col_of_pos[p]; soff / loff are the exclusive scans of
-// short columns / long pieces over positions, so an iteration's selected set
-// J (a position range) maps to one short-descriptor range and one
-// long-descriptor range, whose bounds sit in device memory (a captured
-// epoch replays without host involvement).
+// order holds column col_of_pos[p] and the descriptor desc_s[p] (length 0
+// when the column is long), so a short group goes from its position straight
+// to its column.  loff is the exclusive scan of long pieces over positions;
+// an iteration's selected set J (a position range) maps to one long-piece
+// range whose bounds sit in device memory (a captured epoch replays without
+// host involvement).
 #include "gencd_common.hpp"
 #include "gencd_kernels.hpp"
 
@@ -226,14 +227,19 @@ __device__ __forceinline__ bool desc_single(const int4 &d) { return (uint32_t(d.
 
 // Role of a wave in a two-class launch: the first `nl` waves walk the long
 // pieces (one piece per wave), the others walk the short columns (64/GS per
-// wave).  At least one wave is kept for each role.
+// wave).  At least one wave is kept for each role.  Waves are numbered
+// slot-major (wave slot in the workgroup, then workgroup), so the long waves
+// take the first wave of every workgroup before any workgroup gets a second
+// one: their scattered gathers spread over all compute units instead of
+// queueing on the address units of a few.  No kernel using roles shares LDS
+// or barriers between waves.
 struct Roles {
   int64_t wave, nwaves, nl;
   int wl;
 };
 __device__ __forceinline__ Roles roles(int32_t nl_req) {
   Roles r;
-  r.wave = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave;
+  r.wave = int64_t(threadIdx.x / kWave) * gridDim.x + blockIdx.x;
   r.nwaves = int64_t(gridDim.x) * (kBlock / kWave);
   int64_t nl = nl_req < 1 ? 1 : nl_req;
   if (nl > r.nwaves - 1) nl = r.nwaves - 1;
@@ -432,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_list_counts(const int32_t *cols, int
 // Descriptors of the order: each position's static descriptors, re-tagged
 // with the position (8 lanes per position for long columns).
 __global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos, int64_t m,
-                                                        const int32_t *soff, const int32_t *loff,
+                                                        const int32_t *loff,
                                                         const int32_t *all_soff,
                                                         const int32_t *all_loff,
                                                         const int4 *desc_all_s,
@@ -443,14 +449,16 @@ __global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos
   for (int64_t p = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / L; p < m;
        p += int64_t(gridDim.x) * kBlock / L) {
     const int32_t j = col_of_pos[p];
-    if (soff[p + 1] > soff[p]) {
+    const int32_t sj = all_soff[j];
+    if (all_soff[j + 1] > sj) {  // short column
       if (lane == 0) {
-        int4 d = desc_all_s[all_soff[j]];
+        int4 d = desc_all_s[sj];
         d.z = int32_t(p);
-        desc_s[soff[p]] = d;
+        desc_s[p] = d;
       }
       continue;
     }
+    if (lane == 0) desc_s[p] = make_int4(0, j, int32_t(p), 0);  // long: length 0
     const int32_t a = loff[p], b = loff[p + 1], src = all_loff[j];
     for (int32_t q0 = a; q0 < b; q0 += L * kUnroll) {
       int4 d[kUnroll];
@@ -497,32 +505,27 @@ __global__ __launch_bounds__(kBlock) void k_color_fill(const int32_t *cls_off,
   }
 }
 
-// Descriptor ranges of every window: wbs[t] / wbl[t] = first short column /
-// long piece of window t.
-__global__ __launch_bounds__(kBlock) void k_window_bounds(const int32_t *soff, const int32_t *loff,
+// Long-piece ranges of every window: wbl[t] = first long piece of window t.
+__global__ __launch_bounds__(kBlock) void k_window_bounds(const int32_t *loff,
                                                            const int32_t *win_off, int64_t S,
-                                                           int64_t m, int64_t T, int32_t *wbs,
-                                                           int32_t *wbl) {
+                                                           int64_t m, int64_t T, int32_t *wbl) {
   for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t <= T;
        t += int64_t(gridDim.x) * kBlock) {
     int64_t pos = win_off ? int64_t(win_off[t]) : (t * S < m ? t * S : m);
-    wbs[t] = soff[pos];
     wbl[t] = loff[pos];
   }
 }
 
 static int order_tail(const Ws &w, int64_t m, const int32_t *win_off, int64_t S, int64_t T,
                       hipStream_t s) {
-  int st = scan_exclusive(w.tmp_cnt, w.soff, m, w.scan_part, s);
-  if (st) return st;
-  st = scan_exclusive(w.tmp_cnt2, w.loff, m, w.scan_part, s);
+  int st = scan_exclusive(w.tmp_cnt2, w.loff, m, w.scan_part, s);
   if (st) return st;
   if (m > 0)
     hipLaunchKernelGGL(k_order_desc, dim3(grid_for(m * 8)), dim3(kBlock), 0, s, w.col_of_pos, m,
-                       w.soff, w.loff, w.all_soff, w.all_loff, w.desc_all_s, w.desc_all_l,
-                       w.desc_s, w.desc_l);
-  hipLaunchKernelGGL(k_window_bounds, dim3(grid_for(T + 1)), dim3(kBlock), 0, s, w.soff, w.loff,
-                     win_off, S, m, T, w.wbs, w.wbl);
+                       w.loff, w.all_soff, w.all_loff, w.desc_all_s, w.desc_all_l, w.desc_s,
+                       w.desc_l);
+  hipLaunchKernelGGL(k_window_bounds, dim3(grid_for(T + 1)), dim3(kBlock), 0, s, w.loff, win_off,
+                     S, m, T, w.wbl);
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
@@ -622,9 +625,10 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t i = ri[u] >= 0 ? ri[u] : 0;
-      zh[u] = a.z_hi[i];
-      zl[u] = a.z_lo[i];
-      yy[u] = a.y[i];
+      const float4 zr = a.zs[i];  // one 16-byte gather: z_hi, z_lo, y
+      zh[u] = zr.x;
+      zl[u] = zr.y;
+      yy[u] = zr.z;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -655,7 +659,8 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
 // MODE 0: accept all, atomic scatter (Shotgun, stochastic, cyclic)
 // MODE 1: accept all, plain scatter (Coloring: rows of a class are disjoint)
 // MODE 2: deferred acceptance (Thread-Greedy, Greedy)
-template <int GS, int MODE>
+// UL: entries per lane per batch on long pieces (piece / 64, 4 or 8).
+template <int GS, int MODE, int UL>
 __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
   const Roles r = roles(a.nl);
   int32_t P0, P1;
@@ -663,12 +668,14 @@ __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
   if (r.wave < r.nl) {
     const int32_t q1 = a.wbl[a.t + 1];
     for (int64_t q = a.wbl[a.t] + r.wave; q < q1; q += r.nl)
-      propose_piece<kWave, MODE, 2 * kUnroll>(a, a.desc_l[q], q, r.wl, P0);
+      propose_piece<kWave, MODE, UL>(a, a.desc_l[q], q, r.wl, P0);
   } else {
-    const int32_t q1 = a.wbs[a.t + 1];
     const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
-    for (int64_t q = a.wbs[a.t] + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < q1; q += step)
-      propose_piece<GS, MODE>(a, a.desc_s[q], q, r.wl & (GS - 1), P0);
+    for (int64_t p = P0 + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; p < P1; p += step) {
+      const int4 dsc = a.desc_s[p];
+      if (desc_len(dsc) == 0) continue;  // long column: the long waves take it
+      propose_piece<GS, MODE>(a, dsc, p, r.wl & (GS - 1), P0);
+    }
   }
 }
 
@@ -771,26 +778,26 @@ __device__ __forceinline__ void scatter_piece(const IterArgs &a, int64_t beg, in
     if (MODE == 1) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (ri[u] >= 0) scatter_plain(a.z_hi, a.z_lo, ri[u], d, vv[u]);
+        if (ri[u] >= 0) scatter_plain(a.zs, ri[u], d, vv[u]);
     } else if (!a.exact_accum) {
       // increments accumulate in the low word (non-returning atomics); the
       // pair is renormalised exactly at the end of the epoch
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (ri[u] >= 0) atomicAdd(&a.z_lo[ri[u]], d * vv[u]);
+        if (ri[u] >= 0) atomicAdd(&a.zs[ri[u]].y, d * vv[u]);
     } else {
       // issue all the returning atomics first, then the compensations
       float pp[U], old[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         pp[u] = d * vv[u];
-        old[u] = ri[u] >= 0 ? atomicAdd(&a.z_hi[ri[u]], pp[u]) : 0.0f;
+        old[u] = ri[u] >= 0 ? atomicAdd(&a.zs[ri[u]].x, pp[u]) : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (ri[u] < 0) continue;
         const float corr = twosum_err(old[u], pp[u]) + fmaf(d, vv[u], -pp[u]);
-        if (corr != 0.0f) atomicAdd(&a.z_lo[ri[u]], corr);
+        if (corr != 0.0f) atomicAdd(&a.zs[ri[u]].y, corr);
       }
     }
   }
@@ -800,7 +807,7 @@ __device__ __forceinline__ void scatter_piece(const IterArgs &a, int64_t beg, in
 // Accept-all rules finalise split columns here: every piece recomputes the
 // same delta from the partial sums and the weight snapshot; the column's
 // first piece writes w_j, delta_j and phi_j.
-template <int GS, int MODE>
+template <int GS, int MODE, int UL>
 __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   const Roles r = roles(a.nl);
   int32_t P0, P1;
@@ -832,62 +839,98 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
         }
       }
       if (d == 0.0f) continue;
-      scatter_piece<kWave, MODE, 2 * kUnroll>(a, desc_beg(dsc), desc_len(dsc), d, r.wl);
+      scatter_piece<kWave, MODE, UL>(a, desc_beg(dsc), desc_len(dsc), d, r.wl);
     }
   } else {
-    const int32_t q1 = a.wbs[a.t + 1];
     const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
     const int lane = r.wl & (GS - 1);
-    for (int64_t q = a.wbs[a.t] + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < q1; q += step) {
-      const int4 dsc = a.desc_s[q];
-      const int32_t slot = dsc.z - P0;
+    for (int64_t p = P0 + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; p < P1; p += step) {
+      const int4 dsc = a.desc_s[p];  // loads of dsc, acc and delta are independent
+      const int64_t slot = p - P0;
       if (MODE == 2 && !a.acc[slot]) continue;
       const float d = a.delta[slot];
-      if (d == 0.0f) continue;
+      if (d == 0.0f || desc_len(dsc) == 0) continue;
       scatter_piece<GS, MODE>(a, desc_beg(dsc), desc_len(dsc), d, lane);
     }
   }
 }
 
 // Exact renormalisation of the fitted values: (z_hi, z_lo) <- TwoSum.
-__global__ __launch_bounds__(kBlock) void k_renorm(int64_t n, float *z_hi, float *z_lo) {
+__global__ __launch_bounds__(kBlock) void k_renorm(int64_t n, float4 *zs) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * kBlock) {
-    const float h = z_hi[i], l = z_lo[i];
-    const float s = h + l;
-    z_lo[i] = twosum_err(h, l);
-    z_hi[i] = s;
+    float2 *hl = reinterpret_cast<float2 *>(zs + i);
+    const float2 v = *hl;
+    *hl = make_float2(v.x + v.y, twosum_err(v.x, v.y));
   }
 }
 
-int launch_renorm(int64_t n, float *z_hi, float *z_lo, hipStream_t s) {
-  hipLaunchKernelGGL(k_renorm, dim3(grid_for(n, 2048)), dim3(kBlock), 0, s, n, z_hi, z_lo);
+int launch_renorm(int64_t n, float4 *zs, hipStream_t s) {
+  hipLaunchKernelGGL(k_renorm, dim3(grid_for(n, 2048)), dim3(kBlock), 0, s, n, zs);
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
-template <int GS>
+__global__ __launch_bounds__(kBlock) void k_pack_state(int64_t n, const float *z_hi,
+                                                        const float *z_lo, const float *y,
+                                                        float4 *zs) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    zs[i] = make_float4(z_hi[i], z_lo[i], y[i], 0.0f);
+}
+
+__global__ __launch_bounds__(kBlock) void k_unpack_state(int64_t n, const float4 *zs, float *z_hi,
+                                                          float *z_lo) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const float4 v = zs[i];
+    z_hi[i] = v.x;
+    z_lo[i] = v.y;
+  }
+}
+
+int launch_pack_state(int64_t n, const float *z_hi, const float *z_lo, const float *y, float4 *zs,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_state, dim3(grid_for(n)), dim3(kBlock), 0, s, n, z_hi, z_lo, y, zs);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+int launch_unpack_state(int64_t n, const float4 *zs, float *z_hi, float *z_lo, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_state, dim3(grid_for(n)), dim3(kBlock), 0, s, n, zs, z_hi, z_lo);
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+template <int GS, int UL>
 static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsigned blocks,
                               int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
                               hipEvent_t ev1) {
   const dim3 grid(blocks), blk(kBlock);
   if (ev0) (void)hipEventRecord(ev0, s);
   if (mode == 0)
-    hipLaunchKernelGGL((k_propose<GS, 0>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_propose<GS, 0, UL>), grid, blk, 0, s, a);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_propose<GS, 1>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_propose<GS, 1, UL>), grid, blk, 0, s, a);
   else
-    hipLaunchKernelGGL((k_propose<GS, 2>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_propose<GS, 2, UL>), grid, blk, 0, s, a);
   if (ev1) (void)hipEventRecord(ev1, s);
   if (mode == 0) {
-    hipLaunchKernelGGL((k_update<GS, 0>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<GS, 0, UL>), grid, blk, 0, s, a);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_update<GS, 1>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<GS, 1, UL>), grid, blk, 0, s, a);
   } else {
     unsigned nb = unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
     hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
-    hipLaunchKernelGGL((k_update<GS, 2>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_update<GS, 2, UL>), grid, blk, 0, s, a);
   }
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+template <int GS>
+static int launch_iteration_u(const IterArgs &a, int mode, int64_t block, unsigned blocks,
+                              int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
+                              hipEvent_t ev1) {
+  if (a.piece <= kWave * kUnroll)
+    return launch_iteration_g<GS, kUnroll>(a, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+  return launch_iteration_g<GS, 2 * kUnroll>(a, mode, block, blocks, nblocks_accept, s, ev0, ev1);
 }
 
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
@@ -899,10 +942,10 @@ int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int6
   two_class_grid(short_bound, long_bound, group, &blocks, &nl);
   b.nl = nl;
   switch (group) {
-    case 4: return launch_iteration_g<4>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
-    case 8: return launch_iteration_g<8>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
-    case 16: return launch_iteration_g<16>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
-    default: return launch_iteration_g<32>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    case 4: return launch_iteration_u<4>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    case 8: return launch_iteration_u<8>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    case 16: return launch_iteration_u<16>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    default: return launch_iteration_u<32>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
   }
 }
 
@@ -961,7 +1004,7 @@ __global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, c
 
 __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, const float *y,
                                                         const double *z64, double *r64,
-                                                        float *z_hi, float *z_lo, double *red) {
+                                                        float4 *zs, double *red) {
   __shared__ double sred[kBlock];
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -970,10 +1013,9 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, cons
     const double yi = double(y[i]);
     acc += loss_f64(loss, yi, t);
     r64[i] = dloss_f64(loss, yi, t);
-    if (z_hi) {
+    if (zs) {  // re-sync: z_hi + z_lo = z64 to about 2^-48 relative, and the label
       const float h = float(t);
-      z_hi[i] = h;
-      z_lo[i] = float(t - double(h));
+      zs[i] = make_float4(h, float(t - double(h)), y[i], 0.0f);
     }
   }
   sred[threadIdx.x] = acc;
@@ -1127,7 +1169,7 @@ int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const
     hipLaunchKernelGGL((k_check_spmv<8, float>), dim3(blocks), dim3(kBlock), 0, s, X->row_idx,
                        X->val, ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, w, ws.z64);
   hipLaunchKernelGGL(k_check_rows, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
-                     ws.z64, ws.r64, resync ? ws.z_hi : nullptr, ws.z_lo, ws.red);
+                     ws.z64, ws.r64, resync ? ws.zs : nullptr, ws.red);
   if (n_short + n_lpieces > 0)
     hipLaunchKernelGGL(k_check_cols<8>, dim3(blocks), dim3(kBlock), 0, s, X->row_idx, X->val,
                        ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, ws.r64, ws.g64);

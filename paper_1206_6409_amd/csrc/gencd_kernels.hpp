@@ -10,18 +10,19 @@ struct IterArgs {
   const int64_t *col_ptr;
   const int32_t *row_idx;
   const float *val;
-  const float *y;
   float n_f;
   int32_t loss;
   float lam;
   const float *c;
   float *w;
-  float *z_hi, *z_lo;
+  float4 *zs;                      // {z_hi, z_lo, y, 0} per row
   const int32_t *col_of_pos;
   const int32_t *loff;             // long-piece offsets of the positions
-  const int4 *desc_s, *desc_l;     // descriptors of the current order
-  const int32_t *wbs, *wbl;        // window t: short [wbs[t], wbs[t+1]), long [wbl[t], wbl[t+1])
+  const int4 *desc_s;              // descriptor of every position (length 0: long column)
+  const int4 *desc_l;              // long-piece descriptors of the current order
+  const int32_t *wbl;              // window t: long pieces [wbl[t], wbl[t+1])
   int32_t nl;                      // waves walking long pieces (set by the launcher)
+  int32_t piece;                   // nonzeros per long piece
   const int32_t *win_off;  // per-epoch window offsets, or null: [win_lo, win_hi)
   int32_t t, win_lo, win_hi;
   float *delta, *phi, *gacc, *gout, *wsnap;
@@ -64,7 +65,11 @@ int launch_rho(const gencd_csc *X, int32_t n_short, int32_t n_lpieces, const Ws 
                int iters, hipStream_t s);
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
                  int32_t n_short, int32_t n_lpieces, const Ws &ws, bool resync, hipStream_t s);
-int launch_renorm(int64_t n, float *z_hi, float *z_lo, hipStream_t s);
+int launch_renorm(int64_t n, float4 *zs, hipStream_t s);
+// Copy caller-held (z_hi, z_lo) and the labels into the packed rows, and back.
+int launch_pack_state(int64_t n, const float *z_hi, const float *z_lo, const float *y, float4 *zs,
+                      hipStream_t s);
+int launch_unpack_state(int64_t n, const float4 *zs, float *z_hi, float *z_lo, hipStream_t s);
 int launch_round_f32(const double *src, float *dst, int64_t m, hipStream_t s);
 
 }  // namespace gencd

@@ -640,8 +640,8 @@ int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_
   if (!X || !p || !out_bytes || X->n <= 0 || X->k <= 0 || X->nnz < 0) return GENCD_ERR_INVALID_ARG;
   if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
   if (p->select_size <= 0) return GENCD_ERR_INVALID_ARG;
-  const int piece = p->piece ? p->piece : 512;
-  const int group = p->group ? p->group : 8;
+  const int piece = p->piece ? p->piece : kDefaultPiece;
+  const int group = p->group ? p->group : kDefaultGroup;
   *out_bytes = path_workspace_bytes(X->n, X->k, X->nnz, std::min<int64_t>(p->select_size, X->k), B,
                                     piece, group * kUnroll) + 256;
   return GENCD_OK;

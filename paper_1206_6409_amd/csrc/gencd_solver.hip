@@ -19,8 +19,6 @@
 namespace gencd {
 
 static constexpr size_t kAlign = 256;
-static constexpr int kDefaultPiece = 512;
-static constexpr int kDefaultGroup = 8;
 
 // long pieces: a long column has more than short_max nonzeros, so there are
 // at most nnz / (short_max + 1) of them, each with at most one partial piece
@@ -70,15 +68,13 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.desc_s = c.take<int4>(k);
   w.desc_l = c.take<int4>(ml);
   w.win_off = c.take<int32_t>(k + 1);
-  w.wbs = c.take<int32_t>(k + 2);
   w.wbl = c.take<int32_t>(k + 2);
   w.delta = c.take<float>(k);
   w.phi = c.take<float>(k);
   w.gacc = c.take<float>(ml);
   w.wsnap = c.take<float>(k);
   w.acc = c.take<int32_t>(k);
-  w.z_hi = c.take<float>(n);
-  w.z_lo = c.take<float>(n);
+  w.zs = c.take<float4>(n);
   w.w_ckpt = c.take<float>(k);
   w.z64 = c.take<double>(n);
   w.r64 = c.take<double>(n);
@@ -270,20 +266,19 @@ int mode_of(int rule) {
 }
 
 IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, const Setup &su,
-                   float *w, float *z_hi, float *z_lo) {
+                   float *w, float4 *zs) {
   const Ws &ws = su.ws;
   IterArgs a{};
+  a.piece = su.piece;
   a.col_ptr = X->col_ptr;
   a.row_idx = X->row_idx;
   a.val = X->val;
-  a.y = y;
   a.n_f = float(X->n);
   a.loss = p->loss;
   a.lam = float(p->lambda);
   a.c = ws.c;
   a.w = w;
-  a.z_hi = z_hi;
-  a.z_lo = z_lo;
+  a.zs = zs;
   a.col_of_pos = ws.col_of_pos;
   a.loff = ws.loff;
   a.desc_s = ws.desc_s;
@@ -293,7 +288,6 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   a.gacc = ws.gacc;
   a.gout = nullptr;
   a.wsnap = ws.wsnap;
-  a.wbs = ws.wbs;
   a.wbl = ws.wbl;
   a.acc = ws.acc;
   a.counters = reinterpret_cast<unsigned long long *>(ws.red) + 8;
@@ -491,7 +485,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   int64_t *epoch_dev = reinterpret_cast<int64_t *>(ws.red + 12);
   st = fill_f64(ws.red + 12, 1, 0.0, s);  // epoch counter = 0
   if (st) return st;
-  IterArgs a = base_args(X, y, p, su, w, ws.z_hi, ws.z_lo);
+  IterArgs a = base_args(X, y, p, su, w, ws.zs);
   unsigned long long acc_nnz_seen = 0, acc_cnt_seen = 0;
   // GENCD_PROFILE: one event pair per Propose launch between two checks
   const bool use_graph = (p->flags & GENCD_USE_GRAPH) != 0;
@@ -550,7 +544,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       if (rc) return rc;
     }
     if (mode != 1 && !a.exact_accum) {
-      rc = launch_renorm(X->n, ws.z_hi, ws.z_lo, es);
+      rc = launch_renorm(X->n, ws.zs, es);
       if (rc) return rc;
     }
     return launch_inc_epoch(epoch_dev, es);
@@ -680,7 +674,9 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
   st = launch_list_order(ws, J, nJ, s);
   if (st) return st;
   const int mode = mode_of(p->rule);
-  IterArgs a = base_args(X, y, p, su, w, z_hi, z_lo);
+  st = launch_pack_state(X->n, z_hi, z_lo, y, ws.zs, s);
+  if (st) return st;
+  IterArgs a = base_args(X, y, p, su, w, ws.zs);
   a.win_off = nullptr;
   a.win_lo = 0;
   a.win_hi = int32_t(nJ);
@@ -689,6 +685,8 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
   const int64_t B = (p->rule == GENCD_THREAD_GREEDY) ? p->block : nJ;
   st = launch_iteration(a, su.group, mode, B, nJ, std::max<int64_t>(long_bound_for(su, nJ), 1),
                         (nJ + B - 1) / B, s);
+  if (st) return st;
+  st = launch_unpack_state(X->n, ws.zs, z_hi, z_lo, s);
   if (st) return st;
   if (delta) st = copy_f32(delta, ws.delta, nJ, s);
   if (st) return st;

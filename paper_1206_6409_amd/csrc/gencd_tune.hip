@@ -123,7 +123,7 @@ int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, in
   if (cache_lookup(cache_path, key, out)) return GENCD_OK;
 
   const int groups[] = {4, 8, 16};
-  const int pieces[] = {256, 512, 1024};
+  const int pieces[] = {128, 256, 512};
   const unsigned gflags[] = {0u, GENCD_USE_GRAPH};
   double best = 1e300;
   for (int g : groups)
