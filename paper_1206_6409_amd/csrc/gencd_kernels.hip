@@ -607,9 +607,9 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
   const int32_t j = dsc.y, p = dsc.z;
   const bool single = desc_single(dsc);
   float wj = 0.0f, cj = 0.0f;
-  if (single && lane == 0) {  // issued early, consumed after the reduction
+  if (lane == 0) {  // issued early, consumed after the reduction
     wj = a.w[j];
-    cj = a.c[j];
+    if (single) cj = a.c[j];
   }
   float s = 0.0f;
   for (int32_t base = 0; base < len; base += G * U) {
@@ -639,7 +639,7 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
   const int32_t slot = p - P0;
   if (!single) {
     a.gacc[q] = s;
-    if (MODE != 2) a.wsnap[slot] = a.w[j];  // stable copy for Update
+    if (MODE != 2) a.wsnap[slot] = wj;  // stable copy for Update
     return;
   }
   const float g = s / a.n_f;
@@ -762,44 +762,58 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
   }
 }
 
-// Scatter z += d x over one piece (G lanes).
-template <int G, int MODE, int U = kUnroll>
-__device__ __forceinline__ void scatter_piece(const IterArgs &a, int64_t beg, int32_t len, float d,
-                                              int lane) {
-  for (int32_t base = 0; base < len; base += G * U) {
-    int32_t ri[U];
-    float vv[U];
+// Scatter z += d x over one piece (G lanes), U entries per lane per batch.
+template <int G, int U>
+__device__ __forceinline__ void load_batch(const IterArgs &a, int64_t beg, int32_t len,
+                                           int32_t base, int lane, int32_t (&ri)[U],
+                                           float (&vv)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int32_t e = base + u * G + lane;
+    ri[u] = e < len ? a.row_idx[beg + e] : -1;
+    vv[u] = e < len ? a.val[beg + e] : 0.0f;
+  }
+}
+
+template <int MODE, int U>
+__device__ __forceinline__ void scatter_batch(const IterArgs &a, const int32_t (&ri)[U],
+                                              const float (&vv)[U], float d) {
+  if (MODE == 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ri[u] >= 0) scatter_plain(a.zs, ri[u], d, vv[u]);
+  } else if (!a.exact_accum) {
+    // increments accumulate in the low word (non-returning atomics); the
+    // pair is renormalised exactly at the end of the epoch
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ri[u] >= 0) atomicAdd(&a.zs[ri[u]].y, d * vv[u]);
+  } else {
+    // issue all the returning atomics first, then the compensations
+    float pp[U], old[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int32_t e = base + u * G + lane;
-      ri[u] = e < len ? a.row_idx[beg + e] : -1;
-      vv[u] = e < len ? a.val[beg + e] : 0.0f;
+      pp[u] = d * vv[u];
+      old[u] = ri[u] >= 0 ? atomicAdd(&a.zs[ri[u]].x, pp[u]) : 0.0f;
     }
-    if (MODE == 1) {
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ri[u] >= 0) scatter_plain(a.zs, ri[u], d, vv[u]);
-    } else if (!a.exact_accum) {
-      // increments accumulate in the low word (non-returning atomics); the
-      // pair is renormalised exactly at the end of the epoch
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ri[u] >= 0) atomicAdd(&a.zs[ri[u]].y, d * vv[u]);
-    } else {
-      // issue all the returning atomics first, then the compensations
-      float pp[U], old[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        pp[u] = d * vv[u];
-        old[u] = ri[u] >= 0 ? atomicAdd(&a.zs[ri[u]].x, pp[u]) : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (ri[u] < 0) continue;
-        const float corr = twosum_err(old[u], pp[u]) + fmaf(d, vv[u], -pp[u]);
-        if (corr != 0.0f) atomicAdd(&a.zs[ri[u]].y, corr);
-      }
+    for (int u = 0; u < U; ++u) {
+      if (ri[u] < 0) continue;
+      const float corr = twosum_err(old[u], pp[u]) + fmaf(d, vv[u], -pp[u]);
+      if (corr != 0.0f) atomicAdd(&a.zs[ri[u]].y, corr);
     }
+  }
+}
+
+// Entries from `from` on (batches of G * U).
+template <int G, int MODE, int U = kUnroll>
+__device__ __forceinline__ void scatter_piece(const IterArgs &a, int64_t beg, int32_t len, float d,
+                                              int lane, int32_t from = 0) {
+  for (int32_t base = from; base < len; base += G * U) {
+    int32_t ri[U];
+    float vv[U];
+    load_batch<G, U>(a, beg, len, base, lane, ri, vv);
+    scatter_batch<MODE, U>(a, ri, vv, d);
   }
 }
 
