@@ -25,6 +25,42 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one Propose launch, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size) and kept
+# as a text summary.  It is reported only while the kernel sources and
+# launch configuration are the ones the counters were taken on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_propose_zipf1.1-logistic_n100k_k500k_pmc.md")
+TRAFFIC_SOURCES = ["gencd_common.hpp", "gencd_kernels.hpp", "gencd_kernels.hip", "gencd_solver.hip"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1206_6409_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per Propose launch from the counter summary, or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and " = " in line:
+            k, v = line[2:].split(" = ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -58,6 +94,9 @@ def main():
     ap.add_argument("--req-scale", type=float, default=0.25,
                     help="serve: scale of the n and k ranges of the request distribution")
     ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
+    ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (the reference "
+                         "dispatch for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -75,6 +114,15 @@ def main():
         sys.exit(1)
     G.lib()  # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
+    if args.calibration_copy > 0:
+        nb = args.calibration_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nb} bytes read, {nb} bytes written")
+        del src, dst
     if args.workload != "shotgun":
         names = ["coloring", "path", "serve"] if args.workload == "all" else [args.workload]
         for name in names:
@@ -135,7 +183,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 6),
-        "traffic": None,
+        "traffic": measured_traffic(),
         "avg_launch_us": round(prof_ms * 1e3 / max(prof_launch, 1), 3),
         "bytes_per_launch": round(prof_bytes / max(prof_launch, 1), 1),
         "launches": prof_launch,

@@ -19,6 +19,8 @@
 // an iteration's selected set J (a position range) maps to one long-piece
 // range whose bounds sit in device memory (a captured epoch replays without
 // host involvement).
+#include <hip/hip_ext.h>
+
 #include "gencd_common.hpp"
 #include "gencd_kernels.hpp"
 
@@ -918,14 +920,22 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
                               int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
                               hipEvent_t ev1) {
   const dim3 grid(blocks), blk(kBlock);
-  if (ev0) (void)hipEventRecord(ev0, s);
-  if (mode == 0)
+  // with events, Propose is launched through the extension that stamps the
+  // kernel's own start and end (no dispatch gap in the measured interval)
+  if (ev0 && ev1) {
+    if (mode == 0)
+      hipExtLaunchKernelGGL((k_propose<GS, 0, UL>), grid, blk, 0, s, ev0, ev1, 0, a);
+    else if (mode == 1)
+      hipExtLaunchKernelGGL((k_propose<GS, 1, UL>), grid, blk, 0, s, ev0, ev1, 0, a);
+    else
+      hipExtLaunchKernelGGL((k_propose<GS, 2, UL>), grid, blk, 0, s, ev0, ev1, 0, a);
+  } else if (mode == 0) {
     hipLaunchKernelGGL((k_propose<GS, 0, UL>), grid, blk, 0, s, a);
-  else if (mode == 1)
+  } else if (mode == 1) {
     hipLaunchKernelGGL((k_propose<GS, 1, UL>), grid, blk, 0, s, a);
-  else
+  } else {
     hipLaunchKernelGGL((k_propose<GS, 2, UL>), grid, blk, 0, s, a);
-  if (ev1) (void)hipEventRecord(ev1, s);
+  }
   if (mode == 0) {
     hipLaunchKernelGGL((k_update<GS, 0, UL>), grid, blk, 0, s, a);
   } else if (mode == 1) {

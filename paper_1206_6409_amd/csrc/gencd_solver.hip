@@ -559,7 +559,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
         // no system-scope fence at the markers: the pair then brackets the
         // kernel without an extra cache flush
         for (auto &ev : evs)
-          if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) ev = nullptr;
+          if (hipEventCreate(&ev) != hipSuccess) ev = nullptr;
       }
     }
     if (use_graph) {
