@@ -18,7 +18,7 @@ import numpy as np
 from . import build as _build
 
 SQUARED, LOGISTIC = 0, 1
-CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING = range(6)
+CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY = range(7)
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -67,7 +67,7 @@ def lib():
         L.orc_propose.restype = None
         L.orc_propose.argtypes = [D, D, D, D, P, P]
         L.orc_step.restype = I32
-        L.orc_step.argtypes = [P, P, I32, D, P, P, I64, I64, P, P, P, P, P, P, P, P]
+        L.orc_step.argtypes = [P, P, I32, D, P, P, I64, I64, I64, P, P, P, P, P, P, P, P]
         L.orc_check.restype = None
         L.orc_check.argtypes = [P, P, I32, D, P, P, P, P, P, P]
         L.orc_duality_gap.restype = D
@@ -158,8 +158,10 @@ class StepResult:
     nnz_updates: int
 
 
-def step(X: Matrix, y, kind, lam, J, w, z, block=0, forced=None, c=None):
-    """One Jacobi iteration on J; w and z (float64) are updated in place."""
+def step(X: Matrix, y, kind, lam, J, w, z, block=0, forced=None, c=None, top=0):
+    """One Jacobi iteration on J; w and z (float64) are updated in place.
+    top > 0 accepts the `top` best proposals of the window (forced: the
+    accepted positions instead); block > 0 the best of each block."""
     y = np.ascontiguousarray(y, dtype=np.float64)
     J = np.ascontiguousarray(J, dtype=np.int32)
     if c is None:
@@ -170,7 +172,7 @@ def step(X: Matrix, y, kind, lam, J, w, z, block=0, forced=None, c=None):
     f = None if forced is None else np.ascontiguousarray(forced, dtype=np.int32)
     nu = C.c_int64()
     assert w.dtype == np.float64 and z.dtype == np.float64
-    st = lib().orc_step(X.ref, _p(y), kind, float(lam), _p(c), _p(J), m, int(block), _p(f),
+    st = lib().orc_step(X.ref, _p(y), kind, float(lam), _p(c), _p(J), m, int(block), int(top), _p(f),
                         _p(w), _p(z), _p(g), _p(d), _p(ph), _p(acc), C.byref(nu))
     if st != 0:
         raise ValueError(f"orc_step failed: {st}")

@@ -56,6 +56,7 @@
 #define ORC_THREAD_GREEDY 3
 #define ORC_GREEDY 4
 #define ORC_COLORING 5
+#define ORC_TOP_GREEDY 6 /* Thread-Greedy accepting the best |J'| of the window */
 
 typedef struct {
   int64_t n, k, nnz;
@@ -208,9 +209,25 @@ void orc_propose(double g, double c, double w, double lambda, double *delta, dou
  *   Update (Algorithm 3): in ascending position, w_j += delta_j and
  *     z += delta_j X_j.
  * Optional outputs g/delta/phi (length nJ) and acc (0/1 per position). */
+/* Order of window positions for the global accept: by proxy, ties to the
+ * lower position. */
+static const double *g_top_phi;
+static int cmp_top(const void *a, const void *b) {
+  int64_t ta = *(const int64_t *)a, tb = *(const int64_t *)b;
+  if (g_top_phi[ta] < g_top_phi[tb]) return -1;
+  if (g_top_phi[ta] > g_top_phi[tb]) return 1;
+  return ta < tb ? -1 : (ta > tb ? 1 : 0);
+}
+
+/* One Jacobi iteration on the window J (Algorithm 1).  Accept:
+ *   top > 0:   the `top` proposals with the smallest phi over the whole
+ *              window (Thread-Greedy with global acceptance, section 4.1);
+ *   block > 0: in each block of `block` consecutive positions the first
+ *              position with minimal phi (Thread-Greedy, Greedy);
+ *   otherwise every proposal (Shotgun, Coloring, CCD). */
 int orc_step(const orc_csc *X, const double *y, int loss, double lambda, const double *c,
-             const int32_t *J, int64_t nJ, int64_t block, const int32_t *forced, double *w,
-             double *z, double *g_out, double *d_out, double *p_out, int32_t *acc_out,
+             const int32_t *J, int64_t nJ, int64_t block, int64_t top, const int32_t *forced,
+             double *w, double *z, double *g_out, double *d_out, double *p_out, int32_t *acc_out,
              int64_t *nnz_updates) {
   if (nJ < 0) return ORC_EINVAL;
   for (int64_t t = 0; t < nJ; ++t)
@@ -237,7 +254,25 @@ int orc_step(const orc_csc *X, const double *y, int loss, double lambda, const d
     if (g_out) g_out[t] = g;
   }
   /* Accept */
-  if (block <= 0) {
+  if (top > 0) {
+    int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nJ > 0 ? nJ : 1));
+    if (!ord) {
+      free(d);
+      free(ph);
+      free(acc);
+      return ORC_ENOMEM;
+    }
+    for (int64_t t = 0; t < nJ; ++t) ord[t] = t;
+    g_top_phi = ph;
+    qsort(ord, (size_t)nJ, sizeof(int64_t), cmp_top);
+    for (int64_t t = 0; t < nJ && t < top; ++t) acc[ord[t]] = 1;
+    if (forced) { /* forced accept set: positions listed in forced[0..top) */
+      for (int64_t t = 0; t < nJ; ++t) acc[t] = 0;
+      for (int64_t t = 0; t < top && t < nJ; ++t)
+        if (forced[t] >= 0 && forced[t] < nJ) acc[forced[t]] = 1;
+    }
+    free(ord);
+  } else if (block <= 0) {
     for (int64_t t = 0; t < nJ; ++t) acc[t] = 1;
   } else {
     int64_t nb = (nJ + block - 1) / block;
@@ -523,9 +558,11 @@ int orc_solve(const orc_csc *X, const double *y, const orc_params *P, double *w,
   memset(st, 0, sizeof(*st));
   if (X->n <= 0 || X->k <= 0 || P->lambda < 0) return ORC_EINVAL;
   int rule = P->rule;
-  if (rule < ORC_CYCLIC || rule > ORC_COLORING) return ORC_EINVAL;
-  if ((rule == ORC_SHOTGUN || rule == ORC_THREAD_GREEDY) && P->select_size <= 0) return ORC_EINVAL;
-  if (rule == ORC_THREAD_GREEDY && P->block <= 0) return ORC_EINVAL;
+  if (rule < ORC_CYCLIC || rule > ORC_TOP_GREEDY) return ORC_EINVAL;
+  if ((rule == ORC_SHOTGUN || rule == ORC_THREAD_GREEDY || rule == ORC_TOP_GREEDY) &&
+      P->select_size <= 0)
+    return ORC_EINVAL;
+  if ((rule == ORC_THREAD_GREEDY || rule == ORC_TOP_GREEDY) && P->block <= 0) return ORC_EINVAL;
   if (rule == ORC_COLORING && (!P->color || P->num_colors <= 0)) return ORC_EINVAL;
 
   int64_t n = X->n, k = X->k;
@@ -565,6 +602,7 @@ int orc_solve(const orc_csc *X, const double *y, const orc_params *P, double *w,
       for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) z[X->row_idx[p]] += w[j] * X->val[p];
 
   int64_t block = (rule == ORC_THREAD_GREEDY) ? P->block : (rule == ORC_GREEDY ? k_live : 0);
+  int64_t top = (rule == ORC_TOP_GREEDY) ? P->block : 0;
   int64_t per_epoch;
   if (rule == ORC_CYCLIC || rule == ORC_STOCHASTIC) per_epoch = k_live;
   else if (rule == ORC_COLORING) per_epoch = ncls;
@@ -579,9 +617,10 @@ int orc_solve(const orc_csc *X, const double *y, const orc_params *P, double *w,
       int64_t m = select_set(P, k_live, live, cls_off, cls_mem, ncls, e, t, J);
       if (m == 0) continue;
       int64_t nu = 0;
-      orc_step(X, y, P->loss, P->lambda, c, J, m, block, NULL, w, z, NULL, NULL, NULL, NULL, &nu);
+      orc_step(X, y, P->loss, P->lambda, c, J, m, block, top, NULL, w, z, NULL, NULL, NULL, NULL,
+               &nu);
       st->iters++;
-      st->coord_updates += block > 0 ? (m + block - 1) / block : m;
+      st->coord_updates += top > 0 ? (m < top ? m : top) : (block > 0 ? (m + block - 1) / block : m);
       st->nnz_updates += nu;
     }
     st->epochs = e + 1;

@@ -630,3 +630,76 @@ def test_rho_ignores_empty_columns_and_pstar_clamps():
     assert k1 == k2 == 13 and r1 == r2
     assert O.pstar(1000, 2.0) == 250 and O.pstar(1000, 3.0) == 166
     assert O.pstar(10, 100.0) == 1 and O.pstar(10**7, 1.0) == 1024 and O.pstar(5, 0.0) == 1
+
+
+# --------------------------------------------------------------------------
+# Thread-Greedy with global acceptance of the best |J'| (section 4.1)
+# --------------------------------------------------------------------------
+
+def test_top_greedy_reductions():
+    P, X, A, y = small_problem(90, 24, O.LOGISTIC, 41, density=0.3)
+    lam = 0.004
+    rng = np.random.default_rng(5)
+    w0 = rng.normal(size=24) * (rng.random(24) < 0.4)
+    J = rng.permutation(24)[:15].astype(np.int32)
+    # |J'| = |J| accepts everything, like Shotgun
+    w1, z1 = w0.copy(), A @ w0
+    w2, z2 = w0.copy(), A @ w0
+    O.step(X, y, O.LOGISTIC, lam, J, w1, z1)
+    r2 = O.step(X, y, O.LOGISTIC, lam, J, w2, z2, top=J.size)
+    assert r2.accepted.sum() == J.size
+    assert np.array_equal(w1, w2) and np.array_equal(z1, z2)
+    # |J'| = 1 is Greedy on J (Thread-Greedy with one block)
+    w3, z3 = w0.copy(), A @ w0
+    w4, z4 = w0.copy(), A @ w0
+    O.step(X, y, O.LOGISTIC, lam, J, w3, z3, block=J.size)
+    O.step(X, y, O.LOGISTIC, lam, J, w4, z4, top=1)
+    assert np.array_equal(w3, w4) and np.array_equal(z3, z4)
+
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_top_greedy_accepts_the_smallest_proxies(kind):
+    P, X, A, y = small_problem(120, 40, kind, 43, density=0.25)
+    lam = 0.003
+    rng = np.random.default_rng(6)
+    w0 = rng.normal(size=40) * (rng.random(40) < 0.3)
+    J = rng.permutation(40)[:31].astype(np.int32)
+    for K in (2, 7, 30):
+        w, z = w0.copy(), A @ w0
+        r = O.step(X, y, kind, lam, J, w, z, top=K)
+        # brute force: the K smallest (phi, position) pairs
+        want = np.zeros(J.size, dtype=np.int32)
+        want[np.lexsort((np.arange(J.size), r.phi))[:K]] = 1
+        assert np.array_equal(r.accepted, want)
+        # only accepted columns moved, by their proposals, and z = A w
+        moved = np.zeros(40)
+        moved[J[want == 1]] = r.delta[want == 1]
+        np.testing.assert_allclose(w, w0 + moved, rtol=0, atol=0)
+        np.testing.assert_allclose(z, A @ w, rtol=1e-12, atol=1e-12)
+
+
+def test_top_greedy_ties_go_to_the_first_position():
+    # duplicate columns give identical proposals: the earlier positions win
+    n = 30
+    rng = np.random.default_rng(2)
+    col = rng.normal(size=n)
+    A = np.stack([col] * 6 + [rng.normal(size=n) * 1e-3], axis=1)
+    X = _csc_matrix(A)
+    y = rng.normal(size=n)
+    J = np.array([5, 3, 6, 0, 4, 1, 2], dtype=np.int32)
+    w, z = np.zeros(7), np.zeros(n)
+    r = O.step(X, y, O.SQUARED, 1e-4, J, w, z, top=3)
+    assert r.accepted.tolist() == [1, 1, 0, 1, 0, 0, 0]
+
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_top_greedy_solve_reaches_the_optimum(kind):
+    P = synth.c1_ccd_logistic(scale=0.15) if kind == O.LOGISTIC else synth.dense_small(60, 90, O.SQUARED, 7, density=0.2)
+    X = O.Matrix.of(P)
+    y = P.y.astype(np.float64)
+    lam = 0.1 * O.lambda_max(X, y, P.loss)
+    ref = O.solve(X, y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=200000)
+    r = O.solve(X, y, P.loss, lam, O.TOP_GREEDY, select_size=32, block=8, seed=4, tol=1e-10,
+                max_epochs=200000)
+    assert ref.converged and r.converged
+    assert r.objective == pytest.approx(ref.objective, rel=1e-9)
