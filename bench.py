@@ -231,6 +231,15 @@ def main():
             "kkt_max": st2[-1]["kkt_max"], "block": 64,
         }
 
+        log("timing Top-Greedy solves")
+        dt3, st3, _ = run(G.TOP_GREEDY, 1, 0, block=256)
+        out["top_greedy"] = {
+            "nnz_updates_per_s": st3[-1]["nnz_updates"] / dt3,
+            "solves_per_s": 1.0 / dt3,
+            "epochs": st3[-1]["epochs"], "objective": st3[-1]["objective"],
+            "kkt_max": st3[-1]["kkt_max"], "accepted_per_iteration": 256,
+        }
+
     if not args.no_cpu_baseline:
         import oracle as O
 

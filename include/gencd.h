@@ -66,7 +66,10 @@ typedef enum {
   GENCD_SHOTGUN = 2,       /* random |J| columns, accept all */
   GENCD_THREAD_GREEDY = 3, /* random |J| columns, best proposal per block of B */
   GENCD_GREEDY = 4,        /* all columns, single best proposal */
-  GENCD_COLORING = 5       /* one colour class per iteration, accept all */
+  GENCD_COLORING = 5,      /* one colour class per iteration, accept all */
+  GENCD_TOP_GREEDY = 6     /* random |J| columns, the `block` proposals with the smallest
+                              phi over the whole window (ties: lowest position);
+                              Thread-Greedy with global acceptance, section 4.1 */
 } gencd_rule;
 
 /* flags */
@@ -91,7 +94,8 @@ typedef struct {
   int64_t select_size;   /* |J| (Shotgun, Thread-Greedy); 0: floor(k_live / (2 rho))
                             clamped to [1, 1024], rho estimated by 20 power
                             iterations (gencd_estimate_rho; section 4.1) */
-  int64_t block;         /* B, proposals per accepting block (Thread-Greedy) */
+  int64_t block;         /* B, proposals per accepting block (Thread-Greedy);
+                            |J'|, proposals accepted per iteration (Top-Greedy) */
   uint64_t seed;         /* seed of the per-epoch selection permutation */
   double kkt_tol;        /* stop when max_j KKT violation <= kkt_tol ... */
   double gap_tol;        /* ... and duality gap <= gap_tol * |objective| (0: off) */

@@ -45,7 +45,7 @@ struct ColorWs {
 
 static size_t sort_temp_bytes(int64_t items, int end_bit) {
   size_t bytes = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, static_cast<const uint64_t *>(nullptr),
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, static_cast<const uint64_t *>(nullptr),
                                      static_cast<uint64_t *>(nullptr),
                                      static_cast<const int32_t *>(nullptr),
                                      static_cast<int32_t *>(nullptr), int(items), 0, end_bit);

@@ -681,6 +681,44 @@ __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
   }
 }
 
+// Finalise the split columns among positions [lo, hi) of the window: find
+// them in parallel, then sum each one's partials (in piece order) with the
+// whole workgroup of NT threads, and write delta, phi (and g).
+template <int NT>
+__device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_t P0,
+                               int32_t *smulti, int32_t *nmulti, float *sred) {
+  for (int64_t c0 = lo; c0 < hi; c0 += NT) {
+    if (threadIdx.x == 0) *nmulti = 0;
+    __syncthreads();
+    const int64_t pp = c0 + threadIdx.x;
+    if (pp < hi && a.loff[pp + 1] - a.loff[pp] > 1) smulti[atomicAdd(nmulti, 1)] = int32_t(pp);
+    __syncthreads();
+    const int32_t cnt = *nmulti;
+    for (int32_t m = 0; m < cnt; ++m) {
+      const int32_t p = smulti[m];
+      const int32_t pf = a.loff[p], np = a.loff[p + 1] - pf;
+      float t = 0.0f;
+      for (int32_t u = threadIdx.x; u < np; u += NT) t += a.gacc[pf + u];
+      sred[threadIdx.x] = t;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        const int32_t j = a.col_of_pos[p];
+        const float g = sred[0] / a.n_f;
+        float d, ph;
+        propose_f32(g, a.c[j], a.w[j], a.lam, d, ph);
+        a.delta[p - P0] = d;
+        a.phi[p - P0] = ph;
+        if (a.gout) a.gout[p - P0] = g;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Accept for Thread-Greedy / Greedy (section 2.3): in each block of B
 // positions the first position with minimal phi.  One workgroup per block;
 // it first finalises the block's split columns from their partial sums.
@@ -695,38 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
   const int64_t nblk = (int64_t(P1 - P0) + B - 1) / B;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int64_t lo = P0 + b * B, hi = min(lo + B, int64_t(P1));
-    // finalise the block's split columns: find them in parallel, then sum
-    // each one's partials (in piece order) with the whole workgroup
-    for (int64_t c0 = lo; c0 < hi; c0 += kBlock) {
-      if (threadIdx.x == 0) nmulti = 0;
-      __syncthreads();
-      const int64_t pp = c0 + threadIdx.x;
-      if (pp < hi && a.loff[pp + 1] - a.loff[pp] > 1) smulti[atomicAdd(&nmulti, 1)] = int32_t(pp);
-      __syncthreads();
-      const int32_t cnt = nmulti;
-      for (int32_t m = 0; m < cnt; ++m) {
-        const int32_t p = smulti[m];
-        const int32_t pf = a.loff[p], np = a.loff[p + 1] - pf;
-        float t = 0.0f;
-        for (int32_t u = threadIdx.x; u < np; u += kBlock) t += a.gacc[pf + u];
-        sred[threadIdx.x] = t;
-        __syncthreads();
-        for (int off = kBlock / 2; off > 0; off >>= 1) {
-          if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
-          __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-          const int32_t j = a.col_of_pos[p];
-          const float g = sred[0] / a.n_f;
-          float d, ph;
-          propose_f32(g, a.c[j], a.w[j], a.lam, d, ph);
-          a.delta[p - P0] = d;
-          a.phi[p - P0] = ph;
-          if (a.gout) a.gout[p - P0] = g;
-        }
-        __syncthreads();
-      }
-    }
+    finalize_split<kBlock>(a, lo, hi, P0, smulti, &nmulti, sred);
     float best = INFINITY;
     int32_t bpos = INT32_MAX;
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBlock) {
@@ -761,6 +768,95 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
       atomicAdd(a.counters + 1, 1ull);
     }
     __syncthreads();
+  }
+}
+
+// Global acceptance (Thread-Greedy accepting the best |J'| of the window,
+// section 4.1): the K = min(accept_top, |window|) positions with the smallest
+// (phi, position) keys.  One workgroup finds the K-th smallest 64-bit key
+// (phi mapped to an order-preserving integer, -0 folded into +0, in the
+// high word; the window offset in the low word) by an 8-pass radix select
+// over LDS histograms, then accepts every key up to it: exactly K positions.
+constexpr int kTopThreads = 1024;
+
+__device__ __forceinline__ unsigned long long top_key(float phi, int64_t off) {
+  uint32_t u = __float_as_uint(phi);
+  if ((u & 0x7FFFFFFFu) == 0u) u = 0u;
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return (static_cast<unsigned long long>(u) << 32) | static_cast<unsigned long long>(off);
+}
+
+__global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
+  __shared__ float sred[kTopThreads];
+  __shared__ int32_t smulti[kTopThreads];
+  __shared__ int32_t nmulti;
+  __shared__ uint32_t hist[256];
+  __shared__ unsigned long long s_prefix;
+  __shared__ int64_t s_rank;
+  __shared__ unsigned long long s_cnt[2][kTopThreads / kWave];
+  int32_t P0, P1;
+  window_of(a, P0, P1);
+  const int64_t m = int64_t(P1) - P0;
+  if (m <= 0) return;
+  finalize_split<kTopThreads>(a, P0, P1, P0, smulti, &nmulti, sred);
+  const int64_t K = a.accept_top < m ? a.accept_top : m;
+  if (threadIdx.x == 0) {
+    s_prefix = 0ull;
+    s_rank = K;  // 1-based rank of the wanted key among the candidates
+  }
+  unsigned long long mask = 0ull;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const unsigned long long prefix = s_prefix;
+    for (int64_t q = threadIdx.x; q < m; q += kTopThreads) {
+      const unsigned long long key = top_key(a.phi[q], q);
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t r = s_rank, cum = 0;
+      int b = 0;
+      for (; b < 255; ++b) {
+        if (cum + int64_t(hist[b]) >= r) break;
+        cum += hist[b];
+      }
+      s_rank = r - cum;
+      s_prefix = prefix | (static_cast<unsigned long long>(b) << shift);
+    }
+    mask |= 255ull << shift;
+    __syncthreads();
+  }
+  const unsigned long long kth = s_prefix;
+  unsigned long long nnz = 0ull, cnt = 0ull;
+  for (int64_t q = threadIdx.x; q < m; q += kTopThreads) {
+    const bool take = top_key(a.phi[q], q) <= kth;
+    a.acc[q] = take ? 1 : 0;
+    if (take) {
+      const int32_t j = a.col_of_pos[P0 + q];
+      const float d = a.delta[q];
+      if (d != 0.0f) a.w[j] += d;
+      nnz += static_cast<unsigned long long>(a.col_ptr[j + 1] - a.col_ptr[j]);
+      cnt += 1ull;
+    }
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    nnz += __shfl_xor(nnz, off);
+    cnt += __shfl_xor(cnt, off);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_cnt[0][threadIdx.x / kWave] = nnz;
+    s_cnt[1][threadIdx.x / kWave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tn = 0ull, tc = 0ull;
+    for (int w = 0; w < kTopThreads / kWave; ++w) {
+      tn += s_cnt[0][w];
+      tc += s_cnt[1][w];
+    }
+    atomicAdd(a.counters + 0, tn);
+    atomicAdd(a.counters + 1, tc);
   }
 }
 
@@ -941,8 +1037,13 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
   } else if (mode == 1) {
     hipLaunchKernelGGL((k_update<GS, 1, UL>), grid, blk, 0, s, a);
   } else {
-    unsigned nb = unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
-    hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
+    if (a.accept_top > 0) {
+      hipLaunchKernelGGL(k_accept_top, dim3(1), dim3(kTopThreads), 0, s, a);
+    } else {
+      unsigned nb =
+          unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
+      hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
+    }
     hipLaunchKernelGGL((k_update<GS, 2, UL>), grid, blk, 0, s, a);
   }
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;

@@ -23,6 +23,7 @@ struct IterArgs {
   const int32_t *wbl;              // window t: long pieces [wbl[t], wbl[t+1])
   int32_t nl;                      // waves walking long pieces (set by the launcher)
   int32_t piece;                   // nonzeros per long piece
+  int64_t accept_top;              // > 0: deferred acceptance of the best accept_top of the window
   const int32_t *win_off;  // per-epoch window offsets, or null: [win_lo, win_hi)
   int32_t t, win_lo, win_hi;
   float *delta, *phi, *gacc, *gout, *wsnap;

@@ -101,7 +101,9 @@ bool csc_ok(const gencd_csc *X) {
 
 // Shotgun and Thread-Greedy with select_size 0 take |J| from the estimate.
 bool wants_rho(const gencd_params *p) {
-  return p && (p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY) && p->select_size == 0;
+  return p &&
+         (p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY || p->rule == GENCD_TOP_GREEDY) &&
+         p->select_size == 0;
 }
 
 int resolve_schedule(const gencd_params *p, int *piece, int *group) {
@@ -119,10 +121,13 @@ int params_ok(const gencd_params *p, bool need_rule) {
   if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return GENCD_ERR_INVALID_ARG;
   if (!need_rule) return GENCD_OK;
-  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_COLORING) return GENCD_ERR_INVALID_ARG;
-  if ((p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY) && p->select_size < 0)
+  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_TOP_GREEDY) return GENCD_ERR_INVALID_ARG;
+  if ((p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY ||
+       p->rule == GENCD_TOP_GREEDY) &&
+      p->select_size < 0)
     return GENCD_ERR_INVALID_ARG;
-  if (p->rule == GENCD_THREAD_GREEDY && p->block <= 0) return GENCD_ERR_INVALID_ARG;
+  if ((p->rule == GENCD_THREAD_GREEDY || p->rule == GENCD_TOP_GREEDY) && p->block <= 0)
+    return GENCD_ERR_INVALID_ARG;
   if (p->rule == GENCD_COLORING && (!p->color || p->num_colors <= 0)) return GENCD_ERR_INVALID_ARG;
   if (!(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0 || p->check_every < 0)
     return GENCD_ERR_INVALID_ARG;
@@ -261,7 +266,7 @@ bool converged(const gencd_params *p, const CheckOut &ck) {
 
 int mode_of(int rule) {
   if (rule == GENCD_COLORING) return 1;
-  if (rule == GENCD_THREAD_GREEDY || rule == GENCD_GREEDY) return 2;
+  if (rule == GENCD_THREAD_GREEDY || rule == GENCD_GREEDY || rule == GENCD_TOP_GREEDY) return 2;
   return 0;
 }
 
@@ -270,6 +275,7 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   const Ws &ws = su.ws;
   IterArgs a{};
   a.piece = su.piece;
+  a.accept_top = p->rule == GENCD_TOP_GREEDY ? p->block : 0;
   a.col_ptr = X->col_ptr;
   a.row_idx = X->row_idx;
   a.val = X->val;
@@ -360,14 +366,14 @@ struct GraphHolder {
   hipGraphExec_t exec = nullptr;
   hipStream_t cs = nullptr;  // capture stream
   void reset() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (g) hipGraphDestroy(g);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (g) (void)hipGraphDestroy(g);
     exec = nullptr;
     g = nullptr;
   }
   ~GraphHolder() {
     reset();
-    if (cs) hipStreamDestroy(cs);
+    if (cs) (void)hipStreamDestroy(cs);
   }
 };
 
@@ -376,7 +382,7 @@ struct EventPool {
   std::vector<hipEvent_t> v;
   ~EventPool() {
     for (auto e : v)
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -573,7 +579,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamEndCapture(graph.cs, &g);
         if (st) {
-          if (g) hipGraphDestroy(g);
+          if (g) (void)hipGraphDestroy(g);
           return st;
         }
         if (ce != hipSuccess) return GENCD_ERR_HIP;
@@ -609,7 +615,9 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       }
       const bool bad = !std::isfinite(ck.objective) ||
                        ck.objective > best + 1e-3 * std::fabs(best) + 1e-12;
-      if (bad && (rule == GENCD_SHOTGUN || rule == GENCD_THREAD_GREEDY) && S > 1) {
+      if (bad &&
+          (rule == GENCD_SHOTGUN || rule == GENCD_THREAD_GREEDY || rule == GENCD_TOP_GREEDY) &&
+          S > 1) {
         // Divergence guard: restore the last checked point, halve |J|.
         st = copy_f32(w, ws.w_ckpt, X->k, s);
         if (st) return st;
@@ -653,8 +661,9 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
   (void)hipGetLastError();  // launch checks below must not see an earlier error
   int st = params_ok(p, false);
   if (st) return st;
-  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_COLORING) return GENCD_ERR_INVALID_ARG;
-  if (p->rule == GENCD_THREAD_GREEDY && p->block <= 0) return GENCD_ERR_INVALID_ARG;
+  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_TOP_GREEDY) return GENCD_ERR_INVALID_ARG;
+  if ((p->rule == GENCD_THREAD_GREEDY || p->rule == GENCD_TOP_GREEDY) && p->block <= 0)
+    return GENCD_ERR_INVALID_ARG;
   if (!w || !z_hi || !z_lo || nJ < 0 || (nJ > 0 && !J)) return GENCD_ERR_INVALID_ARG;
   if (nJ > X->k) return GENCD_ERR_INVALID_ARG;
   Setup su;

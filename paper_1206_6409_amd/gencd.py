@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(HERE, "libgencd.so")
 
 OK, NOT_CONVERGED = 0, 1
 SQUARED, LOGISTIC = 0, 1
-CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING = range(6)
+CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY = range(7)
 WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE, EXACT_ACCUM = 0x1, 0x2, 0x4, 0x8, 0x10
 RULES = {"cyclic": CYCLIC, "stochastic": STOCHASTIC, "shotgun": SHOTGUN,
-         "thread_greedy": THREAD_GREEDY, "greedy": GREEDY, "coloring": COLORING}
+         "thread_greedy": THREAD_GREEDY, "greedy": GREEDY, "coloring": COLORING,
+         "top_greedy": TOP_GREEDY}
 
 
 class GencdError(RuntimeError):

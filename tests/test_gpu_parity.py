@@ -119,6 +119,8 @@ STEP_CASES = [
     ("c2", G.GREEDY, 0, 8, 1024), ("c2", G.GREEDY, 0, 4, 64),
     ("c3", G.SHOTGUN, 0, 8, 64), ("c4", G.SHOTGUN, 0, 4, 64), ("c4", G.THREAD_GREEDY, 16, 8, 64),
     ("c2", G.SHOTGUN, 0, 8, 256, G.EXACT_ACCUM), ("c2", G.THREAD_GREEDY, 64, 8, 256, G.EXACT_ACCUM),
+    ("c2", G.TOP_GREEDY, 64, 8, 256), ("c2", G.TOP_GREEDY, 1, 16, 64), ("c4", G.TOP_GREEDY, 100, 8, 64),
+    ("c1", G.TOP_GREEDY, 100000, 4, 128),
 ]
 
 
@@ -154,11 +156,12 @@ def test_step_parity(problems, case):
     wo = w.astype(np.float64)
     zo = z_hi.astype(np.float64) + z_lo.astype(np.float64)
     oblock = block if rule == G.THREAD_GREEDY else (m if rule == G.GREEDY else 0)
+    otop = min(block, m) if rule == G.TOP_GREEDY else 0
     g_gpu = res.g.cpu().numpy().astype(np.float64)
     d_gpu = res.delta.cpu().numpy().astype(np.float64)
     acc_gpu = res.accepted.cpu().numpy()
     # propose parity (state at entry)
-    probe = O.step(Xo, P.y, P.loss, lam, J, wo.copy(), zo.copy(), block=oblock)
+    probe = O.step(Xo, P.y, P.loss, lam, J, wo.copy(), zo.copy(), block=oblock, top=otop)
     gs = np.abs(probe.g).max()
     assert np.max(np.abs(g_gpu - probe.g)) <= 1e-5 * gs
     ds = max(np.abs(probe.delta).max(), 1e-30)
@@ -175,9 +178,18 @@ def test_step_parity(problems, case):
             if gpos != opos:  # near tie: accept only if the proxies agree to 1e-6
                 assert probe.phi[gpos] - probe.phi[opos] <= 1e-6 * abs(probe.phi[opos])
             forced[b] = gpos
+    elif otop > 0:
+        # the otop smallest proxies of the window; where FP32 and FP64 order
+        # differ, the GPU's extra picks must tie the oracle's last pick to 1e-6
+        assert acc_gpu.sum() == otop
+        gset, oset = np.nonzero(acc_gpu)[0], np.nonzero(probe.accepted)[0]
+        kth = np.sort(probe.phi)[otop - 1]
+        for q in np.setdiff1d(gset, oset):
+            assert probe.phi[q] - kth <= 1e-6 * abs(kth)
+        forced = gset.astype(np.int32)
     else:
         assert np.all(acc_gpu == 1)
-    O.step(Xo, P.y, P.loss, lam, J, wo, zo, block=oblock, forced=forced)
+    O.step(Xo, P.y, P.loss, lam, J, wo, zo, block=oblock, forced=forced, top=otop)
     z_gpu = zh_d.cpu().numpy().astype(np.float64) + zl_d.cpu().numpy().astype(np.float64)
     ok, worst = rel_close(z_gpu, zo, 1e-5)
     assert ok, f"z mismatch {worst}"
@@ -193,6 +205,8 @@ SOLVE_CASES = [
     ("c1", G.THREAD_GREEDY, dict(select_size=1024, block=8)),
     ("c2", G.SHOTGUN, dict(select_size=512)),
     ("c2", G.THREAD_GREEDY, dict(select_size=2048, block=16)),
+    ("c1", G.TOP_GREEDY, dict(select_size=1024, block=64)),
+    ("c2", G.TOP_GREEDY, dict(select_size=2048, block=256)),
     ("c3", G.SHOTGUN, dict(select_size=256)),
     ("c4", G.SHOTGUN, dict(select_size=256)),
     ("c1s", G.STOCHASTIC, dict()),
@@ -307,6 +321,8 @@ def test_error_paths():
 
 @pytest.mark.parametrize("name,rule,kw", [("c2", G.SHOTGUN, dict(select_size=512)),
                                           ("c2", G.THREAD_GREEDY, dict(select_size=2048, block=16)),
+    ("c1", G.TOP_GREEDY, dict(select_size=1024, block=64)),
+    ("c2", G.TOP_GREEDY, dict(select_size=2048, block=256)),
                                           ("c4", G.SHOTGUN, dict(select_size=256))])
 def test_graph_path_matches_plain(problems, optima, name, rule, kw):
     """The captured epoch is replayed once per epoch, with the eager FP64
