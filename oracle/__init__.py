@@ -31,7 +31,7 @@ class _Params(C.Structure):
     _fields_ = [("loss", C.c_int32), ("rule", C.c_int32), ("lam", C.c_double),
                 ("select_size", C.c_int64), ("block", C.c_int64), ("seed", C.c_uint64),
                 ("tol", C.c_double), ("max_epochs", C.c_int64), ("check_every", C.c_int64),
-                ("color", C.c_void_p), ("num_colors", C.c_int32)]
+                ("color", C.c_void_p), ("num_colors", C.c_int32), ("improve", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -67,7 +67,7 @@ def lib():
         L.orc_propose.restype = None
         L.orc_propose.argtypes = [D, D, D, D, P, P]
         L.orc_step.restype = I32
-        L.orc_step.argtypes = [P, P, I32, D, P, P, I64, I64, I64, P, P, P, P, P, P, P, P]
+        L.orc_step.argtypes = [P, P, I32, D, P, P, I64, I64, I64, I32, P, P, P, P, P, P, P, P]
         L.orc_check.restype = None
         L.orc_check.argtypes = [P, P, I32, D, P, P, P, P, P, P]
         L.orc_duality_gap.restype = D
@@ -158,7 +158,7 @@ class StepResult:
     nnz_updates: int
 
 
-def step(X: Matrix, y, kind, lam, J, w, z, block=0, forced=None, c=None, top=0):
+def step(X: Matrix, y, kind, lam, J, w, z, block=0, forced=None, c=None, top=0, improve=0):
     """One Jacobi iteration on J; w and z (float64) are updated in place.
     top > 0 accepts the `top` best proposals of the window (forced: the
     accepted positions instead); block > 0 the best of each block."""
@@ -172,7 +172,8 @@ def step(X: Matrix, y, kind, lam, J, w, z, block=0, forced=None, c=None, top=0):
     f = None if forced is None else np.ascontiguousarray(forced, dtype=np.int32)
     nu = C.c_int64()
     assert w.dtype == np.float64 and z.dtype == np.float64
-    st = lib().orc_step(X.ref, _p(y), kind, float(lam), _p(c), _p(J), m, int(block), int(top), _p(f),
+    st = lib().orc_step(X.ref, _p(y), kind, float(lam), _p(c), _p(J), m, int(block), int(top),
+                        int(improve), _p(f),
                         _p(w), _p(z), _p(g), _p(d), _p(ph), _p(acc), C.byref(nu))
     if st != 0:
         raise ValueError(f"orc_step failed: {st}")
@@ -250,7 +251,7 @@ class SolveResult:
 
 
 def solve(X: Matrix, y, kind, lam, rule, select_size=1, block=1, seed=0, tol=1e-6,
-          max_epochs=1000, check_every=1, colors=None, w0=None):
+          max_epochs=1000, check_every=1, colors=None, w0=None, improve=0):
     y = np.ascontiguousarray(y, dtype=np.float64)
     w = np.zeros(X.k) if w0 is None else np.array(w0, dtype=np.float64)
     z = np.zeros(X.n)
@@ -261,7 +262,7 @@ def solve(X: Matrix, y, kind, lam, rule, select_size=1, block=1, seed=0, tol=1e-
         nc = int(col.max()) + 1 if col.size else 0
     prm = _Params(kind, rule, float(lam), int(select_size), int(block), C.c_uint64(seed).value,
                   float(tol), int(max_epochs), int(check_every),
-                  _p(col).value if col is not None else None, nc)
+                  _p(col).value if col is not None else None, nc, int(improve))
     st = _Stats()
     rc = lib().orc_solve(X.ref, _p(y), C.byref(prm), _p(w), _p(z), C.byref(st))
     if rc < 0:

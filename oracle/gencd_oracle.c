@@ -77,6 +77,7 @@ typedef struct {
   int64_t check_every; /* epochs between convergence checks */
   const int32_t *color; /* Coloring: colour of every column */
   int32_t num_colors;
+  int32_t improve;      /* extra quadratic-approximation steps per accepted proposal */
 } orc_params;
 
 typedef struct {
@@ -225,10 +226,35 @@ static int cmp_top(const void *a, const void *b) {
  *   block > 0: in each block of `block` consecutive positions the first
  *              position with minimal phi (Thread-Greedy, Greedy);
  *   otherwise every proposal (Shotgun, Coloring, CCD). */
+/* "Improve delta_j" (Algorithm 3, section 4.1): up to `steps` further steps
+ * of the quadratic approximation on the one-dimensional objective
+ *   f_j(d) = (1/n) sum_i l(y_i, z_i + d x_ij) + lambda |w_j + d|
+ * along column j, from d = delta and the state z of the iteration start:
+ *   g = (1/n) sum_i x_ij l'(y_i, z_i + d x_ij),
+ *   d <- d + (Eq. 7 increment at the point w_j + d with gradient g).
+ * An increment of exactly zero is a fixed point, so the loop stops there. */
+static double improve_delta(const orc_csc *X, const double *y, int loss, double lambda, double c,
+                            int64_t j, double wj, const double *z, double d, int32_t steps) {
+  if (d == 0.0) return d;
+  for (int32_t s = 0; s < steps; ++s) {
+    double g = 0.0;
+    for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) {
+      int32_t i = X->row_idx[p];
+      g += X->val[p] * orc_dloss(loss, y[i], z[i] + d * X->val[p]);
+    }
+    g /= (double)X->n;
+    double inc, unused;
+    orc_propose(g, c, wj + d, lambda, &inc, &unused);
+    if (inc == 0.0) break;
+    d += inc;
+  }
+  return d;
+}
+
 int orc_step(const orc_csc *X, const double *y, int loss, double lambda, const double *c,
-             const int32_t *J, int64_t nJ, int64_t block, int64_t top, const int32_t *forced,
-             double *w, double *z, double *g_out, double *d_out, double *p_out, int32_t *acc_out,
-             int64_t *nnz_updates) {
+             const int32_t *J, int64_t nJ, int64_t block, int64_t top, int32_t improve,
+             const int32_t *forced, double *w, double *z, double *g_out, double *d_out,
+             double *p_out, int32_t *acc_out, int64_t *nnz_updates) {
   if (nJ < 0) return ORC_EINVAL;
   for (int64_t t = 0; t < nJ; ++t)
     if (J[t] < 0 || J[t] >= X->k) return ORC_EINVAL;
@@ -285,7 +311,11 @@ int orc_step(const orc_csc *X, const double *y, int loss, double lambda, const d
       if (best >= lo && best < hi) acc[best] = 1;
     }
   }
-  /* Update */
+  /* Update: every accepted proposal is improved against the iteration-start
+   * state first (the loop of Algorithm 3 is parallel), then applied */
+  if (improve > 0)
+    for (int64_t t = 0; t < nJ; ++t)
+      if (acc[t]) d[t] = improve_delta(X, y, loss, lambda, c[J[t]], J[t], w[J[t]], z, d[t], improve);
   int64_t nu = 0;
   for (int64_t t = 0; t < nJ; ++t) {
     if (!acc[t]) continue;
@@ -617,8 +647,8 @@ int orc_solve(const orc_csc *X, const double *y, const orc_params *P, double *w,
       int64_t m = select_set(P, k_live, live, cls_off, cls_mem, ncls, e, t, J);
       if (m == 0) continue;
       int64_t nu = 0;
-      orc_step(X, y, P->loss, P->lambda, c, J, m, block, top, NULL, w, z, NULL, NULL, NULL, NULL,
-               &nu);
+      orc_step(X, y, P->loss, P->lambda, c, J, m, block, top, P->improve, NULL, w, z, NULL, NULL,
+               NULL, NULL, &nu);
       st->iters++;
       st->coord_updates += top > 0 ? (m < top ? m : top) : (block > 0 ? (m + block - 1) / block : m);
       st->nnz_updates += nu;

@@ -703,3 +703,93 @@ def test_top_greedy_solve_reaches_the_optimum(kind):
                 max_epochs=200000)
     assert ref.converged and r.converged
     assert r.objective == pytest.approx(ref.objective, rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# "Improve delta_j": extra quadratic-approximation steps per accepted
+# proposal (Algorithm 3, section 4.1)
+# --------------------------------------------------------------------------
+
+def _subgradient_gap(A, y, kind, lam, w, z, j, d):
+    """Distance of 0 from the subdifferential of the 1-D objective along
+    column j at w_j + d (from the iteration-start z)."""
+    n = A.shape[0]
+    t = z + d * A[:, j]
+    if kind == O.SQUARED:
+        g = A[:, j] @ (t - y) / n
+    else:
+        g = A[:, j] @ (-y / (1.0 + np.exp(y * t))) / n
+    wj = w[j] + d
+    if wj != 0.0:
+        return abs(g + lam * np.sign(wj))
+    return max(abs(g) - lam, 0.0)
+
+
+def test_improve_is_exact_for_squared_loss():
+    # the curvature c_j is the exact second derivative: the first step is
+    # already the 1-D minimiser and extra steps change nothing
+    P, X, A, y = small_problem(70, 18, O.SQUARED, 51, density=0.4)
+    rng = np.random.default_rng(1)
+    w0 = rng.normal(size=18) * (rng.random(18) < 0.5)
+    J = rng.permutation(18)[:9].astype(np.int32)
+    w1, z1 = w0.copy(), A @ w0
+    w2, z2 = w0.copy(), A @ w0
+    O.step(X, y, O.SQUARED, 0.01, J, w1, z1)
+    O.step(X, y, O.SQUARED, 0.01, J, w2, z2, improve=50)
+    np.testing.assert_allclose(w2, w1, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_improve_reaches_each_coordinate_minimiser(seed):
+    # logistic: enough extra steps solve every accepted 1-D problem from the
+    # iteration-start z (Jacobi), checked by the subgradient condition and by
+    # bisection on the 1-D derivative
+    P, X, A, y = small_problem(80, 16, O.LOGISTIC, 60 + seed, density=0.35)
+    lam = 0.003
+    rng = np.random.default_rng(seed)
+    w0 = rng.normal(size=16) * (rng.random(16) < 0.5)
+    J = rng.permutation(16)[:8].astype(np.int32)
+    w, z0 = w0.copy(), A @ w0
+    z = z0.copy()
+    O.step(X, y, O.LOGISTIC, lam, J, w, z, improve=500)
+    for j in J:
+        d = w[j] - w0[j]
+        assert _subgradient_gap(A, y, O.LOGISTIC, lam, w0, z0, j, d) < 1e-10
+        # bisection on the smooth part's derivative where w_j + d keeps its sign
+        if w[j] != 0.0:
+            s = np.sign(w[j])
+            f = lambda dd: A[:, j] @ (-y / (1.0 + np.exp(y * (z0 + dd * A[:, j])))) / A.shape[0] + lam * s
+            lo, hi = d - 1.0, d + 1.0
+            assert f(lo) < 0 < f(hi)
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                lo, hi = (mid, hi) if f(mid) < 0 else (lo, mid)
+            assert abs(d - 0.5 * (lo + hi)) < 1e-9
+    np.testing.assert_allclose(z, A @ w, rtol=1e-12, atol=1e-12)
+
+
+def test_improve_never_does_worse_than_one_step():
+    # each extra step minimises a majoriser of the 1-D objective, so a single
+    # coordinate step with improvement ends no higher than without
+    P, X, A, y = small_problem(90, 12, O.LOGISTIC, 71, density=0.5)
+    lam = 0.002
+    rng = np.random.default_rng(9)
+    w0 = rng.normal(size=12)
+    for j in range(12):
+        J = np.array([j], dtype=np.int32)
+        w1, z1 = w0.copy(), A @ w0
+        w2, z2 = w0.copy(), A @ w0
+        O.step(X, y, O.LOGISTIC, lam, J, w1, z1)
+        O.step(X, y, O.LOGISTIC, lam, J, w2, z2, improve=30)
+        assert dense_objective(A, y, O.LOGISTIC, lam, w2) <= dense_objective(A, y, O.LOGISTIC, lam, w1) + 1e-15
+
+
+def test_improved_solve_reaches_the_optimum():
+    P = synth.c1_ccd_logistic(scale=0.15)
+    X = O.Matrix.of(P)
+    y = P.y.astype(np.float64)
+    lam = 0.1 * O.lambda_max(X, y, P.loss)
+    ref = O.solve(X, y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=200000)
+    r = O.solve(X, y, P.loss, lam, O.SHOTGUN, select_size=32, seed=4, tol=1e-10,
+                max_epochs=200000, improve=500)
+    assert r.converged and r.objective == pytest.approx(ref.objective, rel=1e-9)
