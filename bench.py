@@ -240,6 +240,15 @@ def main():
             "kkt_max": st3[-1]["kkt_max"], "accepted_per_iteration": 256,
         }
 
+        log("timing Shotgun solves with 500 improve-delta steps")
+        dt4, st4, _ = run(G.SHOTGUN, 1, 0, improve=500)
+        out["shotgun_improve500"] = {
+            "nnz_updates_per_s": st4[-1]["nnz_updates"] / dt4,
+            "solves_per_s": 1.0 / dt4,
+            "epochs": st4[-1]["epochs"], "objective": st4[-1]["objective"],
+            "kkt_max": st4[-1]["kkt_max"],
+        }
+
     if not args.no_cpu_baseline:
         import oracle as O
 

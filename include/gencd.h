@@ -108,6 +108,12 @@ typedef struct {
                             64..2^22); 0 = library default */
   int32_t group;         /* lanes per short column (4, 8, 16 or 32); columns of
                             at most 4 * group nonzeros are short; 0 = default */
+  int32_t improve_steps; /* "Improve delta_j" (Algorithm 3, section 4.1): up to this
+                            many further quadratic-approximation steps on each
+                            accepted proposal's 1-D objective, from the state at
+                            the start of the iteration; stops early at a fixed
+                            point.  0 = off (default); the paper used 500.
+                            gencd_solve / gencd_step only (0..1000000) */
 } gencd_params;
 
 /* Host-side statistics filled by the solve calls. */

@@ -650,7 +650,12 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
   a.delta[slot] = d;
   a.phi[slot] = ph;
   if (a.gout) a.gout[slot] = g;
-  if (MODE != 2 && d != 0.0f) a.w[j] = wj + d;
+  if (MODE != 2) {
+    if (a.improve > 0)
+      a.wsnap[slot] = wj;  // k_improve writes w_j from the improved increment
+    else if (d != 0.0f)
+      a.w[j] = wj + d;
+  }
 }
 
 // Propose (Algorithm 2 / 4).  A column that fits in one piece is finalised
@@ -763,7 +768,10 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
       a.acc[p - P0] = 1;
       const int32_t j = a.col_of_pos[p];
       const float d = a.delta[p - P0];
-      if (d != 0.0f) a.w[j] += d;
+      if (a.improve > 0)
+        a.wsnap[p - P0] = a.w[j];
+      else if (d != 0.0f)
+        a.w[j] += d;
       atomicAdd(a.counters + 0, (unsigned long long)(a.col_ptr[j + 1] - a.col_ptr[j]));
       atomicAdd(a.counters + 1, 1ull);
     }
@@ -835,7 +843,10 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
     if (take) {
       const int32_t j = a.col_of_pos[P0 + q];
       const float d = a.delta[q];
-      if (d != 0.0f) a.w[j] += d;
+      if (a.improve > 0)
+        a.wsnap[q] = a.w[j];
+      else if (d != 0.0f)
+        a.w[j] += d;
       nnz += static_cast<unsigned long long>(a.col_ptr[j + 1] - a.col_ptr[j]);
       cnt += 1ull;
     }
@@ -933,8 +944,8 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       if (MODE == 2) {
         if (!a.acc[slot]) continue;
         d = a.delta[slot];
-      } else if (desc_single(dsc)) {
-        d = a.delta[slot];
+      } else if (desc_single(dsc) || a.improve > 0) {
+        d = a.delta[slot];  // single piece, or improved by k_improve
       } else {
         const int32_t pf = a.loff[dsc.z], np = a.loff[dsc.z + 1] - pf;
         const int32_t j = dsc.y;
@@ -1011,10 +1022,89 @@ int launch_unpack_state(int64_t n, const float4 *zs, float *z_hi, float *z_lo, h
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
+// "Improve delta_j" (Algorithm 3, section 4.1): one wave per accepted
+// position of the window runs up to `improve` further quadratic-
+// approximation steps on the column's 1-D objective from the state at the
+// start of the iteration:
+//   g = (1/n) sum_i x_ij l'(y_i, z_i + d x_ij),  d += Eq. 7 increment at w_j + d,
+// stopping at a fixed point (an increment of exactly zero).  The first
+// kImproveRegs * 64 entries stay in registers across steps; longer columns
+// re-read the rest each step.  Split columns (accept-all rules) get their
+// first increment here from the partial sums.  Writes delta and w_j =
+// wsnap + d (Propose / Accept left w_j untouched and its value in wsnap).
+constexpr int kImproveRegs = 4;
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_improve(IterArgs a) {
+  int32_t P0, P1;
+  window_of(a, P0, P1);
+  const int lane = int(threadIdx.x) & (kWave - 1);
+  const int64_t nw = int64_t(gridDim.x) * (kBlock / kWave);
+  for (int64_t p = P0 + (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave; p < P1; p += nw) {
+    const int64_t slot = p - P0;
+    if (MODE == 2 && !a.acc[slot]) continue;
+    const int32_t j = a.col_of_pos[p];
+    const int64_t cb = a.col_ptr[j];
+    const int64_t len = a.col_ptr[j + 1] - cb;
+    const float cj = a.c[j];
+    const float w0 = a.wsnap[slot];
+    float d;
+    if (MODE != 2 && a.loff[p + 1] - a.loff[p] > 1) {
+      const int32_t pf = a.loff[p], np = a.loff[p + 1] - pf;
+      const float g = split_sum(a.gacc, pf, np, lane) / a.n_f;
+      float ph;
+      propose_f32(g, cj, w0, a.lam, d, ph);
+      if (lane == 0) {
+        a.phi[slot] = ph;
+        if (a.gout) a.gout[slot] = g;
+      }
+    } else {
+      d = a.delta[slot];
+    }
+    if (d != 0.0f) {
+      int32_t ri[kImproveRegs];
+      float vv[kImproveRegs], zb[kImproveRegs], yy[kImproveRegs];
+#pragma unroll
+      for (int u = 0; u < kImproveRegs; ++u) {
+        const int64_t e = int64_t(u) * kWave + lane;
+        ri[u] = e < len ? a.row_idx[cb + e] : -1;
+        vv[u] = e < len ? a.val[cb + e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kImproveRegs; ++u) {
+        const float4 zr = a.zs[ri[u] >= 0 ? ri[u] : 0];
+        zb[u] = zr.x + zr.y;
+        yy[u] = zr.z;
+      }
+      for (int32_t s = 0; s < a.improve; ++s) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kImproveRegs; ++u)
+          if (ri[u] >= 0) sum += vv[u] * dloss_f32(a.loss, yy[u], zb[u] + d * vv[u]);
+        for (int64_t e = int64_t(kImproveRegs) * kWave + lane; e < len; e += kWave) {
+          const int32_t i = a.row_idx[cb + e];
+          const float v = a.val[cb + e];
+          const float4 zr = a.zs[i];
+          sum += v * dloss_f32(a.loss, zr.z, (zr.x + zr.y) + d * v);
+        }
+        const float g = group_sum<kWave>(sum) / a.n_f;  // identical in every lane
+        float inc, ph;
+        propose_f32(g, cj, w0 + d, a.lam, inc, ph);
+        if (inc == 0.0f) break;
+        d += inc;
+      }
+    }
+    if (lane == 0) {
+      a.delta[slot] = d;
+      a.w[j] = w0 + d;
+    }
+  }
+}
+
 template <int GS, int UL>
 static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsigned blocks,
-                              int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
-                              hipEvent_t ev1) {
+                              int64_t nblocks_accept, unsigned improve_blocks, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 grid(blocks), blk(kBlock);
   // with events, Propose is launched through the extension that stamps the
   // kernel's own start and end (no dispatch gap in the measured interval)
@@ -1033,8 +1123,12 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
     hipLaunchKernelGGL((k_propose<GS, 2, UL>), grid, blk, 0, s, a);
   }
   if (mode == 0) {
+    if (a.improve > 0)
+      hipLaunchKernelGGL(k_improve<0>, dim3(improve_blocks), blk, 0, s, a);
     hipLaunchKernelGGL((k_update<GS, 0, UL>), grid, blk, 0, s, a);
   } else if (mode == 1) {
+    if (a.improve > 0)
+      hipLaunchKernelGGL(k_improve<1>, dim3(improve_blocks), blk, 0, s, a);
     hipLaunchKernelGGL((k_update<GS, 1, UL>), grid, blk, 0, s, a);
   } else {
     if (a.accept_top > 0) {
@@ -1044,6 +1138,8 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
           unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
       hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
     }
+    if (a.improve > 0)
+      hipLaunchKernelGGL(k_improve<2>, dim3(improve_blocks), blk, 0, s, a);
     hipLaunchKernelGGL((k_update<GS, 2, UL>), grid, blk, 0, s, a);
   }
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
@@ -1051,11 +1147,13 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
 
 template <int GS>
 static int launch_iteration_u(const IterArgs &a, int mode, int64_t block, unsigned blocks,
-                              int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
-                              hipEvent_t ev1) {
+                              int64_t nblocks_accept, unsigned improve_blocks, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
   if (a.piece <= kWave * kUnroll)
-    return launch_iteration_g<GS, kUnroll>(a, mode, block, blocks, nblocks_accept, s, ev0, ev1);
-  return launch_iteration_g<GS, 2 * kUnroll>(a, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    return launch_iteration_g<GS, kUnroll>(a, mode, block, blocks, nblocks_accept, improve_blocks,
+                                           s, ev0, ev1);
+  return launch_iteration_g<GS, 2 * kUnroll>(a, mode, block, blocks, nblocks_accept,
+                                             improve_blocks, s, ev0, ev1);
 }
 
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
@@ -1066,11 +1164,16 @@ int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int6
   int32_t nl;
   two_class_grid(short_bound, long_bound, group, &blocks, &nl);
   b.nl = nl;
+  // k_improve: one wave per window position (grid-stride beyond 16384 blocks)
+  const int64_t ib = (short_bound + kBlock / kWave - 1) / (kBlock / kWave);
+  const unsigned iblocks = unsigned(ib < 1 ? 1 : (ib > 16384 ? 16384 : ib));
   switch (group) {
-    case 4: return launch_iteration_u<4>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
-    case 8: return launch_iteration_u<8>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
-    case 16: return launch_iteration_u<16>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
-    default: return launch_iteration_u<32>(b, mode, block, blocks, nblocks_accept, s, ev0, ev1);
+    case 4: return launch_iteration_u<4>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
+    case 8: return launch_iteration_u<8>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
+    case 16:
+      return launch_iteration_u<16>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
+    default:
+      return launch_iteration_u<32>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
   }
 }
 

@@ -24,6 +24,7 @@ struct IterArgs {
   int32_t nl;                      // waves walking long pieces (set by the launcher)
   int32_t piece;                   // nonzeros per long piece
   int64_t accept_top;              // > 0: deferred acceptance of the best accept_top of the window
+  int32_t improve;                 // extra quadratic-approximation steps per accepted proposal
   const int32_t *win_off;  // per-epoch window offsets, or null: [win_lo, win_hi)
   int32_t t, win_lo, win_hi;
   float *delta, *phi, *gacc, *gout, *wsnap;

@@ -654,7 +654,7 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
   auto t0 = std::chrono::steady_clock::now();
   if (!X || !p || !lambdas || L <= 0 || !W || !stats) return GENCD_ERR_INVALID_ARG;
   if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
-  if (p->rule != GENCD_SHOTGUN) return GENCD_ERR_UNSUPPORTED;
+  if (p->rule != GENCD_SHOTGUN || p->improve_steps != 0) return GENCD_ERR_UNSUPPORTED;
   if (p->select_size <= 0 || !(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0)
     return GENCD_ERR_INVALID_ARG;
   if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;

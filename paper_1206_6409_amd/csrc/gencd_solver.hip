@@ -120,6 +120,7 @@ int params_ok(const gencd_params *p, bool need_rule) {
   if (!p) return GENCD_ERR_INVALID_ARG;
   if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return GENCD_ERR_INVALID_ARG;
+  if (p->improve_steps < 0 || p->improve_steps > 1000000) return GENCD_ERR_INVALID_ARG;
   if (!need_rule) return GENCD_OK;
   if (p->rule < GENCD_CYCLIC || p->rule > GENCD_TOP_GREEDY) return GENCD_ERR_INVALID_ARG;
   if ((p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY ||
@@ -276,6 +277,7 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   IterArgs a{};
   a.piece = su.piece;
   a.accept_top = p->rule == GENCD_TOP_GREEDY ? p->block : 0;
+  a.improve = p->improve_steps;
   a.col_ptr = X->col_ptr;
   a.row_idx = X->row_idx;
   a.val = X->val;
