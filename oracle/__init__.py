@@ -18,7 +18,7 @@ import numpy as np
 from . import build as _build
 
 SQUARED, LOGISTIC = 0, 1
-CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY = range(7)
+CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY, BLOCK_SHOTGUN = range(8)
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -77,6 +77,9 @@ def lib():
         L.orc_rho.argtypes = [P, I32, P, P]
         L.orc_pstar.restype = I64
         L.orc_pstar.argtypes = [I64, D, I64]
+        L.orc_block_base.restype = I64
+        L.orc_block_base.argtypes = [P, C.c_uint64, P]
+        L.orc_block_pstar.argtypes = [P, C.c_uint64, I64, I32, P, P]
         L.orc_color.argtypes = [I64, I64, P, P, I32, P, P, P]
         L.orc_solve.restype = I32
         L.orc_solve.argtypes = [P, P, P, P, P, P]
@@ -220,6 +223,24 @@ def rho(X: Matrix, iters=20):
 def pstar(k_live, rho_est, cap=1024):
     """Selection size floor(k_live / (2 rho)) clamped to [1, cap]."""
     return int(lib().orc_pstar(int(k_live), float(rho_est), int(cap)))
+
+
+def block_base(X: Matrix, seed):
+    """Preset order of the non-empty columns; block b is the range
+    [b k_live / nb, (b+1) k_live / nb) of it."""
+    out = np.zeros(max(X.k, 1), dtype=np.int32)
+    kl = lib().orc_block_base(X.ref, C.c_uint64(seed).value, _p(out))
+    return out[:kl]
+
+
+def block_pstar(X: Matrix, seed, nb, iters=20):
+    """(rho_b, P_b*) of every preset block."""
+    rho = np.zeros(nb)
+    ps = np.zeros(nb, dtype=np.int64)
+    st = lib().orc_block_pstar(X.ref, C.c_uint64(seed).value, int(nb), int(iters), _p(rho), _p(ps))
+    if st != 0:
+        raise ValueError(f"orc_block_pstar failed: {st}")
+    return rho, ps
 
 
 def color(n, k, col_ptr, row_idx, order_mode=0):

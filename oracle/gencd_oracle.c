@@ -57,6 +57,7 @@
 #define ORC_GREEDY 4
 #define ORC_COLORING 5
 #define ORC_TOP_GREEDY 6 /* Thread-Greedy accepting the best |J'| of the window */
+#define ORC_BLOCK_SHOTGUN 7 /* Shotgun inside preset blocks, |J| = P_b* per block */
 
 typedef struct {
   int64_t n, k, nnz;
@@ -438,12 +439,15 @@ double orc_duality_gap(const orc_csc *X, const double *y, int loss, double lambd
  *   u = G v,  rho_t = ||u||_2,  v <- u / rho_t,   t = 1..iters.
  * Returns rho_iters (0 if every column is empty); hist[t-1] = rho_t when hist
  * is non-null; *k_live receives the number of non-empty columns. */
-double orc_rho(const orc_csc *X, int32_t iters, double *hist, int64_t *k_live) {
+/* The same restricted to the columns with in_set[j] != 0 (all when NULL). */
+double orc_rho_subset(const orc_csc *X, const uint8_t *in_set, int32_t iters, double *hist,
+                      int64_t *k_live) {
   int64_t n = X->n, k = X->k, kl = 0;
   double *dinv = (double *)calloc((size_t)k, sizeof(double)); /* D^{-1/2}, 0 on empty columns */
   double *v = (double *)calloc((size_t)k, sizeof(double));
   double *s = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
   for (int64_t j = 0; j < k; ++j) {
+    if (in_set && !in_set[j]) continue;
     double q = 0.0;
     for (int64_t p = X->col_ptr[j]; p < X->col_ptr[j + 1]; ++p) q += X->val[p] * X->val[p];
     if (q > 0.0) {
@@ -482,6 +486,10 @@ double orc_rho(const orc_csc *X, int32_t iters, double *hist, int64_t *k_live) {
   return rho;
 }
 
+double orc_rho(const orc_csc *X, int32_t iters, double *hist, int64_t *k_live) {
+  return orc_rho_subset(X, NULL, iters, hist, k_live);
+}
+
 /* Selection size from the estimate: floor(k_live / (2 rho)), clamped to
  * [1, cap]. */
 int64_t orc_pstar(int64_t k_live, double rho, int64_t cap) {
@@ -490,6 +498,62 @@ int64_t orc_pstar(int64_t k_live, double rho, int64_t cap) {
   if (q < 1.0) return 1;
   if (q > (double)cap) return cap;
   return (int64_t)q;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block Shotgun (section 7): preset random blocks with their own P_b*        */
+/* ------------------------------------------------------------------------ */
+
+/* Key of the preset partition and of the within-block orders. */
+static uint64_t block_seed(uint64_t seed, int64_t b) {
+  return orc_mix64(seed ^ orc_mix64(0x626c6f636b73ull + (uint64_t)(b + 1)));
+}
+
+/* Preset blocks: the non-empty columns in the order of the seeded
+ * permutation (epoch 0 of block_seed(seed, -1)) are cut into nb contiguous
+ * ranges [b k_live / nb, (b+1) k_live / nb).  base[q] is the column at
+ * preset position q (k_live entries); returns k_live. */
+int64_t orc_block_base(const orc_csc *X, uint64_t seed, int32_t *base) {
+  int64_t kl = 0;
+  int32_t *live = (int32_t *)malloc(sizeof(int32_t) * (size_t)(X->k > 0 ? X->k : 1));
+  for (int64_t j = 0; j < X->k; ++j)
+    if (X->col_ptr[j + 1] > X->col_ptr[j]) live[kl++] = (int32_t)j;
+  for (int64_t q = 0; q < kl; ++q) base[q] = live[orc_perm(kl, block_seed(seed, -1), 0, q)];
+  free(live);
+  return kl;
+}
+
+static int64_t block_lo(int64_t b, int64_t kl, int64_t nb) { return b * kl / nb; }
+
+/* rho_b (power iteration, `iters` steps) and P_b* = floor(k_b / (2 rho_b))
+ * clamped to [1, k_b] for every preset block; nb in [1, k_live]. */
+int orc_block_pstar(const orc_csc *X, uint64_t seed, int64_t nb, int32_t iters, double *rho_out,
+                    int64_t *pstar_out) {
+  int32_t *base = (int32_t *)malloc(sizeof(int32_t) * (size_t)(X->k > 0 ? X->k : 1));
+  uint8_t *in_set = (uint8_t *)calloc((size_t)X->k, 1);
+  int64_t kl = orc_block_base(X, seed, base);
+  if (nb < 1 || nb > kl) {
+    free(base);
+    free(in_set);
+    return ORC_EINVAL;
+  }
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t lo = block_lo(b, kl, nb), hi = block_lo(b + 1, kl, nb);
+    for (int64_t q = lo; q < hi; ++q) in_set[base[q]] = 1;
+    int64_t kb = 0;
+    double r = orc_rho_subset(X, in_set, iters, NULL, &kb);
+    for (int64_t q = lo; q < hi; ++q) in_set[base[q]] = 0;
+    int64_t p = 1;
+    if (r > 0.0) {
+      double f = floor((double)kb / (2.0 * r));
+      p = f < 1.0 ? 1 : (f > (double)kb ? kb : (int64_t)f);
+    }
+    rho_out[b] = r;
+    pstar_out[b] = p;
+  }
+  free(base);
+  free(in_set);
+  return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -588,7 +652,8 @@ int orc_solve(const orc_csc *X, const double *y, const orc_params *P, double *w,
   memset(st, 0, sizeof(*st));
   if (X->n <= 0 || X->k <= 0 || P->lambda < 0) return ORC_EINVAL;
   int rule = P->rule;
-  if (rule < ORC_CYCLIC || rule > ORC_TOP_GREEDY) return ORC_EINVAL;
+  if (rule < ORC_CYCLIC || rule > ORC_BLOCK_SHOTGUN) return ORC_EINVAL;
+  if (rule == ORC_BLOCK_SHOTGUN && P->block <= 0) return ORC_EINVAL;
   if ((rule == ORC_SHOTGUN || rule == ORC_THREAD_GREEDY || rule == ORC_TOP_GREEDY) &&
       P->select_size <= 0)
     return ORC_EINVAL;
@@ -633,16 +698,47 @@ int orc_solve(const orc_csc *X, const double *y, const orc_params *P, double *w,
 
   int64_t block = (rule == ORC_THREAD_GREEDY) ? P->block : (rule == ORC_GREEDY ? k_live : 0);
   int64_t top = (rule == ORC_TOP_GREEDY) ? P->block : 0;
+  /* Block Shotgun: preset blocks and their P_b* (20 power iterations) */
+  int64_t nblk = 0;
+  int32_t *bbase = NULL;
+  int64_t *bp = NULL;
+  double *brho = NULL;
+  if (rule == ORC_BLOCK_SHOTGUN && k_live > 0) {
+    nblk = P->block < k_live ? P->block : k_live;
+    bbase = (int32_t *)malloc(sizeof(int32_t) * (size_t)k_live);
+    bp = (int64_t *)malloc(sizeof(int64_t) * (size_t)nblk);
+    brho = (double *)malloc(sizeof(double) * (size_t)nblk);
+    orc_block_base(X, P->seed, bbase);
+    orc_block_pstar(X, P->seed, nblk, 20, brho, bp);
+  }
   int64_t per_epoch;
   if (rule == ORC_CYCLIC || rule == ORC_STOCHASTIC) per_epoch = k_live;
   else if (rule == ORC_COLORING) per_epoch = ncls;
   else if (rule == ORC_GREEDY) per_epoch = 1;
+  else if (rule == ORC_BLOCK_SHOTGUN) per_epoch = 0; /* windows come from the blocks */
   else per_epoch = (k_live + P->select_size - 1) / P->select_size;
   int64_t check_every = P->check_every > 0 ? P->check_every : 1;
 
   int status = ORC_NOT_CONVERGED;
   double last_obj = INFINITY;
   for (int64_t e = 0; e < P->max_epochs && k_live > 0; ++e) {
+    /* Block Shotgun epoch: blocks in a per-epoch permuted order; inside
+     * block b its members in a per-epoch permuted order, windows of P_b* */
+    for (int64_t u = 0; u < nblk; ++u) {
+      int64_t b = orc_perm(nblk, P->seed, e, u);
+      int64_t lo = block_lo(b, k_live, nblk), kb = block_lo(b + 1, k_live, nblk) - lo;
+      for (int64_t t0 = 0; t0 < kb; t0 += bp[b]) {
+        int64_t m = kb - t0 < bp[b] ? kb - t0 : bp[b];
+        for (int64_t i = 0; i < m; ++i)
+          J[i] = bbase[lo + orc_perm(kb, block_seed(P->seed, b), e, t0 + i)];
+        int64_t nu = 0;
+        orc_step(X, y, P->loss, P->lambda, c, J, m, 0, 0, P->improve, NULL, w, z, NULL, NULL,
+                 NULL, NULL, &nu);
+        st->iters++;
+        st->coord_updates += m;
+        st->nnz_updates += nu;
+      }
+    }
     for (int64_t t = 0; t < per_epoch; ++t) {
       int64_t m = select_set(P, k_live, live, cls_off, cls_mem, ncls, e, t, J);
       if (m == 0) continue;
@@ -686,5 +782,6 @@ int orc_solve(const orc_csc *X, const double *y, const orc_params *P, double *w,
   }
   if (z_out) memcpy(z_out, z, sizeof(double) * (size_t)n);
   free(c); free(z); free(live); free(J); free(cls_off); free(cls_mem);
+  free(bbase); free(bp); free(brho);
   return status;
 }

@@ -793,3 +793,70 @@ def test_improved_solve_reaches_the_optimum():
     r = O.solve(X, y, P.loss, lam, O.SHOTGUN, select_size=32, seed=4, tol=1e-10,
                 max_epochs=200000, improve=500)
     assert r.converged and r.objective == pytest.approx(ref.objective, rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Block Shotgun: preset random blocks with their own P_b* (section 7)
+# --------------------------------------------------------------------------
+
+def _submatrix(P, cols):
+    cols = np.asarray(cols)
+    A = np.zeros((P.n, P.k))
+    for j in cols:
+        lo, hi = P.col_ptr[j], P.col_ptr[j + 1]
+        A[P.row_idx[lo:hi], j] = P.val[lo:hi]
+    return A
+
+
+def test_block_partition_is_balanced_and_complete():
+    P = synth.c1_ccd_logistic(scale=0.1)
+    X = O.Matrix.of(P)
+    base = O.block_base(X, 17)
+    live = np.nonzero(np.diff(P.col_ptr) > 0)[0]
+    assert sorted(base.tolist()) == live.tolist()  # a permutation of the live columns
+    assert not np.array_equal(base, live)          # and not the identity
+    kl = base.size
+    for nb in (1, 3, 7, kl):
+        sizes = [(b + 1) * kl // nb - b * kl // nb for b in range(nb)]
+        assert sum(sizes) == kl and max(sizes) - min(sizes) <= 1
+
+
+def test_block_pstar_equals_rho_of_each_block():
+    P = synth.c1_ccd_logistic(scale=0.1)
+    X = O.Matrix.of(P)
+    nb = 5
+    rho, ps = O.block_pstar(X, 17, nb)
+    base = O.block_base(X, 17)
+    kl = base.size
+    for b in range(nb):
+        cols = base[b * kl // nb:(b + 1) * kl // nb]
+        r, _, kb = O.rho(_csc_matrix(_submatrix(P, cols)[:, cols]), 20)
+        assert kb == cols.size and rho[b] == pytest.approx(r, rel=1e-12)
+        assert ps[b] == max(1, min(kb, int(np.floor(kb / (2 * r)))))
+    # one block: the global estimate, without the serving cap
+    r1, p1 = O.block_pstar(X, 17, 1)
+    rg, _, klg = O.rho(X, 20)
+    assert r1[0] == pytest.approx(rg, rel=1e-12) and p1[0] == max(1, int(np.floor(klg / (2 * rg))))
+
+
+def test_block_pstar_orthogonal_design():
+    # disjoint columns: rho_b = 1 in every block, P_b* = floor(k_b / 2)
+    P = synth.orthogonal_design(400, 90, O.SQUARED, 5)
+    rho, ps = O.block_pstar(O.Matrix.of(P), 3, 4)
+    np.testing.assert_allclose(rho, 1.0, rtol=1e-14)
+    assert ps.tolist() == [(((b + 1) * 90) // 4 - (b * 90) // 4) // 2 for b in range(4)]
+
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_block_shotgun_reaches_the_optimum(kind):
+    P = synth.c1_ccd_logistic(scale=0.15) if kind == O.LOGISTIC else synth.dense_small(60, 90, O.SQUARED, 7, density=0.2)
+    X = O.Matrix.of(P)
+    y = P.y.astype(np.float64)
+    lam = 0.1 * O.lambda_max(X, y, P.loss)
+    ref = O.solve(X, y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=200000)
+    r = O.solve(X, y, P.loss, lam, O.BLOCK_SHOTGUN, block=4, seed=4, tol=1e-10, max_epochs=200000)
+    assert ref.converged and r.converged
+    assert r.objective == pytest.approx(ref.objective, rel=1e-9)
+    # every live column is visited once per epoch
+    kl = int(np.sum(np.diff(P.col_ptr) > 0))
+    assert r.coord_updates == kl * r.epochs
