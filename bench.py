@@ -240,6 +240,16 @@ def main():
             "kkt_max": st3[-1]["kkt_max"], "accepted_per_iteration": 256,
         }
 
+        log("timing Block Shotgun solves (64 preset blocks)")
+        dt5, st5, _ = run(G.BLOCK_SHOTGUN, 1, 0, block=64)
+        out["block_shotgun"] = {
+            "nnz_updates_per_s": st5[-1]["nnz_updates"] / dt5,
+            "solves_per_s": 1.0 / dt5,
+            "epochs": st5[-1]["epochs"], "objective": st5[-1]["objective"],
+            "kkt_max": st5[-1]["kkt_max"], "blocks": 64,
+            "max_block_pstar": st5[-1]["select_size"], "max_block_rho": st5[-1]["rho"],
+        }
+
         log("timing Shotgun solves with 500 improve-delta steps")
         dt4, st4, _ = run(G.SHOTGUN, 1, 0, improve=500)
         out["shotgun_improve500"] = {

@@ -67,9 +67,13 @@ typedef enum {
   GENCD_THREAD_GREEDY = 3, /* random |J| columns, best proposal per block of B */
   GENCD_GREEDY = 4,        /* all columns, single best proposal */
   GENCD_COLORING = 5,      /* one colour class per iteration, accept all */
-  GENCD_TOP_GREEDY = 6     /* random |J| columns, the `block` proposals with the smallest
+  GENCD_TOP_GREEDY = 6,    /* random |J| columns, the `block` proposals with the smallest
                               phi over the whole window (ties: lowest position);
                               Thread-Greedy with global acceptance, section 4.1 */
+  GENCD_BLOCK_SHOTGUN = 7  /* `block` preset random blocks of the live columns, each with
+                              its own P_b* = floor(k_b / (2 rho_b)) (section 7); an
+                              epoch visits the blocks in a permuted order and each
+                              block's members, permuted, in windows of P_b*; accept all */
 } gencd_rule;
 
 /* flags */
@@ -95,7 +99,8 @@ typedef struct {
                             clamped to [1, 1024], rho estimated by 20 power
                             iterations (gencd_estimate_rho; section 4.1) */
   int64_t block;         /* B, proposals per accepting block (Thread-Greedy);
-                            |J'|, proposals accepted per iteration (Top-Greedy) */
+                            |J'|, proposals accepted per iteration (Top-Greedy);
+                            number of preset blocks, 1..4096 (Block Shotgun) */
   uint64_t seed;         /* seed of the per-epoch selection permutation */
   double kkt_tol;        /* stop when max_j KKT violation <= kkt_tol ... */
   double gap_tol;        /* ... and duality gap <= gap_tol * |objective| (0: off) */
@@ -262,6 +267,23 @@ int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, in
  * VALIDATE_DEVICE), WORKSPACE, UNSUPPORTED, HIP.
  * ------------------------------------------------------------------------ */
 int gencd_rho_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out_bytes);
+
+/* Per-block estimate behind Block Shotgun (section 7).  The live columns, in
+ * the order of a seeded permutation (p->seed), are cut into num_blocks
+ * contiguous preset blocks [b k_live / nb, (b+1) k_live / nb); for every
+ * block the same power iteration runs on its own normalised Gram matrix.
+ *   num_blocks   1..min(k_live, 4096)
+ *   iters        1..64 (gencd_solve uses 20)
+ *   rho_out      host double[num_blocks]: rho_b after `iters` iterations
+ *   pstar_out    host int64[num_blocks]: floor(k_b / (2 rho_b)) clamped to [1, k_b]
+ *   ws           device workspace of gencd_block_rho_workspace_bytes bytes
+ * Synchronises the stream.  Errors: INVALID_ARG (also num_blocks > k_live),
+ * BAD_MATRIX (with VALIDATE_DEVICE), WORKSPACE, UNSUPPORTED, HIP. */
+int gencd_block_rho_workspace_bytes(const gencd_csc *X, const gencd_params *p, int64_t num_blocks,
+                                    size_t *out_bytes);
+int gencd_estimate_block_rho(const gencd_csc *X, const gencd_params *p, int64_t num_blocks,
+                             int32_t iters, double *rho_out, int64_t *pstar_out, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
 int gencd_estimate_rho(const gencd_csc *X, const gencd_params *p, int32_t iters, double *rho_hist,
                        int64_t *k_live, int64_t *select_size, void *ws, size_t ws_bytes,
                        hipStream_t stream);

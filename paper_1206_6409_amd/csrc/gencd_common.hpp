@@ -116,6 +116,17 @@ __host__ __device__ inline PermKey make_perm_key(int64_t m, uint64_t seed, int64
   return pk;
 }
 
+// Key of the preset block partition (b = -1) and of block b's per-epoch
+// member order (Block Shotgun).
+__host__ __device__ inline uint64_t block_seed(uint64_t seed, int64_t b) {
+  return splitmix_fin(seed ^ splitmix_fin(0x626c6f636b73ull + uint64_t(b + 1)));
+}
+
+// Preset block b covers the preset positions [block_lo(b), block_lo(b + 1)).
+__host__ __device__ inline int64_t block_lo(int64_t b, int64_t k_live, int64_t nb) {
+  return b * k_live / nb;
+}
+
 __host__ __device__ __forceinline__ uint64_t perm_apply(const PermKey &pk, uint64_t x) {
   const uint64_t mask = pk.half >= 32 ? 0xFFFFFFFFull : ((uint64_t(1) << pk.half) - 1);
   do {
@@ -198,10 +209,19 @@ struct Ws {
   double *z64, *r64;     // [n]
   double *g64;           // [k]
   double *red;           // [16] reductions, counters, flags; [12] epoch counter
-  // spectral-radius estimate (only when |J| is chosen from it)
+  // spectral-radius estimate (only when |J| is chosen from it, or blocks)
   double *rho_dinv;      // [k] 1/||X_j|| (0 for empty columns)
   double *rho_x;         // [k] D^{-1/2} v, the scaled iterate
   double *rho_hist;      // [kRhoMaxIters] ||G v||^2 per iteration
+  // Block Shotgun (only with preset blocks)
+  int64_t nblocks;
+  int32_t *bbase;        // [k] preset order of the live columns
+  int32_t *bcol;         // [k] block of every column (-1: empty)
+  int32_t *bp;           // [nblocks] P_b* of every block
+  int32_t *bstart;       // [nblocks+1] per-epoch position offsets of the blocks
+  int32_t *bwin;         // [nblocks+1] per-epoch window offsets of the blocks
+  double *bs;            // [n][nblocks] per-block products X x in the power iteration
+  double *bhist;         // [kBlockRhoMaxIters][nblocks] ||G_b v_b||^2
   size_t scan_part_len;
   int64_t max_lpieces;
 };
@@ -213,8 +233,10 @@ constexpr int kDefaultPiece = 256;
 constexpr int kRhoIters = 20;       // power iterations behind an automatic |J|
 constexpr int kRhoMaxIters = 1024;  // cap for the standalone estimate
 constexpr int64_t kRhoSelectCap = 1024;  // automatic |J| is clamped to [1, this]
+constexpr int kBlockRhoMaxIters = 64;    // power iterations of the per-block estimate
+constexpr int64_t kMaxBlocks = 4096;     // preset blocks of Block Shotgun
 size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, bool rho,
-                        void *base, Ws *ws);
+                        int64_t nblocks, void *base, Ws *ws);
 size_t scan_partials_for(int64_t len);
 
 // Exclusive scan of int32 counts: out[0..len] (out[len] = total).

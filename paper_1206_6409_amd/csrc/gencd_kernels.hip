@@ -1491,6 +1491,206 @@ int launch_rho(const gencd_csc *X, int32_t n_short, int32_t n_lpieces, const Ws 
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 
+// ---------------------------------------------------------------------------
+// Block Shotgun (section 7): preset random blocks, each with its own P_b*
+// ---------------------------------------------------------------------------
+// Preset order: base[q] = live column at position q of the seeded
+// permutation; block of position q = the b with block_lo(b) <= q <
+// block_lo(b + 1), i.e. floor(((q + 1) nb - 1) / k_live).
+__global__ __launch_bounds__(kBlock) void k_block_base(const int32_t *live, int64_t k_live,
+                                                        int64_t nb, PermKey pk, int32_t *base,
+                                                        int32_t *bcol) {
+  for (int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x; q < k_live;
+       q += int64_t(gridDim.x) * kBlock) {
+    const int32_t j = live[perm_apply(pk, uint64_t(q))];
+    base[q] = j;
+    bcol[j] = int32_t(((q + 1) * nb - 1) / k_live);
+  }
+}
+
+// Per-block power iteration: the power iteration of launch_rho run on every
+// block's normalised Gram matrix at once, with one product vector per block
+// (bs[row][b]).  Columns are walked one wave each in preset order.
+__global__ __launch_bounds__(kBlock) void k_brho_init(int64_t k, int64_t n, int64_t nb,
+                                                       int64_t k_live, const int32_t *bcol,
+                                                       double *ss_u, double *dinv, double *x,
+                                                       double *bs, double *hist, int iters) {
+  const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t nt = int64_t(gridDim.x) * kBlock;
+  for (int64_t j = tid; j < k; j += nt) {
+    const int32_t b = bcol[j];
+    const double q = ss_u[j];
+    const double d = (b >= 0 && q > 0.0) ? 1.0 / sqrt(q) : 0.0;
+    dinv[j] = d;
+    if (b >= 0) {
+      const int64_t kb = block_lo(b + 1, k_live, nb) - block_lo(b, k_live, nb);
+      x[j] = d * (1.0 / sqrt(double(kb)));
+    } else {
+      x[j] = 0.0;
+    }
+    ss_u[j] = 0.0;
+  }
+  for (int64_t i = tid; i < n * nb; i += nt) bs[i] = 0.0;
+  for (int64_t t = tid; t < int64_t(iters) * nb; t += nt) hist[t] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_brho_spmv(const int64_t *col_ptr, const int32_t *row_idx,
+                                                       const float *val, const int32_t *base,
+                                                       int64_t k_live, const int32_t *bcol,
+                                                       int64_t nb, const double *x, double *bs) {
+  const int lane = int(threadIdx.x) & (kWave - 1);
+  const int64_t nw = int64_t(gridDim.x) * (kBlock / kWave);
+  for (int64_t q = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave; q < k_live; q += nw) {
+    const int32_t j = base[q];
+    const double xj = x[j];
+    if (xj == 0.0) continue;
+    const int64_t b = bcol[j];
+    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave)
+      atomicAdd(&bs[int64_t(row_idx[e]) * nb + b], double(val[e]) * xj);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_brho_cols(const int64_t *col_ptr, const int32_t *row_idx,
+                                                       const float *val, const int32_t *base,
+                                                       int64_t k_live, const int32_t *bcol,
+                                                       int64_t nb, const double *bs, double *u) {
+  const int lane = int(threadIdx.x) & (kWave - 1);
+  const int64_t nw = int64_t(gridDim.x) * (kBlock / kWave);
+  for (int64_t q = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave; q < k_live; q += nw) {
+    const int32_t j = base[q];
+    const int64_t b = bcol[j];
+    double acc = 0.0;
+    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave)
+      acc += double(val[e]) * bs[int64_t(row_idx[e]) * nb + b];
+    acc = group_sum<kWave>(acc);
+    if (lane == 0) u[j] = acc;
+  }
+}
+
+// ||D^{-1/2} U||^2 per block.  Each thread walks a contiguous run of preset
+// positions (blocks are contiguous runs), flushing its sum at every block
+// boundary.
+constexpr int kBrhoRun = 64;
+__global__ __launch_bounds__(kBlock) void k_brho_norm(const int32_t *base, int64_t k_live,
+                                                       const int32_t *bcol, const double *dinv,
+                                                       const double *u, double *hist_t) {
+  const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t nt = int64_t(gridDim.x) * kBlock;
+  for (int64_t q0 = tid * kBrhoRun; q0 < k_live; q0 += nt * kBrhoRun) {
+    const int64_t q1 = q0 + kBrhoRun < k_live ? q0 + kBrhoRun : k_live;
+    int32_t cur = -1;
+    double acc = 0.0;
+    for (int64_t q = q0; q < q1; ++q) {
+      const int32_t j = base[q];
+      const int32_t b = bcol[j];
+      if (b != cur) {
+        if (cur >= 0) atomicAdd(&hist_t[cur], acc);
+        cur = b;
+        acc = 0.0;
+      }
+      const double v = dinv[j] * u[j];
+      acc += v * v;
+    }
+    if (cur >= 0) atomicAdd(&hist_t[cur], acc);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_brho_scale(int64_t k, int64_t n, int64_t nb,
+                                                        const int32_t *bcol, const double *dinv,
+                                                        double *u, double *x, double *bs,
+                                                        const double *hist_t) {
+  const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t nt = int64_t(gridDim.x) * kBlock;
+  for (int64_t j = tid; j < k; j += nt) {
+    const int32_t b = bcol[j];
+    if (b < 0) continue;
+    const double rho = sqrt(hist_t[b]);
+    const double v = dinv[j] * u[j];
+    x[j] = rho > 0.0 ? dinv[j] * (v / rho) : 0.0;
+    u[j] = 0.0;
+  }
+  for (int64_t i = tid; i < n * nb; i += nt) bs[i] = 0.0;
+}
+
+int launch_block_setup(const gencd_csc *X, const Ws &ws, int64_t k_live, uint64_t seed, int iters,
+                       hipStream_t s) {
+  const int64_t nb = ws.nblocks;
+  if (nb < 1 || nb > k_live || iters < 1 || iters > kBlockRhoMaxIters) return GENCD_ERR_INVALID_ARG;
+  int st = fill_i32(ws.bcol, X->k, -1, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_block_base, dim3(grid_for(k_live)), dim3(kBlock), 0, s, ws.live, k_live, nb,
+                     make_perm_key(k_live, block_seed(seed, -1), 0), ws.bbase, ws.bcol);
+  const int64_t nk = X->n * nb > X->k ? X->n * nb : X->k;
+  hipLaunchKernelGGL(k_brho_init, dim3(grid_for(nk)), dim3(kBlock), 0, s, X->k, X->n, nb, k_live,
+                     ws.bcol, ws.g64, ws.rho_dinv, ws.rho_x, ws.bs, ws.bhist, iters);
+  const unsigned wg = waves_grid(k_live, 16384);
+  const unsigned rg = grid_for((k_live + kBrhoRun - 1) / kBrhoRun);
+  for (int t = 0; t < iters; ++t) {
+    double *ht = ws.bhist + int64_t(t) * nb;
+    hipLaunchKernelGGL(k_brho_spmv, dim3(wg), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
+                       ws.bbase, k_live, ws.bcol, nb, ws.rho_x, ws.bs);
+    hipLaunchKernelGGL(k_brho_cols, dim3(wg), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
+                       ws.bbase, k_live, ws.bcol, nb, ws.bs, ws.g64);
+    hipLaunchKernelGGL(k_brho_norm, dim3(rg), dim3(kBlock), 0, s, ws.bbase, k_live, ws.bcol,
+                       ws.rho_dinv, ws.g64, ht);
+    hipLaunchKernelGGL(k_brho_scale, dim3(grid_for(nk)), dim3(kBlock), 0, s, X->k, X->n, nb,
+                       ws.bcol, ws.rho_dinv, ws.g64, ws.rho_x, ws.bs, ht);
+  }
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// Per-epoch order: blocks in a permuted order, each block's members in a
+// per-epoch permuted order, windows of P_b* positions inside every block.
+__global__ __launch_bounds__(kBlock) void k_block_sizes(int64_t nb, int64_t k_live, uint64_t seed,
+                                                         const int64_t *epoch, const int32_t *bp,
+                                                         int32_t *cnt, int32_t *wcnt) {
+  const PermKey pk = make_perm_key(nb, seed, *epoch);
+  for (int64_t u = int64_t(blockIdx.x) * kBlock + threadIdx.x; u < nb;
+       u += int64_t(gridDim.x) * kBlock) {
+    const int64_t b = int64_t(perm_apply(pk, uint64_t(u)));
+    const int64_t kb = block_lo(b + 1, k_live, nb) - block_lo(b, k_live, nb);
+    cnt[u] = int32_t(kb);
+    wcnt[u] = int32_t((kb + bp[b] - 1) / bp[b]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_block_fill(int64_t nb, int64_t k_live, uint64_t seed,
+                                                        const int64_t *epoch, const int32_t *bp,
+                                                        const int32_t *base, const int32_t *bstart,
+                                                        const int32_t *bwin, int32_t *col_of_pos,
+                                                        int32_t *win_off) {
+  const int64_t e = *epoch;
+  const PermKey pk = make_perm_key(nb, seed, e);
+  for (int64_t u = blockIdx.x; u < nb; u += gridDim.x) {
+    const int64_t b = int64_t(perm_apply(pk, uint64_t(u)));
+    const int64_t lo = block_lo(b, k_live, nb), kb = block_lo(b + 1, k_live, nb) - lo;
+    const PermKey pkb = make_perm_key(kb, block_seed(seed, b), e);
+    const int32_t o = bstart[u];
+    for (int64_t i = threadIdx.x; i < kb; i += kBlock)
+      col_of_pos[o + i] = base[lo + int64_t(perm_apply(pkb, uint64_t(i)))];
+    const int32_t w0 = bwin[u], nw = bwin[u + 1] - w0;
+    for (int32_t t = threadIdx.x; t < nw; t += kBlock) win_off[w0 + t] = o + t * bp[b];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) win_off[bwin[nb]] = int32_t(k_live);
+}
+
+int launch_block_order(const Ws &w, int64_t k_live, uint64_t seed, const int64_t *epoch, int64_t T,
+                       hipStream_t s) {
+  const int64_t nb = w.nblocks;
+  hipLaunchKernelGGL(k_block_sizes, dim3(grid_for(nb)), dim3(kBlock), 0, s, nb, k_live, seed,
+                     epoch, w.bp, w.tmp_cnt, w.tmp_cnt2);
+  int st = scan_exclusive(w.tmp_cnt, w.bstart, nb, w.scan_part, s);
+  if (st) return st;
+  st = scan_exclusive(w.tmp_cnt2, w.bwin, nb, w.scan_part, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_block_fill, dim3(unsigned(nb < 8192 ? nb : 8192)), dim3(kBlock), 0, s, nb,
+                     k_live, seed, epoch, w.bp, w.bbase, w.bstart, w.bwin, w.col_of_pos,
+                     w.win_off);
+  hipLaunchKernelGGL(k_list_counts, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.col_of_pos,
+                     k_live, w.all_soff, w.all_loff, w.tmp_cnt, w.tmp_cnt2);
+  return order_tail(w, k_live, w.win_off, 0, T, s);
+}
+
 // Copy z64 rounded to FP32 into a caller buffer.
 __global__ __launch_bounds__(kBlock) void k_round_f32(const double *src, float *dst, int64_t m) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < m;

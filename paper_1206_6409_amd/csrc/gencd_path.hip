@@ -448,7 +448,7 @@ int path_setup(const gencd_csc *X, const float *y, const gencd_params *p, void *
 
 size_t path_workspace_bytes(int64_t n, int64_t k, int64_t nnz, int64_t S, int B, int piece,
                             int short_max) {
-  return workspace_layout(n, k, nnz, piece, short_max, false, nullptr, nullptr) + 256 +
+  return workspace_layout(n, k, nnz, piece, short_max, false, 0, nullptr, nullptr) + 256 +
          path_layout(n, k, S, B, nullptr, nullptr) + 256;
 }
 

@@ -44,7 +44,7 @@ struct Carver {
 }  // namespace
 
 size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, bool rho,
-                        void *base, Ws *ws) {
+                        int64_t nblocks, void *base, Ws *ws) {
   Carver c{static_cast<char *>(base)};
   Ws w{};
   const int64_t ml = max_lpieces_for(k, nnz, piece, short_max);
@@ -80,10 +80,20 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.r64 = c.take<double>(n);
   w.g64 = c.take<double>(k);
   w.red = c.take<double>(16);
-  if (rho) {
+  if (rho || nblocks > 0) {
     w.rho_dinv = c.take<double>(k);
     w.rho_x = c.take<double>(k);
     w.rho_hist = c.take<double>(kRhoMaxIters);
+  }
+  w.nblocks = nblocks;
+  if (nblocks > 0) {
+    w.bbase = c.take<int32_t>(k);
+    w.bcol = c.take<int32_t>(k);
+    w.bp = c.take<int32_t>(nblocks);
+    w.bstart = c.take<int32_t>(nblocks + 1);
+    w.bwin = c.take<int32_t>(nblocks + 1);
+    w.bs = c.take<double>(n * nblocks);
+    w.bhist = c.take<double>(int64_t(kBlockRhoMaxIters) * nblocks);
   }
   if (ws) *ws = w;
   return c.off + kAlign;
@@ -97,6 +107,11 @@ bool csc_ok(const gencd_csc *X) {
   if (!X->col_ptr) return false;
   if (X->nnz > 0 && (!X->row_idx || !X->val)) return false;
   return true;
+}
+
+// Block Shotgun: number of preset blocks the workspace holds.
+int64_t blocks_of(const gencd_params *p) {
+  return (p && p->rule == GENCD_BLOCK_SHOTGUN && p->block > 0) ? p->block : 0;
 }
 
 // Shotgun and Thread-Greedy with select_size 0 take |J| from the estimate.
@@ -122,7 +137,9 @@ int params_ok(const gencd_params *p, bool need_rule) {
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return GENCD_ERR_INVALID_ARG;
   if (p->improve_steps < 0 || p->improve_steps > 1000000) return GENCD_ERR_INVALID_ARG;
   if (!need_rule) return GENCD_OK;
-  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_TOP_GREEDY) return GENCD_ERR_INVALID_ARG;
+  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_BLOCK_SHOTGUN) return GENCD_ERR_INVALID_ARG;
+  if (p->rule == GENCD_BLOCK_SHOTGUN && (p->block < 1 || p->block > kMaxBlocks))
+    return GENCD_ERR_INVALID_ARG;
   if ((p->rule == GENCD_SHOTGUN || p->rule == GENCD_THREAD_GREEDY ||
        p->rule == GENCD_TOP_GREEDY) &&
       p->select_size < 0)
@@ -166,6 +183,8 @@ struct Setup {
   int64_t k_live = 0;
   std::vector<double> rho_hist;  // spectral-radius estimate after each power iteration
   double rho = 0.0;
+  std::vector<double> brho;      // Block Shotgun: rho_b of every preset block
+  std::vector<int32_t> bp;       // Block Shotgun: P_b* of every preset block
 };
 
 // |J| = floor(k_live / (2 rho)) clamped to [1, kRhoSelectCap] (section 4.1).
@@ -182,22 +201,24 @@ int64_t pstar_of(int64_t k_live, double rho) {
 // workspace.  y may be null only when need_y is false (no label check).
 int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, void *ws_base,
           size_t ws_bytes, bool validate_matrix, hipStream_t s, Setup *out, int rho_iters = 0,
-          bool need_y = true) {
+          bool need_y = true, int64_t nblocks = 0, int block_iters = kRhoIters) {
   if (!csc_ok(X) || (need_y && !y)) return GENCD_ERR_INVALID_ARG;
   if (rho_iters < 0 || rho_iters > kRhoMaxIters) return GENCD_ERR_INVALID_ARG;
+  if (nblocks < 0 || nblocks > kMaxBlocks || block_iters < 1 || block_iters > kBlockRhoMaxIters)
+    return GENCD_ERR_INVALID_ARG;
   int st = resolve_schedule(p, &out->piece, &out->group);
   if (st) return st;
   const int smax = short_max_of(out->group);
   if (max_lpieces_for(X->k, X->nnz, out->piece, smax) >= INT32_MAX ||
       X->nnz >= (int64_t(1) << 32))
     return GENCD_ERR_UNSUPPORTED;
-  size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, smax, rho_iters > 0, nullptr, nullptr);
+  size_t need = workspace_layout(X->n, X->k, X->nnz, out->piece, smax, rho_iters > 0, nblocks, nullptr, nullptr);
   if (!ws_base || ws_bytes < need) return GENCD_ERR_WORKSPACE;
   // align the carve base
   char *base = static_cast<char *>(ws_base);
   size_t mis = reinterpret_cast<uintptr_t>(base) % kAlign;
   if (mis) base += kAlign - mis;
-  workspace_layout(X->n, X->k, X->nnz, out->piece, smax, rho_iters > 0, base, &out->ws);
+  workspace_layout(X->n, X->k, X->nnz, out->piece, smax, rho_iters > 0, nblocks, base, &out->ws);
   const Ws &w = out->ws;
   st = fill_f64(w.red, 16, 0.0, s);
   if (st) return st;
@@ -232,6 +253,32 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
       for (double &h : out->rho_hist) h = std::sqrt(h);
     }
     out->rho = out->rho_hist.back();
+  }
+  if (nblocks > 0 && out->k_live > 0) {
+    // preset blocks and P_b* = floor(k_b / (2 rho_b)) clamped to [1, k_b]
+    const int64_t nb = std::min<int64_t>(nblocks, out->k_live);
+    out->ws.nblocks = nb;
+    st = launch_block_setup(X, out->ws, out->k_live, p ? p->seed : 0, block_iters, s);
+    if (st) return st;
+    std::vector<double> h(size_t(block_iters) * size_t(nb));
+    GENCD_HIP(hipMemcpyAsync(h.data(), w.bhist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    GENCD_HIP(hipStreamSynchronize(s));
+    out->brho.resize(size_t(nb));
+    out->bp.resize(size_t(nb));
+    for (int64_t b = 0; b < nb; ++b) {
+      const double r = std::sqrt(h[size_t(block_iters - 1) * size_t(nb) + size_t(b)]);
+      const int64_t kb = block_lo(b + 1, out->k_live, nb) - block_lo(b, out->k_live, nb);
+      int64_t pb = 1;
+      if (r > 0.0) {
+        const double f = std::floor(double(kb) / (2.0 * r));
+        pb = f < 1.0 ? 1 : (f > double(kb) ? kb : int64_t(f));
+      }
+      out->brho[size_t(b)] = r;
+      out->bp[size_t(b)] = int32_t(pb);
+    }
+    GENCD_HIP(hipMemcpyAsync(out->ws.bp, out->bp.data(), sizeof(int32_t) * size_t(nb),
+                             hipMemcpyHostToDevice, s));
+    GENCD_HIP(hipStreamSynchronize(s));
   }
   st = fill_f32(w.gacc, w.max_lpieces, 0.0f, s);
   if (st) return st;
@@ -420,7 +467,7 @@ int path_setup(const gencd_csc *X, const float *y, const gencd_params *p, void *
   out->n_short = su.n_short;
   out->n_lpieces = su.n_lpieces;
   out->k_live = su.k_live;
-  *used = workspace_layout(X->n, X->k, X->nnz, su.piece, short_max_of(su.group), false, nullptr,
+  *used = workspace_layout(X->n, X->k, X->nnz, su.piece, short_max_of(su.group), false, 0, nullptr,
                            nullptr) +
           kAlign;
   return GENCD_OK;
@@ -441,7 +488,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   if (!w) return GENCD_ERR_INVALID_ARG;
   Setup su;
   st = setup(X, y, p->loss, p, ws_base, ws_bytes, (p->flags & GENCD_VALIDATE_DEVICE) != 0, s, &su,
-             wants_rho(p) ? kRhoIters : 0);
+             wants_rho(p) ? kRhoIters : 0, true, blocks_of(p));
   if (st) return st;
   const Ws &ws = su.ws;
   const int rule = p->rule;
@@ -486,6 +533,20 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   if (S > k_live) S = k_live;
   if (S < 1) S = 1;
   st_out->rho = su.rho;
+  // Block Shotgun: windows of P_b* inside every block; T_blk windows per epoch
+  int64_t T_blk = 0, max_pb = 0;
+  if (rule == GENCD_BLOCK_SHOTGUN) {
+    const int64_t nb = int64_t(su.bp.size());
+    double rmax = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t kb = block_lo(b + 1, k_live, nb) - block_lo(b, k_live, nb);
+      T_blk += (kb + su.bp[size_t(b)] - 1) / su.bp[size_t(b)];
+      max_pb = std::max<int64_t>(max_pb, su.bp[size_t(b)]);
+      rmax = std::max(rmax, su.brho[size_t(b)]);
+    }
+    S = std::max<int64_t>(max_pb, 1);
+    st_out->rho = rmax;
+  }
   st_out->select_size = S;
   const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
   int64_t max_class = 0;
@@ -523,7 +584,9 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   // of Algorithm 1, then the epoch counter increment.  Every argument is
   // independent of the epoch number, so the sequence can be captured once.
   auto enqueue_epoch = [&](int64_t T, int64_t e_host, bool record, hipStream_t es) -> int {
-    int rc = launch_epoch_order(ws, k_live, rule, p->seed, epoch_dev, C, S, T, es);
+    int rc = rule == GENCD_BLOCK_SHOTGUN
+                 ? launch_block_order(ws, k_live, p->seed, epoch_dev, T, es)
+                 : launch_epoch_order(ws, k_live, rule, p->seed, epoch_dev, C, S, T, es);
     if (rc) return rc;
     PermKey cpk{};
     if (rule == GENCD_COLORING && !use_graph) cpk = make_perm_key(C, p->seed, e_host);
@@ -532,6 +595,9 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       if (rule == GENCD_COLORING) {
         a.win_off = ws.win_off;
         positions = use_graph ? max_class : cls_sizes[size_t(perm_apply(cpk, uint64_t(t)))];
+      } else if (rule == GENCD_BLOCK_SHOTGUN) {
+        a.win_off = ws.win_off;  // windows of at most max_pb positions
+        positions = max_pb;
       } else {
         a.win_off = nullptr;
         a.win_lo = int32_t(t * S);
@@ -559,7 +625,9 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   };
 
   for (int64_t e = 0; status != GENCD_OK && e < p->max_epochs && k_live > 0; ++e) {
-    const int64_t T = (rule == GENCD_COLORING) ? C : (k_live + S - 1) / S;
+    const int64_t T = (rule == GENCD_COLORING)         ? C
+                      : (rule == GENCD_BLOCK_SHOTGUN) ? T_blk
+                                                      : (k_live + S - 1) / S;
     if (prof && evs.empty()) {
       const int64_t want = 2 * std::max<int64_t>(T, 1) * check_every;
       if (want <= 2 * 65536) {
@@ -663,7 +731,7 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
   (void)hipGetLastError();  // launch checks below must not see an earlier error
   int st = params_ok(p, false);
   if (st) return st;
-  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_TOP_GREEDY) return GENCD_ERR_INVALID_ARG;
+  if (p->rule < GENCD_CYCLIC || p->rule > GENCD_BLOCK_SHOTGUN) return GENCD_ERR_INVALID_ARG;
   if ((p->rule == GENCD_THREAD_GREEDY || p->rule == GENCD_TOP_GREEDY) && p->block <= 0)
     return GENCD_ERR_INVALID_ARG;
   if (!w || !z_hi || !z_lo || nJ < 0 || (nJ > 0 && !J)) return GENCD_ERR_INVALID_ARG;
@@ -767,7 +835,7 @@ int gencd_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t *out
   int st = resolve_schedule(p, &piece, &group);
   if (st) return st;
   *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), wants_rho(p),
-                               nullptr, nullptr) +
+                               blocks_of(p), nullptr, nullptr) +
                kAlign;
   return GENCD_OK;
 }
@@ -805,7 +873,7 @@ int gencd_rho_workspace_bytes(const gencd_csc *X, const gencd_params *p, size_t 
   int piece, group;
   int st = resolve_schedule(p, &piece, &group);
   if (st) return st;
-  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), true, nullptr,
+  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), true, 0, nullptr,
                                 nullptr) +
                kAlign;
   return GENCD_OK;
@@ -826,6 +894,42 @@ int gencd_estimate_rho(const gencd_csc *X, const gencd_params *p, int32_t iters,
   for (int32_t t = 0; t < iters; ++t) rho_hist[t] = su.rho_hist[size_t(t)];
   if (k_live) *k_live = su.k_live;
   if (select_size) *select_size = pstar_of(su.k_live, su.rho);
+  return GENCD_OK;
+}
+
+int gencd_block_rho_workspace_bytes(const gencd_csc *X, const gencd_params *p, int64_t num_blocks,
+                                    size_t *out_bytes) {
+  if (!out_bytes || !X || X->n <= 0 || X->k <= 0 || X->nnz < 0 || num_blocks < 1 ||
+      num_blocks > kMaxBlocks)
+    return GENCD_ERR_INVALID_ARG;
+  int piece, group;
+  int st = resolve_schedule(p, &piece, &group);
+  if (st) return st;
+  *out_bytes = workspace_layout(X->n, X->k, X->nnz, piece, short_max_of(group), false, num_blocks,
+                                nullptr, nullptr) +
+               kAlign;
+  return GENCD_OK;
+}
+
+int gencd_estimate_block_rho(const gencd_csc *X, const gencd_params *p, int64_t num_blocks,
+                             int32_t iters, double *rho_out, int64_t *pstar_out, void *ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  (void)hipGetLastError();
+  if (!rho_out || !pstar_out || num_blocks < 1 || num_blocks > kMaxBlocks || iters < 1 ||
+      iters > kBlockRhoMaxIters)
+    return GENCD_ERR_INVALID_ARG;
+  gencd_params q{};
+  if (p) q = *p;
+  q.loss = GENCD_SQUARED;  // no labels: nothing to validate
+  Setup su;
+  int st = setup(X, nullptr, GENCD_SQUARED, &q, ws, ws_bytes, (q.flags & GENCD_VALIDATE_DEVICE) != 0,
+                 stream, &su, 0, false, num_blocks, iters);
+  if (st) return st;
+  if (num_blocks > su.k_live) return GENCD_ERR_INVALID_ARG;
+  for (int64_t b = 0; b < num_blocks; ++b) {
+    rho_out[b] = su.brho[size_t(b)];
+    pstar_out[b] = su.bp[size_t(b)];
+  }
   return GENCD_OK;
 }
 

@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(HERE, "libgencd.so")
 
 OK, NOT_CONVERGED = 0, 1
 SQUARED, LOGISTIC = 0, 1
-CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY = range(7)
+CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY, BLOCK_SHOTGUN = range(8)
 WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE, EXACT_ACCUM = 0x1, 0x2, 0x4, 0x8, 0x10
 RULES = {"cyclic": CYCLIC, "stochastic": STOCHASTIC, "shotgun": SHOTGUN,
          "thread_greedy": THREAD_GREEDY, "greedy": GREEDY, "coloring": COLORING,
-         "top_greedy": TOP_GREEDY}
+         "top_greedy": TOP_GREEDY, "block_shotgun": BLOCK_SHOTGUN}
 
 
 class GencdError(RuntimeError):
@@ -75,6 +75,9 @@ _SIGS = {
                               C.c_void_p]),
     "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "gencd_rho_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_block_rho_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gencd_estimate_block_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "gencd_estimate_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "gencd_color_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -221,6 +224,20 @@ def estimate_rho(X: Matrix, iters=20, params=None):
                                     _ptr(ws), ws.numel(), _stream()), "gencd_estimate_rho")
     h = list(hist)
     return RhoResult(h[-1], h, kl.value, sel.value)
+
+
+def estimate_block_rho(X: Matrix, num_blocks, iters=20, params=None):
+    """(rho_b, P_b*) of the preset blocks of Block Shotgun (section 7)."""
+    pp = C.byref(params) if params is not None else None
+    nb = C.c_size_t()
+    _check(lib().gencd_block_rho_workspace_bytes(X.ref, pp, int(num_blocks), C.byref(nb)),
+           "gencd_block_rho_workspace_bytes")
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=X.col_ptr.device)
+    rho = (C.c_double * int(num_blocks))()
+    ps = (C.c_int64 * int(num_blocks))()
+    _check(lib().gencd_estimate_block_rho(X.ref, pp, int(num_blocks), int(iters), rho, ps, _ptr(ws),
+                                          ws.numel(), _stream()), "gencd_estimate_block_rho")
+    return list(rho), list(ps)
 
 
 @dataclass

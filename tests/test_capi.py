@@ -123,3 +123,24 @@ def test_rho_host_validation():
     assert G.lib().gencd_estimate_rho(C.byref(X), None, 4, None, None, None, None, 0, None) == -1
     bad = _fake_matrix(0, 5, 0)
     assert G.lib().gencd_rho_workspace_bytes(C.byref(bad), None, C.byref(out)) == -1
+
+
+def test_block_rho_host_validation():
+    X = _fake_matrix(1000, 500, 4000)
+    out = C.c_size_t()
+    base = C.c_size_t()
+    assert G.lib().gencd_block_rho_workspace_bytes(C.byref(X), None, 8, C.byref(out)) == 0
+    assert G.lib().gencd_workspace_bytes(C.byref(X), None, C.byref(base)) == 0
+    assert out.value >= base.value + 8 * 1000 * 8  # one product vector per block
+    p = G.make_params(1, 0.1, rule=G.BLOCK_SHOTGUN, block=8)
+    solve_bytes = C.c_size_t()
+    assert G.lib().gencd_workspace_bytes(C.byref(X), C.byref(p), C.byref(solve_bytes)) == 0
+    assert solve_bytes.value >= out.value
+    for nb in (0, -1, 4097):
+        assert G.lib().gencd_block_rho_workspace_bytes(C.byref(X), None, nb, C.byref(out)) == -1
+    rho = (C.c_double * 4)()
+    ps = (C.c_int64 * 4)()
+    for nb, it in ((0, 20), (4, 0), (4, 65)):
+        assert G.lib().gencd_estimate_block_rho(C.byref(X), None, nb, it, rho, ps, None, 0, None) == -1
+    bad = G.make_params(1, 0.1, rule=G.BLOCK_SHOTGUN, block=0)
+    assert G.lib().gencd_solve(C.byref(X), None, C.byref(bad), None, None, None, 0, None, None) == -1
