@@ -167,6 +167,16 @@ def main():
                       "nnz_updates_per_s": sum(s["nnz_updates"] for s in stats_g) / dt_g}
         if dt_g < dt_plain:
             dt, stats, path = dt_g, stats_g, "graph (one captured HIP graph per epoch)"
+    fused_info = None
+    if not args.no_graph:
+        # fused asynchronous Shotgun (Propose and Update in one launch; the
+        # trajectory is not the Jacobi one, the optimum is the same)
+        log("timing fused asynchronous Shotgun solves (captured epoch graphs)")
+        dt_f, stats_f, _ = run(G.SHOTGUN, args.steps, args.warmup, flags=G.USE_GRAPH | G.FUSED)
+        fused_info = {"solves_per_s": args.steps / dt_f,
+                      "nnz_updates_per_s": sum(s["nnz_updates"] for s in stats_f) / dt_f,
+                      "epochs_per_solve": stats_f[-1]["epochs"],
+                      "objective": stats_f[-1]["objective"], "kkt_max": stats_f[-1]["kkt_max"]}
     prof_src = stats_plain
     nnz_upd = sum(s["nnz_updates"] for s in stats)
     coord_upd = sum(s["coord_updates"] for s in stats)
@@ -210,6 +220,7 @@ def main():
         "plain_path": {"solves_per_s": args.steps / dt_plain,
                        "nnz_updates_per_s": sum(s["nnz_updates"] for s in stats_plain) / dt_plain},
         "graph_path": graph_info,
+        "fused_async_path": fused_info,
         "solves_per_s": args.steps / dt,
         "coord_updates_per_s": coord_upd / dt,
         "epochs_per_solve": last["epochs"],

@@ -82,6 +82,12 @@ typedef enum {
 #define GENCD_USE_GRAPH 0x4u       /* replay each epoch as a captured HIP graph */
 #define GENCD_PROFILE 0x8u         /* time every Propose launch with HIP events */
 #define GENCD_EXACT_ACCUM 0x10u    /* TwoSum-compensate every atomic update of z */
+#define GENCD_FUSED 0x20u          /* accept-all rules except Coloring: fused asynchronous
+                                      Propose+Update (section 4.1); each column reads z as
+                                      others of its window update it and split columns
+                                      are applied one launch later, so the trajectory is
+                                      not the Jacobi one (the optimum is the same).  Not
+                                      with EXACT_ACCUM or improve_steps (UNSUPPORTED) */
 
 /* Device CSC matrix (see the conventions above). */
 typedef struct {

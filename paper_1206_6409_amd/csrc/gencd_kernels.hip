@@ -1156,6 +1156,134 @@ static int launch_iteration_u(const IterArgs &a, int mode, int64_t block, unsign
                                              improve_blocks, s, ev0, ev1);
 }
 
+// ---------------------------------------------------------------------------
+// Fused asynchronous Shotgun (accept-all rules, GENCD_FUSED): Propose and
+// Update in one launch, as section 4.1 notes Shotgun allows.  Each column
+// forms g from the current z (other columns of its window may already have
+// updated shared rows), takes its Eq. 7 step and scatters at once.  A split
+// column publishes partial sums and w_j (position-indexed snapshot); the
+// next launch, or the flush launch at the end of the epoch, applies it.
+// ---------------------------------------------------------------------------
+template <int G, int U>
+__device__ __forceinline__ void fused_column(const IterArgs &a, int64_t beg, int32_t len,
+                                             int32_t j, int lane) {
+  const float wj = a.w[j], cj = a.c[j];  // the same address in every lane: one load each
+  float s = 0.0f;
+  int32_t ri[U];
+  float vv[U];
+  for (int32_t base = 0; base < len; base += G * U) {
+    load_batch<G, U>(a, beg, len, base, lane, ri, vv);
+    float zh[U], zl[U], yy[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float4 zr = a.zs[ri[u] >= 0 ? ri[u] : 0];
+      zh[u] = zr.x;
+      zl[u] = zr.y;
+      yy[u] = zr.z;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ri[u] >= 0) s += vv[u] * dloss_f32(a.loss, yy[u], zh[u] + zl[u]);
+  }
+  s = group_sum<G>(s);  // identical in every lane of the group
+  float d, ph;
+  propose_f32(s / a.n_f, cj, wj, a.lam, d, ph);
+  if (d == 0.0f) return;
+  if (lane == 0) a.w[j] = wj + d;
+  if (len <= G * U)
+    scatter_batch<0, U>(a, ri, vv, d);  // the only batch is still in registers
+  else
+    scatter_piece<G, 0, U>(a, beg, len, d, lane);
+}
+
+template <int GS, int UL>
+__global__ __launch_bounds__(kBlock) void k_fused(IterArgs a, int32_t flush) {
+  const Roles r = roles(a.nl);
+  int32_t P0 = 0, P1 = 0;
+  if (!flush) window_of(a, P0, P1);
+  if (r.wave < r.nl) {
+    // current window's pieces, then the previous window's split pieces
+    const int32_t q0 = flush ? 0 : a.wbl[a.t], q1 = flush ? 0 : a.wbl[a.t + 1];
+    const int32_t qp0 = a.t > 0 ? a.wbl[a.t - 1] : 0, qp1 = a.t > 0 ? a.wbl[a.t] : 0;
+    const int64_t ncur = q1 - q0, ntot = ncur + (qp1 - qp0);
+    for (int64_t u = r.wave; u < ntot; u += r.nl) {
+      if (u < ncur) {
+        const int64_t q = q0 + u;
+        const int4 dsc = a.desc_l[q];
+        if (desc_single(dsc)) {
+          fused_column<kWave, UL>(a, desc_beg(dsc), desc_len(dsc), dsc.y, r.wl);
+        } else {
+          // partial gradient of a split column, and its weight at this time
+          const int64_t beg = desc_beg(dsc);
+          const int32_t len = desc_len(dsc);
+          float s = 0.0f;
+          for (int32_t base = 0; base < len; base += kWave * UL) {
+            int32_t ri[UL];
+            float vv[UL];
+            load_batch<kWave, UL>(a, beg, len, base, r.wl, ri, vv);
+#pragma unroll
+            for (int v = 0; v < UL; ++v) {
+              const float4 zr = a.zs[ri[v] >= 0 ? ri[v] : 0];
+              if (ri[v] >= 0) s += vv[v] * dloss_f32(a.loss, zr.z, zr.x + zr.y);
+            }
+          }
+          s = group_sum<kWave>(s);
+          if (r.wl == 0) {
+            a.gacc[q] = s;
+            a.wsnap[dsc.z] = a.w[dsc.y];
+          }
+        }
+      } else {
+        const int64_t q = qp0 + (u - ncur);
+        const int4 dsc = a.desc_l[q];
+        if (desc_single(dsc)) continue;  // applied in its own launch
+        const int32_t p = dsc.z, j = dsc.y;
+        const int32_t pf = a.loff[p], np = a.loff[p + 1] - pf;
+        const float ws = a.wsnap[p];
+        const float g = split_sum(a.gacc, pf, np, r.wl) / a.n_f;
+        float d, ph;
+        propose_f32(g, a.c[j], ws, a.lam, d, ph);
+        if (d == 0.0f) continue;
+        if (q == pf && r.wl == 0) a.w[j] = ws + d;
+        scatter_piece<kWave, 0, UL>(a, desc_beg(dsc), desc_len(dsc), d, r.wl);
+      }
+    }
+  } else {
+    const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
+    const int lane = r.wl & (GS - 1);
+    for (int64_t p = P0 + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; p < P1; p += step) {
+      const int4 dsc = a.desc_s[p];
+      if (desc_len(dsc) == 0) continue;  // long column: the long waves take it
+      fused_column<GS, kUnroll>(a, desc_beg(dsc), desc_len(dsc), dsc.y, lane);
+    }
+  }
+}
+
+template <int GS>
+static void launch_fused_g(const IterArgs &a, unsigned blocks, bool flush, hipStream_t s) {
+  if (a.piece <= kWave * kUnroll)
+    hipLaunchKernelGGL((k_fused<GS, kUnroll>), dim3(blocks), dim3(kBlock), 0, s, a, int32_t(flush));
+  else
+    hipLaunchKernelGGL((k_fused<GS, 2 * kUnroll>), dim3(blocks), dim3(kBlock), 0, s, a,
+                       int32_t(flush));
+}
+
+int launch_fused(const IterArgs &a, int group, int64_t short_bound, int64_t long_bound, bool flush,
+                 hipStream_t s) {
+  IterArgs b = a;
+  unsigned blocks;
+  int32_t nl;
+  two_class_grid(flush ? 0 : short_bound, long_bound, group, &blocks, &nl);
+  b.nl = nl;
+  switch (group) {
+    case 4: launch_fused_g<4>(b, blocks, flush, s); break;
+    case 8: launch_fused_g<8>(b, blocks, flush, s); break;
+    case 16: launch_fused_g<16>(b, blocks, flush, s); break;
+    default: launch_fused_g<32>(b, blocks, flush, s); break;
+  }
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
                      int64_t long_bound, int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
                      hipEvent_t ev1) {

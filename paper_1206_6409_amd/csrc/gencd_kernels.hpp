@@ -60,6 +60,11 @@ int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s);
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
                      int64_t long_bound, int64_t nblocks_accept, hipStream_t s,
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Fused asynchronous Shotgun iteration (accept-all rules): window a.t, plus
+// the split columns of window a.t - 1; `flush` applies only the latter
+// (a.t = number of windows).
+int launch_fused(const IterArgs &a, int group, int64_t short_bound, int64_t long_bound, bool flush,
+                 hipStream_t s);
 // Power-iteration estimate of the normalised Gram spectral radius; needs the
 // column sums of squares in ws.g64 (left there by launch_curvature) and the
 // rho arrays of the workspace.  Squared norms land in ws.rho_hist[0..iters).

@@ -147,6 +147,11 @@ int params_ok(const gencd_params *p, bool need_rule) {
   if ((p->rule == GENCD_THREAD_GREEDY || p->rule == GENCD_TOP_GREEDY) && p->block <= 0)
     return GENCD_ERR_INVALID_ARG;
   if (p->rule == GENCD_COLORING && (!p->color || p->num_colors <= 0)) return GENCD_ERR_INVALID_ARG;
+  if ((p->flags & GENCD_FUSED) &&
+      ((p->rule != GENCD_CYCLIC && p->rule != GENCD_STOCHASTIC && p->rule != GENCD_SHOTGUN &&
+        p->rule != GENCD_BLOCK_SHOTGUN) ||
+       (p->flags & GENCD_EXACT_ACCUM) || p->improve_steps > 0))
+    return GENCD_ERR_UNSUPPORTED;
   if (!(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0 || p->check_every < 0)
     return GENCD_ERR_INVALID_ARG;
   return GENCD_OK;
@@ -558,7 +563,8 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   unsigned long long acc_nnz_seen = 0, acc_cnt_seen = 0;
   // GENCD_PROFILE: one event pair per Propose launch between two checks
   const bool use_graph = (p->flags & GENCD_USE_GRAPH) != 0;
-  const bool prof = (p->flags & GENCD_PROFILE) != 0 && !use_graph;
+  const bool fused = (p->flags & GENCD_FUSED) != 0;
+  const bool prof = (p->flags & GENCD_PROFILE) != 0 && !use_graph && !fused;
   EventPool pool;
   std::vector<hipEvent_t> &evs = pool.v;
   size_t ev_used = 0;
@@ -606,6 +612,12 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       }
       if (positions == 0) continue;
       a.t = int32_t(t);
+      if (fused) {
+        // this window's pieces and the previous window's split pieces
+        rc = launch_fused(a, su.group, positions, 2 * long_bound_for(su, positions), false, es);
+        if (rc) return rc;
+        continue;
+      }
       const int64_t B = (rule == GENCD_THREAD_GREEDY) ? p->block : positions;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (record && !evs.empty() && ev_used + 2 <= evs.size()) {
@@ -615,6 +627,12 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       }
       rc = launch_iteration(a, su.group, mode, B, positions, long_bound_for(su, positions),
                             (positions + B - 1) / B, es, e0, e1);
+      if (rc) return rc;
+    }
+    if (fused && T > 0) {  // the last window's split columns
+      a.t = int32_t(T);
+      const int64_t last = rule == GENCD_BLOCK_SHOTGUN ? max_pb : S;
+      rc = launch_fused(a, su.group, 0, long_bound_for(su, last), true, es);
       if (rc) return rc;
     }
     if (mode != 1 && !a.exact_accum) {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgencd.so")
 OK, NOT_CONVERGED = 0, 1
 SQUARED, LOGISTIC = 0, 1
 CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY, BLOCK_SHOTGUN = range(8)
-WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE, EXACT_ACCUM = 0x1, 0x2, 0x4, 0x8, 0x10
+WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE, EXACT_ACCUM, FUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 RULES = {"cyclic": CYCLIC, "stochastic": STOCHASTIC, "shotgun": SHOTGUN,
          "thread_greedy": THREAD_GREEDY, "greedy": GREEDY, "coloring": COLORING,
          "top_greedy": TOP_GREEDY, "block_shotgun": BLOCK_SHOTGUN}
