@@ -141,7 +141,11 @@ def main():
     ws = G.workspace(X, G.make_params(**base))
 
     def run(rule, steps, warmup, flags=0, **kw):
+        nonlocal ws
         pr = dict(base, rule=rule, **kw)
+        need = G.workspace_bytes(X, G.make_params(flags=flags, **pr))
+        if need > ws.numel():  # e.g. Block Shotgun's per-block vectors
+            ws = G.workspace(X, G.make_params(flags=flags, **pr))
         for _ in range(warmup):
             G.solve(X, y, G.make_params(**pr), ws=ws)
         torch.cuda.synchronize()

@@ -122,8 +122,9 @@ typedef struct {
   int32_t improve_steps; /* "Improve delta_j" (Algorithm 3, section 4.1): up to this
                             many further quadratic-approximation steps on each
                             accepted proposal's 1-D objective, from the state at
-                            the start of the iteration; stops early at a fixed
-                            point.  0 = off (default); the paper used 500.
+                            the start of the iteration; stops early once a step
+                            no longer changes the increment.  0 = off (default);
+                            the paper used 500.
                             gencd_solve / gencd_step only (0..1000000) */
 } gencd_params;
 

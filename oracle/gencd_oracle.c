@@ -233,7 +233,8 @@ static int cmp_top(const void *a, const void *b) {
  * along column j, from d = delta and the state z of the iteration start:
  *   g = (1/n) sum_i x_ij l'(y_i, z_i + d x_ij),
  *   d <- d + (Eq. 7 increment at the point w_j + d with gradient g).
- * An increment of exactly zero is a fixed point, so the loop stops there. */
+ * The loop stops once a step no longer changes d (in the arithmetic's own
+ * precision): from there every further step would repeat it. */
 static double improve_delta(const orc_csc *X, const double *y, int loss, double lambda, double c,
                             int64_t j, double wj, const double *z, double d, int32_t steps) {
   if (d == 0.0) return d;
@@ -246,8 +247,9 @@ static double improve_delta(const orc_csc *X, const double *y, int loss, double 
     g /= (double)X->n;
     double inc, unused;
     orc_propose(g, c, wj + d, lambda, &inc, &unused);
-    if (inc == 0.0) break;
-    d += inc;
+    double dn = d + inc;
+    if (dn == d) break; /* the step no longer changes the increment */
+    d = dn;
   }
   return d;
 }

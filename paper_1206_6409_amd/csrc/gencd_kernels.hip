@@ -687,11 +687,13 @@ __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
 }
 
 // Finalise the split columns among positions [lo, hi) of the window: find
-// them in parallel, then sum each one's partials (in piece order) with the
-// whole workgroup of NT threads, and write delta, phi (and g).
+// them in parallel, then each wave of the NT-thread workgroup takes one and
+// sums its partials (in piece order, as Update does) with shuffles, and
+// writes delta, phi (and g).
 template <int NT>
 __device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_t P0,
-                               int32_t *smulti, int32_t *nmulti, float *sred) {
+                               int32_t *smulti, int32_t *nmulti) {
+  const int lane = int(threadIdx.x) & (kWave - 1);
   for (int64_t c0 = lo; c0 < hi; c0 += NT) {
     if (threadIdx.x == 0) *nmulti = 0;
     __syncthreads();
@@ -699,28 +701,20 @@ __device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_
     if (pp < hi && a.loff[pp + 1] - a.loff[pp] > 1) smulti[atomicAdd(nmulti, 1)] = int32_t(pp);
     __syncthreads();
     const int32_t cnt = *nmulti;
-    for (int32_t m = 0; m < cnt; ++m) {
+    for (int32_t m = int32_t(threadIdx.x) / kWave; m < cnt; m += NT / kWave) {
       const int32_t p = smulti[m];
       const int32_t pf = a.loff[p], np = a.loff[p + 1] - pf;
-      float t = 0.0f;
-      for (int32_t u = threadIdx.x; u < np; u += NT) t += a.gacc[pf + u];
-      sred[threadIdx.x] = t;
-      __syncthreads();
-      for (int off = NT / 2; off > 0; off >>= 1) {
-        if (int(threadIdx.x) < off) sred[threadIdx.x] += sred[threadIdx.x + off];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) {
+      const float g = split_sum(a.gacc, pf, np, lane) / a.n_f;
+      if (lane == 0) {
         const int32_t j = a.col_of_pos[p];
-        const float g = sred[0] / a.n_f;
         float d, ph;
         propose_f32(g, a.c[j], a.w[j], a.lam, d, ph);
         a.delta[p - P0] = d;
         a.phi[p - P0] = ph;
         if (a.gout) a.gout[p - P0] = g;
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -730,7 +724,6 @@ __device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_
 __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
   __shared__ float sphi[kBlock];
   __shared__ int32_t spos[kBlock];
-  __shared__ float sred[kBlock];
   __shared__ int32_t smulti[kBlock];
   __shared__ int32_t nmulti;
   int32_t P0, P1;
@@ -738,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
   const int64_t nblk = (int64_t(P1 - P0) + B - 1) / B;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int64_t lo = P0 + b * B, hi = min(lo + B, int64_t(P1));
-    finalize_split<kBlock>(a, lo, hi, P0, smulti, &nmulti, sred);
+    finalize_split<kBlock>(a, lo, hi, P0, smulti, &nmulti);
     float best = INFINITY;
     int32_t bpos = INT32_MAX;
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBlock) {
@@ -795,18 +788,17 @@ __device__ __forceinline__ unsigned long long top_key(float phi, int64_t off) {
 }
 
 __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
-  __shared__ float sred[kTopThreads];
   __shared__ int32_t smulti[kTopThreads];
   __shared__ int32_t nmulti;
   __shared__ uint32_t hist[256];
   __shared__ unsigned long long s_prefix;
-  __shared__ int64_t s_rank;
+  __shared__ int64_t s_rank, s_bincnt;
   __shared__ unsigned long long s_cnt[2][kTopThreads / kWave];
   int32_t P0, P1;
   window_of(a, P0, P1);
   const int64_t m = int64_t(P1) - P0;
   if (m <= 0) return;
-  finalize_split<kTopThreads>(a, P0, P1, P0, smulti, &nmulti, sred);
+  finalize_split<kTopThreads>(a, P0, P1, P0, smulti, &nmulti);
   const int64_t K = a.accept_top < m ? a.accept_top : m;
   if (threadIdx.x == 0) {
     s_prefix = 0ull;
@@ -822,18 +814,43 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
       if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t r = s_rank, cum = 0;
-      int b = 0;
-      for (; b < 255; ++b) {
-        if (cum + int64_t(hist[b]) >= r) break;
-        cum += hist[b];
+    if (threadIdx.x < kWave) {
+      // the bin holding rank r: wave prefix sum over 4 bins per lane
+      const int lane = int(threadIdx.x);
+      const int64_t r = s_rank;
+      int64_t c[4], tot = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        c[i] = hist[4 * lane + i];
+        tot += c[i];
       }
-      s_rank = r - cum;
-      s_prefix = prefix | (static_cast<unsigned long long>(b) << shift);
+      int64_t incl = tot;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t o = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += o;
+      }
+      int64_t cum = incl - tot;
+      if (cum < r && r <= incl) {  // exactly one lane
+        int i = 0;
+        for (; i < 3; ++i) {
+          if (cum + c[i] >= r) break;
+          cum += c[i];
+        }
+        s_rank = r - cum;
+        s_bincnt = c[i];
+        s_prefix = prefix | (static_cast<unsigned long long>(4 * lane + i) << shift);
+      }
     }
     mask |= 255ull << shift;
     __syncthreads();
+    // after the proxy half of the key: if every candidate left is taken,
+    // the positions need no further passes
+    if (shift == 32 && s_rank == s_bincnt) {
+      if (threadIdx.x == 0) s_prefix |= 0xFFFFFFFFull;
+      __syncthreads();
+      break;
+    }
   }
   const unsigned long long kth = s_prefix;
   unsigned long long nnz = 0ull, cnt = 0ull;
@@ -1027,7 +1044,7 @@ int launch_unpack_state(int64_t n, const float4 *zs, float *z_hi, float *z_lo, h
 // approximation steps on the column's 1-D objective from the state at the
 // start of the iteration:
 //   g = (1/n) sum_i x_ij l'(y_i, z_i + d x_ij),  d += Eq. 7 increment at w_j + d,
-// stopping at a fixed point (an increment of exactly zero).  The first
+// stopping once a step no longer changes d in FP32.  The first
 // kImproveRegs * 64 entries stay in registers across steps; longer columns
 // re-read the rest each step.  Split columns (accept-all rules) get their
 // first increment here from the partial sums.  Writes delta and w_j =
@@ -1081,17 +1098,29 @@ __global__ __launch_bounds__(kBlock) void k_improve(IterArgs a) {
 #pragma unroll
         for (int u = 0; u < kImproveRegs; ++u)
           if (ri[u] >= 0) sum += vv[u] * dloss_f32(a.loss, yy[u], zb[u] + d * vv[u]);
-        for (int64_t e = int64_t(kImproveRegs) * kWave + lane; e < len; e += kWave) {
-          const int32_t i = a.row_idx[cb + e];
-          const float v = a.val[cb + e];
-          const float4 zr = a.zs[i];
-          sum += v * dloss_f32(a.loss, zr.z, (zr.x + zr.y) + d * v);
+        for (int64_t e0 = int64_t(kImproveRegs) * kWave + lane; e0 < len;
+             e0 += int64_t(kUnroll) * kWave) {
+          int32_t rj[kUnroll];
+          float vj[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int64_t e = e0 + int64_t(u) * kWave;
+            rj[u] = e < len ? a.row_idx[cb + e] : -1;
+            vj[u] = e < len ? a.val[cb + e] : 0.0f;
+          }
+          float4 zr[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) zr[u] = a.zs[rj[u] >= 0 ? rj[u] : 0];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u)
+            if (rj[u] >= 0) sum += vj[u] * dloss_f32(a.loss, zr[u].z, (zr[u].x + zr[u].y) + d * vj[u]);
         }
         const float g = group_sum<kWave>(sum) / a.n_f;  // identical in every lane
         float inc, ph;
         propose_f32(g, cj, w0 + d, a.lam, inc, ph);
-        if (inc == 0.0f) break;
-        d += inc;
+        const float dn = d + inc;
+        if (dn == d) break;  // the step no longer changes d: every later one would repeat it
+        d = dn;
       }
     }
     if (lane == 0) {
