@@ -38,7 +38,8 @@ struct ColorWs {
   int32_t *fcnt;              // [k+1] frontier nnz counts, then offsets
   int32_t *foff;              // [k+1]
   int32_t *scan_part;
-  int32_t *ctl;               // [8] next frontier size, max colour, error flags
+  int32_t *ctl;               // [8] frontier sizes (0, 4: by round parity), max colour
+                              // snapshot (1), error flag (2), max colour (3), coloured (5)
   void *sort_tmp;
   size_t sort_tmp_bytes;
 };
@@ -156,13 +157,15 @@ __global__ __launch_bounds__(kBlock) void k_init_count(const int64_t *col_ptr, i
 }
 
 // colour of each frontier column: mex of the colours in its row prefixes
-__global__ __launch_bounds__(kBlock) void k_mex(const int64_t *col_ptr, const int32_t *row_idx,
-                                                 const int32_t *front, int32_t F,
+// (one workgroup per frontier column, LDS bitmap of the colours so far)
+__global__ __launch_bounds__(kBlock) void k_mex(const int32_t *Fp, const int64_t *col_ptr,
+                                                 const int32_t *row_idx, const int32_t *front,
                                                  const int32_t *row_ptr, const int32_t *rank_at,
                                                  const int32_t *pos_in_row, const int32_t *order,
                                                  int32_t *color, int32_t *ctl) {
   __shared__ uint32_t bits[kMexWords];
   __shared__ int32_t best;
+  const int32_t F = *Fp;
   const int32_t maxc = ctl[1];  // largest colour so far (-1 initially)
   int32_t words = (maxc + 2 + 31) / 32;
   if (words > kMexWords) words = kMexWords;
@@ -174,8 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_mex(const int64_t *col_ptr, const in
     for (int64_t e = col_ptr[j] + threadIdx.x; e < col_ptr[j + 1]; e += kBlock) {
       const int32_t r = row_idx[e];
       const int32_t a = row_ptr[r], b = a + pos_in_row[e];
-      for (int32_t s = a; s < b; ++s) {
-        const int32_t c = color[order[rank_at[s]]];
+      for (int32_t q = a; q < b; ++q) {
+        const int32_t c = color[order[rank_at[q]]];
         if (c >= 0 && c < kMexWords * 32) atomicOr(&bits[c >> 5], 1u << (c & 31));
       }
     }
@@ -203,8 +206,9 @@ __global__ __launch_bounds__(kBlock) void k_mex(const int64_t *col_ptr, const in
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_front_nnz(const int64_t *col_ptr, const int32_t *front,
-                                                       int32_t F, int32_t *cnt) {
+__global__ __launch_bounds__(kBlock) void k_front_nnz(const int32_t *Fp, const int64_t *col_ptr,
+                                                       const int32_t *front, int32_t *cnt) {
+  const int32_t F = *Fp;
   for (int64_t f = int64_t(blockIdx.x) * kBlock + threadIdx.x; f < F;
        f += int64_t(gridDim.x) * kBlock) {
     const int32_t j = front[f];
@@ -213,13 +217,14 @@ __global__ __launch_bounds__(kBlock) void k_front_nnz(const int64_t *col_ptr, co
 }
 
 // Flattened over the frontier's CSC entries: decrement later row neighbours.
-__global__ __launch_bounds__(kBlock) void k_decrement(const int64_t *col_ptr, const int32_t *row_idx,
-                                                       const int32_t *front, int32_t F,
+__global__ __launch_bounds__(kBlock) void k_decrement(const int32_t *Fp, const int64_t *col_ptr,
+                                                       const int32_t *row_idx, const int32_t *front,
                                                        const int32_t *foff, const int32_t *row_ptr,
                                                        const int32_t *rank_at,
                                                        const int32_t *pos_in_row,
                                                        const int32_t *order, int32_t *count,
-                                                       int32_t *next, int32_t *ctl) {
+                                                       int32_t *next, int32_t *next_cnt) {
+  const int32_t F = *Fp;
   const int32_t total = foff[F];
   for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < total;
        t += int64_t(gridDim.x) * kBlock) {
@@ -234,8 +239,18 @@ __global__ __launch_bounds__(kBlock) void k_decrement(const int64_t *col_ptr, co
     const int32_t b = row_ptr[r + 1];
     for (int32_t s = row_ptr[r] + pos_in_row[e] + 1; s < b; ++s) {
       const int32_t j2 = order[rank_at[s]];
-      if (atomicSub(&count[j2], 1) == 1) next[atomicAdd(&ctl[0], 1)] = j2;
+      if (atomicSub(&count[j2], 1) == 1) next[atomicAdd(next_cnt, 1)] = j2;
     }
+  }
+}
+
+// End of a round: snapshot of the largest colour for the next mex, running
+// count of coloured columns, and a zero count for the round after next.
+__global__ void k_round_end(int32_t *ctl, const int32_t *Fp, int32_t *clear_cnt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[1] = ctl[3];
+    ctl[5] += *Fp;
+    *clear_cnt = 0;
   }
 }
 
@@ -292,39 +307,44 @@ int color_run(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws_
   hipLaunchKernelGGL(k_init_count, dim3(g1(k * kWave, 8192)), dim3(kBlock), 0, s, X->col_ptr, k,
                      w.pos_in_row, w.count, color, w.front_a, w.ctl);
   GENCD_HIP(hipGetLastError());
-  int32_t F = 0;
-  GENCD_HIP(hipMemcpyAsync(&F, w.ctl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GENCD_HIP(hipStreamSynchronize(s));
-  int64_t coloured = 0;
+  // Rounds run without the host: every kernel reads the frontier size from
+  // the device (counters by round parity); the host looks at the counters
+  // once per kRoundsPerSync rounds.  Rounds past the last frontier find an
+  // empty one and do nothing.
+  constexpr int kRoundsPerSync = 32;
+  st = fill_i32(w.fcnt, k + 1, 0, s);  // the scan covers all k entries; those past F stay finite
+  if (st) return st;
+  const unsigned mex_grid = 4096;  // grid-stride over the frontier (one column per wave or block)
   int32_t *cur = w.front_a, *nxt = w.front_b;
   int32_t ctl_host[8];
-  while (F > 0) {
-    coloured += F;
-    if (coloured > k) return GENCD_ERR_HIP;  // cannot happen for a valid CSC
-    st = fill_i32(w.ctl, 1, 0, s);
-    if (st) return st;
-    hipLaunchKernelGGL(k_mex, dim3(unsigned(F < 16384 ? F : 16384)), dim3(kBlock), 0, s,
-                       X->col_ptr, X->row_idx, cur, F, w.row_ptr, w.rank_at, w.pos_in_row,
-                       w.order, color, w.ctl);
-    hipLaunchKernelGGL(k_front_nnz, dim3(g1(F)), dim3(kBlock), 0, s, X->col_ptr, cur, F, w.fcnt);
-    st = scan_exclusive(w.fcnt, w.foff, F, w.scan_part, s);
-    if (st) return st;
-    hipLaunchKernelGGL(k_decrement, dim3(g1(nnz > 0 ? nnz : 1, 8192)), dim3(kBlock), 0, s,
-                       X->col_ptr, X->row_idx, cur, F, w.foff, w.row_ptr, w.rank_at,
-                       w.pos_in_row, w.order, w.count, nxt, w.ctl);
-    // the next round's mex needs the largest colour: ctl[1] <- ctl[3]
-    GENCD_HIP(hipMemcpyAsync(w.ctl + 1, w.ctl + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  int64_t round = 0;
+  for (;;) {
+    for (int r = 0; r < kRoundsPerSync; ++r, ++round) {
+      int32_t *fc = w.ctl + ((round & 1) ? 4 : 0), *fn = w.ctl + ((round & 1) ? 0 : 4);
+      hipLaunchKernelGGL(k_mex, dim3(mex_grid), dim3(kBlock), 0, s, fc, X->col_ptr, X->row_idx,
+                         cur, w.row_ptr, w.rank_at, w.pos_in_row, w.order, color, w.ctl);
+      hipLaunchKernelGGL(k_front_nnz, dim3(g1(k)), dim3(kBlock), 0, s, fc, X->col_ptr, cur,
+                         w.fcnt);
+      st = scan_exclusive(w.fcnt, w.foff, k, w.scan_part, s);  // entries before F count
+      if (st) return st;
+      hipLaunchKernelGGL(k_decrement, dim3(g1(nnz > 0 ? nnz : 1, 8192)), dim3(kBlock), 0, s, fc,
+                         X->col_ptr, X->row_idx, cur, w.foff, w.row_ptr, w.rank_at, w.pos_in_row,
+                         w.order, w.count, nxt, fn);
+      // this round's counter is next written as the frontier two rounds on
+      hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, w.ctl, fc, fc);
+      int32_t *t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    GENCD_HIP(hipGetLastError());
     GENCD_HIP(hipMemcpyAsync(ctl_host, w.ctl, sizeof(ctl_host), hipMemcpyDeviceToHost, s));
     GENCD_HIP(hipStreamSynchronize(s));
     if (ctl_host[2]) return GENCD_ERR_UNSUPPORTED;  // more colours than the bitmap holds
-    F = ctl_host[0];
-    int32_t *t = cur;
-    cur = nxt;
-    nxt = t;
+    if (ctl_host[5] > k) return GENCD_ERR_HIP;      // cannot happen for a valid CSC
+    if (ctl_host[(round & 1) ? 4 : 0] == 0) break;
+    if (round > k + kRoundsPerSync) return GENCD_ERR_HIP;
   }
-  if (coloured != k) return GENCD_ERR_HIP;
-  GENCD_HIP(hipMemcpyAsync(ctl_host, w.ctl, sizeof(ctl_host), hipMemcpyDeviceToHost, s));
-  GENCD_HIP(hipStreamSynchronize(s));
+  if (ctl_host[5] != k) return GENCD_ERR_HIP;
   *num_colors = ctl_host[3] + 1;
   return GENCD_OK;
 }
