@@ -80,6 +80,8 @@ def lib():
         L.orc_block_base.restype = I64
         L.orc_block_base.argtypes = [P, C.c_uint64, P]
         L.orc_block_pstar.argtypes = [P, C.c_uint64, I64, I32, P, P]
+        L.orc_balance_colors.restype = I32
+        L.orc_balance_colors.argtypes = [I64, P, P, I32, I64, P]
         L.orc_color.argtypes = [I64, I64, P, P, I32, P, P, P]
         L.orc_solve.restype = I32
         L.orc_solve.argtypes = [P, P, P, P, P, P]
@@ -241,6 +243,16 @@ def block_pstar(X: Matrix, seed, nb, iters=20):
     if st != 0:
         raise ValueError(f"orc_block_pstar failed: {st}")
     return rho, ps
+
+
+def balance_colors(k, col_ptr, color, num_colors, cap=0):
+    """Split every class above `cap` live columns into near-equal parts
+    (members in column order); returns (new colours, number of colours)."""
+    col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int64)
+    color = np.ascontiguousarray(color, dtype=np.int32)
+    out = np.zeros(k, dtype=np.int32)
+    nc = lib().orc_balance_colors(int(k), _p(col_ptr), _p(color), int(num_colors), int(cap), _p(out))
+    return out, int(nc)
 
 
 def color(n, k, col_ptr, row_idx, order_mode=0):

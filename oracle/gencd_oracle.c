@@ -630,6 +630,50 @@ int orc_color(int64_t n, int64_t k, const int64_t *col_ptr, const int32_t *row_i
 /* ------------------------------------------------------------------------ */
 
 /* Selected set J for iteration t of epoch e.  Returns its size. */
+/* Balanced colouring (section 4.1 Coloring, "more colours, even class
+ * sizes"): every class of more than `cap` live columns is split into
+ * parts = ceil(size / cap) parts; the member of rank r (column order) goes
+ * to part floor(r * parts / size).  A part of an independent set is
+ * independent, so the result is a valid colouring with classes of at most
+ * cap columns.  New colours are numbered class by class, parts in order.
+ * cap <= 0 takes the mean class size ceil(k_live / C).  Empty columns keep
+ * their colour's first part.  Returns the number of colours. */
+int32_t orc_balance_colors(int64_t k, const int64_t *col_ptr, const int32_t *color, int32_t C,
+                           int64_t cap, int32_t *out) {
+  int64_t *size = (int64_t *)calloc((size_t)C + 1, sizeof(int64_t));
+  int64_t *parts = (int64_t *)calloc((size_t)C + 1, sizeof(int64_t));
+  int64_t *first = (int64_t *)calloc((size_t)C + 1, sizeof(int64_t));
+  int64_t *seen = (int64_t *)calloc((size_t)C + 1, sizeof(int64_t));
+  int64_t kl = 0;
+  for (int64_t j = 0; j < k; ++j)
+    if (col_ptr[j + 1] > col_ptr[j]) {
+      size[color[j]]++;
+      kl++;
+    }
+  if (cap <= 0) cap = C > 0 ? (kl + C - 1) / C : 1;
+  if (cap < 1) cap = 1;
+  int64_t total = 0;
+  for (int32_t c = 0; c < C; ++c) {
+    parts[c] = size[c] > cap ? (size[c] + cap - 1) / cap : 1;
+    first[c] = total;
+    total += parts[c];
+  }
+  for (int64_t j = 0; j < k; ++j) {
+    int32_t c = color[j];
+    if (col_ptr[j + 1] > col_ptr[j]) {
+      int64_t r = seen[c]++;
+      out[j] = (int32_t)(first[c] + r * parts[c] / size[c]);
+    } else {
+      out[j] = (int32_t)first[c];
+    }
+  }
+  free(size);
+  free(parts);
+  free(first);
+  free(seen);
+  return (int32_t)total;
+}
+
 static int64_t select_set(const orc_params *P, int64_t k_live, const int32_t *live,
                           const int64_t *cls_off, const int32_t *cls_mem, int32_t ncls, int64_t e,
                           int64_t t, int32_t *J) {

@@ -398,11 +398,9 @@ def test_objective_is_unique_across_rules():
 # colouring (section 4.1, partial distance-2 colouring)
 # --------------------------------------------------------------------------
 
-def check_colouring(n, k, col_ptr, row_idx, color, order):
+def check_colouring(n, k, col_ptr, row_idx, color, order, mex=True):
     rows_of = [set(row_idx[col_ptr[j]:col_ptr[j + 1]].tolist()) for j in range(k)]
     # valid: no two columns of one colour share a row
-    for i in range(n):
-        pass
     by_row = {}
     for j in range(k):
         for i in rows_of[j]:
@@ -410,6 +408,8 @@ def check_colouring(n, k, col_ptr, row_idx, color, order):
     for i, cols in by_row.items():
         cs = [color[j] for j in cols]
         assert len(cs) == len(set(cs)), f"row {i} has a repeated colour"
+    if not mex:
+        return
     # greedy: colour = mex over earlier neighbours in the visit order
     pos = np.empty(k, dtype=np.int64)
     pos[order] = np.arange(k)
@@ -860,3 +860,41 @@ def test_block_shotgun_reaches_the_optimum(kind):
     # every live column is visited once per epoch
     kl = int(np.sum(np.diff(P.col_ptr) > 0))
     assert r.coord_updates == kl * r.epochs
+
+
+# --------------------------------------------------------------------------
+# Balanced colouring: classes above a cap are split into near-equal parts
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cap", [0, 1, 7, 10**9])
+def test_balanced_colouring_is_valid_and_even(cap):
+    P = synth.c3_zipf_lasso(scale=0.003)
+    color, nc, order = O.color(P.n, P.k, P.col_ptr, P.row_idx)
+    bal, nb = O.balance_colors(P.k, P.col_ptr, color, nc, cap)
+    live = np.diff(P.col_ptr) > 0
+    kl = int(live.sum())
+    sizes = np.bincount(color[live], minlength=nc)
+    bsizes = np.bincount(bal[live], minlength=nb)
+    c = cap if cap > 0 else -(-kl // nc)
+    # every class of the balanced colouring fits the cap, unless it was
+    # already a single class no larger than the cap
+    assert bsizes.max() <= max(c, 1)
+    assert bsizes.sum() == kl and nb == sum(max(1, -(-int(s) // c)) for s in sizes)
+    # a refinement of the original colouring: still a valid colouring
+    first = {}
+    for j in np.nonzero(live)[0]:
+        assert first.setdefault(int(bal[j]), int(color[j])) == int(color[j])
+    check_colouring(P.n, P.k, P.col_ptr, P.row_idx, bal, order, mex=False)
+    if cap == 10**9:
+        assert nb == nc and np.array_equal(bal[live], color[live])
+    if cap == 1:
+        assert nb >= kl
+
+
+def test_balanced_colouring_parts_are_near_equal():
+    # one class of 10 columns with cap 4: parts of 4, 3, 3 in column order
+    k = 10
+    col_ptr = np.arange(k + 1, dtype=np.int64)
+    color = np.zeros(k, dtype=np.int32)
+    bal, nb = O.balance_colors(k, col_ptr, color, 1, 4)
+    assert nb == 3 and bal.tolist() == [0, 0, 0, 0, 1, 1, 1, 2, 2, 2]
