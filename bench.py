@@ -344,6 +344,13 @@ def bench_coloring(args):
                            reps=args.steps)
     best = min(t_plain, t_graph)
     st = (resg if t_graph <= t_plain else res).stats
+    # balanced colouring: classes above the mean size split into parts
+    t_bal, (bal, nbal) = _timed(lambda: G.balance_colors(X, colors, nc, 0), reps=3)
+    bparams = dict(params, colors=bal, num_colors=nbal)
+    G.solve(X, y, G.make_params(**bparams))
+    t_bsolve, resb = _timed(lambda: G.solve(X, y, G.make_params(flags=G.USE_GRAPH, **bparams)),
+                            reps=args.steps)
+    bsizes = np.bincount(bal.cpu().numpy()[np.diff(P.col_ptr) > 0], minlength=nbal)
     Xo = O.Matrix.of(P)
     t0 = time.perf_counter()
     r = O.solve(Xo, P.y.astype(np.float64), P.loss, lam, O.COLORING, colors=ocol, seed=3,
@@ -358,6 +365,9 @@ def bench_coloring(args):
         "colouring": {"gpu_ms": t_col * 1e3, "oracle_cpu_ms": t_ocol * 1e3, "colors": int(nc),
                       "bit_exact": exact, "mean_class_size": float(sizes[sizes > 0].mean()),
                       "max_class_size": int(sizes.max())},
+        "balanced": {"gpu_ms": t_bal * 1e3, "colors": int(nbal), "max_class_size": int(bsizes.max()),
+                     "solve_ms": t_bsolve * 1e3, "epochs": resb.stats["epochs"],
+                     "objective": resb.stats["objective"]},
         "solves_per_s": 1.0 / best, "plain_path_ms": t_plain * 1e3, "graph_path_ms": t_graph * 1e3,
         "epochs": st["epochs"], "iters": st["iters"], "objective": st["objective"],
         "kkt_max": st["kkt_max"],

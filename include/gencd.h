@@ -213,6 +213,25 @@ int gencd_color_workspace_bytes(const gencd_csc *X, size_t *out_bytes);
 int gencd_color(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws,
                 size_t ws_bytes, hipStream_t stream);
 
+/* Balanced colouring ("more colours, even class sizes"): every class of the
+ * colouring `color` (device int32[k], values in [0, num_colors)) with more
+ * than `cap` live columns is split into ceil(size / cap) near-equal parts,
+ * its members in column order (rank r of a class of size s split into p
+ * parts goes to part floor(r p / s)); cap <= 0 takes the mean class size
+ * ceil(k_live / num_colors).  A part of an independent set is independent,
+ * so the result is a valid colouring for GENCD_COLORING with classes of at
+ * most cap columns.  New colours are numbered class by class, parts in
+ * order; an empty column gets its class's first part.
+ *   balanced      device int32[k] output (may not alias color)
+ *   num_balanced  host: number of colours of the result
+ *   ws            device workspace of gencd_balance_workspace_bytes bytes
+ * Synchronises the stream.  Errors: INVALID_ARG (also a colour outside
+ * [0, num_colors)), WORKSPACE, UNSUPPORTED, HIP. */
+int gencd_balance_workspace_bytes(const gencd_csc *X, int32_t num_colors, size_t *out_bytes);
+int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_colors,
+                         int64_t cap, int32_t *balanced, int32_t *num_balanced, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
 /* Regularisation path: solve Eq. (1) for L values of lambda (any order;
  * decreasing order makes the warm starts effective) on one matrix, B of them
  * at a time in one batched launch sequence (B in {16, 32, 64}).  All slots

@@ -17,6 +17,7 @@
 //     next round's frontier.
 // Each frontier column takes the mex of the colours in its row prefixes.
 #include <hipcub/hipcub.hpp>
+#include <vector>
 
 #include "gencd_common.hpp"
 #include "gencd_kernels.hpp"
@@ -353,6 +354,142 @@ size_t color_workspace(int64_t n, int64_t k, int64_t nnz) {
   return color_layout(n, k, nnz, nullptr, nullptr) + 256;
 }
 
+// ---------------------------------------------------------------------------
+// Balanced colouring: every class above `cap` live columns is split into
+// ceil(size / cap) near-equal parts, members in column order (rank r of a
+// class of size s with p parts goes to part floor(r p / s)).  A stable sort
+// of the live columns by colour gives each member its rank.
+// ---------------------------------------------------------------------------
+struct BalanceWs {
+  uint32_t *keys_a, *keys_b;  // [k]
+  int32_t *vals_a, *vals_b;   // [k]
+  int32_t *size, *first, *parts, *off;  // [C+1]
+  void *sort_tmp;
+  size_t sort_tmp_bytes;
+};
+
+static size_t balance_layout(int64_t k, int64_t C, void *base, BalanceWs *w) {
+  const size_t al = 256;
+  size_t off = 0;
+  char *b = static_cast<char *>(base);
+  auto take = [&](size_t bytes) -> void * {
+    off = (off + al - 1) / al * al;
+    void *p = b ? b + off : nullptr;
+    off += bytes > 0 ? bytes : 1;
+    return p;
+  };
+  BalanceWs c{};
+  c.keys_a = static_cast<uint32_t *>(take(sizeof(uint32_t) * k));
+  c.keys_b = static_cast<uint32_t *>(take(sizeof(uint32_t) * k));
+  c.vals_a = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  c.vals_b = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  c.size = static_cast<int32_t *>(take(sizeof(int32_t) * (C + 1)));
+  c.first = static_cast<int32_t *>(take(sizeof(int32_t) * (C + 1)));
+  c.parts = static_cast<int32_t *>(take(sizeof(int32_t) * (C + 1)));
+  c.off = static_cast<int32_t *>(take(sizeof(int32_t) * (C + 1)));
+  size_t tb = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, static_cast<const uint32_t *>(nullptr),
+                                           static_cast<uint32_t *>(nullptr),
+                                           static_cast<const int32_t *>(nullptr),
+                                           static_cast<int32_t *>(nullptr), int(k), 0, 32);
+  c.sort_tmp_bytes = tb;
+  c.sort_tmp = take(tb);
+  if (w) *w = c;
+  return off + al;
+}
+
+// keys: colour of live columns, C for empty ones (sorted last); class sizes
+__global__ __launch_bounds__(kBlock) void k_bal_keys(const int64_t *col_ptr, int64_t k,
+                                                      const int32_t *color, int32_t C,
+                                                      uint32_t *keys, int32_t *vals, int32_t *size,
+                                                      int32_t *bad) {
+  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
+       j += int64_t(gridDim.x) * kBlock) {
+    const int32_t c = color[j];
+    if (c < 0 || c >= C) {
+      atomicOr(bad, 1);
+      keys[j] = uint32_t(C);
+    } else if (col_ptr[j + 1] > col_ptr[j]) {
+      keys[j] = uint32_t(c);
+      atomicAdd(&size[c], 1);
+    } else {
+      keys[j] = uint32_t(C);
+    }
+    vals[j] = int32_t(j);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bal_assign(const int64_t *col_ptr, int64_t k,
+                                                        const int32_t *color, const uint32_t *keys,
+                                                        const int32_t *vals, const int32_t *size,
+                                                        const int32_t *first, const int32_t *parts,
+                                                        const int32_t *off, int32_t C,
+                                                        int32_t *out) {
+  for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < k;
+       t += int64_t(gridDim.x) * kBlock) {
+    const int32_t j = vals[t];
+    const uint32_t c = keys[t];
+    if (c < uint32_t(C)) {
+      const int64_t r = t - off[c];  // rank of j in its class, column order
+      out[j] = int32_t(first[c] + r * parts[c] / size[c]);
+    } else {
+      const int32_t c0 = color[j];
+      out[j] = (c0 >= 0 && c0 < C) ? first[c0] : 0;
+    }
+  }
+}
+
+int balance_run(const gencd_csc *X, const int32_t *color, int32_t C, int64_t cap, int32_t *out,
+                int32_t *num_out, void *ws_base, size_t ws_bytes, hipStream_t s) {
+  const int64_t k = X->k;
+  size_t need = balance_layout(k, C, nullptr, nullptr);
+  if (!ws_base || ws_bytes < need) return GENCD_ERR_WORKSPACE;
+  char *base = static_cast<char *>(ws_base);
+  size_t mis = reinterpret_cast<uintptr_t>(base) % 256;
+  if (mis) base += 256 - mis;
+  BalanceWs w{};
+  balance_layout(k, C, base, &w);
+  int st = fill_i32(w.size, C + 1, 0, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_bal_keys, dim3(g1(k)), dim3(kBlock), 0, s, X->col_ptr, k, color, C, w.keys_a,
+                     w.vals_a, w.size, w.size + C);
+  GENCD_HIP(hipGetLastError());
+  size_t tb = w.sort_tmp_bytes;
+  GENCD_HIP(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.keys_a, w.keys_b, w.vals_a,
+                                               w.vals_b, int(k), 0, 32, s));
+  // parts and numbering on the host (C + 1 counters)
+  std::vector<int32_t> size(size_t(C) + 1), first(size_t(C) + 1), parts(size_t(C) + 1),
+      off(size_t(C) + 1);
+  GENCD_HIP(hipMemcpyAsync(size.data(), w.size, sizeof(int32_t) * (size_t(C) + 1),
+                           hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipStreamSynchronize(s));
+  if (size[size_t(C)]) return GENCD_ERR_INVALID_ARG;  // a colour outside [0, C)
+  int64_t kl = 0;
+  for (int32_t c = 0; c < C; ++c) kl += size[size_t(c)];
+  if (cap <= 0) cap = (kl + C - 1) / C;
+  if (cap < 1) cap = 1;
+  int64_t total = 0, o = 0;
+  for (int32_t c = 0; c < C; ++c) {
+    const int64_t sz = size[size_t(c)];
+    const int64_t pc = sz > cap ? (sz + cap - 1) / cap : 1;
+    parts[size_t(c)] = int32_t(pc);
+    first[size_t(c)] = int32_t(total);
+    off[size_t(c)] = int32_t(o);
+    total += pc;
+    o += sz;
+  }
+  if (total >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  GENCD_HIP(hipMemcpyAsync(w.first, first.data(), sizeof(int32_t) * size_t(C), hipMemcpyHostToDevice, s));
+  GENCD_HIP(hipMemcpyAsync(w.parts, parts.data(), sizeof(int32_t) * size_t(C), hipMemcpyHostToDevice, s));
+  GENCD_HIP(hipMemcpyAsync(w.off, off.data(), sizeof(int32_t) * size_t(C), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_bal_assign, dim3(g1(k)), dim3(kBlock), 0, s, X->col_ptr, k, color, w.keys_b,
+                     w.vals_b, w.size, w.first, w.parts, w.off, C, out);
+  GENCD_HIP(hipGetLastError());
+  GENCD_HIP(hipStreamSynchronize(s));  // the host vectors above must outlive the copies
+  *num_out = int32_t(total);
+  return GENCD_OK;
+}
+
 }  // namespace gencd
 
 extern "C" {
@@ -362,6 +499,24 @@ int gencd_color_workspace_bytes(const gencd_csc *X, size_t *out_bytes) {
   if (X->n > INT32_MAX || X->k >= INT32_MAX || X->nnz >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
   *out_bytes = gencd::color_workspace(X->n, X->k, X->nnz);
   return GENCD_OK;
+}
+
+int gencd_balance_workspace_bytes(const gencd_csc *X, int32_t num_colors, size_t *out_bytes) {
+  if (!X || !out_bytes || X->k <= 0 || num_colors <= 0) return GENCD_ERR_INVALID_ARG;
+  if (X->k >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  *out_bytes = gencd::balance_layout(X->k, num_colors, nullptr, nullptr) + 256;
+  return GENCD_OK;
+}
+
+int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_colors,
+                         int64_t cap, int32_t *balanced, int32_t *num_balanced, void *ws,
+                         size_t ws_bytes, hipStream_t stream) {
+  if (!X || !color || !balanced || !num_balanced || X->k <= 0 || !X->col_ptr || num_colors <= 0)
+    return GENCD_ERR_INVALID_ARG;
+  if (X->k >= INT32_MAX) return GENCD_ERR_UNSUPPORTED;
+  (void)hipGetLastError();
+  return gencd::balance_run(X, color, num_colors, cap, balanced, num_balanced, ws, ws_bytes,
+                            stream);
 }
 
 int gencd_color(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws, size_t ws_bytes,

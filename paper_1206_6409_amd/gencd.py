@@ -75,6 +75,9 @@ _SIGS = {
                               C.c_void_p]),
     "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "gencd_rho_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_balance_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "gencd_balance_colors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "gencd_block_rho_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "gencd_estimate_block_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -224,6 +227,21 @@ def estimate_rho(X: Matrix, iters=20, params=None):
                                     _ptr(ws), ws.numel(), _stream()), "gencd_estimate_rho")
     h = list(hist)
     return RhoResult(h[-1], h, kl.value, sel.value)
+
+
+def balance_colors(X: Matrix, colors: torch.Tensor, num_colors, cap=0):
+    """Split every colour class above `cap` live columns into near-equal
+    parts (column order); returns (colours, number of colours)."""
+    nb = C.c_size_t()
+    _check(lib().gencd_balance_workspace_bytes(X.ref, int(num_colors), C.byref(nb)),
+           "gencd_balance_workspace_bytes")
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=X.col_ptr.device)
+    out = torch.empty(X.k, dtype=torch.int32, device=X.col_ptr.device)
+    nc = C.c_int32()
+    _check(lib().gencd_balance_colors(X.ref, _ptr(colors), int(num_colors), int(cap), _ptr(out),
+                                      C.byref(nc), _ptr(ws), ws.numel(), _stream()),
+           "gencd_balance_colors")
+    return out, nc.value
 
 
 def estimate_block_rho(X: Matrix, num_blocks, iters=20, params=None):

@@ -144,3 +144,15 @@ def test_block_rho_host_validation():
         assert G.lib().gencd_estimate_block_rho(C.byref(X), None, nb, it, rho, ps, None, 0, None) == -1
     bad = G.make_params(1, 0.1, rule=G.BLOCK_SHOTGUN, block=0)
     assert G.lib().gencd_solve(C.byref(X), None, C.byref(bad), None, None, None, 0, None, None) == -1
+
+
+def test_balance_host_validation():
+    X = _fake_matrix(1000, 500, 4000)
+    out = C.c_size_t()
+    assert G.lib().gencd_balance_workspace_bytes(C.byref(X), 40, C.byref(out)) == 0
+    assert out.value >= 4 * 4 * 500
+    assert G.lib().gencd_balance_workspace_bytes(C.byref(X), 0, C.byref(out)) == -1
+    nc = C.c_int32()
+    assert G.lib().gencd_balance_colors(C.byref(X), None, 4, 0, None, C.byref(nc), None, 0, None) == -1
+    assert G.lib().gencd_balance_colors(C.byref(X), C.c_void_p(0x10), 0, 0, C.c_void_p(0x20),
+                                        C.byref(nc), None, 0, None) == -1

@@ -143,3 +143,35 @@ def test_coloring_graph_replays_bit_identical():
         assert res.status == G.OK and res.stats["epochs"] > 2
         ws.append(res.w.cpu().numpy())
     assert np.array_equal(ws[0], ws[1]) and np.array_equal(ws[1], ws[2])
+
+
+@pytest.mark.parametrize("cap", [0, 1, 5, 10**9])
+def test_balanced_colouring_bit_exact(cap):
+    """Balanced colouring on the GPU equals the oracle's bit for bit, and the
+    Coloring solve on it reaches the optimum."""
+    print("CASE balance", cap, flush=True)
+    P = synth.c3_zipf_lasso(scale=0.003)
+    X = G.Matrix.of(P)
+    colors, nc = G.color(X)
+    bal, nb = G.balance_colors(X, colors, nc, cap)
+    ocol, onc, _ = O.color(P.n, P.k, P.col_ptr, P.row_idx)
+    obal, onb = O.balance_colors(P.k, P.col_ptr, ocol, onc, cap)
+    assert nb == onb and np.array_equal(bal.cpu().numpy(), obal)
+    if cap == 0:
+        Xo = O.Matrix.of(P)
+        lam = 0.1 * O.lambda_max(Xo, P.y, P.loss)
+        ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000)
+        params = G.make_params(P.loss, lam, rule=G.COLORING, colors=bal, num_colors=nb, seed=3,
+                               tol=1e-7, max_epochs=20000)
+        res = G.solve(X, torch.as_tensor(P.y, device="cuda"), params)
+        assert res.status == G.OK
+        oc = O.check(Xo, P.y, P.loss, lam, res.w.cpu().numpy().astype(np.float64))
+        assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+def test_balanced_colouring_rejects_out_of_range():
+    P = synth.c3_zipf_lasso(scale=0.003)
+    X = G.Matrix.of(P)
+    colors, nc = G.color(X)
+    with pytest.raises(G.GencdError):
+        G.balance_colors(X, colors, max(1, nc - 1), 0)
