@@ -1,0 +1,125 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (default schedule, |J| = 4096 Shotgun windows, captured
+graphs), against the FP64 oracle on the same inputs.
+
+* zipf1.1-logistic (n 1e5, k 5e5, 5.0 M nonzeros): one iteration on the
+  first window of epoch 0 from a random state (z within 1e-5 of
+  |z_or| + rms(z_or), every accepted increment within 1e-5 of max |delta|),
+  and a whole solve to KKT 1e-6 against the oracle's solve of the same
+  configuration (objective to 1e-9, which the identical selection makes
+  possible; z at 2000 sampled rows to 1e-6).
+* zipf1.2-lasso (n 2e5, k 1e6, 6.0 M nonzeros): the colouring bit-exact, and
+  a Coloring solve against the oracle's.
+* binary-path (n 5e4, k 2e5, 5.0 M nonzeros): the first 8 lambdas of the
+  64-value path through the batched solver (B = 16), each to KKT 1e-8,
+  against warm-started oracle solves (objective within 1e-6).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1206_6409_amd import gencd as G
+from paper_1206_6409_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _case(*a):
+    print("CASE", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    P = synth.c2_zipf_logistic()
+    Xo = O.Matrix.of(P)
+    lam = 0.05 * O.lambda_max(Xo, P.y, P.loss)
+    return P, Xo, lam
+
+
+def test_full_c2_first_window_step(c2):
+    _case("full c2 step")
+    P, Xo, lam = c2
+    kl = int(np.sum(np.diff(P.col_ptr) > 0))
+    live = np.nonzero(np.diff(P.col_ptr) > 0)[0]
+    # the first Shotgun window of epoch 0 (seed 7), as the solve selects it
+    perm = O.perm(kl, 7, 0)
+    J = live[perm[:4096]].astype(np.int32)
+    rng = np.random.default_rng(5)
+    w = np.zeros(P.k, dtype=np.float32)
+    sup = rng.choice(live, size=2000, replace=False)
+    w[sup] = (rng.normal(size=sup.size) * 0.2).astype(np.float32)
+    oc = O.check(Xo, P.y, P.loss, 0.0, w.astype(np.float64))
+    z_hi = oc.z.astype(np.float32)
+    z_lo = (oc.z - z_hi.astype(np.float64)).astype(np.float32)
+    params = G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=4096)
+    w_d = torch.as_tensor(w, device=DEV)
+    zh_d, zl_d = torch.as_tensor(z_hi, device=DEV), torch.as_tensor(z_lo, device=DEV)
+    res = G.step(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV), params,
+                 torch.as_tensor(J, device=DEV), w_d, zh_d, zl_d)
+    torch.cuda.synchronize()
+    wo = w.astype(np.float64)
+    zo = z_hi.astype(np.float64) + z_lo.astype(np.float64)
+    r = O.step(Xo, P.y, P.loss, lam, J, wo, zo)
+    d = res.delta.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(d - r.delta)) <= 1e-5 * np.abs(r.delta).max() + 1e-6 * np.abs(w).max()
+    z = zh_d.cpu().numpy().astype(np.float64) + zl_d.cpu().numpy().astype(np.float64)
+    scale = np.abs(zo) + np.sqrt(np.mean(zo ** 2))
+    assert np.all(np.abs(z - zo) <= 1e-5 * scale)
+
+
+def test_full_c2_solve(c2):
+    _case("full c2 solve")
+    P, Xo, lam = c2
+    params = G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=4096, seed=7, tol=1e-6,
+                           max_epochs=100000, flags=G.USE_GRAPH)
+    res = G.solve(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV), params)
+    assert res.status == G.OK
+    r = O.solve(Xo, P.y, P.loss, lam, O.SHOTGUN, select_size=4096, seed=7, tol=1e-6,
+                max_epochs=100000)
+    assert r.converged and res.stats["epochs"] == r.epochs
+    assert abs(res.stats["objective"] - r.objective) <= 1e-9 * abs(r.objective)
+    rows = np.random.default_rng(1).choice(P.n, size=2000, replace=False)
+    z = res.z.cpu().numpy().astype(np.float64)[rows]
+    np.testing.assert_allclose(z, r.z[rows], rtol=1e-6, atol=1e-6 * np.abs(r.z).max())
+
+
+def test_full_c3_colouring_and_solve():
+    _case("full c3")
+    P = synth.c3_zipf_lasso()
+    X = G.Matrix.of(P)
+    colors, nc = G.color(X)
+    ocol, onc, _ = O.color(P.n, P.k, P.col_ptr, P.row_idx)
+    assert nc == onc and np.array_equal(colors.cpu().numpy(), ocol)
+    Xo = O.Matrix.of(P)
+    lam = 0.1 * O.lambda_max(Xo, P.y, P.loss)
+    params = G.make_params(P.loss, lam, rule=G.COLORING, colors=colors, num_colors=nc, seed=3,
+                           tol=1e-6, max_epochs=100000, flags=G.USE_GRAPH)
+    res = G.solve(X, torch.as_tensor(P.y, device=DEV), params)
+    assert res.status == G.OK
+    r = O.solve(Xo, P.y, P.loss, lam, O.COLORING, colors=ocol, seed=3, tol=1e-6,
+                max_epochs=100000)
+    assert r.converged
+    assert abs(res.stats["objective"] - r.objective) <= 1e-7 * abs(r.objective)
+
+
+def test_full_c4_path_head():
+    _case("full c4 path")
+    P = synth.c4_binary_path()
+    X = G.Matrix.of(P)
+    Xo = O.Matrix.of(P)
+    lm = O.lambda_max(Xo, P.y, P.loss)
+    lams = synth.lambda_grid(lm, count=64, ratio=1e-3)[:8]
+    params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=1024, seed=11, tol=1e-8,
+                           max_epochs=20000)
+    res = G.solve_path(X, torch.as_tensor(P.y, device=DEV), params, lams, B=16)
+    W = res.W.cpu().numpy().astype(np.float64)
+    w0 = None
+    for t, lam in enumerate(lams):
+        r = O.solve(Xo, P.y, P.loss, lam, O.SHOTGUN, select_size=1024, seed=11, tol=1e-10,
+                    max_epochs=200000, w0=w0)
+        w0 = r.w
+        assert res.stats[t]["converged"] == 1 and res.stats[t]["kkt_max"] <= 1e-8
+        oc = O.check(Xo, P.y, P.loss, lam, W[t])
+        assert abs(oc.objective - r.objective) <= 1e-6 * abs(r.objective)
