@@ -404,6 +404,13 @@ def bench_path(args):
         assert all(s["converged"] for s in res.stats)
         batched[B] = (dt, res)
         log(f"path B={B}: {dt:.2f}s")
+    # fused asynchronous windows (one launch per window; not the Jacobi trajectory)
+    fused = {}
+    for B in (16, 32, 64):
+        dt, res = _timed(lambda: G.solve_path(X, y, G.make_params(flags=G.FUSED, **base), lams, B=B))
+        assert all(s["converged"] for s in res.stats)
+        fused[B] = (dt, res)
+        log(f"fused path B={B}: {dt:.2f}s")
     # plain path: one solve per lambda, warm-started from the previous solution
     ws = G.workspace(X, G.make_params(**base))
 
@@ -442,6 +449,11 @@ def bench_path(args):
                    "n": P.n, "k": P.k, "nnz": P.nnz, "select_size": 1024},
         "batched": {str(B): {"seconds": batched[B][0], "solves_per_s": len(lams) / batched[B][0]}
                     for B in batched},
+        "batched_fused": {str(B): {"seconds": fused[B][0], "solves_per_s": len(lams) / fused[B][0],
+                                   "max_objective_rel_diff_vs_plain": max(
+                                       abs(a["objective"] - b) / abs(b)
+                                       for a, b in zip(fused[B][1].stats, objs_plain))}
+                          for B in fused},
         "best_B": Bbest, "plain_path": {"seconds": t_plain, "solves_per_s": len(lams) / t_plain,
                                         "epochs_total": ep_plain},
         "speedup_vs_plain": t_plain / t_b,

@@ -87,7 +87,8 @@ typedef enum {
                                       others of its window update it and split columns
                                       are applied one launch later, so the trajectory is
                                       not the Jacobi one (the optimum is the same).  Not
-                                      with EXACT_ACCUM or improve_steps (UNSUPPORTED) */
+                                      with EXACT_ACCUM or improve_steps (UNSUPPORTED).
+                                      gencd_solve_path: one launch per shared window */
 
 /* Device CSC matrix (see the conventions above). */
 typedef struct {

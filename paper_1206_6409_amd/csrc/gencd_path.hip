@@ -180,6 +180,79 @@ __global__ __launch_bounds__(kBlock) void k_path_update(PathArgs a) {
   }
 }
 
+// Fused asynchronous form (GENCD_FUSED): the same thread shape as
+// k_path_propose; after the slot's step the workgroup scatters delta_s x_ij
+// from the entries it still holds in registers, so Propose and Update of a
+// window are one launch.  Columns of a window read Z while others update it.
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
+  using SH = PathShape<B>;
+  constexpr int R = SH::R, PU = SH::PU, NW = SH::NW;
+  __shared__ float sred[NW][B];
+  __shared__ float sdel[B];
+  const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
+  const int64_t npos = a.win_hi - a.win_lo;
+  for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
+    const int4 pd = a.pdesc[a.win_lo + p];
+    const int32_t j = pd.y;
+    const int64_t cb = int64_t(uint32_t(pd.x)), ce = cb + pd.z;
+    const bool one = ce - cb <= int64_t(R) * PU;  // the whole column in one batch
+    int32_t ri[PU];
+    float vv[PU];
+    float acc = 0.0f;
+    for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
+#pragma unroll
+      for (int q = 0; q < PU; ++q) {
+        const int64_t e = base + int64_t(q) * R + r;
+        ri[q] = e < ce ? a.row_idx[e] : -1;
+        vv[q] = e < ce ? a.val[e] : 0.0f;
+      }
+      float zh[PU], zl[PU], yy[PU];
+#pragma unroll
+      for (int q = 0; q < PU; ++q) {
+        const int64_t i = ri[q] >= 0 ? ri[q] : 0;
+        zh[q] = a.zh[i * B + s];
+        zl[q] = a.zl[i * B + s];
+        yy[q] = a.y[i];
+      }
+#pragma unroll
+      for (int q = 0; q < PU; ++q)
+        if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yy[q], zh[q] + zl[q]);
+    }
+#pragma unroll
+    for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
+    if (int(threadIdx.x) % kWave < B) sred[threadIdx.x / kWave][s] = acc;
+    __syncthreads();
+    if (int(threadIdx.x) < B) {
+      float g = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) g += sred[w][s];
+      float d = 0.0f;
+      if (a.active[s] != 0) {
+        g /= a.n_f;
+        const float wj = a.W[int64_t(j) * B + s];
+        float ph;
+        propose_f32(g, a.c[j], wj, a.lam[s], d, ph);
+        if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
+      }
+      sdel[s] = d;
+    }
+    __syncthreads();
+    const float d = sdel[s];
+    if (d != 0.0f) {
+      if (one) {
+#pragma unroll
+        for (int q = 0; q < PU; ++q)
+          if (ri[q] >= 0) atomicAdd(&a.zl[int64_t(ri[q]) * B + s], d * vv[q]);
+      } else {
+        for (int64_t e = cb + r; e < ce; e += R)
+          atomicAdd(&a.zl[int64_t(a.row_idx[e]) * B + s], d * a.val[e]);
+      }
+    }
+    __syncthreads();  // sred / sdel are reused by the next column
+  }
+}
+
 // Staged form (used at B = 64): one group of B lanes per column, GPB = 256 / B columns per block;
 // the group stages B entries at a time in LDS and issues one B-wide atomic
 // row per entry.
@@ -535,6 +608,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   // measured on the 64-lambda binary workload: the staged update wins at
   // B = 64 (one full wave per column row), the block update below that
   constexpr bool upd_staged = B == 64;
+  const bool fused = (p->flags & GENCD_FUSED) != 0;
   std::vector<double> red;
   const int64_t T = (k_live + S - 1) / S;
   int64_t e = 0;
@@ -602,6 +676,10 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
       const int64_t npos = a.win_hi - a.win_lo;
       const unsigned grid = unsigned(std::min<int64_t>(npos > 0 ? npos : 1, 65536));
+      if (fused) {
+        hipLaunchKernelGGL(k_path_fused<B>, dim3(grid), dim3(kBlock), 0, s, a);
+        continue;
+      }
       hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, s, a);
       if constexpr (upd_staged)
         hipLaunchKernelGGL(k_path_update_staged<B>,
@@ -654,7 +732,9 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
   auto t0 = std::chrono::steady_clock::now();
   if (!X || !p || !lambdas || L <= 0 || !W || !stats) return GENCD_ERR_INVALID_ARG;
   if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
-  if (p->rule != GENCD_SHOTGUN || p->improve_steps != 0) return GENCD_ERR_UNSUPPORTED;
+  if (p->rule != GENCD_SHOTGUN || p->improve_steps != 0 ||
+      ((p->flags & GENCD_FUSED) && (p->flags & GENCD_EXACT_ACCUM)))
+    return GENCD_ERR_UNSUPPORTED;
   if (p->select_size <= 0 || !(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0)
     return GENCD_ERR_INVALID_ARG;
   if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;

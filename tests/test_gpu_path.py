@@ -19,15 +19,16 @@ def binary_problem():
     return P, Xo, lm
 
 
-@pytest.mark.parametrize("B,L", [(16, 20), (32, 12), (64, 6)])
-def test_path_matches_independent_solves(binary_problem, B, L):
-    print("CASE path", B, L, flush=True)
+@pytest.mark.parametrize("B,L,flags", [(16, 20, 0), (32, 12, 0), (64, 6, 0),
+                                       (16, 20, G.FUSED), (64, 6, G.FUSED)])
+def test_path_matches_independent_solves(binary_problem, B, L, flags):
+    print("CASE path", B, L, flags, flush=True)
     P, Xo, lm = binary_problem
     lams = synth.lambda_grid(lm, count=L, ratio=0.1)
     X = G.Matrix.of(P)
     y = torch.as_tensor(P.y, device=DEV)
     params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-8,
-                           max_epochs=20000)
+                           max_epochs=20000, flags=flags)
     res = G.solve_path(X, y, params, lams, B=B)
     assert res.status == G.OK
     W = res.W.cpu().numpy().astype(np.float64)
