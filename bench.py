@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--req-scale", type=float, default=0.25,
                     help="serve: scale of the n and k ranges of the request distribution")
     ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
+    ap.add_argument("--serve-jacobi", action="store_true",
+                    help="serve: Jacobi Propose/Update instead of the fused iteration")
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (the reference "
                          "dispatch for scaling HBM counters)")
@@ -481,6 +483,9 @@ def bench_serve(args):
 
     sc = args.req_scale
     pool_n = 24
+    # requests run the fused asynchronous Shotgun (one launch per window);
+    # --serve-jacobi keeps the two-launch Jacobi iteration instead
+    serve_flags = 0 if args.serve_jacobi else G.FUSED
     stream = synth.c5_request_stream(count=args.requests, rate=1.0,
                                      n_range=(int(1000 * sc), int(50000 * sc)),
                                      k_range=(int(1000 * sc), int(200000 * sc)))
@@ -504,7 +509,7 @@ def bench_serve(args):
         # |J| = floor(k_live / (2 rho)) clamped to [1, 1024], rho from 20 power
         # iterations on the normalised Gram matrix (section 4.1's P*)
         return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=0, seed=11, tol=1e-6,
-                             max_epochs=20000, flags=G.USE_GRAPH)
+                             max_epochs=20000, flags=G.USE_GRAPH | serve_flags)
 
     need = max(G.workspace_bytes(X, params(P, 1.0)) for P, X, y, lm in pool)
     slots = 8
@@ -557,6 +562,7 @@ def bench_serve(args):
                                 "latency_p50_s": float(np.percentile(lat1, 50)),
                                 "latency_p99_s": float(np.percentile(lat1, 99))},
         "all_converged": bool(all(r["stats"]["converged"] for r in res)),
+        "iteration": "Jacobi" if args.serve_jacobi else "fused asynchronous",
         "select_size_from_rho": {"min": int(min(r["stats"]["select_size"] for r in res)),
                                  "median": float(np.median([r["stats"]["select_size"] for r in res])),
                                  "max": int(max(r["stats"]["select_size"] for r in res))},
