@@ -1,0 +1,100 @@
+"""Degenerate cases of Top-Greedy, Block Shotgun, the fused iteration and
+improve-delta on the GPU, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1206_6409_amd import gencd as G
+from paper_1206_6409_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _solve(P, lam, tol=1e-8, max_epochs=200000, **kw):
+    params = G.make_params(P.loss, lam, seed=2, tol=tol, max_epochs=max_epochs, **kw)
+    return G.solve(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV), params)
+
+
+def _ref(P, lam):
+    Xo = O.Matrix.of(P)
+    r = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000)
+    assert r.converged
+    return Xo, r
+
+
+def _assert_optimum(P, lam, res, Xo, ref, kkt=1e-8):
+    assert res.status == G.OK and res.stats["kkt_max"] <= kkt
+    oc = O.check(Xo, P.y, P.loss, lam, res.w.cpu().numpy().astype(np.float64))
+    assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = synth.c1_ccd_logistic(scale=0.1)
+    lam = 0.1 * O.lambda_max(O.Matrix.of(P), P.y, P.loss)
+    Xo, ref = _ref(P, lam)
+    return P, lam, Xo, ref
+
+
+def test_block_shotgun_one_column_per_block(small):
+    # every block a single column: P_b* = 1, windows of one column
+    P, lam, Xo, ref = small
+    kl = int(np.sum(np.diff(P.col_ptr) > 0))
+    rho, ps = G.estimate_block_rho(G.Matrix.of(P), kl, 20, G.make_params(0, 0.0, seed=2))
+    np.testing.assert_allclose(rho, 1.0, rtol=1e-12)
+    assert set(ps) == {1}
+    res = _solve(P, lam, rule=G.BLOCK_SHOTGUN, block=kl)
+    _assert_optimum(P, lam, res, Xo, ref)
+    assert res.stats["iters"] == kl * res.stats["epochs"]
+
+
+def test_block_shotgun_more_blocks_than_columns_clamps(small):
+    P, lam, Xo, ref = small
+    kl = int(np.sum(np.diff(P.col_ptr) > 0))
+    res = _solve(P, lam, rule=G.BLOCK_SHOTGUN, block=min(4096, kl + 50))
+    _assert_optimum(P, lam, res, Xo, ref)
+
+
+def test_top_greedy_window_smaller_than_accept_count(small):
+    P, lam, Xo, ref = small
+    res = _solve(P, lam, rule=G.TOP_GREEDY, select_size=37, block=1000)
+    _assert_optimum(P, lam, res, Xo, ref)
+
+
+@pytest.mark.parametrize("rule,kw", [(G.SHOTGUN, dict(select_size=1)), (G.SHOTGUN, dict(select_size=10**6)),
+                                     (G.CYCLIC, dict()), (G.BLOCK_SHOTGUN, dict(block=3))])
+def test_fused_extreme_windows(small, rule, kw):
+    P, lam, Xo, ref = small
+    res = _solve(P, lam, rule=rule, flags=G.FUSED | G.USE_GRAPH, **kw)
+    _assert_optimum(P, lam, res, Xo, ref)
+
+
+def test_single_column_logistic_improve_is_the_minimiser():
+    # k = 1: one improved coordinate step solves the problem (1-D logistic)
+    rng = np.random.default_rng(4)
+    n = 300
+    x = rng.normal(size=n).astype(np.float32)
+    y = np.where(rng.random(n) < 1 / (1 + np.exp(-0.7 * x)), 1.0, -1.0).astype(np.float32)
+    col_ptr = np.array([0, n], dtype=np.int64)
+    P = synth.Problem(n, 1, col_ptr, np.arange(n, dtype=np.int32), x, y, O.LOGISTIC,
+                      np.zeros(1), "one column")
+    lam = 0.01
+    Xo, ref = _ref(P, lam)
+    res = _solve(P, lam, rule=G.CYCLIC, improve=500, max_epochs=3, tol=1e-7)
+    assert res.stats["epochs"] == 1  # converged at the first check (FP32 floor ~1e-8)
+    oc = O.check(Xo, P.y, P.loss, lam, res.w.cpu().numpy().astype(np.float64))
+    assert abs(oc.objective - ref.objective) <= 1e-7 * abs(ref.objective)
+
+
+def test_empty_matrix_new_rules():
+    n, k = 20, 6
+    P = synth.Problem(n, k, np.zeros(k + 1, np.int64), np.zeros(0, np.int32),
+                      np.zeros(0, np.float32), np.where(np.arange(n) % 2, 1.0, -1.0).astype(np.float32),
+                      O.LOGISTIC, np.zeros(k), "empty")
+    for kw in (dict(rule=G.TOP_GREEDY, select_size=4, block=2), dict(rule=G.BLOCK_SHOTGUN, block=2),
+               dict(rule=G.SHOTGUN, select_size=4, flags=G.FUSED), dict(rule=G.SHOTGUN, select_size=0),
+               dict(rule=G.SHOTGUN, select_size=4, improve=10)):
+        res = _solve(P, 0.1, **kw)
+        assert res.status == G.OK and np.all(res.w.cpu().numpy() == 0)
