@@ -250,15 +250,18 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
                      const double *lambdas, int32_t L, int32_t B, float *W, void *ws,
                      size_t ws_bytes, hipStream_t stream, gencd_stats *stats);
 
-/* Schedule autotuner.  Times every candidate schedule (lanes per piece in
- * {16, 32, 64} x nonzeros per piece in {256, 512, 1024} x captured-epoch
- * graph on/off) on `epochs` epochs of the real solve from w = 0 and returns
+/* Schedule autotuner.  Times every candidate schedule (lanes per short
+ * column in {4, 8, 16} x nonzeros per long piece in {128, 256, 512} x
+ * captured-epoch graph on/off) on `epochs` epochs of the real solve from
+ * w = 0 and returns
  * the fastest in *out; copy out->group, out->piece and out->flags into
  * gencd_params to use it.  Results are cached (JSON lines) in cache_path, or
  * in $GENCD_TUNE_CACHE when cache_path is NULL, under a key made of the
  * device, the problem shape and rule, and the histogram of column lengths;
  * a cached key is answered without timing.  w_scratch: device float32[k];
- * the workspace must be at least gencd_workspace_bytes for piece = 256. */
+ * the workspace must be at least gencd_workspace_bytes for piece = 128 and
+ * group = 4 (the candidate needing the most); candidates that do not fit
+ * are skipped. */
 typedef struct {
   int32_t group, piece;
   uint32_t flags;            /* GENCD_USE_GRAPH or 0 */
@@ -269,6 +272,26 @@ typedef struct {
 int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, int32_t epochs,
                    const char *cache_path, float *w_scratch, void *ws, size_t ws_bytes,
                    hipStream_t stream, gencd_schedule *out);
+
+/* Path autotuner: times gencd_solve_path on the caller's lambdas for every
+ * slot count B in {16, 32, 64}, each with and without GENCD_FUSED, and
+ * returns the fastest (B and the flag to add).  Cached like gencd_autotune,
+ * under a key that also holds L and the lambda range.
+ *   W_scratch  device float32[L][k] (overwritten)
+ *   ws         at least gencd_path_workspace_bytes(X, p, 64) bytes
+ * Errors: those of gencd_solve_path; NOT_CONVERGED of a candidate run is
+ * accepted (its time still counts). */
+typedef struct {
+  int32_t B;
+  uint32_t flags;            /* GENCD_FUSED or 0 */
+  double seconds;            /* whole path, measured on the tuning run */
+  int32_t from_cache;
+} gencd_path_schedule;
+
+int gencd_autotune_path(const gencd_csc *X, const float *y, const gencd_params *p,
+                        const double *lambdas, int32_t L, const char *cache_path,
+                        float *W_scratch, void *ws, size_t ws_bytes, hipStream_t stream,
+                        gencd_path_schedule *out);
 
 /* ------------------------------------------------------------------------
  * Spectral radius of the column-normalised Gram matrix (section 4.1: Shotgun

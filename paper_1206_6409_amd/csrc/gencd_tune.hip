@@ -162,4 +162,78 @@ int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, in
   return GENCD_OK;
 }
 
+int gencd_autotune_path(const gencd_csc *X, const float *y, const gencd_params *p,
+                        const double *lambdas, int32_t L, const char *cache_path,
+                        float *W_scratch, void *ws, size_t ws_bytes, hipStream_t stream,
+                        gencd_path_schedule *out) {
+  (void)hipGetLastError();
+  if (!X || !y || !p || !out || !lambdas || L <= 0 || !W_scratch || X->k <= 0 || !X->col_ptr)
+    return GENCD_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  if (!cache_path) cache_path = std::getenv("GENCD_TUNE_CACHE");
+  if (!ws || ws_bytes < 256) return GENCD_ERR_WORKSPACE;
+  unsigned long long *hd = static_cast<unsigned long long *>(ws);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, hd, 32);
+  const unsigned grid = unsigned(std::min<int64_t>((X->k + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_len_hist, dim3(grid), dim3(256), 0, stream, X->col_ptr, X->k, hd);
+  unsigned long long h[32];
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(h, hd, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return GENCD_ERR_HIP;
+  double lo = lambdas[0], hi = lambdas[0];
+  for (int32_t t = 1; t < L; ++t) {
+    lo = std::min(lo, lambdas[t]);
+    hi = std::max(hi, lambdas[t]);
+  }
+  std::ostringstream ks;
+  ks << "path|" << signature(X, p, h) << "|L" << L << "|lam" << lo << ":" << hi << "|tol"
+     << p->kkt_tol;
+  const std::string key = ks.str();
+  gencd_schedule cached{};
+  if (cache_lookup(cache_path, key, &cached)) {
+    out->B = cached.group;  // stored in the "group" field of the cache line
+    out->flags = cached.flags;
+    out->seconds = cached.seconds_per_epoch;
+    out->from_cache = 1;
+    return GENCD_OK;
+  }
+  std::vector<gencd_stats> st(static_cast<size_t>(L));
+  const int Bs[] = {16, 32, 64};
+  const unsigned fl[] = {0u, GENCD_FUSED};
+  double best = 1e300;
+  bool warmed = false;
+  for (int B : Bs)
+    for (unsigned f : fl) {
+      gencd_params q = *p;
+      q.flags = (p->flags & ~GENCD_FUSED) | f;
+      size_t need = 0;
+      if (gencd_path_workspace_bytes(X, &q, B, &need) != GENCD_OK || need > ws_bytes) continue;
+      if (!warmed) {  // first-use costs (code objects, caches) stay out of the timings
+        (void)gencd_solve_path(X, y, &q, lambdas, std::min<int32_t>(L, 2), B, W_scratch, ws,
+                               ws_bytes, stream, st.data());
+        warmed = true;
+      }
+      auto t0 = std::chrono::steady_clock::now();
+      const int rc = gencd_solve_path(X, y, &q, lambdas, L, B, W_scratch, ws, ws_bytes, stream,
+                                      st.data());
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (rc < 0) continue;
+      if (sec < best) {
+        best = sec;
+        out->B = B;
+        out->flags = f;
+        out->seconds = sec;
+      }
+    }
+  if (best == 1e300) return GENCD_ERR_WORKSPACE;
+  gencd_schedule rec{};
+  rec.group = out->B;
+  rec.piece = 0;
+  rec.flags = out->flags;
+  rec.seconds_per_epoch = out->seconds;
+  cache_store(cache_path, key, rec);
+  return GENCD_OK;
+}
+
 }  // extern "C"

@@ -75,6 +75,9 @@ _SIGS = {
                               C.c_void_p]),
     "gencd_select_perm": (C.c_int, [C.c_int64, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "gencd_rho_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_autotune_path": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                      C.c_char_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                      C.c_void_p]),
     "gencd_balance_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "gencd_balance_colors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -465,14 +468,40 @@ class Schedule(C.Structure):
 
 def autotune(X: Matrix, y, params: Params, epochs=2, cache_path=None):
     """Fastest (group, piece, graph) schedule for this problem; apply with apply_schedule."""
-    p256 = Params.from_buffer_copy(params)
-    p256.piece, p256.group = 256, 16
-    ws = workspace(X, p256)
+    # the candidate needing the most workspace: smallest pieces and groups
+    pmax = Params.from_buffer_copy(params)
+    pmax.piece, pmax.group = 128, 4
+    ws = workspace(X, pmax)
     w = torch.empty(X.k, dtype=torch.float32, device=X.col_ptr.device)
     out = Schedule()
     _check(lib().gencd_autotune(X.ref, _ptr(y), C.byref(params), int(epochs),
                                 cache_path.encode() if cache_path else None, _ptr(w), _ptr(ws),
                                 ws.numel(), _stream(), C.byref(out)), "gencd_autotune")
+    return out.as_dict()
+
+
+class PathSchedule(C.Structure):
+    _fields_ = [("B", C.c_int32), ("flags", C.c_uint32), ("seconds", C.c_double),
+                ("from_cache", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def autotune_path(X: Matrix, y, params: Params, lambdas, cache_path=None):
+    """Fastest (B, fused or not) for gencd_solve_path on these lambdas."""
+    import numpy as _np
+    lam = _np.ascontiguousarray(_np.asarray(lambdas, dtype=_np.float64))
+    nb = C.c_size_t()
+    _check(lib().gencd_path_workspace_bytes(X.ref, C.byref(params), 64, C.byref(nb)),
+           "gencd_path_workspace_bytes")
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=X.col_ptr.device)
+    W = torch.empty((lam.size, X.k), dtype=torch.float32, device=X.col_ptr.device)
+    out = PathSchedule()
+    _check(lib().gencd_autotune_path(X.ref, _ptr(y), C.byref(params),
+                                     lam.ctypes.data_as(C.c_void_p), int(lam.size),
+                                     cache_path.encode() if cache_path else None, _ptr(W), _ptr(ws),
+                                     ws.numel(), _stream(), C.byref(out)), "gencd_autotune_path")
     return out.as_dict()
 
 

@@ -53,3 +53,22 @@ def test_every_tunable_schedule_is_correct(group, piece):
         assert res.status == G.OK
         oc = O.check(Xo, P.y, P.loss, lam, res.w.cpu().numpy().astype(np.float64))
         assert oc.kkt <= 1e-8 * (1 + 1e-6)
+
+
+def test_path_autotune_picks_a_candidate_and_caches(tmp_path):
+    P = synth.c4_binary_path(scale=0.05)
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device="cuda")
+    lm = G.lambda_max(X, y, P.loss)
+    lams = synth.lambda_grid(lm, count=12, ratio=0.1)
+    params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-6,
+                           max_epochs=20000)
+    cache = str(tmp_path / "tune.jsonl")
+    s1 = G.autotune_path(X, y, params, lams, cache_path=cache)
+    assert s1["B"] in (16, 32, 64) and s1["flags"] in (0, G.FUSED) and s1["from_cache"] == 0
+    s2 = G.autotune_path(X, y, params, lams, cache_path=cache)
+    assert s2["from_cache"] == 1 and (s2["B"], s2["flags"]) == (s1["B"], s1["flags"])
+    # the chosen schedule solves the path
+    params.flags |= s1["flags"]
+    res = G.solve_path(X, y, params, lams, B=s1["B"])
+    assert res.status == G.OK
