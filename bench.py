@@ -82,8 +82,10 @@ def main():
                     choices=["shotgun", "coloring", "path", "serve", "all"],
                     help="shotgun (default, the headline line) or an extra workload")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    # a solve takes ~10 ms: enough warm-up and timed solves that clock and
+    # cache state after the box comes up do not decide the figure
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink n and k (tests only)")
     ap.add_argument("--select", type=int, default=4096)
     ap.add_argument("--tol", type=float, default=1e-6)
