@@ -243,6 +243,9 @@ int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_c
  * (section 4.1 mentions starting from a large lambda and decreasing it).
  *   lambdas: host double[L];  W: device float32[L][k] (row t = solution for
  *   lambdas[t]);  stats: host gencd_stats[L].
+ * Flags: GENCD_FUSED (one launch per window, see above), GENCD_USE_GRAPH
+ * (every epoch replays one captured HIP graph; which lambdas the slots hold
+ * lives in device arrays, so the graph is captured once per call).
  * Workspace bytes from gencd_path_workspace_bytes. */
 int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_t B,
                                size_t *out_bytes);

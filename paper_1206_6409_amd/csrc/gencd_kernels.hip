@@ -721,7 +721,10 @@ __device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_
 // Accept for Thread-Greedy / Greedy (section 2.3): in each block of B
 // positions the first position with minimal phi.  One workgroup per block;
 // it first finalises the block's split columns from their partial sums.
-__global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
+// With `chunk` set, this is the first stage of a global accept (Greedy: one
+// block holding the whole window): B is the chunk size, and each workgroup
+// only records its chunk's winner in bw_pos / bw_phi for k_accept_final.
+__global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B, int32_t chunk) {
   __shared__ float sphi[kBlock];
   __shared__ int32_t spos[kBlock];
   __shared__ int32_t smulti[kBlock];
@@ -756,7 +759,12 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0 && spos[0] != INT32_MAX) {
+    if (chunk) {
+      if (threadIdx.x == 0) {
+        a.bw_pos[b] = spos[0];
+        a.bw_phi[b] = __float_as_int(sphi[0]);
+      }
+    } else if (threadIdx.x == 0 && spos[0] != INT32_MAX) {
       const int32_t p = spos[0];
       a.acc[p - P0] = 1;
       const int32_t j = a.col_of_pos[p];
@@ -769,6 +777,52 @@ __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B) {
       atomicAdd(a.counters + 1, 1ull);
     }
     __syncthreads();
+  }
+}
+
+// Second stage of the global accept: the first minimal phi over the chunk
+// winners (chunks are in position order, so ties still go to the lowest
+// position), accepted as k_accept accepts a block's winner.
+__global__ __launch_bounds__(kBlock) void k_accept_final(IterArgs a, int64_t nchunks) {
+  __shared__ float sphi[kBlock];
+  __shared__ int32_t spos[kBlock];
+  int32_t P0, P1;
+  window_of(a, P0, P1);
+  float best = INFINITY;
+  int32_t bpos = INT32_MAX;
+  for (int64_t b = threadIdx.x; b < nchunks; b += kBlock) {
+    const int32_t p = a.bw_pos[b];
+    const float v = __int_as_float(a.bw_phi[b]);
+    if (p != INT32_MAX && v < best) {
+      best = v;
+      bpos = p;
+    }
+  }
+  sphi[threadIdx.x] = best;
+  spos[threadIdx.x] = bpos;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      float v2 = sphi[threadIdx.x + off];
+      int32_t p2 = spos[threadIdx.x + off];
+      if (v2 < sphi[threadIdx.x] || (v2 == sphi[threadIdx.x] && p2 < spos[threadIdx.x])) {
+        sphi[threadIdx.x] = v2;
+        spos[threadIdx.x] = p2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && spos[0] != INT32_MAX) {
+    const int32_t p = spos[0];
+    a.acc[p - P0] = 1;
+    const int32_t j = a.col_of_pos[p];
+    const float d = a.delta[p - P0];
+    if (a.improve > 0)
+      a.wsnap[p - P0] = a.w[j];
+    else if (d != 0.0f)
+      a.w[j] += d;
+    atomicAdd(a.counters + 0, (unsigned long long)(a.col_ptr[j + 1] - a.col_ptr[j]));
+    atomicAdd(a.counters + 1, 1ull);
   }
 }
 
@@ -1130,6 +1184,9 @@ __global__ __launch_bounds__(kBlock) void k_improve(IterArgs a) {
   }
 }
 
+// positions per first-stage workgroup of a global accept
+constexpr int64_t kAcceptChunk = 2048;
+
 template <int GS, int UL>
 static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsigned blocks,
                               int64_t nblocks_accept, unsigned improve_blocks, hipStream_t s,
@@ -1162,10 +1219,16 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
   } else {
     if (a.accept_top > 0) {
       hipLaunchKernelGGL(k_accept_top, dim3(1), dim3(kTopThreads), 0, s, a);
+    } else if (nblocks_accept == 1 && block > kAcceptChunk) {
+      // one block over the whole window (Greedy): chunk winners, then the best
+      const int64_t nc = (block + kAcceptChunk - 1) / kAcceptChunk;
+      hipLaunchKernelGGL(k_accept, dim3(unsigned(nc < 4096 ? nc : 4096)), blk, 0, s, a,
+                         int64_t(kAcceptChunk), 1);
+      hipLaunchKernelGGL(k_accept_final, dim3(1), blk, 0, s, a, nc);
     } else {
       unsigned nb =
           unsigned(nblocks_accept < 4096 ? (nblocks_accept > 0 ? nblocks_accept : 1) : 4096);
-      hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block);
+      hipLaunchKernelGGL(k_accept, dim3(nb), blk, 0, s, a, block, 0);
     }
     if (a.improve > 0)
       hipLaunchKernelGGL(k_improve<2>, dim3(improve_blocks), blk, 0, s, a);

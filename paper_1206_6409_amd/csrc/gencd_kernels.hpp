@@ -29,6 +29,7 @@ struct IterArgs {
   int32_t t, win_lo, win_hi;
   float *delta, *phi, *gacc, *gout, *wsnap;
   int32_t *acc;
+  int32_t *bw_pos, *bw_phi;  // per-chunk winners of a two-stage global accept (scratch)
   int32_t exact_accum;     // 1: TwoSum per update (returning atomics); 0: low-word accumulation
   unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals (greedy rules)
 };

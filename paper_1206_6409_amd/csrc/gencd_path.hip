@@ -30,7 +30,13 @@ struct PathWs {
   double *z64, *r64;     // [n][B]
   double *g64;           // [k][B]
   double *red;           // [B][8]: loss, l1, kkt bits, nnz, gmax bits, dual
+  double *rep;           // [kRedRep][B][8]: the same, one partial per replica
 };
+
+// The check's per-slot reductions go to kRedRep replicas (workgroup b adds
+// into replica b % kRedRep) and k_path_fold combines them: with one address
+// per slot, every workgroup's FP64 atomic on it would be serialised.
+constexpr int kRedRep = 64;
 
 static size_t path_layout(int64_t n, int64_t k, int64_t S, int B, void *base, PathWs *o) {
   const size_t al = 256;
@@ -54,6 +60,7 @@ static size_t path_layout(int64_t n, int64_t k, int64_t S, int B, void *base, Pa
   w.r64 = static_cast<double *>(take(sizeof(double) * n * B));
   w.g64 = static_cast<double *>(take(sizeof(double) * k * B));
   w.red = static_cast<double *>(take(sizeof(double) * 8 * B));
+  w.rep = static_cast<double *>(take(sizeof(double) * 8 * B * kRedRep));
   if (o) *o = w;
   return off + al;
 }
@@ -308,10 +315,16 @@ __global__ __launch_bounds__(kBlock) void k_path_zero(double *z64, int64_t n, do
   const int64_t nt = int64_t(gridDim.x) * kBlock;
   for (int64_t i = tid; i < n * B; i += nt) z64[i] = 0.0;
   for (int64_t j = tid; j < k * B; j += nt) g64[j] = 0.0;
-  if (tid < 8 * B) red[tid] = 0.0;
+  if (tid < 8 * B * kRedRep) red[tid] = 0.0;
 }
 
-// one group of B lanes per column: z64[i][s] += W[j][s] * x_ij
+// rows or columns per lane taken together by the streaming check kernels
+constexpr int kChkU = 4;
+
+// one group of B lanes per column: z64[i][s] += W[j][s] * x_ij.  Entries
+// are read kSpmvU at a time, so a column costs one load round per kSpmvU
+// entries instead of one per entry.
+constexpr int kSpmvU = 8;
 template <int B>
 __global__ __launch_bounds__(kBlock) void k_path_spmv(const int64_t *col_ptr, const int32_t *row_idx,
                                                       const float *val, int64_t k, const float *W,
@@ -319,10 +332,21 @@ __global__ __launch_bounds__(kBlock) void k_path_spmv(const int64_t *col_ptr, co
   constexpr int GPB = kBlock / B;
   const int grp = threadIdx.x / B, s = threadIdx.x % B;
   for (int64_t j = int64_t(blockIdx.x) * GPB + grp; j < k; j += int64_t(gridDim.x) * GPB) {
+    const int64_t e0 = col_ptr[j], e1 = col_ptr[j + 1];
     const double wj = double(W[j * B + s]);
     if (wj == 0.0) continue;
-    for (int64_t e = col_ptr[j]; e < col_ptr[j + 1]; ++e)
-      atomicAdd(&z64[int64_t(row_idx[e]) * B + s], wj * double(val[e]));
+    for (int64_t e = e0; e < e1; e += kSpmvU) {
+      int32_t ri[kSpmvU];
+      float v[kSpmvU];
+#pragma unroll
+      for (int q = 0; q < kSpmvU; ++q) {
+        ri[q] = e + q < e1 ? row_idx[e + q] : -1;
+        v[q] = e + q < e1 ? val[e + q] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < kSpmvU; ++q)
+        if (ri[q] >= 0) atomicAdd(&z64[int64_t(ri[q]) * B + s], wj * double(v[q]));
+    }
   }
 }
 
@@ -333,22 +357,34 @@ __global__ __launch_bounds__(kBlock) void k_path_rows(int64_t n, int loss, const
   constexpr int GPB = kBlock / B;
   __shared__ double sacc[kBlock];
   const int grp = threadIdx.x / B, s = threadIdx.x % B;
+  const int64_t stride = int64_t(gridDim.x) * GPB;
   double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * GPB + grp; i < n; i += int64_t(gridDim.x) * GPB) {
-    const double t = z64[i * B + s];
-    const double yi = double(y[i]);
-    acc += loss_f64(loss, yi, t);
-    r64[i * B + s] = dloss_f64(loss, yi, t);
-    const float h = float(t);
-    zh[i * B + s] = h;
-    zl[i * B + s] = float(t - double(h));
+  for (int64_t i0 = int64_t(blockIdx.x) * GPB + grp; i0 < n; i0 += kChkU * stride) {
+    double zt[kChkU], yv[kChkU];
+#pragma unroll
+    for (int u = 0; u < kChkU; ++u) {  // all loads of the batch before any store
+      const int64_t i = i0 + u * stride;
+      zt[u] = i < n ? z64[i * B + s] : 0.0;
+      yv[u] = i < n ? double(y[i]) : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kChkU; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i >= n) break;
+      const double t = zt[u];
+      acc += loss_f64(loss, yv[u], t);
+      r64[i * B + s] = dloss_f64(loss, yv[u], t);
+      const float h = float(t);
+      zh[i * B + s] = h;
+      zl[i * B + s] = float(t - double(h));
+    }
   }
   sacc[threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.x < B) {
     double t = 0.0;
     for (int g = 0; g < GPB; ++g) t += sacc[g * B + threadIdx.x];
-    atomicAdd(&red[threadIdx.x * 8 + 0], t);
+    atomicAdd(&red[(blockIdx.x % kRedRep) * 8 * B + threadIdx.x * 8 + 0], t);
   }
 }
 
@@ -385,22 +421,36 @@ __global__ __launch_bounds__(kBlock) void k_path_kkt(int64_t k, double *g64, con
   __shared__ double smax[kBlock], sl1[kBlock], sgm[kBlock], snz[kBlock];
   const int grp = threadIdx.x / B, s = threadIdx.x % B;
   const double l = lam[s];
+  const int64_t stride = int64_t(gridDim.x) * GPB;
   double vmax = 0.0, l1 = 0.0, gmax = 0.0, nz = 0.0;
-  for (int64_t j = int64_t(blockIdx.x) * GPB + grp; j < k; j += int64_t(gridDim.x) * GPB) {
-    const double g = g64[j * B + s] * inv_n;
-    g64[j * B + s] = g;
-    if (!(fabs(g) <= gmax)) gmax = fabs(g);
-    const double wj = double(W[j * B + s]);
-    double v;
-    if (wj != 0.0) {
-      v = fabs(g + (wj > 0.0 ? l : -l));
-      l1 += fabs(wj);
-      nz += 1.0;
-    } else {
-      v = fabs(g) - l;
-      if (v < 0.0) v = 0.0;
+  for (int64_t j0 = int64_t(blockIdx.x) * GPB + grp; j0 < k; j0 += kChkU * stride) {
+    double gv[kChkU];
+    float wv[kChkU];
+#pragma unroll
+    for (int u = 0; u < kChkU; ++u) {
+      const int64_t j = j0 + u * stride;
+      gv[u] = j < k ? g64[j * B + s] : 0.0;
+      wv[u] = j < k ? W[j * B + s] : 0.0f;
     }
-    if (!(v <= vmax)) vmax = v;
+#pragma unroll
+    for (int u = 0; u < kChkU; ++u) {
+      const int64_t j = j0 + u * stride;
+      if (j >= k) break;
+      const double g = gv[u] * inv_n;
+      g64[j * B + s] = g;
+      if (!(fabs(g) <= gmax)) gmax = fabs(g);
+      const double wj = double(wv[u]);
+      double v;
+      if (wj != 0.0) {
+        v = fabs(g + (wj > 0.0 ? l : -l));
+        l1 += fabs(wj);
+        nz += 1.0;
+      } else {
+        v = fabs(g) - l;
+        if (v < 0.0) v = 0.0;
+      }
+      if (!(v <= vmax)) vmax = v;
+    }
   }
   smax[threadIdx.x] = vmax;
   sl1[threadIdx.x] = l1;
@@ -416,36 +466,50 @@ __global__ __launch_bounds__(kBlock) void k_path_kkt(int64_t k, double *g64, con
       a1 += sl1[t];
       z += snz[t];
     }
-    unsigned long long *rb = reinterpret_cast<unsigned long long *>(red + threadIdx.x * 8);
+    double *rr = red + (blockIdx.x % kRedRep) * 8 * B + threadIdx.x * 8;
+    unsigned long long *rb = reinterpret_cast<unsigned long long *>(rr);
     atomicMax(rb + 2, (m != m) ? 0x7FF8000000000000ull : (unsigned long long)__double_as_longlong(m));
     atomicMax(rb + 4, (gm != gm) ? 0x7FF8000000000000ull : (unsigned long long)__double_as_longlong(gm));
-    atomicAdd(&red[threadIdx.x * 8 + 1], a1);
-    atomicAdd(&red[threadIdx.x * 8 + 3], z);
+    atomicAdd(rr + 1, a1);
+    atomicAdd(rr + 3, z);
   }
 }
 
 template <int B>
 __global__ __launch_bounds__(kBlock) void k_path_dual(int64_t n, int loss, const float *y,
                                                       const double *r64, const double *lam,
-                                                      double *red) {
+                                                      const double *fold, double *red) {
   constexpr int GPB = kBlock / B;
   __shared__ double sacc[kBlock];
   const int grp = threadIdx.x / B, s = threadIdx.x % B;
   const double l = lam[s];
-  const double gm = __longlong_as_double(reinterpret_cast<long long *>(red + s * 8)[4]);
+  // max |g| of the slot, folded from k_path_kkt's replicas into fold[s][4]
+  const double gm = fold[s * 8 + 4];
   const double sc = (gm > l) ? l / gm : 1.0;
+  const int64_t stride = int64_t(gridDim.x) * GPB;
   double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * GPB + grp; i < n; i += int64_t(gridDim.x) * GPB) {
-    const double v = sc * r64[i * B + s];
-    const double yi = double(y[i]);
-    if (loss == GENCD_SQUARED) {
-      acc -= v * yi + 0.5 * v * v;
-    } else {
-      const double pp = -v * yi;
-      double h = 0.0;
-      if (pp > 0.0) h -= pp * log(pp);
-      if (pp < 1.0) h -= (1.0 - pp) * log1p(-pp);
-      acc += h;
+  for (int64_t i0 = int64_t(blockIdx.x) * GPB + grp; i0 < n; i0 += kChkU * stride) {
+    double rv[kChkU], yv[kChkU];
+#pragma unroll
+    for (int u = 0; u < kChkU; ++u) {
+      const int64_t i = i0 + u * stride;
+      rv[u] = i < n ? r64[i * B + s] : 0.0;
+      yv[u] = i < n ? double(y[i]) : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kChkU; ++u) {
+      if (i0 + u * stride >= n) break;
+      const double v = sc * rv[u];
+      const double yi = yv[u];
+      if (loss == GENCD_SQUARED) {
+        acc -= v * yi + 0.5 * v * v;
+      } else {
+        const double pp = -v * yi;
+        double h = 0.0;
+        if (pp > 0.0) h -= pp * log(pp);
+        if (pp < 1.0) h -= (1.0 - pp) * log1p(-pp);
+        acc += h;
+      }
     }
   }
   sacc[threadIdx.x] = acc;
@@ -453,7 +517,29 @@ __global__ __launch_bounds__(kBlock) void k_path_dual(int64_t n, int loss, const
   if (threadIdx.x < B) {
     double t = 0.0;
     for (int g = 0; g < GPB; ++g) t += sacc[g * B + threadIdx.x];
-    atomicAdd(&red[threadIdx.x * 8 + 5], t);
+    atomicAdd(&red[(blockIdx.x % kRedRep) * 8 * B + threadIdx.x * 8 + 5], t);
+  }
+}
+
+// Combine the kRedRep replicas into red[B][8]: maxima (entries 2 and 4, as
+// bit patterns of non-negative doubles, NaN above all) and sums.
+template <int B>
+__global__ __launch_bounds__(8 * B) void k_path_fold(const double *rep, double *red) {
+  const int tid = int(threadIdx.x);
+  const int q = tid % 8;
+  if (q == 2 || q == 4) {
+    unsigned long long m = 0;
+#pragma unroll 16
+    for (int r = 0; r < kRedRep; ++r) {
+      const unsigned long long b = reinterpret_cast<const unsigned long long *>(rep)[r * 8 * B + tid];
+      m = b > m ? b : m;
+    }
+    red[tid] = __longlong_as_double((long long)m);
+  } else {
+    double t = 0.0;
+#pragma unroll 16
+    for (int r = 0; r < kRedRep; ++r) t += rep[r * 8 * B + tid];
+    red[tid] = t;
   }
 }
 
@@ -488,20 +574,23 @@ static int path_check(const gencd_csc *X, const float *y, int loss, const PathWs
                       std::vector<double> *red) {
   constexpr int GPB = kBlock / B;
   const int64_t n = X->n, k = X->k;
-  hipLaunchKernelGGL(k_path_zero<B>, dim3(g1((n > k ? n : k) * B)), dim3(kBlock), 0, s, w.z64, n,
-                     w.g64, k, w.red);
+  hipLaunchKernelGGL(k_path_zero<B>, dim3(g1(std::max<int64_t>(n > k ? n : k, 8 * kRedRep) * B)),
+                     dim3(kBlock), 0, s, w.z64, n, w.g64, k, w.rep);
   const unsigned gk = unsigned(std::min<int64_t>((k + GPB - 1) / GPB, 16384));
   const unsigned gn = unsigned(std::min<int64_t>((n + GPB - 1) / GPB, 2048));
   hipLaunchKernelGGL(k_path_spmv<B>, dim3(gk), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
                      k, w.W, w.z64);
   hipLaunchKernelGGL(k_path_rows<B>, dim3(gn), dim3(kBlock), 0, s, n, loss, y, w.z64, w.r64, w.zh,
-                     w.zl, w.red);
+                     w.zl, w.rep);
   hipLaunchKernelGGL(k_path_cols<B>, dim3(gk), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
                      k, w.r64, w.g64);
-  hipLaunchKernelGGL(k_path_kkt<B>, dim3(std::min<unsigned>(gk, 512)), dim3(kBlock), 0, s, k,
-                     w.g64, w.W, w.lam64, 1.0 / double(n), w.red);
-  hipLaunchKernelGGL(k_path_dual<B>, dim3(std::min<unsigned>(gn, 512)), dim3(kBlock), 0, s, n,
-                     loss, y, w.r64, w.lam64, w.red);
+  hipLaunchKernelGGL(k_path_kkt<B>, dim3(std::min<unsigned>(gk, 4096)), dim3(kBlock), 0, s, k,
+                     w.g64, w.W, w.lam64, 1.0 / double(n), w.rep);
+  // fold once for the maximum |g| that the dual needs, and again after it
+  hipLaunchKernelGGL(k_path_fold<B>, dim3(1), dim3(8 * B), 0, s, w.rep, w.red);
+  hipLaunchKernelGGL(k_path_dual<B>, dim3(gn), dim3(kBlock), 0, s, n, loss, y, w.r64, w.lam64,
+                     w.red, w.rep);
+  hipLaunchKernelGGL(k_path_fold<B>, dim3(1), dim3(8 * B), 0, s, w.rep, w.red);
   GENCD_HIP(hipGetLastError());
   red->resize(size_t(8) * B);
   GENCD_HIP(hipMemcpyAsync(red->data(), w.red, sizeof(double) * 8 * B, hipMemcpyDeviceToHost, s));
@@ -524,6 +613,19 @@ size_t path_workspace_bytes(int64_t n, int64_t k, int64_t nnz, int64_t S, int B,
   return workspace_layout(n, k, nnz, piece, short_max, false, 0, nullptr, nullptr) + 256 +
          path_layout(n, k, S, B, nullptr, nullptr) + 256;
 }
+
+// A captured epoch and the private stream it was captured on, released on
+// every return path.
+struct PathGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cs = nullptr;
+  ~PathGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
 
 template <int B>
 int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const double *lambdas,
@@ -611,6 +713,39 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   const bool fused = (p->flags & GENCD_FUSED) != 0;
   std::vector<double> red;
   const int64_t T = (k_live + S - 1) / S;
+  // One epoch: selection order (section 2.1), the shared windows' launches,
+  // the renormalisation of (z_hi, z_lo) and the epoch counter.  No argument
+  // depends on the epoch or on which lambdas the slots hold (those live in
+  // device arrays), so GENCD_USE_GRAPH captures it once and replays it.
+  auto enqueue_epoch = [&](hipStream_t es) -> int {
+    int rc = launch_epoch_order(ws, k_live, GENCD_SHOTGUN, p->seed, epoch_dev, 0, S, T, es);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_path_desc, dim3(g1(k_live)), dim3(kBlock), 0, es, k_live, ws.col_of_pos,
+                       X->col_ptr, ws.desc_s);
+    for (int64_t t = 0; t < T; ++t) {
+      a.win_lo = int32_t(t * S);
+      a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
+      const int64_t npos = a.win_hi - a.win_lo;
+      const unsigned grid = unsigned(std::min<int64_t>(npos > 0 ? npos : 1, 65536));
+      if (fused) {
+        hipLaunchKernelGGL(k_path_fused<B>, dim3(grid), dim3(kBlock), 0, es, a);
+        continue;
+      }
+      hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, es, a);
+      if constexpr (upd_staged)
+        hipLaunchKernelGGL(k_path_update_staged<B>,
+                           dim3(unsigned(std::min<int64_t>((npos + kBlock / B - 1) / (kBlock / B), 16384))),
+                           dim3(kBlock), 0, es, a);
+      else
+        hipLaunchKernelGGL(k_path_update<B>, dim3(grid), dim3(kBlock), 0, es, a);
+    }
+    hipLaunchKernelGGL(k_path_renorm<B>, dim3(g1(n * B)), dim3(kBlock), 0, es, n * B, w.zh, w.zl);
+    rc = launch_inc_epoch(epoch_dev, es);
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+  };
+  const bool use_graph = (p->flags & GENCD_USE_GRAPH) != 0;
+  PathGraph graph;
   int64_t e = 0;
   bool resync = true;
   int remaining = L;
@@ -667,31 +802,25 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       }
     }
     // one epoch over the live columns with shared windows
-    st = launch_epoch_order(ws, k_live, GENCD_SHOTGUN, p->seed, epoch_dev, 0, S, T, s);
-    if (st) return st;
-    hipLaunchKernelGGL(k_path_desc, dim3(g1(k_live)), dim3(kBlock), 0, s, k_live, ws.col_of_pos,
-                       X->col_ptr, ws.desc_s);
-    for (int64_t t = 0; t < T; ++t) {
-      a.win_lo = int32_t(t * S);
-      a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
-      const int64_t npos = a.win_hi - a.win_lo;
-      const unsigned grid = unsigned(std::min<int64_t>(npos > 0 ? npos : 1, 65536));
-      if (fused) {
-        hipLaunchKernelGGL(k_path_fused<B>, dim3(grid), dim3(kBlock), 0, s, a);
-        continue;
+    if (use_graph) {
+      if (!graph.exec) {
+        // capture on a private stream (the caller's may be the legacy
+        // default stream, which cannot be captured); replay on the caller's
+        if (!graph.cs) GENCD_HIP(hipStreamCreateWithFlags(&graph.cs, hipStreamNonBlocking));
+        GENCD_HIP(hipStreamBeginCapture(graph.cs, hipStreamCaptureModeRelaxed));
+        st = enqueue_epoch(graph.cs);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(graph.cs, &g);
+        graph.g = g;
+        if (st) return st;
+        if (ce != hipSuccess || !g) return GENCD_ERR_HIP;
+        GENCD_HIP(hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0));
       }
-      hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, s, a);
-      if constexpr (upd_staged)
-        hipLaunchKernelGGL(k_path_update_staged<B>,
-                           dim3(unsigned(std::min<int64_t>((npos + kBlock / B - 1) / (kBlock / B), 16384))),
-                           dim3(kBlock), 0, s, a);
-      else
-        hipLaunchKernelGGL(k_path_update<B>, dim3(grid), dim3(kBlock), 0, s, a);
+      GENCD_HIP(hipGraphLaunch(graph.exec, s));
+    } else {
+      st = enqueue_epoch(s);
+      if (st) return st;
     }
-    hipLaunchKernelGGL(k_path_renorm<B>, dim3(g1(n * B)), dim3(kBlock), 0, s, n * B, w.zh, w.zl);
-    st = launch_inc_epoch(epoch_dev, s);
-    if (st) return st;
-    GENCD_HIP(hipGetLastError());
     for (int slot = 0; slot < B; ++slot) {
       const int32_t t = slot_lambda[slot];
       if (t >= 0 && !done[t]) {

@@ -350,6 +350,8 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   a.wsnap = ws.wsnap;
   a.wbl = ws.wbl;
   a.acc = ws.acc;
+  a.bw_pos = ws.tmp_cnt;  // free once the epoch order is built
+  a.bw_phi = ws.tmp_cnt2;
   a.counters = reinterpret_cast<unsigned long long *>(ws.red) + 8;
   a.exact_accum = (p->flags & GENCD_EXACT_ACCUM) ? 1 : 0;
   return a;
@@ -650,10 +652,11 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       const int64_t want = 2 * std::max<int64_t>(T, 1) * check_every;
       if (want <= 2 * 65536) {
         evs.resize(size_t(want));
-        // no system-scope fence at the markers: the pair then brackets the
-        // kernel without an extra cache flush
+        // timing-only events: no system-scope fence when they complete, so
+        // the stamped dispatch ends without a cache writeback of its own
+        // (they are read only after the stream has been synchronised)
         for (auto &ev : evs)
-          if (hipEventCreate(&ev) != hipSuccess) ev = nullptr;
+          if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) ev = nullptr;
       }
     }
     if (use_graph) {

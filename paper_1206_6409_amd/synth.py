@@ -100,7 +100,7 @@ def zipf_rows(rng: np.random.Generator, n: int, k: int, a: float, mean_len: int)
     lens = np.minimum(lens, k)
     cdf = _zipf_cdf(k, a)
     rank_to_col = rng.permutation(k).astype(np.int64)
-    have = np.zeros(0, dtype=np.int64)  # key = row * k + rank
+    have = np.zeros(0, dtype=np.int64)  # sorted distinct keys row * k + rank
     deficit = lens.copy()
     while True:
         need = int(deficit.sum())
@@ -110,9 +110,14 @@ def zipf_rows(rng: np.random.Generator, n: int, k: int, a: float, mean_len: int)
         u = rng.random(need)
         rank = np.searchsorted(cdf, u, side="right").astype(np.int64)
         rank = np.minimum(rank, k - 1)
-        have = np.unique(np.concatenate([have, r * k + rank]))
-        cnt = np.bincount(have // k, minlength=n).astype(np.int64)
-        deficit = lens - cnt
+        new = np.unique(r * k + rank)
+        if have.size:
+            at = np.minimum(np.searchsorted(have, new), have.size - 1)
+            new = new[have[at] != new]
+        # two sorted runs: the stable sort merges them in linear time
+        have = np.sort(np.concatenate([have, new]), kind="stable")
+        cnt = np.bincount(new // k, minlength=n).astype(np.int64)
+        deficit = deficit - cnt
     rows = have // k
     cols = rank_to_col[have % k]
     return rows, cols

@@ -121,6 +121,10 @@ STEP_CASES = [
     ("c2", G.SHOTGUN, 0, 8, 256, G.EXACT_ACCUM), ("c2", G.THREAD_GREEDY, 64, 8, 256, G.EXACT_ACCUM),
     ("c2", G.TOP_GREEDY, 64, 8, 256), ("c2", G.TOP_GREEDY, 1, 16, 64), ("c4", G.TOP_GREEDY, 100, 8, 64),
     ("c1", G.TOP_GREEDY, 100000, 4, 128),
+    # J = every live column: the whole-window accept runs in two stages
+    # (chunk winners, then the best of them)
+    ("c2", G.GREEDY, 0, 8, 256, 0, 100000), ("c4", G.GREEDY, 0, 8, 256, 0, 100000),
+    ("c2", G.THREAD_GREEDY, 100000, 8, 256, 0, 100000),
 ]
 
 
@@ -128,7 +132,8 @@ STEP_CASES = [
 def test_step_parity(problems, case):
     name, rule, block, group, piece = case[:5]
     flags = case[5] if len(case) > 5 else 0
-    _print_case("step", name, rule, block, group, piece, flags)
+    m_cap = case[6] if len(case) > 6 else 700
+    _print_case("step", name, rule, block, group, piece, flags, m_cap)
     P = problems[name]
     X = G.Matrix.of(P)
     Xo = O.Matrix.of(P)
@@ -140,7 +145,7 @@ def test_step_parity(problems, case):
     lam = 0.1 * O.lambda_max(Xo, P.y, P.loss)
     live = np.nonzero(np.diff(P.col_ptr) > 0)[0]
     # J: random live columns, plus the heaviest column so split columns are covered
-    m = min(live.size, 700)
+    m = min(live.size, m_cap)
     J = rng.choice(live, size=m, replace=False).astype(np.int32)
     heavy = int(np.argmax(np.diff(P.col_ptr)))
     if heavy not in J:

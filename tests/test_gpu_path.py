@@ -20,7 +20,9 @@ def binary_problem():
 
 
 @pytest.mark.parametrize("B,L,flags", [(16, 20, 0), (32, 12, 0), (64, 6, 0),
-                                       (16, 20, G.FUSED), (64, 6, G.FUSED)])
+                                       (16, 20, G.FUSED), (64, 6, G.FUSED),
+                                       (16, 20, G.USE_GRAPH), (64, 6, G.USE_GRAPH),
+                                       (32, 12, G.FUSED | G.USE_GRAPH)])
 def test_path_matches_independent_solves(binary_problem, B, L, flags):
     print("CASE path", B, L, flags, flush=True)
     P, Xo, lm = binary_problem
@@ -66,3 +68,30 @@ def test_path_rejects_bad_args(binary_problem):
                      [0.1 * lm], B=16)
     with pytest.raises(G.GencdError):
         G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=64), [0.1 * lm], B=24)
+
+
+@pytest.mark.parametrize("loss,B,flags", [(synth.SQUARED, 32, G.USE_GRAPH), (synth.SQUARED, 64, 0),
+                                          (synth.LOGISTIC, 16, G.USE_GRAPH)])
+def test_path_check_statistics_match_oracle(loss, B, flags):
+    """Every per-slot statistic of the batched FP64 check (objective, KKT,
+    duality gap, nnz(w)) against the oracle evaluated at the returned w."""
+    print("CASE path check stats", loss, B, flags, flush=True)
+    P = synth.make_bernoulli_problem(1500, 4000, 0.004, loss, seed=31, support=30)
+    Xo = O.Matrix.of(P)
+    lm = O.lambda_max(Xo, P.y, P.loss)
+    lams = synth.lambda_grid(lm, count=B + 5, ratio=0.05)
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=128, seed=2, tol=1e-7,
+                           max_epochs=20000, flags=flags)
+    res = G.solve_path(X, y, params, lams, B=B)
+    assert res.status == G.OK
+    W = res.W.cpu().numpy().astype(np.float64)
+    for t, lam in enumerate(lams):
+        st = res.stats[t]
+        oc = O.check(Xo, P.y, P.loss, lam, W[t])
+        gap, prim = O.duality_gap(Xo, P.y, P.loss, lam, W[t])
+        assert st["objective"] == pytest.approx(oc.objective, rel=1e-12), t
+        assert st["kkt_max"] == pytest.approx(oc.kkt, rel=1e-9, abs=1e-15), t
+        assert st["gap"] == pytest.approx(gap, rel=1e-6, abs=1e-12 * abs(prim)), t
+        assert st["nnz_w"] == int(np.count_nonzero(W[t])), t
