@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--sweep-scales", type=float, nargs="+", default=[1.0, 8.0],
                     help="sweep: scales of the logistic workload")
     ap.add_argument("--sweep-iters", type=int, default=10, help="sweep: Greedy iterations")
+    ap.add_argument("--sweep-group", type=int, default=0, help="sweep: lanes per short column")
+    ap.add_argument("--sweep-piece", type=int, default=0, help="sweep: nonzeros per long piece")
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (the reference "
                          "dispatch for scaling HBM counters)")
@@ -586,7 +588,9 @@ def bench_sweep(args):
     one |J| = 4096 window.  Runs on the logistic workload (X ~40 MB, held by
     the 256 MB last-level cache) and on its 8x scaled version (n = 8e5,
     k = 4e6, X ~320 MB, which does not fit), to show the kernel against the
-    HBM roofline once launch and latency costs are amortised."""
+    HBM roofline once launch and latency costs are amortised.  Windows this
+    large read a refreshed residual vector (4 B per row gather); the bytes
+    counted are 12 per nonzero and 28 per column."""
     import torch
 
     from paper_1206_6409_amd import gencd as G
@@ -607,7 +611,8 @@ def bench_sweep(args):
             # one epoch of Greedy = one iteration over the whole live set;
             # one FP64 check, after the last epoch
             return G.make_params(P.loss, lam, rule=G.GREEDY, select_size=1, seed=7, tol=0.0,
-                                 max_epochs=epochs, check_every=epochs, flags=flags)
+                                 max_epochs=epochs, check_every=epochs, flags=flags,
+                                 group=args.sweep_group, piece=args.sweep_piece)
 
         ws = G.workspace(X, prm(G.PROFILE, iters))
         G.solve(X, y, prm(0, 2), ws=ws)  # warm-up

@@ -127,6 +127,14 @@ typedef struct {
                             no longer changes the increment.  0 = off (default);
                             the paper used 500.
                             gencd_solve / gencd_step only (0..1000000) */
+  int32_t residual;      /* how Propose forms l'(y_i, z_i) (Algorithm 2): 1 = per
+                            entry from the gathered z_hi, z_lo, y of its row;
+                            2 = from a residual vector refreshed (one pass over
+                            the rows) before the window's Propose, so entries
+                            gather 4 bytes; 0 = automatic: 2 when the window's
+                            expected nonzeros (|window| nnz / live columns)
+                            reach 4 n, else 1.  The same FP32 arithmetic either
+                            way.  gencd_solve / gencd_step only */
 } gencd_params;
 
 /* Host-side statistics filled by the solve calls. */
@@ -145,10 +153,11 @@ typedef struct {
   int32_t converged;
   int32_t num_colors;
   /* GENCD_PROFILE: Propose launches, their summed duration (HIP events on
-   * the solve's stream) and the algorithmic bytes they moved: 20 B per
-   * proposed nonzero (row index, value, and the gathered z_hi, z_lo, y from
-   * which l'(y, z) is formed) and 32 B per proposed column (piece
-   * descriptor, w, c, delta and phi). */
+   * the solve's stream) and the algorithmic bytes they moved: 12 B per
+   * proposed nonzero (row index, value, and the row's residual) and 28 B per
+   * proposed column (column bounds, w, c, delta and phi).  The per-entry
+   * form gathers z_hi, z_lo and y (12 B) instead of the residual, so it
+   * moves more than this count. */
   int64_t prof_launches;
   double prof_kernel_ms;
   double prof_bytes;

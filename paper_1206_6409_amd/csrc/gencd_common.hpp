@@ -205,6 +205,8 @@ struct Ws {
   float4 *zs;            // [n] {z_hi, z_lo, y, 0}: compensated fitted value and label
                          // of a row in one 16-byte record (one gather per entry)
   float *w_ckpt;         // [k]
+  float *rs;             // [n] residual l'(y, z) of every row, refreshed before a
+                         // Propose that reads it (large windows)
   // FP64 check
   double *z64, *r64;     // [n]
   double *g64;           // [k]

@@ -601,7 +601,11 @@ __device__ __forceinline__ float split_sum(const float *part, int32_t pf, int32_
 // Propose of one piece by a group of G lanes.
 // U entries per lane per batch: long pieces (G = 64) take 8 so that a
 // 512-entry piece is one round of dependent loads; short groups take 4.
-template <int G, int MODE, int U = kUnroll>
+// RS: l'(y, z) comes from the refreshed residual vector (a 4-byte gather
+// from an array a quarter of the packed rows' size); otherwise it is formed
+// per entry from the row's packed {z_hi, z_lo, y}.  Both evaluate the same
+// FP32 expression.
+template <int G, int MODE, int U = kUnroll, bool RS = false>
 __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc, int64_t q,
                                               int lane, int32_t P0) {
   const int64_t beg = desc_beg(dsc);
@@ -623,18 +627,27 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
       ri[u] = e < len ? a.row_idx[beg + e] : -1;
       vv[u] = e < len ? a.val[beg + e] : 0.0f;
     }
-    float zh[U], zl[U], yy[U];
+    if constexpr (RS) {
+      float rr[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t i = ri[u] >= 0 ? ri[u] : 0;
-      const float4 zr = a.zs[i];  // one 16-byte gather: z_hi, z_lo, y
-      zh[u] = zr.x;
-      zl[u] = zr.y;
-      yy[u] = zr.z;
+      for (int u = 0; u < U; ++u) rr[u] = a.rs[ri[u] >= 0 ? ri[u] : 0];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ri[u] >= 0) s += vv[u] * rr[u];
+    } else {
+      float zh[U], zl[U], yy[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t i = ri[u] >= 0 ? ri[u] : 0;
+        const float4 zr = a.zs[i];  // one 16-byte gather: z_hi, z_lo, y
+        zh[u] = zr.x;
+        zl[u] = zr.y;
+        yy[u] = zr.z;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ri[u] >= 0) s += vv[u] * dloss_f32(a.loss, yy[u], zh[u] + zl[u]);
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (ri[u] >= 0) s += vv[u] * dloss_f32(a.loss, yy[u], zh[u] + zl[u]);
   }
   s = group_sum<G>(s);
   if (lane != 0) return;
@@ -667,7 +680,7 @@ __device__ __forceinline__ void propose_piece(const IterArgs &a, const int4 dsc,
 // MODE 1: accept all, plain scatter (Coloring: rows of a class are disjoint)
 // MODE 2: deferred acceptance (Thread-Greedy, Greedy)
 // UL: entries per lane per batch on long pieces (piece / 64, 4 or 8).
-template <int GS, int MODE, int UL>
+template <int GS, int MODE, int UL, bool RS>
 __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
   const Roles r = roles(a.nl);
   int32_t P0, P1;
@@ -675,14 +688,25 @@ __global__ __launch_bounds__(kBlock) void k_propose(IterArgs a) {
   if (r.wave < r.nl) {
     const int32_t q1 = a.wbl[a.t + 1];
     for (int64_t q = a.wbl[a.t] + r.wave; q < q1; q += r.nl)
-      propose_piece<kWave, MODE, UL>(a, a.desc_l[q], q, r.wl, P0);
+      propose_piece<kWave, MODE, UL, RS>(a, a.desc_l[q], q, r.wl, P0);
   } else {
     const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
     for (int64_t p = P0 + (r.wave - r.nl) * (kWave / GS) + r.wl / GS; p < P1; p += step) {
       const int4 dsc = a.desc_s[p];
       if (desc_len(dsc) == 0) continue;  // long column: the long waves take it
-      propose_piece<GS, MODE>(a, dsc, p, r.wl & (GS - 1), P0);
+      propose_piece<GS, MODE, kUnroll, RS>(a, dsc, p, r.wl & (GS - 1), P0);
     }
+  }
+}
+
+// Residual refresh (the r = l'(y, z) of Algorithm 1's state) for a Propose
+// that reads it: one pass over the rows.
+__global__ __launch_bounds__(kBlock) void k_refresh(int64_t n, int32_t loss, const float4 *zs,
+                                                     float *rs) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const float4 zr = zs[i];
+    rs[i] = dloss_f32(loss, zr.z, zr.x + zr.y);
   }
 }
 
@@ -1187,26 +1211,36 @@ __global__ __launch_bounds__(kBlock) void k_improve(IterArgs a) {
 // positions per first-stage workgroup of a global accept
 constexpr int64_t kAcceptChunk = 2048;
 
+// With events, Propose is launched through the extension that stamps the
+// kernel's own dispatch with them.
+template <void (*K)(IterArgs)>
+static void launch_propose(const IterArgs &a, dim3 grid, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  if (ev0 && ev1)
+    hipExtLaunchKernelGGL(K, grid, dim3(kBlock), 0, s, ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL(K, grid, dim3(kBlock), 0, s, a);
+}
+
 template <int GS, int UL>
 static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsigned blocks,
                               int64_t nblocks_accept, unsigned improve_blocks, hipStream_t s,
                               hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 grid(blocks), blk(kBlock);
-  // with events, Propose is launched through the extension that stamps the
-  // kernel's own start and end (no dispatch gap in the measured interval)
-  if (ev0 && ev1) {
+  if (a.rs) {
+    hipLaunchKernelGGL(k_refresh, dim3(grid_for(a.nrows)), blk, 0, s, a.nrows, a.loss, a.zs, a.rs);
     if (mode == 0)
-      hipExtLaunchKernelGGL((k_propose<GS, 0, UL>), grid, blk, 0, s, ev0, ev1, 0, a);
+      launch_propose<k_propose<GS, 0, UL, true>>(a, grid, s, ev0, ev1);
     else if (mode == 1)
-      hipExtLaunchKernelGGL((k_propose<GS, 1, UL>), grid, blk, 0, s, ev0, ev1, 0, a);
+      launch_propose<k_propose<GS, 1, UL, true>>(a, grid, s, ev0, ev1);
     else
-      hipExtLaunchKernelGGL((k_propose<GS, 2, UL>), grid, blk, 0, s, ev0, ev1, 0, a);
+      launch_propose<k_propose<GS, 2, UL, true>>(a, grid, s, ev0, ev1);
   } else if (mode == 0) {
-    hipLaunchKernelGGL((k_propose<GS, 0, UL>), grid, blk, 0, s, a);
+    launch_propose<k_propose<GS, 0, UL, false>>(a, grid, s, ev0, ev1);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_propose<GS, 1, UL>), grid, blk, 0, s, a);
+    launch_propose<k_propose<GS, 1, UL, false>>(a, grid, s, ev0, ev1);
   } else {
-    hipLaunchKernelGGL((k_propose<GS, 2, UL>), grid, blk, 0, s, a);
+    launch_propose<k_propose<GS, 2, UL, false>>(a, grid, s, ev0, ev1);
   }
   if (mode == 0) {
     if (a.improve > 0)

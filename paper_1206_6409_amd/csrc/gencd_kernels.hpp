@@ -16,6 +16,8 @@ struct IterArgs {
   const float *c;
   float *w;
   float4 *zs;                      // {z_hi, z_lo, y, 0} per row
+  float *rs;                       // non-null: refresh l'(y, z) into rs, Propose reads it
+  int64_t nrows;
   const int32_t *col_of_pos;
   const int32_t *loff;             // long-piece offsets of the positions
   const int4 *desc_s;              // descriptor of every position (length 0: long column)

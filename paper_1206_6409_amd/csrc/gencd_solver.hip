@@ -76,6 +76,7 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.acc = c.take<int32_t>(k);
   w.zs = c.take<float4>(n);
   w.w_ckpt = c.take<float>(k);
+  w.rs = c.take<float>(n);
   w.z64 = c.take<double>(n);
   w.r64 = c.take<double>(n);
   w.g64 = c.take<double>(k);
@@ -136,6 +137,7 @@ int params_ok(const gencd_params *p, bool need_rule) {
   if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return GENCD_ERR_INVALID_ARG;
   if (p->improve_steps < 0 || p->improve_steps > 1000000) return GENCD_ERR_INVALID_ARG;
+  if (p->residual < 0 || p->residual > 2) return GENCD_ERR_INVALID_ARG;
   if (!need_rule) return GENCD_OK;
   if (p->rule < GENCD_CYCLIC || p->rule > GENCD_BLOCK_SHOTGUN) return GENCD_ERR_INVALID_ARG;
   if (p->rule == GENCD_BLOCK_SHOTGUN && (p->block < 1 || p->block > kMaxBlocks))
@@ -330,6 +332,7 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   a.piece = su.piece;
   a.accept_top = p->rule == GENCD_TOP_GREEDY ? p->block : 0;
   a.improve = p->improve_steps;
+  a.nrows = X->n;
   a.col_ptr = X->col_ptr;
   a.row_idx = X->row_idx;
   a.val = X->val;
@@ -441,6 +444,17 @@ struct EventPool {
       if (e) (void)hipEventDestroy(e);
   }
 };
+
+// Whether Propose reads a refreshed residual vector for a window of
+// `positions` columns: forced by p->residual, or when the window's expected
+// nonzeros reach 4 n (then one pass over the rows costs little next to the
+// 12-byte row gathers it replaces with 4-byte ones).
+bool wants_rs(const gencd_params *p, int64_t positions, int64_t nnz, int64_t k_live, int64_t n) {
+  if (p->residual == 1) return false;
+  if (p->residual == 2) return true;
+  if (k_live <= 0) return false;
+  return double(positions) * double(nnz) / double(k_live) >= 4.0 * double(n);
+}
 
 // Expected long pieces in a window of `positions` columns (sizes the grid;
 // the kernels stride over the actual count).
@@ -621,6 +635,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
         continue;
       }
       const int64_t B = (rule == GENCD_THREAD_GREEDY) ? p->block : positions;
+      a.rs = wants_rs(p, positions, X->nnz, k_live, X->n) ? ws.rs : nullptr;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (record && !evs.empty() && ev_used + 2 <= evs.size()) {
         e0 = evs[ev_used];
@@ -691,7 +706,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
     st_out->iters += iters;
     if (mode != 2) st_out->coord_updates += k_live;
     st_out->epochs = e + 1;
-    if (!evs.empty()) prof_bytes_pending += 20.0 * double(X->nnz) + 32.0 * double(k_live);
+    if (!evs.empty()) prof_bytes_pending += 12.0 * double(X->nnz) + 28.0 * double(k_live);
     st_out->nnz_visits += X->nnz;
     if (mode != 2) st_out->nnz_updates += X->nnz;
     if ((e + 1) % check_every == 0 || e + 1 == p->max_epochs) {
@@ -783,6 +798,7 @@ int step_impl(const gencd_csc *X, const float *y, const gencd_params *p, const i
   a.t = 0;
   a.gout = g;
   const int64_t B = (p->rule == GENCD_THREAD_GREEDY) ? p->block : nJ;
+  a.rs = wants_rs(p, nJ, X->nnz, su.k_live, X->n) ? su.ws.rs : nullptr;
   st = launch_iteration(a, su.group, mode, B, nJ, std::max<int64_t>(long_bound_for(su, nJ), 1),
                         (nJ + B - 1) / B, s);
   if (st) return st;

@@ -64,7 +64,8 @@ def test_workspace_bytes_host_only():
 
 @pytest.mark.parametrize("field,value", [
     ("loss", 7), ("lam", -1.0), ("lam", float("nan")), ("rule", 9),
-    ("select_size", -1), ("max_epochs", -1),
+    ("select_size", -1), ("max_epochs", -1), ("residual", 3), ("residual", -1),
+    ("improve_steps", -1),
 ])
 def test_solve_rejects_bad_params_before_device_work(field, value):
     X = _fake_matrix()

@@ -126,6 +126,14 @@ STEP_CASES = [
     ("c2", G.GREEDY, 0, 8, 256, 0, 100000), ("c4", G.GREEDY, 0, 8, 256, 0, 100000),
     ("c2", G.THREAD_GREEDY, 100000, 8, 256, 0, 100000),
 ]
+# Propose from the refreshed residual vector (2) and per entry (1), whatever
+# the automatic choice would be for the case
+STEP_CASES += [c[:5] + ((c[5] if len(c) > 5 else 0), (c[6] if len(c) > 6 else 700), r)
+               for c in [("c1", G.SHOTGUN, 0, 8, 64), ("c2", G.SHOTGUN, 0, 8, 1024),
+                         ("c2", G.THREAD_GREEDY, 64, 8, 256), ("c2", G.GREEDY, 0, 8, 256, 0, 100000),
+                         ("c3", G.SHOTGUN, 0, 8, 64), ("c4", G.TOP_GREEDY, 100, 8, 64),
+                         ("c2", G.SHOTGUN, 0, 8, 256, G.EXACT_ACCUM)]
+               for r in (1, 2)]
 
 
 @pytest.mark.parametrize("case", STEP_CASES)
@@ -133,7 +141,8 @@ def test_step_parity(problems, case):
     name, rule, block, group, piece = case[:5]
     flags = case[5] if len(case) > 5 else 0
     m_cap = case[6] if len(case) > 6 else 700
-    _print_case("step", name, rule, block, group, piece, flags, m_cap)
+    residual = case[7] if len(case) > 7 else 0
+    _print_case("step", name, rule, block, group, piece, flags, m_cap, residual)
     P = problems[name]
     X = G.Matrix.of(P)
     Xo = O.Matrix.of(P)
@@ -151,7 +160,7 @@ def test_step_parity(problems, case):
     if heavy not in J:
         J[0] = heavy
     params = G.make_params(P.loss, lam, rule=rule, select_size=m, block=block, group=group,
-                           piece=piece, flags=flags)
+                           piece=piece, flags=flags, residual=residual)
     w_d = torch.as_tensor(w, device=DEV)
     zh_d = torch.as_tensor(z_hi, device=DEV)
     zl_d = torch.as_tensor(z_lo, device=DEV)
@@ -215,6 +224,9 @@ SOLVE_CASES = [
     ("c3", G.SHOTGUN, dict(select_size=256)),
     ("c4", G.SHOTGUN, dict(select_size=256)),
     ("c1s", G.STOCHASTIC, dict()),
+    ("c2", G.SHOTGUN, dict(select_size=512, residual=1)),
+    ("c2", G.SHOTGUN, dict(select_size=512, residual=2)),
+    ("c3", G.SHOTGUN, dict(select_size=256, residual=2)),
 ]
 LAM_FRAC = {"c1": 0.1, "c2": 0.05, "c3": 0.1, "c4": 0.05, "c1s": 0.1}
 
