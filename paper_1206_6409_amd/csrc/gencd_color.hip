@@ -16,6 +16,10 @@
 //     later column of the row; a counter reaching zero puts the column in the
 //     next round's frontier.
 // Each frontier column takes the mex of the colours in its row prefixes.
+// A small frontier (the heavy columns come first and form long chains of
+// single-column rounds) spreads its row prefixes over the whole grid, into
+// a bitmap per frontier column in global memory; a large one takes one
+// workgroup per column with the bitmap in LDS.
 #include <hipcub/hipcub.hpp>
 #include <vector>
 
@@ -25,6 +29,7 @@
 namespace gencd {
 
 constexpr int kMexWords = 8192;  // LDS bitmap: 262144 colours
+constexpr int kFlatMax = 64;     // frontiers up to this size use the spread mex
 
 struct ColorWs {
   uint64_t *keys_a, *keys_b;  // [max(k, nnz)]
@@ -41,6 +46,8 @@ struct ColorWs {
   int32_t *scan_part;
   int32_t *ctl;               // [8] frontier sizes (0, 4: by round parity), max colour
                               // snapshot (1), error flag (2), max colour (3), coloured (5)
+  uint32_t *gbits;            // [kFlatMax][kMexWords] colour bitmaps of a small frontier
+                              // (all zero between rounds)
   void *sort_tmp;
   size_t sort_tmp_bytes;
 };
@@ -84,6 +91,7 @@ static size_t color_layout(int64_t n, int64_t k, int64_t nnz, void *base, ColorW
   const int64_t scan_len = mn + 1;
   c.scan_part = static_cast<int32_t *>(take(sizeof(int32_t) * scan_partials_for(scan_len)));
   c.ctl = static_cast<int32_t *>(take(sizeof(int32_t) * 8));
+  c.gbits = static_cast<uint32_t *>(take(sizeof(uint32_t) * kFlatMax * kMexWords));
   size_t t1 = sort_temp_bytes(k, 64), t2 = sort_temp_bytes(nnz, 64);
   c.sort_tmp_bytes = t1 > t2 ? t1 : t2;
   c.sort_tmp = take(c.sort_tmp_bytes);
@@ -167,6 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_mex(const int32_t *Fp, const int64_t
   __shared__ uint32_t bits[kMexWords];
   __shared__ int32_t best;
   const int32_t F = *Fp;
+  if (F <= kFlatMax) return;  // k_mex_flat / k_mex_pick take small frontiers
   const int32_t maxc = ctl[1];  // largest colour so far (-1 initially)
   int32_t words = (maxc + 2 + 31) / 32;
   if (words > kMexWords) words = kMexWords;
@@ -207,6 +216,98 @@ __global__ __launch_bounds__(kBlock) void k_mex(const int32_t *Fp, const int64_t
   }
 }
 
+// Small frontier, first pass: the frontier's CSC entries, in order, are cut
+// into one contiguous chunk per workgroup.  A workgroup marks the colours of
+// its entries' row prefixes in an LDS bitmap, column by column of its
+// chunk, and ORs each nonzero word into that column's global bitmap (one
+// global atomic per word and workgroup: the heavy columns' prefixes would
+// otherwise pile millions of atomics onto a few words).
+__global__ __launch_bounds__(kBlock) void k_mex_flat(const int32_t *Fp, const int32_t *foff,
+                                                      const int32_t *front, const int64_t *col_ptr,
+                                                      const int32_t *row_idx, const int32_t *row_ptr,
+                                                      const int32_t *rank_at,
+                                                      const int32_t *pos_in_row,
+                                                      const int32_t *order, const int32_t *color,
+                                                      const int32_t *ctl, uint32_t *gbits) {
+  __shared__ uint32_t bits[kMexWords];
+  const int32_t F = *Fp;
+  if (F > kFlatMax || F == 0) return;
+  const int32_t total = foff[F];
+  const int32_t maxc = ctl[1];
+  int32_t words = (maxc + 2 + 31) / 32;
+  if (words > kMexWords) words = kMexWords;
+  const int32_t chunk = int32_t((int64_t(total) + gridDim.x - 1) / gridDim.x);
+  int32_t t0 = int32_t(int64_t(blockIdx.x) * chunk);
+  const int32_t t1 = int32_t(std::min<int64_t>(int64_t(t0) + chunk, total));
+  if (t0 >= t1) return;
+  int32_t f = 0, hi = F;  // last f with foff[f] <= t0
+  while (hi - f > 1) {
+    const int32_t mid = (f + hi) >> 1;
+    if (foff[mid] <= t0) f = mid; else hi = mid;
+  }
+  while (t0 < t1) {
+    const int32_t fe = std::min(t1, foff[f + 1]);
+    for (int32_t u = threadIdx.x; u < words; u += kBlock) bits[u] = 0u;
+    __syncthreads();
+    const int64_t cbeg = col_ptr[front[f]] - foff[f];
+    for (int32_t t = t0 + int32_t(threadIdx.x); t < fe; t += kBlock) {
+      const int64_t e = cbeg + t;
+      const int32_t r = row_idx[e];
+      const int32_t a = row_ptr[r], b = a + pos_in_row[e];
+      for (int32_t q = a; q < b; ++q) {
+        const int32_t c = color[order[rank_at[q]]];
+        if (c >= 0 && c < words * 32) atomicOr(&bits[c >> 5], 1u << (c & 31));
+      }
+    }
+    __syncthreads();
+    uint32_t *g = gbits + int64_t(f) * kMexWords;
+    for (int32_t u = threadIdx.x; u < words; u += kBlock)
+      if (bits[u]) atomicOr(&g[u], bits[u]);
+    __syncthreads();
+    t0 = fe;
+    ++f;
+  }
+}
+
+// Small frontier, second pass: one workgroup per frontier column takes the
+// lowest clear bit of its bitmap, then clears the words it read.
+__global__ __launch_bounds__(kBlock) void k_mex_pick(const int32_t *Fp, const int32_t *front,
+                                                      int32_t *color, int32_t *ctl,
+                                                      uint32_t *gbits) {
+  __shared__ int32_t best;
+  const int32_t F = *Fp;
+  if (F > kFlatMax) return;
+  const int32_t maxc = ctl[1];
+  int32_t words = (maxc + 2 + 31) / 32;
+  if (words > kMexWords) words = kMexWords;
+  for (int32_t f = blockIdx.x; f < F; f += gridDim.x) {
+    uint32_t *bits = gbits + int64_t(f) * kMexWords;
+    if (threadIdx.x == 0) best = INT32_MAX;
+    __syncthreads();
+    int32_t mine = INT32_MAX;
+    for (int32_t u = threadIdx.x; u < words; u += kBlock) {
+      const uint32_t free_bits = ~bits[u];
+      if (free_bits) {
+        mine = u * 32 + __ffs(int(free_bits)) - 1;
+        break;
+      }
+    }
+    if (mine != INT32_MAX) atomicMin(&best, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t c = best == INT32_MAX ? words * 32 : best;
+      if (c >= kMexWords * 32) {
+        atomicOr(&ctl[2], 1);
+        c = kMexWords * 32 - 1;
+      }
+      color[front[f]] = c;
+      atomicMax(&ctl[3], c);
+    }
+    for (int32_t u = threadIdx.x; u < words; u += kBlock) bits[u] = 0u;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_front_nnz(const int32_t *Fp, const int64_t *col_ptr,
                                                        const int32_t *front, int32_t *cnt) {
   const int32_t F = *Fp;
@@ -218,6 +319,13 @@ __global__ __launch_bounds__(kBlock) void k_front_nnz(const int32_t *Fp, const i
 }
 
 // Flattened over the frontier's CSC entries: decrement later row neighbours.
+// A heavy column's rows share later columns many times over, so each
+// workgroup first sums its decrements per column in an LDS hash table and
+// applies one atomic per distinct column (a column whose slot is not found
+// within kProbe probes is decremented directly).  The atomic that takes a
+// count to zero puts the column in the next frontier.
+constexpr int kHash = 2048;
+constexpr int kProbe = 8;
 __global__ __launch_bounds__(kBlock) void k_decrement(const int32_t *Fp, const int64_t *col_ptr,
                                                        const int32_t *row_idx, const int32_t *front,
                                                        const int32_t *foff, const int32_t *row_ptr,
@@ -225,23 +333,54 @@ __global__ __launch_bounds__(kBlock) void k_decrement(const int32_t *Fp, const i
                                                        const int32_t *pos_in_row,
                                                        const int32_t *order, int32_t *count,
                                                        int32_t *next, int32_t *next_cnt) {
+  __shared__ int32_t hkey[kHash];
+  __shared__ int32_t hcnt[kHash];
   const int32_t F = *Fp;
   const int32_t total = foff[F];
-  for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < total;
-       t += int64_t(gridDim.x) * kBlock) {
-    int32_t lo = 0, hi = F;  // find f with foff[f] <= t < foff[f+1]
-    while (hi - lo > 1) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (foff[mid] <= t) lo = mid; else hi = mid;
+  if (int64_t(blockIdx.x) * kBlock >= total) return;  // no entries for this workgroup
+  for (int32_t u = threadIdx.x; u < kHash; u += kBlock) {
+    hkey[u] = -1;
+    hcnt[u] = 0;
+  }
+  __syncthreads();
+  for (int64_t base = int64_t(blockIdx.x) * kBlock; base < total;
+       base += int64_t(gridDim.x) * kBlock) {
+    const int64_t t = base + threadIdx.x;
+    if (t < total) {
+      int32_t lo = 0, hi = F;  // find f with foff[f] <= t < foff[f+1]
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (foff[mid] <= t) lo = mid; else hi = mid;
+      }
+      const int32_t j = front[lo];
+      const int64_t e = col_ptr[j] + (t - foff[lo]);
+      const int32_t r = row_idx[e];
+      const int32_t b = row_ptr[r + 1];
+      for (int32_t q = row_ptr[r] + pos_in_row[e] + 1; q < b; ++q) {
+        const int32_t j2 = order[rank_at[q]];
+        uint32_t h = (uint32_t(j2) * 2654435761u) & (kHash - 1);
+        bool done = false;
+        for (int p = 0; p < kProbe && !done; ++p, h = (h + 1) & (kHash - 1)) {
+          const int32_t prev = atomicCAS(&hkey[h], -1, j2);
+          if (prev == -1 || prev == j2) {
+            atomicAdd(&hcnt[h], 1);
+            done = true;
+          }
+        }
+        if (!done && atomicSub(&count[j2], 1) == 1) next[atomicAdd(next_cnt, 1)] = j2;
+      }
     }
-    const int32_t j = front[lo];
-    const int64_t e = col_ptr[j] + (t - foff[lo]);
-    const int32_t r = row_idx[e];
-    const int32_t b = row_ptr[r + 1];
-    for (int32_t s = row_ptr[r] + pos_in_row[e] + 1; s < b; ++s) {
-      const int32_t j2 = order[rank_at[s]];
-      if (atomicSub(&count[j2], 1) == 1) next[atomicAdd(next_cnt, 1)] = j2;
+    __syncthreads();
+    for (int32_t u = threadIdx.x; u < kHash; u += kBlock) {
+      const int32_t key = hkey[u];
+      if (key >= 0) {
+        const int32_t c = hcnt[u];
+        if (atomicSub(&count[key], c) == c) next[atomicAdd(next_cnt, 1)] = key;
+        hkey[u] = -1;
+        hcnt[u] = 0;
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -300,6 +439,8 @@ int color_run(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws_
   }
   st = fill_i32(w.ctl, 8, 0, s);
   if (st) return st;
+  st = fill_i32(reinterpret_cast<int32_t *>(w.gbits), int64_t(kFlatMax) * kMexWords, 0, s);
+  if (st) return st;
   // ctl[1] = largest colour so far, start at -1
   st = fill_i32(w.ctl + 1, 1, -1, s);
   if (st) return st;
@@ -322,12 +463,18 @@ int color_run(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws_
   for (;;) {
     for (int r = 0; r < kRoundsPerSync; ++r, ++round) {
       int32_t *fc = w.ctl + ((round & 1) ? 4 : 0), *fn = w.ctl + ((round & 1) ? 0 : 4);
-      hipLaunchKernelGGL(k_mex, dim3(mex_grid), dim3(kBlock), 0, s, fc, X->col_ptr, X->row_idx,
-                         cur, w.row_ptr, w.rank_at, w.pos_in_row, w.order, color, w.ctl);
       hipLaunchKernelGGL(k_front_nnz, dim3(g1(k)), dim3(kBlock), 0, s, fc, X->col_ptr, cur,
                          w.fcnt);
       st = scan_exclusive(w.fcnt, w.foff, k, w.scan_part, s);  // entries before F count
       if (st) return st;
+      // the colours of the frontier: one of the two forms runs, by its size
+      hipLaunchKernelGGL(k_mex, dim3(mex_grid), dim3(kBlock), 0, s, fc, X->col_ptr, X->row_idx,
+                         cur, w.row_ptr, w.rank_at, w.pos_in_row, w.order, color, w.ctl);
+      hipLaunchKernelGGL(k_mex_flat, dim3(2048), dim3(kBlock), 0, s, fc, w.foff, cur, X->col_ptr,
+                         X->row_idx, w.row_ptr, w.rank_at, w.pos_in_row, w.order, color, w.ctl,
+                         w.gbits);
+      hipLaunchKernelGGL(k_mex_pick, dim3(kFlatMax), dim3(kBlock), 0, s, fc, cur, color, w.ctl,
+                         w.gbits);
       hipLaunchKernelGGL(k_decrement, dim3(g1(nnz > 0 ? nnz : 1, 8192)), dim3(kBlock), 0, s, fc,
                          X->col_ptr, X->row_idx, cur, w.foff, w.row_ptr, w.rank_at, w.pos_in_row,
                          w.order, w.count, nxt, fn);
