@@ -264,9 +264,9 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
 
 /* Schedule autotuner.  Times every candidate schedule (lanes per short
  * column in {4, 8, 16} x nonzeros per long piece in {128, 256, 512} x
- * captured-epoch graph on/off) on `epochs` epochs of the real solve from
- * w = 0 and returns
- * the fastest in *out; copy out->group, out->piece and out->flags into
+ * captured-epoch graph on/off x residual per entry / refreshed vector) on
+ * `epochs` epochs of the real solve from w = 0 and returns the fastest in
+ * *out; copy out->group, out->piece, out->flags and out->residual into
  * gencd_params to use it.  Results are cached (JSON lines) in cache_path, or
  * in $GENCD_TUNE_CACHE when cache_path is NULL, under a key made of the
  * device, the problem shape and rule, and the histogram of column lengths;
@@ -279,6 +279,7 @@ typedef struct {
   uint32_t flags;            /* GENCD_USE_GRAPH or 0 */
   double seconds_per_epoch;  /* measured on the tuning run */
   int32_t from_cache;
+  int32_t residual;          /* gencd_params.residual of the schedule (1 or 2) */
 } gencd_schedule;
 
 int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, int32_t epochs,

@@ -1,7 +1,7 @@
 // Schedule autotuner for gencd_solve.
 //
 // A schedule is (lanes per piece, nonzeros per piece, captured-epoch graph
-// on/off).  The tuner times each candidate on a short run of the real solve
+// on/off, residual formed per entry or read from a refreshed vector).  The tuner times each candidate on a short run of the real solve
 // (a few epochs from w = 0, no convergence test in between) and keeps the
 // fastest.  Results are cached on disk, one JSON object per line, keyed by a
 // problem signature: device architecture and CU count, n, k, nnz, loss,
@@ -65,9 +65,11 @@ static bool cache_lookup(const char *path, const std::string &key, gencd_schedul
   const std::string pat = "\"key\": \"" + key + "\"";
   while (std::getline(f, line)) {
     if (line.find(pat) == std::string::npos) continue;
-    int g = 0, pc = 0;
+    int g = 0, pc = 0, rs = 0;
     unsigned fl = 0;
     double sec = 0;
+    const char *v = std::strstr(line.c_str(), "\"residual\":");
+    if (v) (void)std::sscanf(v, "\"residual\": %d", &rs);
     const char *q = std::strstr(line.c_str(), "\"group\":");
     const char *r = std::strstr(line.c_str(), "\"piece\":");
     const char *t = std::strstr(line.c_str(), "\"flags\":");
@@ -79,6 +81,7 @@ static bool cache_lookup(const char *path, const std::string &key, gencd_schedul
       out->piece = pc;
       out->flags = fl;
       out->seconds_per_epoch = sec;
+      out->residual = rs;
       out->from_cache = 1;
       found = true;  // last entry for the key wins
     }
@@ -91,7 +94,8 @@ static void cache_store(const char *path, const std::string &key, const gencd_sc
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ofstream f(path, std::ios::app);
   f << "{\"key\": \"" << key << "\", \"group\": " << s.group << ", \"piece\": " << s.piece
-    << ", \"flags\": " << s.flags << ", \"seconds_per_epoch\": " << s.seconds_per_epoch << "}\n";
+    << ", \"flags\": " << s.flags << ", \"residual\": " << s.residual
+    << ", \"seconds_per_epoch\": " << s.seconds_per_epoch << "}\n";
 }
 
 }  // namespace gencd
@@ -125,37 +129,41 @@ int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, in
   const int groups[] = {4, 8, 16};
   const int pieces[] = {128, 256, 512};
   const unsigned gflags[] = {0u, GENCD_USE_GRAPH};
+  const int residuals[] = {1, 2};
   double best = 1e300;
   for (int g : groups)
     for (int pc : pieces)
-      for (unsigned gf : gflags) {
-        gencd_params q = *p;
-        q.group = g;
-        q.piece = pc;
-        q.flags = (p->flags & ~(GENCD_WARM_START | GENCD_USE_GRAPH | GENCD_PROFILE)) | gf;
-        q.kkt_tol = 0.0;  // run exactly `epochs` epochs
-        q.gap_tol = 0.0;
-        q.max_epochs = epochs;
-        q.check_every = epochs;
-        size_t need = 0;
-        if (gencd_workspace_bytes(X, &q, &need) != GENCD_OK || need > ws_bytes) continue;
-        gencd_stats st{};
-        // first run warms caches and (for graphs) pays the capture once
-        int rc = solve_impl(X, y, &q, w_scratch, nullptr, ws, ws_bytes, stream, &st);
-        if (rc < 0) continue;
-        auto t0 = std::chrono::steady_clock::now();
-        rc = solve_impl(X, y, &q, w_scratch, nullptr, ws, ws_bytes, stream, &st);
-        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (rc < 0 || st.epochs <= 0) continue;
-        const double per = sec / double(st.epochs);
-        if (per < best) {
-          best = per;
-          out->group = g;
-          out->piece = pc;
-          out->flags = gf;
-          out->seconds_per_epoch = per;
+      for (unsigned gf : gflags)
+        for (int rs : residuals) {
+          gencd_params q = *p;
+          q.group = g;
+          q.piece = pc;
+          q.residual = rs;
+          q.flags = (p->flags & ~(GENCD_WARM_START | GENCD_USE_GRAPH | GENCD_PROFILE)) | gf;
+          q.kkt_tol = 0.0;  // run exactly `epochs` epochs
+          q.gap_tol = 0.0;
+          q.max_epochs = epochs;
+          q.check_every = epochs;
+          size_t need = 0;
+          if (gencd_workspace_bytes(X, &q, &need) != GENCD_OK || need > ws_bytes) continue;
+          gencd_stats st{};
+          // first run warms caches and (for graphs) pays the capture once
+          int rc = solve_impl(X, y, &q, w_scratch, nullptr, ws, ws_bytes, stream, &st);
+          if (rc < 0) continue;
+          auto t0 = std::chrono::steady_clock::now();
+          rc = solve_impl(X, y, &q, w_scratch, nullptr, ws, ws_bytes, stream, &st);
+          const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          if (rc < 0 || st.epochs <= 0) continue;
+          const double per = sec / double(st.epochs);
+          if (per < best) {
+            best = per;
+            out->group = g;
+            out->piece = pc;
+            out->flags = gf;
+            out->residual = rs;
+            out->seconds_per_epoch = per;
+          }
         }
-      }
   if (best == 1e300) return GENCD_ERR_WORKSPACE;
   out->from_cache = 0;
   cache_store(cache_path, key, *out);

@@ -461,14 +461,16 @@ def server_plan(arena_bytes, max_slots, bytes_, arrival, service):
 
 class Schedule(C.Structure):
     _fields_ = [("group", C.c_int32), ("piece", C.c_int32), ("flags", C.c_uint32),
-                ("seconds_per_epoch", C.c_double), ("from_cache", C.c_int32)]
+                ("seconds_per_epoch", C.c_double), ("from_cache", C.c_int32),
+                ("residual", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def autotune(X: Matrix, y, params: Params, epochs=2, cache_path=None):
-    """Fastest (group, piece, graph) schedule for this problem; apply with apply_schedule."""
+    """Fastest (group, piece, graph, residual) schedule for this problem; apply with
+    apply_schedule."""
     # the candidate needing the most workspace: smallest pieces and groups
     pmax = Params.from_buffer_copy(params)
     pmax.piece, pmax.group = 128, 4
@@ -510,4 +512,5 @@ def apply_schedule(params: Params, sched: dict):
     params.group = int(sched["group"])
     params.piece = int(sched["piece"])
     params.flags = (params.flags & ~USE_GRAPH) | int(sched["flags"])
+    params.residual = int(sched.get("residual", 0))
     return params

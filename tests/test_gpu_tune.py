@@ -22,12 +22,13 @@ def test_autotune_cache_and_correctness(tmp_path):
                            max_epochs=20000)
     cache = str(tmp_path / "tune.jsonl")
     s1 = G.autotune(X, y, params, epochs=3, cache_path=cache)
-    assert s1["group"] in (4, 8, 16) and s1["piece"] in (128, 256, 512)
+    assert s1["group"] in (4, 8, 16) and s1["piece"] in (128, 256, 512) and s1["residual"] in (1, 2)
     assert s1["from_cache"] == 0 and s1["seconds_per_epoch"] > 0
     assert os.path.getsize(cache) > 0
     s2 = G.autotune(X, y, params, epochs=3, cache_path=cache)
     assert s2["from_cache"] == 1
-    assert (s2["group"], s2["piece"], s2["flags"]) == (s1["group"], s1["piece"], s1["flags"])
+    assert (s2["group"], s2["piece"], s2["flags"], s2["residual"]) == \
+        (s1["group"], s1["piece"], s1["flags"], s1["residual"])
     res = G.solve(X, y, G.apply_schedule(params, s1))
     assert res.status == G.OK
     ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000)
