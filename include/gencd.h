@@ -162,7 +162,8 @@ typedef struct {
   double prof_kernel_ms;
   double prof_bytes;
   double rho;             /* spectral-radius estimate when |J| came from it, else 0 */
-  int64_t select_size;    /* |J| used by the solve */
+  int64_t select_size;    /* |J| used by the solve (after any halving by the
+                             divergence guard) */
 } gencd_stats;
 
 const char *gencd_status_string(int status);

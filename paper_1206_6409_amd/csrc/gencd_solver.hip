@@ -730,6 +730,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
         st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
         if (st) return st;
         S = (S + 1) / 2;
+        st_out->select_size = S;
         continue;
       }
       if (!std::isfinite(ck.objective)) return GENCD_ERR_DIVERGED;

@@ -98,3 +98,25 @@ def test_empty_matrix_new_rules():
                dict(rule=G.SHOTGUN, select_size=4, improve=10)):
         res = _solve(P, 0.1, **kw)
         assert res.status == G.OK and np.all(res.w.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("flags", [0, G.USE_GRAPH])
+def test_divergence_guard_halves_the_selection_and_converges(flags):
+    """Jacobi Shotgun over every column of strongly correlated columns
+    overshoots; the guard restores the last checked point, halves |J| and
+    rebuilds the selection order, and the solve still reaches the optimum."""
+    rng = np.random.default_rng(5)
+    n, k = 200, 64
+    # a shared component correlates every pair of columns (rho ~ 14 on the
+    # normalised Gram matrix, so only |J| <= 8 is stable)
+    dense = rng.standard_normal((n, k)) + 0.5 * rng.standard_normal((n, 1))
+    y = (dense[:, :5] @ rng.standard_normal(5) + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    col_ptr = np.arange(0, n * k + 1, n, dtype=np.int64)
+    row_idx = np.tile(np.arange(n, dtype=np.int32), k)
+    val = dense.T.reshape(-1).astype(np.float32)
+    P = synth.Problem(n, k, col_ptr, row_idx, val, y, synth.SQUARED, name="correlated")
+    lam = 0.05 * O.lambda_max(O.Matrix.of(P), P.y, P.loss)
+    Xo, ref = _ref(P, lam)
+    res = _solve(P, lam, tol=1e-7, rule=G.SHOTGUN, select_size=k, flags=flags)
+    assert res.stats["select_size"] < k  # the guard fired
+    _assert_optimum(P, lam, res, Xo, ref, kkt=1e-7)
