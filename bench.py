@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--req-scale", type=float, default=0.25,
                     help="serve: scale of the n and k ranges of the request distribution")
     ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
+    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent request slots")
     ap.add_argument("--serve-jacobi", action="store_true",
                     help="serve: Jacobi Propose/Update instead of the fused iteration")
     ap.add_argument("--sweep-scales", type=float, nargs="+", default=[1.0, 8.0],
@@ -525,7 +526,7 @@ def bench_serve(args):
                              max_epochs=20000, flags=G.USE_GRAPH | serve_flags)
 
     need = max(G.workspace_bytes(X, params(P, 1.0)) for P, X, y, lm in pool)
-    slots = 8
+    slots = args.slots
     srv = G.Server(arena_bytes=slots * need + (64 << 20), max_slots=slots)
 
     def run_stream(server, arrivals):
@@ -537,9 +538,14 @@ def bench_serve(args):
             if at > now:
                 time.sleep(at - now)
             server.submit(X, y, params(P, lam), outs[i], tag=i)
+            if (i + 1) % 50 == 0:
+                log(f"  submitted {i + 1} requests")
         res = []
         while len(res) < len(reqs):
-            res += server.poll(wait_for=1)
+            got = server.poll(wait_for=1)
+            if got and (len(res) + len(got)) // 25 > len(res) // 25:
+                log(f"  {len(res) + len(got)} of {len(reqs)} requests done")
+            res += got
         return res
 
     # saturated throughput: everything arrives at once
