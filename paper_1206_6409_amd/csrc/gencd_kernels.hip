@@ -1562,22 +1562,36 @@ __global__ __launch_bounds__(kBlock) void k_check_kkt(int64_t k, double *g64, co
   __shared__ unsigned long long snz[kBlock];
   double vmax = 0.0, l1 = 0.0, gmax = 0.0;
   unsigned long long nz = 0;
-  for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
-       j += int64_t(gridDim.x) * kBlock) {
-    const double g = g64[j] * inv_n;
-    g64[j] = g;
-    if (!(fabs(g) <= gmax)) gmax = fabs(g);
-    const double wj = w ? double(w[j]) : 0.0;
-    double v;
-    if (wj != 0.0) {
-      v = fabs(g + (wj > 0.0 ? lam : -lam));
-      l1 += fabs(wj);
-      ++nz;
-    } else {
-      v = fabs(g) - lam;
-      if (v < 0.0) v = 0.0;
+  // four columns per thread and round: their loads are issued together
+  constexpr int U = 4;
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t j0 = int64_t(blockIdx.x) * kBlock + threadIdx.x; j0 < k; j0 += U * stride) {
+    double gv[U], wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * stride;
+      gv[u] = j < k ? g64[j] : 0.0;
+      wv[u] = (w && j < k) ? double(w[j]) : 0.0;
     }
-    if (!(v <= vmax)) vmax = v;  // propagates NaN
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * stride;
+      if (j >= k) break;
+      const double g = gv[u] * inv_n;
+      g64[j] = g;
+      if (!(fabs(g) <= gmax)) gmax = fabs(g);
+      const double wj = wv[u];
+      double v;
+      if (wj != 0.0) {
+        v = fabs(g + (wj > 0.0 ? lam : -lam));
+        l1 += fabs(wj);
+        ++nz;
+      } else {
+        v = fabs(g) - lam;
+        if (v < 0.0) v = 0.0;
+      }
+      if (!(v <= vmax)) vmax = v;  // propagates NaN
+    }
   }
   smax[threadIdx.x] = vmax;
   sl1[threadIdx.x] = l1;
