@@ -112,6 +112,16 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
     const int4 pd = a.pdesc[a.win_lo + p];
     const int32_t j = pd.y;
     const int64_t cb = int64_t(uint32_t(pd.x)), ce = cb + pd.z;
+    // the slot's weight, curvature, lambda and activity: issued with the
+    // entries' loads, consumed after the reduction
+    float wj = 0.0f, cj = 0.0f, lam = 0.0f;
+    int32_t act = 0;
+    if (int(threadIdx.x) < B) {
+      wj = a.W[int64_t(j) * B + s];
+      cj = a.c[j];
+      lam = a.lam[s];
+      act = a.active[s];
+    }
     float acc = 0.0f;
     for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
       int32_t ri[PU];
@@ -143,11 +153,10 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
 #pragma unroll
       for (int w = 0; w < NW; ++w) g += sred[w][s];
       float d = 0.0f;
-      if (a.active[s] != 0) {
+      if (act != 0) {
         g /= a.n_f;
-        const float wj = a.W[int64_t(j) * B + s];
         float ph;
-        propose_f32(g, a.c[j], wj, a.lam[s], d, ph);
+        propose_f32(g, cj, wj, lam, d, ph);
         if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
       }
       a.delta[p * B + s] = d;
@@ -204,6 +213,17 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
     const int32_t j = pd.y;
     const int64_t cb = int64_t(uint32_t(pd.x)), ce = cb + pd.z;
     const bool one = ce - cb <= int64_t(R) * PU;  // the whole column in one batch
+    // the slot's weight (written only by this workgroup, which owns column
+    // j in this window), curvature, lambda and activity: issued with the
+    // entries' loads, consumed after the reduction
+    float wj = 0.0f, cj = 0.0f, lam = 0.0f;
+    int32_t act = 0;
+    if (int(threadIdx.x) < B) {
+      wj = a.W[int64_t(j) * B + s];
+      cj = a.c[j];
+      lam = a.lam[s];
+      act = a.active[s];
+    }
     int32_t ri[PU];
     float vv[PU];
     float acc = 0.0f;
@@ -235,11 +255,10 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
 #pragma unroll
       for (int w = 0; w < NW; ++w) g += sred[w][s];
       float d = 0.0f;
-      if (a.active[s] != 0) {
+      if (act != 0) {
         g /= a.n_f;
-        const float wj = a.W[int64_t(j) * B + s];
         float ph;
-        propose_f32(g, a.c[j], wj, a.lam[s], d, ph);
+        propose_f32(g, cj, wj, lam, d, ph);
         if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
       }
       sdel[s] = d;
