@@ -30,6 +30,10 @@ namespace gencd {
 
 constexpr int kMexWords = 8192;  // LDS bitmap: 262144 colours
 constexpr int kFlatMax = 64;     // frontiers up to this size use the spread mex
+// Lanes that share one CSC entry's row prefix (mex) or row suffix
+// (readiness counts): a row holds ~30 entries on the Lasso workload, so one
+// or two rounds of loads instead of a serial walk.
+constexpr int kSG = 16;
 
 struct ColorWs {
   uint64_t *keys_a, *keys_b;  // [max(k, nnz)]
@@ -150,44 +154,61 @@ __global__ __launch_bounds__(kBlock) void k_init_count(const int64_t *col_ptr, i
                                                         const int32_t *pos_in_row, int32_t *count,
                                                         int32_t *color, int32_t *front,
                                                         int32_t *ctl) {
+  // An empty column has no neighbours: the greedy order gives it colour 0
+  // (the mex of nothing) whenever it is visited, so it is coloured here and
+  // counted once per workgroup instead of joining the first frontier, where
+  // the many empty columns would queue on one counter.
+  __shared__ int32_t nempty;
+  if (threadIdx.x == 0) nempty = 0;
+  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave;
   const int64_t nw = int64_t(gridDim.x) * kBlock / kWave;
   for (int64_t j = wid; j < k; j += nw) {
+    const int64_t e0 = col_ptr[j], e1 = col_ptr[j + 1];
     int32_t s = 0;
-    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave) s += pos_in_row[e];
+    for (int64_t e = e0 + lane; e < e1; e += kWave) s += pos_in_row[e];
     s = group_sum<kWave>(s);
     if (lane == 0) {
       count[j] = s;
-      color[j] = -1;
-      if (s == 0) front[atomicAdd(&ctl[0], 1)] = int32_t(j);
+      if (e1 == e0) {
+        color[j] = 0;
+        atomicAdd(&nempty, 1);
+      } else {
+        color[j] = -1;
+        if (s == 0) front[atomicAdd(&ctl[0], 1)] = int32_t(j);
+      }
     }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && nempty > 0) {
+    atomicAdd(&ctl[5], nempty);  // coloured columns
+    atomicMax(&ctl[3], 0);       // largest colour so far
   }
 }
 
 // colour of each frontier column: mex of the colours in its row prefixes
 // (one workgroup per frontier column, LDS bitmap of the colours so far)
-__global__ __launch_bounds__(kBlock) void k_mex(const int32_t *Fp, const int64_t *col_ptr,
-                                                 const int32_t *row_idx, const int32_t *front,
-                                                 const int32_t *row_ptr, const int32_t *rank_at,
-                                                 const int32_t *pos_in_row, const int32_t *order,
-                                                 int32_t *color, int32_t *ctl) {
-  __shared__ uint32_t bits[kMexWords];
-  __shared__ int32_t best;
+__device__ void mex_blocks(int64_t vb, int64_t nvb, uint32_t *bits, int32_t &best,
+                           const int32_t *Fp, const int64_t *col_ptr, const int32_t *row_idx,
+                           const int32_t *front, const int32_t *row_ptr, const int32_t *rank_at,
+                           const int32_t *pos_in_row, const int32_t *order, int32_t *color,
+                           int32_t *ctl) {
   const int32_t F = *Fp;
   if (F <= kFlatMax) return;  // k_mex_flat / k_mex_pick take small frontiers
   const int32_t maxc = ctl[1];  // largest colour so far (-1 initially)
   int32_t words = (maxc + 2 + 31) / 32;
   if (words > kMexWords) words = kMexWords;
-  for (int64_t f = blockIdx.x; f < F; f += gridDim.x) {
+  for (int64_t f = vb; f < F; f += nvb) {
     const int32_t j = front[f];
     for (int32_t u = threadIdx.x; u < words; u += kBlock) bits[u] = 0u;
     if (threadIdx.x == 0) best = INT32_MAX;
     __syncthreads();
-    for (int64_t e = col_ptr[j] + threadIdx.x; e < col_ptr[j + 1]; e += kBlock) {
+    const int sub = int(threadIdx.x) / kSG, l = int(threadIdx.x) % kSG;
+    for (int64_t e = col_ptr[j] + sub; e < col_ptr[j + 1]; e += kBlock / kSG) {
       const int32_t r = row_idx[e];
       const int32_t a = row_ptr[r], b = a + pos_in_row[e];
-      for (int32_t q = a; q < b; ++q) {
+      for (int32_t q = a + l; q < b; q += kSG) {
         const int32_t c = color[order[rank_at[q]]];
         if (c >= 0 && c < kMexWords * 32) atomicOr(&bits[c >> 5], 1u << (c & 31));
       }
@@ -222,22 +243,20 @@ __global__ __launch_bounds__(kBlock) void k_mex(const int32_t *Fp, const int64_t
 // chunk, and ORs each nonzero word into that column's global bitmap (one
 // global atomic per word and workgroup: the heavy columns' prefixes would
 // otherwise pile millions of atomics onto a few words).
-__global__ __launch_bounds__(kBlock) void k_mex_flat(const int32_t *Fp, const int32_t *foff,
-                                                      const int32_t *front, const int64_t *col_ptr,
-                                                      const int32_t *row_idx, const int32_t *row_ptr,
-                                                      const int32_t *rank_at,
-                                                      const int32_t *pos_in_row,
-                                                      const int32_t *order, const int32_t *color,
-                                                      const int32_t *ctl, uint32_t *gbits) {
-  __shared__ uint32_t bits[kMexWords];
+__device__ void mex_flat_blocks(int64_t vb, int64_t nvb, uint32_t *bits, const int32_t *Fp,
+                                const int32_t *foff, const int32_t *front, const int64_t *col_ptr,
+                                const int32_t *row_idx, const int32_t *row_ptr,
+                                const int32_t *rank_at, const int32_t *pos_in_row,
+                                const int32_t *order, const int32_t *color, const int32_t *ctl,
+                                uint32_t *gbits) {
   const int32_t F = *Fp;
   if (F > kFlatMax || F == 0) return;
   const int32_t total = foff[F];
   const int32_t maxc = ctl[1];
   int32_t words = (maxc + 2 + 31) / 32;
   if (words > kMexWords) words = kMexWords;
-  const int32_t chunk = int32_t((int64_t(total) + gridDim.x - 1) / gridDim.x);
-  int32_t t0 = int32_t(int64_t(blockIdx.x) * chunk);
+  const int32_t chunk = int32_t((int64_t(total) + nvb - 1) / nvb);
+  int32_t t0 = int32_t(vb * chunk);
   const int32_t t1 = int32_t(std::min<int64_t>(int64_t(t0) + chunk, total));
   if (t0 >= t1) return;
   int32_t f = 0, hi = F;  // last f with foff[f] <= t0
@@ -250,11 +269,12 @@ __global__ __launch_bounds__(kBlock) void k_mex_flat(const int32_t *Fp, const in
     for (int32_t u = threadIdx.x; u < words; u += kBlock) bits[u] = 0u;
     __syncthreads();
     const int64_t cbeg = col_ptr[front[f]] - foff[f];
-    for (int32_t t = t0 + int32_t(threadIdx.x); t < fe; t += kBlock) {
+    const int sub = int(threadIdx.x) / kSG, l = int(threadIdx.x) % kSG;
+    for (int32_t t = t0 + sub; t < fe; t += kBlock / kSG) {
       const int64_t e = cbeg + t;
       const int32_t r = row_idx[e];
       const int32_t a = row_ptr[r], b = a + pos_in_row[e];
-      for (int32_t q = a; q < b; ++q) {
+      for (int32_t q = a + l; q < b; q += kSG) {
         const int32_t c = color[order[rank_at[q]]];
         if (c >= 0 && c < words * 32) atomicOr(&bits[c >> 5], 1u << (c & 31));
       }
@@ -270,17 +290,20 @@ __global__ __launch_bounds__(kBlock) void k_mex_flat(const int32_t *Fp, const in
 }
 
 // Small frontier, second pass: one workgroup per frontier column takes the
-// lowest clear bit of its bitmap, then clears the words it read.
-__global__ __launch_bounds__(kBlock) void k_mex_pick(const int32_t *Fp, const int32_t *front,
+// lowest clear bit of its bitmap, then clears the words it read.  The last
+// workgroup to finish (by a ticket) also ends the round: the snapshot of
+// the largest colour for the next round's mex, the running count of
+// coloured columns, and a zero count for the round after next (`fc`, this
+// round's frontier counter, read by no later kernel of the round).
+__global__ __launch_bounds__(kBlock) void k_mex_pick(int32_t *Fp, const int32_t *front,
                                                       int32_t *color, int32_t *ctl,
                                                       uint32_t *gbits) {
   __shared__ int32_t best;
   const int32_t F = *Fp;
-  if (F > kFlatMax) return;
   const int32_t maxc = ctl[1];
   int32_t words = (maxc + 2 + 31) / 32;
   if (words > kMexWords) words = kMexWords;
-  for (int32_t f = blockIdx.x; f < F; f += gridDim.x) {
+  for (int32_t f = blockIdx.x; F <= kFlatMax && f < F; f += gridDim.x) {
     uint32_t *bits = gbits + int64_t(f) * kMexWords;
     if (threadIdx.x == 0) best = INT32_MAX;
     __syncthreads();
@@ -306,15 +329,100 @@ __global__ __launch_bounds__(kBlock) void k_mex_pick(const int32_t *Fp, const in
     for (int32_t u = threadIdx.x; u < words; u += kBlock) bits[u] = 0u;
     __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&ctl[6], 1) == int32_t(gridDim.x) - 1) {  // every other workgroup is done
+      ctl[6] = 0;
+      ctl[1] = atomicAdd(&ctl[3], 0);
+      ctl[5] += F;
+      *Fp = 0;
+    }
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_front_nnz(const int32_t *Fp, const int64_t *col_ptr,
-                                                       const int32_t *front, int32_t *cnt) {
+// Offsets of the frontier columns' entries, foff[0..F] (exclusive scan of
+// their nonzero counts), in three passes that read F from the device and
+// touch only the frontier: tile sums, scan of the tile sums, apply.
+constexpr int kFItems = 8;
+constexpr int kFTile = kBlock * kFItems;
+
+__device__ __forceinline__ int32_t front_block_scan(int32_t v, int32_t &total) {
+  __shared__ int32_t wsum[kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t t = __shfl_up(x, off, kWave);
+    if (lane >= off) x += t;
+  }
+  if (lane == kWave - 1) wsum[wid] = x;
+  __syncthreads();
+  int32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    if (w < wid) pre += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+__device__ __forceinline__ int32_t front_len(const int32_t *front, const int64_t *col_ptr,
+                                             int64_t f, int32_t F) {
+  if (f >= F) return 0;
+  const int32_t j = front[f];
+  return int32_t(col_ptr[j + 1] - col_ptr[j]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fscan_tiles(const int32_t *Fp, const int32_t *front,
+                                                         const int64_t *col_ptr, int32_t *part) {
   const int32_t F = *Fp;
-  for (int64_t f = int64_t(blockIdx.x) * kBlock + threadIdx.x; f < F;
-       f += int64_t(gridDim.x) * kBlock) {
-    const int32_t j = front[f];
-    cnt[f] = int32_t(col_ptr[j + 1] - col_ptr[j]);
+  if (int64_t(blockIdx.x) * kFTile >= F) return;  // past the frontier (uniform per workgroup)
+  const int64_t base = int64_t(blockIdx.x) * kFTile + int64_t(threadIdx.x) * kFItems;
+  int32_t sum = 0;
+#pragma unroll
+  for (int u = 0; u < kFItems; ++u) sum += front_len(front, col_ptr, base + u, F);
+  int32_t tot;
+  front_block_scan(sum, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fscan_part(const int32_t *Fp, int32_t *part) {
+  const int64_t np = (int64_t(*Fp) + kFTile - 1) / kFTile;
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < np; b0 += kBlock) {
+    const int64_t i = b0 + threadIdx.x;
+    const int32_t v = i < np ? part[i] : 0;
+    int32_t tot;
+    const int32_t ex = front_block_scan(v, tot);
+    if (i < np) part[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[np] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fscan_apply(const int32_t *Fp, const int32_t *front,
+                                                         const int64_t *col_ptr,
+                                                         const int32_t *part, int32_t *foff) {
+  const int32_t F = *Fp;
+  const int64_t np = (int64_t(F) + kFTile - 1) / kFTile;
+  if (blockIdx.x == 0 && threadIdx.x == 0) foff[F] = part[np];
+  if (int64_t(blockIdx.x) >= np) return;
+  const int64_t base = int64_t(blockIdx.x) * kFTile + int64_t(threadIdx.x) * kFItems;
+  int32_t v[kFItems];
+  int32_t sum = 0;
+#pragma unroll
+  for (int u = 0; u < kFItems; ++u) {
+    v[u] = front_len(front, col_ptr, base + u, F);
+    sum += v[u];
+  }
+  int32_t tot;
+  int32_t ex = front_block_scan(sum, tot) + part[blockIdx.x];
+#pragma unroll
+  for (int u = 0; u < kFItems; ++u) {
+    if (base + u < F) foff[base + u] = ex;
+    ex += v[u];
   }
 }
 
@@ -326,73 +434,85 @@ __global__ __launch_bounds__(kBlock) void k_front_nnz(const int32_t *Fp, const i
 // count to zero puts the column in the next frontier.
 constexpr int kHash = 2048;
 constexpr int kProbe = 8;
-__global__ __launch_bounds__(kBlock) void k_decrement(const int32_t *Fp, const int64_t *col_ptr,
-                                                       const int32_t *row_idx, const int32_t *front,
-                                                       const int32_t *foff, const int32_t *row_ptr,
-                                                       const int32_t *rank_at,
-                                                       const int32_t *pos_in_row,
-                                                       const int32_t *order, int32_t *count,
-                                                       int32_t *next, int32_t *next_cnt) {
-  __shared__ int32_t hkey[kHash];
-  __shared__ int32_t hcnt[kHash];
+__device__ void decrement_blocks(int64_t vb, int64_t nvb, int32_t *hkey, int32_t *hcnt,
+                                 const int32_t *Fp, const int64_t *col_ptr, const int32_t *row_idx,
+                                 const int32_t *front, const int32_t *foff, const int32_t *row_ptr,
+                                 const int32_t *rank_at, const int32_t *pos_in_row,
+                                 const int32_t *order, int32_t *count, int32_t *next,
+                                 int32_t *next_cnt) {
   const int32_t F = *Fp;
   const int32_t total = foff[F];
-  if (int64_t(blockIdx.x) * kBlock >= total) return;  // no entries for this workgroup
+  constexpr int EPB = kBlock / kSG;  // entries per workgroup and pass
+  if (vb * EPB >= total) return;  // no entries for this workgroup
   for (int32_t u = threadIdx.x; u < kHash; u += kBlock) {
     hkey[u] = -1;
     hcnt[u] = 0;
   }
   __syncthreads();
-  for (int64_t base = int64_t(blockIdx.x) * kBlock; base < total;
-       base += int64_t(gridDim.x) * kBlock) {
-    const int64_t t = base + threadIdx.x;
-    if (t < total) {
-      int32_t lo = 0, hi = F;  // find f with foff[f] <= t < foff[f+1]
-      while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (foff[mid] <= t) lo = mid; else hi = mid;
-      }
-      const int32_t j = front[lo];
-      const int64_t e = col_ptr[j] + (t - foff[lo]);
-      const int32_t r = row_idx[e];
-      const int32_t b = row_ptr[r + 1];
-      for (int32_t q = row_ptr[r] + pos_in_row[e] + 1; q < b; ++q) {
-        const int32_t j2 = order[rank_at[q]];
-        uint32_t h = (uint32_t(j2) * 2654435761u) & (kHash - 1);
-        bool done = false;
-        for (int p = 0; p < kProbe && !done; ++p, h = (h + 1) & (kHash - 1)) {
-          const int32_t prev = atomicCAS(&hkey[h], -1, j2);
-          if (prev == -1 || prev == j2) {
-            atomicAdd(&hcnt[h], 1);
-            done = true;
-          }
+  const int sub = int(threadIdx.x) / kSG, l = int(threadIdx.x) % kSG;
+  for (int64_t t = vb * EPB + sub; t < total; t += nvb * EPB) {
+    int32_t lo = 0, hi = F;  // find f with foff[f] <= t < foff[f+1]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (foff[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int32_t j = front[lo];
+    const int64_t e = col_ptr[j] + (t - foff[lo]);
+    const int32_t r = row_idx[e];
+    const int32_t b = row_ptr[r + 1];
+    for (int32_t q = row_ptr[r] + pos_in_row[e] + 1 + l; q < b; q += kSG) {
+      const int32_t j2 = order[rank_at[q]];
+      uint32_t h = (uint32_t(j2) * 2654435761u) & (kHash - 1);
+      bool done = false;
+      for (int p = 0; p < kProbe && !done; ++p, h = (h + 1) & (kHash - 1)) {
+        const int32_t prev = atomicCAS(&hkey[h], -1, j2);
+        if (prev == -1 || prev == j2) {
+          atomicAdd(&hcnt[h], 1);
+          done = true;
         }
-        if (!done && atomicSub(&count[j2], 1) == 1) next[atomicAdd(next_cnt, 1)] = j2;
       }
+      if (!done && atomicSub(&count[j2], 1) == 1) next[atomicAdd(next_cnt, 1)] = j2;
     }
-    __syncthreads();
-    for (int32_t u = threadIdx.x; u < kHash; u += kBlock) {
-      const int32_t key = hkey[u];
-      if (key >= 0) {
-        const int32_t c = hcnt[u];
-        if (atomicSub(&count[key], c) == c) next[atomicAdd(next_cnt, 1)] = key;
-        hkey[u] = -1;
-        hcnt[u] = 0;
-      }
+  }
+  __syncthreads();
+  for (int32_t u = threadIdx.x; u < kHash; u += kBlock) {
+    const int32_t key = hkey[u];
+    if (key >= 0) {
+      const int32_t c = hcnt[u];
+      if (atomicSub(&count[key], c) == c) next[atomicAdd(next_cnt, 1)] = key;
     }
-    __syncthreads();
   }
 }
 
-// End of a round: snapshot of the largest colour for the next mex, running
-// count of coloured columns, and a zero count for the round after next.
-__global__ void k_round_end(int32_t *ctl, const int32_t *Fp, int32_t *clear_cnt) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ctl[1] = ctl[3];
-    ctl[5] += *Fp;
-    *clear_cnt = 0;
+// One launch per round for the three independent jobs of the frontier:
+// workgroups [0, gm) colour a large frontier one column per workgroup,
+// [gm, gm + gf) spread a small frontier's entries (k_mex_pick finishes it),
+// and the rest update the readiness counts.  Colouring reads only colours
+// of earlier rounds and the counts are not read by it, so the jobs do not
+// depend on each other.  The LDS buffer serves the role a workgroup takes.
+__global__ __launch_bounds__(kBlock) void k_round_work(
+    const int32_t *Fp, const int64_t *col_ptr, const int32_t *row_idx, const int32_t *front,
+    const int32_t *foff, const int32_t *row_ptr, const int32_t *rank_at, const int32_t *pos_in_row,
+    const int32_t *order, int32_t *color, int32_t *ctl, uint32_t *gbits, int32_t *count,
+    int32_t *next, int32_t *next_cnt, int32_t gm, int32_t gf) {
+  __shared__ uint32_t lds[kMexWords];  // mex bitmap, or the decrement hash (2 x kHash ints)
+  __shared__ int32_t best;
+  static_assert(2 * kHash <= kMexWords, "hash table fits the bitmap buffer");
+  const int64_t b = blockIdx.x;
+  if (b < gm) {
+    mex_blocks(b, gm, lds, best, Fp, col_ptr, row_idx, front, row_ptr, rank_at, pos_in_row,
+               order, color, ctl);
+  } else if (b < gm + gf) {
+    mex_flat_blocks(b - gm, gf, lds, Fp, foff, front, col_ptr, row_idx, row_ptr, rank_at,
+                    pos_in_row, order, color, ctl, gbits);
+  } else {
+    int32_t *h = reinterpret_cast<int32_t *>(lds);
+    decrement_blocks(b - gm - gf, int64_t(gridDim.x) - gm - gf, h, h + kHash, Fp, col_ptr,
+                     row_idx, front, foff, row_ptr, rank_at, pos_in_row, order, count, next,
+                     next_cnt);
   }
 }
+
 
 static unsigned g1(int64_t m, unsigned cap = 4096) {
   int64_t b = (m + kBlock - 1) / kBlock;
@@ -454,32 +574,29 @@ int color_run(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws_
   // once per kRoundsPerSync rounds.  Rounds past the last frontier find an
   // empty one and do nothing.
   constexpr int kRoundsPerSync = 32;
-  st = fill_i32(w.fcnt, k + 1, 0, s);  // the scan covers all k entries; those past F stay finite
-  if (st) return st;
-  const unsigned mex_grid = 4096;  // grid-stride over the frontier (one column per wave or block)
+  // workgroups of the three jobs of k_round_work
+  constexpr int32_t kMexGrid = 4096, kFlatGrid = 2048, kDecGrid = 8192;
   int32_t *cur = w.front_a, *nxt = w.front_b;
   int32_t ctl_host[8];
   int64_t round = 0;
   for (;;) {
     for (int r = 0; r < kRoundsPerSync; ++r, ++round) {
       int32_t *fc = w.ctl + ((round & 1) ? 4 : 0), *fn = w.ctl + ((round & 1) ? 0 : 4);
-      hipLaunchKernelGGL(k_front_nnz, dim3(g1(k)), dim3(kBlock), 0, s, fc, X->col_ptr, cur,
-                         w.fcnt);
-      st = scan_exclusive(w.fcnt, w.foff, k, w.scan_part, s);  // entries before F count
-      if (st) return st;
-      // the colours of the frontier: one of the two forms runs, by its size
-      hipLaunchKernelGGL(k_mex, dim3(mex_grid), dim3(kBlock), 0, s, fc, X->col_ptr, X->row_idx,
-                         cur, w.row_ptr, w.rank_at, w.pos_in_row, w.order, color, w.ctl);
-      hipLaunchKernelGGL(k_mex_flat, dim3(2048), dim3(kBlock), 0, s, fc, w.foff, cur, X->col_ptr,
-                         X->row_idx, w.row_ptr, w.rank_at, w.pos_in_row, w.order, color, w.ctl,
-                         w.gbits);
+      const unsigned ft = unsigned((k + kFTile - 1) / kFTile);  // tiles of the largest frontier
+      hipLaunchKernelGGL(k_fscan_tiles, dim3(ft), dim3(kBlock), 0, s, fc, cur, X->col_ptr,
+                         w.scan_part);
+      hipLaunchKernelGGL(k_fscan_part, dim3(1), dim3(kBlock), 0, s, fc, w.scan_part);
+      hipLaunchKernelGGL(k_fscan_apply, dim3(ft), dim3(kBlock), 0, s, fc, cur, X->col_ptr,
+                         w.scan_part, w.foff);
+      // the frontier's colours (one of the two forms, by its size) and the
+      // readiness counts in one launch; then the small form's pick, which
+      // also ends the round
+      hipLaunchKernelGGL(k_round_work, dim3(kMexGrid + kFlatGrid + kDecGrid), dim3(kBlock), 0, s,
+                         fc, X->col_ptr, X->row_idx, cur, w.foff, w.row_ptr, w.rank_at,
+                         w.pos_in_row, w.order, color, w.ctl, w.gbits, w.count, nxt, fn,
+                         kMexGrid, kFlatGrid);
       hipLaunchKernelGGL(k_mex_pick, dim3(kFlatMax), dim3(kBlock), 0, s, fc, cur, color, w.ctl,
                          w.gbits);
-      hipLaunchKernelGGL(k_decrement, dim3(g1(nnz > 0 ? nnz : 1, 8192)), dim3(kBlock), 0, s, fc,
-                         X->col_ptr, X->row_idx, cur, w.foff, w.row_ptr, w.rank_at, w.pos_in_row,
-                         w.order, w.count, nxt, fn);
-      // this round's counter is next written as the frontier two rounds on
-      hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, w.ctl, fc, fc);
       int32_t *t = cur;
       cur = nxt;
       nxt = t;
