@@ -574,8 +574,10 @@ int color_run(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws_
   // once per kRoundsPerSync rounds.  Rounds past the last frontier find an
   // empty one and do nothing.
   constexpr int kRoundsPerSync = 32;
-  // workgroups of the three jobs of k_round_work
-  constexpr int32_t kMexGrid = 4096, kFlatGrid = 2048, kDecGrid = 8192;
+  // workgroups of the three jobs of k_round_work (they stride over their
+  // work; on the Lasso workload 2-8x larger grids were slower, as most
+  // rounds are small and every workgroup is dispatched)
+  constexpr int32_t kMexGrid = 512, kFlatGrid = 256, kDecGrid = 1024;
   int32_t *cur = w.front_a, *nxt = w.front_b;
   int32_t ctl_host[8];
   int64_t round = 0;
