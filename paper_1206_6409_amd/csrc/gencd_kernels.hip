@@ -711,20 +711,16 @@ __global__ __launch_bounds__(kBlock) void k_refresh(int64_t n, int32_t loss, con
 }
 
 // Finalise the split columns among positions [lo, hi) of the window: find
-// them in parallel, then each wave of the NT-thread workgroup takes one and
-// sums its partials (in piece order, as Update does) with shuffles, and
-// writes delta, phi (and g).
+// them in parallel (kSplitCap * NT slots, so a 4096-position window is
+// searched in one go), then each wave of the NT-thread workgroup takes one
+// and sums its partials (in piece order, as Update does) with shuffles, and
+// writes delta, phi (and g).  smulti holds kSplitCap * NT entries.
+constexpr int kSplitCap = 4;
 template <int NT>
 __device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_t P0,
                                int32_t *smulti, int32_t *nmulti) {
   const int lane = int(threadIdx.x) & (kWave - 1);
-  for (int64_t c0 = lo; c0 < hi; c0 += NT) {
-    if (threadIdx.x == 0) *nmulti = 0;
-    __syncthreads();
-    const int64_t pp = c0 + threadIdx.x;
-    if (pp < hi && a.loff[pp + 1] - a.loff[pp] > 1) smulti[atomicAdd(nmulti, 1)] = int32_t(pp);
-    __syncthreads();
-    const int32_t cnt = *nmulti;
+  auto process = [&](int32_t cnt) {
     for (int32_t m = int32_t(threadIdx.x) / kWave; m < cnt; m += NT / kWave) {
       const int32_t p = smulti[m];
       const int32_t pf = a.loff[p], np = a.loff[p + 1] - pf;
@@ -738,8 +734,23 @@ __device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_
         if (a.gout) a.gout[p - P0] = g;
       }
     }
+  };
+  if (threadIdx.x == 0) *nmulti = 0;
+  __syncthreads();
+  for (int64_t c0 = lo; c0 < hi; c0 += NT) {
+    if (*nmulti + NT > kSplitCap * NT) {  // no room for a further NT: finalise these first
+      const int32_t cnt = *nmulti;
+      process(cnt);
+      __syncthreads();
+      if (threadIdx.x == 0) *nmulti = 0;
+      __syncthreads();
+    }
+    const int64_t pp = c0 + threadIdx.x;
+    if (pp < hi && a.loff[pp + 1] - a.loff[pp] > 1) smulti[atomicAdd(nmulti, 1)] = int32_t(pp);
     __syncthreads();
   }
+  process(*nmulti);
+  __syncthreads();
 }
 
 // Accept for Thread-Greedy / Greedy (section 2.3): in each block of B
@@ -751,7 +762,7 @@ __device__ void finalize_split(const IterArgs &a, int64_t lo, int64_t hi, int32_
 __global__ __launch_bounds__(kBlock) void k_accept(IterArgs a, int64_t B, int32_t chunk) {
   __shared__ float sphi[kBlock];
   __shared__ int32_t spos[kBlock];
-  __shared__ int32_t smulti[kBlock];
+  __shared__ int32_t smulti[kSplitCap * kBlock];
   __shared__ int32_t nmulti;
   int32_t P0, P1;
   window_of(a, P0, P1);
@@ -865,31 +876,65 @@ __device__ __forceinline__ unsigned long long top_key(float phi, int64_t off) {
   return (static_cast<unsigned long long>(u) << 32) | static_cast<unsigned long long>(off);
 }
 
+// Keys of a window of at most kTopKeys positions are computed once and held
+// in registers (kTopKeys / kTopThreads per thread); larger windows re-read
+// phi in every pass.  Each wave counts into its own LDS histogram: near
+// the optimum most proxies are exactly 0 and share one bin, and a single
+// histogram would serialise their atomics.
+constexpr int kTopPer = 4;
+constexpr int64_t kTopKeys = int64_t(kTopThreads) * kTopPer;
+constexpr int kTopWaves = kTopThreads / kWave;
+
 __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
-  __shared__ int32_t smulti[kTopThreads];
+  __shared__ int32_t smulti[kSplitCap * kTopThreads];
   __shared__ int32_t nmulti;
+  __shared__ uint32_t whist[kTopWaves][256];
   __shared__ uint32_t hist[256];
   __shared__ unsigned long long s_prefix;
   __shared__ int64_t s_rank, s_bincnt;
-  __shared__ unsigned long long s_cnt[2][kTopThreads / kWave];
+  __shared__ unsigned long long s_cnt[2][kTopWaves];
   int32_t P0, P1;
   window_of(a, P0, P1);
   const int64_t m = int64_t(P1) - P0;
   if (m <= 0) return;
   finalize_split<kTopThreads>(a, P0, P1, P0, smulti, &nmulti);
   const int64_t K = a.accept_top < m ? a.accept_top : m;
+  const bool cached = m <= kTopKeys;
+  unsigned long long kreg[kTopPer];
+#pragma unroll
+  for (int u = 0; u < kTopPer; ++u) {
+    const int64_t q = int64_t(threadIdx.x) + int64_t(u) * kTopThreads;
+    kreg[u] = (cached && q < m) ? top_key(a.phi[q], q) : ~0ull;
+  }
   if (threadIdx.x == 0) {
     s_prefix = 0ull;
     s_rank = K;  // 1-based rank of the wanted key among the candidates
   }
+  const int wv = int(threadIdx.x) / kWave;
   unsigned long long mask = 0ull;
   for (int shift = 56; shift >= 0; shift -= 8) {
-    if (threadIdx.x < 256) hist[threadIdx.x] = 0u;
+    for (int u = int(threadIdx.x); u < kTopWaves * 256; u += kTopThreads) (&whist[0][0])[u] = 0u;
     __syncthreads();
     const unsigned long long prefix = s_prefix;
-    for (int64_t q = threadIdx.x; q < m; q += kTopThreads) {
-      const unsigned long long key = top_key(a.phi[q], q);
-      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
+    if (cached) {
+#pragma unroll
+      for (int u = 0; u < kTopPer; ++u) {
+        const int64_t q = int64_t(threadIdx.x) + int64_t(u) * kTopThreads;
+        if (q < m && (kreg[u] & mask) == prefix)
+          atomicAdd(&whist[wv][(kreg[u] >> shift) & 255ull], 1u);
+      }
+    } else {
+      for (int64_t q = threadIdx.x; q < m; q += kTopThreads) {
+        const unsigned long long key = top_key(a.phi[q], q);
+        if ((key & mask) == prefix) atomicAdd(&whist[wv][(key >> shift) & 255ull], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+      uint32_t t = 0u;
+#pragma unroll
+      for (int w = 0; w < kTopWaves; ++w) t += whist[w][threadIdx.x];
+      hist[threadIdx.x] = t;
     }
     __syncthreads();
     if (threadIdx.x < kWave) {
@@ -932,8 +977,8 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
   }
   const unsigned long long kth = s_prefix;
   unsigned long long nnz = 0ull, cnt = 0ull;
-  for (int64_t q = threadIdx.x; q < m; q += kTopThreads) {
-    const bool take = top_key(a.phi[q], q) <= kth;
+  auto accept = [&](int64_t q, unsigned long long key) {
+    const bool take = key <= kth;
     a.acc[q] = take ? 1 : 0;
     if (take) {
       const int32_t j = a.col_of_pos[P0 + q];
@@ -945,6 +990,15 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
       nnz += static_cast<unsigned long long>(a.col_ptr[j + 1] - a.col_ptr[j]);
       cnt += 1ull;
     }
+  };
+  if (cached) {
+#pragma unroll
+    for (int u = 0; u < kTopPer; ++u) {
+      const int64_t q = int64_t(threadIdx.x) + int64_t(u) * kTopThreads;
+      if (q < m) accept(q, kreg[u]);
+    }
+  } else {
+    for (int64_t q = threadIdx.x; q < m; q += kTopThreads) accept(q, top_key(a.phi[q], q));
   }
   for (int off = kWave / 2; off > 0; off >>= 1) {
     nnz += __shfl_xor(nnz, off);
@@ -957,7 +1011,7 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long tn = 0ull, tc = 0ull;
-    for (int w = 0; w < kTopThreads / kWave; ++w) {
+    for (int w = 0; w < kTopWaves; ++w) {
       tn += s_cnt[0][w];
       tc += s_cnt[1][w];
     }
@@ -1444,11 +1498,15 @@ __global__ __launch_bounds__(kBlock) void k_check_zero(double *z64, int64_t n, d
   if (tid < 8) red[tid] = 0ull;
 }
 
+// With nb > 1 the products of the preset blocks are kept apart:
+// z64[row * nb + block of the column] (Block Shotgun's power iteration).
 template <int G, typename WT>
 __device__ __forceinline__ void spmv_piece(const int32_t *row_idx, const float *val, const int4 d,
-                                           const WT *w, double *z64, int lane) {
+                                           const WT *w, double *z64, int lane, int64_t nb = 1,
+                                           const int32_t *bcol = nullptr) {
   const double wj = double(w[d.y]);
   if (wj == 0.0) return;
+  const int64_t b = bcol ? int64_t(bcol[d.y]) : 0;
   const int64_t beg = desc_beg(d);
   const int32_t len = desc_len(d);
   for (int32_t base = 0; base < len; base += G * kUnroll) {
@@ -1462,25 +1520,26 @@ __device__ __forceinline__ void spmv_piece(const int32_t *row_idx, const float *
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-      if (ri[u] >= 0) atomicAdd(&z64[ri[u]], wj * double(vv[u]));
+      if (ri[u] >= 0) atomicAdd(&z64[int64_t(ri[u]) * nb + b], wj * double(vv[u]));
   }
 }
 
 // z64 += X w over all pieces (w float for the check, double for the
-// spectral-radius iteration)
+// spectral-radius iteration; nb > 1: per preset block, see spmv_piece)
 template <int GS, typename WT>
 __global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, const float *val,
                                                         const int4 *ds, int32_t ns,
                                                         const int4 *dl, int32_t nlp, int32_t nl_req,
-                                                        const WT *w, double *z64) {
+                                                        const WT *w, double *z64, int64_t nb = 1,
+                                                        const int32_t *bcol = nullptr) {
   const Roles r = roles(nl_req);
   if (r.wave < r.nl) {
     for (int64_t q = r.wave; q < nlp; q += r.nl)
-      spmv_piece<kWave, WT>(row_idx, val, dl[q], w, z64, r.wl);
+      spmv_piece<kWave, WT>(row_idx, val, dl[q], w, z64, r.wl, nb, bcol);
   } else {
     const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
     for (int64_t q = (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < ns; q += step)
-      spmv_piece<GS, WT>(row_idx, val, ds[q], w, z64, r.wl & (GS - 1));
+      spmv_piece<GS, WT>(row_idx, val, ds[q], w, z64, r.wl & (GS - 1), nb, bcol);
   }
 }
 
@@ -1511,9 +1570,11 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, cons
 
 template <int G>
 __device__ __forceinline__ void cols_piece(const int32_t *row_idx, const float *val, const int4 d,
-                                           const double *r64, double *g64, int lane) {
+                                           const double *r64, double *g64, int lane,
+                                           int64_t nb = 1, const int32_t *bcol = nullptr) {
   const int64_t beg = desc_beg(d);
   const int32_t len = desc_len(d);
+  const int64_t b = bcol ? int64_t(bcol[d.y]) : 0;
   double s = 0.0;
   for (int32_t base = 0; base < len; base += G * kUnroll) {
     int32_t ri[kUnroll];
@@ -1526,7 +1587,7 @@ __device__ __forceinline__ void cols_piece(const int32_t *row_idx, const float *
     }
     double rr[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) rr[u] = r64[ri[u] >= 0 ? ri[u] : 0];
+    for (int u = 0; u < kUnroll; ++u) rr[u] = r64[int64_t(ri[u] >= 0 ? ri[u] : 0) * nb + b];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       if (ri[u] >= 0) s += double(vv[u]) * rr[u];
@@ -1544,14 +1605,17 @@ template <int GS>
 __global__ __launch_bounds__(kBlock) void k_check_cols(const int32_t *row_idx, const float *val,
                                                         const int4 *ds, int32_t ns,
                                                         const int4 *dl, int32_t nlp, int32_t nl_req,
-                                                        const double *r64, double *g64) {
+                                                        const double *r64, double *g64,
+                                                        int64_t nb = 1,
+                                                        const int32_t *bcol = nullptr) {
   const Roles r = roles(nl_req);
   if (r.wave < r.nl) {
-    for (int64_t q = r.wave; q < nlp; q += r.nl) cols_piece<kWave>(row_idx, val, dl[q], r64, g64, r.wl);
+    for (int64_t q = r.wave; q < nlp; q += r.nl)
+      cols_piece<kWave>(row_idx, val, dl[q], r64, g64, r.wl, nb, bcol);
   } else {
     const int64_t step = (r.nwaves - r.nl) * (kWave / GS);
     for (int64_t q = (r.wave - r.nl) * (kWave / GS) + r.wl / GS; q < ns; q += step)
-      cols_piece<GS>(row_idx, val, ds[q], r64, g64, r.wl & (GS - 1));
+      cols_piece<GS>(row_idx, val, ds[q], r64, g64, r.wl & (GS - 1), nb, bcol);
   }
 }
 
@@ -1802,39 +1866,6 @@ __global__ __launch_bounds__(kBlock) void k_brho_init(int64_t k, int64_t n, int6
   for (int64_t t = tid; t < int64_t(iters) * nb; t += nt) hist[t] = 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_brho_spmv(const int64_t *col_ptr, const int32_t *row_idx,
-                                                       const float *val, const int32_t *base,
-                                                       int64_t k_live, const int32_t *bcol,
-                                                       int64_t nb, const double *x, double *bs) {
-  const int lane = int(threadIdx.x) & (kWave - 1);
-  const int64_t nw = int64_t(gridDim.x) * (kBlock / kWave);
-  for (int64_t q = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave; q < k_live; q += nw) {
-    const int32_t j = base[q];
-    const double xj = x[j];
-    if (xj == 0.0) continue;
-    const int64_t b = bcol[j];
-    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave)
-      atomicAdd(&bs[int64_t(row_idx[e]) * nb + b], double(val[e]) * xj);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_brho_cols(const int64_t *col_ptr, const int32_t *row_idx,
-                                                       const float *val, const int32_t *base,
-                                                       int64_t k_live, const int32_t *bcol,
-                                                       int64_t nb, const double *bs, double *u) {
-  const int lane = int(threadIdx.x) & (kWave - 1);
-  const int64_t nw = int64_t(gridDim.x) * (kBlock / kWave);
-  for (int64_t q = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave; q < k_live; q += nw) {
-    const int32_t j = base[q];
-    const int64_t b = bcol[j];
-    double acc = 0.0;
-    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave)
-      acc += double(val[e]) * bs[int64_t(row_idx[e]) * nb + b];
-    acc = group_sum<kWave>(acc);
-    if (lane == 0) u[j] = acc;
-  }
-}
-
 // ||D^{-1/2} U||^2 per block.  Each thread walks a contiguous run of preset
 // positions (blocks are contiguous runs), flushing its sum at every block
 // boundary.
@@ -1880,8 +1911,8 @@ __global__ __launch_bounds__(kBlock) void k_brho_scale(int64_t k, int64_t n, int
   for (int64_t i = tid; i < n * nb; i += nt) bs[i] = 0.0;
 }
 
-int launch_block_setup(const gencd_csc *X, const Ws &ws, int64_t k_live, uint64_t seed, int iters,
-                       hipStream_t s) {
+int launch_block_setup(const gencd_csc *X, int32_t n_short, int32_t n_lpieces, const Ws &ws,
+                       int64_t k_live, uint64_t seed, int iters, hipStream_t s) {
   const int64_t nb = ws.nblocks;
   if (nb < 1 || nb > k_live || iters < 1 || iters > kBlockRhoMaxIters) return GENCD_ERR_INVALID_ARG;
   int st = fill_i32(ws.bcol, X->k, -1, s);
@@ -1891,14 +1922,22 @@ int launch_block_setup(const gencd_csc *X, const Ws &ws, int64_t k_live, uint64_
   const int64_t nk = X->n * nb > X->k ? X->n * nb : X->k;
   hipLaunchKernelGGL(k_brho_init, dim3(grid_for(nk)), dim3(kBlock), 0, s, X->k, X->n, nb, k_live,
                      ws.bcol, ws.g64, ws.rho_dinv, ws.rho_x, ws.bs, ws.bhist, iters);
-  const unsigned wg = waves_grid(k_live, 16384);
+  // the products by pieces, as in the check: a heavy column is spread over
+  // many waves instead of walked by one
+  unsigned blocks;
+  int32_t nl;
+  two_class_grid(n_short, n_lpieces, 8, &blocks, &nl);
   const unsigned rg = grid_for((k_live + kBrhoRun - 1) / kBrhoRun);
   for (int t = 0; t < iters; ++t) {
     double *ht = ws.bhist + int64_t(t) * nb;
-    hipLaunchKernelGGL(k_brho_spmv, dim3(wg), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
-                       ws.bbase, k_live, ws.bcol, nb, ws.rho_x, ws.bs);
-    hipLaunchKernelGGL(k_brho_cols, dim3(wg), dim3(kBlock), 0, s, X->col_ptr, X->row_idx, X->val,
-                       ws.bbase, k_live, ws.bcol, nb, ws.bs, ws.g64);
+    if (n_short + n_lpieces > 0) {
+      hipLaunchKernelGGL((k_check_spmv<8, double>), dim3(blocks), dim3(kBlock), 0, s, X->row_idx,
+                         X->val, ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, ws.rho_x,
+                         ws.bs, nb, ws.bcol);
+      hipLaunchKernelGGL(k_check_cols<8>, dim3(blocks), dim3(kBlock), 0, s, X->row_idx, X->val,
+                         ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, ws.bs, ws.g64, nb,
+                         ws.bcol);
+    }
     hipLaunchKernelGGL(k_brho_norm, dim3(rg), dim3(kBlock), 0, s, ws.bbase, k_live, ws.bcol,
                        ws.rho_dinv, ws.g64, ht);
     hipLaunchKernelGGL(k_brho_scale, dim3(grid_for(nk)), dim3(kBlock), 0, s, X->k, X->n, nb,

@@ -76,8 +76,8 @@ int launch_rho(const gencd_csc *X, int32_t n_short, int32_t n_lpieces, const Ws 
 // Block Shotgun: preset blocks (base order, block of every column) and the
 // per-block power iteration; needs the column sums of squares in ws.g64.
 // Squared norms land in ws.bhist[t][b].
-int launch_block_setup(const gencd_csc *X, const Ws &ws, int64_t k_live, uint64_t seed, int iters,
-                       hipStream_t s);
+int launch_block_setup(const gencd_csc *X, int32_t n_short, int32_t n_lpieces, const Ws &ws,
+                       int64_t k_live, uint64_t seed, int iters, hipStream_t s);
 // Per-epoch order of Block Shotgun (col_of_pos, windows win_off[0..T]).
 int launch_block_order(const Ws &w, int64_t k_live, uint64_t seed, const int64_t *epoch, int64_t T,
                        hipStream_t s);

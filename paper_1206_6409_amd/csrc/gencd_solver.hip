@@ -265,7 +265,8 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
     // preset blocks and P_b* = floor(k_b / (2 rho_b)) clamped to [1, k_b]
     const int64_t nb = std::min<int64_t>(nblocks, out->k_live);
     out->ws.nblocks = nb;
-    st = launch_block_setup(X, out->ws, out->k_live, p ? p->seed : 0, block_iters, s);
+    st = launch_block_setup(X, out->n_short, out->n_lpieces, out->ws, out->k_live,
+                            p ? p->seed : 0, block_iters, s);
     if (st) return st;
     std::vector<double> h(size_t(block_iters) * size_t(nb));
     GENCD_HIP(hipMemcpyAsync(h.data(), w.bhist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
