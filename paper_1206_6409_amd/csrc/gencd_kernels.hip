@@ -885,6 +885,29 @@ constexpr int kTopPer = 4;
 constexpr int64_t kTopKeys = int64_t(kTopThreads) * kTopPer;
 constexpr int kTopWaves = kTopThreads / kWave;
 
+// Exclusive prefix sum over the kTopThreads threads of the workgroup.
+__device__ __forceinline__ int32_t top_block_scan(int32_t v, int32_t &total) {
+  __shared__ int32_t wsum[kTopWaves];
+  const int lane = int(threadIdx.x) & (kWave - 1), wid = int(threadIdx.x) / kWave;
+  int32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t t = __shfl_up(x, off, kWave);
+    if (lane >= off) x += t;
+  }
+  if (lane == kWave - 1) wsum[wid] = x;
+  __syncthreads();
+  int32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kTopWaves; ++w) {
+    if (w < wid) pre += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
 __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
   __shared__ int32_t smulti[kSplitCap * kTopThreads];
   __shared__ int32_t nmulti;
@@ -911,6 +934,7 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
     s_rank = K;  // 1-based rank of the wanted key among the candidates
   }
   const int wv = int(threadIdx.x) / kWave;
+  bool by_rank = false;  // uniform: every thread reads the same shared values
   unsigned long long mask = 0ull;
   for (int shift = 56; shift >= 0; shift -= 8) {
     for (int u = int(threadIdx.x); u < kTopWaves * 256; u += kTopThreads) (&whist[0][0])[u] = 0u;
@@ -968,17 +992,24 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
     mask |= 255ull << shift;
     __syncthreads();
     // after the proxy half of the key: if every candidate left is taken,
-    // the positions need no further passes
-    if (shift == 32 && s_rank == s_bincnt) {
-      if (threadIdx.x == 0) s_prefix |= 0xFFFFFFFFull;
-      __syncthreads();
-      break;
+    // the positions need no further passes; with cached keys, the ties of
+    // the K-th proxy are resolved by position rank (the low half of the key
+    // is the position) instead of four more passes
+    if (shift == 32) {
+      if (s_rank == s_bincnt) {
+        if (threadIdx.x == 0) s_prefix |= 0xFFFFFFFFull;
+        __syncthreads();
+        break;
+      }
+      if (cached) {
+        by_rank = true;
+        break;
+      }
     }
   }
   const unsigned long long kth = s_prefix;
   unsigned long long nnz = 0ull, cnt = 0ull;
-  auto accept = [&](int64_t q, unsigned long long key) {
-    const bool take = key <= kth;
+  auto accept = [&](int64_t q, bool take) {
     a.acc[q] = take ? 1 : 0;
     if (take) {
       const int32_t j = a.col_of_pos[P0 + q];
@@ -991,14 +1022,30 @@ __global__ __launch_bounds__(kTopThreads) void k_accept_top(IterArgs a) {
       cnt += 1ull;
     }
   };
-  if (cached) {
+  if (by_rank) {
+    // every key whose proxy half is below the K-th one, and the first s_rank
+    // (in position order) of those equal to it
+    const uint32_t ph = uint32_t(kth >> 32);
+    const int64_t rk = s_rank;
+    int64_t before = 0;  // tied keys in the earlier segments of positions
 #pragma unroll
     for (int u = 0; u < kTopPer; ++u) {
       const int64_t q = int64_t(threadIdx.x) + int64_t(u) * kTopThreads;
-      if (q < m) accept(q, kreg[u]);
+      const uint32_t kh = uint32_t(kreg[u] >> 32);
+      const bool tie = q < m && kh == ph;
+      int32_t seg;
+      const int32_t ex = top_block_scan(tie ? 1 : 0, seg);
+      if (q < m) accept(q, kh < ph || (tie && before + ex < rk));
+      before += seg;
+    }
+  } else if (cached) {
+#pragma unroll
+    for (int u = 0; u < kTopPer; ++u) {
+      const int64_t q = int64_t(threadIdx.x) + int64_t(u) * kTopThreads;
+      if (q < m) accept(q, kreg[u] <= kth);
     }
   } else {
-    for (int64_t q = threadIdx.x; q < m; q += kTopThreads) accept(q, top_key(a.phi[q], q));
+    for (int64_t q = threadIdx.x; q < m; q += kTopThreads) accept(q, top_key(a.phi[q], q) <= kth);
   }
   for (int off = kWave / 2; off > 0; off >>= 1) {
     nnz += __shfl_xor(nnz, off);

@@ -120,3 +120,38 @@ def test_divergence_guard_halves_the_selection_and_converges(flags):
     res = _solve(P, lam, tol=1e-7, rule=G.SHOTGUN, select_size=k, flags=flags)
     assert res.stats["select_size"] < k  # the guard fired
     _assert_optimum(P, lam, res, Xo, ref, kkt=1e-7)
+
+
+@pytest.mark.parametrize("m,K,neg", [(700, 64, 0), (4096, 300, 10), (3000, 1, 0), (4096, 4096, 5)])
+def test_top_greedy_ties_go_to_the_lowest_positions(m, K, neg):
+    """At lambda >= lambda_max from w = 0 every proxy is exactly 0; a few
+    columns are then made to propose by a nonzero start.  Top-Greedy takes
+    the proposals with phi < 0 and, among the tied zeros, the lowest window
+    positions, whatever the number of ties."""
+    print("CASE top-greedy ties", m, K, neg, flush=True)
+    P = synth.c2_zipf_logistic(scale=0.02)
+    Xo = O.Matrix.of(P)
+    lam = 2.0 * O.lambda_max(Xo, P.y, P.loss)
+    live = np.nonzero(np.diff(P.col_ptr) > 0)[0]
+    rng = np.random.default_rng(3)
+    J = rng.choice(live, size=min(m, live.size), replace=False).astype(np.int32)
+    m = J.size
+    w = np.zeros(P.k, dtype=np.float32)
+    w[J[rng.choice(m, size=neg, replace=False)]] = 0.5  # these propose moving back to 0
+    oc = O.check(Xo, P.y, P.loss, 0.0, w.astype(np.float64))
+    z_hi = oc.z.astype(np.float32)
+    z_lo = (oc.z - z_hi.astype(np.float64)).astype(np.float32)
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    params = G.make_params(P.loss, lam, rule=G.TOP_GREEDY, select_size=m, block=K)
+    res = G.step(X, y, params, torch.as_tensor(J, device=DEV), torch.as_tensor(w, device=DEV),
+                 torch.as_tensor(z_hi, device=DEV), torch.as_tensor(z_lo, device=DEV))
+    torch.cuda.synchronize()
+    acc = res.accepted.cpu().numpy()
+    phi = res.phi.cpu().numpy()
+    assert acc.sum() == min(K, m)
+    below = np.nonzero(phi < 0)[0]
+    assert below.size == neg and np.all(acc[below] == 1)
+    zeros = np.nonzero(phi == 0)[0]
+    take = min(K, m) - below.size
+    assert np.array_equal(np.nonzero(acc[zeros])[0], np.arange(take))  # the first tied positions
