@@ -211,6 +211,7 @@ struct Ws {
   double *z64, *r64;     // [n]
   double *g64;           // [k]
   double *red;           // [16] reductions, counters, flags; [12] epoch counter
+  double *rrep;          // [kChkRep * 16] replicas of the check's reductions, one line each
   // spectral-radius estimate (only when |J| is chosen from it, or blocks)
   double *rho_dinv;      // [k] 1/||X_j|| (0 for empty columns)
   double *rho_x;         // [k] D^{-1/2} v, the scaled iterate
@@ -237,6 +238,11 @@ constexpr int kRhoMaxIters = 1024;  // cap for the standalone estimate
 constexpr int64_t kRhoSelectCap = 1024;  // automatic |J| is clamped to [1, this]
 constexpr int kBlockRhoMaxIters = 64;    // power iterations of the per-block estimate
 constexpr int64_t kMaxBlocks = 4096;     // preset blocks of Block Shotgun
+// The check's block results go to kChkRep replicas (workgroup b to replica
+// b mod kChkRep), each on its own 128-byte line: atomics on one address
+// serialise, so a single accumulator would cost one atomic per workgroup in
+// sequence.  The host folds the replicas when it reads the check.
+constexpr int kChkRep = 64;
 size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_max, bool rho,
                         int64_t nblocks, void *base, Ws *ws);
 size_t scan_partials_for(int64_t len);

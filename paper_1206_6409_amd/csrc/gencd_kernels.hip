@@ -1537,12 +1537,21 @@ int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int6
 // duality gap (and the FP32 re-sync z_hi + z_lo = z64)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_check_zero(double *z64, int64_t n, double *g64,
-                                                        int64_t k, unsigned long long *red) {
+                                                        int64_t k, unsigned long long *red,
+                                                        unsigned long long *rep) {
   const int64_t tid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t nt = int64_t(gridDim.x) * kBlock;
   for (int64_t i = tid; i < n; i += nt) z64[i] = 0.0;
   for (int64_t j = tid; j < k; j += nt) g64[j] = 0.0;
   if (tid < 8) red[tid] = 0ull;
+  for (int64_t i = tid; i < int64_t(kChkRep) * 16; i += nt) rep[i] = 0ull;
+}
+
+static_assert(kChkRep == kWave, "k_check_dual folds the replicas with one wave");
+
+// This workgroup's replica line of the check reductions.
+__device__ __forceinline__ unsigned long long *rep_line(unsigned long long *rep) {
+  return rep + (blockIdx.x % kChkRep) * 16;
 }
 
 // With nb > 1 the products of the preset blocks are kept apart:
@@ -1592,7 +1601,7 @@ __global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, c
 
 __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, const float *y,
                                                         const double *z64, double *r64,
-                                                        float4 *zs, double *red) {
+                                                        float4 *zs, unsigned long long *rep) {
   __shared__ double sred[kBlock];
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -1612,7 +1621,7 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, cons
     if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(&red[0], sred[0]);
+  if (threadIdx.x == 0) atomicAdd(reinterpret_cast<double *>(rep_line(rep)), sred[0]);
 }
 
 template <int G>
@@ -1668,7 +1677,7 @@ __global__ __launch_bounds__(kBlock) void k_check_cols(const int32_t *row_idx, c
 
 __global__ __launch_bounds__(kBlock) void k_check_kkt(int64_t k, double *g64, const float *w,
                                                        double lam, double inv_n,
-                                                       unsigned long long *red) {
+                                                       unsigned long long *rep) {
   __shared__ double smax[kBlock], sl1[kBlock], sgm[kBlock];
   __shared__ unsigned long long snz[kBlock];
   double vmax = 0.0, l1 = 0.0, gmax = 0.0;
@@ -1721,6 +1730,7 @@ __global__ __launch_bounds__(kBlock) void k_check_kkt(int64_t k, double *g64, co
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    unsigned long long *red = rep_line(rep);
     double m = smax[0];
     unsigned long long bits = (m != m) ? 0x7FF8000000000000ull : __double_as_longlong(m);
     atomicMax(&red[2], bits);  // non-negative doubles order like their bit patterns
@@ -1735,9 +1745,20 @@ __global__ __launch_bounds__(kBlock) void k_check_kkt(int64_t k, double *g64, co
 // scale s = min(1, lambda / |g|_inf) uses the maximum of the previous pass).
 __global__ __launch_bounds__(kBlock) void k_check_dual(int64_t n, int loss, const float *y,
                                                         const double *r64, double lam,
-                                                        unsigned long long *red) {
+                                                        unsigned long long *rep) {
   __shared__ double sred[kBlock];
-  const double gm = __longlong_as_double((long long)red[4]);
+  __shared__ unsigned long long sgm;
+  if (threadIdx.x < kWave) {  // |g|_inf: the maximum over the replicas (kChkRep == kWave)
+    unsigned long long v = rep[threadIdx.x * 16 + 4];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(v, off);
+      v = o > v ? o : v;
+    }
+    if (threadIdx.x == 0) sgm = v;
+  }
+  __syncthreads();
+  const double gm = __longlong_as_double((long long)sgm);
   const double s = (gm > lam) ? lam / gm : 1.0;
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -1760,7 +1781,7 @@ __global__ __launch_bounds__(kBlock) void k_check_dual(int64_t n, int loss, cons
     if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(reinterpret_cast<double *>(&red[5]), sred[0]);
+  if (threadIdx.x == 0) atomicAdd(reinterpret_cast<double *>(rep_line(rep) + 5), sred[0]);
 }
 
 int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
@@ -1770,20 +1791,21 @@ int launch_check(const gencd_csc *X, const float *y, int loss, double lam, const
   unsigned blocks;
   int32_t nl;
   two_class_grid(n_short, n_lpieces, 8, &blocks, &nl);
+  unsigned long long *rep = reinterpret_cast<unsigned long long *>(ws.rrep);
   hipLaunchKernelGGL(k_check_zero, dim3(grid_for(nk)), dim3(kBlock), 0, s, ws.z64, X->n, ws.g64,
-                     X->k, red);
+                     X->k, red, rep);
   if (w && n_short + n_lpieces > 0)
     hipLaunchKernelGGL((k_check_spmv<8, float>), dim3(blocks), dim3(kBlock), 0, s, X->row_idx,
                        X->val, ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, w, ws.z64);
   hipLaunchKernelGGL(k_check_rows, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
-                     ws.z64, ws.r64, resync ? ws.zs : nullptr, ws.red);
+                     ws.z64, ws.r64, resync ? ws.zs : nullptr, rep);
   if (n_short + n_lpieces > 0)
     hipLaunchKernelGGL(k_check_cols<8>, dim3(blocks), dim3(kBlock), 0, s, X->row_idx, X->val,
                        ws.desc_all_s, n_short, ws.desc_all_l, n_lpieces, nl, ws.r64, ws.g64);
   hipLaunchKernelGGL(k_check_kkt, dim3(grid_for(X->k, 256)), dim3(kBlock), 0, s, X->k, ws.g64, w,
-                     lam, 1.0 / double(X->n), red);
+                     lam, 1.0 / double(X->n), rep);
   hipLaunchKernelGGL(k_check_dual, dim3(grid_for(X->n, 256)), dim3(kBlock), 0, s, X->n, loss, y,
-                     ws.r64, lam, red);
+                     ws.r64, lam, rep);
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
 

@@ -81,6 +81,7 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.r64 = c.take<double>(n);
   w.g64 = c.take<double>(k);
   w.red = c.take<double>(16);
+  w.rrep = c.take<double>(int64_t(kChkRep) * 16);
   if (rho || nblocks > 0) {
     w.rho_dinv = c.take<double>(k);
     w.rho_x = c.take<double>(k);
@@ -304,8 +305,24 @@ int run_check(const gencd_csc *X, const float *y, int loss, double lam, const fl
   int st = launch_check(X, y, loss, lam, w, su.n_short, su.n_lpieces, su.ws, resync, s);
   if (st) return st;
   Red r{};
+  // the replicas first (same stream, so read_red's wait covers both copies)
+  double rep[kChkRep * 16];
+  GENCD_HIP(hipMemcpyAsync(rep, su.ws.rrep, sizeof(rep), hipMemcpyDeviceToHost, s));
   st = read_red(su.ws, s, &r);
   if (st) return st;
+  r.loss_sum = r.l1 = r.dual_sum = 0.0;
+  r.kkt_bits = r.nnz_w = r.gmax_bits = 0ull;
+  for (int i = 0; i < kChkRep; ++i) {  // fold in replica order
+    const double *f = rep + i * 16;
+    unsigned long long u[6];
+    std::memcpy(u, f, sizeof(u));
+    r.loss_sum += f[0];
+    r.l1 += f[1];
+    r.kkt_bits = std::max(r.kkt_bits, u[2]);
+    r.nnz_w += u[3];
+    r.gmax_bits = std::max(r.gmax_bits, u[4]);
+    r.dual_sum += f[5];
+  }
   out->objective = r.loss_sum / double(X->n) + lam * r.l1;
   out->kkt = bits_to_double(r.kkt_bits);
   out->gap = out->objective - r.dual_sum / double(X->n);
