@@ -437,8 +437,12 @@ __global__ __launch_bounds__(kBlock) void k_list_counts(const int32_t *cols, int
     pos_counts(cols[p], all_soff, all_loff, sc[p], lc[p]);
 }
 
-// Descriptors of the order: each position's static descriptors, re-tagged
-// with the position (8 lanes per position for long columns).
+// Descriptors of the order: each position's static descriptor, re-tagged
+// with the position.  A thread takes a position; then the whole wave copies
+// the pieces of its long columns, one column at a time, so that a heavy
+// column's hundreds of pieces take a round or two of 64 x kUnroll loads
+// instead of a long serial loop on a few lanes.  The loop is uniform over
+// the wave (every lane runs the same bases).
 __global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos, int64_t m,
                                                         const int32_t *loff,
                                                         const int32_t *all_soff,
@@ -446,35 +450,46 @@ __global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos
                                                         const int4 *desc_all_s,
                                                         const int4 *desc_all_l, int4 *desc_s,
                                                         int4 *desc_l) {
-  constexpr int L = 8;
-  const int lane = threadIdx.x & (L - 1);
-  for (int64_t p = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / L; p < m;
-       p += int64_t(gridDim.x) * kBlock / L) {
-    const int32_t j = col_of_pos[p];
-    const int32_t sj = all_soff[j];
-    if (all_soff[j + 1] > sj) {  // short column
-      if (lane == 0) {
+  const int lane = int(threadIdx.x) & (kWave - 1);
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t base = int64_t(blockIdx.x) * kBlock + threadIdx.x - lane; base < m;
+       base += stride) {
+    const int64_t p = base + lane;
+    int32_t j = 0;
+    bool lng = false;
+    if (p < m) {
+      j = col_of_pos[p];
+      const int32_t sj = all_soff[j];
+      if (all_soff[j + 1] > sj) {  // short column
         int4 d = desc_all_s[sj];
         d.z = int32_t(p);
         desc_s[p] = d;
+      } else {
+        desc_s[p] = make_int4(0, j, int32_t(p), 0);  // long: length 0
+        lng = true;
       }
-      continue;
     }
-    if (lane == 0) desc_s[p] = make_int4(0, j, int32_t(p), 0);  // long: length 0
-    const int32_t a = loff[p], b = loff[p + 1], src = all_loff[j];
-    for (int32_t q0 = a; q0 < b; q0 += L * kUnroll) {
-      int4 d[kUnroll];
+    unsigned long long left = __ballot(lng);
+    while (left) {
+      const int g = __builtin_ctzll(left);  // a lane whose position is long
+      left &= left - 1;
+      const int64_t pg = base + g;
+      const int32_t jg = __shfl(j, g);
+      const int32_t a = loff[pg], b = loff[pg + 1], src = all_loff[jg];
+      for (int32_t q0 = a; q0 < b; q0 += kWave * kUnroll) {
+        int4 d[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t q = q0 + u * L + lane;
-        if (q < b) d[u] = desc_all_l[src + (q - a)];
-      }
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t q = q0 + u * kWave + lane;
+          if (q < b) d[u] = desc_all_l[src + (q - a)];
+        }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t q = q0 + u * L + lane;
-        if (q < b) {
-          d[u].z = int32_t(p);
-          desc_l[q] = d[u];
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t q = q0 + u * kWave + lane;
+          if (q < b) {
+            d[u].z = int32_t(pg);
+            desc_l[q] = d[u];
+          }
         }
       }
     }
@@ -523,7 +538,7 @@ static int order_tail(const Ws &w, int64_t m, const int32_t *win_off, int64_t S,
   int st = scan_exclusive(w.tmp_cnt2, w.loff, m, w.scan_part, s);
   if (st) return st;
   if (m > 0)
-    hipLaunchKernelGGL(k_order_desc, dim3(grid_for(m * 8)), dim3(kBlock), 0, s, w.col_of_pos, m,
+    hipLaunchKernelGGL(k_order_desc, dim3(grid_for(m)), dim3(kBlock), 0, s, w.col_of_pos, m,
                        w.loff, w.all_soff, w.all_loff, w.desc_all_s, w.desc_all_l, w.desc_s,
                        w.desc_l);
   hipLaunchKernelGGL(k_window_bounds, dim3(grid_for(T + 1)), dim3(kBlock), 0, s, w.loff, win_off,
