@@ -181,6 +181,8 @@ struct Ws {
   int32_t *all_soff;     // [k+1] short-column index of every column (natural order)
   int32_t *all_loff;     // [k+1] long-piece offsets of every column
   int4 *desc_all_s;      // [k] short-column descriptors, natural order
+  int4 *live_rec;        // [k] per live index: the short descriptor, or for a long
+                         //     column {first piece, column, pieces, 0}
   int4 *desc_all_l;      // [max_lpieces] long-piece descriptors, natural order
   int32_t *tmp_cnt;      // [k+1] scratch counts
   int32_t *tmp_cnt2;     // [k+1] scratch counts

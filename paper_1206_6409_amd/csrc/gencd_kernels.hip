@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_col_scatter(const int64_t *col_ptr, 
                                                          const int32_t *all_loff,
                                                          const int32_t *live_pos,
                                                          int4 *desc_all_s, int4 *desc_all_l,
-                                                         int32_t *live) {
+                                                         int32_t *live, int4 *live_rec) {
   for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
        j += int64_t(gridDim.x) * kBlock) {
     const int64_t cb = col_ptr[j], ce = col_ptr[j + 1];
@@ -283,7 +283,12 @@ __global__ __launch_bounds__(kBlock) void k_col_scatter(const int64_t *col_ptr, 
       const int64_t len = (ce - beg) < piece ? (ce - beg) : piece;
       desc_all_l[q] = make_desc(beg, int32_t(j), -1, int32_t(len), b - a == 1);
     }
-    if (ce > cb) live[live_pos[j]] = int32_t(j);
+    if (ce > cb) {
+      live[live_pos[j]] = int32_t(j);
+      live_rec[live_pos[j]] = all_soff[j + 1] > all_soff[j]
+                                  ? make_desc(cb, int32_t(j), -1, int32_t(ce - cb), true)
+                                  : make_int4(a, int32_t(j), b - a, 0);
+    }
   }
 }
 
@@ -353,7 +358,8 @@ int launch_preprocess(const gencd_csc *X, int loss, int piece, int short_max, co
   st = scan_exclusive(w.col_of_pos, w.soff, k, w.scan_part, s);  // live positions
   if (st) return st;
   hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(k)), dim3(kBlock), 0, s, X->col_ptr, k, piece,
-                     w.all_soff, w.all_loff, w.soff, w.desc_all_s, w.desc_all_l, w.live);
+                     w.all_soff, w.all_loff, w.soff, w.desc_all_s, w.desc_all_l, w.live,
+                     w.live_rec);
   return fill_f64(w.g64, k, 0.0, s);
 }
 
@@ -407,19 +413,30 @@ __device__ __forceinline__ void pos_counts(int32_t j, const int32_t *all_soff,
 
 // natural != 0: live columns in index order (cyclic rule).  The epoch
 // number is read from device memory so that a captured epoch replays.
-__global__ __launch_bounds__(kBlock) void k_epoch_order(const int32_t *live, int64_t k_live,
+// One 16-byte gather per position (the live column's record) gives the
+// column, its class counts and, for a short column, its descriptor, which
+// is written here; k_order_desc then only lays out the long pieces.
+__global__ __launch_bounds__(kBlock) void k_epoch_order(const int4 *live_rec, int64_t k_live,
                                                          uint64_t seed, const int64_t *epoch,
-                                                         int natural, const int32_t *all_soff,
-                                                         const int32_t *all_loff,
-                                                         int32_t *col_of_pos, int32_t *sc,
-                                                         int32_t *lc) {
+                                                         int natural, int32_t *col_of_pos,
+                                                         int32_t *sc, int32_t *lc,
+                                                         int4 *desc_s) {
   const PermKey pk = make_perm_key(k_live, seed, *epoch);
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < k_live;
        p += int64_t(gridDim.x) * kBlock) {
     int64_t src = natural ? p : int64_t(perm_apply(pk, uint64_t(p)));
-    int32_t j = live[src];
-    col_of_pos[p] = j;
-    pos_counts(j, all_soff, all_loff, sc[p], lc[p]);
+    int4 r = live_rec[src];
+    col_of_pos[p] = r.y;
+    if (desc_len(r) > 0) {  // short column
+      sc[p] = 1;
+      lc[p] = 0;
+      r.z = int32_t(p);
+      desc_s[p] = r;
+    } else {
+      sc[p] = 0;
+      lc[p] = r.z;
+      desc_s[p] = make_int4(0, r.y, int32_t(p), 0);  // long: length 0
+    }
   }
 }
 
@@ -449,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos
                                                         const int32_t *all_loff,
                                                         const int4 *desc_all_s,
                                                         const int4 *desc_all_l, int4 *desc_s,
-                                                        int4 *desc_l) {
+                                                        int4 *desc_l, int32_t shorts_done) {
   const int lane = int(threadIdx.x) & (kWave - 1);
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t base = int64_t(blockIdx.x) * kBlock + threadIdx.x - lane; base < m;
@@ -457,7 +474,10 @@ __global__ __launch_bounds__(kBlock) void k_order_desc(const int32_t *col_of_pos
     const int64_t p = base + lane;
     int32_t j = 0;
     bool lng = false;
-    if (p < m) {
+    if (p < m && shorts_done) {  // every desc_s written: find the long positions
+      lng = loff[p + 1] > loff[p];
+      if (lng) j = col_of_pos[p];
+    } else if (p < m) {
       j = col_of_pos[p];
       const int32_t sj = all_soff[j];
       if (all_soff[j + 1] > sj) {  // short column
@@ -534,13 +554,13 @@ __global__ __launch_bounds__(kBlock) void k_window_bounds(const int32_t *loff,
 }
 
 static int order_tail(const Ws &w, int64_t m, const int32_t *win_off, int64_t S, int64_t T,
-                      hipStream_t s) {
+                      hipStream_t s, bool shorts_done = false) {
   int st = scan_exclusive(w.tmp_cnt2, w.loff, m, w.scan_part, s);
   if (st) return st;
   if (m > 0)
     hipLaunchKernelGGL(k_order_desc, dim3(grid_for(m)), dim3(kBlock), 0, s, w.col_of_pos, m,
                        w.loff, w.all_soff, w.all_loff, w.desc_all_s, w.desc_all_l, w.desc_s,
-                       w.desc_l);
+                       w.desc_l, int32_t(shorts_done ? 1 : 0));
   hipLaunchKernelGGL(k_window_bounds, dim3(grid_for(T + 1)), dim3(kBlock), 0, s, w.loff, win_off,
                      S, m, T, w.wbl);
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
@@ -561,10 +581,10 @@ int launch_epoch_order(const Ws &w, int64_t k_live, int rule, uint64_t seed,
                        k_live, w.all_soff, w.all_loff, w.tmp_cnt, w.tmp_cnt2);
     return order_tail(w, k_live, w.win_off, 0, num_colors, s);
   }
-  hipLaunchKernelGGL(k_epoch_order, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.live, k_live,
-                     seed, epoch, rule == GENCD_CYCLIC ? 1 : 0, w.all_soff, w.all_loff,
-                     w.col_of_pos, w.tmp_cnt, w.tmp_cnt2);
-  return order_tail(w, k_live, nullptr, S, T, s);
+  hipLaunchKernelGGL(k_epoch_order, dim3(grid_for(k_live)), dim3(kBlock), 0, s, w.live_rec,
+                     k_live, seed, epoch, rule == GENCD_CYCLIC ? 1 : 0, w.col_of_pos, w.tmp_cnt,
+                     w.tmp_cnt2, w.desc_s);
+  return order_tail(w, k_live, nullptr, S, T, s, true);
 }
 
 int launch_inc_epoch(int64_t *epoch, hipStream_t s) {

@@ -56,6 +56,7 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.all_soff = c.take<int32_t>(k + 1);
   w.all_loff = c.take<int32_t>(k + 1);
   w.desc_all_s = c.take<int4>(k);
+  w.live_rec = c.take<int4>(k);
   w.desc_all_l = c.take<int4>(ml);
   w.tmp_cnt = c.take<int32_t>(k + 1);
   w.tmp_cnt2 = c.take<int32_t>(k + 1);
