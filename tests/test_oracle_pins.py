@@ -898,3 +898,69 @@ def test_balanced_colouring_parts_are_near_equal():
     color = np.zeros(k, dtype=np.int32)
     bal, nb = O.balance_colors(k, col_ptr, color, 1, 4)
     assert nb == 3 and bal.tolist() == [0, 0, 0, 0, 1, 1, 1, 2, 2, 2]
+
+
+# --------------------------------------------------------------------------
+# losses (section 1): values against numpy's logaddexp, derivatives against
+# central differences, and the curvature bound beta of Eq. 5
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("y", [1.0, -1.0])
+def test_logistic_loss_matches_logaddexp_and_is_stable(y):
+    for t in [0.0, 1e-8, 0.3, -2.5, 17.0, -40.0, 700.0, -700.0, 1e4, -1e4]:
+        ref = float(np.logaddexp(0.0, -y * t))
+        got = O.loss(O.LOGISTIC, y, t)
+        assert math.isfinite(got)
+        assert got == pytest.approx(ref, rel=1e-14, abs=1e-300)
+    assert O.loss(O.LOGISTIC, y, 0.0) == pytest.approx(math.log(2.0), rel=1e-15)
+    # a margin of -1e4 costs exactly 1e4 (the log1p term underflows to 0)
+    assert O.loss(O.LOGISTIC, y, -y * 1e4) == 1e4
+
+
+@pytest.mark.parametrize("kind", [O.SQUARED, O.LOGISTIC])
+def test_loss_derivative_is_the_derivative_of_the_loss(kind):
+    h = 1e-5
+    for y in (1.0, -1.0, 0.7):
+        if kind == O.LOGISTIC and abs(y) != 1.0:
+            continue
+        for t in (-6.0, -1.3, -0.2, 0.0, 0.4, 2.2, 9.0):
+            fd = (O.loss(kind, y, t + h) - O.loss(kind, y, t - h)) / (2 * h)
+            assert O.dloss(kind, y, t) == pytest.approx(fd, rel=1e-7, abs=1e-10)
+    if kind == O.LOGISTIC:
+        # the derivative is -y sigma(-y t): bounded by 1 and signed -y, with the
+        # exact limits at extreme margins
+        assert O.dloss(kind, 1.0, -1e4) == -1.0 and O.dloss(kind, -1.0, 1e4) == 1.0
+        assert -1e-300 <= O.dloss(kind, 1.0, 1e4) <= 0.0
+        for t in np.linspace(-30, 30, 61):
+            d = O.dloss(kind, 1.0, float(t))
+            assert -1.0 <= d <= 0.0
+
+
+@pytest.mark.parametrize("kind,beta", [(O.SQUARED, 1.0), (O.LOGISTIC, 0.25)])
+def test_curvature_bound_is_the_largest_second_derivative(kind, beta):
+    # Eq. 5 bounds the loss by a quadratic of curvature beta: beta is the
+    # supremum of the second derivative (1 for squared loss, sigma'(0) = 1/4
+    # for the logistic loss, reached at t = 0)
+    h = 1e-4
+    ys = (1.0,) if kind == O.LOGISTIC else (1.0, -0.3)
+    second = []
+    for y in ys:
+        for t in np.linspace(-8, 8, 161):
+            t = float(t)
+            second.append((O.dloss(kind, y, t + h) - O.dloss(kind, y, t - h)) / (2 * h))
+    assert max(second) == pytest.approx(beta, rel=1e-6)
+    # the column curvature is beta ||X_j||^2 / n
+    rng = np.random.default_rng(3)
+    n, k = 7, 4
+    A = rng.standard_normal((n, k)) * (rng.random((n, k)) < 0.6)
+    col_ptr = [0]
+    rows, vals = [], []
+    for j in range(k):
+        nz = np.nonzero(A[:, j])[0]
+        rows.extend(nz.tolist())
+        vals.extend(A[nz, j].tolist())
+        col_ptr.append(len(rows))
+    X = O.Matrix(n, k, np.array(col_ptr, dtype=np.int64), np.array(rows, dtype=np.int32),
+                 np.array(vals, dtype=np.float64))
+    np.testing.assert_allclose(O.curvature(X, kind), beta * (A ** 2).sum(axis=0) / n,
+                               rtol=1e-14, atol=0)
