@@ -9,9 +9,11 @@ KKT <= 1e-6 (inputs already resident in HBM).
 
 Printed value: nnz-updates/s = sum over accepted proposals of nnz_j, divided
 by the wall time of the timed solves.  Also reported: solves/s, coordinate
-updates/s, the Thread-Greedy variant, the roofline of the dominant kernel
-(Propose, timed with HIP events on the solve's stream) and the FP64 oracle
-timed on the host as the CPU baseline.
+updates/s, the nonzeros actually scattered, the Thread-Greedy variant, the
+roofline of Propose and of Update (each timed with HIP events around its own
+dispatches on the solve's stream; `roofline` is the one with the larger
+total time), the error of the result against the oracle's tight optimum,
+and the FP64 oracle timed on the host as the CPU baseline.
 """
 import argparse
 import json
@@ -25,11 +27,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of one Propose launch, measured with rocprofv3 counters
-# (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size) and kept
-# as a text summary.  It is reported only while the kernel sources and
-# launch configuration are the ones the counters were taken on.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_propose_zipf1.1-logistic_n100k_k500k_pmc.md")
+# HBM traffic of one Propose and one Update launch, measured with rocprofv3
+# counters (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size)
+# and kept as a text summary.  It is reported only while the kernel sources
+# and launch configuration are the ones the counters were taken on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_propose_k_update_zipf1.1-logistic_n100k_k500k_pmc.md")
 TRAFFIC_SOURCES = ["gencd_common.hpp", "gencd_kernels.hpp", "gencd_kernels.hip", "gencd_solver.hip"]
 
 
@@ -42,9 +44,9 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Bytes per Propose launch from the counter summary, or None when the
-    summary is missing or was taken on other kernel sources."""
+def measured_traffic(kernel="k_propose"):
+    """Bytes per launch of `kernel` from the counter summary, or None when
+    the summary is missing or was taken on other kernel sources."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
@@ -57,7 +59,7 @@ def measured_traffic():
     if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[f"traffic_bytes_per_launch.{kernel}"])
     except (KeyError, ValueError):
         return None
 
@@ -150,6 +152,8 @@ def main():
                 tol=args.tol, max_epochs=100000, check_every=1)
     ws = G.workspace(X, G.make_params(**base))
 
+    last_res = {}
+
     def run(rule, steps, warmup, flags=0, **kw):
         nonlocal ws
         pr = dict(base, rule=rule, **kw)
@@ -167,6 +171,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         assert all(s["converged"] == 1 for s in stats), stats[-1]
+        last_res[(rule, flags)] = res
         return dt, stats, res
 
     log("timing Shotgun solves (plain launches, kernel events on)")
@@ -196,22 +201,39 @@ def main():
     coord_upd = sum(s["coord_updates"] for s in stats)
     value = nnz_upd / dt
     last = stats[-1]
-    prof_ms = sum(s["prof_kernel_ms"] for s in prof_src)
-    prof_launch = sum(s["prof_launches"] for s in prof_src)
-    prof_bytes = sum(s["prof_bytes"] for s in prof_src)
-    achieved = prof_bytes / (prof_ms * 1e-3) / 1e9 if prof_ms > 0 else 0.0
-    roofline = {
-        "bound": "hbm",
-        "kernel": "k_propose (Propose: gradient, step and proxy of every selected column)",
-        "achieved": round(achieved, 3),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 6),
-        "traffic": measured_traffic(),
-        "avg_launch_us": round(prof_ms * 1e3 / max(prof_launch, 1), 3),
-        "bytes_per_launch": round(prof_bytes / max(prof_launch, 1), 1),
-        "launches": prof_launch,
-    }
+
+    def kernel_roofline(name, what, ms, launches, nbytes, extra=None):
+        achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        r = {"bound": "hbm", "kernel": f"{name} ({what})", "achieved": round(achieved, 3),
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+             "traffic": measured_traffic(name),
+             "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
+             "bytes_per_launch": round(nbytes / max(launches, 1), 1),
+             "launches": launches, "total_ms": round(ms, 3)}
+        if extra:
+            r.update(extra)
+        return r
+
+    p_ms = sum(s["prof_kernel_ms"] for s in prof_src)
+    u_ms = sum(s["prof_update_ms"] for s in prof_src)
+    u_launch = sum(s["prof_update_launches"] for s in prof_src)
+    scattered = sum(s["nnz_scattered"] for s in prof_src)
+    coord_plain = sum(s["coord_updates"] for s in prof_src)
+    # Update bytes counted over the columns whose increment was nonzero only
+    # (the kernel skips the others): 24 B per scattered nonzero + 8 B per column
+    u_bytes_nz = 24.0 * scattered + 8.0 * coord_plain
+    rf_p = kernel_roofline(
+        "k_propose", "Propose: gradient, step and proxy of every selected column; "
+        "12 B per nonzero + 28 B per column", p_ms, sum(s["prof_launches"] for s in prof_src),
+        sum(s["prof_bytes"] for s in prof_src))
+    rf_u = kernel_roofline(
+        "k_update", "Update: w_j += delta_j, z += delta_j X_j; 24 B per nonzero of every "
+        "accepted column + 8 B per column", u_ms, u_launch,
+        sum(s["prof_update_bytes"] for s in prof_src),
+        {"achieved_nonzero_delta_only": round(u_bytes_nz / (u_ms * 1e-3) / 1e9, 3) if u_ms > 0 else 0.0,
+         "bytes_per_launch_nonzero_delta_only": round(u_bytes_nz / max(u_launch, 1), 1)})
+    dominant = rf_u if u_ms > p_ms else rf_p
+    roofline = dict(dominant)
     out = {
         "metric": "nnz-updates/s of Shotgun solves to FP64 KKT 1e-6",
         "value": value,
@@ -243,7 +265,14 @@ def main():
         "kkt_max": last["kkt_max"],
         "duality_gap": last["gap"],
         "nnz_w": last["nnz_w"],
+        # nonzeros the Update launches actually scattered (delta_j != 0), as a
+        # fraction of the accepted nonzeros (profiled plain solves) and as a rate
+        # on the headline path
+        "nnz_scattered_fraction": scattered / max(sum(s["nnz_updates"] for s in prof_src), 1),
+        "nnz_scattered_per_s": value * scattered / max(sum(s["nnz_updates"] for s in prof_src), 1),
+        "z_drift_low_word_accumulation": max(s["z_drift"] for s in stats),
         "roofline": roofline,
+        "kernels": {"k_propose": rf_p, "k_update": rf_u},
     }
 
     if not args.no_thread_greedy:
@@ -306,8 +335,32 @@ def main():
             "objective": r.objective,
         }
         out["objective_rel_diff_vs_oracle"] = abs(last["objective"] - r.objective) / abs(r.objective)
+        # the oracle's optimum to KKT 1e-10 (warm-started from its own solve),
+        # against which every GPU result of this line is stated
+        log("solving the oracle to KKT 1e-10 for the precision figures")
+        ref = O.solve(Xo, yo, P.loss, float(lam), O.SHOTGUN, select_size=args.select, seed=7,
+                      tol=1e-10, max_epochs=100000, w0=r.w)
+        res_h = last_res[(G.SHOTGUN, G.USE_GRAPH)] if (G.SHOTGUN, G.USE_GRAPH) in last_res \
+            else last_res[(G.SHOTGUN, G.PROFILE)]
+        out["precision"] = precision_vs_oracle(O, Xo, yo, P.loss, float(lam), ref, res_h)
 
     print(json.dumps(out), flush=True)
+
+
+def precision_vs_oracle(O, Xo, yo, loss, lam, ref, res):
+    """Error of one GPU solve against the oracle's tight optimum: relative
+    objective error, max_i |z_i - z*_i| / (|z*_i| + rms(z*)), and the KKT
+    violation of the GPU's w evaluated independently by the oracle."""
+    import numpy as np
+    w = res.w.double().cpu().numpy()
+    chk = O.check(Xo, yo, loss, lam, w)
+    z = res.z.double().cpu().numpy() if res.z is not None else chk.z
+    zs = ref.z
+    scale = np.abs(zs) + np.sqrt(np.mean(zs ** 2)) + 1e-300
+    return {"oracle_optimum_objective": ref.objective, "oracle_optimum_kkt": ref.kkt,
+            "objective_rel_err": abs(chk.objective - ref.objective) / abs(ref.objective),
+            "z_max_rel_err": float(np.max(np.abs(z - zs) / scale)),
+            "kkt_max": chk.kkt, "gpu_reported_kkt_max": res.stats["kkt_max"]}
 
 
 # ---------------------------------------------------------------------------

@@ -80,7 +80,8 @@ typedef enum {
 #define GENCD_WARM_START 0x1u      /* w holds the starting point on entry */
 #define GENCD_VALIDATE_DEVICE 0x2u /* check CSC structure and labels on the device */
 #define GENCD_USE_GRAPH 0x4u       /* replay each epoch as a captured HIP graph */
-#define GENCD_PROFILE 0x8u         /* time every Propose launch with HIP events */
+#define GENCD_PROFILE 0x8u         /* time every Propose and Update launch with HIP events
+                                      (plain launch path only) */
 #define GENCD_EXACT_ACCUM 0x10u    /* TwoSum-compensate every atomic update of z */
 #define GENCD_FUSED 0x20u          /* accept-all rules except Coloring: fused asynchronous
                                       Propose+Update (section 4.1); each column reads z as
@@ -164,6 +165,21 @@ typedef struct {
   double rho;             /* spectral-radius estimate when |J| came from it, else 0 */
   int64_t select_size;    /* |J| used by the solve (after any halving by the
                              divergence guard) */
+  /* GENCD_PROFILE: Update launches (Algorithm 3), their summed duration (HIP
+   * events) and algorithmic bytes: 24 B per nonzero of every accepted column
+   * (its row index and value, and a read-modify-write of the 8-byte fitted
+   * value pair z_hi, z_lo) plus 8 B per accepted column (w_j, delta_j).
+   * Columns whose increment is zero cost nothing in the kernel; their
+   * nonzeros still count here, see nnz_scattered. */
+  int64_t prof_update_launches;
+  double prof_update_ms;
+  double prof_update_bytes;
+  int64_t nnz_scattered;  /* GENCD_PROFILE: nonzeros the Update launches actually
+                             scattered (columns with delta_j != 0); 0 otherwise */
+  double z_drift;         /* largest max_i |z_i - (Xw)_i| / rms(Xw) over the FP64
+                             checks after the first: z_i is the FP32 pair
+                             z_hi + z_lo that the iterations accumulated since the
+                             previous re-sync, Xw the FP64 product of the check */
 } gencd_stats;
 
 const char *gencd_status_string(int status);
@@ -252,7 +268,9 @@ int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_c
  * lambda takes it, starting from the latest iterate of the previous lambda
  * (section 4.1 mentions starting from a large lambda and decreasing it).
  *   lambdas: host double[L];  W: device float32[L][k] (row t = solution for
- *   lambdas[t]);  stats: host gencd_stats[L].
+ *   lambdas[t]);  Z: device float32[L][n] or NULL (row t = X W[t], the FP32
+ *   rounding of the FP64 product of the slot's final check);
+ *   stats: host gencd_stats[L].
  * Flags: GENCD_FUSED (one launch per window, see above), GENCD_USE_GRAPH
  * (every epoch replays one captured HIP graph; which lambdas the slots hold
  * lives in device arrays, so the graph is captured once per call).
@@ -260,7 +278,7 @@ int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_c
 int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_t B,
                                size_t *out_bytes);
 int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
-                     const double *lambdas, int32_t L, int32_t B, float *W, void *ws,
+                     const double *lambdas, int32_t L, int32_t B, float *W, float *Z, void *ws,
                      size_t ws_bytes, hipStream_t stream, gencd_stats *stats);
 
 /* Schedule autotuner.  Times every candidate schedule (lanes per short

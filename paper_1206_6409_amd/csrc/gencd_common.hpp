@@ -214,6 +214,7 @@ struct Ws {
   double *g64;           // [k]
   double *red;           // [16] reductions, counters, flags; [12] epoch counter
   double *rrep;          // [kChkRep * 16] replicas of the check's reductions, one line each
+  unsigned long long *scat;  // [kChkRep * 16] nonzeros scattered by Update (GENCD_PROFILE)
   // spectral-radius estimate (only when |J| is chosen from it, or blocks)
   double *rho_dinv;      // [k] 1/||X_j|| (0 for empty columns)
   double *rho_x;         // [k] D^{-1/2} v, the scaled iterate

@@ -1166,6 +1166,7 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   const Roles r = roles(a.nl);
   int32_t P0, P1;
   window_of(a, P0, P1);
+  uint32_t scattered = 0;  // nonzeros this lane's group scattered (counted with a.scat)
   if (r.wave < r.nl) {
     const int32_t q1 = a.wbl[a.t + 1];
     for (int64_t q = a.wbl[a.t] + r.wave; q < q1; q += r.nl) {
@@ -1193,6 +1194,7 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
         }
       }
       if (d == 0.0f) continue;
+      if (r.wl == 0) scattered += uint32_t(desc_len(dsc));
       scatter_piece<kWave, MODE, UL>(a, desc_beg(dsc), desc_len(dsc), d, r.wl);
     }
   } else {
@@ -1204,8 +1206,15 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       if (MODE == 2 && !a.acc[slot]) continue;
       const float d = a.delta[slot];
       if (d == 0.0f || desc_len(dsc) == 0) continue;
+      if (lane == 0) scattered += uint32_t(desc_len(dsc));
       scatter_piece<GS, MODE>(a, desc_beg(dsc), desc_len(dsc), d, lane);
     }
+  }
+  if (a.scat) {  // profiling only: one atomic per wave, spread over the replica lines
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) scattered += __shfl_xor(scattered, off);
+    if (r.wl == 0 && scattered > 0)
+      atomicAdd(a.scat + (blockIdx.x % kChkRep) * 16, (unsigned long long)scattered);
   }
 }
 
@@ -1358,10 +1367,16 @@ static void launch_propose(const IterArgs &a, dim3 grid, hipStream_t s, hipEvent
     hipLaunchKernelGGL(K, grid, dim3(kBlock), 0, s, a);
 }
 
+template <void (*K)(IterArgs)>
+static void launch_update(const IterArgs &a, dim3 grid, hipStream_t s, hipEvent_t ev2,
+                          hipEvent_t ev3) {
+  launch_propose<K>(a, grid, s, ev2, ev3);
+}
+
 template <int GS, int UL>
 static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsigned blocks,
                               int64_t nblocks_accept, unsigned improve_blocks, hipStream_t s,
-                              hipEvent_t ev0, hipEvent_t ev1) {
+                              hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3) {
   const dim3 grid(blocks), blk(kBlock);
   if (a.rs) {
     hipLaunchKernelGGL(k_refresh, dim3(grid_for(a.nrows)), blk, 0, s, a.nrows, a.loss, a.zs, a.rs);
@@ -1381,11 +1396,11 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
   if (mode == 0) {
     if (a.improve > 0)
       hipLaunchKernelGGL(k_improve<0>, dim3(improve_blocks), blk, 0, s, a);
-    hipLaunchKernelGGL((k_update<GS, 0, UL>), grid, blk, 0, s, a);
+    launch_update<k_update<GS, 0, UL>>(a, grid, s, ev2, ev3);
   } else if (mode == 1) {
     if (a.improve > 0)
       hipLaunchKernelGGL(k_improve<1>, dim3(improve_blocks), blk, 0, s, a);
-    hipLaunchKernelGGL((k_update<GS, 1, UL>), grid, blk, 0, s, a);
+    launch_update<k_update<GS, 1, UL>>(a, grid, s, ev2, ev3);
   } else {
     if (a.accept_top > 0) {
       hipLaunchKernelGGL(k_accept_top, dim3(1), dim3(kTopThreads), 0, s, a);
@@ -1402,7 +1417,7 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
     }
     if (a.improve > 0)
       hipLaunchKernelGGL(k_improve<2>, dim3(improve_blocks), blk, 0, s, a);
-    hipLaunchKernelGGL((k_update<GS, 2, UL>), grid, blk, 0, s, a);
+    launch_update<k_update<GS, 2, UL>>(a, grid, s, ev2, ev3);
   }
   return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
 }
@@ -1410,12 +1425,12 @@ static int launch_iteration_g(const IterArgs &a, int mode, int64_t block, unsign
 template <int GS>
 static int launch_iteration_u(const IterArgs &a, int mode, int64_t block, unsigned blocks,
                               int64_t nblocks_accept, unsigned improve_blocks, hipStream_t s,
-                              hipEvent_t ev0, hipEvent_t ev1) {
+                              hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3) {
   if (a.piece <= kWave * kUnroll)
     return launch_iteration_g<GS, kUnroll>(a, mode, block, blocks, nblocks_accept, improve_blocks,
-                                           s, ev0, ev1);
+                                           s, ev0, ev1, ev2, ev3);
   return launch_iteration_g<GS, 2 * kUnroll>(a, mode, block, blocks, nblocks_accept,
-                                             improve_blocks, s, ev0, ev1);
+                                             improve_blocks, s, ev0, ev1, ev2, ev3);
 }
 
 // ---------------------------------------------------------------------------
@@ -1548,7 +1563,7 @@ int launch_fused(const IterArgs &a, int group, int64_t short_bound, int64_t long
 
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
                      int64_t long_bound, int64_t nblocks_accept, hipStream_t s, hipEvent_t ev0,
-                     hipEvent_t ev1) {
+                     hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3) {
   IterArgs b = a;
   unsigned blocks;
   int32_t nl;
@@ -1558,12 +1573,18 @@ int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int6
   const int64_t ib = (short_bound + kBlock / kWave - 1) / (kBlock / kWave);
   const unsigned iblocks = unsigned(ib < 1 ? 1 : (ib > 16384 ? 16384 : ib));
   switch (group) {
-    case 4: return launch_iteration_u<4>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
-    case 8: return launch_iteration_u<8>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
+    case 4:
+      return launch_iteration_u<4>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1,
+                                   ev2, ev3);
+    case 8:
+      return launch_iteration_u<8>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1,
+                                   ev2, ev3);
     case 16:
-      return launch_iteration_u<16>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
+      return launch_iteration_u<16>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1,
+                                    ev2, ev3);
     default:
-      return launch_iteration_u<32>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1);
+      return launch_iteration_u<32>(b, mode, block, blocks, nblocks_accept, iblocks, s, ev0, ev1,
+                                    ev2, ev3);
   }
 }
 
@@ -1634,11 +1655,15 @@ __global__ __launch_bounds__(kBlock) void k_check_spmv(const int32_t *row_idx, c
   }
 }
 
+// Loss sum, residual and (zs non-null) the re-sync of the FP32 state.  The
+// re-sync also measures how far the accumulated pair z_hi + z_lo drifted
+// from z64: max_i |z_i - z64_i| into replica word 6 (bit pattern of a
+// non-negative double) and sum_i z64_i^2 into word 7.
 __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, const float *y,
                                                         const double *z64, double *r64,
                                                         float4 *zs, unsigned long long *rep) {
-  __shared__ double sred[kBlock];
-  double acc = 0.0;
+  __shared__ double sred[kBlock], sdr[kBlock], ssq[kBlock];
+  double acc = 0.0, drift = 0.0, sq = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * kBlock) {
     const double t = z64[i];
@@ -1646,17 +1671,36 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int64_t n, int loss, cons
     acc += loss_f64(loss, yi, t);
     r64[i] = dloss_f64(loss, yi, t);
     if (zs) {  // re-sync: z_hi + z_lo = z64 to about 2^-48 relative, and the label
+      const float4 old = zs[i];
+      const double dv = fabs((double(old.x) + double(old.y)) - t);
+      if (!(dv <= drift)) drift = dv;  // propagates NaN
+      sq += t * t;
       const float h = float(t);
       zs[i] = make_float4(h, float(t - double(h)), y[i], 0.0f);
     }
   }
   sred[threadIdx.x] = acc;
+  sdr[threadIdx.x] = drift;
+  ssq[threadIdx.x] = sq;
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+    if (threadIdx.x < off) {
+      sred[threadIdx.x] += sred[threadIdx.x + off];
+      ssq[threadIdx.x] += ssq[threadIdx.x + off];
+      const double o = sdr[threadIdx.x + off];
+      if (!(o <= sdr[threadIdx.x])) sdr[threadIdx.x] = o;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(reinterpret_cast<double *>(rep_line(rep)), sred[0]);
+  if (threadIdx.x == 0) {
+    unsigned long long *line = rep_line(rep);
+    atomicAdd(reinterpret_cast<double *>(line), sred[0]);
+    if (zs) {
+      const double m = sdr[0];
+      atomicMax(line + 6, (m != m) ? 0x7FF8000000000000ull : (unsigned long long)__double_as_longlong(m));
+      atomicAdd(reinterpret_cast<double *>(line + 7), ssq[0]);
+    }
+  }
 }
 
 template <int G>

@@ -34,6 +34,8 @@ struct IterArgs {
   int32_t *bw_pos, *bw_phi;  // per-chunk winners of a two-stage global accept (scratch)
   int32_t exact_accum;     // 1: TwoSum per update (returning atomics); 0: low-word accumulation
   unsigned long long *counters;  // [0] accepted nnz, [1] accepted proposals (greedy rules)
+  unsigned long long *scat;      // non-null: Update adds the nonzeros it scatters here
+                                 // (replica line b % kChkRep of workgroup b, 16 words each)
 };
 
 int fill_f32(float *p, int64_t m, float v, hipStream_t s);
@@ -60,9 +62,11 @@ int launch_list_order(const Ws &w, const int32_t *J, int64_t nJ, hipStream_t s);
 // group: lanes per short column (4, 8, 16 or 32); short_bound / long_bound:
 // expected short columns / long pieces of a window (they size the grid; the
 // kernels stride over whatever the window holds).
+// ev0/ev1 (optional) stamp the Propose dispatch, ev2/ev3 the Update dispatch.
 int launch_iteration(const IterArgs &a, int group, int mode, int64_t block, int64_t short_bound,
                      int64_t long_bound, int64_t nblocks_accept, hipStream_t s,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                     hipEvent_t ev2 = nullptr, hipEvent_t ev3 = nullptr);
 // Fused asynchronous Shotgun iteration (accept-all rules): window a.t, plus
 // the split columns of window a.t - 1; `flush` applies only the latter
 // (a.t = number of windows).

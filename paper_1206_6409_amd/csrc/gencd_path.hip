@@ -581,6 +581,14 @@ __global__ __launch_bounds__(kBlock) void k_strided_copy(int64_t k, const float 
     dst[j * ds + so] = src ? src[j * ss + si] : 0.0f;
 }
 
+// dst[i] = float(src[i * stride + slot]) for i < n: one slot's FP64 fitted values
+__global__ __launch_bounds__(kBlock) void k_slot_round(int64_t n, const double *src,
+                                                       int64_t stride, int64_t slot, float *dst) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    dst[i] = float(src[i * stride + slot]);
+}
+
 static unsigned g1(int64_t m, unsigned cap = 4096) {
   int64_t b = (m + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
@@ -648,8 +656,8 @@ struct PathGraph {
 
 template <int B>
 int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const double *lambdas,
-             int32_t L, float *W_out, char *path_base, const PathSetup &su, hipStream_t s,
-             gencd_stats *stats) {
+             int32_t L, float *W_out, float *Z_out, char *path_base, const PathSetup &su,
+             hipStream_t s, gencd_stats *stats) {
   const int64_t n = X->n, k = X->k, k_live = su.k_live;
   int64_t S = std::min<int64_t>(p->select_size, std::max<int64_t>(k_live, 1));
   PathWs w{};
@@ -798,6 +806,9 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
           so.converged = conv ? 1 : 0;
           hipLaunchKernelGGL(k_strided_copy, dim3(g1(k)), dim3(kBlock), 0, s, k, w.W, int64_t(B),
                              int64_t(slot), W_out + int64_t(t) * k, int64_t(1), int64_t(0));
+          if (Z_out)  // the check just formed z64 = X W of this slot
+            hipLaunchKernelGGL(k_slot_round, dim3(g1(n)), dim3(kBlock), 0, s, n, w.z64,
+                               int64_t(B), int64_t(slot), Z_out + int64_t(t) * n);
           GENCD_HIP(hipGetLastError());
           done[t] = 1;
           --remaining;
@@ -874,7 +885,7 @@ int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_
 }
 
 int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
-                     const double *lambdas, int32_t L, int32_t B, float *W, void *ws,
+                     const double *lambdas, int32_t L, int32_t B, float *W, float *Z, void *ws,
                      size_t ws_bytes, hipStream_t stream, gencd_stats *stats) {
   (void)hipGetLastError();
   auto t0 = std::chrono::steady_clock::now();
@@ -901,9 +912,9 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
   size_t mis = reinterpret_cast<uintptr_t>(pb) % 256;
   if (mis) pb += 256 - mis;
   switch (B) {
-    case 16: st = path_run<16>(X, y, p, lambdas, L, W, pb, su, stream, stats); break;
-    case 32: st = path_run<32>(X, y, p, lambdas, L, W, pb, su, stream, stats); break;
-    default: st = path_run<64>(X, y, p, lambdas, L, W, pb, su, stream, stats); break;
+    case 16: st = path_run<16>(X, y, p, lambdas, L, W, Z, pb, su, stream, stats); break;
+    case 32: st = path_run<32>(X, y, p, lambdas, L, W, Z, pb, su, stream, stats); break;
+    default: st = path_run<64>(X, y, p, lambdas, L, W, Z, pb, su, stream, stats); break;
   }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int all = 1;

@@ -83,6 +83,7 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.g64 = c.take<double>(k);
   w.red = c.take<double>(16);
   w.rrep = c.take<double>(int64_t(kChkRep) * 16);
+  w.scat = c.take<unsigned long long>(int64_t(kChkRep) * 16);
   if (rho || nblocks > 0) {
     w.rho_dinv = c.take<double>(k);
     w.rho_x = c.take<double>(k);
@@ -299,6 +300,7 @@ struct CheckOut {
   double objective, kkt, gap;
   int64_t nnz_w;
   unsigned long long acc_nnz, acc_cnt;
+  double drift_rel;  // re-syncing checks: max_i |z_i - z64_i| / rms(z64) (0 if z64 = 0)
 };
 
 int run_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
@@ -313,9 +315,11 @@ int run_check(const gencd_csc *X, const float *y, int loss, double lam, const fl
   if (st) return st;
   r.loss_sum = r.l1 = r.dual_sum = 0.0;
   r.kkt_bits = r.nnz_w = r.gmax_bits = 0ull;
+  unsigned long long drift_bits = 0ull;
+  double zsq = 0.0;
   for (int i = 0; i < kChkRep; ++i) {  // fold in replica order
     const double *f = rep + i * 16;
-    unsigned long long u[6];
+    unsigned long long u[8];
     std::memcpy(u, f, sizeof(u));
     r.loss_sum += f[0];
     r.l1 += f[1];
@@ -323,7 +327,11 @@ int run_check(const gencd_csc *X, const float *y, int loss, double lam, const fl
     r.nnz_w += u[3];
     r.gmax_bits = std::max(r.gmax_bits, u[4]);
     r.dual_sum += f[5];
+    drift_bits = std::max(drift_bits, u[6]);
+    zsq += f[7];
   }
+  const double rms = std::sqrt(zsq / double(X->n));
+  out->drift_rel = rms > 0.0 ? bits_to_double(drift_bits) / rms : 0.0;
   out->objective = r.loss_sum / double(X->n) + lam * r.l1;
   out->kkt = bits_to_double(r.kkt_bits);
   out->gap = out->objective - r.dual_sum / double(X->n);
@@ -376,6 +384,7 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   a.bw_phi = ws.tmp_cnt2;
   a.counters = reinterpret_cast<unsigned long long *>(ws.red) + 8;
   a.exact_accum = (p->flags & GENCD_EXACT_ACCUM) ? 1 : 0;
+  a.scat = nullptr;
   return a;
 }
 
@@ -601,21 +610,33 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   const bool fused = (p->flags & GENCD_FUSED) != 0;
   const bool prof = (p->flags & GENCD_PROFILE) != 0 && !use_graph && !fused;
   EventPool pool;
-  std::vector<hipEvent_t> &evs = pool.v;
+  std::vector<hipEvent_t> &evs = pool.v;  // per iteration: Propose pair, Update pair
   size_t ev_used = 0;
-  double prof_bytes_pending = 0.0;
+  double prof_bytes_pending = 0.0, prof_ubytes_pending = 0.0;
+  if (prof) {
+    a.scat = ws.scat;
+    st = fill_i32(reinterpret_cast<int32_t *>(ws.scat), int64_t(kChkRep) * 32, 0, s);
+    if (st) return st;
+  }
   auto harvest = [&]() {
     // called after a stream synchronisation: every recorded pair is complete
-    double ms = 0.0;
-    for (size_t u = 0; u + 1 < ev_used; u += 2) {
+    double ms = 0.0, ums = 0.0;
+    for (size_t u = 0; u + 3 < ev_used; u += 4) {
       float t = 0.0f;
       if (evs[u] && evs[u + 1] && hipEventElapsedTime(&t, evs[u], evs[u + 1]) == hipSuccess)
         ms += double(t);
+      t = 0.0f;
+      if (evs[u + 2] && evs[u + 3] &&
+          hipEventElapsedTime(&t, evs[u + 2], evs[u + 3]) == hipSuccess)
+        ums += double(t);
     }
     st_out->prof_kernel_ms += ms;
-    st_out->prof_launches += int64_t(ev_used / 2);
+    st_out->prof_launches += int64_t(ev_used / 4);
     st_out->prof_bytes += prof_bytes_pending;
-    prof_bytes_pending = 0.0;
+    st_out->prof_update_ms += ums;
+    st_out->prof_update_launches += int64_t(ev_used / 4);
+    st_out->prof_update_bytes += prof_ubytes_pending;
+    prof_bytes_pending = prof_ubytes_pending = 0.0;
     ev_used = 0;
   };
   GraphHolder graph;
@@ -655,14 +676,16 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       }
       const int64_t B = (rule == GENCD_THREAD_GREEDY) ? p->block : positions;
       a.rs = wants_rs(p, positions, X->nnz, k_live, X->n) ? ws.rs : nullptr;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (record && !evs.empty() && ev_used + 2 <= evs.size()) {
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+      if (record && !evs.empty() && ev_used + 4 <= evs.size()) {
         e0 = evs[ev_used];
         e1 = evs[ev_used + 1];
-        ev_used += 2;
+        e2 = evs[ev_used + 2];
+        e3 = evs[ev_used + 3];
+        ev_used += 4;
       }
       rc = launch_iteration(a, su.group, mode, B, positions, long_bound_for(su, positions),
-                            (positions + B - 1) / B, es, e0, e1);
+                            (positions + B - 1) / B, es, e0, e1, e2, e3);
       if (rc) return rc;
     }
     if (fused && T > 0) {  // the last window's split columns
@@ -683,8 +706,8 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
                       : (rule == GENCD_BLOCK_SHOTGUN) ? T_blk
                                                       : (k_live + S - 1) / S;
     if (prof && evs.empty()) {
-      const int64_t want = 2 * std::max<int64_t>(T, 1) * check_every;
-      if (want <= 2 * 65536) {
+      const int64_t want = 4 * std::max<int64_t>(T, 1) * check_every;
+      if (want <= 4 * 65536) {
         evs.resize(size_t(want));
         // timing-only events: no system-scope fence when they complete, so
         // the stamped dispatch ends without a cache writeback of its own
@@ -725,19 +748,30 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
     st_out->iters += iters;
     if (mode != 2) st_out->coord_updates += k_live;
     st_out->epochs = e + 1;
-    if (!evs.empty()) prof_bytes_pending += 12.0 * double(X->nnz) + 28.0 * double(k_live);
+    if (!evs.empty()) {
+      prof_bytes_pending += 12.0 * double(X->nnz) + 28.0 * double(k_live);
+      // accept-all rules: every live column is accepted once per epoch
+      if (mode != 2) prof_ubytes_pending += 24.0 * double(X->nnz) + 8.0 * double(k_live);
+    }
     st_out->nnz_visits += X->nnz;
     if (mode != 2) st_out->nnz_updates += X->nnz;
     if ((e + 1) % check_every == 0 || e + 1 == p->max_epochs) {
       st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
       if (st) return st;
-      if (!evs.empty()) harvest();
+      if (std::isfinite(ck.drift_rel))
+        st_out->z_drift = std::max(st_out->z_drift, ck.drift_rel);
+      else
+        st_out->z_drift = ck.drift_rel;
       if (mode == 2) {
+        if (!evs.empty())
+          prof_ubytes_pending += 24.0 * double(ck.acc_nnz - acc_nnz_seen) +
+                                 8.0 * double(ck.acc_cnt - acc_cnt_seen);
         st_out->coord_updates += int64_t(ck.acc_cnt - acc_cnt_seen);
         st_out->nnz_updates += int64_t(ck.acc_nnz - acc_nnz_seen);
         acc_cnt_seen = ck.acc_cnt;
         acc_nnz_seen = ck.acc_nnz;
       }
+      if (!evs.empty()) harvest();
       const bool bad = !std::isfinite(ck.objective) ||
                        ck.objective > best + 1e-3 * std::fabs(best) + 1e-12;
       if (bad &&
@@ -772,6 +806,12 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   if (z) {
     st = launch_round_f32(ws.z64, z, X->n, s);
     if (st) return st;
+  }
+  if (prof) {
+    unsigned long long sc[kChkRep * 16];
+    GENCD_HIP(hipMemcpyAsync(sc, ws.scat, sizeof(sc), hipMemcpyDeviceToHost, s));
+    GENCD_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < kChkRep; ++i) st_out->nnz_scattered += int64_t(sc[i * 16]);
   }
   GENCD_HIP(hipStreamSynchronize(s));
   st_out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -218,12 +218,12 @@ int gencd_autotune_path(const gencd_csc *X, const float *y, const gencd_params *
       size_t need = 0;
       if (gencd_path_workspace_bytes(X, &q, B, &need) != GENCD_OK || need > ws_bytes) continue;
       if (!warmed) {  // first-use costs (code objects, caches) stay out of the timings
-        (void)gencd_solve_path(X, y, &q, lambdas, std::min<int32_t>(L, 2), B, W_scratch, ws,
+        (void)gencd_solve_path(X, y, &q, lambdas, std::min<int32_t>(L, 2), B, W_scratch, nullptr, ws,
                                ws_bytes, stream, st.data());
         warmed = true;
       }
       auto t0 = std::chrono::steady_clock::now();
-      const int rc = gencd_solve_path(X, y, &q, lambdas, L, B, W_scratch, ws, ws_bytes, stream,
+      const int rc = gencd_solve_path(X, y, &q, lambdas, L, B, W_scratch, nullptr, ws, ws_bytes, stream,
                                       st.data());
       const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (rc < 0) continue;

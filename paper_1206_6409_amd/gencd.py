@@ -53,7 +53,10 @@ class Stats(C.Structure):
                 ("seconds", C.c_double),
                 ("nnz_w", C.c_int64), ("converged", C.c_int32), ("num_colors", C.c_int32),
                 ("prof_launches", C.c_int64), ("prof_kernel_ms", C.c_double),
-                ("prof_bytes", C.c_double), ("rho", C.c_double), ("select_size", C.c_int64)]
+                ("prof_bytes", C.c_double), ("rho", C.c_double), ("select_size", C.c_int64),
+                ("prof_update_launches", C.c_int64), ("prof_update_ms", C.c_double),
+                ("prof_update_bytes", C.c_double), ("nnz_scattered", C.c_int64),
+                ("z_drift", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -99,8 +102,8 @@ _SIGS = {
     "gencd_server_plan": (C.c_int, [C.c_size_t, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
     "gencd_solve_path": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
-                                   C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
-                                   C.c_void_p]),
+                                   C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                   C.c_void_p, C.c_void_p]),
     "gencd_color": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                               C.c_void_p]),
 }
@@ -356,9 +359,10 @@ class PathResult:
     status: int
     W: torch.Tensor      # [L, k]
     stats: list
+    Z: torch.Tensor = None  # [L, n] fitted values X W[t] (want_z)
 
 
-def solve_path(X: Matrix, y, params: Params, lambdas, B=32, ws=None):
+def solve_path(X: Matrix, y, params: Params, lambdas, B=32, ws=None, want_z=False):
     """Batched regularisation path (B lambda slots per launch sequence)."""
     import numpy as _np
     lam = _np.ascontiguousarray(_np.asarray(lambdas, dtype=_np.float64))
@@ -369,12 +373,13 @@ def solve_path(X: Matrix, y, params: Params, lambdas, B=32, ws=None):
                "gencd_path_workspace_bytes")
         ws = torch.empty(nb.value, dtype=torch.uint8, device=X.col_ptr.device)
     W = torch.empty((L, X.k), dtype=torch.float32, device=X.col_ptr.device)
+    Z = torch.empty((L, X.n), dtype=torch.float32, device=X.col_ptr.device) if want_z else None
     st = (Stats * L)()
     rc = lib().gencd_solve_path(X.ref, _ptr(y), C.byref(params),
-                                lam.ctypes.data_as(C.c_void_p), L, int(B), _ptr(W), _ptr(ws),
-                                ws.numel(), _stream(), st)
+                                lam.ctypes.data_as(C.c_void_p), L, int(B), _ptr(W), _ptr(Z),
+                                _ptr(ws), ws.numel(), _stream(), st)
     _check(rc, "gencd_solve_path", allow=(OK, NOT_CONVERGED))
-    return PathResult(rc, W, [s.as_dict() for s in st])
+    return PathResult(rc, W, [s.as_dict() for s in st], Z)
 
 
 class Request(C.Structure):

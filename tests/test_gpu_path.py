@@ -84,12 +84,16 @@ def test_path_check_statistics_match_oracle(loss, B, flags):
     y = torch.as_tensor(P.y, device=DEV)
     params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=128, seed=2, tol=1e-7,
                            max_epochs=20000, flags=flags)
-    res = G.solve_path(X, y, params, lams, B=B)
+    res = G.solve_path(X, y, params, lams, B=B, want_z=True)
     assert res.status == G.OK
     W = res.W.cpu().numpy().astype(np.float64)
+    Z = res.Z.cpu().numpy().astype(np.float64)
     for t, lam in enumerate(lams):
         st = res.stats[t]
         oc = O.check(Xo, P.y, P.loss, lam, W[t])
+        # Z[t] = X W[t]: the FP32 rounding of an FP64 product (summation order differs)
+        scale = np.abs(oc.z) + np.sqrt(np.mean(oc.z ** 2)) + 1e-300
+        assert np.max(np.abs(Z[t] - oc.z) / scale) <= 1e-6, t
         gap, prim = O.duality_gap(Xo, P.y, P.loss, lam, W[t])
         assert st["objective"] == pytest.approx(oc.objective, rel=1e-12), t
         assert st["kkt_max"] == pytest.approx(oc.kkt, rel=1e-9, abs=1e-15), t
