@@ -34,11 +34,14 @@ def test_no_device_exits_nonzero_without_a_line():
 
 def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "pmc.md"
-    prof.write_text("# counters\n\n- traffic_bytes_per_launch = 1234.5\n"
+    prof.write_text("# counters\n\n- traffic_bytes_per_launch.k_propose = 1234.5\n"
+                    "- traffic_bytes_per_launch.k_update = 777\n"
                     "- kernel_sources_sha256 = `abc`\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "abc")
     assert bench.measured_traffic() == 1234.5
+    assert bench.measured_traffic("k_update") == 777.0
+    assert bench.measured_traffic("k_fused") is None
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "def")
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
