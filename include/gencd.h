@@ -371,27 +371,39 @@ int gencd_estimate_rho(const gencd_csc *X, const gencd_params *p, int32_t iters,
                        hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Continuous-batching server.  Requests are whole solves of Eq. (1); they
- * are admitted in arrival order while a slot is free and their workspace
- * (gencd_workspace_bytes) fits in the caller's device arena.  Admitted
- * requests run concurrently, each on a worker thread with its own stream;
- * their state stays in the arena until they finish.  A request larger than
- * the whole arena is rejected with GENCD_ERR_BUDGET.
+ * Continuous-batching server.  Requests are Shotgun solves of Eq. (1)
+ * (rule GENCD_SHOTGUN; |J| = select_size, or 0 for P* = floor(k_live /
+ * (2 rho)) as in gencd_solve).  They are admitted in arrival order while a
+ * slot is free and their state fits in the caller's device arena; a request
+ * larger than the whole arena is rejected with GENCD_ERR_BUDGET.  Admitted
+ * requests advance together: each round is one Propose launch and one
+ * Update launch (Algorithms 2-4, then Algorithm 3) over a device work table
+ * holding a window of every admitted request, on the stream given at
+ * creation.  Each request keeps its state (w, the fitted values, the epoch
+ * order, the FP64 check arrays) in the arena until it finishes; its FP64
+ * check runs at each of its epoch ends with an asynchronous read-back, and a
+ * request that meets its tolerance leaves the table while the others go on.
+ * Results are the checked iterates: the same computation as gencd_solve with
+ * the same parameters (default flags), up to the order of the FP32 atomic
+ * additions.  Supported flags: GENCD_WARM_START, GENCD_VALIDATE_DEVICE
+ * (GENCD_USE_GRAPH is ignored); others, other rules and improve_steps give
+ * GENCD_ERR_UNSUPPORTED at submission.
  * ------------------------------------------------------------------------ */
 typedef struct gencd_server gencd_server;
 
 typedef struct {
   gencd_csc X;          /* device matrix, caller owned, valid until polled */
   const float *y;       /* device labels, idem */
-  gencd_params params;  /* loss, lambda, rule, ... (colour array for COLORING) */
-  float *w;             /* device float32[k] solution (read first with WARM_START) */
-  float *z;             /* device float32[n] fitted values or NULL */
+  gencd_params params;  /* loss, lambda, select_size, seed, kkt_tol, ... */
+  float *w;             /* device float32[k] solution (read first with WARM_START);
+                           it holds iterates while the request runs */
+  float *z;             /* device float32[n] fitted values Xw or NULL */
   int64_t user_tag;     /* returned unchanged in the result */
 } gencd_request;
 
 typedef struct {
   int64_t ticket, user_tag;
-  int32_t status;       /* gencd_solve's status for this request */
+  int32_t status;       /* GENCD_OK, GENCD_NOT_CONVERGED or an error */
   gencd_stats stats;
   double submit_s, start_s, finish_s;  /* seconds since gencd_server_create */
 } gencd_result;
@@ -399,12 +411,26 @@ typedef struct {
 typedef struct {
   int32_t running, waiting, finished_unpolled;
   size_t arena_used, arena_bytes;
+  int64_t rounds;        /* Propose/Update launch pairs so far */
+  int64_t slot_rounds;   /* sum over rounds of the requests each advanced */
+  int64_t shared_rounds; /* rounds that advanced two or more requests */
 } gencd_server_status;
 
-/* arena: device memory owned by the caller for the server's lifetime;
- * max_slots: concurrent solves (1..256).  The device current at creation is
- * used by every worker. */
-int gencd_server_create(void *arena, size_t arena_bytes, int32_t max_slots, gencd_server **out);
+/* arena: device memory owned by the caller for the server's lifetime (the
+ * server keeps 1 MiB plus 96 B per slot of it for its work tables);
+ * max_slots: concurrent requests (1..256); stream: the rounds run on it and
+ * it must stay valid until gencd_server_destroy.  The device current at
+ * creation is used by the server's threads.  The server creates one stream
+ * of its own (admission work), events and pinned host buffers, released by
+ * gencd_server_destroy. */
+int gencd_server_create(void *arena, size_t arena_bytes, int32_t max_slots, hipStream_t stream,
+                        gencd_server **out);
+/* Arena bytes one request holds while it is admitted (its solve workspace
+ * and the best checked iterate), and the fixed part of the arena the server
+ * keeps for its work tables; an arena of gencd_server_overhead_bytes(s) plus
+ * the sum of any s requests' bytes admits those s requests together. */
+int gencd_server_request_bytes(const gencd_csc *X, const gencd_params *p, size_t *out_bytes);
+size_t gencd_server_overhead_bytes(int32_t max_slots);
 /* Non-blocking; *ticket identifies the request in its result. */
 int gencd_server_submit(gencd_server *sv, const gencd_request *req, int64_t *ticket);
 /* Moves up to max finished results to out (host).  wait_for > 0 first
@@ -414,6 +440,29 @@ int gencd_server_poll(gencd_server *sv, gencd_result *out, int32_t max, int32_t 
 int gencd_server_info(gencd_server *sv, gencd_server_status *out);
 /* Waits for every submitted request, then releases the server. */
 int gencd_server_destroy(gencd_server *sv);
+/* ------------------------------------------------------------------------
+ * Synthetic serving requests on the device (inputs of the serving
+ * benchmark; not part of a solve).  Every entry of the n x k matrix is
+ * nonzero independently with probability `density` (0 < density < 1), the
+ * nonzero values are N(0, 1), and the labels come from a ground truth w*
+ * with `support` N(0, 1) weights on non-empty columns: y = Xw* + N(0, 0.01)
+ * for GENCD_SQUARED, y = +1 with probability sigma((Xw*)_i) else -1 for
+ * GENCD_LOGISTIC.  The result depends only on (n, k, density, seed, loss,
+ * support).  Two calls, so that the caller can size row_idx and val:
+ *   gencd_gen_count writes col_ptr (device int64[k+1]) and *nnz (host),
+ *     synchronising the stream;
+ *   gencd_gen_fill writes row_idx (device int32[nnz]), val (device
+ *     float32[nnz]) and y (device float32[n]) from that col_ptr.
+ * ws: device workspace of gencd_gen_workspace_bytes(n, k) bytes, the same
+ * for both calls.  Errors: INVALID_ARG, WORKSPACE, UNSUPPORTED (nnz >= 2^31),
+ * HIP. */
+int gencd_gen_workspace_bytes(int64_t n, int64_t k, size_t *out_bytes);
+int gencd_gen_count(int64_t n, int64_t k, double density, uint64_t seed, int64_t *col_ptr,
+                    int64_t *nnz, void *ws, size_t ws_bytes, hipStream_t stream);
+int gencd_gen_fill(int64_t n, int64_t k, double density, uint64_t seed, int32_t loss,
+                   int32_t support, const int64_t *col_ptr, int32_t *row_idx, float *val, float *y,
+                   void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Host-only replay of the admission policy (capacity planning, tests):
  * request i arrives at arrival[i] (non-decreasing), needs bytes[i] of arena
  * and holds its slot for service[i] seconds; start[i] receives its start time

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgencd.so")
 SOURCES = ["gencd_kernels.hip", "gencd_solver.hip", "gencd_color.hip", "gencd_path.hip",
-           "gencd_server.hip", "gencd_tune.hip"]
+           "gencd_server.hip", "gencd_tune.hip", "gencd_gen.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -20,7 +20,6 @@
 // single-column rounds) spreads its row prefixes over the whole grid, into
 // a bitmap per frontier column in global memory; a large one takes one
 // workgroup per column with the bitmap in LDS.
-#include <hipcub/hipcub.hpp>
 #include <vector>
 
 #include "gencd_common.hpp"
@@ -36,10 +35,12 @@ constexpr int kFlatMax = 64;     // frontiers up to this size use the spread mex
 constexpr int kSG = 16;
 
 struct ColorWs {
-  uint64_t *keys_a, *keys_b;  // [max(k, nnz)]
-  int32_t *vals_a, *vals_b;   // [max(k, nnz)]
+  uint32_t *keys_a, *keys_b;  // [max(k, nnz)] radix sort keys
+  int32_t *vals_a, *vals_b;   // [max(k, nnz)] radix sort values
   int32_t *order;             // [k] column at each priority rank
   int32_t *rank;              // [k] priority rank of each column
+  int32_t *roff;              // [k+1] first slot of each rank's entries in the rank-ordered list
+  int32_t *erank;             // [nnz] priority rank of the column of each CSC entry
   int32_t *row_ptr;           // [n+1]
   int32_t *rank_at;           // [nnz] CSR slot -> column rank
   int32_t *pos_in_row;        // [nnz] CSC entry -> position in its CSR row
@@ -48,22 +49,12 @@ struct ColorWs {
   int32_t *fcnt;              // [k+1] frontier nnz counts, then offsets
   int32_t *foff;              // [k+1]
   int32_t *scan_part;
+  int32_t *rhist, *roffs;     // [radix_hist_len(max(k, nnz))] radix digit counts, offsets
   int32_t *ctl;               // [8] frontier sizes (0, 4: by round parity), max colour
                               // snapshot (1), error flag (2), max colour (3), coloured (5)
   uint32_t *gbits;            // [kFlatMax][kMexWords] colour bitmaps of a small frontier
                               // (all zero between rounds)
-  void *sort_tmp;
-  size_t sort_tmp_bytes;
 };
-
-static size_t sort_temp_bytes(int64_t items, int end_bit) {
-  size_t bytes = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, static_cast<const uint64_t *>(nullptr),
-                                     static_cast<uint64_t *>(nullptr),
-                                     static_cast<const int32_t *>(nullptr),
-                                     static_cast<int32_t *>(nullptr), int(items), 0, end_bit);
-  return bytes;
-}
 
 static size_t color_layout(int64_t n, int64_t k, int64_t nnz, void *base, ColorWs *w) {
   const size_t al = 256;
@@ -77,12 +68,14 @@ static size_t color_layout(int64_t n, int64_t k, int64_t nnz, void *base, ColorW
   };
   const int64_t m = k > nnz ? k : nnz;
   ColorWs c{};
-  c.keys_a = static_cast<uint64_t *>(take(sizeof(uint64_t) * m));
-  c.keys_b = static_cast<uint64_t *>(take(sizeof(uint64_t) * m));
+  c.keys_a = static_cast<uint32_t *>(take(sizeof(uint32_t) * m));
+  c.keys_b = static_cast<uint32_t *>(take(sizeof(uint32_t) * m));
   c.vals_a = static_cast<int32_t *>(take(sizeof(int32_t) * m));
   c.vals_b = static_cast<int32_t *>(take(sizeof(int32_t) * m));
   c.order = static_cast<int32_t *>(take(sizeof(int32_t) * k));
   c.rank = static_cast<int32_t *>(take(sizeof(int32_t) * k));
+  c.roff = static_cast<int32_t *>(take(sizeof(int32_t) * (k + 1)));
+  c.erank = static_cast<int32_t *>(take(sizeof(int32_t) * nnz));
   c.row_ptr = static_cast<int32_t *>(take(sizeof(int32_t) * (n + 1)));
   c.rank_at = static_cast<int32_t *>(take(sizeof(int32_t) * nnz));
   c.pos_in_row = static_cast<int32_t *>(take(sizeof(int32_t) * nnz));
@@ -92,60 +85,76 @@ static size_t color_layout(int64_t n, int64_t k, int64_t nnz, void *base, ColorW
   const int64_t mn = m > n ? m : n;
   c.fcnt = static_cast<int32_t *>(take(sizeof(int32_t) * (mn + 1)));
   c.foff = static_cast<int32_t *>(take(sizeof(int32_t) * (k + 1)));
-  const int64_t scan_len = mn + 1;
+  const int64_t rl = radix_hist_len(m);
+  const int64_t scan_len = mn + 1 > rl ? mn + 1 : rl;
   c.scan_part = static_cast<int32_t *>(take(sizeof(int32_t) * scan_partials_for(scan_len)));
+  c.rhist = static_cast<int32_t *>(take(sizeof(int32_t) * rl));
+  c.roffs = static_cast<int32_t *>(take(sizeof(int32_t) * rl));
   c.ctl = static_cast<int32_t *>(take(sizeof(int32_t) * 8));
   c.gbits = static_cast<uint32_t *>(take(sizeof(uint32_t) * kFlatMax * kMexWords));
-  size_t t1 = sort_temp_bytes(k, 64), t2 = sort_temp_bytes(nnz, 64);
-  c.sort_tmp_bytes = t1 > t2 ? t1 : t2;
-  c.sort_tmp = take(c.sort_tmp_bytes);
   if (w) *w = c;
   return off + al;
 }
 
+// priority key n - nnz_j: a stable sort of the columns (natural order) by it
+// gives decreasing nnz, ties by index
 __global__ __launch_bounds__(kBlock) void k_prio_keys(const int64_t *col_ptr, int64_t k, int64_t n,
-                                                       uint64_t *keys, int32_t *vals) {
+                                                       uint32_t *keys, int32_t *vals) {
   for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < k;
        j += int64_t(gridDim.x) * kBlock) {
     int64_t m = col_ptr[j + 1] - col_ptr[j];
-    keys[j] = (uint64_t(n - m) << 32) | uint64_t(j);
+    keys[j] = uint32_t(n - m);
     vals[j] = int32_t(j);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_rank_of(const int32_t *order, int64_t k, int32_t *rank) {
+// rank of every column and the nnz of the column at every rank
+__global__ __launch_bounds__(kBlock) void k_rank_of(const int32_t *order, int64_t k,
+                                                     const int64_t *col_ptr, int32_t *rank,
+                                                     int32_t *rnnz) {
   for (int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x; r < k;
-       r += int64_t(gridDim.x) * kBlock)
-    rank[order[r]] = int32_t(r);
+       r += int64_t(gridDim.x) * kBlock) {
+    const int32_t j = order[r];
+    rank[j] = int32_t(r);
+    rnnz[r] = int32_t(col_ptr[j + 1] - col_ptr[j]);
+  }
 }
 
-// one wave per column: CSR sort keys (row, rank) and row histogram
-__global__ __launch_bounds__(kBlock) void k_csr_keys(const int64_t *col_ptr, const int32_t *row_idx,
-                                                      int64_t k, const int32_t *rank, uint64_t *keys,
-                                                      int32_t *vals, int32_t *hist) {
+// One wave per rank: the CSC entries listed column by column in priority
+// order (sort key: the entry's row, value: the entry), the rank of every
+// entry's column, and the row histogram.  A stable sort of this list by row
+// leaves each row's entries in priority order.
+__global__ __launch_bounds__(kBlock) void k_csr_list(const int64_t *col_ptr, const int32_t *row_idx,
+                                                      int64_t k, const int32_t *order,
+                                                      const int32_t *roff, uint32_t *keys,
+                                                      int32_t *vals, int32_t *erank, int32_t *hist) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wid = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / kWave;
   const int64_t nw = int64_t(gridDim.x) * kBlock / kWave;
-  for (int64_t j = wid; j < k; j += nw) {
-    const uint64_t rj = uint64_t(rank[j]);
-    for (int64_t e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += kWave) {
-      const int32_t r = row_idx[e];
-      keys[e] = (uint64_t(r) << 32) | rj;
-      vals[e] = int32_t(e);
-      atomicAdd(&hist[r], 1);
+  for (int64_t r = wid; r < k; r += nw) {
+    const int32_t j = order[r];
+    const int64_t e0 = col_ptr[j], e1 = col_ptr[j + 1];
+    const int64_t p0 = roff[r];
+    for (int64_t e = e0 + lane; e < e1; e += kWave) {
+      const int32_t row = row_idx[e];
+      keys[p0 + (e - e0)] = uint32_t(row);
+      vals[p0 + (e - e0)] = int32_t(e);
+      erank[e] = int32_t(r);
+      atomicAdd(&hist[row], 1);
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_csr_fill(const uint64_t *keys, const int32_t *vals,
+__global__ __launch_bounds__(kBlock) void k_csr_fill(const uint32_t *rows, const int32_t *ents,
                                                       int64_t nnz, const int32_t *row_ptr,
-                                                      int32_t *rank_at, int32_t *pos_in_row) {
+                                                      const int32_t *erank, int32_t *rank_at,
+                                                      int32_t *pos_in_row) {
   for (int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x; q < nnz;
        q += int64_t(gridDim.x) * kBlock) {
-    const uint64_t key = keys[q];
-    const int32_t row = int32_t(key >> 32);
-    rank_at[q] = int32_t(key & 0xFFFFFFFFull);
-    pos_in_row[vals[q]] = int32_t(q) - row_ptr[row];
+    const int32_t row = int32_t(rows[q]);
+    const int32_t e = ents[q];
+    rank_at[q] = erank[e];
+    pos_in_row[e] = int32_t(q) - row_ptr[row];
   }
 }
 
@@ -532,30 +541,32 @@ int color_run(const gencd_csc *X, int32_t *color, int32_t *num_colors, void *ws_
   ColorWs w{};
   color_layout(n, k, nnz, base, &w);
   int st;
-  // priority order: decreasing nnz, ties by index (keys are unique)
+  // priority order: decreasing nnz, ties by index
   hipLaunchKernelGGL(k_prio_keys, dim3(g1(k)), dim3(kBlock), 0, s, X->col_ptr, k, n, w.keys_a,
                      w.vals_a);
-  int kbits = 32;
-  while (kbits < 64 && (uint64_t(n) >> (kbits - 32)) != 0) ++kbits;
-  size_t tb = w.sort_tmp_bytes;
-  GENCD_HIP(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.keys_a, w.keys_b, w.vals_a,
-                                               w.order, int(k), 0, kbits, s));
-  hipLaunchKernelGGL(k_rank_of, dim3(g1(k)), dim3(kBlock), 0, s, w.order, k, w.rank);
-  // CSR with rows sorted by priority rank (keys (row, rank) are unique)
+  int ob = 0;
+  st = radix_sort_pairs(w.keys_a, w.vals_a, w.keys_b, w.vals_b, k, bits_for(uint64_t(n)), w.rhist,
+                        w.roffs, w.scan_part, s, &ob);
+  if (st) return st;
+  st = copy_i32(w.order, ob ? w.vals_b : w.vals_a, k, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_rank_of, dim3(g1(k)), dim3(kBlock), 0, s, w.order, k, X->col_ptr, w.rank,
+                     w.fcnt);
+  st = scan_exclusive(w.fcnt, w.roff, k, w.scan_part, s);
+  if (st) return st;
+  // CSR with every row's entries in priority order
   st = fill_i32(w.fcnt, n + 1, 0, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_csr_keys, dim3(g1(k * kWave, 8192)), dim3(kBlock), 0, s, X->col_ptr,
-                     X->row_idx, k, w.rank, w.keys_a, w.vals_a, w.fcnt);
+  hipLaunchKernelGGL(k_csr_list, dim3(g1(k * kWave, 8192)), dim3(kBlock), 0, s, X->col_ptr,
+                     X->row_idx, k, w.order, w.roff, w.keys_a, w.vals_a, w.erank, w.fcnt);
   st = scan_exclusive(w.fcnt, w.row_ptr, n, w.scan_part, s);
   if (st) return st;
   if (nnz > 0) {
-    int rbits = 32;
-    while (rbits < 64 && (uint64_t(n) >> (rbits - 32)) != 0) ++rbits;
-    tb = w.sort_tmp_bytes;
-    GENCD_HIP(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.keys_a, w.keys_b, w.vals_a,
-                                                 w.vals_b, int(nnz), 0, rbits, s));
-    hipLaunchKernelGGL(k_csr_fill, dim3(g1(nnz)), dim3(kBlock), 0, s, w.keys_b, w.vals_b, nnz,
-                       w.row_ptr, w.rank_at, w.pos_in_row);
+    st = radix_sort_pairs(w.keys_a, w.vals_a, w.keys_b, w.vals_b, nnz, bits_for(uint64_t(n - 1)),
+                          w.rhist, w.roffs, w.scan_part, s, &ob);
+    if (st) return st;
+    hipLaunchKernelGGL(k_csr_fill, dim3(g1(nnz)), dim3(kBlock), 0, s, ob ? w.keys_b : w.keys_a,
+                       ob ? w.vals_b : w.vals_a, nnz, w.row_ptr, w.erank, w.rank_at, w.pos_in_row);
   }
   st = fill_i32(w.ctl, 8, 0, s);
   if (st) return st;
@@ -630,8 +641,8 @@ struct BalanceWs {
   uint32_t *keys_a, *keys_b;  // [k]
   int32_t *vals_a, *vals_b;   // [k]
   int32_t *size, *first, *parts, *off;  // [C+1]
-  void *sort_tmp;
-  size_t sort_tmp_bytes;
+  int32_t *rhist, *roffs;     // [radix_hist_len(k)]
+  int32_t *scan_part;
 };
 
 static size_t balance_layout(int64_t k, int64_t C, void *base, BalanceWs *w) {
@@ -653,13 +664,10 @@ static size_t balance_layout(int64_t k, int64_t C, void *base, BalanceWs *w) {
   c.first = static_cast<int32_t *>(take(sizeof(int32_t) * (C + 1)));
   c.parts = static_cast<int32_t *>(take(sizeof(int32_t) * (C + 1)));
   c.off = static_cast<int32_t *>(take(sizeof(int32_t) * (C + 1)));
-  size_t tb = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, static_cast<const uint32_t *>(nullptr),
-                                           static_cast<uint32_t *>(nullptr),
-                                           static_cast<const int32_t *>(nullptr),
-                                           static_cast<int32_t *>(nullptr), int(k), 0, 32);
-  c.sort_tmp_bytes = tb;
-  c.sort_tmp = take(tb);
+  const int64_t rl = radix_hist_len(k);
+  c.rhist = static_cast<int32_t *>(take(sizeof(int32_t) * rl));
+  c.roffs = static_cast<int32_t *>(take(sizeof(int32_t) * rl));
+  c.scan_part = static_cast<int32_t *>(take(sizeof(int32_t) * scan_partials_for(rl)));
   if (w) *w = c;
   return off + al;
 }
@@ -720,9 +728,11 @@ int balance_run(const gencd_csc *X, const int32_t *color, int32_t C, int64_t cap
   hipLaunchKernelGGL(k_bal_keys, dim3(g1(k)), dim3(kBlock), 0, s, X->col_ptr, k, color, C, w.keys_a,
                      w.vals_a, w.size, w.size + C);
   GENCD_HIP(hipGetLastError());
-  size_t tb = w.sort_tmp_bytes;
-  GENCD_HIP(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.keys_a, w.keys_b, w.vals_a,
-                                               w.vals_b, int(k), 0, 32, s));
+  // stable by colour (key C: empty columns, last), so each class keeps column order
+  int ob = 0;
+  st = radix_sort_pairs(w.keys_a, w.vals_a, w.keys_b, w.vals_b, k, bits_for(uint64_t(C)), w.rhist,
+                        w.roffs, w.scan_part, s, &ob);
+  if (st) return st;
   // parts and numbering on the host (C + 1 counters)
   std::vector<int32_t> size(size_t(C) + 1), first(size_t(C) + 1), parts(size_t(C) + 1),
       off(size_t(C) + 1);
@@ -748,8 +758,9 @@ int balance_run(const gencd_csc *X, const int32_t *color, int32_t C, int64_t cap
   GENCD_HIP(hipMemcpyAsync(w.first, first.data(), sizeof(int32_t) * size_t(C), hipMemcpyHostToDevice, s));
   GENCD_HIP(hipMemcpyAsync(w.parts, parts.data(), sizeof(int32_t) * size_t(C), hipMemcpyHostToDevice, s));
   GENCD_HIP(hipMemcpyAsync(w.off, off.data(), sizeof(int32_t) * size_t(C), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_bal_assign, dim3(g1(k)), dim3(kBlock), 0, s, X->col_ptr, k, color, w.keys_b,
-                     w.vals_b, w.size, w.first, w.parts, w.off, C, out);
+  hipLaunchKernelGGL(k_bal_assign, dim3(g1(k)), dim3(kBlock), 0, s, X->col_ptr, k, color,
+                     ob ? w.keys_b : w.keys_a, ob ? w.vals_b : w.vals_a, w.size, w.first, w.parts,
+                     w.off, C, out);
   GENCD_HIP(hipGetLastError());
   GENCD_HIP(hipStreamSynchronize(s));  // the host vectors above must outlive the copies
   *num_out = int32_t(total);

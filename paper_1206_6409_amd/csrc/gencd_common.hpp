@@ -188,7 +188,8 @@ struct Ws {
   int32_t *tmp_cnt2;     // [k+1] scratch counts
   int32_t *scan_part;    // [scan partials]
   int32_t *cls_off;      // [k+1] colour class offsets (COLORING)
-  int32_t *cls_mem;      // [k] live members by colour
+  int32_t *cls_mem;      // [k] live members by colour, column order inside a class
+  int32_t *rad_h, *rad_o;  // [radix_hist_len(k)] digit counts and offsets of a radix sort
   // per-epoch order
   int32_t *col_of_pos;   // [k]
   int32_t *soff;         // [k+1] scratch (live-column scan at set-up)
@@ -253,5 +254,21 @@ size_t scan_partials_for(int64_t len);
 // Exclusive scan of int32 counts: out[0..len] (out[len] = total).
 int scan_exclusive(const int32_t *in, int32_t *out, int64_t len, int32_t *partials,
                    hipStream_t s);
+
+// Stable LSD radix sort of m (uint32 key, int32 value) pairs on the low
+// `bits` key bits (8 per pass).  (k0, v0) hold the input and (k1, v1) are
+// scratch of length m; the sorted pairs end in buffer *out_buf (0: k0/v0,
+// 1: k1/v1).  hist and offs hold radix_hist_len(m) int32 each, part
+// scan_partials_for(radix_hist_len(m)).
+int64_t radix_hist_len(int64_t m);
+int radix_sort_pairs(uint32_t *k0, int32_t *v0, uint32_t *k1, int32_t *v1, int64_t m, int bits,
+                     int32_t *hist, int32_t *offs, int32_t *part, hipStream_t s, int *out_buf);
+
+// Number of bits needed for values up to v (0 for v = 0).
+inline int bits_for(uint64_t v) {
+  int b = 0;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
 
 }  // namespace gencd

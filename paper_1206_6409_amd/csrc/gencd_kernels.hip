@@ -119,6 +119,118 @@ int scan_exclusive(const int32_t *in, int32_t *out, int64_t len, int32_t *part, 
 }
 
 // ---------------------------------------------------------------------------
+// Stable LSD radix sort of (uint32 key, int32 value) pairs, 8 key bits per
+// pass.  A pass has three steps: every tile of kRadixTile items counts its
+// digits (k_radix_hist, digit-major so that one exclusive scan turns the
+// counts into output offsets), the scan, and a stable scatter
+// (k_radix_scatter).  The scatter walks its tile in input order, kBlock
+// items per round; inside a round each wave finds the lanes holding the
+// same digit from eight ballots (one per digit bit), so an item's rank is
+// the digit's count from earlier rounds and earlier waves plus its peers in
+// lower lanes.
+// ---------------------------------------------------------------------------
+constexpr int kRadixBins = 256;
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kBlock * kRadixItems;
+static_assert(kRadixBins == kBlock, "one digit counter per thread");
+
+int64_t radix_hist_len(int64_t m) {
+  const int64_t tiles = (m + kRadixTile - 1) / kRadixTile;
+  return int64_t(kRadixBins) * (tiles > 0 ? tiles : 1) + 1;
+}
+
+// Lanes of the wave whose 9-bit digit equals this lane's (bit 8 marks an
+// item past the end).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d) {
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 9; ++b) {
+    const uint64_t bal = __ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? bal : ~bal;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t *keys, int64_t m, int shift,
+                                                        int64_t ntiles, int32_t *hist) {
+  __shared__ int32_t h[kRadixBins];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = int(threadIdx.x) & (kWave - 1);
+  const int64_t t0 = int64_t(blockIdx.x) * kRadixTile;
+  for (int i = 0; i < kRadixItems; ++i) {
+    const int64_t q = t0 + int64_t(i) * kBlock + threadIdx.x;
+    const uint32_t d = q < m ? (keys[q] >> shift) & 0xFFu : 0x100u;
+    const uint64_t peers = digit_peers(d);  // one LDS atomic per distinct digit of a wave
+    if (d < 0x100u && __popcll(peers & ((1ull << lane) - 1)) == 0)
+      atomicAdd(&h[d], int32_t(__popcll(peers)));
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *kin, const int32_t *vin,
+                                                           int64_t m, int shift, int64_t ntiles,
+                                                           const int32_t *offs, uint32_t *kout,
+                                                           int32_t *vout) {
+  constexpr int NW = kBlock / kWave;
+  __shared__ int32_t base[kRadixBins];
+  __shared__ int32_t goff[kRadixBins];
+  __shared__ int32_t wcnt[NW][kRadixBins];
+  const int t = int(threadIdx.x), lane = t & (kWave - 1), wv = t / kWave;
+  base[t] = 0;
+  goff[t] = offs[int64_t(t) * ntiles + blockIdx.x];
+  const int64_t t0 = int64_t(blockIdx.x) * kRadixTile;
+  for (int i = 0; i < kRadixItems; ++i) {
+    const int64_t q = t0 + int64_t(i) * kBlock + t;
+    const bool ok = q < m;
+    const uint32_t key = ok ? kin[q] : 0u;
+    const int32_t val = ok ? vin[q] : 0;
+    const uint32_t d = ok ? (key >> shift) & 0xFFu : 0x100u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;  // column t: only this thread touches it here
+    __syncthreads();
+    const uint64_t peers = digit_peers(d);
+    const int below = __popcll(peers & ((1ull << lane) - 1));
+    if (ok && below == 0) wcnt[wv][d] = __popcll(peers);
+    __syncthreads();
+    if (ok) {
+      int32_t r = base[d] + below;
+      for (int w = 0; w < wv; ++w) r += wcnt[w][d];
+      const int64_t dst = int64_t(goff[d]) + r;
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+    int32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) add += wcnt[w][t];
+    base[t] += add;  // read after the next round's first barrier
+  }
+}
+
+int radix_sort_pairs(uint32_t *k0, int32_t *v0, uint32_t *k1, int32_t *v1, int64_t m, int bits,
+                     int32_t *hist, int32_t *offs, int32_t *part, hipStream_t s, int *out_buf) {
+  *out_buf = 0;
+  if (m <= 0 || bits <= 0) return GENCD_OK;
+  const int64_t ntiles = (m + kRadixTile - 1) / kRadixTile;
+  uint32_t *kb[2] = {k0, k1};
+  int32_t *vb[2] = {v0, v1};
+  int cur = 0;
+  for (int shift = 0; shift < bits && shift < 32; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(unsigned(ntiles)), dim3(kBlock), 0, s, kb[cur], m, shift,
+                       ntiles, hist);
+    const int st = scan_exclusive(hist, offs, int64_t(kRadixBins) * ntiles, part, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(unsigned(ntiles)), dim3(kBlock), 0, s, kb[cur],
+                       vb[cur], m, shift, ntiles, offs, kb[cur ^ 1], vb[cur ^ 1]);
+    cur ^= 1;
+  }
+  *out_buf = cur;
+  return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
 // Small utility kernels
 // ---------------------------------------------------------------------------
 template <typename T>

@@ -15,6 +15,7 @@
 
 #include "gencd_common.hpp"
 #include "gencd_kernels.hpp"
+#include "gencd_solver.hpp"
 
 namespace gencd {
 
@@ -48,7 +49,9 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   Carver c{static_cast<char *>(base)};
   Ws w{};
   const int64_t ml = max_lpieces_for(k, nnz, piece, short_max);
-  const int64_t scan_len = ml > k + 1 ? ml : k + 1;
+  const int64_t rl = radix_hist_len(k);
+  int64_t scan_len = ml > k + 1 ? ml : k + 1;
+  if (rl > scan_len) scan_len = rl;
   w.max_lpieces = ml;
   w.scan_part_len = scan_partials_for(scan_len);
   w.c = c.take<float>(k);
@@ -63,6 +66,8 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   w.scan_part = c.take<int32_t>(int64_t(w.scan_part_len));
   w.cls_off = c.take<int32_t>(k + 1);
   w.cls_mem = c.take<int32_t>(k);
+  w.rad_h = c.take<int32_t>(rl);
+  w.rad_o = c.take<int32_t>(rl);
   w.col_of_pos = c.take<int32_t>(k);
   w.soff = c.take<int32_t>(k + 1);
   w.loff = c.take<int32_t>(k + 1);
@@ -102,8 +107,6 @@ size_t workspace_layout(int64_t n, int64_t k, int64_t nnz, int piece, int short_
   if (ws) *ws = w;
   return c.off + kAlign;
 }
-
-namespace {
 
 bool csc_ok(const gencd_csc *X) {
   if (!X || X->n <= 0 || X->k <= 0 || X->nnz < 0) return false;
@@ -163,17 +166,6 @@ int params_ok(const gencd_params *p, bool need_rule) {
 }
 
 // Device -> host copy of the reduction block, then wait for the stream.
-struct Red {
-  double loss_sum, l1;
-  unsigned long long kkt_bits, nnz_w;
-  unsigned long long gmax_bits;
-  double dual_sum;
-  unsigned long long pad[2];
-  unsigned long long acc_nnz, acc_cnt, bad, spare;
-  unsigned long long pad2[4];
-};
-static_assert(sizeof(Red) == 16 * 8, "reduction block layout");
-
 int read_red(const Ws &w, hipStream_t s, Red *out) {
   GENCD_HIP(hipMemcpyAsync(out, w.red, sizeof(Red), hipMemcpyDeviceToHost, s));
   GENCD_HIP(hipStreamSynchronize(s));
@@ -186,17 +178,6 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
-struct Setup {
-  Ws ws{};
-  int piece = kDefaultPiece, group = kDefaultGroup;
-  int32_t n_short = 0, n_lpieces = 0;
-  int64_t k_live = 0;
-  std::vector<double> rho_hist;  // spectral-radius estimate after each power iteration
-  double rho = 0.0;
-  std::vector<double> brho;      // Block Shotgun: rho_b of every preset block
-  std::vector<int32_t> bp;       // Block Shotgun: P_b* of every preset block
-};
-
 // |J| = floor(k_live / (2 rho)) clamped to [1, kRhoSelectCap] (section 4.1).
 int64_t pstar_of(int64_t k_live, double rho) {
   if (!(rho > 0.0)) return 1;
@@ -206,12 +187,9 @@ int64_t pstar_of(int64_t k_live, double rho) {
   return int64_t(q);
 }
 
-// Preprocessing: validation, piece decomposition, live columns, curvature
-// and (rho_iters > 0) the spectral-radius estimate.  Writes only the
-// workspace.  y may be null only when need_y is false (no label check).
 int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, void *ws_base,
-          size_t ws_bytes, bool validate_matrix, hipStream_t s, Setup *out, int rho_iters = 0,
-          bool need_y = true, int64_t nblocks = 0, int block_iters = kRhoIters) {
+          size_t ws_bytes, bool validate_matrix, hipStream_t s, Setup *out, int rho_iters,
+          bool need_y, int64_t nblocks, int block_iters) {
   if (!csc_ok(X) || (need_y && !y)) return GENCD_ERR_INVALID_ARG;
   if (rho_iters < 0 || rho_iters > kRhoMaxIters) return GENCD_ERR_INVALID_ARG;
   if (nblocks < 0 || nblocks > kMaxBlocks || block_iters < 1 || block_iters > kBlockRhoMaxIters)
@@ -296,23 +274,18 @@ int setup(const gencd_csc *X, const float *y, int loss, const gencd_params *p, v
   return fill_i32(w.acc, X->k, 0, s);
 }
 
-struct CheckOut {
-  double objective, kkt, gap;
-  int64_t nnz_w;
-  unsigned long long acc_nnz, acc_cnt;
-  double drift_rel;  // re-syncing checks: max_i |z_i - z64_i| / rms(z64) (0 if z64 = 0)
-};
-
-int run_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
-              const Setup &su, bool resync, hipStream_t s, CheckOut *out) {
+int enqueue_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
+                  const Setup &su, bool resync, hipStream_t s, double *host_rep, Red *host_red) {
   int st = launch_check(X, y, loss, lam, w, su.n_short, su.n_lpieces, su.ws, resync, s);
   if (st) return st;
-  Red r{};
-  // the replicas first (same stream, so read_red's wait covers both copies)
-  double rep[kChkRep * 16];
-  GENCD_HIP(hipMemcpyAsync(rep, su.ws.rrep, sizeof(rep), hipMemcpyDeviceToHost, s));
-  st = read_red(su.ws, s, &r);
-  if (st) return st;
+  GENCD_HIP(hipMemcpyAsync(host_rep, su.ws.rrep, sizeof(double) * kChkRep * 16,
+                           hipMemcpyDeviceToHost, s));
+  GENCD_HIP(hipMemcpyAsync(host_red, su.ws.red, sizeof(Red), hipMemcpyDeviceToHost, s));
+  return GENCD_OK;
+}
+
+void fold_check(const double *rep, const Red &red, int64_t n, double lam, CheckOut *out) {
+  Red r = red;
   r.loss_sum = r.l1 = r.dual_sum = 0.0;
   r.kkt_bits = r.nnz_w = r.gmax_bits = 0ull;
   unsigned long long drift_bits = 0ull;
@@ -330,16 +303,28 @@ int run_check(const gencd_csc *X, const float *y, int loss, double lam, const fl
     drift_bits = std::max(drift_bits, u[6]);
     zsq += f[7];
   }
-  const double rms = std::sqrt(zsq / double(X->n));
+  const double rms = std::sqrt(zsq / double(n));
   out->drift_rel = rms > 0.0 ? bits_to_double(drift_bits) / rms : 0.0;
-  out->objective = r.loss_sum / double(X->n) + lam * r.l1;
+  out->objective = r.loss_sum / double(n) + lam * r.l1;
   out->kkt = bits_to_double(r.kkt_bits);
-  out->gap = out->objective - r.dual_sum / double(X->n);
+  out->gap = out->objective - r.dual_sum / double(n);
   out->nnz_w = int64_t(r.nnz_w);
   out->acc_nnz = r.acc_nnz;
   out->acc_cnt = r.acc_cnt;
+}
+
+int run_check(const gencd_csc *X, const float *y, int loss, double lam, const float *w,
+              const Setup &su, bool resync, hipStream_t s, CheckOut *out) {
+  double rep[kChkRep * 16];
+  Red r{};
+  int st = enqueue_check(X, y, loss, lam, w, su, resync, s, rep, &r);
+  if (st) return st;
+  GENCD_HIP(hipStreamSynchronize(s));
+  fold_check(rep, r, X->n, lam, out);
   return GENCD_OK;
 }
+
+namespace {
 
 bool converged(const gencd_params *p, const CheckOut &ck) {
   if (!(ck.kkt <= p->kkt_tol)) return false;
@@ -388,46 +373,52 @@ IterArgs base_args(const gencd_csc *X, const float *y, const gencd_params *p, co
   return a;
 }
 
-// Colour classes: live members of every colour (order inside a class does
-// not affect the result: the members' rows are disjoint).
-__global__ void k_class_count(const int32_t *live, int64_t k_live, const int32_t *color,
-                              int32_t C, int32_t *cnt, unsigned long long *bad) {
+// Colour classes: the live columns stably sorted by colour (members of a
+// class in column order, though any order gives the same iteration: the
+// members' rows are disjoint), and the class offsets read off the sorted
+// keys.  No counter is shared between columns.
+__global__ void k_class_keys(const int32_t *live, int64_t k_live, const int32_t *color, int32_t C,
+                             uint32_t *keys, int32_t *vals, unsigned long long *bad) {
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < k_live;
        t += int64_t(gridDim.x) * blockDim.x) {
-    int32_t c = color[live[t]];
-    if (c < 0 || c >= C)
-      atomicOr(bad, 4ull);
-    else
-      atomicAdd(&cnt[c], 1);
+    const int32_t j = live[t];
+    int32_t c = color[j];
+    if (c < 0 || c >= C) {
+      atomicOr(bad, 4ull);  // reported as INVALID_ARG
+      c = 0;
+    }
+    keys[t] = uint32_t(c);
+    vals[t] = j;
   }
 }
 
-__global__ void k_class_fill(const int32_t *live, int64_t k_live, const int32_t *color, int32_t C,
-                             const int32_t *off, int32_t *fill, int32_t *mem) {
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < k_live;
+// off[c] = first sorted position with colour >= c, for c in [0, C]
+__global__ void k_class_bounds(const uint32_t *keys, int64_t k_live, int32_t C, int32_t *off) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t <= k_live;
        t += int64_t(gridDim.x) * blockDim.x) {
-    int32_t j = live[t];
-    int32_t c = color[j];
-    if (c < 0 || c >= C) continue;
-    int32_t pos = atomicAdd(&fill[c], 1);
-    mem[off[c] + pos] = j;
+    const int64_t lo = t == 0 ? 0 : int64_t(keys[t - 1]) + 1;
+    const int64_t hi = t == k_live ? int64_t(C) : int64_t(keys[t]);
+    for (int64_t c = lo; c <= hi; ++c) off[c] = int32_t(t);
   }
 }
 
 int build_classes(const Setup &su, const int32_t *color, int32_t C, hipStream_t s,
                   std::vector<int32_t> *sizes) {
   const Ws &w = su.ws;
-  int st = fill_i32(w.tmp_cnt, C + 1, 0, s);
-  if (st) return st;
+  // sort buffers: set-up scratch that the epoch order overwrites later
+  uint32_t *k0 = reinterpret_cast<uint32_t *>(w.tmp_cnt), *k1 = reinterpret_cast<uint32_t *>(w.col_of_pos);
+  int32_t *v0 = w.tmp_cnt2, *v1 = w.soff;
   unsigned grid = unsigned(std::min<int64_t>((su.k_live + 255) / 256 + 1, 4096));
-  hipLaunchKernelGGL(k_class_count, dim3(grid), dim3(256), 0, s, w.live, su.k_live, color, C,
-                     w.tmp_cnt, reinterpret_cast<unsigned long long *>(w.red) + 10);
-  st = scan_exclusive(w.tmp_cnt, w.cls_off, C, w.scan_part, s);
+  hipLaunchKernelGGL(k_class_keys, dim3(grid), dim3(256), 0, s, w.live, su.k_live, color, C, k0,
+                     v0, reinterpret_cast<unsigned long long *>(w.red) + 10);
+  int ob = 0;
+  int st = radix_sort_pairs(k0, v0, k1, v1, su.k_live, bits_for(uint64_t(C - 1)), w.rad_h, w.rad_o,
+                            w.scan_part, s, &ob);
   if (st) return st;
-  st = fill_i32(w.tmp_cnt, C + 1, 0, s);
+  st = copy_i32(w.cls_mem, ob ? v1 : v0, su.k_live, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_class_fill, dim3(grid), dim3(256), 0, s, w.live, su.k_live, color, C,
-                     w.cls_off, w.tmp_cnt, w.cls_mem);
+  hipLaunchKernelGGL(k_class_bounds, dim3(grid), dim3(256), 0, s, ob ? k1 : k0, su.k_live, C,
+                     w.cls_off);
   GENCD_HIP(hipGetLastError());
   std::vector<int32_t> off(size_t(C) + 1);
   GENCD_HIP(hipMemcpyAsync(off.data(), w.cls_off, sizeof(int32_t) * (C + 1),

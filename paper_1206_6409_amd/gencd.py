@@ -94,8 +94,16 @@ _SIGS = {
     "gencd_path_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "gencd_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_char_p,
                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
-    "gencd_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]),
+    "gencd_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gencd_gen_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_void_p]),
+    "gencd_gen_count": (C.c_int, [C.c_int64, C.c_int64, C.c_double, C.c_uint64, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "gencd_gen_fill": (C.c_int, [C.c_int64, C.c_int64, C.c_double, C.c_uint64, C.c_int32, C.c_int32,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_size_t, C.c_void_p]),
     "gencd_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_server_request_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gencd_server_overhead_bytes": (C.c_size_t, [C.c_int32]),
     "gencd_server_poll": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "gencd_server_info": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gencd_server_destroy": (C.c_int, [C.c_void_p]),
@@ -400,22 +408,43 @@ class Result(C.Structure):
 
 class ServerStatus(C.Structure):
     _fields_ = [("running", C.c_int32), ("waiting", C.c_int32), ("finished_unpolled", C.c_int32),
-                ("arena_used", C.c_size_t), ("arena_bytes", C.c_size_t)]
+                ("arena_used", C.c_size_t), ("arena_bytes", C.c_size_t),
+                ("rounds", C.c_int64), ("slot_rounds", C.c_int64), ("shared_rounds", C.c_int64)]
 
 
 class Server:
-    """Continuous-batching solve server over a torch-owned device arena."""
+    """Continuous-batching solve server over a torch-owned device arena; its
+    rounds run on `stream` (a new torch stream of default priority when
+    None)."""
 
-    def __init__(self, arena_bytes, max_slots=8, device=None):
+    def __init__(self, arena_bytes, max_slots=8, device=None, stream=None):
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
         self._h = C.c_void_p()
         self._keep = {}
+        torch.cuda.current_stream(dev).synchronize()  # the arena and inputs exist before rounds
         _check(lib().gencd_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots),
-                                         C.byref(self._h)), "gencd_server_create")
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(self._h)),
+               "gencd_server_create")
+
+    @staticmethod
+    def request_bytes(X: Matrix, params: Params):
+        """Arena bytes the request holds while admitted."""
+        out = C.c_size_t()
+        _check(lib().gencd_server_request_bytes(X.ref, C.byref(params), C.byref(out)),
+               "gencd_server_request_bytes")
+        return out.value
+
+    @staticmethod
+    def overhead_bytes(max_slots):
+        """Fixed arena bytes of the server's work tables."""
+        return int(lib().gencd_server_overhead_bytes(int(max_slots)))
 
     def submit(self, X: Matrix, y, params: Params, w, z=None, tag=0):
-        """Non-blocking; X, y, w (and z) must stay alive until the result is polled."""
+        """Non-blocking; X, y, w (and z) must stay alive until the result is
+        polled.  Work on torch's current stream that produced them must be
+        complete (the server's streams do not wait for it)."""
         req = Request(X._s, y.data_ptr(), params, w.data_ptr(),
                       z.data_ptr() if z is not None else None, int(tag))
         t = C.c_int64()
@@ -434,6 +463,9 @@ class Server:
         return out
 
     def info(self):
+        """running, waiting, finished_unpolled, arena_used, arena_bytes, rounds
+        (Propose/Update launch pairs), slot_rounds (sum of the requests each
+        round advanced) and shared_rounds (rounds advancing two or more)."""
         s = ServerStatus()
         _check(lib().gencd_server_info(self._h, C.byref(s)), "gencd_server_info")
         return {f: getattr(s, f) for f, _ in s._fields_}
@@ -448,6 +480,29 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def generate_request(n, k, density, loss, seed, support=50, device=None):
+    """A synthetic serving request generated on the device (Bernoulli(density)
+    pattern, N(0, 1) values, labels from a `support`-sparse ground truth):
+    (Matrix, y).  Runs on torch's current stream."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    nb = C.c_size_t()
+    _check(lib().gencd_gen_workspace_bytes(int(n), int(k), C.byref(nb)), "gencd_gen_workspace_bytes")
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    col_ptr = torch.empty(int(k) + 1, dtype=torch.int64, device=dev)
+    nnz = C.c_int64()
+    _check(lib().gencd_gen_count(int(n), int(k), float(density), C.c_uint64(seed).value,
+                                 _ptr(col_ptr), C.byref(nnz), _ptr(ws), ws.numel(), _stream()),
+           "gencd_gen_count")
+    row_idx = torch.empty(max(int(nnz.value), 1), dtype=torch.int32, device=dev)[:int(nnz.value)]
+    val = torch.empty(max(int(nnz.value), 1), dtype=torch.float32, device=dev)[:int(nnz.value)]
+    y = torch.empty(int(n), dtype=torch.float32, device=dev)
+    _check(lib().gencd_gen_fill(int(n), int(k), float(density), C.c_uint64(seed).value, int(loss),
+                                int(support), _ptr(col_ptr), _ptr(row_idx) if nnz.value else None,
+                                _ptr(val) if nnz.value else None, _ptr(y), _ptr(ws), ws.numel(),
+                                _stream()), "gencd_gen_fill")
+    return Matrix(int(n), int(k), col_ptr, row_idx, val), y
 
 
 def server_plan(arena_bytes, max_slots, bytes_, arrival, service):

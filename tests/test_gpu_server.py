@@ -1,6 +1,7 @@
 """The continuous-batching server on the GPU: every result equals the same
-solve run alone (objective within 1e-6 of it and of the oracle), under
-concurrency, backpressure and failures."""
+solve run alone (objective within 1e-6 of it and of the oracle), requests
+advance together in shared rounds, and backpressure and failures stay
+per request."""
 import numpy as np
 import pytest
 import torch
@@ -26,9 +27,16 @@ def _requests(count, seed):
     return out
 
 
-def _params(P, lam, flags=0):
-    return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=256, seed=9, tol=1e-8,
+def _params(P_loss, lam, flags=0, select=256, tol=1e-8):
+    return G.make_params(P_loss, lam, rule=G.SHOTGUN, select_size=select, seed=9, tol=tol,
                          max_epochs=50000, flags=flags)
+
+
+def _drain(srv, count):
+    out = []
+    while len(out) < count:
+        out += srv.poll(wait_for=1)
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -37,29 +45,29 @@ def reqs():
 
 
 def test_server_results_equal_alone(reqs):
+    print("CASE server equal alone", flush=True)
     dev = []
     for r, P, Xo, lam in reqs:
-        X = G.Matrix.of(P)
-        y = torch.as_tensor(P.y, device=DEV)
-        dev.append((X, y))
+        dev.append((G.Matrix.of(P), torch.as_tensor(P.y, device=DEV)))
     alone = []
     for (r, P, Xo, lam), (X, y) in zip(reqs, dev):
-        res = G.solve(X, y, _params(P, lam))
+        res = G.solve(X, y, _params(P.loss, lam))
         assert res.status == G.OK
         alone.append(res.stats["objective"])
-    biggest = max(G.workspace_bytes(X, _params(P, lam)) for (r, P, Xo, lam), (X, y) in zip(reqs, dev))
-    srv = G.Server(arena_bytes=3 * biggest + (1 << 20), max_slots=4)
-    ws = []
+    need = sorted(G.Server.request_bytes(X, _params(P.loss, lam))
+                  for (r, P, Xo, lam), (X, y) in zip(reqs, dev))
+    srv = G.Server(arena_bytes=G.Server.overhead_bytes(4) + sum(need[-3:]) + 4096, max_slots=4)
+    ws, zs = [], []
     for i, ((r, P, Xo, lam), (X, y)) in enumerate(zip(reqs, dev)):
-        w = torch.empty(P.k, dtype=torch.float32, device=DEV)
-        ws.append(w)
-        srv.submit(X, y, _params(P, lam), w, tag=i)
-    results = []
-    while len(results) < len(reqs):
-        results += srv.poll(wait_for=1)
+        ws.append(torch.empty(P.k, dtype=torch.float32, device=DEV))
+        zs.append(torch.empty(P.n, dtype=torch.float32, device=DEV))
+    torch.cuda.synchronize()
+    for i, ((r, P, Xo, lam), (X, y)) in enumerate(zip(reqs, dev)):
+        srv.submit(X, y, _params(P.loss, lam), ws[i], zs[i], tag=i)
+    results = _drain(srv, len(reqs))
+    info = srv.info()
     srv.close()
     assert sorted(r["user_tag"] for r in results) == list(range(len(reqs)))
-    overlap = False
     for res in results:
         i = res["user_tag"]
         r, P, Xo, lam = reqs[i]
@@ -69,34 +77,103 @@ def test_server_results_equal_alone(reqs):
         assert abs(st["objective"] - alone[i]) <= 1e-6 * abs(alone[i])
         oc = O.check(Xo, P.y, P.loss, lam, ws[i].cpu().numpy().astype(np.float64))
         assert oc.kkt <= 1e-8 * (1 + 1e-6)
+        assert st["objective"] == pytest.approx(oc.objective, rel=1e-12)
+        z = zs[i].double().cpu().numpy()
+        assert np.max(np.abs(z - oc.z) / (np.abs(oc.z) + np.sqrt(np.mean(oc.z ** 2)))) <= 1e-6
         assert res["start_s"] >= res["submit_s"] and res["finish_s"] >= res["start_s"]
-    # several requests ran at the same time
-    iv = sorted((r["start_s"], r["finish_s"]) for r in results)
-    overlap = any(b[0] < a[1] for a, b in zip(iv[:-1], iv[1:]))
-    assert overlap
+    # several requests advanced in the same launches
+    assert info["rounds"] > 0 and info["shared_rounds"] > 0, info
+    assert info["slot_rounds"] >= 1.5 * info["rounds"], info
+
+
+# Three requests drawn from the full serving ranges (n in 1k..50k, k in
+# 1k..200k, density 0.1%..2%), generated on the device.
+FULL = [(50000, 200000, 0.002, synth.LOGISTIC, 0.1, 501),
+        (12000, 150000, 0.01, synth.SQUARED, 0.05, 502),
+        (45000, 30000, 0.02, synth.LOGISTIC, 0.2, 503)]
+
+
+def test_server_full_range_requests_same_alone_and_in_the_mix(reqs):
+    print("CASE server full range alone vs mix", flush=True)
+    big = []
+    for n, k, d, loss, ratio, seed in FULL:
+        X, y = G.generate_request(n, k, d, loss, seed)
+        lam = ratio * G.lambda_max(X, y, loss)
+        big.append((X, y, loss, lam))
+    small = [(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV), P.loss, lam)
+             for (r, P, Xo, lam) in reqs[:6]]
+    torch.cuda.synchronize()
+    allreq = big + small
+
+    def run(which, slots):
+        need = [G.Server.request_bytes(allreq[i][0], _params(allreq[i][2], allreq[i][3], tol=1e-7,
+                                                             select=0))
+                for i in which]
+        srv = G.Server(arena_bytes=G.Server.overhead_bytes(slots) + sum(sorted(need)[-slots:]) + 4096,
+                       max_slots=slots)
+        outs = {}
+        for i in which:
+            X, y, loss, lam = allreq[i]
+            outs[i] = (torch.empty(X.k, dtype=torch.float32, device=DEV),
+                       torch.empty(X.n, dtype=torch.float32, device=DEV))
+        torch.cuda.synchronize()
+        for i in which:
+            X, y, loss, lam = allreq[i]
+            srv.submit(X, y, _params(loss, lam, tol=1e-7, select=0), outs[i][0], outs[i][1], tag=i)
+        res = {r["user_tag"]: r for r in _drain(srv, len(which))}
+        info = srv.info()
+        srv.close()
+        return res, outs, info
+
+    alone = {}
+    for i in range(len(big)):  # each large request on its own
+        r, o, _ = run([i], 1)
+        alone[i] = (r[i], o[i])
+    mix, outs, info = run(list(range(len(allreq))), 6)
+    print("mixed run:", info, flush=True)
+    # the short requests finish early, so the long ones end alone; many
+    # launches still advanced several requests at once
+    assert info["shared_rounds"] >= 100 and info["slot_rounds"] > 1.2 * info["rounds"], info
+    for i in range(len(big)):
+        ra, (wa, za) = alone[i]
+        rm = mix[i]
+        assert ra["status"] == G.OK and rm["status"] == G.OK, (ra, rm)
+        assert rm["stats"]["kkt_max"] <= 1e-7 and ra["stats"]["kkt_max"] <= 1e-7
+        oa, om = ra["stats"]["objective"], rm["stats"]["objective"]
+        print(f"request {i}: objective alone {oa:.12g} mix {om:.12g} "
+              f"epochs {ra['stats']['epochs']} / {rm['stats']['epochs']} "
+              f"|J| {rm['stats']['select_size']}", flush=True)
+        assert abs(oa - om) <= 1e-6 * abs(oa)
+        zm = outs[i][1].double()
+        zd = (zm - za.double()).abs() / (za.double().abs() + za.double().pow(2).mean().sqrt())
+        assert float(zd.max()) <= 1e-4
+        # the single-problem solve gives the same optimum
+        X, y, loss, lam = allreq[i]
+        s1 = G.solve(X, y, _params(loss, lam, tol=1e-7, select=0))
+        assert abs(s1.stats["objective"] - oa) <= 1e-6 * abs(oa)
 
 
 def test_server_backpressure_and_failures(reqs):
+    print("CASE server backpressure", flush=True)
     r0, P0, Xo0, lam0 = reqs[0]
     X = G.Matrix.of(P0)
     y = torch.as_tensor(P0.y, device=DEV)
-    need = G.workspace_bytes(X, _params(P0, lam0))
+    need = G.Server.request_bytes(X, _params(P0.loss, lam0))
     # an arena for exactly one request at a time: requests are serialised
-    srv = G.Server(arena_bytes=need + 4096, max_slots=4)
+    srv = G.Server(arena_bytes=G.Server.overhead_bytes(4) + need + 4096, max_slots=4)
     ws = [torch.empty(P0.k, dtype=torch.float32, device=DEV) for _ in range(3)]
+    torch.cuda.synchronize()
     for i in range(3):
-        srv.submit(X, y, _params(P0, lam0), ws[i], tag=i)
+        srv.submit(X, y, _params(P0.loss, lam0), ws[i], tag=i)
     # a request larger than the arena is rejected at submit
     big = reqs[int(np.argmax([p.nnz + p.k + p.n for _, p, _, _ in reqs]))]
     Xb = G.Matrix.of(big[1])
-    if G.workspace_bytes(Xb, _params(big[1], big[3])) > need + 4096:
+    if G.Server.request_bytes(Xb, _params(big[1].loss, big[3])) > need + 4096:
         with pytest.raises(G.GencdError) as e:
-            srv.submit(Xb, torch.as_tensor(big[1].y, device=DEV), _params(big[1], big[3]),
+            srv.submit(Xb, torch.as_tensor(big[1].y, device=DEV), _params(big[1].loss, big[3]),
                        torch.empty(big[1].k, dtype=torch.float32, device=DEV))
         assert e.value.status == -8
-    res = []
-    while len(res) < 3:
-        res += srv.poll(wait_for=1)
+    res = _drain(srv, 3)
     srv.close()
     res.sort(key=lambda r: r["user_tag"])
     for a, b in zip(res[:-1], res[1:]):
@@ -104,7 +181,7 @@ def test_server_backpressure_and_failures(reqs):
     for r in res:
         assert r["status"] == G.OK
     # a failing request fails alone
-    srv = G.Server(arena_bytes=8 * need, max_slots=4)
+    srv = G.Server(arena_bytes=G.Server.overhead_bytes(4) + 8 * need, max_slots=4)
     lg = [(p, xo, l) for (_, p, xo, l) in reqs if p.loss == G.LOGISTIC]
     Pl, _, laml = lg[0]
     Xl = G.Matrix.of(Pl)
@@ -112,11 +189,46 @@ def test_server_backpressure_and_failures(reqs):
     bad = torch.as_tensor(Pl.y * 0.5, device=DEV)
     wg = torch.empty(Pl.k, dtype=torch.float32, device=DEV)
     wb = torch.empty(Pl.k, dtype=torch.float32, device=DEV)
-    srv.submit(Xl, bad, _params(Pl, laml), wb, tag=1)
-    srv.submit(Xl, good, _params(Pl, laml), wg, tag=2)
-    out = []
-    while len(out) < 2:
-        out += srv.poll(wait_for=1)
+    torch.cuda.synchronize()
+    srv.submit(Xl, bad, _params(Pl.loss, laml), wb, tag=1)
+    srv.submit(Xl, good, _params(Pl.loss, laml), wg, tag=2)
+    out = _drain(srv, 2)
     srv.close()
     st = {r["user_tag"]: r["status"] for r in out}
     assert st[1] == -3 and st[2] == G.OK
+    # rules other than Shotgun are refused at submission
+    srv = G.Server(arena_bytes=G.Server.overhead_bytes(1) + 8 * need, max_slots=1)
+    with pytest.raises(G.GencdError) as e:
+        srv.submit(Xl, good, G.make_params(Pl.loss, laml, rule=G.THREAD_GREEDY, select_size=64,
+                                           block=8), wg)
+    assert e.value.status == -5
+    srv.close()
+
+
+def test_generated_requests_follow_their_law():
+    """Device-generated serving requests: valid CSC, deterministic in the
+    seed, Bernoulli(density) counts, N(0, 1) values, labels of the loss."""
+    print("CASE generator", flush=True)
+    for n, k, d, loss, seed in [(3000, 5000, 0.01, synth.LOGISTIC, 7), (1000, 20000, 0.002, synth.SQUARED, 8)]:
+        X, y = G.generate_request(n, k, d, loss, seed)
+        X2, y2 = G.generate_request(n, k, d, loss, seed)
+        cp = X.col_ptr.cpu().numpy()
+        ri = X.row_idx.cpu().numpy()
+        v = X.val.cpu().numpy().astype(np.float64)
+        assert cp[0] == 0 and np.all(np.diff(cp) >= 0) and cp[-1] == X.nnz
+        assert torch.equal(X.col_ptr, X2.col_ptr) and torch.equal(X.row_idx, X2.row_idx)
+        assert torch.equal(X.val, X2.val) and torch.equal(y, y2)
+        for j in range(k):
+            rr = ri[cp[j]:cp[j + 1]]
+            assert np.all(rr >= 0) and np.all(rr < n) and np.all(np.diff(rr) > 0)
+        mean = n * k * d
+        assert abs(X.nnz - mean) <= 6 * np.sqrt(mean * (1 - d))
+        assert abs(v.mean()) <= 6 / np.sqrt(v.size) and abs(v.var() - 1) <= 0.05
+        yy = y.cpu().numpy()
+        if loss == synth.LOGISTIC:
+            assert set(np.unique(yy)) <= {-1.0, 1.0}
+        # rows are spread uniformly: the per-row counts have the Binomial mean
+        rc = np.bincount(ri, minlength=n)
+        assert abs(rc.mean() - k * d) <= 0.05 * k * d
+        X3, _ = G.generate_request(n, k, d, loss, seed + 1)
+        assert not torch.equal(X3.col_ptr, X.col_ptr)
