@@ -23,7 +23,8 @@
  *     before any device work; on an error no output has been modified unless
  *     stated.  Nothing crosses the ABI as a C++ exception.
  *   - Calls on different streams with disjoint workspaces are independent.
- *     The library has no global mutable state.
+ *     The library has no global mutable state, apart from the static scratch
+ *     of gencd_solve_noalloc and the table of its per-device addresses.
  *
  * Matrix X (n x k) is CSC: col_ptr int64[k+1] (col_ptr[0] = 0,
  * non-decreasing, col_ptr[k] = nnz), row_idx int32[nnz] (sorted and unique
@@ -53,7 +54,9 @@ typedef enum {
   GENCD_ERR_UNSUPPORTED = -5,     /* option combination not implemented */
   GENCD_ERR_DIVERGED = -6,        /* non-finite objective at a check */
   GENCD_ERR_HIP = -7,             /* a HIP runtime call failed */
-  GENCD_ERR_BUDGET = -8           /* server: request larger than the arena */
+  GENCD_ERR_BUDGET = -8,          /* server: request larger than the arena */
+  GENCD_ERR_TOO_LARGE = -9        /* the problem needs more device scratch than the
+                                     fixed static scratch of an allocation-free call */
 } gencd_status;
 
 typedef enum { GENCD_SQUARED = 0, GENCD_LOGISTIC = 1 } gencd_loss;
@@ -203,6 +206,22 @@ int gencd_lambda_max(const gencd_csc *X, const float *y, int32_t loss, double *o
  * after max_epochs, GENCD_ERR_DIVERGED on a non-finite objective. */
 int gencd_solve(const gencd_csc *X, const float *y, const gencd_params *p, float *w, float *z,
                 void *ws, size_t ws_bytes, hipStream_t stream, gencd_stats *stats);
+
+/* Allocation-free variant of gencd_solve, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a static device array of
+ * 64 MiB that the library holds on every device it runs on until the
+ * process ends; the call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  Every call on a device shares that device's
+ * array and the solve initialises every part of it that it reads, so the
+ * contents left by an earlier call do not matter; calls that overlap on one
+ * device (several host threads, or streams running concurrently) race on it
+ * and must not be made.  Arguments as gencd_solve.  Errors: those of
+ * gencd_solve; GENCD_ERR_TOO_LARGE (before any device work) when
+ * gencd_workspace_bytes of the problem exceeds 64 MiB; GENCD_ERR_UNSUPPORTED
+ * with GENCD_USE_GRAPH or GENCD_PROFILE (they create HIP objects). */
+int gencd_solve_noalloc(const gencd_csc *X, const float *y, const gencd_params *p, float *w,
+                        float *z, hipStream_t stream, gencd_stats *stats);
 
 /* One iteration of Algorithm 1 on a given selected set, for step-by-step
  * comparison.  J: device int32[nJ] distinct column indices.  The state is

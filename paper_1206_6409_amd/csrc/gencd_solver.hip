@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gencd_common.hpp"
@@ -895,6 +896,42 @@ int check_impl(const gencd_csc *X, const float *y, int loss, double lambda, cons
 }  // namespace gencd
 
 // ---------------------------------------------------------------------------
+// Allocation-free solve.  Its workspace is this fixed device array: every
+// device the library runs on holds one copy until the process ends, and
+// every allocation-free call on that device shares it.
+// ---------------------------------------------------------------------------
+namespace gencd {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxScratchDevices = 64;
+}  // namespace gencd
+
+static __device__ __align__(256) unsigned char scratch[gencd::kScratchBytes];
+
+namespace gencd {
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept.  The array's name is only
+// a host-side stand-in, never a device address.
+int scratch_ptr(void **out) {
+  int dev = -1;
+  GENCD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return GENCD_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GENCD_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GENCD_OK;
+}
+}  // namespace
+}  // namespace gencd
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 using namespace gencd;
@@ -913,6 +950,7 @@ const char *gencd_status_string(int status) {
     case GENCD_ERR_DIVERGED: return "diverged (non-finite objective)";
     case GENCD_ERR_HIP: return "HIP runtime error";
     case GENCD_ERR_BUDGET: return "request exceeds the memory budget";
+    case GENCD_ERR_TOO_LARGE: return "problem exceeds the static scratch of the allocation-free call";
     default: return "unknown status";
   }
 }
@@ -941,6 +979,22 @@ int gencd_lambda_max(const gencd_csc *X, const float *y, int32_t loss, double *o
 int gencd_solve(const gencd_csc *X, const float *y, const gencd_params *p, float *w, float *z,
                 void *ws, size_t ws_bytes, hipStream_t stream, gencd_stats *stats) {
   return solve_impl(X, y, p, w, z, ws, ws_bytes, stream, stats);
+}
+
+int gencd_solve_noalloc(const gencd_csc *X, const float *y, const gencd_params *p, float *w,
+                        float *z, hipStream_t stream, gencd_stats *stats) {
+  // host checks first: a problem that does not fit is rejected before any
+  // HIP call
+  if (!p || !w) return GENCD_ERR_INVALID_ARG;
+  if (p->flags & (GENCD_USE_GRAPH | GENCD_PROFILE)) return GENCD_ERR_UNSUPPORTED;
+  size_t need = 0;
+  int st = gencd_workspace_bytes(X, p, &need);
+  if (st) return st;
+  if (need > kScratchBytes) return GENCD_ERR_TOO_LARGE;
+  void *base = nullptr;
+  st = scratch_ptr(&base);
+  if (st) return st;
+  return solve_impl(X, y, p, w, z, base, kScratchBytes, stream, stats);
 }
 
 int gencd_step(const gencd_csc *X, const float *y, const gencd_params *p, const int32_t *J,

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgencd.so")
 
 OK, NOT_CONVERGED = 0, 1
+ERR_UNSUPPORTED, ERR_TOO_LARGE = -5, -9
 SQUARED, LOGISTIC = 0, 1
 CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY, BLOCK_SHOTGUN = range(8)
 WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE, EXACT_ACCUM, FUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
@@ -71,6 +72,8 @@ _SIGS = {
                                    C.c_size_t, C.c_void_p]),
     "gencd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "gencd_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]),
     "gencd_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -293,6 +296,22 @@ def solve(X: Matrix, y: torch.Tensor, params: Params, w0=None, ws=None, want_z=T
     rc = lib().gencd_solve(X.ref, _ptr(y), C.byref(params), _ptr(w), _ptr(z), _ptr(ws),
                            ws.numel(), _stream(), C.byref(st))
     _check(rc, "gencd_solve", allow=(OK, NOT_CONVERGED))
+    return SolveResult(rc, w, z, st.as_dict())
+
+
+def solve_noalloc(X: Matrix, y: torch.Tensor, params: Params, w0=None, want_z=True):
+    """gencd_solve with the library's static device scratch as workspace (no
+    device allocation inside the call; w and z are the caller's outputs)."""
+    if w0 is not None:
+        w = w0.clone().to(torch.float32)
+        params.flags |= WARM_START
+    else:
+        w = torch.empty(X.k, dtype=torch.float32, device=X.col_ptr.device)
+    z = torch.empty(X.n, dtype=torch.float32, device=X.col_ptr.device) if want_z else None
+    st = Stats()
+    rc = lib().gencd_solve_noalloc(X.ref, _ptr(y), C.byref(params), _ptr(w), _ptr(z), _stream(),
+                                   C.byref(st))
+    _check(rc, "gencd_solve_noalloc", allow=(OK, NOT_CONVERGED))
     return SolveResult(rc, w, z, st.as_dict())
 
 
