@@ -94,13 +94,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-thread-greedy", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time only the plain launch path")
-    ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
-    ap.add_argument("--req-scale", type=float, default=0.25,
-                    help="serve: scale of the n and k ranges of the request distribution")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
+    ap.add_argument("--calibration", type=int, default=200,
+                    help="serve: warm-up requests, submitted at once, that set the rate")
+    ap.add_argument("--plain-requests", type=int, default=100,
+                    help="serve: prefix of the stream timed on the plain path")
+    ap.add_argument("--oracle-sample", type=int, default=8,
+                    help="serve: stratified requests checked against the oracle")
+    ap.add_argument("--oracle-max-nnz", type=float, default=4e5,
+                    help="serve: largest expected nnz of an oracle-checked request")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serve: arrival rate (skips the calibration run when > 0)")
     ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
-    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent request slots")
-    ap.add_argument("--serve-jacobi", action="store_true",
-                    help="serve: Jacobi Propose/Update instead of the fused iteration")
+    ap.add_argument("--slots", type=int, default=16, help="serve: concurrent request slots")
     ap.add_argument("--sweep-scales", type=float, nargs="+", default=[1.0, 8.0],
                     help="sweep: scales of the logistic workload")
     ap.add_argument("--sweep-iters", type=int, default=10, help="sweep: Greedy iterations")
@@ -537,109 +543,208 @@ def bench_path(args):
 
 
 def bench_serve(args):
-    """Serving: a Poisson stream of L1 solves, 50/50 Lasso and logistic,
-    n ~ U{1k..50k}*s, k ~ U{1k..200k}*s (s = --req-scale), density
-    U[0.1%, 2%], lambda/lambda_max log-uniform [1e-3, 0.5]; matrices drawn
-    from a pool of distinct generated problems.  Reports p50/p99 latency and
-    solves/s for the continuous-batching server and for one-at-a-time
-    (plain) service of the same stream."""
+    """Serving: a Poisson stream of L1 solve requests, 50/50 Lasso and
+    logistic, n ~ U{1k..50k}, k ~ U{1k..200k}, density U[0.1%, 2%], N(0, 1)
+    values, lambda/lambda_max log-uniform [1e-3, 0.5], every request a
+    distinct matrix generated on the device at its arrival.  The rate is 0.7x
+    the saturated throughput of the server measured on a warm-up of
+    --calibration requests submitted at once.  Reports p50/p99 latency
+    (finish - arrival) and solves/s of the continuous-batching server; the
+    plain path (one gencd_solve after another) on a prefix of the same
+    stream, as a FIFO queue replayed with its measured solve times; and the
+    error against the oracle's tight optimum on a stratified sample."""
     import numpy as np
     import torch
 
+    import oracle as O
     from paper_1206_6409_amd import gencd as G
     from paper_1206_6409_amd import synth
 
-    sc = args.req_scale
-    pool_n = 24
-    # requests run the fused asynchronous Shotgun (one launch per window);
-    # --serve-jacobi keeps the two-launch Jacobi iteration instead
-    serve_flags = 0 if args.serve_jacobi else G.FUSED
-    stream = synth.c5_request_stream(count=args.requests, rate=1.0,
-                                     n_range=(int(1000 * sc), int(50000 * sc)),
-                                     k_range=(int(1000 * sc), int(200000 * sc)))
-    t = time.time()
-    pool = []
-    for i in range(pool_n):
-        r = stream[i]
-        P = synth.request_problem(r)
-        X = G.Matrix.of(P)
-        y = torch.as_tensor(P.y, device="cuda")
-        lm = G.lambda_max(X, y, P.loss)
-        pool.append((P, X, y, lm))
-    log(f"generated a pool of {pool_n} request problems in {time.time() - t:.1f}s, "
-        f"mean nnz {np.mean([p[0].nnz for p in pool]):.0f}")
-    reqs = []
-    for r in stream:
-        P, X, y, lm = pool[r.ticket % pool_n]
-        reqs.append((P, X, y, r.lambda_ratio * lm))
+    count, slots, tol = args.requests, args.slots, args.tol
+    dev = torch.device("cuda", 0)
+    stream = synth.c5_request_stream(count=count, rate=1.0)
+    calib = synth.c5_request_stream(count=args.calibration, rate=1.0, seed=106, arrival_seed=1060)
 
-    def params(P, lam):
-        # |J| = floor(k_live / (2 rho)) clamped to [1, 1024], rho from 20 power
-        # iterations on the normalised Gram matrix (section 4.1's P*)
-        return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=0, seed=11, tol=1e-6,
-                             max_epochs=20000, flags=G.USE_GRAPH | serve_flags)
+    def make(r):
+        X, y = G.generate_request(r.n, r.k, r.density, r.loss, r.seed)
+        lam = r.lambda_ratio * G.lambda_max(X, y, r.loss)  # synchronises: X and y exist
+        return X, y, lam
 
-    need = max(G.workspace_bytes(X, params(P, 1.0)) for P, X, y, lm in pool)
-    slots = args.slots
-    srv = G.Server(arena_bytes=slots * need + (64 << 20), max_slots=slots)
+    def params(loss, lam):
+        # |J| = P* = floor(k_live / (2 rho)) clamped to [1, k_live] (section 4.1)
+        return G.make_params(loss, lam, rule=G.SHOTGUN, select_size=0, seed=11, tol=tol,
+                             max_epochs=100000)
 
-    def run_stream(server, arrivals):
-        outs = [torch.empty(P.k, dtype=torch.float32, device="cuda") for P, X, y, lam in reqs]
-        t0 = time.perf_counter()
-        base = None
-        for i, ((P, X, y, lam), at) in enumerate(zip(reqs, arrivals)):
-            now = time.perf_counter() - t0
-            if at > now:
-                time.sleep(at - now)
-            server.submit(X, y, params(P, lam), outs[i], tag=i)
-            if (i + 1) % 50 == 0:
-                log(f"  submitted {i + 1} requests")
-        res = []
-        while len(res) < len(reqs):
-            got = server.poll(wait_for=1)
-            if got and (len(res) + len(got)) // 25 > len(res) // 25:
-                log(f"  {len(res) + len(got)} of {len(reqs)} requests done")
-            res += got
-        return res
+    # the largest request of the ranges fixes the per-slot arena share
+    worst = G.Matrix(50000, 200000, torch.zeros(200001, dtype=torch.int64, device=dev),
+                     torch.empty(0, dtype=torch.int32, device=dev),
+                     torch.empty(0, dtype=torch.float32, device=dev))
+    worst._s.nnz = int(50000 * 200000 * 0.02 * 1.01)
+    per_slot = G.Server.request_bytes(worst, params(synth.LOGISTIC, 1.0))
+    arena = G.Server.overhead_bytes(slots) + slots * per_slot
+    log(f"serving: {slots} slots, arena {arena / 2**30:.1f} GiB")
 
-    # saturated throughput: everything arrives at once
-    res = run_stream(srv, np.zeros(len(reqs)))
-    span = max(r["finish_s"] for r in res) - min(r["submit_s"] for r in res)
-    sat = len(reqs) / span
-    assert all(r["status"] == G.OK for r in res)
-    rate = 0.7 * sat
-    gaps = np.random.default_rng(1050).exponential(1.0 / rate, size=len(reqs))
+    def run_stream(reqs, arrivals, keep=()):
+        """Submit reqs[i] at arrivals[i] (seconds from the server's start) and
+        collect every result; progress lines go to stderr."""
+        srv = G.Server(arena_bytes=arena, max_slots=slots)
+        t0 = time.perf_counter()  # the server's clock starts within microseconds of this
+        live, results, kept = {}, {}, {}
+        nxt, last_log = 0, t0
+        saturated = None  # (seconds, results) when the last waiting request was admitted
+        while len(results) < len(reqs):
+            while nxt < len(reqs) and arrivals[nxt] <= time.perf_counter() - t0:
+                r = reqs[nxt]
+                X, y, lam = make(r)
+                w = torch.empty(r.k, dtype=torch.float32, device=dev)
+                z = torch.empty(r.n, dtype=torch.float32, device=dev)
+                srv.submit(X, y, params(r.loss, lam), w, z, tag=nxt)
+                live[nxt] = (X, y, lam, w, z)
+                nxt += 1
+            got = srv.poll(wait_for=0)
+            if not got:
+                time.sleep(0.0005)
+            for g in got:
+                i = g["user_tag"]
+                X, y, lam, w, z = live.pop(i)
+                g["latency_s"] = g["finish_s"] - arrivals[i]
+                g["lambda"] = lam
+                results[i] = g
+                if i in keep:
+                    kept[i] = (X, y, lam, w, z)
+            if saturated is None and nxt == len(reqs) and srv.info()["waiting"] == 0:
+                saturated = (time.perf_counter() - t0, len(results))
+            if time.perf_counter() - last_log > 20.0:
+                last_log = time.perf_counter()
+                log(f"  {nxt} of {len(reqs)} submitted, {len(results)} done, "
+                    f"{len(live)} in the server")
+        info = srv.info()
+        info["saturated_until"] = saturated
+        srv.close()
+        return [results[i] for i in range(len(reqs))], info, kept
+
+    # saturated throughput on the calibration requests (all at time 0)
+    if args.rate > 0:
+        rate, sat, sat_makespan = args.rate, args.rate / 0.7, None
+        log(f"rate {rate}/s given on the command line (no calibration run)")
+    else:
+        log(f"calibration: {len(calib)} requests submitted at once")
+        res_c, info_c, _ = run_stream(calib, np.zeros(len(calib)))
+        span_c = max(r["finish_s"] for r in res_c) - min(r["submit_s"] for r in res_c)
+        sat_makespan = len(calib) / span_c
+        # saturated = every slot busy and requests waiting: completions up to
+        # the admission of the last waiting one (the tail after it is the
+        # longest requests finishing alone)
+        t_sat, n_sat = info_c["saturated_until"] or (span_c, len(calib))
+        sat = n_sat / t_sat if n_sat > 0 else sat_makespan
+        rate = 0.7 * sat
+    gaps = np.random.default_rng(1050).exponential(1.0 / rate, size=count)
     arrivals = np.cumsum(gaps) - gaps[0]
-    res = run_stream(srv, arrivals)
-    srv.close()
-    lat = np.array([r["finish_s"] - r["submit_s"] for r in res])
+    # stratified sample for the oracle: requests at nnz quantiles small enough
+    # for the host (about 2 M nonzeros), both losses
+    exp_nnz = np.array([r.n * r.k * r.density for r in stream])
+    small = [i for i in np.argsort(exp_nnz) if exp_nnz[i] <= args.oracle_max_nnz]
+    sample = sorted(set(small[int(q * (len(small) - 1))] for q in np.linspace(0, 1, args.oracle_sample)))
+    log(f"stream: {count} requests at {rate:.2f}/s (0.7 x {sat:.2f} saturated)")
+    t_main = time.perf_counter()
+    res, info, kept = run_stream(stream, arrivals, keep=set(int(i) for i in sample))
+    wall = time.perf_counter() - t_main
+    # latency = finish - arrival: the client generates each request at its
+    # arrival, so the generation time counts
+    lat = np.array([r["latency_s"] for r in res])
     span = max(r["finish_s"] for r in res) - min(r["submit_s"] for r in res)
-    # plain: one request at a time, same arrivals
-    srv1 = G.Server(arena_bytes=need + (64 << 20), max_slots=1)
-    res1 = run_stream(srv1, arrivals)
-    srv1.close()
-    lat1 = np.array([r["finish_s"] - r["submit_s"] for r in res1])
-    span1 = max(r["finish_s"] for r in res1) - min(r["submit_s"] for r in res1)
-    nnz = sum(r["stats"]["nnz_updates"] for r in res)
-    return {
-        "metric": "serving: solves/s and p50/p99 latency at 0.7x saturated rate",
-        "value": len(reqs) / span, "unit": "solves/s", "n_gpus": 1, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{len(reqs)} Poisson requests, 50/50 Lasso/logistic, n,k ranges x{sc}, "
-                               f"density 0.1-2%, lambda/lambda_max logU[1e-3,0.5], pool of {pool_n}",
-                   "slots": slots, "rate_per_s": rate, "mean_nnz": float(np.mean([r[0].nnz for r in reqs]))},
-        "saturated_solves_per_s": sat,
+    statuses = {}
+    for r in res:
+        statuses[r["status"]] = statuses.get(r["status"], 0) + 1
+    nnz_upd = sum(r["stats"]["nnz_updates"] for r in res)
+    epochs = np.array([r["stats"]["epochs"] for r in res])
+    # plain path: gencd_solve back to back on a prefix, queue replayed at the same arrivals
+    nplain = min(args.plain_requests, count)
+    service = []
+    log(f"plain path: {nplain} requests one after another")
+    for i in range(nplain):
+        X, y, lam = make(stream[i])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        G.solve(X, y, params(stream[i].loss, lam))
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t1)
+        del X, y
+        if (i + 1) % 10 == 0:
+            log(f"  plain {i + 1} of {nplain}: {sum(service):.1f} s so far")
+    fin, t_free = [], 0.0
+    for i in range(nplain):
+        start = max(arrivals[i], t_free)
+        t_free = start + service[i]
+        fin.append(t_free - arrivals[i])
+    fin = np.array(fin)
+    # error against the oracle's tight optimum, and the oracle's own speed
+    prec, o_upd, o_time, o_solves = [], 0, 0.0, 0
+    for i in sample:
+        if i not in kept:
+            continue
+        X, y, lam, w, z = kept[i]
+        r = stream[i]
+        log(f"oracle on request {i}: n={r.n} k={r.k} nnz={X.nnz}")
+        Xo = O.Matrix(X.n, X.k, X.col_ptr.cpu().numpy(), X.row_idx.cpu().numpy(),
+                      X.val.cpu().numpy().astype(np.float64))
+        yo = y.cpu().numpy().astype(np.float64)
+        t1 = time.perf_counter()
+        base = O.solve(Xo, yo, r.loss, lam, O.SHOTGUN, select_size=1024, seed=11, tol=tol,
+                       max_epochs=100000)
+        o_time += time.perf_counter() - t1
+        o_upd += base.nnz_updates
+        o_solves += 1
+        ref = O.solve(Xo, yo, r.loss, lam, O.SHOTGUN, select_size=1024, seed=11, tol=1e-10,
+                      max_epochs=20000, w0=base.w)
+        chk = O.check(Xo, yo, r.loss, lam, w.double().cpu().numpy())
+        zz = z.double().cpu().numpy()
+        sc = np.abs(ref.z) + np.sqrt(np.mean(ref.z ** 2)) + 1e-300
+        prec.append({"request": int(i), "n": r.n, "k": r.k, "nnz": X.nnz, "loss": r.loss,
+                     "lambda_ratio": r.lambda_ratio,
+                     "oracle_reference_kkt": ref.kkt,
+                     "objective_rel_err": abs(chk.objective - ref.objective) / abs(ref.objective),
+                     "z_max_rel_err": float(np.max(np.abs(zz - ref.z) / sc)), "kkt_max": chk.kkt})
+    out = {
+        "metric": "serving: solves/s and p50/p99 latency at 0.7x the saturated rate",
+        "value": count / span, "unit": "solves/s", "n_gpus": 1, "dtype": "f32",
+        "data": "synthetic, generated on the device per request",
+        "config": {"workload": f"{count} Poisson requests, 50/50 Lasso/logistic, n U{{1k..50k}}, "
+                               f"k U{{1k..200k}}, density U[0.1%,2%], N(0,1) values, "
+                               f"lambda/lambda_max logU[1e-3,0.5], KKT {tol}",
+                   "slots": slots, "rate_per_s": rate,
+                   "mean_nnz": float(np.mean([r["stats"]["nnz_visits"] / max(r["stats"]["epochs"], 1)
+                                              for r in res]))},
+        "saturated_solves_per_s": sat, "calibration_requests": len(calib),
+        "calibration_makespan_solves_per_s": sat_makespan,
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
-        "nnz_updates_per_s": nnz / span,
-        "plain_one_at_a_time": {"solves_per_s": len(reqs) / span1,
-                                "latency_p50_s": float(np.percentile(lat1, 50)),
-                                "latency_p99_s": float(np.percentile(lat1, 99))},
-        "all_converged": bool(all(r["stats"]["converged"] for r in res)),
-        "iteration": "Jacobi" if args.serve_jacobi else "fused asynchronous",
+        "latency_max_s": float(lat.max()),
+        "nnz_updates_per_s": nnz_upd / span, "wall_s": wall,
+        "status_counts": {str(k): v for k, v in statuses.items()},
+        "epochs": {"p50": float(np.percentile(epochs, 50)), "p99": float(np.percentile(epochs, 99)),
+                   "max": int(epochs.max())},
+        "rounds": info["rounds"], "request_windows": info["slot_rounds"],
+        "requests_per_round": info["slot_rounds"] / max(info["rounds"], 1),
+        "rounds_with_several_requests": info["shared_rounds"],
+        "plain_one_at_a_time": {"requests": nplain, "solves_per_s": nplain / sum(service),
+                                "latency_p50_s": float(np.percentile(fin, 50)),
+                                "latency_p99_s": float(np.percentile(fin, 99)),
+                                "note": "FIFO replay of the same arrivals with measured gencd_solve times"},
+        "precision": {"sample": prec,
+                      "objective_rel_err_max": max((p["objective_rel_err"] for p in prec), default=None),
+                      "z_max_rel_err_max": max((p["z_max_rel_err"] for p in prec), default=None),
+                      "kkt_max": max((p["kkt_max"] for p in prec), default=None)},
         "select_size_from_rho": {"min": int(min(r["stats"]["select_size"] for r in res)),
                                  "median": float(np.median([r["stats"]["select_size"] for r in res])),
                                  "max": int(max(r["stats"]["select_size"] for r in res))},
+        "cpu_baseline": {"value": o_solves / o_time if o_time > 0 else None, "unit": "solves/s",
+                         "cores": 1, "kind": "oracle",
+                         "nnz_updates_per_s": o_upd / o_time if o_time > 0 else None,
+                         "sample": f"{o_solves} requests of the stream at nnz quantiles up to 2e6 "
+                                   f"(both losses), Shotgun |J|=1024 to KKT {tol}, {o_time:.1f} s "
+                                   f"on 1 thread of {cpu_model()}"},
     }
+    return out
 
 
 def bench_sweep(args):

@@ -106,8 +106,8 @@ typedef struct {
   int32_t loss;          /* gencd_loss */
   int32_t rule;          /* gencd_rule */
   double lambda;         /* lambda >= 0 of Eq. (1) */
-  int64_t select_size;   /* |J| (Shotgun, Thread-Greedy); 0: floor(k_live / (2 rho))
-                            clamped to [1, 1024], rho estimated by 20 power
+  int64_t select_size;   /* |J| (Shotgun, Thread-Greedy); 0: P* = floor(k_live / (2 rho))
+                            clamped to [1, k_live], rho estimated by 20 power
                             iterations (gencd_estimate_rho; section 4.1) */
   int64_t block;         /* B, proposals per accepting block (Thread-Greedy);
                             |J'|, proposals accepted per iteration (Top-Greedy);
@@ -362,7 +362,7 @@ int gencd_autotune_path(const gencd_csc *X, const float *y, const gencd_params *
  *                first iteration with G v = 0 on)
  *   k_live       host, may be NULL: number of non-empty columns
  *   select_size  host, may be NULL: floor(k_live / (2 rho_iters)) clamped to
- *                [1, 1024], the |J| gencd_solve takes for select_size 0
+ *                [1, k_live], the |J| gencd_solve takes for select_size 0
  *   ws           device workspace of gencd_rho_workspace_bytes bytes
  * Synchronises the stream.  Errors: INVALID_ARG, BAD_MATRIX (with
  * VALIDATE_DEVICE), WORKSPACE, UNSUPPORTED, HIP.
@@ -436,7 +436,7 @@ typedef struct {
 } gencd_server_status;
 
 /* arena: device memory owned by the caller for the server's lifetime (the
- * server keeps 1 MiB plus 96 B per slot of it for its work tables);
+ * server keeps 4 MiB plus 96 B per slot of it for its work tables);
  * max_slots: concurrent requests (1..256); stream: the rounds run on it and
  * it must stay valid until gencd_server_destroy.  The device current at
  * creation is used by the server's threads.  The server creates one stream

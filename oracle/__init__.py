@@ -222,9 +222,10 @@ def rho(X: Matrix, iters=20):
     return r, hist[:int(iters)], kl.value
 
 
-def pstar(k_live, rho_est, cap=1024):
-    """Selection size floor(k_live / (2 rho)) clamped to [1, cap]."""
-    return int(lib().orc_pstar(int(k_live), float(rho_est), int(cap)))
+def pstar(k_live, rho_est, cap=None):
+    """Selection size floor(k_live / (2 rho)) clamped to [1, cap] (cap: k_live)."""
+    cap = int(k_live) if cap is None else int(cap)
+    return int(lib().orc_pstar(int(k_live), float(rho_est), max(cap, 1)))
 
 
 def block_base(X: Matrix, seed):

@@ -239,7 +239,6 @@ constexpr int kDefaultGroup = 8;
 constexpr int kDefaultPiece = 256;
 constexpr int kRhoIters = 20;       // power iterations behind an automatic |J|
 constexpr int kRhoMaxIters = 1024;  // cap for the standalone estimate
-constexpr int64_t kRhoSelectCap = 1024;  // automatic |J| is clamped to [1, this]
 constexpr int kBlockRhoMaxIters = 64;    // power iterations of the per-block estimate
 constexpr int64_t kMaxBlocks = 4096;     // preset blocks of Block Shotgun
 // The check's block results go to kChkRep replicas (workgroup b to replica

@@ -159,8 +159,12 @@ struct MpSlot {
   int32_t S, k_live;       // |J| and the live column count
 };
 
-// Work item (one wave): slot, window-relative positions [lo, hi).
-constexpr int kMpRoundsPerItem = 4;  // column batches a wave takes per item
+// Work item (one wave): slot, window-relative positions [lo, hi).  A wave
+// takes one batch of 64 / G columns, so a round's dependence chain is one
+// column long; a slot gets more positions per item only when its window
+// would exceed its share of the item table.
+constexpr int kMpRoundsPerItem = 1;
+constexpr int32_t kMpMaxItems = 262144;  // work items of one round (4 MiB table)
 
 // Round r of every slot: window t = (r - r0) mod T of its epoch order.
 // Propose (UPD = false) writes delta and w_j += delta_j; Update (UPD = true)
@@ -694,8 +698,8 @@ int gencd_server_create(void *arena, size_t arena_bytes, int32_t max_slots, hipS
   size_t mis = reinterpret_cast<uintptr_t>(base) % 256;
   size_t skip = mis ? 256 - mis : 0;
   const size_t tab_bytes = (sizeof(MpSlot) * size_t(max_slots) + 255) / 256 * 256;
-  const int32_t max_items = 65536;  // work items of one round (each slot gets a share);
-                                    // gencd_server_overhead_bytes counts this table
+  const int32_t max_items = kMpMaxItems;  // each slot gets a share of the table;
+                                          // gencd_server_overhead_bytes counts it
   const size_t item_bytes = sizeof(int4) * size_t(max_items);
   if (arena_bytes <= skip + tab_bytes + item_bytes + 256) {
     delete sv;
@@ -759,7 +763,7 @@ int gencd_server_request_bytes(const gencd_csc *X, const gencd_params *p, size_t
 
 size_t gencd_server_overhead_bytes(int32_t max_slots) {
   const size_t tab = (sizeof(MpSlot) * size_t(max_slots > 0 ? max_slots : 1) + 255) / 256 * 256;
-  return tab + sizeof(int4) * 65536 + 512;
+  return tab + sizeof(int4) * size_t(kMpMaxItems) + 512;
 }
 
 int gencd_server_submit(gencd_server *sv, const gencd_request *req, int64_t *ticket) {

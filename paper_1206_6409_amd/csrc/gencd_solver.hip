@@ -179,12 +179,12 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
-// |J| = floor(k_live / (2 rho)) clamped to [1, kRhoSelectCap] (section 4.1).
+// |J| = P* = floor(k_live / (2 rho)) clamped to [1, k_live] (section 4.1).
 int64_t pstar_of(int64_t k_live, double rho) {
   if (!(rho > 0.0)) return 1;
   const double q = std::floor(double(k_live) / (2.0 * rho));
   if (q < 1.0) return 1;
-  if (q > double(kRhoSelectCap)) return kRhoSelectCap;
+  if (q > double(k_live)) return k_live > 0 ? k_live : 1;
   return int64_t(q);
 }
 

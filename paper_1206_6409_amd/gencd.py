@@ -229,7 +229,7 @@ class RhoResult:
     rho: float            # estimate after the last iteration
     history: list         # estimate after each iteration
     k_live: int
-    select_size: int      # floor(k_live / (2 rho)) clamped to [1, 1024]
+    select_size: int      # floor(k_live / (2 rho)) clamped to [1, k_live]
 
 
 def estimate_rho(X: Matrix, iters=20, params=None):

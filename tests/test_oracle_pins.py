@@ -629,7 +629,8 @@ def test_rho_ignores_empty_columns_and_pstar_clamps():
     r2, h2, k2 = O.rho(_csc_matrix(Z), 20)
     assert k1 == k2 == 13 and r1 == r2
     assert O.pstar(1000, 2.0) == 250 and O.pstar(1000, 3.0) == 166
-    assert O.pstar(10, 100.0) == 1 and O.pstar(10**7, 1.0) == 1024 and O.pstar(5, 0.0) == 1
+    assert O.pstar(10, 100.0) == 1 and O.pstar(10**7, 1.0) == 5 * 10**6 and O.pstar(5, 0.0) == 1
+    assert O.pstar(10**7, 1.0, cap=1024) == 1024 and O.pstar(3, 0.25) == 3  # k/(2 rho) > k: all
 
 
 # --------------------------------------------------------------------------
