@@ -105,6 +105,11 @@ def main():
                     help="serve: largest expected nnz of an oracle-checked request")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serve: arrival rate (skips the calibration run when > 0)")
+    ap.add_argument("--slice", type=int, nargs=2, default=None, metavar=("FIRST", "END"),
+                    help="serve: run only requests [FIRST, END) of the stream, arrivals "
+                         "shifted to start at 0 (a long stream in several runs)")
+    ap.add_argument("--merge", nargs="+", default=None, metavar="JSON",
+                    help="serve: combine the lines of slice runs into one line")
     ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
     ap.add_argument("--slots", type=int, default=16, help="serve: concurrent request slots")
     ap.add_argument("--sweep-scales", type=float, nargs="+", default=[1.0, 8.0],
@@ -141,6 +146,9 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
+    if args.workload == "serve" and args.merge:
+        print(json.dumps(merge_serve(args.merge)), flush=True)
+        return
     if args.workload != "shotgun":
         names = ["coloring", "path", "serve"] if args.workload == "all" else [args.workload]
         for name in names:
@@ -640,6 +648,13 @@ def bench_serve(args):
         rate = 0.7 * sat
     gaps = np.random.default_rng(1050).exponential(1.0 / rate, size=count)
     arrivals = np.cumsum(gaps) - gaps[0]
+    first, end = (0, count) if args.slice is None else (max(args.slice[0], 0), min(args.slice[1], count))
+    if args.slice is not None:
+        # a slice of the same stream: its own arrivals, shifted to start at 0
+        stream = stream[first:end]
+        arrivals = arrivals[first:end] - arrivals[first]
+        count = len(stream)
+        log(f"slice [{first}, {end}) of the stream")
     # stratified sample for the oracle: requests at nnz quantiles small enough
     # for the host (about 2 M nonzeros), both losses
     exp_nnz = np.array([r.n * r.k * r.density for r in stream])
@@ -721,6 +736,9 @@ def bench_serve(args):
         "latency_max_s": float(lat.max()),
         "nnz_updates_per_s": nnz_upd / span, "wall_s": wall,
         "status_counts": {str(k): v for k, v in statuses.items()},
+        "slice": [first, end],
+        "latencies_s": [round(float(x), 6) for x in lat],
+        "busy_span_s": span, "nnz_updates": nnz_upd,
         "epochs": {"p50": float(np.percentile(epochs, 50)), "p99": float(np.percentile(epochs, 99)),
                    "max": int(epochs.max())},
         "rounds": info["rounds"], "request_windows": info["slot_rounds"],
@@ -744,6 +762,43 @@ def bench_serve(args):
                                    f"(both losses), Shotgun |J|=1024 to KKT {tol}, {o_time:.1f} s "
                                    f"on 1 thread of {cpu_model()}"},
     }
+    return out
+
+
+def merge_serve(paths):
+    """One serving line from the lines of slice runs of one stream (same rate):
+    latency percentiles over every request, solves/s over the summed spans."""
+    import numpy as np
+    lines = [json.loads(open(p).read().strip().splitlines()[-1]) for p in paths]
+    lat = np.concatenate([np.array(l["latencies_s"]) for l in lines])
+    span = sum(l["busy_span_s"] for l in lines)
+    out = dict(lines[0])
+    out.pop("latencies_s", None)
+    out["slices"] = [l["slice"] for l in lines]
+    out["value"] = len(lat) / span
+    out["latency_p50_s"] = float(np.percentile(lat, 50))
+    out["latency_p99_s"] = float(np.percentile(lat, 99))
+    out["latency_max_s"] = float(lat.max())
+    out["nnz_updates_per_s"] = sum(l["nnz_updates"] for l in lines) / span
+    out["wall_s"] = sum(l["wall_s"] for l in lines)
+    sc = {}
+    for l in lines:
+        for k, v in l["status_counts"].items():
+            sc[k] = sc.get(k, 0) + v
+    out["status_counts"] = sc
+    for key in ("rounds", "request_windows", "rounds_with_several_requests"):
+        out[key] = sum(l[key] for l in lines)
+    out["requests_per_round"] = out["request_windows"] / max(out["rounds"], 1)
+    out["config"] = dict(out["config"])
+    out["config"]["workload"] = out["config"]["workload"].replace(
+        f"{lines[0]['slice'][1] - lines[0]['slice'][0]} Poisson", f"{len(lat)} Poisson")
+    prec = [p for l in lines for p in l["precision"]["sample"]]
+    out["precision"] = {"sample": prec,
+                        "objective_rel_err_max": max((p["objective_rel_err"] for p in prec), default=None),
+                        "z_max_rel_err_max": max((p["z_max_rel_err"] for p in prec), default=None),
+                        "kkt_max": max((p["kkt_max"] for p in prec), default=None)}
+    out["note"] = ("one stream run as consecutive slices, each started empty; latencies and "
+                   "rates combine every request of every slice")
     return out
 
 

@@ -116,7 +116,11 @@ typedef struct {
   double kkt_tol;        /* stop when max_j KKT violation <= kkt_tol ... */
   double gap_tol;        /* ... and duality gap <= gap_tol * |objective| (0: off) */
   int64_t max_epochs;    /* epoch = one pass of Select over the live columns */
-  int64_t check_every;   /* epochs between FP64 convergence checks (>= 1) */
+  int64_t check_every;   /* epochs between FP64 convergence checks; 0: adaptive, a
+                            tenth of the epochs run so far (between 1 and 64), so a
+                            solve stops at most about 10% of its epochs after its
+                            first converged epoch (gencd_solve_path: the epochs of
+                            its youngest slot) */
   uint32_t flags;        /* GENCD_* flags */
   const int32_t *color;  /* COLORING: device int32[k] colours (gencd_color) */
   int32_t num_colors;    /* COLORING: number of colours */
@@ -139,6 +143,10 @@ typedef struct {
                             expected nonzeros (|window| nnz / live columns)
                             reach 4 n, else 1.  The same FP32 arithmetic either
                             way.  gencd_solve / gencd_step only */
+  int32_t stagger;       /* gencd_solve_path: a lambda takes a free slot only once its
+                            predecessor has run this many epochs (or finished), so it
+                            starts from a partly converged iterate; 0 = as soon as a
+                            slot is free */
 } gencd_params;
 
 /* Host-side statistics filled by the solve calls. */

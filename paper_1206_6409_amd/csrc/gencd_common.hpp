@@ -263,6 +263,16 @@ int64_t radix_hist_len(int64_t m);
 int radix_sort_pairs(uint32_t *k0, int32_t *v0, uint32_t *k1, int32_t *v1, int64_t m, int bits,
                      int32_t *hist, int32_t *offs, int32_t *part, hipStream_t s, int *out_buf);
 
+// Epochs from a check to the next, `done` epochs after the start of the
+// solve: check_every > 0 fixes it; check_every = 0 adapts it to a tenth of
+// the epochs run so far (1 for the first twenty, at most 64), so a solve
+// that first meets its tolerance at epoch N is checked by about 1.1 N.
+inline int64_t check_interval(int64_t check_every, int64_t done) {
+  if (check_every > 0) return check_every;
+  const int64_t c = done / 10;
+  return c < 1 ? 1 : (c > 64 ? 64 : c);
+}
+
 // Number of bits needed for values up to v (0 for v = 0).
 inline int bits_for(uint64_t v) {
   int b = 0;

@@ -476,14 +476,19 @@ int launch_preprocess(const gencd_csc *X, int loss, int piece, int short_max, co
 }
 
 // grid for a two-class pass over ns short columns and nlp long pieces
+// Waves of a two-role launch: one per long piece up to kMaxLongWaves (whole-
+// matrix passes such as the FP64 check walk many pieces per wave beyond
+// that, each a dependent descriptor -> weight -> entries chain, so more waves
+// keep more chains in flight), and one per 64 / gs short columns up to 28672.
+constexpr int64_t kMaxLongWaves = 16384;
 static void two_class_grid(int64_t ns, int64_t nlp, int gs, unsigned *blocks, int32_t *nl) {
-  int64_t lw = nlp < 4096 ? nlp : 4096;
+  int64_t lw = nlp < kMaxLongWaves ? nlp : kMaxLongWaves;
   int64_t sw = (ns + (kWave / gs) - 1) / (kWave / gs);
   if (sw > 28672) sw = 28672;
   if (lw < 1) lw = 1;
   if (sw < 1) sw = 1;
   *nl = int32_t(lw);
-  *blocks = waves_grid(lw + sw);
+  *blocks = waves_grid(lw + sw, 12288);
 }
 
 int launch_curvature(const gencd_csc *X, int loss, int32_t n_short, int32_t n_lpieces,

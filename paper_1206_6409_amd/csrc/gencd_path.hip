@@ -699,7 +699,14 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
                        int64_t(B), int64_t(slot));
     return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
   };
-  for (int slot = 0; slot < B && next < L; ++slot) {
+  // a lambda may enter once its predecessor has run `stagger` epochs (or is
+  // done), so that it starts from a partly converged iterate
+  const int64_t stagger = p->stagger > 0 ? p->stagger : 0;
+  auto may_admit = [&](int64_t e) {
+    return next < L && (stagger == 0 || next == 0 || done[next - 1] ||
+                        e - start_epoch[next - 1] >= stagger);
+  };
+  for (int slot = 0; slot < B && may_admit(0); ++slot) {
     st = admit(slot, 0);
     if (st) return st;
   }
@@ -733,7 +740,8 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   a.lam = w.lam;
   a.active = w.active;
   a.delta = w.delta;
-  const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
+  const int64_t check_every = p->check_every;  // 0: adaptive, on the youngest slot's age
+  int64_t next_check = 0;
   // measured on the 64-lambda binary workload: the staged update wins at
   // B = 64 (one full wave per column row), the block update below that
   constexpr bool upd_staged = B == 64;
@@ -777,7 +785,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   bool resync = true;
   int remaining = L;
   while (remaining > 0) {
-    if (resync || e % check_every == 0) {
+    if (resync || e >= next_check) {
       st = path_check<B>(X, y, p->loss, w, s, &red);
       if (st) return st;
       resync = false;
@@ -816,16 +824,28 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
           act_host[slot] = 0;
           lam_host[slot] = 0.0f;
           lam64_host[slot] = 0.0;
-          if (next < L) {
-            st = admit(slot, e);
-            if (st) return st;
-            admitted = true;
-          }
         }
+      }
+      for (int slot = 0; slot < B && may_admit(e); ++slot) {
+        if (slot_lambda[slot] >= 0) continue;
+        st = admit(slot, e);
+        if (st) return st;
+        admitted = true;
       }
       st = push_slots();
       if (st) return st;
       if (remaining == 0) break;
+      // next check: from the age of the youngest slot (adaptive interval)
+      int64_t young = -1;
+      for (int slot = 0; slot < B; ++slot) {
+        const int32_t t = slot_lambda[slot];
+        if (t >= 0 && !done[t]) young = young < 0 ? e - start_epoch[t] : std::min(young, e - start_epoch[t]);
+      }
+      next_check = e + check_interval(check_every, young < 0 ? 0 : young);
+      bool free_slot = false;
+      for (int slot = 0; slot < B; ++slot) free_slot |= slot_lambda[slot] < 0;
+      if (free_slot && stagger > 0 && next < L && !done[next - 1])
+        next_check = std::min(next_check, start_epoch[next - 1] + stagger);  // the next entry
       if (admitted) {
         resync = true;  // z of the admitted slots must be recomputed from W
         continue;

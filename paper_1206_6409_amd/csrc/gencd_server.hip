@@ -295,7 +295,7 @@ struct gencd_server {
     Setup su;
     float *w_best = nullptr;
     MpSlot dev{};
-    int64_t S = 1, T = 1, epoch = 0, in_epoch = 0;
+    int64_t S = 1, T = 1, epoch = 0, in_epoch = 0, next_check = 1;
     double best = 0.0;
     bool check_pending = false;
     bool retiring = false;
@@ -446,6 +446,7 @@ void gencd_server::admission_loop() {
     }
     sl.S = S;
     sl.T = (sl.su.k_live + S - 1) / S;
+    sl.next_check = check_interval(p.check_every, 0);
     sl.epoch = 0;
     sl.in_epoch = 0;
     sl.best = ck.objective;
@@ -663,8 +664,8 @@ void gencd_server::driver_loop() {
       so.nnz_visits += sl.req.X.nnz;
       so.nnz_updates += sl.req.X.nnz;
       ++sl.epoch;
-      const int64_t every = p.check_every > 0 ? p.check_every : 1;
-      if (sl.epoch % every == 0 || sl.epoch >= p.max_epochs) {
+      if (sl.epoch >= sl.next_check || sl.epoch >= p.max_epochs) {
+        sl.next_check = sl.epoch + check_interval(p.check_every, sl.epoch);
         Red *red = reinterpret_cast<Red *>(sl.h_rep + kChkRep * 16);
         if (!fail)
           fail = enqueue_check(&sl.req.X, sl.req.y, p.loss, p.lambda, sl.req.w, sl.su, true,

@@ -589,7 +589,8 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
     st_out->rho = rmax;
   }
   st_out->select_size = S;
-  const int64_t check_every = p->check_every > 0 ? p->check_every : 1;
+  const int64_t check_every = p->check_every;  // 0: adaptive (check_interval)
+  int64_t next_check = check_interval(check_every, 0);
   int64_t max_class = 0;
   for (int32_t sz : cls_sizes) max_class = std::max<int64_t>(max_class, sz);
   int64_t *epoch_dev = reinterpret_cast<int64_t *>(ws.red + 12);
@@ -698,7 +699,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
                       : (rule == GENCD_BLOCK_SHOTGUN) ? T_blk
                                                       : (k_live + S - 1) / S;
     if (prof && evs.empty()) {
-      const int64_t want = 4 * std::max<int64_t>(T, 1) * check_every;
+      const int64_t want = 4 * std::max<int64_t>(T, 1) * (check_every > 0 ? check_every : 64);
       if (want <= 4 * 65536) {
         evs.resize(size_t(want));
         // timing-only events: no system-scope fence when they complete, so
@@ -747,7 +748,8 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
     }
     st_out->nnz_visits += X->nnz;
     if (mode != 2) st_out->nnz_updates += X->nnz;
-    if ((e + 1) % check_every == 0 || e + 1 == p->max_epochs) {
+    if (e + 1 >= next_check || e + 1 == p->max_epochs) {
+      next_check = e + 1 + check_interval(check_every, e + 1);
       st = run_check(X, y, p->loss, p->lambda, w, su, true, s, &ck);
       if (st) return st;
       if (std::isfinite(ck.drift_rel))

@@ -44,7 +44,7 @@ class Params(C.Structure):
                 ("check_every", C.c_int64),
                 ("flags", C.c_uint32), ("color", C.c_void_p), ("num_colors", C.c_int32),
                 ("piece", C.c_int32), ("group", C.c_int32), ("improve_steps", C.c_int32),
-                ("residual", C.c_int32)]
+                ("residual", C.c_int32), ("stagger", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -193,14 +193,14 @@ class Matrix:
 
 def make_params(loss, lam, rule=SHOTGUN, select_size=1, block=1, seed=0, tol=1e-6,
                 gap_tol=0.0, max_epochs=1000, check_every=1, flags=0, colors=None,
-                num_colors=0, piece=0, group=0, improve=0, residual=0):
+                num_colors=0, piece=0, group=0, improve=0, residual=0, stagger=0):
     if isinstance(rule, str):
         rule = RULES[rule]
     return Params(int(loss), int(rule), float(lam), int(select_size), int(block),
                   C.c_uint64(seed).value, float(tol), float(gap_tol), int(max_epochs),
                   int(check_every),
                   int(flags), colors.data_ptr() if colors is not None else None, int(num_colors),
-                  int(piece), int(group), int(improve), int(residual))
+                  int(piece), int(group), int(improve), int(residual), int(stagger))
 
 
 def workspace_bytes(X: Matrix, params: Params = None):

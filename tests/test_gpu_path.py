@@ -19,18 +19,22 @@ def binary_problem():
     return P, Xo, lm
 
 
-@pytest.mark.parametrize("B,L,flags", [(16, 20, 0), (32, 12, 0), (64, 6, 0),
-                                       (16, 20, G.FUSED), (64, 6, G.FUSED),
-                                       (16, 20, G.USE_GRAPH), (64, 6, G.USE_GRAPH),
-                                       (32, 12, G.FUSED | G.USE_GRAPH)])
-def test_path_matches_independent_solves(binary_problem, B, L, flags):
-    print("CASE path", B, L, flags, flush=True)
+@pytest.mark.parametrize("B,L,flags,stagger,every", [
+    (16, 20, 0, 0, 1), (32, 12, 0, 0, 1), (64, 6, 0, 0, 1),
+    (16, 20, G.FUSED, 0, 1), (64, 6, G.FUSED, 0, 1),
+    (16, 20, G.USE_GRAPH, 0, 1), (64, 6, G.USE_GRAPH, 0, 1),
+    (32, 12, G.FUSED | G.USE_GRAPH, 0, 1),
+    # staggered admission (a lambda enters once its predecessor ran 3 epochs)
+    # and the adaptive check interval
+    (64, 20, G.USE_GRAPH, 3, 0), (16, 20, 0, 5, 0), (32, 12, G.FUSED, 2, 1)])
+def test_path_matches_independent_solves(binary_problem, B, L, flags, stagger, every):
+    print("CASE path", B, L, flags, stagger, every, flush=True)
     P, Xo, lm = binary_problem
     lams = synth.lambda_grid(lm, count=L, ratio=0.1)
     X = G.Matrix.of(P)
     y = torch.as_tensor(P.y, device=DEV)
     params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-8,
-                           max_epochs=20000, flags=flags)
+                           max_epochs=20000, flags=flags, stagger=stagger, check_every=every)
     res = G.solve_path(X, y, params, lams, B=B)
     assert res.status == G.OK
     W = res.W.cpu().numpy().astype(np.float64)
