@@ -437,6 +437,11 @@ def bench_coloring(args):
     r = O.solve(Xo, P.y.astype(np.float64), P.loss, lam, O.COLORING, colors=ocol, seed=3,
                 tol=args.tol, max_epochs=100000)
     t_or = time.perf_counter() - t0
+    log("solving the oracle to KKT 1e-10 for the precision figures")
+    ref = O.solve(Xo, P.y.astype(np.float64), P.loss, lam, O.COLORING, colors=ocol, seed=3,
+                  tol=1e-10, max_epochs=100000, w0=r.w)
+    prec = precision_vs_oracle(O, Xo, P.y.astype(np.float64), P.loss, lam, ref,
+                               resg if t_graph <= t_plain else res)
     return {
         "metric": "nnz-updates/s of Coloring solves to FP64 KKT 1e-6; colouring time",
         "value": st["nnz_updates"] / best, "unit": "nnz-updates/s", "n_gpus": 1,
@@ -453,6 +458,8 @@ def bench_coloring(args):
         "epochs": st["epochs"], "iters": st["iters"], "objective": st["objective"],
         "kkt_max": st["kkt_max"],
         "objective_rel_diff_vs_oracle": abs(st["objective"] - r.objective) / abs(r.objective),
+        "precision": prec,
+        "z_drift_pair_update": st["z_drift"],
         "cpu_baseline": {"value": r.nnz_updates / t_or, "unit": "nnz-updates/s", "cores": 1,
                          "kind": "oracle", "sample": f"one full Coloring solve ({r.epochs} epochs, "
                                                      f"{t_or:.1f} s) on 1 thread of {cpu_model()}"},
