@@ -471,7 +471,8 @@ GOLDEN_PATH = os.path.join(ROOT, "tests", "golden", "c4_path_optima.txt")
 
 def load_path_optima(lams):
     """Oracle optima of the 64-lambda path (tests/golden, written by an
-    oracle-only script), or None when absent or for another grid."""
+    oracle-only script) as (objective, kkt, l1 norm) arrays, or None when
+    absent or for another grid."""
     try:
         rows = [l.split() for l in open(GOLDEN_PATH) if l.strip() and not l.startswith("#")]
     except OSError:
@@ -482,7 +483,8 @@ def load_path_optima(lams):
     lam_g = np.array([float(r[1]) for r in rows])
     if np.max(np.abs(lam_g - lams) / lams) > 1e-12:
         return None
-    return np.array([float(r[2]) for r in rows])
+    return (np.array([float(r[2]) for r in rows]), np.array([float(r[3]) for r in rows]),
+            np.array([float(r[5]) for r in rows]))
 
 
 def bench_path(args):
@@ -514,23 +516,32 @@ def bench_path(args):
         return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=1024, seed=5, tol=tol,
                              max_epochs=60000, check_every=0, flags=flags, stagger=stagger)
 
-    def errors(objs):
+    def errors(objs, kkts, l1s):
+        """Relative objective error against the oracle's optimum, and the
+        convexity bound it must respect: for two points a, b of the same
+        Eq. (1), |P(a) - P(b)| <= max(KKT(a), KKT(b)) (|a|_1 + |b|_1)."""
         if optima is None:
             return None
-        e = np.abs(np.array(objs) - optima) / np.abs(optima)
+        obj_g, kkt_g, l1_g = optima
+        e = np.abs(np.array(objs) - obj_g) / np.abs(obj_g)
+        bound = np.maximum(np.array(kkts), kkt_g) * (np.array(l1s) + l1_g) / np.abs(obj_g)
         return {"max": float(e.max()), "median": float(np.median(e)),
-                "per_lambda": [float(x) for x in e]}
+                "lambdas_within_1e-6": int(np.sum(e <= 1e-6)),
+                "lambdas_within_convexity_bound": int(np.sum(e <= np.maximum(bound, 1e-12))),
+                "per_lambda": [float(x) for x in e],
+                "convexity_bound_per_lambda": [float(x) for x in bound]}
 
     def plain(tol):
         ws = G.workspace(X, prm(tol))
-        w0, objs, kkts, epochs = None, [], [], 0
+        w0, objs, kkts, l1s, epochs = None, [], [], [], 0
         for lam in lams:
             r = G.solve(X, y, prm(tol, flags=G.USE_GRAPH, lam=float(lam)), w0=w0, ws=ws)
             assert r.stats["converged"], r.stats
             w0, epochs = r.w, epochs + r.stats["epochs"]
             objs.append(r.stats["objective"])
             kkts.append(r.stats["kkt_max"])
-        return objs, kkts, epochs
+            l1s.append(float(r.w.double().abs().sum()))
+        return objs, kkts, l1s, epochs
 
     out = {"metric": "solves/s of a 64-lambda path to FP64 KKT 1e-6, batched vs plain GPU path",
            "unit": "solves/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
@@ -538,9 +549,10 @@ def bench_path(args):
                       "n": P.n, "k": P.k, "nnz": P.nnz, "select_size": 1024,
                       "check_every": "adaptive (a tenth of the epochs run, 1..64)"},
            "levels": {}}
-    configs = {1e-6: [(16, 0, 0), (16, G.FUSED, 0), (32, 0, 0), (32, G.FUSED, 0), (64, 0, 0),
-                      (64, G.FUSED, 0), (64, G.FUSED, 20)],
-               1e-9: [(16, G.FUSED, 0), (16, 0, 0), (64, G.FUSED, 100)]}
+    FE = G.FUSED | G.FUSED_EPOCH
+    configs = {1e-6: [(16, 0, 0), (16, G.FUSED, 0), (16, FE, 0), (32, 0, 0), (32, FE, 0), (64, 0, 0),
+                      (64, G.FUSED, 0), (64, FE, 0), (64, FE, 20)],
+               1e-9: [(16, FE, 0), (16, G.FUSED, 0), (64, FE, 100)]}
     for tol in (args.tol,) if args.no_path_tight else (args.tol, 1e-9):
         lvl = {"batched": {}}
         best = None
@@ -550,20 +562,24 @@ def bench_path(args):
             dt, res = _timed(lambda: G.solve_path(X, y, p_, lams, B=B))
             assert all(st["converged"] for st in res.stats)
             objs = [st["objective"] for st in res.stats]
-            name = f"B{B}" + ("_fused" if fl else "") + (f"_stagger{stag}" if stag else "")
+            kkts = [st["kkt_max"] for st in res.stats]
+            l1s = res.W.double().abs().sum(dim=1).tolist()
+            name = (f"B{B}" + ("_fused_epoch" if fl & G.FUSED_EPOCH else "_fused" if fl else "")
+                    + (f"_stagger{stag}" if stag else ""))
             lvl["batched"][name] = {
                 "seconds": dt, "solves_per_s": len(lams) / dt,
                 "max_epochs": max(st["epochs"] for st in res.stats),
                 "nnz_updates_per_s": sum(st["nnz_updates"] for st in res.stats) / dt,
-                "objective_rel_err_vs_oracle": errors(objs),
-                "kkt_max": max(st["kkt_max"] for st in res.stats)}
+                "objective_rel_err_vs_oracle": errors(objs, kkts, l1s),
+                "kkt_max": max(kkts)}
             log(f"KKT {tol:g} path {name}: {dt:.2f}s")
             if best is None or dt < lvl["batched"][best]["seconds"]:
                 best = name
-        t_plain, (objs_p, kkts_p, ep_p) = _timed(lambda: plain(tol))
+        t_plain, (objs_p, kkts_p, l1s_p, ep_p) = _timed(lambda: plain(tol))
         log(f"KKT {tol:g} plain path: {t_plain:.2f}s")
         lvl["plain_path"] = {"seconds": t_plain, "solves_per_s": len(lams) / t_plain,
-                             "epochs_total": ep_p, "objective_rel_err_vs_oracle": errors(objs_p),
+                             "epochs_total": ep_p,
+                             "objective_rel_err_vs_oracle": errors(objs_p, kkts_p, l1s_p),
                              "kkt_max": max(kkts_p)}
         lvl["best_batched"] = best
         lvl["speedup_vs_plain"] = t_plain / lvl["batched"][best]["seconds"]

@@ -93,6 +93,13 @@ typedef enum {
                                       not the Jacobi one (the optimum is the same).  Not
                                       with EXACT_ACCUM or improve_steps (UNSUPPORTED).
                                       gencd_solve_path: one launch per shared window */
+#define GENCD_FUSED_EPOCH 0x40u    /* gencd_solve_path with GENCD_FUSED: the whole epoch in one
+                                      launch of |J| workgroups, workgroup b taking positions
+                                      b, b + |J|, b + 2|J|, ... of the epoch order one column
+                                      at a time; at most |J| columns are in flight and none
+                                      waits for another (asynchronous Shotgun with |J|
+                                      concurrent updates, section 4.1).  Ignored elsewhere;
+                                      UNSUPPORTED without GENCD_FUSED */
 
 /* Device CSC matrix (see the conventions above). */
 typedef struct {
@@ -298,7 +305,8 @@ int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_c
  *   lambdas[t]);  Z: device float32[L][n] or NULL (row t = X W[t], the FP32
  *   rounding of the FP64 product of the slot's final check);
  *   stats: host gencd_stats[L].
- * Flags: GENCD_FUSED (one launch per window, see above), GENCD_USE_GRAPH
+ * Flags: GENCD_FUSED (one launch per window, see above), GENCD_FUSED_EPOCH
+ * (with GENCD_FUSED: one launch per epoch, see above), GENCD_USE_GRAPH
  * (every epoch replays one captured HIP graph; which lambdas the slots hold
  * lives in device arrays, so the graph is captured once per call).
  * Workspace bytes from gencd_path_workspace_bytes. */
@@ -333,8 +341,9 @@ int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, in
                    hipStream_t stream, gencd_schedule *out);
 
 /* Path autotuner: times gencd_solve_path on the caller's lambdas for every
- * slot count B in {16, 32, 64}, each with and without GENCD_FUSED, and
- * returns the fastest (B and the flag to add).  Cached like gencd_autotune,
+ * slot count B in {16, 32, 64}, each without GENCD_FUSED, with it, and with
+ * GENCD_FUSED | GENCD_FUSED_EPOCH, and returns the fastest (B and the flags
+ * to add).  Cached like gencd_autotune,
  * under a key that also holds L and the lambda range.
  *   W_scratch  device float32[L][k] (overwritten)
  *   ws         at least gencd_path_workspace_bytes(X, p, 64) bytes
@@ -342,7 +351,7 @@ int gencd_autotune(const gencd_csc *X, const float *y, const gencd_params *p, in
  * accepted (its time still counts). */
 typedef struct {
   int32_t B;
-  uint32_t flags;            /* GENCD_FUSED or 0 */
+  uint32_t flags;            /* 0, GENCD_FUSED or GENCD_FUSED | GENCD_FUSED_EPOCH */
   double seconds;            /* whole path, measured on the tuning run */
   int32_t from_cache;
 } gencd_path_schedule;

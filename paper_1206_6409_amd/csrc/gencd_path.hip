@@ -746,6 +746,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   // B = 64 (one full wave per column row), the block update below that
   constexpr bool upd_staged = B == 64;
   const bool fused = (p->flags & GENCD_FUSED) != 0;
+  const bool fused_epoch = fused && (p->flags & GENCD_FUSED_EPOCH) != 0;
   std::vector<double> red;
   const int64_t T = (k_live + S - 1) / S;
   // One epoch: selection order (section 2.1), the shared windows' launches,
@@ -757,7 +758,15 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
     if (rc) return rc;
     hipLaunchKernelGGL(k_path_desc, dim3(g1(k_live)), dim3(kBlock), 0, es, k_live, ws.col_of_pos,
                        X->col_ptr, ws.desc_s);
-    for (int64_t t = 0; t < T; ++t) {
+    if (fused_epoch) {
+      // every position of the epoch in one launch: S workgroups, each one
+      // column at a time in the order of its positions (grid stride S)
+      a.win_lo = 0;
+      a.win_hi = int32_t(k_live);
+      hipLaunchKernelGGL(k_path_fused<B>, dim3(unsigned(std::min<int64_t>(S, 65536))),
+                         dim3(kBlock), 0, es, a);
+    }
+    for (int64_t t = 0; t < (fused_epoch ? 0 : T); ++t) {
       a.win_lo = int32_t(t * S);
       a.win_hi = int32_t(std::min(k_live, (t + 1) * S));
       const int64_t npos = a.win_hi - a.win_lo;
@@ -912,7 +921,8 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
   if (!X || !p || !lambdas || L <= 0 || !W || !stats) return GENCD_ERR_INVALID_ARG;
   if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
   if (p->rule != GENCD_SHOTGUN || p->improve_steps != 0 ||
-      ((p->flags & GENCD_FUSED) && (p->flags & GENCD_EXACT_ACCUM)))
+      ((p->flags & GENCD_FUSED) && (p->flags & GENCD_EXACT_ACCUM)) ||
+      ((p->flags & GENCD_FUSED_EPOCH) && !(p->flags & GENCD_FUSED)))
     return GENCD_ERR_UNSUPPORTED;
   if (p->select_size <= 0 || !(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0)
     return GENCD_ERR_INVALID_ARG;

@@ -208,13 +208,13 @@ int gencd_autotune_path(const gencd_csc *X, const float *y, const gencd_params *
   }
   std::vector<gencd_stats> st(static_cast<size_t>(L));
   const int Bs[] = {16, 32, 64};
-  const unsigned fl[] = {0u, GENCD_FUSED};
+  const unsigned fl[] = {0u, GENCD_FUSED, GENCD_FUSED | GENCD_FUSED_EPOCH};
   double best = 1e300;
   bool warmed = false;
   for (int B : Bs)
     for (unsigned f : fl) {
       gencd_params q = *p;
-      q.flags = (p->flags & ~GENCD_FUSED) | f;
+      q.flags = (p->flags & ~(GENCD_FUSED | GENCD_FUSED_EPOCH)) | f;
       size_t need = 0;
       if (gencd_path_workspace_bytes(X, &q, B, &need) != GENCD_OK || need > ws_bytes) continue;
       if (!warmed) {  // first-use costs (code objects, caches) stay out of the timings

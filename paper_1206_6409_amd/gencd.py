@@ -21,6 +21,7 @@ ERR_UNSUPPORTED, ERR_TOO_LARGE = -5, -9
 SQUARED, LOGISTIC = 0, 1
 CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY, BLOCK_SHOTGUN = range(8)
 WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE, EXACT_ACCUM, FUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+FUSED_EPOCH = 0x40
 RULES = {"cyclic": CYCLIC, "stochastic": STOCHASTIC, "shotgun": SHOTGUN,
          "thread_greedy": THREAD_GREEDY, "greedy": GREEDY, "coloring": COLORING,
          "top_greedy": TOP_GREEDY, "block_shotgun": BLOCK_SHOTGUN}

@@ -26,7 +26,10 @@ def binary_problem():
     (32, 12, G.FUSED | G.USE_GRAPH, 0, 1),
     # staggered admission (a lambda enters once its predecessor ran 3 epochs)
     # and the adaptive check interval
-    (64, 20, G.USE_GRAPH, 3, 0), (16, 20, 0, 5, 0), (32, 12, G.FUSED, 2, 1)])
+    (64, 20, G.USE_GRAPH, 3, 0), (16, 20, 0, 5, 0), (32, 12, G.FUSED, 2, 1),
+    # the whole epoch in one launch of |J| workgroups
+    (16, 20, G.FUSED | G.FUSED_EPOCH, 0, 1), (64, 6, G.FUSED | G.FUSED_EPOCH | G.USE_GRAPH, 0, 0),
+    (32, 12, G.FUSED | G.FUSED_EPOCH | G.USE_GRAPH, 3, 0)])
 def test_path_matches_independent_solves(binary_problem, B, L, flags, stagger, every):
     print("CASE path", B, L, flags, stagger, every, flush=True)
     P, Xo, lm = binary_problem
@@ -72,6 +75,10 @@ def test_path_rejects_bad_args(binary_problem):
                      [0.1 * lm], B=16)
     with pytest.raises(G.GencdError):
         G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=64), [0.1 * lm], B=24)
+    with pytest.raises(G.GencdError) as e:  # one launch per epoch only in the fused form
+        G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=64,
+                                         flags=G.FUSED_EPOCH), [0.1 * lm], B=16)
+    assert e.value.status == G.ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("loss,B,flags", [(synth.SQUARED, 32, G.USE_GRAPH), (synth.SQUARED, 64, 0),
