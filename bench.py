@@ -586,6 +586,27 @@ def bench_path(args):
         out["levels"][f"kkt_{tol:g}"] = lvl
     top = out["levels"][f"kkt_{args.tol:g}"]
     out["value"] = top["batched"][top["best_batched"]]["solves_per_s"]
+    # roofline of the one-launch-per-epoch fused kernel: GENCD_PROFILE puts
+    # HIP events around every k_path_fused launch on the call's stream (plain
+    # launches); bytes per launch are the algorithmic count the library
+    # reports (12 + 16 B per nonzero, 20 + 8 B per column at B slots)
+    kern = {}
+    for B in (16, 64):
+        p_ = prm(args.tol, flags=G.FUSED | G.FUSED_EPOCH | G.PROFILE)
+        s0 = G.solve_path(X, y, p_, lams, B=B).stats[0]
+        nl = max(s0["prof_launches"], 1)
+        us = s0["prof_kernel_ms"] * 1e3 / nl
+        bpl = s0["prof_bytes"] / nl
+        kern[f"k_path_fused<{B}>"] = {
+            "bound": "hbm",
+            "kernel": f"k_path_fused<{B}> (the whole epoch in one launch: every slot's gradient, "
+                      f"step and scatter; 12 + 16*{B} B per nonzero + 20 + 8*{B} B per column)",
+            "achieved": round(bpl / us / 1e3, 3), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(bpl / us / 1e3 / 8000.0, 6), "traffic": None,
+            "avg_launch_us": round(us, 3), "bytes_per_launch": bpl, "launches": nl}
+        log(f"k_path_fused<{B}>: {us:.1f} us per epoch launch, {bpl / us / 1e3:.0f} GB/s")
+    out["roofline"] = kern["k_path_fused<16>"]
+    out["kernels"] = kern
     out["oracle_optima"] = "tests/golden/c4_path_optima.txt (oracle, KKT 1e-10)" if optima is not None \
         else "absent: objectives not compared"
     # oracle on the first lambdas (bounded sample), warm-started like the plain path

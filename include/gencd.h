@@ -308,7 +308,14 @@ int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_c
  * Flags: GENCD_FUSED (one launch per window, see above), GENCD_FUSED_EPOCH
  * (with GENCD_FUSED: one launch per epoch, see above), GENCD_USE_GRAPH
  * (every epoch replays one captured HIP graph; which lambdas the slots hold
- * lives in device arrays, so the graph is captured once per call).
+ * lives in device arrays, so the graph is captured once per call),
+ * GENCD_PROFILE (without GENCD_USE_GRAPH: HIP events around every fused
+ * launch, or every Propose and every Update launch; stats[0].prof_launches,
+ * prof_kernel_ms and prof_bytes then hold the call's totals for the fused
+ * or Propose launches, prof_update_* those of the Update launches.  Bytes
+ * per nonzero of a launch's columns: fused 12 + 16 B, Propose 12 + 8 B,
+ * Update 8 + 8 B; per column: fused and Propose 20 + 8 B, Update
+ * 16 + 4 B).
  * Workspace bytes from gencd_path_workspace_bytes. */
 int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_t B,
                                size_t *out_bytes);

@@ -200,6 +200,23 @@ __global__ __launch_bounds__(kBlock) void k_path_update(PathArgs a) {
 // k_path_propose; after the slot's step the workgroup scatters delta_s x_ij
 // from the entries it still holds in registers, so Propose and Update of a
 // window are one launch.  Columns of a window read Z while others update it.
+// A workgroup that takes several positions (grid stride; all of them with
+// GENCD_FUSED_EPOCH) loads the next position's descriptor, first batch of
+// entries, weight, curvature, lambda and activity while it works on the
+// current one: the matrix, the order, c, lambda and activity do not change
+// during the launch, and column j's weights are written only by the
+// workgroup that holds position of j in this epoch.
+template <int B, int PU, int R>
+__device__ __forceinline__ void path_batch(const PathArgs &a, int64_t base, int64_t ce, int r,
+                                           int32_t (&ri)[PU], float (&vv)[PU]) {
+#pragma unroll
+  for (int q = 0; q < PU; ++q) {
+    const int64_t e = base + int64_t(q) * R + r;
+    ri[q] = e < ce ? a.row_idx[e] : -1;
+    vv[q] = e < ce ? a.val[e] : 0.0f;
+  }
+}
+
 template <int B>
 __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
   using SH = PathShape<B>;
@@ -207,33 +224,33 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
   __shared__ float sred[NW][B];
   __shared__ float sdel[B];
   const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
+  const bool slot_lane = int(threadIdx.x) < B;
   const int64_t npos = a.win_hi - a.win_lo;
-  for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
-    const int4 pd = a.pdesc[a.win_lo + p];
+  int64_t p = blockIdx.x;
+  if (p >= npos) return;  // uniform over the workgroup
+  // the current position's descriptor, first batch and per-slot scalars
+  int4 pd = a.pdesc[a.win_lo + p];
+  int32_t ri[PU];
+  float vv[PU];
+  path_batch<B, PU, R>(a, int64_t(uint32_t(pd.x)), int64_t(uint32_t(pd.x)) + pd.z, r, ri, vv);
+  float wj = 0.0f, cj = 0.0f, lam = 0.0f;
+  int32_t act = 0;
+  if (slot_lane) {
+    wj = a.W[int64_t(pd.y) * B + s];
+    cj = a.c[pd.y];
+    lam = a.lam[s];
+    act = a.active[s];
+  }
+  for (; p < npos; p += gridDim.x) {
     const int32_t j = pd.y;
     const int64_t cb = int64_t(uint32_t(pd.x)), ce = cb + pd.z;
     const bool one = ce - cb <= int64_t(R) * PU;  // the whole column in one batch
-    // the slot's weight (written only by this workgroup, which owns column
-    // j in this window), curvature, lambda and activity: issued with the
-    // entries' loads, consumed after the reduction
-    float wj = 0.0f, cj = 0.0f, lam = 0.0f;
-    int32_t act = 0;
-    if (int(threadIdx.x) < B) {
-      wj = a.W[int64_t(j) * B + s];
-      cj = a.c[j];
-      lam = a.lam[s];
-      act = a.active[s];
-    }
-    int32_t ri[PU];
-    float vv[PU];
+    const int64_t pn = p + gridDim.x;
+    const bool more = pn < npos;
+    const int4 pdn = more ? a.pdesc[a.win_lo + pn] : make_int4(0, 0, 0, 0);
     float acc = 0.0f;
     for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
-#pragma unroll
-      for (int q = 0; q < PU; ++q) {
-        const int64_t e = base + int64_t(q) * R + r;
-        ri[q] = e < ce ? a.row_idx[e] : -1;
-        vv[q] = e < ce ? a.val[e] : 0.0f;
-      }
+      if (base != cb) path_batch<B, PU, R>(a, base, ce, r, ri, vv);
       float zh[PU], zl[PU], yy[PU];
 #pragma unroll
       for (int q = 0; q < PU; ++q) {
@@ -250,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
     for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
     if (int(threadIdx.x) % kWave < B) sred[threadIdx.x / kWave][s] = acc;
     __syncthreads();
-    if (int(threadIdx.x) < B) {
+    if (slot_lane) {
       float g = 0.0f;
 #pragma unroll
       for (int w = 0; w < NW; ++w) g += sred[w][s];
@@ -265,6 +282,17 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
     }
     __syncthreads();
     const float d = sdel[s];
+    // the next position's loads go out before this column's atomics
+    int32_t rn[PU];
+    float vn[PU];
+    float wn = 0.0f, cn = 0.0f;
+    if (more) {
+      path_batch<B, PU, R>(a, int64_t(uint32_t(pdn.x)), int64_t(uint32_t(pdn.x)) + pdn.z, r, rn, vn);
+      if (slot_lane) {
+        wn = a.W[int64_t(pdn.y) * B + s];
+        cn = a.c[pdn.y];
+      }
+    }
     if (d != 0.0f) {
       if (one) {
 #pragma unroll
@@ -276,6 +304,14 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
       }
     }
     __syncthreads();  // sred / sdel are reused by the next column
+    pd = pdn;
+#pragma unroll
+    for (int q = 0; q < PU; ++q) {
+      ri[q] = rn[q];
+      vv[q] = vn[q];
+    }
+    wj = wn;
+    cj = cn;
   }
 }
 
@@ -641,6 +677,15 @@ size_t path_workspace_bytes(int64_t n, int64_t k, int64_t nnz, int64_t S, int B,
          path_layout(n, k, S, B, nullptr, nullptr) + 256;
 }
 
+// HIP events of one call, released on every return path.
+struct PathEvents {
+  std::vector<hipEvent_t> v;
+  ~PathEvents() {
+    for (auto e : v)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // A captured epoch and the private stream it was captured on, released on
 // every return path.
 struct PathGraph {
@@ -753,6 +798,54 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   // the renormalisation of (z_hi, z_lo) and the epoch counter.  No argument
   // depends on the epoch or on which lambdas the slots hold (those live in
   // device arrays), so GENCD_USE_GRAPH captures it once and replays it.
+  // GENCD_PROFILE (plain launches only): an event pair around every fused
+  // launch, or around every Propose and every Update launch; the totals of
+  // the call go to stats[0].  Algorithmic bytes per nonzero of a launch's
+  // columns: fused 12 + 16 B (row index, value, y; each slot's z_hi and z_lo
+  // read and z_lo read-modify-write), Propose 12 + 8 B, Update 8 + 8 B; per
+  // column: fused and Propose 20 + 8 B (descriptor, c; each slot's weight
+  // read and written, or read and its delta written), Update 16 + 4 B.
+  const bool use_graph = (p->flags & GENCD_USE_GRAPH) != 0;
+  const bool prof = (p->flags & GENCD_PROFILE) != 0 && !use_graph;
+  PathEvents pev;
+  size_t ev_used = 0;
+  std::vector<int> ev_kind;  // 0: fused or Propose pair, 1: Update pair
+  std::vector<double> ev_bytes;
+  double prof_ms[2] = {0.0, 0.0}, prof_by[2] = {0.0, 0.0};
+  int64_t prof_n[2] = {0, 0};
+  const size_t ev_cap = prof ? 8192 : 0;
+  if (prof) {
+    pev.v.assign(ev_cap, nullptr);
+    for (auto &ev : pev.v)
+      if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) ev = nullptr;
+    ev_kind.assign(ev_cap / 2, 0);
+    ev_bytes.assign(ev_cap / 2, 0.0);
+  }
+  auto harvest = [&]() {  // after a stream synchronisation
+    for (size_t u = 0; u + 1 < ev_used; u += 2) {
+      float t = 0.0f;
+      if (pev.v[u] && pev.v[u + 1] && hipEventElapsedTime(&t, pev.v[u], pev.v[u + 1]) == hipSuccess) {
+        prof_ms[ev_kind[u / 2]] += double(t);
+        prof_by[ev_kind[u / 2]] += ev_bytes[u / 2];
+        ++prof_n[ev_kind[u / 2]];
+      }
+    }
+    ev_used = 0;
+  };
+  const double nnz_per_col = double(X->nnz) / double(std::max<int64_t>(k_live, 1));
+  // record the start of a timed launch; returns the pair's index or -1
+  auto tstart = [&](hipStream_t es, int kind, double cols, double per_nnz, double per_col) -> long {
+    if (!prof || ev_used + 2 > ev_cap) return -1;
+    const size_t u = ev_used;
+    ev_used += 2;
+    ev_kind[u / 2] = kind;
+    ev_bytes[u / 2] = cols * (nnz_per_col * per_nnz + per_col);
+    if (pev.v[u]) (void)hipEventRecord(pev.v[u], es);
+    return long(u);
+  };
+  auto tstop = [&](hipStream_t es, long u) {
+    if (u >= 0 && pev.v[size_t(u) + 1]) (void)hipEventRecord(pev.v[size_t(u) + 1], es);
+  };
   auto enqueue_epoch = [&](hipStream_t es) -> int {
     int rc = launch_epoch_order(ws, k_live, GENCD_SHOTGUN, p->seed, epoch_dev, 0, S, T, es);
     if (rc) return rc;
@@ -763,8 +856,10 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       // column at a time in the order of its positions (grid stride S)
       a.win_lo = 0;
       a.win_hi = int32_t(k_live);
+      const long u = tstart(es, 0, double(k_live), 12.0 + 16.0 * B, 20.0 + 8.0 * B);
       hipLaunchKernelGGL(k_path_fused<B>, dim3(unsigned(std::min<int64_t>(S, 65536))),
                          dim3(kBlock), 0, es, a);
+      tstop(es, u);
     }
     for (int64_t t = 0; t < (fused_epoch ? 0 : T); ++t) {
       a.win_lo = int32_t(t * S);
@@ -772,23 +867,28 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       const int64_t npos = a.win_hi - a.win_lo;
       const unsigned grid = unsigned(std::min<int64_t>(npos > 0 ? npos : 1, 65536));
       if (fused) {
+        const long u = tstart(es, 0, double(npos), 12.0 + 16.0 * B, 20.0 + 8.0 * B);
         hipLaunchKernelGGL(k_path_fused<B>, dim3(grid), dim3(kBlock), 0, es, a);
+        tstop(es, u);
         continue;
       }
+      const long u0 = tstart(es, 0, double(npos), 12.0 + 8.0 * B, 20.0 + 8.0 * B);
       hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, es, a);
+      tstop(es, u0);
+      const long u1 = tstart(es, 1, double(npos), 8.0 + 8.0 * B, 16.0 + 4.0 * B);
       if constexpr (upd_staged)
         hipLaunchKernelGGL(k_path_update_staged<B>,
                            dim3(unsigned(std::min<int64_t>((npos + kBlock / B - 1) / (kBlock / B), 16384))),
                            dim3(kBlock), 0, es, a);
       else
         hipLaunchKernelGGL(k_path_update<B>, dim3(grid), dim3(kBlock), 0, es, a);
+      tstop(es, u1);
     }
     hipLaunchKernelGGL(k_path_renorm<B>, dim3(g1(n * B)), dim3(kBlock), 0, es, n * B, w.zh, w.zl);
     rc = launch_inc_epoch(epoch_dev, es);
     if (rc) return rc;
     return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
   };
-  const bool use_graph = (p->flags & GENCD_USE_GRAPH) != 0;
   PathGraph graph;
   int64_t e = 0;
   bool resync = true;
@@ -797,6 +897,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
     if (resync || e >= next_check) {
       st = path_check<B>(X, y, p->loss, w, s, &red);
       if (st) return st;
+      if (prof) harvest();  // the check synchronised the stream
       resync = false;
       bool admitted = false;
       for (int slot = 0; slot < B; ++slot) {
@@ -877,6 +978,10 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       }
       GENCD_HIP(hipGraphLaunch(graph.exec, s));
     } else {
+      if (prof && ev_used + 4 * size_t(T) + 2 > ev_cap) {  // room for one more epoch
+        GENCD_HIP(hipStreamSynchronize(s));
+        harvest();
+      }
       st = enqueue_epoch(s);
       if (st) return st;
     }
@@ -892,6 +997,15 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
     ++e;
   }
   GENCD_HIP(hipStreamSynchronize(s));
+  if (prof) {
+    harvest();
+    stats[0].prof_launches = prof_n[0];
+    stats[0].prof_kernel_ms = prof_ms[0];
+    stats[0].prof_bytes = prof_by[0];
+    stats[0].prof_update_launches = prof_n[1];
+    stats[0].prof_update_ms = prof_ms[1];
+    stats[0].prof_update_bytes = prof_by[1];
+  }
   return GENCD_OK;
 }
 

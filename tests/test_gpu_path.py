@@ -110,3 +110,40 @@ def test_path_check_statistics_match_oracle(loss, B, flags):
         assert st["kkt_max"] == pytest.approx(oc.kkt, rel=1e-9, abs=1e-15), t
         assert st["gap"] == pytest.approx(gap, rel=1e-6, abs=1e-12 * abs(prim)), t
         assert st["nnz_w"] == int(np.count_nonzero(W[t])), t
+
+
+@pytest.mark.parametrize("flags", [G.FUSED | G.FUSED_EPOCH, G.FUSED, 0])
+def test_path_profile_events(binary_problem, flags):
+    """GENCD_PROFILE on the batched path: HIP events around every fused (or
+    Propose and Update) launch, totals in stats[0]; one fused launch per
+    epoch covers every live column, so its bytes per launch are exactly the
+    stated count."""
+    print("CASE path profile", flags, flush=True)
+    P, Xo, lm = binary_problem
+    lams = synth.lambda_grid(lm, count=6, ratio=0.1)
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    B = 16
+    base = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-7,
+                         max_epochs=20000, flags=flags)
+    ref = G.solve_path(X, y, base, lams, B=B)
+    res = G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4,
+                                           tol=1e-7, max_epochs=20000, flags=flags | G.PROFILE),
+                       lams, B=B)
+    assert res.status == G.OK
+    for a, b in zip(ref.stats, res.stats):
+        assert abs(a["objective"] - b["objective"]) <= 1e-6 * abs(a["objective"])
+    s0 = res.stats[0]
+    epochs = max(s["epochs"] for s in res.stats)
+    assert s0["prof_launches"] >= epochs and s0["prof_kernel_ms"] > 0.0
+    k_live = int(np.count_nonzero(np.diff(P.col_ptr)))
+    if flags & G.FUSED_EPOCH:
+        per = P.nnz * (12 + 16 * B) + k_live * (20 + 8 * B)
+        assert s0["prof_bytes"] == pytest.approx(s0["prof_launches"] * per, rel=1e-9)
+        assert s0["prof_update_launches"] == 0
+    elif flags & G.FUSED:
+        assert s0["prof_update_launches"] == 0
+    else:
+        assert s0["prof_update_launches"] == s0["prof_launches"] and s0["prof_update_ms"] > 0.0
+    for s in res.stats[1:]:
+        assert s["prof_launches"] == 0
