@@ -112,7 +112,7 @@ def main():
                     help="serve: combine the lines of slice runs into one line")
     ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
     ap.add_argument("--no-path-tight", action="store_true",
-                    help="path: skip the KKT 1e-9 level (profiling runs)")
+                    help="path: skip the KKT 1e-10 level (profiling runs)")
     ap.add_argument("--slots", type=int, default=16, help="serve: concurrent request slots")
     ap.add_argument("--sweep-scales", type=float, nargs="+", default=[1.0, 8.0],
                     help="sweep: scales of the logistic workload")
@@ -492,10 +492,11 @@ def bench_path(args):
     lambda geometric from lambda_max down to 1e-3 lambda_max: the batched
     solver (B slots sharing the selected sets, warm-started lambdas,
     adaptive FP64 checks) against the plain path (one warm-started
-    gencd_solve per lambda), at the metric's KKT 1e-6 and at KKT 1e-9, where
+    gencd_solve per lambda), at the metric's KKT 1e-6 and at KKT 1e-10, where
     every objective is compared with the oracle's optimum.  At the small
-    lambdas of this path an absolute KKT 1e-6 exceeds lambda itself, so only
-    the tighter level pins the objective."""
+    lambdas of this path an absolute KKT 1e-6 exceeds lambda itself, and at
+    KKT 1e-9 the objective is still up to ~8e-6 above the optimum there (the
+    weights' l1 norm reaches 4e4), so the tighter level is KKT 1e-10."""
     import numpy as np
     import torch
 
@@ -534,7 +535,9 @@ def bench_path(args):
     def plain(tol):
         ws = G.workspace(X, prm(tol))
         w0, objs, kkts, l1s, epochs = None, [], [], [], 0
-        for lam in lams:
+        for t, lam in enumerate(lams):
+            if t % 8 == 0 or t >= 40:
+                log(f"KKT {tol:g} plain path: lambda {t} of {len(lams)}")
             r = G.solve(X, y, prm(tol, flags=G.USE_GRAPH, lam=float(lam)), w0=w0, ws=ws)
             assert r.stats["converged"], r.stats
             w0, epochs = r.w, epochs + r.stats["epochs"]
@@ -552,8 +555,8 @@ def bench_path(args):
     FE = G.FUSED | G.FUSED_EPOCH
     configs = {1e-6: [(16, 0, 0), (16, G.FUSED, 0), (16, FE, 0), (32, 0, 0), (32, FE, 0), (64, 0, 0),
                       (64, G.FUSED, 0), (64, FE, 0), (64, FE, 20)],
-               1e-9: [(16, FE, 0), (16, G.FUSED, 0), (64, FE, 100)]}
-    for tol in (args.tol,) if args.no_path_tight else (args.tol, 1e-9):
+               1e-10: [(16, FE, 0)]}
+    for tol in (args.tol,) if args.no_path_tight else (args.tol, 1e-10):
         lvl = {"batched": {}}
         best = None
         for B, fl, stag in configs.get(tol, configs[1e-6]):
