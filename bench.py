@@ -27,28 +27,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of one Propose and one Update launch, measured with rocprofv3
-# counters (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size)
-# and kept as a text summary.  It is reported only while the kernel sources
-# and launch configuration are the ones the counters were taken on.
+# HBM traffic of one Propose and one Update launch (headline), and of one
+# fused epoch launch of the batched path, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size) and kept
+# as text summaries.  A figure is reported only while the kernel sources it
+# was taken on are unchanged.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_propose_k_update_zipf1.1-logistic_n100k_k500k_pmc.md")
 TRAFFIC_SOURCES = ["gencd_common.hpp", "gencd_kernels.hpp", "gencd_kernels.hip", "gencd_solver.hip"]
+PATH_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_path_fused_binary_n50k_k200k_path64.md")
+PATH_TRAFFIC_SOURCES = ["gencd_common.hpp", "gencd_kernels.hpp", "gencd_path.hip"]
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for name in TRAFFIC_SOURCES:
+    for name in sources or TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_1206_6409_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel="k_propose"):
-    """Bytes per launch of `kernel` from the counter summary, or None when
-    the summary is missing or was taken on other kernel sources."""
+def measured_traffic(kernel="k_propose", profile=None, sources=None):
+    """Bytes per launch of `kernel` from a counter summary, or None when the
+    summary is missing or was taken on other kernel sources."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(profile or TRAFFIC_PROFILE).read()
     except OSError:
         return None
     vals = {}
@@ -56,7 +59,7 @@ def measured_traffic(kernel="k_propose"):
         if line.startswith("- ") and " = " in line:
             k, v = line[2:].split(" = ", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256(sources):
         return None
     try:
         return float(vals[f"traffic_bytes_per_launch.{kernel}"])
@@ -113,6 +116,9 @@ def main():
     ap.add_argument("--lambdas", type=int, default=64, help="path: number of lambda values")
     ap.add_argument("--no-path-tight", action="store_true",
                     help="path: skip the KKT 1e-10 level (profiling runs)")
+    ap.add_argument("--path-only", default=None, metavar="NAME",
+                    help="path: run only the batched configuration NAME (e.g. B16_fused_epoch), "
+                         "no plain path and no oracle leg (profiling runs)")
     ap.add_argument("--slots", type=int, default=16, help="serve: concurrent request slots")
     ap.add_argument("--sweep-scales", type=float, nargs="+", default=[1.0, 8.0],
                     help="sweep: scales of the logistic workload")
@@ -560,6 +566,10 @@ def bench_path(args):
         lvl = {"batched": {}}
         best = None
         for B, fl, stag in configs.get(tol, configs[1e-6]):
+            name = (f"B{B}" + ("_fused_epoch" if fl & G.FUSED_EPOCH else "_fused" if fl else "")
+                    + (f"_stagger{stag}" if stag else ""))
+            if args.path_only and name != args.path_only:
+                continue
             p_ = prm(tol, flags=G.USE_GRAPH | fl, stagger=stag)
             G.solve_path(X, y, p_, lams[:2], B=B)  # first-use costs out of the timing
             dt, res = _timed(lambda: G.solve_path(X, y, p_, lams, B=B))
@@ -567,8 +577,6 @@ def bench_path(args):
             objs = [st["objective"] for st in res.stats]
             kkts = [st["kkt_max"] for st in res.stats]
             l1s = res.W.double().abs().sum(dim=1).tolist()
-            name = (f"B{B}" + ("_fused_epoch" if fl & G.FUSED_EPOCH else "_fused" if fl else "")
-                    + (f"_stagger{stag}" if stag else ""))
             lvl["batched"][name] = {
                 "seconds": dt, "solves_per_s": len(lams) / dt,
                 "max_epochs": max(st["epochs"] for st in res.stats),
@@ -578,14 +586,17 @@ def bench_path(args):
             log(f"KKT {tol:g} path {name}: {dt:.2f}s")
             if best is None or dt < lvl["batched"][best]["seconds"]:
                 best = name
-        t_plain, (objs_p, kkts_p, l1s_p, ep_p) = _timed(lambda: plain(tol))
-        log(f"KKT {tol:g} plain path: {t_plain:.2f}s")
-        lvl["plain_path"] = {"seconds": t_plain, "solves_per_s": len(lams) / t_plain,
-                             "epochs_total": ep_p,
-                             "objective_rel_err_vs_oracle": errors(objs_p, kkts_p, l1s_p),
-                             "kkt_max": max(kkts_p)}
         lvl["best_batched"] = best
-        lvl["speedup_vs_plain"] = t_plain / lvl["batched"][best]["seconds"]
+        if best is None:
+            raise SystemExit(f"--path-only {args.path_only}: no such configuration")
+        if not args.path_only:
+            t_plain, (objs_p, kkts_p, l1s_p, ep_p) = _timed(lambda: plain(tol))
+            log(f"KKT {tol:g} plain path: {t_plain:.2f}s")
+            lvl["plain_path"] = {"seconds": t_plain, "solves_per_s": len(lams) / t_plain,
+                                 "epochs_total": ep_p,
+                                 "objective_rel_err_vs_oracle": errors(objs_p, kkts_p, l1s_p),
+                                 "kkt_max": max(kkts_p)}
+            lvl["speedup_vs_plain"] = t_plain / lvl["batched"][best]["seconds"]
         out["levels"][f"kkt_{tol:g}"] = lvl
     top = out["levels"][f"kkt_{args.tol:g}"]
     out["value"] = top["batched"][top["best_batched"]]["solves_per_s"]
@@ -605,13 +616,16 @@ def bench_path(args):
             "kernel": f"k_path_fused<{B}> (the whole epoch in one launch: every slot's gradient, "
                       f"step and scatter; 12 + 16*{B} B per nonzero + 20 + 8*{B} B per column)",
             "achieved": round(bpl / us / 1e3, 3), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(bpl / us / 1e3 / 8000.0, 6), "traffic": None,
+            "frac": round(bpl / us / 1e3 / 8000.0, 6),
+            "traffic": measured_traffic(f"k_path_fused<{B}>", PATH_TRAFFIC_PROFILE, PATH_TRAFFIC_SOURCES),
             "avg_launch_us": round(us, 3), "bytes_per_launch": bpl, "launches": nl}
         log(f"k_path_fused<{B}>: {us:.1f} us per epoch launch, {bpl / us / 1e3:.0f} GB/s")
     out["roofline"] = kern["k_path_fused<16>"]
     out["kernels"] = kern
     out["oracle_optima"] = "tests/golden/c4_path_optima.txt (oracle, KKT 1e-10)" if optima is not None \
         else "absent: objectives not compared"
+    if args.path_only:
+        return out
     # oracle on the first lambdas (bounded sample), warm-started like the plain path
     Xo = O.Matrix.of(P)
     yo = P.y.astype(np.float64)
@@ -775,6 +789,15 @@ def bench_serve(args):
         t_free = start + service[i]
         fin.append(t_free - arrivals[i])
     fin = np.array(fin)
+    # the server on the same requests, all submitted at once: its throughput
+    # against the plain path's on identical work
+    same = None
+    if nplain:
+        log(f"server on the plain path's {nplain} requests, submitted at once")
+        res_s, _, _ = run_stream(stream[:nplain], np.zeros(nplain))
+        span_s = max(r["finish_s"] for r in res_s) - min(r["submit_s"] for r in res_s)
+        same = {"requests": nplain, "solves_per_s": nplain / span_s,
+                "all_converged": all(r["status"] == 0 for r in res_s)}
     # error against the oracle's tight optimum, and the oracle's own speed
     prec, o_upd, o_time, o_solves = [], 0, 0.0, 0
     for i in sample:
@@ -832,6 +855,7 @@ def bench_serve(args):
                                 "latency_p50_s": float(np.percentile(fin, 50)) if nplain else None,
                                 "latency_p99_s": float(np.percentile(fin, 99)) if nplain else None,
                                 "note": "FIFO replay of the same arrivals with measured gencd_solve times"},
+        "server_saturated_on_plain_requests": same,
         "precision": {"sample": prec,
                       "objective_rel_err_max": max((p["objective_rel_err"] for p in prec), default=None),
                       "z_max_rel_err_max": max((p["z_max_rel_err"] for p in prec), default=None),
@@ -881,6 +905,11 @@ def merge_serve(paths):
                         "objective_rel_err_max": max((p["objective_rel_err"] for p in prec), default=None),
                         "z_max_rel_err_max": max((p["z_max_rel_err"] for p in prec), default=None),
                         "kkt_max": max((p["kkt_max"] for p in prec), default=None)}
+    for key in ("plain_one_at_a_time", "server_saturated_on_plain_requests", "cpu_baseline"):
+        for l in lines:  # the slice that ran the leg
+            v = l.get(key)
+            if v and (v.get("requests") or v.get("value")):
+                out[key] = v
     out["note"] = ("one stream run as consecutive slices, each started empty; latencies and "
                    "rates combine every request of every slice")
     return out

@@ -38,11 +38,11 @@ def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
                     "- traffic_bytes_per_launch.k_update = 777\n"
                     "- kernel_sources_sha256 = `abc`\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
-    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "abc")
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda sources=None: "abc")
     assert bench.measured_traffic() == 1234.5
     assert bench.measured_traffic("k_update") == 777.0
     assert bench.measured_traffic("k_fused") is None
-    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "def")
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda sources=None: "def")
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
@@ -51,5 +51,6 @@ def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
 def test_source_hash_covers_the_propose_sources():
     h = bench.kernel_sources_sha256()
     assert len(h) == 64 and int(h, 16) >= 0
-    for name in bench.TRAFFIC_SOURCES:
+    for name in bench.TRAFFIC_SOURCES + bench.PATH_TRAFFIC_SOURCES:
         assert os.path.exists(os.path.join(ROOT, "paper_1206_6409_amd", "csrc", name))
+    assert bench.kernel_sources_sha256(bench.PATH_TRAFFIC_SOURCES) != h
