@@ -428,9 +428,13 @@ int gencd_estimate_rho(const gencd_csc *X, const gencd_params *p, int32_t iters,
  * request that meets its tolerance leaves the table while the others go on.
  * Results are the checked iterates: the same computation as gencd_solve with
  * the same parameters (default flags), up to the order of the FP32 atomic
- * additions.  Supported flags: GENCD_WARM_START, GENCD_VALIDATE_DEVICE
- * (GENCD_USE_GRAPH is ignored); others, other rules and improve_steps give
- * GENCD_ERR_UNSUPPORTED at submission.
+ * additions.  Supported flags: GENCD_WARM_START, GENCD_VALIDATE_DEVICE,
+ * GENCD_FUSED (the request's Propose launch scatters each column's step as
+ * soon as it is formed, section 4.1's fused loops; its columns read the
+ * fitted values while others of the window update them, and a round whose
+ * requests are all fused is one launch); GENCD_USE_GRAPH and
+ * GENCD_FUSED_EPOCH are ignored.  GENCD_EXACT_ACCUM, GENCD_PROFILE, other
+ * rules and improve_steps give GENCD_ERR_UNSUPPORTED at submission.
  * ------------------------------------------------------------------------ */
 typedef struct gencd_server gencd_server;
 
@@ -454,13 +458,14 @@ typedef struct {
 typedef struct {
   int32_t running, waiting, finished_unpolled;
   size_t arena_used, arena_bytes;
-  int64_t rounds;        /* Propose/Update launch pairs so far */
+  int64_t rounds;        /* rounds so far (a Propose and an Update launch, or one
+                            launch when every request of the round is fused) */
   int64_t slot_rounds;   /* sum over rounds of the requests each advanced */
   int64_t shared_rounds; /* rounds that advanced two or more requests */
 } gencd_server_status;
 
 /* arena: device memory owned by the caller for the server's lifetime (the
- * server keeps 4 MiB plus 96 B per slot of it for its work tables);
+ * server keeps 4 MiB plus 104 B per slot of it for its work tables);
  * max_slots: concurrent requests (1..256); stream: the rounds run on it and
  * it must stay valid until gencd_server_destroy.  The device current at
  * creation is used by the server's threads.  The server creates one stream

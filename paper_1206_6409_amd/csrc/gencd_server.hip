@@ -157,6 +157,7 @@ struct MpSlot {
   float lam, n_f;
   int32_t loss, G;         // G: lanes per column (4..64, from the mean column length)
   int32_t S, k_live;       // |J| and the live column count
+  int32_t fused, pad_;     // fused: Propose scatters each step at once (GENCD_FUSED)
 };
 
 // Work item (one wave): slot, window-relative positions [lo, hi).  A wave
@@ -169,7 +170,11 @@ constexpr int32_t kMpMaxItems = 262144;  // work items of one round (4 MiB table
 // Round r of every slot: window t = (r - r0) mod T of its epoch order.
 // Propose (UPD = false) writes delta and w_j += delta_j; Update (UPD = true)
 // scatters delta_j x_ij into the low words z_lo (non-returning atomics; the
-// FP64 check at the epoch end re-syncs the pair).
+// FP64 check at the epoch end re-syncs the pair).  A fused slot
+// (GENCD_FUSED, section 4.1) scatters each column's step in its Propose
+// launch, as soon as the group has it, and leaves delta at zero, so the
+// Update launch passes over it; its columns read z while others of the
+// window update it.
 template <bool UPD>
 __global__ __launch_bounds__(kBlock) void k_mp_round(const MpSlot *slots, const int4 *items,
                                                      int32_t nitems, int64_t round) {
@@ -178,6 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_round(const MpSlot *slots, const 
   const int lane = int(threadIdx.x) & (kWave - 1);
   const int4 it = items[wid];
   const MpSlot &sl = slots[it.x];
+  if (UPD && sl.fused) return;  // its steps were scattered by Propose
   const int64_t t = (round - sl.r0) % sl.T;
   const int32_t P0 = int32_t(t * sl.S);
   const int32_t P1 = min(P0 + sl.S, sl.k_live);
@@ -187,12 +193,12 @@ __global__ __launch_bounds__(kBlock) void k_mp_round(const MpSlot *slots, const 
     const int32_t j = sl.col_of_pos[p];
     const int64_t b = sl.col_ptr[j];
     const int32_t len = int32_t(sl.col_ptr[j + 1] - b);
+    int32_t ri[kUnroll];
+    float vv[kUnroll];
     if constexpr (!UPD) {
       const float wj = sl.w[j], cj = sl.c[j];
       float s = 0.0f;
       for (int32_t base = 0; base < len; base += G * kUnroll) {
-        int32_t ri[kUnroll];
-        float vv[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int32_t e = base + u * G + gl;
@@ -206,19 +212,36 @@ __global__ __launch_bounds__(kBlock) void k_mp_round(const MpSlot *slots, const 
         for (int u = 0; u < kUnroll; ++u)
           if (ri[u] >= 0) s += vv[u] * dloss_f32(sl.loss, zr[u].z, zr[u].x + zr[u].y);
       }
+      // butterfly: every lane of the group holds the same sum, hence the same step
       for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+      float d, ph;
+      propose_f32(s / sl.n_f, cj, wj, sl.lam, d, ph);
       if (gl == 0) {
-        float d, ph;
-        propose_f32(s / sl.n_f, cj, wj, sl.lam, d, ph);
-        sl.delta[p - P0] = d;
+        sl.delta[p - P0] = sl.fused ? 0.0f : d;
         if (d != 0.0f) sl.w[j] = wj + d;
+      }
+      if (!sl.fused || d == 0.0f) continue;
+      if (len <= G * kUnroll) {  // the only batch is still in registers
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (ri[u] >= 0) atomicAdd(&sl.zs[ri[u]].y, d * vv[u]);
+        continue;
+      }
+      for (int32_t base = 0; base < len; base += G * kUnroll) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t e = base + u * G + gl;
+          ri[u] = e < len ? sl.row_idx[b + e] : -1;
+          vv[u] = e < len ? sl.val[b + e] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (ri[u] >= 0) atomicAdd(&sl.zs[ri[u]].y, d * vv[u]);
       }
     } else {
       const float d = sl.delta[p - P0];
       if (d == 0.0f) continue;
       for (int32_t base = 0; base < len; base += G * kUnroll) {
-        int32_t ri[kUnroll];
-        float vv[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int32_t e = base + u * G + gl;
@@ -461,6 +484,7 @@ void gencd_server::driver_loop() {
   std::vector<int> active;  // slots in the current work table
   int fail = GENCD_OK;
   bool dirty = false;
+  bool all_fused = false;  // every slot of the work table is fused: no Update launch
   const int Q = int(ev_round.size());
   int stage_next = 0;
 
@@ -582,6 +606,7 @@ void gencd_server::driver_loop() {
       (void)hipEventSynchronize(sg.ev);  // its previous upload has been consumed
       int32_t nitems = 0;
       const int32_t budget = std::max<int32_t>(1, max_items / max_slots);
+      all_fused = true;
       for (int si : active) {
         Slot &sl = slots[size_t(si)];
         const Ws &w = sl.su.ws;
@@ -601,6 +626,9 @@ void gencd_server::driver_loop() {
         d.G = group_for(sl.req.X.nnz, sl.su.k_live);
         d.S = int32_t(sl.S);
         d.k_live = int32_t(sl.su.k_live);
+        d.fused = (sl.req.params.flags & GENCD_FUSED) ? 1 : 0;
+        d.pad_ = 0;
+        all_fused = all_fused && d.fused;
         sg.slots[si] = d;
         int32_t span = (kWave / d.G) * kMpRoundsPerItem;
         const int32_t need = (d.S + budget - 1) / budget;  // at most `budget` items per slot
@@ -625,8 +653,9 @@ void gencd_server::driver_loop() {
     const unsigned grid = unsigned((cur_items + (kBlock / kWave) - 1) / (kBlock / kWave));
     hipLaunchKernelGGL(k_mp_round<false>, dim3(grid), dim3(kBlock), 0, stream, d_slots, d_items,
                        cur_items, rounds);
-    hipLaunchKernelGGL(k_mp_round<true>, dim3(grid), dim3(kBlock), 0, stream, d_slots, d_items,
-                       cur_items, rounds);
+    if (!all_fused)  // fused slots scattered their steps in the Propose launch
+      hipLaunchKernelGGL(k_mp_round<true>, dim3(grid), dim3(kBlock), 0, stream, d_slots, d_items,
+                         cur_items, rounds);
     if (hipGetLastError() != hipSuccess || hipEventRecord(ev_round[size_t(rounds % Q)], stream) != hipSuccess) {
       fail = GENCD_ERR_HIP;
       continue;
@@ -774,7 +803,7 @@ int gencd_server_submit(gencd_server *sv, const gencd_request *req, int64_t *tic
   if (st) return st;
   if (!req->w || !req->y || !csc_ok(&req->X)) return GENCD_ERR_INVALID_ARG;
   if (p.rule != GENCD_SHOTGUN || p.improve_steps != 0 ||
-      (p.flags & (GENCD_FUSED | GENCD_EXACT_ACCUM | GENCD_PROFILE)))
+      (p.flags & (GENCD_EXACT_ACCUM | GENCD_PROFILE)))
     return GENCD_ERR_UNSUPPORTED;
   size_t bytes = 0;
   st = gencd_workspace_bytes(&req->X, &p, &bytes);

@@ -86,6 +86,67 @@ def test_server_results_equal_alone(reqs):
     assert info["slot_rounds"] >= 1.5 * info["rounds"], info
 
 
+def test_server_fused_and_jacobi_requests_in_one_mix(reqs):
+    """Fused requests (GENCD_FUSED: each column's step scattered in the
+    Propose launch) and Jacobi requests share rounds; every result reaches
+    the optimum of its own solve alone with the same flags and of the
+    oracle (objective within 1e-6, KKT 1e-8)."""
+    print("CASE server fused and Jacobi mix", flush=True)
+    dev = [(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV)) for r, P, Xo, lam in reqs]
+    flags = [G.FUSED if i % 2 == 0 else 0 for i in range(len(reqs))]
+    alone = []
+    for (r, P, Xo, lam), (X, y), fl in zip(reqs, dev, flags):
+        res = G.solve(X, y, _params(P.loss, lam, flags=fl))
+        assert res.status == G.OK
+        alone.append(res.stats["objective"])
+    need = sorted(G.Server.request_bytes(X, _params(P.loss, lam))
+                  for (r, P, Xo, lam), (X, y) in zip(reqs, dev))
+    srv = G.Server(arena_bytes=G.Server.overhead_bytes(4) + sum(need[-4:]) + 4096, max_slots=4)
+    ws = [torch.empty(P.k, dtype=torch.float32, device=DEV) for r, P, Xo, lam in reqs]
+    torch.cuda.synchronize()
+    for i, ((r, P, Xo, lam), (X, y)) in enumerate(zip(reqs, dev)):
+        srv.submit(X, y, _params(P.loss, lam, flags=flags[i]), ws[i], tag=i)
+    results = _drain(srv, len(reqs))
+    info = srv.info()
+    srv.close()
+    assert info["shared_rounds"] > 0, info
+    for res in results:
+        i = res["user_tag"]
+        r, P, Xo, lam = reqs[i]
+        assert res["status"] == G.OK, res
+        st = res["stats"]
+        assert st["kkt_max"] <= 1e-8
+        assert abs(st["objective"] - alone[i]) <= 1e-6 * abs(alone[i]), (i, flags[i])
+        oc = O.check(Xo, P.y, P.loss, lam, ws[i].cpu().numpy().astype(np.float64))
+        assert oc.kkt <= 1e-8 * (1 + 1e-6)
+        assert st["objective"] == pytest.approx(oc.objective, rel=1e-12)
+        ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000)
+        assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective), i
+
+
+def test_server_all_fused(reqs):
+    """A server whose requests are all fused (one launch per round) returns
+    the optimum of every request."""
+    print("CASE server all fused", flush=True)
+    sub = reqs[:5]
+    dev = [(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV)) for r, P, Xo, lam in sub]
+    need = sorted(G.Server.request_bytes(X, _params(P.loss, lam))
+                  for (r, P, Xo, lam), (X, y) in zip(sub, dev))
+    srv = G.Server(arena_bytes=G.Server.overhead_bytes(3) + sum(need[-3:]) + 4096, max_slots=3)
+    ws = [torch.empty(P.k, dtype=torch.float32, device=DEV) for r, P, Xo, lam in sub]
+    torch.cuda.synchronize()
+    for i, ((r, P, Xo, lam), (X, y)) in enumerate(zip(sub, dev)):
+        srv.submit(X, y, _params(P.loss, lam, flags=G.FUSED), ws[i], tag=i)
+    results = _drain(srv, len(sub))
+    srv.close()
+    for res in results:
+        i = res["user_tag"]
+        r, P, Xo, lam = sub[i]
+        assert res["status"] == G.OK and res["stats"]["kkt_max"] <= 1e-8, res
+        ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000)
+        assert abs(res["stats"]["objective"] - ref.objective) <= 1e-6 * abs(ref.objective), i
+
+
 # Three requests drawn from the full serving ranges (n in 1k..50k, k in
 # 1k..200k, density 0.1%..2%), generated on the device.
 FULL = [(50000, 200000, 0.002, synth.LOGISTIC, 0.1, 501),
