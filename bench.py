@@ -120,6 +120,9 @@ def main():
                     help="path: run only the batched configuration NAME (e.g. B16_fused_epoch), "
                          "no plain path and no oracle leg (profiling runs)")
     ap.add_argument("--slots", type=int, default=16, help="serve: concurrent request slots")
+    ap.add_argument("--serve-check", type=int, default=0, metavar="E",
+                    help="serve: check_every of the requests (0: a tenth of the epochs run; "
+                         "-m: an m-th)")
     ap.add_argument("--serve-fused", action="store_true",
                     help="serve: requests with GENCD_FUSED (server and plain path alike)")
     ap.add_argument("--sweep-scales", type=float, nargs="+", default=[1.0, 8.0],
@@ -679,7 +682,7 @@ def bench_serve(args):
         # |J| = P* = floor(k_live / (2 rho)) clamped to [1, k_live] (section 4.1);
         # adaptive FP64 check interval (a tenth of the epochs run, 1..64)
         return G.make_params(loss, lam, rule=G.SHOTGUN, select_size=0, seed=11, tol=tol,
-                             max_epochs=100000, check_every=0,
+                             max_epochs=100000, check_every=args.serve_check,
                              flags=G.FUSED if args.serve_fused else 0)
 
     # the largest request of the ranges fixes the per-slot arena share
@@ -835,7 +838,8 @@ def bench_serve(args):
         "config": {"workload": f"{count} Poisson requests, 50/50 Lasso/logistic, n U{{1k..50k}}, "
                                f"k U{{1k..200k}}, density U[0.1%,2%], N(0,1) values, "
                                f"lambda/lambda_max logU[1e-3,0.5], KKT {tol}, |J| = P*, "
-                               f"adaptive check interval"
+                               + ("adaptive check interval" if args.serve_check == 0 else
+                                  f"check_every {args.serve_check}")
                                + (", fused Propose+Update (GENCD_FUSED)" if args.serve_fused else ""),
                    "slots": slots, "rate_per_s": rate,
                    "mean_nnz": float(np.mean([r["stats"]["nnz_visits"] / max(r["stats"]["epochs"], 1)

@@ -127,7 +127,9 @@ typedef struct {
                             tenth of the epochs run so far (between 1 and 64), so a
                             solve stops at most about 10% of its epochs after its
                             first converged epoch (gencd_solve_path: the epochs of
-                            its youngest slot) */
+                            its youngest slot); -m (m >= 1): adaptive with an m-th
+                            of the epochs run instead of a tenth (fewer checks,
+                            up to about 1/m of the epochs after convergence) */
   uint32_t flags;        /* GENCD_* flags */
   const int32_t *color;  /* COLORING: device int32[k] colours (gencd_color) */
   int32_t num_colors;    /* COLORING: number of colours */

@@ -266,10 +266,12 @@ int radix_sort_pairs(uint32_t *k0, int32_t *v0, uint32_t *k1, int32_t *v1, int64
 // Epochs from a check to the next, `done` epochs after the start of the
 // solve: check_every > 0 fixes it; check_every = 0 adapts it to a tenth of
 // the epochs run so far (1 for the first twenty, at most 64), so a solve
-// that first meets its tolerance at epoch N is checked by about 1.1 N.
+// that first meets its tolerance at epoch N is checked by about 1.1 N;
+// check_every = -m adapts it to an m-th (checked by about (1 + 1/m) N).
 inline int64_t check_interval(int64_t check_every, int64_t done) {
   if (check_every > 0) return check_every;
-  const int64_t c = done / 10;
+  const int64_t m = check_every < 0 ? -check_every : 10;
+  const int64_t c = done / m;
   return c < 1 ? 1 : (c > 64 ? 64 : c);
 }
 

@@ -161,7 +161,8 @@ int params_ok(const gencd_params *p, bool need_rule) {
         p->rule != GENCD_BLOCK_SHOTGUN) ||
        (p->flags & GENCD_EXACT_ACCUM) || p->improve_steps > 0))
     return GENCD_ERR_UNSUPPORTED;
-  if (!(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0 || p->check_every < 0)
+  if (!(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0 ||
+      p->check_every < -1000)
     return GENCD_ERR_INVALID_ARG;
   return GENCD_OK;
 }

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgencd.so")
 
 OK, NOT_CONVERGED = 0, 1
-ERR_UNSUPPORTED, ERR_TOO_LARGE = -5, -9
+ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_TOO_LARGE = -1, -5, -9
 SQUARED, LOGISTIC = 0, 1
 CYCLIC, STOCHASTIC, SHOTGUN, THREAD_GREEDY, GREEDY, COLORING, TOP_GREEDY, BLOCK_SHOTGUN = range(8)
 WARM_START, VALIDATE_DEVICE, USE_GRAPH, PROFILE, EXACT_ACCUM, FUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
