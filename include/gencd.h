@@ -98,8 +98,9 @@ typedef enum {
                                       b, b + |J|, b + 2|J|, ... of the epoch order one column
                                       at a time; at most |J| columns are in flight and none
                                       waits for another (asynchronous Shotgun with |J|
-                                      concurrent updates, section 4.1).  Ignored elsewhere;
-                                      UNSUPPORTED without GENCD_FUSED */
+                                      concurrent updates, section 4.1).  UNSUPPORTED without
+                                      GENCD_FUSED and in server requests; ignored by the
+                                      other calls */
 
 /* Device CSC matrix (see the conventions above). */
 typedef struct {
@@ -434,9 +435,9 @@ int gencd_estimate_rho(const gencd_csc *X, const gencd_params *p, int32_t iters,
  * GENCD_FUSED (the request's Propose launch scatters each column's step as
  * soon as it is formed, section 4.1's fused loops; its columns read the
  * fitted values while others of the window update them, and a round whose
- * requests are all fused is one launch); GENCD_USE_GRAPH and
- * GENCD_FUSED_EPOCH are ignored.  GENCD_EXACT_ACCUM, GENCD_PROFILE, other
- * rules and improve_steps give GENCD_ERR_UNSUPPORTED at submission.
+ * requests are all fused is one launch); GENCD_USE_GRAPH is ignored.
+ * GENCD_FUSED_EPOCH, GENCD_EXACT_ACCUM, GENCD_PROFILE, other rules and
+ * improve_steps give GENCD_ERR_UNSUPPORTED at submission.
  * ------------------------------------------------------------------------ */
 typedef struct gencd_server gencd_server;
 

@@ -803,7 +803,7 @@ int gencd_server_submit(gencd_server *sv, const gencd_request *req, int64_t *tic
   if (st) return st;
   if (!req->w || !req->y || !csc_ok(&req->X)) return GENCD_ERR_INVALID_ARG;
   if (p.rule != GENCD_SHOTGUN || p.improve_steps != 0 ||
-      (p.flags & (GENCD_EXACT_ACCUM | GENCD_PROFILE)))
+      (p.flags & (GENCD_EXACT_ACCUM | GENCD_PROFILE | GENCD_FUSED_EPOCH)))
     return GENCD_ERR_UNSUPPORTED;
   size_t bytes = 0;
   st = gencd_workspace_bytes(&req->X, &p, &bytes);

@@ -127,6 +127,7 @@ def test_server_fused_and_jacobi_requests_in_one_mix(reqs):
 def test_server_all_fused(reqs):
     """A server whose requests are all fused (one launch per round) returns
     the optimum of every request."""
+    flags = G.FUSED
     print("CASE server all fused", flush=True)
     sub = reqs[:5]
     dev = [(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV)) for r, P, Xo, lam in sub]
@@ -136,7 +137,7 @@ def test_server_all_fused(reqs):
     ws = [torch.empty(P.k, dtype=torch.float32, device=DEV) for r, P, Xo, lam in sub]
     torch.cuda.synchronize()
     for i, ((r, P, Xo, lam), (X, y)) in enumerate(zip(sub, dev)):
-        srv.submit(X, y, _params(P.loss, lam, flags=G.FUSED), ws[i], tag=i)
+        srv.submit(X, y, _params(P.loss, lam, flags=flags), ws[i], tag=i)
     results = _drain(srv, len(sub))
     srv.close()
     for res in results:
@@ -257,11 +258,15 @@ def test_server_backpressure_and_failures(reqs):
     srv.close()
     st = {r["user_tag"]: r["status"] for r in out}
     assert st[1] == -3 and st[2] == G.OK
-    # rules other than Shotgun are refused at submission
+    # rules other than Shotgun, and whole-epoch launches, are refused at
+    # submission
     srv = G.Server(arena_bytes=G.Server.overhead_bytes(1) + 8 * need, max_slots=1)
     with pytest.raises(G.GencdError) as e:
         srv.submit(Xl, good, G.make_params(Pl.loss, laml, rule=G.THREAD_GREEDY, select_size=64,
                                            block=8), wg)
+    assert e.value.status == -5
+    with pytest.raises(G.GencdError) as e:
+        srv.submit(Xl, good, _params(Pl.loss, laml, flags=G.FUSED | G.FUSED_EPOCH), wg)
     assert e.value.status == -5
     srv.close()
 
