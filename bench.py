@@ -38,6 +38,7 @@ PATH_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_path_fused_binary_n50k_
 PATH_TRAFFIC_SOURCES = ["gencd_common.hpp", "gencd_kernels.hpp", "gencd_path.hip"]
 
 
+
 def kernel_sources_sha256(sources=None):
     import hashlib
     h = hashlib.sha256()
@@ -47,9 +48,10 @@ def kernel_sources_sha256(sources=None):
     return h.hexdigest()
 
 
-def measured_traffic(kernel="k_propose", profile=None, sources=None):
+def measured_traffic(kernel="k_propose", profile=None, sources=None, schedule=None):
     """Bytes per launch of `kernel` from a counter summary, or None when the
-    summary is missing or was taken on other kernel sources."""
+    summary is missing or was taken on other kernel sources (or, when
+    `schedule` is given, under another launch schedule)."""
     try:
         text = open(profile or TRAFFIC_PROFILE).read()
     except OSError:
@@ -60,6 +62,8 @@ def measured_traffic(kernel="k_propose", profile=None, sources=None):
             k, v = line[2:].split(" = ", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_sources_sha256") != kernel_sources_sha256(sources):
+        return None
+    if schedule is not None and vals.get("schedule") != schedule:
         return None
     try:
         return float(vals[f"traffic_bytes_per_launch.{kernel}"])
@@ -97,6 +101,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-thread-greedy", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time only the plain launch path")
+    ap.add_argument("--tune", action="store_true",
+                    help="headline: the autotuner's schedule instead of the default one")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="headline with --tune: the autotuner's cache file (read, appended to on a miss)")
+    ap.add_argument("--schedule", type=int, nargs=3, metavar=("GROUP", "PIECE", "RESIDUAL"),
+                    help="headline: this schedule instead of the autotuner's (profiling runs)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--calibration", type=int, default=200,
                     help="serve: warm-up requests, submitted at once, that set the rate")
@@ -179,6 +189,25 @@ def main():
     base = dict(loss=P.loss, lam=lam, rule=G.SHOTGUN, select_size=args.select, seed=7,
                 tol=args.tol, max_epochs=100000, check_every=1)
     ws = G.workspace(X, G.make_params(**base))
+    # schedule of the Shotgun legs: the project's autotuner (lanes per short
+    # column x piece size x captured graph x residual form), which times each
+    # candidate on 3 epochs of this solve and keeps the fastest
+    tuned, sched = {}, None
+    if args.schedule:
+        sched = {"from": "given on the command line"}
+        tuned = dict(zip(("group", "piece", "residual"), args.schedule))
+    elif args.tune:
+        sched = G.autotune(X, y, G.make_params(**base), epochs=3, cache_path=args.tune_cache)
+        tuned = {"group": int(sched["group"]), "piece": int(sched["piece"]),
+                 "residual": int(sched["residual"])}
+        sched = {"from": "autotuner (3 epochs per candidate)"
+                         + (", cached in " + os.path.relpath(args.tune_cache, ROOT)
+                            if sched["from_cache"] else "")}
+        log(f"autotuned schedule: {tuned}")
+    if tuned:
+        ws = G.workspace(X, G.make_params(**base, **tuned))
+    sched_key = ",".join(str(tuned.get(f, d)) for f, d in (("group", 8), ("piece", 256),
+                                                             ("residual", 0)))
 
     last_res = {}
 
@@ -202,14 +231,20 @@ def main():
         last_res[(rule, flags)] = res
         return dt, stats, res
 
-    log("timing Shotgun solves (plain launches, kernel events on)")
-    dt_plain, stats_plain, _ = run(G.SHOTGUN, args.steps, args.warmup, flags=G.PROFILE)
+    log("timing Shotgun solves (plain launches)")
+    dt_plain, stats_plain, _ = run(G.SHOTGUN, args.steps, args.warmup, **tuned)
+    # kernel durations: HIP events around every Propose and Update launch
+    # (GENCD_PROFILE; the library lets the host queue each epoch before it
+    # starts, so no event pair spans a wait for the host), in solves of their
+    # own, apart from the timed ones
+    log("timing Propose and Update launches (kernel events)")
+    _, stats_prof, _ = run(G.SHOTGUN, max(args.steps // 2, 1), 1, flags=G.PROFILE, **tuned)
     dt, stats = dt_plain, stats_plain
     path = "plain (per-iteration launches)"
     graph_info = None
     if not args.no_graph:
         log("timing Shotgun solves (captured epoch graphs)")
-        dt_g, stats_g, _ = run(G.SHOTGUN, args.steps, args.warmup, flags=G.USE_GRAPH)
+        dt_g, stats_g, _ = run(G.SHOTGUN, args.steps, args.warmup, flags=G.USE_GRAPH, **tuned)
         graph_info = {"solves_per_s": args.steps / dt_g,
                       "nnz_updates_per_s": sum(s["nnz_updates"] for s in stats_g) / dt_g}
         if dt_g < dt_plain:
@@ -219,12 +254,13 @@ def main():
         # fused asynchronous Shotgun (Propose and Update in one launch; the
         # trajectory is not the Jacobi one, the optimum is the same)
         log("timing fused asynchronous Shotgun solves (captured epoch graphs)")
-        dt_f, stats_f, _ = run(G.SHOTGUN, args.steps, args.warmup, flags=G.USE_GRAPH | G.FUSED)
+        dt_f, stats_f, _ = run(G.SHOTGUN, args.steps, args.warmup, flags=G.USE_GRAPH | G.FUSED,
+                               **tuned)
         fused_info = {"solves_per_s": args.steps / dt_f,
                       "nnz_updates_per_s": sum(s["nnz_updates"] for s in stats_f) / dt_f,
                       "epochs_per_solve": stats_f[-1]["epochs"],
                       "objective": stats_f[-1]["objective"], "kkt_max": stats_f[-1]["kkt_max"]}
-    prof_src = stats_plain
+    prof_src = stats_prof
     nnz_upd = sum(s["nnz_updates"] for s in stats)
     coord_upd = sum(s["coord_updates"] for s in stats)
     value = nnz_upd / dt
@@ -234,7 +270,7 @@ def main():
         achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         r = {"bound": "hbm", "kernel": f"{name} ({what})", "achieved": round(achieved, 3),
              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-             "traffic": measured_traffic(name),
+             "traffic": measured_traffic(name, schedule=sched_key),
              "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
              "bytes_per_launch": round(nbytes / max(launches, 1), 1),
              "launches": launches, "total_ms": round(ms, 3)}
@@ -280,6 +316,7 @@ def main():
                         f"logistic, lambda=0.05*lambda_max, Shotgun |J|={args.select}",
             "n": P.n, "k": P.k, "nnz": P.nnz, "lambda": lam, "lambda_max": lam_max,
             "kkt_tol": args.tol, "path": path,
+            "schedule": ({**sched, **tuned} if sched else "default (group 8, piece 256)"),
         },
         "plain_path": {"solves_per_s": args.steps / dt_plain,
                        "nnz_updates_per_s": sum(s["nnz_updates"] for s in stats_plain) / dt_plain},

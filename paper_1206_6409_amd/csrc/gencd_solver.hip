@@ -457,6 +457,18 @@ struct GraphHolder {
   }
 };
 
+// GENCD_PROFILE on plain launches: one thread waits on the device's
+// constant-rate clock for `ticks` before an epoch's launches, so that the
+// host has queued the whole epoch when the first of them starts and no
+// event pair spans a wait for the host.  The wait ends by the clock or
+// after `max_polls` polls, whichever comes first.
+__global__ void k_host_lead(int64_t ticks, int64_t max_polls) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t t0 = wall_clock64();
+  for (int64_t i = 0; i < max_polls && wall_clock64() - t0 < ticks; ++i)
+    __builtin_amdgcn_s_sleep(8);
+}
+
 // HIP events owned by one solve call, released on every return path.
 struct EventPool {
   std::vector<hipEvent_t> v;
@@ -607,6 +619,7 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
   std::vector<hipEvent_t> &evs = pool.v;  // per iteration: Propose pair, Update pair
   size_t ev_used = 0;
   double prof_bytes_pending = 0.0, prof_ubytes_pending = 0.0;
+  double lead_ticks_per_us = 0.0;  // device wall-clock ticks per microsecond
   if (prof) {
     a.scat = ws.scat;
     st = fill_i32(reinterpret_cast<int32_t *>(ws.scat), int64_t(kChkRep) * 32, 0, s);
@@ -700,6 +713,11 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
                       : (rule == GENCD_BLOCK_SHOTGUN) ? T_blk
                                                       : (k_live + S - 1) / S;
     if (prof && evs.empty()) {
+      int rate_khz = 0;
+      int dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess)
+        lead_ticks_per_us = double(rate_khz) / 1000.0;
       const int64_t want = 4 * std::max<int64_t>(T, 1) * (check_every > 0 ? check_every : 64);
       if (want <= 4 * 65536) {
         evs.resize(size_t(want));
@@ -731,6 +749,12 @@ int solve_impl(const gencd_csc *X, const float *y, const gencd_params *p, float 
       }
       GENCD_HIP(hipGraphLaunch(graph.exec, s));
     } else {
+      if (prof && lead_ticks_per_us > 0.0) {
+        // about 15 us of host work per profiled iteration, at most 4 ms
+        const double us = std::min(4000.0, 15.0 * double(std::max<int64_t>(T, 1)));
+        hipLaunchKernelGGL(k_host_lead, dim3(1), dim3(64), 0, s, int64_t(us * lead_ticks_per_us),
+                           int64_t(1) << 22);
+      }
       st = enqueue_epoch(T, e, true, s);
       if (st) return st;
     }
