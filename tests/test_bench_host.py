@@ -42,10 +42,21 @@ def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic() == 1234.5
     assert bench.measured_traffic("k_update") == 777.0
     assert bench.measured_traffic("k_fused") is None
+    assert bench.measured_traffic("k_update", schedule="4,128,1") is None  # no schedule line
+    prof.write_text(prof.read_text() + "- schedule = 4,128,1\n")
+    assert bench.measured_traffic("k_update", schedule="4,128,1") == 777.0
+    assert bench.measured_traffic("k_update", schedule="8,256,0") is None
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda sources=None: "def")
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
+
+
+def test_tune_cache_holds_the_headline_schedule():
+    import json
+    lines = [json.loads(l) for l in open(bench.TUNE_CACHE) if l.strip()]
+    assert lines and all({"key", "group", "piece", "flags", "residual"} <= set(l) for l in lines)
+    assert any("|n100000|k500000|" in l["key"] and "|J4096|" in l["key"] for l in lines)
 
 
 def test_source_hash_covers_the_propose_sources():
