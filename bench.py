@@ -344,6 +344,19 @@ def main():
         "kernels": {"k_propose": rf_p, "k_update": rf_u},
     }
 
+    # the same solves with every atomic update of z TwoSum-compensated
+    # (GENCD_EXACT_ACCUM) instead of the low-word accumulation renormalised
+    # at each epoch end: throughput, and the drift of the FP32 pair from
+    # X w measured at each FP64 check
+    log("timing Shotgun solves with per-update compensated accumulation")
+    dt_x, st_x, _ = run(G.SHOTGUN, args.steps, args.warmup, flags=G.EXACT_ACCUM, **tuned)
+    out["exact_accum_path"] = {
+        "solves_per_s": args.steps / dt_x,
+        "nnz_updates_per_s": sum(s["nnz_updates"] for s in st_x) / dt_x,
+        "z_drift": max(s["z_drift"] for s in st_x),
+        "objective": st_x[-1]["objective"], "kkt_max": st_x[-1]["kkt_max"],
+        "note": "plain launches; z drift = max_i |z_hi + z_lo - (Xw)_i| / rms(Xw) at the checks"}
+
     if not args.no_thread_greedy:
         kRuleSolves = 3  # after one untimed solve, on the captured-epoch path
         log("timing Thread-Greedy solves")

@@ -84,7 +84,11 @@ typedef enum {
 #define GENCD_VALIDATE_DEVICE 0x2u /* check CSC structure and labels on the device */
 #define GENCD_USE_GRAPH 0x4u       /* replay each epoch as a captured HIP graph */
 #define GENCD_PROFILE 0x8u         /* time every Propose and Update launch with HIP events
-                                      (plain launch path only) */
+                                      (plain launch path only; each epoch starts behind a
+                                      short wait on the device clock, about 15 us per
+                                      iteration and at most 4 ms, so that the host has
+                                      queued the epoch and no event pair spans a wait for
+                                      the host: the solve's wall time grows by that much) */
 #define GENCD_EXACT_ACCUM 0x10u    /* TwoSum-compensate every atomic update of z */
 #define GENCD_FUSED 0x20u          /* accept-all rules except Coloring: fused asynchronous
                                       Propose+Update (section 4.1); each column reads z as
