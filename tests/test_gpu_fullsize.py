@@ -8,6 +8,8 @@ graphs), against the FP64 oracle on the same inputs.
   and a whole solve to KKT 1e-6 against the oracle's solve of the same
   configuration (objective to 1e-9, which the identical selection makes
   possible; z at 2000 sampled rows to 1e-6).
+  Thread-Greedy (one proposal accepted per block of 64) solved to KKT 1e-6
+  and compared with the oracle's optimum.
 * zipf1.2-lasso (n 2e5, k 1e6, 6.0 M nonzeros): the colouring bit-exact, and
   a Coloring solve against the oracle's.
 * binary-path (n 5e4, k 2e5, 5.0 M nonzeros): the first 8 lambdas of the
@@ -87,6 +89,29 @@ def test_full_c2_solve(c2):
     rows = np.random.default_rng(1).choice(P.n, size=2000, replace=False)
     z = res.z.cpu().numpy().astype(np.float64)[rows]
     np.testing.assert_allclose(z, r.z[rows], rtol=1e-6, atol=1e-6 * np.abs(r.z).max())
+
+
+def test_full_c2_thread_greedy_solve(c2):
+    """Thread-Greedy at full size, in the benchmark's configuration (|J| =
+    4096, one accepted proposal per block of 64 positions, section 4.1),
+    captured graphs: the oracle re-checks the returned w (KKT 1e-6) and the
+    objective is within 1e-6 of the oracle's optimum (KKT 1e-10)."""
+    _case("full c2 thread-greedy solve")
+    P, Xo, lam = c2
+    params = G.make_params(P.loss, lam, rule=G.THREAD_GREEDY, select_size=4096, block=64, seed=7,
+                           tol=1e-6, max_epochs=100000, flags=G.USE_GRAPH)
+    res = G.solve(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV), params)
+    assert res.status == G.OK
+    w = res.w.cpu().numpy().astype(np.float64)
+    chk = O.check(Xo, P.y, P.loss, lam, w)
+    assert chk.kkt <= 1e-6 * (1 + 1e-6)
+    assert res.stats["objective"] == pytest.approx(chk.objective, rel=1e-12)
+    # the oracle's own solve to KKT 1e-6, then cyclic CD to KKT 1e-10
+    start = O.solve(Xo, P.y, P.loss, lam, O.SHOTGUN, select_size=4096, seed=7, tol=1e-6,
+                    max_epochs=100000)
+    ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-10, max_epochs=100000, w0=start.w)
+    assert ref.converged
+    assert abs(chk.objective - ref.objective) <= 1e-6 * abs(ref.objective)
 
 
 def test_full_c3_colouring_and_solve():

@@ -41,14 +41,15 @@ def test_path_matches_independent_solves(binary_problem, B, L, flags, stagger, e
     res = G.solve_path(X, y, params, lams, B=B)
     assert res.status == G.OK
     W = res.W.cpu().numpy().astype(np.float64)
+    w_or = None  # the oracle's own warm-started chain along the path
     for t, lam in enumerate(lams):
         st = res.stats[t]
         assert st["converged"] == 1 and st["kkt_max"] <= 1e-8, (t, st)
         oc = O.check(Xo, P.y, P.loss, lam, W[t])
         assert oc.kkt <= 1e-8 * (1 + 1e-6)
         assert st["objective"] == pytest.approx(oc.objective, rel=1e-12)
-        ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000,
-                      w0=W[t - 1] if t > 0 else None)
+        ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000, w0=w_or)
+        w_or = ref.w
         assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective), t
 
 
