@@ -578,9 +578,10 @@ def bench_path(args):
     lams = synth.lambda_grid(lm, count=args.lambdas, ratio=1e-3)
     optima = load_path_optima(lams) if args.scale == 1.0 else None
 
-    def prm(tol, flags=0, stagger=0, lam=0.0):
+    def prm(tol, flags=0, stagger=0, lam=0.0, improve=0):
         return G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=1024, seed=5, tol=tol,
-                             max_epochs=60000, check_every=0, flags=flags, stagger=stagger)
+                             max_epochs=60000, check_every=0, flags=flags, stagger=stagger,
+                             improve=improve)
 
     def errors(objs, kkts, l1s):
         """Relative objective error against the oracle's optimum, and the
@@ -597,13 +598,14 @@ def bench_path(args):
                 "per_lambda": [float(x) for x in e],
                 "convexity_bound_per_lambda": [float(x) for x in bound]}
 
-    def plain(tol):
+    def plain(tol, improve):
         ws = G.workspace(X, prm(tol))
         w0, objs, kkts, l1s, epochs = None, [], [], [], 0
         for t, lam in enumerate(lams):
             if t % 8 == 0 or t >= 40:
-                log(f"KKT {tol:g} plain path: lambda {t} of {len(lams)}")
-            r = G.solve(X, y, prm(tol, flags=G.USE_GRAPH, lam=float(lam)), w0=w0, ws=ws)
+                log(f"KKT {tol:g} plain path (improve {improve}): lambda {t} of {len(lams)}")
+            r = G.solve(X, y, prm(tol, flags=G.USE_GRAPH, lam=float(lam), improve=improve), w0=w0,
+                        ws=ws)
             assert r.stats["converged"], r.stats
             w0, epochs = r.w, epochs + r.stats["epochs"]
             objs.append(r.stats["objective"])
@@ -618,18 +620,29 @@ def bench_path(args):
                       "check_every": "adaptive (a tenth of the epochs run, 1..64)"},
            "levels": {}}
     FE = G.FUSED | G.FUSED_EPOCH
-    configs = {1e-6: [(16, 0, 0), (16, G.FUSED, 0), (16, FE, 0), (32, 0, 0), (32, FE, 0), (64, 0, 0),
-                      (64, G.FUSED, 0), (64, FE, 0), (64, FE, 20)],
-               1e-10: [(16, FE, 0)]}
+    # (B, flags, stagger, improve-delta steps); the plain path's improve steps
+    configs = {1e-6: [(16, 0, 0, 0), (16, G.FUSED, 0, 0), (16, FE, 0, 0), (32, 0, 0, 0),
+                      (32, FE, 0, 0), (64, 0, 0, 0), (64, G.FUSED, 0, 0), (64, FE, 0, 0),
+                      (64, FE, 20, 0), (16, FE, 0, 5), (16, FE, 0, 10), (16, FE, 0, 50),
+                      (32, FE, 0, 10), (64, FE, 0, 10)],
+               1e-10: [(16, FE, 0, 0), (16, FE, 0, 10), (16, FE, 0, 20), (16, FE, 0, 50),
+                       (16, FE, 0, 200), (32, FE, 0, 20)]}
+    plain_steps = {1e-6: (0, 10), 1e-10: (20,)}
+
+    def leg_name(B, fl, stag, imp):
+        return (f"B{B}" + ("_fused_epoch" if fl & G.FUSED_EPOCH else "_fused" if fl else "")
+                + (f"_stagger{stag}" if stag else "") + (f"_improve{imp}" if imp else ""))
+
+    cfg_of = {leg_name(*c): c for cs in configs.values() for c in cs}
+
     for tol in (args.tol,) if args.no_path_tight else (args.tol, 1e-10):
         lvl = {"batched": {}}
         best = None
-        for B, fl, stag in configs.get(tol, configs[1e-6]):
-            name = (f"B{B}" + ("_fused_epoch" if fl & G.FUSED_EPOCH else "_fused" if fl else "")
-                    + (f"_stagger{stag}" if stag else ""))
+        for B, fl, stag, imp in configs.get(tol, configs[1e-6]):
+            name = leg_name(B, fl, stag, imp)
             if args.path_only and name != args.path_only:
                 continue
-            p_ = prm(tol, flags=G.USE_GRAPH | fl, stagger=stag)
+            p_ = prm(tol, flags=G.USE_GRAPH | fl, stagger=stag, improve=imp)
             G.solve_path(X, y, p_, lams[:2], B=B)  # first-use costs out of the timing
             dt, res = _timed(lambda: G.solve_path(X, y, p_, lams, B=B))
             assert all(st["converged"] for st in res.stats)
@@ -649,13 +662,19 @@ def bench_path(args):
         if best is None:
             raise SystemExit(f"--path-only {args.path_only}: no such configuration")
         if not args.path_only:
-            t_plain, (objs_p, kkts_p, l1s_p, ep_p) = _timed(lambda: plain(tol))
-            log(f"KKT {tol:g} plain path: {t_plain:.2f}s")
-            lvl["plain_path"] = {"seconds": t_plain, "solves_per_s": len(lams) / t_plain,
-                                 "epochs_total": ep_p,
-                                 "objective_rel_err_vs_oracle": errors(objs_p, kkts_p, l1s_p),
-                                 "kkt_max": max(kkts_p)}
-            lvl["speedup_vs_plain"] = t_plain / lvl["batched"][best]["seconds"]
+            # the plain path (one warm-started gencd_solve per lambda) with the
+            # same options; the speed-up is against its fastest form
+            lvl["plain_paths"] = {}
+            for imp in plain_steps.get(tol, (0,)):
+                t_plain, (objs_p, kkts_p, l1s_p, ep_p) = _timed(lambda: plain(tol, imp))
+                log(f"KKT {tol:g} plain path (improve {imp}): {t_plain:.2f}s")
+                lvl["plain_paths"][f"improve{imp}"] = {
+                    "seconds": t_plain, "solves_per_s": len(lams) / t_plain, "epochs_total": ep_p,
+                    "objective_rel_err_vs_oracle": errors(objs_p, kkts_p, l1s_p),
+                    "kkt_max": max(kkts_p)}
+            pbest = min(lvl["plain_paths"], key=lambda k_: lvl["plain_paths"][k_]["seconds"])
+            lvl["plain_path"] = dict(lvl["plain_paths"][pbest], form=pbest)
+            lvl["speedup_vs_plain"] = lvl["plain_path"]["seconds"] / lvl["batched"][best]["seconds"]
         out["levels"][f"kkt_{tol:g}"] = lvl
     top = out["levels"][f"kkt_{args.tol:g}"]
     out["value"] = top["batched"][top["best_batched"]]["solves_per_s"]
@@ -663,23 +682,33 @@ def bench_path(args):
     # HIP events around every k_path_fused launch on the call's stream (plain
     # launches); bytes per launch are the algorithmic count the library
     # reports (12 + 16 B per nonzero, 20 + 8 B per column at B slots)
+    # and of its instance with the improve steps of the fastest configuration
     kern = {}
-    for B in (16, 64):
-        p_ = prm(args.tol, flags=G.FUSED | G.FUSED_EPOCH | G.PROFILE)
+    top_cfg = cfg_of.get(top["best_batched"], (16, FE, 0, 0))
+    profiled = [(16, 0), (64, 0)]
+    if top_cfg[1] & G.FUSED_EPOCH and top_cfg[3] > 0:
+        profiled.append((top_cfg[0], top_cfg[3]))
+    for B, imp in profiled:
+        p_ = prm(args.tol, flags=G.FUSED | G.FUSED_EPOCH | G.PROFILE, improve=imp)
         s0 = G.solve_path(X, y, p_, lams, B=B).stats[0]
         nl = max(s0["prof_launches"], 1)
         us = s0["prof_kernel_ms"] * 1e3 / nl
         bpl = s0["prof_bytes"] / nl
-        kern[f"k_path_fused<{B}>"] = {
+        kname = f"k_path_fused<{B}>" + (f" improve{imp}" if imp else "")
+        kern[kname] = {
             "bound": "hbm",
             "kernel": f"k_path_fused<{B}> (the whole epoch in one launch: every slot's gradient, "
-                      f"step and scatter; 12 + 16*{B} B per nonzero + 20 + 8*{B} B per column)",
+                      f"step and scatter; 12 + 16*{B} B per nonzero + 20 + 8*{B} B per column)"
+                      + (f", up to {imp} improve-delta steps per slot and column (not counted)"
+                         if imp else ""),
             "achieved": round(bpl / us / 1e3, 3), "peak": 8000.0, "unit": "GB/s",
             "frac": round(bpl / us / 1e3 / 8000.0, 6),
-            "traffic": measured_traffic(f"k_path_fused<{B}>", PATH_TRAFFIC_PROFILE, PATH_TRAFFIC_SOURCES),
+            "traffic": measured_traffic(kname, PATH_TRAFFIC_PROFILE, PATH_TRAFFIC_SOURCES),
             "avg_launch_us": round(us, 3), "bytes_per_launch": bpl, "launches": nl}
-        log(f"k_path_fused<{B}>: {us:.1f} us per epoch launch, {bpl / us / 1e3:.0f} GB/s")
-    out["roofline"] = kern["k_path_fused<16>"]
+        log(f"{kname}: {us:.1f} us per epoch launch, {bpl / us / 1e3:.0f} GB/s")
+    # the roofline names the kernel of the fastest configuration
+    rname = f"k_path_fused<{top_cfg[0]}>" + (f" improve{top_cfg[3]}" if top_cfg[3] else "")
+    out["roofline"] = kern.get(rname, kern["k_path_fused<16>"])
     out["kernels"] = kern
     out["oracle_optima"] = "tests/golden/c4_path_optima.txt (oracle, KKT 1e-10)" if optima is not None \
         else "absent: objectives not compared"

@@ -96,7 +96,8 @@ typedef enum {
                                       are applied one launch later, so the trajectory is
                                       not the Jacobi one (the optimum is the same).  Not
                                       with EXACT_ACCUM or improve_steps (UNSUPPORTED).
-                                      gencd_solve_path: one launch per shared window */
+                                      gencd_solve_path: one launch per shared window,
+                                      improve_steps allowed, EXACT_ACCUM UNSUPPORTED */
 #define GENCD_FUSED_EPOCH 0x40u    /* gencd_solve_path with GENCD_FUSED: the whole epoch in one
                                       launch of |J| workgroups, workgroup b taking positions
                                       b, b + |J|, b + 2|J|, ... of the epoch order one column
@@ -147,8 +148,11 @@ typedef struct {
                             accepted proposal's 1-D objective, from the state at
                             the start of the iteration; stops early once a step
                             no longer changes the increment.  0 = off (default);
-                            the paper used 500.
-                            gencd_solve / gencd_step only (0..1000000) */
+                            the paper used 500.  gencd_solve, gencd_step and
+                            gencd_solve_path (0..1000000; on the path every slot
+                            of a column takes its own steps, with GENCD_FUSED
+                            from the z its workgroup read, so concurrent
+                            columns may have moved z meanwhile) */
   int32_t residual;      /* how Propose forms l'(y_i, z_i) (Algorithm 2): 1 = per
                             entry from the gathered z_hi, z_lo, y of its row;
                             2 = from a residual vector refreshed (one pass over
@@ -322,7 +326,13 @@ int gencd_balance_colors(const gencd_csc *X, const int32_t *color, int32_t num_c
  * or Propose launches, prof_update_* those of the Update launches.  Bytes
  * per nonzero of a launch's columns: fused 12 + 16 B, Propose 12 + 8 B,
  * Update 8 + 8 B; per column: fused and Propose 20 + 8 B, Update
- * 16 + 4 B).
+ * 16 + 4 B; the improve steps re-read nothing for a column of at most 32
+ * nonzeros and are not counted).
+ * p->improve_steps > 0: "improve delta_j" on every slot's increment
+ * (Algorithm 3, section 4.1), before it is applied.
+ * Errors: those of gencd_solve (INVALID_ARG also for B, L or a lambda out
+ * of range), and UNSUPPORTED for a rule other than SHOTGUN, GENCD_FUSED with
+ * GENCD_EXACT_ACCUM, or GENCD_FUSED_EPOCH without GENCD_FUSED.
  * Workspace bytes from gencd_path_workspace_bytes. */
 int gencd_path_workspace_bytes(const gencd_csc *X, const gencd_params *p, int32_t B,
                                size_t *out_bytes);

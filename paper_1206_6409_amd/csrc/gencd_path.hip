@@ -83,6 +83,7 @@ struct PathArgs {
   const float *lam;
   const int32_t *active;
   float *delta;
+  int32_t improve;  // "improve delta_j" steps per column and slot (0: off)
 };
 
 // One 256-thread block per column of the window: thread (r, s) = (row lane,
@@ -101,11 +102,82 @@ struct PathShape {
   static constexpr int NW = kBlock / kWave;
 };
 
-template <int B>
+// "Improve delta_j" (Algorithm 3, section 4.1) for every slot of one
+// column: up to a.improve further Eq. 7 steps on the slot's 1-D objective
+//   f_s(d) = (1/n) sum_i l(y_i, Z[i][s] + d x_ij) + lambda_s |W[j][s] + d|
+// from the increment in sdel[s] and the z the workgroup read for the first
+// step.  Called by the whole workgroup with the same thread shape as the
+// first step; a column held in one batch keeps its entries, z and y in
+// registers (zb, yb), a longer one re-reads them every step (in the fused
+// launch other columns may have moved z meanwhile).  A slot whose step no
+// longer changes d keeps it (every later step would repeat it), and the loop
+// ends once no slot changed.  Slot lanes hold the slot's w_j, c_j, lambda;
+// the improved increments are left in sdel.
+template <int B, int R, int PU, int NW>
+__device__ __forceinline__ void path_improve(const PathArgs &a, int64_t cb, int64_t ce, bool one,
+                                             int s, int r, const int32_t (&ri)[PU],
+                                             const float (&vv)[PU], const float (&zb)[PU],
+                                             const float (&yb)[PU], float wj, float cj, float lam,
+                                             float (&sred)[NW][B], float *sdel) {
+  for (int32_t t = 0; t < a.improve; ++t) {
+    const float d = sdel[s];
+    float acc = 0.0f;
+    if (d != 0.0f) {
+      if (one) {
+#pragma unroll
+        for (int q = 0; q < PU; ++q)
+          if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yb[q], zb[q] + d * vv[q]);
+      } else {
+        for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
+          int32_t rj[PU];
+          float vj[PU], zj[PU], yj[PU];
+#pragma unroll
+          for (int q = 0; q < PU; ++q) {
+            const int64_t e = base + int64_t(q) * R + r;
+            rj[q] = e < ce ? a.row_idx[e] : -1;
+            vj[q] = e < ce ? a.val[e] : 0.0f;
+          }
+#pragma unroll
+          for (int q = 0; q < PU; ++q) {
+            const int64_t i = rj[q] >= 0 ? rj[q] : 0;
+            zj[q] = a.zh[i * B + s] + a.zl[i * B + s];
+            yj[q] = a.y[i];
+          }
+#pragma unroll
+          for (int q = 0; q < PU; ++q)
+            if (rj[q] >= 0) acc += vj[q] * dloss_f32(a.loss, yj[q], zj[q] + d * vj[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
+    if (int(threadIdx.x) % kWave < B) sred[threadIdx.x / kWave][s] = acc;
+    __syncthreads();
+    int changed = 0;
+    if (int(threadIdx.x) < B && d != 0.0f) {
+      float g = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) g += sred[w][s];
+      g /= a.n_f;
+      float inc, ph;
+      propose_f32(g, cj, wj + d, lam, inc, ph);
+      const float dn = d + inc;
+      if (dn != d) {
+        sdel[s] = dn;
+        changed = 1;
+      }
+    }
+    // every read of sdel and sred of this step precedes the barrier
+    if (!__syncthreads_or(changed)) break;
+  }
+}
+
+template <int B, bool IMP>
 __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
   using SH = PathShape<B>;
   constexpr int R = SH::R, PU = SH::PU, NW = SH::NW;
   __shared__ float sred[NW][B];
+  __shared__ float sdel[B];
   const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
   const int64_t npos = a.win_hi - a.win_lo;
   for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
@@ -123,26 +195,29 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
       act = a.active[s];
     }
     float acc = 0.0f;
+    int32_t ri[PU];
+    float vv[PU], zb[PU], yb[PU];  // the last batch (the whole column if it fits one)
+#pragma unroll
+    for (int q = 0; q < PU; ++q) {
+      ri[q] = -1;
+      vv[q] = zb[q] = yb[q] = 0.0f;
+    }
     for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
-      int32_t ri[PU];
-      float vv[PU];
 #pragma unroll
       for (int q = 0; q < PU; ++q) {
         const int64_t e = base + int64_t(q) * R + r;
         ri[q] = e < ce ? a.row_idx[e] : -1;
         vv[q] = e < ce ? a.val[e] : 0.0f;
       }
-      float zh[PU], zl[PU], yy[PU];
 #pragma unroll
       for (int q = 0; q < PU; ++q) {
         const int64_t i = ri[q] >= 0 ? ri[q] : 0;  // row 0 stands in for padding
-        zh[q] = a.zh[i * B + s];
-        zl[q] = a.zl[i * B + s];
-        yy[q] = a.y[i];
+        zb[q] = a.zh[i * B + s] + a.zl[i * B + s];
+        yb[q] = a.y[i];
       }
 #pragma unroll
       for (int q = 0; q < PU; ++q)
-        if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yy[q], zh[q] + zl[q]);
+        if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yb[q], zb[q]);
     }
 #pragma unroll
     for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
@@ -157,11 +232,19 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
         g /= a.n_f;
         float ph;
         propose_f32(g, cj, wj, lam, d, ph);
-        if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
       }
+      sdel[s] = d;
+    }
+    __syncthreads();
+    if constexpr (IMP)  // uniform: the whole workgroup takes the steps
+      path_improve<B, R, PU, NW>(a, cb, ce, ce - cb <= int64_t(R) * PU, s, r, ri, vv, zb, yb, wj,
+                                 cj, lam, sred, sdel);
+    if (int(threadIdx.x) < B) {
+      const float d = sdel[s];
+      if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
       a.delta[p * B + s] = d;
     }
-    __syncthreads();  // sred is reused by the next column
+    __syncthreads();  // sred and sdel are reused by the next column
   }
 }
 
@@ -217,7 +300,7 @@ __device__ __forceinline__ void path_batch(const PathArgs &a, int64_t base, int6
   }
 }
 
-template <int B>
+template <int B, bool IMP>
 __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
   using SH = PathShape<B>;
   constexpr int R = SH::R, PU = SH::PU, NW = SH::NW;
@@ -249,19 +332,22 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
     const bool more = pn < npos;
     const int4 pdn = more ? a.pdesc[a.win_lo + pn] : make_int4(0, 0, 0, 0);
     float acc = 0.0f;
+    float zb[PU], yb[PU];
     for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
       if (base != cb) path_batch<B, PU, R>(a, base, ce, r, ri, vv);
-      float zh[PU], zl[PU], yy[PU];
+      float zh[PU], zl[PU];
 #pragma unroll
       for (int q = 0; q < PU; ++q) {
         const int64_t i = ri[q] >= 0 ? ri[q] : 0;
         zh[q] = a.zh[i * B + s];
         zl[q] = a.zl[i * B + s];
-        yy[q] = a.y[i];
+        yb[q] = a.y[i];
       }
 #pragma unroll
-      for (int q = 0; q < PU; ++q)
-        if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yy[q], zh[q] + zl[q]);
+      for (int q = 0; q < PU; ++q) {
+        zb[q] = zh[q] + zl[q];
+        if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yb[q], zb[q]);
+      }
     }
 #pragma unroll
     for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
@@ -276,12 +362,14 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
         g /= a.n_f;
         float ph;
         propose_f32(g, cj, wj, lam, d, ph);
-        if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
       }
       sdel[s] = d;
     }
     __syncthreads();
+    if constexpr (IMP)  // uniform: the whole workgroup takes the steps
+      path_improve<B, R, PU, NW>(a, cb, ce, one, s, r, ri, vv, zb, yb, wj, cj, lam, sred, sdel);
     const float d = sdel[s];
+    if (slot_lane && d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
     // the next position's loads go out before this column's atomics
     int32_t rn[PU];
     float vn[PU];
@@ -785,6 +873,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   a.lam = w.lam;
   a.active = w.active;
   a.delta = w.delta;
+  a.improve = p->improve_steps;
   const int64_t check_every = p->check_every;  // 0: adaptive, on the youngest slot's age
   int64_t next_check = 0;
   // measured on the 64-lambda binary workload: the staged update wins at
@@ -792,6 +881,10 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   constexpr bool upd_staged = B == 64;
   const bool fused = (p->flags & GENCD_FUSED) != 0;
   const bool fused_epoch = fused && (p->flags & GENCD_FUSED_EPOCH) != 0;
+  // the kernel instances with "improve delta_j" steps, or without
+  const bool imp = p->improve_steps > 0;
+  void (*const kfused)(PathArgs) = imp ? k_path_fused<B, true> : k_path_fused<B, false>;
+  void (*const kpropose)(PathArgs) = imp ? k_path_propose<B, true> : k_path_propose<B, false>;
   std::vector<double> red;
   const int64_t T = (k_live + S - 1) / S;
   // One epoch: selection order (section 2.1), the shared windows' launches,
@@ -857,8 +950,8 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       a.win_lo = 0;
       a.win_hi = int32_t(k_live);
       const long u = tstart(es, 0, double(k_live), 12.0 + 16.0 * B, 20.0 + 8.0 * B);
-      hipLaunchKernelGGL(k_path_fused<B>, dim3(unsigned(std::min<int64_t>(S, 65536))),
-                         dim3(kBlock), 0, es, a);
+      hipLaunchKernelGGL(kfused, dim3(unsigned(std::min<int64_t>(S, 65536))), dim3(kBlock), 0, es,
+                         a);
       tstop(es, u);
     }
     for (int64_t t = 0; t < (fused_epoch ? 0 : T); ++t) {
@@ -868,12 +961,12 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       const unsigned grid = unsigned(std::min<int64_t>(npos > 0 ? npos : 1, 65536));
       if (fused) {
         const long u = tstart(es, 0, double(npos), 12.0 + 16.0 * B, 20.0 + 8.0 * B);
-        hipLaunchKernelGGL(k_path_fused<B>, dim3(grid), dim3(kBlock), 0, es, a);
+        hipLaunchKernelGGL(kfused, dim3(grid), dim3(kBlock), 0, es, a);
         tstop(es, u);
         continue;
       }
       const long u0 = tstart(es, 0, double(npos), 12.0 + 8.0 * B, 20.0 + 8.0 * B);
-      hipLaunchKernelGGL(k_path_propose<B>, dim3(grid), dim3(kBlock), 0, es, a);
+      hipLaunchKernelGGL(kpropose, dim3(grid), dim3(kBlock), 0, es, a);
       tstop(es, u0);
       const long u1 = tstart(es, 1, double(npos), 8.0 + 8.0 * B, 16.0 + 4.0 * B);
       if constexpr (upd_staged)
@@ -1034,11 +1127,12 @@ int gencd_solve_path(const gencd_csc *X, const float *y, const gencd_params *p,
   auto t0 = std::chrono::steady_clock::now();
   if (!X || !p || !lambdas || L <= 0 || !W || !stats) return GENCD_ERR_INVALID_ARG;
   if (B != 16 && B != 32 && B != 64) return GENCD_ERR_INVALID_ARG;
-  if (p->rule != GENCD_SHOTGUN || p->improve_steps != 0 ||
+  if (p->rule != GENCD_SHOTGUN ||
       ((p->flags & GENCD_FUSED) && (p->flags & GENCD_EXACT_ACCUM)) ||
       ((p->flags & GENCD_FUSED_EPOCH) && !(p->flags & GENCD_FUSED)))
     return GENCD_ERR_UNSUPPORTED;
-  if (p->select_size <= 0 || !(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0)
+  if (p->select_size <= 0 || !(p->kkt_tol >= 0.0) || !(p->gap_tol >= 0.0) || p->max_epochs < 0 ||
+      p->improve_steps < 0 || p->improve_steps > 1000000)
     return GENCD_ERR_INVALID_ARG;
   if (p->loss != GENCD_SQUARED && p->loss != GENCD_LOGISTIC) return GENCD_ERR_INVALID_ARG;
   for (int32_t t = 0; t < L; ++t)

@@ -53,6 +53,73 @@ def test_path_matches_independent_solves(binary_problem, B, L, flags, stagger, e
         assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective), t
 
 
+@pytest.mark.parametrize("B,L,flags,steps", [
+    (16, 20, G.FUSED | G.FUSED_EPOCH, 50), (32, 12, 0, 20), (64, 6, G.FUSED | G.USE_GRAPH, 5),
+    (16, 20, G.USE_GRAPH, 1), (64, 6, G.FUSED | G.FUSED_EPOCH | G.USE_GRAPH, 500)])
+def test_path_improve_matches_independent_solves(binary_problem, B, L, flags, steps):
+    """"Improve delta_j" (Algorithm 3, section 4.1) on every slot of the
+    batched path: each lambda's result passes the oracle's KKT test and its
+    objective is within 1e-6 of the oracle's own optimum."""
+    print("CASE path improve", B, L, flags, steps, flush=True)
+    P, Xo, lm = binary_problem
+    lams = synth.lambda_grid(lm, count=L, ratio=0.1)
+    params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-8,
+                           max_epochs=20000, flags=flags, improve=steps)
+    res = G.solve_path(G.Matrix.of(P), torch.as_tensor(P.y, device=DEV), params, lams, B=B)
+    assert res.status == G.OK
+    W = res.W.cpu().numpy().astype(np.float64)
+    w_or = None
+    for t, lam in enumerate(lams):
+        st = res.stats[t]
+        assert st["converged"] == 1 and st["kkt_max"] <= 1e-8, (t, st)
+        oc = O.check(Xo, P.y, P.loss, lam, W[t])
+        assert oc.kkt <= 1e-8 * (1 + 1e-6)
+        assert st["objective"] == pytest.approx(oc.objective, rel=1e-12)
+        ref = O.solve(Xo, P.y, P.loss, lam, O.CYCLIC, tol=1e-11, max_epochs=500000, w0=w_or)
+        w_or = ref.w
+        assert abs(oc.objective - ref.objective) <= 1e-6 * abs(ref.objective), t
+
+
+def test_path_improve_single_lambda_equals_solve(binary_problem):
+    """One lambda with improve steps: the batched path and gencd_solve (the
+    same Jacobi windows, the improvement from the state at the window's
+    start) reach the same objective."""
+    P, Xo, lm = binary_problem
+    lam = 0.05 * lm
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+    kw = dict(rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-8, max_epochs=20000, improve=20)
+    single = G.solve(X, y, G.make_params(P.loss, lam, **kw))
+    path = G.solve_path(X, y, G.make_params(P.loss, 0.0, **kw), [lam], B=16)
+    assert single.status == G.OK and path.status == G.OK
+    assert path.stats[0]["converged"] == 1
+    assert abs(path.stats[0]["objective"] - single.stats["objective"]) <= 1e-7 * single.stats["objective"]
+
+
+def test_path_improve_takes_fewer_epochs(binary_problem):
+    """At the small lambdas of the logistic path the quadratic bound's step
+    is far shorter than the coordinate minimiser's; improving each increment
+    cuts the epochs to a tight KKT tolerance (the reason the paper offers the
+    option): without it, three times the epochs the improved solve needed
+    leave some lambda unconverged."""
+    P, Xo, lm = binary_problem
+    lams = synth.lambda_grid(lm, count=64, ratio=1e-3)[60:]
+    X = G.Matrix.of(P)
+    y = torch.as_tensor(P.y, device=DEV)
+
+    def run(steps, max_epochs):
+        params = G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=256, seed=4, tol=1e-8,
+                               max_epochs=max_epochs, improve=steps)
+        return G.solve_path(X, y, params, lams, B=16)
+
+    imp = run(50, 100000)
+    assert imp.status == G.OK and all(st["converged"] for st in imp.stats)
+    e50 = max(st["epochs"] for st in imp.stats)
+    plain = run(0, 3 * e50)
+    assert plain.status == G.NOT_CONVERGED, e50
+    assert not all(st["converged"] for st in plain.stats)
+
+
 def test_path_single_lambda_equals_solve(binary_problem):
     P, Xo, lm = binary_problem
     lam = 0.1 * lm
@@ -80,6 +147,11 @@ def test_path_rejects_bad_args(binary_problem):
         G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=64,
                                          flags=G.FUSED_EPOCH), [0.1 * lm], B=16)
     assert e.value.status == G.ERR_UNSUPPORTED
+    for steps in (-1, 1000001):
+        with pytest.raises(G.GencdError) as e:
+            G.solve_path(X, y, G.make_params(P.loss, 0.0, rule=G.SHOTGUN, select_size=64,
+                                             improve=steps), [0.1 * lm], B=16)
+        assert e.value.status == G.ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("loss,B,flags", [(synth.SQUARED, 32, G.USE_GRAPH), (synth.SQUARED, 64, 0),

@@ -109,6 +109,7 @@ def test_solve_with_select_size_from_rho(seed, rule):
     assert abs(st["rho"] - ro) <= 1e-10 * ro
     assert _pstar_ok(st["select_size"], klo, ro)
     assert res.status == 0 and st["kkt_max"] <= 1e-8
-    ref = O.solve(Xo, P.y, P.loss, lam, O.SHOTGUN, select_size=int(st["select_size"]), seed=5,
+    # the oracle's own |J| from its own rho estimate
+    ref = O.solve(Xo, P.y, P.loss, lam, O.SHOTGUN, select_size=O.pstar(klo, ro), seed=5,
                   tol=1e-10, max_epochs=200000)
     assert abs(st["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
