@@ -623,10 +623,10 @@ def bench_path(args):
     # (B, flags, stagger, improve-delta steps); the plain path's improve steps
     configs = {1e-6: [(16, 0, 0, 0), (16, G.FUSED, 0, 0), (16, FE, 0, 0), (32, 0, 0, 0),
                       (32, FE, 0, 0), (64, 0, 0, 0), (64, G.FUSED, 0, 0), (64, FE, 0, 0),
-                      (64, FE, 20, 0), (16, FE, 0, 5), (16, FE, 0, 10), (16, FE, 0, 50),
+                      (64, FE, 20, 0), (16, FE, 0, 5), (16, FE, 0, 10), (16, FE, 0, 20),
                       (32, FE, 0, 10), (64, FE, 0, 10)],
-               1e-10: [(16, FE, 0, 0), (16, FE, 0, 10), (16, FE, 0, 20), (16, FE, 0, 50),
-                       (16, FE, 0, 200), (32, FE, 0, 20)]}
+               1e-10: [(16, FE, 0, 0), (16, FE, 0, 20), (16, FE, 0, 50), (16, FE, 0, 100),
+                       (32, FE, 0, 50)]}
     plain_steps = {1e-6: (0, 10), 1e-10: (20,)}
 
     def leg_name(B, fl, stag, imp):

@@ -152,7 +152,9 @@ typedef struct {
                             gencd_solve_path (0..1000000; on the path every slot
                             of a column takes its own steps, with GENCD_FUSED
                             from the z its workgroup read, so concurrent
-                            columns may have moved z meanwhile) */
+                            columns may have moved z meanwhile; for a column of
+                            at most 32 nonzeros the steps use the hardware
+                            exponential and reciprocal, about 1 ulp each) */
   int32_t residual;      /* how Propose forms l'(y_i, z_i) (Algorithm 2): 1 = per
                             entry from the gathered z_hi, z_lo, y of its row;
                             2 = from a residual vector refreshed (one pass over

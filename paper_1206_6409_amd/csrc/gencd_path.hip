@@ -172,6 +172,117 @@ __device__ __forceinline__ void path_improve(const PathArgs &a, int64_t cb, int6
   }
 }
 
+// The same steps for a column held in one batch (at most R * PU = 32
+// entries), without workgroup barriers between steps: the column's entries,
+// y and every slot's z go to LDS once, then wave v takes the slots
+// [v B/4, (v+1) B/4), R lanes per slot and PU entries per lane (the first
+// step's thread shape with slots and row lanes swapped), sums over its R
+// lanes with DPP moves (every lane gets the same bits) and repeats until
+// none of its slots changed or the steps run out.
+// l'(y, t) for the improve steps of a column held in one batch: the two
+// signs of m = y t are selected instead of branched on (lanes of one wave
+// see both), m >= 0: e = exp(-m), s = e / (1 + e); m < 0: e = exp(m),
+// s = 1 / (1 + e), with the hardware exponential and reciprocal (about one
+// ulp each) in place of the correctly rounded forms.  The steps are
+// VALU-bound, and they only refine an increment whose effect the FP64 check
+// judges.
+__device__ __forceinline__ float dloss_fast_f32(int loss, float y, float t) {
+  if (loss == GENCD_SQUARED) return t - y;
+  const float m = y * t;
+  const float e = __expf(-fabsf(m));
+  return -y * ((m >= 0.0f ? e : 1.0f) * __builtin_amdgcn_rcpf(1.0f + e));
+}
+
+// Sum over an aligned group of N = 4, 8 or 16 lanes with DPP moves inside
+// a row (xor 1, xor 2, half-row mirror, row mirror): every stage adds the
+// partner's partial to the lane's own, and the partner adds the same two
+// values, so every lane of the group ends with the same bits.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int N>
+__device__ __forceinline__ float row_group_sum(float x) {
+  static_assert(N == 4 || N == 8 || N == 16, "groups inside one DPP row");
+  x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  if constexpr (N >= 8) x += dpp_move<0x141>(x);   // row_half_mirror
+  if constexpr (N >= 16) x += dpp_move<0x140>(x);  // row_mirror
+  return x;
+}
+
+template <int B>
+struct ImproveLds {
+  float z[32][B + 1];  // padded: lanes of one slot read a column of this
+  float v[32], y[32];
+  float w[B], lam[B];
+  float c;
+};
+
+template <int B, int R, int PU>
+__device__ __forceinline__ void path_improve_wave(const PathArgs &a, int s, int r,
+                                                  const int32_t (&ri)[PU], const float (&vv)[PU],
+                                                  const float (&zb)[PU], const float (&yb)[PU],
+                                                  float wj, float cj, float lam, float *sdel,
+                                                  ImproveLds<B> &L) {
+  static_assert(R * PU == 32, "one batch holds 32 entries");
+  constexpr int SPW = B / (kBlock / kWave);  // slots per wave
+  static_assert(SPW * R == kWave, "a wave holds SPW slots of R lanes");
+#pragma unroll
+  for (int q = 0; q < PU; ++q) {
+    const int e = q * R + r;
+    const bool ok = ri[q] >= 0;
+    L.z[e][s] = ok ? zb[q] : 0.0f;
+    if (s == 0) {
+      L.v[e] = ok ? vv[q] : 0.0f;  // padding contributes 0 * l'(1, 0)
+      L.y[e] = ok ? yb[q] : 1.0f;
+    }
+  }
+  if (int(threadIdx.x) < B) {
+    L.w[s] = wj;
+    L.lam[s] = lam;
+    if (s == 0) L.c = cj;
+  }
+  __syncthreads();
+  const int lane = int(threadIdx.x) % kWave;
+  const int sl = lane / R, rl = lane % R;
+  const int s2 = int(threadIdx.x) / kWave * SPW + sl;
+  float v[PU], z[PU], y[PU];
+#pragma unroll
+  for (int q = 0; q < PU; ++q) {
+    const int e = q * R + rl;
+    v[q] = L.v[e];
+    z[q] = L.z[e][s2];
+    y[q] = L.y[e];
+  }
+  const float w2 = L.w[s2], lam2 = L.lam[s2], c2 = L.c;
+  // Eq. 7 at w + d: d <- d - clamp(w + d, (g - lambda) / c, (g + lambda) / c),
+  // with 1/n and 1/c formed once
+  const float rn = 1.0f / a.n_f, rc = c2 > 0.0f ? 1.0f / c2 : 0.0f;
+  float d = c2 > 0.0f ? sdel[s2] : 0.0f;
+  for (int32_t t = 0; t < a.improve; ++t) {
+    float acc = 0.0f;
+    if (d != 0.0f) {
+#pragma unroll
+      for (int q = 0; q < PU; ++q) acc += v[q] * dloss_fast_f32(a.loss, y[q], z[q] + d * v[q]);
+    }
+    acc = row_group_sum<R>(acc);
+    int changed = 0;
+    if (d != 0.0f) {
+      const float g = acc * rn;
+      const float lo = (g - lam2) * rc, hi = (g + lam2) * rc, wd = w2 + d;
+      const float dn = d - (wd < lo ? lo : (wd > hi ? hi : wd));
+      changed = dn != d;
+      d = dn;
+    }
+    if (!__any(changed)) break;  // every slot of the wave keeps its increment
+  }
+  __syncthreads();  // every lane has read sdel before it is rewritten
+  if (rl == 0) sdel[s2] = d;
+  __syncthreads();
+}
+
 template <int B, bool IMP>
 __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
   using SH = PathShape<B>;
@@ -236,9 +347,13 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
       sdel[s] = d;
     }
     __syncthreads();
-    if constexpr (IMP)  // uniform: the whole workgroup takes the steps
-      path_improve<B, R, PU, NW>(a, cb, ce, ce - cb <= int64_t(R) * PU, s, r, ri, vv, zb, yb, wj,
-                                 cj, lam, sred, sdel);
+    if constexpr (IMP) {  // uniform: the whole workgroup takes the steps
+      __shared__ ImproveLds<B> simp;
+      if (ce - cb <= int64_t(R) * PU)
+        path_improve_wave<B, R, PU>(a, s, r, ri, vv, zb, yb, wj, cj, lam, sdel, simp);
+      else
+        path_improve<B, R, PU, NW>(a, cb, ce, false, s, r, ri, vv, zb, yb, wj, cj, lam, sred, sdel);
+    }
     if (int(threadIdx.x) < B) {
       const float d = sdel[s];
       if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
@@ -366,8 +481,13 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
       sdel[s] = d;
     }
     __syncthreads();
-    if constexpr (IMP)  // uniform: the whole workgroup takes the steps
-      path_improve<B, R, PU, NW>(a, cb, ce, one, s, r, ri, vv, zb, yb, wj, cj, lam, sred, sdel);
+    if constexpr (IMP) {  // uniform: the whole workgroup takes the steps
+      __shared__ ImproveLds<B> simp;
+      if (one)
+        path_improve_wave<B, R, PU>(a, s, r, ri, vv, zb, yb, wj, cj, lam, sdel, simp);
+      else
+        path_improve<B, R, PU, NW>(a, cb, ce, false, s, r, ri, vv, zb, yb, wj, cj, lam, sred, sdel);
+    }
     const float d = sdel[s];
     if (slot_lane && d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
     // the next position's loads go out before this column's atomics
