@@ -139,11 +139,20 @@ def test_improved_solve_reaches_the_optimum(problems, name, rule, kw):
 
 
 def test_improve_rejected_where_unsupported(problems):
+    """Improve steps: out of range anywhere, and refused by the server
+    (the batched path takes them; its tests are with the path's)."""
     P = problems["c1"]
     X = G.Matrix.of(P)
     y = torch.as_tensor(P.y, device=DEV)
     lam = 0.1 * G.lambda_max(X, y, P.loss)
-    with pytest.raises(G.GencdError):
-        G.solve_path(X, y, G.make_params(P.loss, lam, select_size=256, improve=5), [lam], B=16)
+    with pytest.raises(G.GencdError) as e:
+        G.solve_path(X, y, G.make_params(P.loss, lam, select_size=256, improve=-1), [lam], B=16)
+    assert e.value.status == G.ERR_INVALID_ARG
     with pytest.raises(G.GencdError):
         G.solve(X, y, G.make_params(P.loss, lam, select_size=256, improve=-1))
+    srv = G.Server(arena_bytes=64 << 20, max_slots=2)
+    w = torch.zeros(P.k, dtype=torch.float32, device=DEV)
+    with pytest.raises(G.GencdError) as e:
+        srv.submit(X, y, G.make_params(P.loss, lam, rule=G.SHOTGUN, select_size=256, improve=5), w)
+    assert e.value.status == G.ERR_UNSUPPORTED
+    srv.close()
