@@ -88,12 +88,27 @@ def test_improved_step_parity(problems, case):
     zo = z_hi.astype(np.float64) + z_lo.astype(np.float64)
     oblock = block if rule == G.THREAD_GREEDY else 0
     otop = min(block, m) if rule == G.TOP_GREEDY else 0
+    # the oracle's own Accept first; a GPU pick that differs must tie the
+    # oracle's best proxy to 1e-6, and the oracle's step then takes that pick
+    probe = O.step(Xo, P.y, P.loss, lam, J, wo.copy(), zo.copy(), block=oblock, top=otop)
     forced = None
     if rule == G.THREAD_GREEDY:
-        forced = np.array([lo + int(np.argmax(acc[lo:lo + block])) for lo in range(0, m, block)],
-                          dtype=np.int32)
+        forced = np.full((m + block - 1) // block, -1, dtype=np.int32)
+        for b, lo in enumerate(range(0, m, block)):
+            hi = min(m, lo + block)
+            assert acc[lo:hi].sum() == 1
+            gpos = lo + int(np.argmax(acc[lo:hi]))
+            opos = lo + int(np.argmax(probe.accepted[lo:hi]))
+            if gpos != opos:
+                assert probe.phi[gpos] - probe.phi[opos] <= 1e-6 * abs(probe.phi[opos])
+            forced[b] = gpos
     elif rule == G.TOP_GREEDY:
-        forced = np.nonzero(acc)[0].astype(np.int32)
+        assert acc.sum() == otop
+        gset, oset = np.nonzero(acc)[0], np.nonzero(probe.accepted)[0]
+        kth = np.sort(probe.phi)[otop - 1]
+        for q in np.setdiff1d(gset, oset):
+            assert probe.phi[q] - kth <= 1e-6 * abs(kth)
+        forced = gset.astype(np.int32)
     r = O.step(Xo, P.y, P.loss, lam, J, wo, zo, block=oblock, top=otop, forced=forced,
                improve=improve)
     sel = acc == 1
