@@ -10,6 +10,7 @@
 // per slot.  A slot whose KKT test passes is retired on the host and the
 // next lambda (decreasing order) is admitted into it, warm-started from the
 // latest iterate of its predecessor.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -921,14 +922,22 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
   std::vector<int32_t> lambda_slot(L, -1);
   std::vector<int32_t> done(L, 0);
   std::vector<int64_t> start_epoch(L, 0);
+  std::vector<int64_t> end_epoch(L, -1);  // epoch of the check that retired the lambda
+  std::vector<char> z_valid(B, 0);         // the slot's z is X times its w
   std::vector<float> lam_host(B, 0.0f);
   std::vector<double> lam64_host(B, 0.0);
   std::vector<int32_t> act_host(B, 0);
   int32_t next = 0;
   int st = fill_f32(w.W, k * B, 0.0f, s);
   if (st) return st;
-  auto admit = [&](int slot, int64_t epoch) -> int {
+  // *z_ok: whether the slot's z now equals X times its warm start, so no
+  // re-sync is needed.  After a check every slot's (z_hi, z_lo) is the split
+  // of its FP64 X w; a predecessor still held in a slot, or retired by this
+  // very check (its slot not yet refilled, see below), lends its column of
+  // z with its weights.
+  auto admit = [&](int slot, int64_t epoch, bool *z_ok) -> int {
     const int32_t t = next++;
+    *z_ok = false;
     slot_lambda[slot] = t;
     lambda_slot[t] = slot;
     lam_host[slot] = float(lambdas[t]);
@@ -938,18 +947,31 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
     // warm start from the latest iterate of the predecessor (decreasing lambdas)
     const float *src = nullptr;
     int64_t ss = 0, si = 0;
+    int32_t zsrc = -1;  // slot whose z column matches the warm start
     if (t > 0 && lambda_slot[t - 1] >= 0 && !done[t - 1]) {
       src = w.W;
       ss = B;
       si = lambda_slot[t - 1];
+      if (z_valid[si]) zsrc = int32_t(si);
     } else if (t > 0 && done[t - 1]) {
       src = W_out + int64_t(t - 1) * k;
       ss = 1;
       si = 0;
+      // slots are refilled in increasing order with increasing lambdas, so
+      // the predecessor's slot still holds its z (or is this slot)
+      if (end_epoch[t - 1] == epoch && z_valid[lambda_slot[t - 1]]) zsrc = lambda_slot[t - 1];
     }
-    if (src == w.W && si == slot) return GENCD_OK;
-    hipLaunchKernelGGL(k_strided_copy, dim3(g1(k)), dim3(kBlock), 0, s, k, src, ss, si, w.W,
-                       int64_t(B), int64_t(slot));
+    if (src)
+      hipLaunchKernelGGL(k_strided_copy, dim3(g1(k)), dim3(kBlock), 0, s, k, src, ss, si, w.W,
+                         int64_t(B), int64_t(slot));
+    if (zsrc >= 0 && zsrc != slot) {
+      hipLaunchKernelGGL(k_strided_copy, dim3(g1(n)), dim3(kBlock), 0, s, n, w.zh, int64_t(B),
+                         int64_t(zsrc), w.zh, int64_t(B), int64_t(slot));
+      hipLaunchKernelGGL(k_strided_copy, dim3(g1(n)), dim3(kBlock), 0, s, n, w.zl, int64_t(B),
+                         int64_t(zsrc), w.zl, int64_t(B), int64_t(slot));
+    }
+    *z_ok = zsrc >= 0;
+    z_valid[slot] = *z_ok;
     return hipGetLastError() == hipSuccess ? GENCD_OK : GENCD_ERR_HIP;
   };
   // a lambda may enter once its predecessor has run `stagger` epochs (or is
@@ -960,7 +982,8 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
                         e - start_epoch[next - 1] >= stagger);
   };
   for (int slot = 0; slot < B && may_admit(0); ++slot) {
-    st = admit(slot, 0);
+    bool z_ok;  // the first check re-syncs every slot anyway
+    st = admit(slot, 0, &z_ok);
     if (st) return st;
   }
   auto push_slots = [&]() -> int {
@@ -1112,6 +1135,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       if (st) return st;
       if (prof) harvest();  // the check synchronised the stream
       resync = false;
+      std::fill(z_valid.begin(), z_valid.end(), 1);  // the check re-synced every slot's z
       bool admitted = false;
       for (int slot = 0; slot < B; ++slot) {
         const int32_t t = slot_lambda[slot];
@@ -1142,6 +1166,7 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
                                int64_t(B), int64_t(slot), Z_out + int64_t(t) * n);
           GENCD_HIP(hipGetLastError());
           done[t] = 1;
+          end_epoch[t] = e;
           --remaining;
           slot_lambda[slot] = -1;
           act_host[slot] = 0;
@@ -1149,11 +1174,14 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
           lam64_host[slot] = 0.0;
         }
       }
+      bool stale = false;  // some admitted slot's z is not X w
       for (int slot = 0; slot < B && may_admit(e); ++slot) {
         if (slot_lambda[slot] >= 0) continue;
-        st = admit(slot, e);
+        bool z_ok;
+        st = admit(slot, e, &z_ok);
         if (st) return st;
         admitted = true;
+        stale |= !z_ok;
       }
       st = push_slots();
       if (st) return st;
@@ -1169,8 +1197,8 @@ int path_run(const gencd_csc *X, const float *y, const gencd_params *p, const do
       for (int slot = 0; slot < B; ++slot) free_slot |= slot_lambda[slot] < 0;
       if (free_slot && stagger > 0 && next < L && !done[next - 1])
         next_check = std::min(next_check, start_epoch[next - 1] + stagger);  // the next entry
-      if (admitted) {
-        resync = true;  // z of the admitted slots must be recomputed from W
+      if (admitted && stale) {
+        resync = true;  // z of an admitted slot must be recomputed from W
         continue;
       }
     }
