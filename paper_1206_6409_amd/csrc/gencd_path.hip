@@ -106,48 +106,39 @@ struct PathShape {
 // "Improve delta_j" (Algorithm 3, section 4.1) for every slot of one
 // column: up to a.improve further Eq. 7 steps on the slot's 1-D objective
 //   f_s(d) = (1/n) sum_i l(y_i, Z[i][s] + d x_ij) + lambda_s |W[j][s] + d|
-// from the increment in sdel[s] and the z the workgroup read for the first
-// step.  Called by the whole workgroup with the same thread shape as the
-// first step; a column held in one batch keeps its entries, z and y in
-// registers (zb, yb), a longer one re-reads them every step (in the fused
-// launch other columns may have moved z meanwhile).  A slot whose step no
-// longer changes d keeps it (every later step would repeat it), and the loop
-// ends once no slot changed.  Slot lanes hold the slot's w_j, c_j, lambda;
-// the improved increments are left in sdel.
+// from the increment in sdel[s] and the z of the first step.  This form
+// serves columns longer than one batch: the whole workgroup takes each step
+// with the first step's thread shape and arithmetic, re-reading the entries,
+// z and y (in the fused launch other columns may have moved z meanwhile).
+// A slot whose step no longer changes d keeps it (every later step would
+// repeat it), and the loop ends once no slot changed.  Slot lanes hold the
+// slot's w_j, c_j, lambda; the improved increments are left in sdel.
 template <int B, int R, int PU, int NW>
-__device__ __forceinline__ void path_improve(const PathArgs &a, int64_t cb, int64_t ce, bool one,
-                                             int s, int r, const int32_t (&ri)[PU],
-                                             const float (&vv)[PU], const float (&zb)[PU],
-                                             const float (&yb)[PU], float wj, float cj, float lam,
+__device__ __forceinline__ void path_improve(const PathArgs &a, int64_t cb, int64_t ce, int s,
+                                             int r, float wj, float cj, float lam,
                                              float (&sred)[NW][B], float *sdel) {
   for (int32_t t = 0; t < a.improve; ++t) {
     const float d = sdel[s];
     float acc = 0.0f;
     if (d != 0.0f) {
-      if (one) {
+      for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
+        int32_t rj[PU];
+        float vj[PU], zj[PU], yj[PU];
+#pragma unroll
+        for (int q = 0; q < PU; ++q) {
+          const int64_t e = base + int64_t(q) * R + r;
+          rj[q] = e < ce ? a.row_idx[e] : -1;
+          vj[q] = e < ce ? a.val[e] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < PU; ++q) {
+          const int64_t i = rj[q] >= 0 ? rj[q] : 0;
+          zj[q] = a.zh[i * B + s] + a.zl[i * B + s];
+          yj[q] = a.y[i];
+        }
 #pragma unroll
         for (int q = 0; q < PU; ++q)
-          if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yb[q], zb[q] + d * vv[q]);
-      } else {
-        for (int64_t base = cb; base < ce; base += int64_t(R) * PU) {
-          int32_t rj[PU];
-          float vj[PU], zj[PU], yj[PU];
-#pragma unroll
-          for (int q = 0; q < PU; ++q) {
-            const int64_t e = base + int64_t(q) * R + r;
-            rj[q] = e < ce ? a.row_idx[e] : -1;
-            vj[q] = e < ce ? a.val[e] : 0.0f;
-          }
-#pragma unroll
-          for (int q = 0; q < PU; ++q) {
-            const int64_t i = rj[q] >= 0 ? rj[q] : 0;
-            zj[q] = a.zh[i * B + s] + a.zl[i * B + s];
-            yj[q] = a.y[i];
-          }
-#pragma unroll
-          for (int q = 0; q < PU; ++q)
-            if (rj[q] >= 0) acc += vj[q] * dloss_f32(a.loss, yj[q], zj[q] + d * vj[q]);
-        }
+          if (rj[q] >= 0) acc += vj[q] * dloss_f32(a.loss, yj[q], zj[q] + d * vj[q]);
       }
     }
 #pragma unroll
@@ -173,13 +164,6 @@ __device__ __forceinline__ void path_improve(const PathArgs &a, int64_t cb, int6
   }
 }
 
-// The same steps for a column held in one batch (at most R * PU = 32
-// entries), without workgroup barriers between steps: the column's entries,
-// y and every slot's z go to LDS once, then wave v takes the slots
-// [v B/4, (v+1) B/4), R lanes per slot and PU entries per lane (the first
-// step's thread shape with slots and row lanes swapped), sums over its R
-// lanes with DPP moves (every lane gets the same bits) and repeats until
-// none of its slots changed or the steps run out.
 // l'(y, t) for the improve steps of a column held in one batch: the two
 // signs of m = y t are selected instead of branched on (lanes of one wave
 // see both), m >= 0: e = exp(-m), s = e / (1 + e); m < 0: e = exp(m),
@@ -213,6 +197,7 @@ __device__ __forceinline__ float row_group_sum(float x) {
   return x;
 }
 
+// One column of at most 32 entries in LDS for path_improve_wave.
 template <int B>
 struct ImproveLds {
   float z[32][B + 1];  // padded: lanes of one slot read a column of this
@@ -221,6 +206,14 @@ struct ImproveLds {
   float c;
 };
 
+// The same steps for a column held in one batch (at most R * PU = 32
+// entries), without workgroup barriers between steps: the column's entries,
+// y and every slot's z go to LDS once, then wave v takes the slots
+// [v B/4, (v+1) B/4), R lanes per slot and PU entries per lane (the first
+// step's thread shape with slots and row lanes swapped), sums over its R
+// lanes with DPP moves (every lane gets the same bits) and repeats until
+// none of its slots changed or the steps run out.  The loss derivative takes
+// the fast forms above, and 1/n and 1/c are formed once.
 template <int B, int R, int PU>
 __device__ __forceinline__ void path_improve_wave(const PathArgs &a, int s, int r,
                                                   const int32_t (&ri)[PU], const float (&vv)[PU],
@@ -353,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
       if (ce - cb <= int64_t(R) * PU)
         path_improve_wave<B, R, PU>(a, s, r, ri, vv, zb, yb, wj, cj, lam, sdel, simp);
       else
-        path_improve<B, R, PU, NW>(a, cb, ce, false, s, r, ri, vv, zb, yb, wj, cj, lam, sred, sdel);
+        path_improve<B, R, PU, NW>(a, cb, ce, s, r, wj, cj, lam, sred, sdel);
     }
     if (int(threadIdx.x) < B) {
       const float d = sdel[s];
@@ -487,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
       if (one)
         path_improve_wave<B, R, PU>(a, s, r, ri, vv, zb, yb, wj, cj, lam, sdel, simp);
       else
-        path_improve<B, R, PU, NW>(a, cb, ce, false, s, r, ri, vv, zb, yb, wj, cj, lam, sred, sdel);
+        path_improve<B, R, PU, NW>(a, cb, ce, s, r, wj, cj, lam, sred, sdel);
     }
     const float d = sdel[s];
     if (slot_lane && d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
