@@ -556,12 +556,14 @@ def bench_path(args):
     """64-lambda regularisation path (binary, n=5e4, k=2e5, density 0.05%),
     lambda geometric from lambda_max down to 1e-3 lambda_max: the batched
     solver (B slots sharing the selected sets, warm-started lambdas,
-    adaptive FP64 checks) against the plain path (one warm-started
-    gencd_solve per lambda), at the metric's KKT 1e-6 and at KKT 1e-10, where
-    every objective is compared with the oracle's optimum.  At the small
-    lambdas of this path an absolute KKT 1e-6 exceeds lambda itself, and at
-    KKT 1e-9 the objective is still up to ~8e-6 above the optimum there (the
-    weights' l1 norm reaches 4e4), so the tighter level is KKT 1e-10."""
+    adaptive FP64 checks; with and without the "improve delta_j" steps of
+    Algorithm 3) against the plain path (one warm-started gencd_solve per
+    lambda, with and without the steps; the speed-up is against its fastest
+    form), at the metric's KKT 1e-6 and at KKT 1e-10, where every objective
+    is compared with the oracle's optimum.  At the small lambdas of this path
+    an absolute KKT 1e-6 exceeds lambda itself, and at KKT 1e-9 the
+    objective is still up to ~8e-6 above the optimum there (the weights' l1
+    norm reaches 4e4), so the tighter level is KKT 1e-10."""
     import numpy as np
     import torch
 
