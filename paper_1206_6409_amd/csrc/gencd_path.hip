@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "gencd_common.hpp"
@@ -197,54 +198,63 @@ __device__ __forceinline__ float row_group_sum(float x) {
   return x;
 }
 
-// One column of at most 32 entries in LDS for path_improve_wave.
+// One column of at most 64 entries (two batches) in LDS for
+// path_improve_wave; the first step's batch loop stages it.
+constexpr int kImproveMax = 64;
+
 template <int B>
 struct ImproveLds {
-  float z[32][B + 1];  // padded: lanes of one slot read a column of this
-  float v[32], y[32];
+  float z[kImproveMax][B + 1];  // padded: lanes of one slot read a column of this
+  float v[kImproveMax], y[kImproveMax];
   float w[B], lam[B];
   float c;
 };
 
-// The same steps for a column held in one batch (at most R * PU = 32
-// entries), without workgroup barriers between steps: the column's entries,
-// y and every slot's z go to LDS once, then wave v takes the slots
-// [v B/4, (v+1) B/4), R lanes per slot and PU entries per lane (the first
-// step's thread shape with slots and row lanes swapped), sums over its R
-// lanes with DPP moves (every lane gets the same bits) and repeats until
-// none of its slots changed or the steps run out.  The loss derivative takes
-// the fast forms above, and 1/n and 1/c are formed once.
+// Stage one batch of the first step (thread (r, s) holds entries
+// boff + q R + r of the column) for the improve steps; padding gets v = 0,
+// z = 0, y = 1, so that it adds 0 * l'(1, 0).
 template <int B, int R, int PU>
-__device__ __forceinline__ void path_improve_wave(const PathArgs &a, int s, int r,
-                                                  const int32_t (&ri)[PU], const float (&vv)[PU],
-                                                  const float (&zb)[PU], const float (&yb)[PU],
-                                                  float wj, float cj, float lam, float *sdel,
-                                                  ImproveLds<B> &L) {
-  static_assert(R * PU == 32, "one batch holds 32 entries");
-  constexpr int SPW = B / (kBlock / kWave);  // slots per wave
-  static_assert(SPW * R == kWave, "a wave holds SPW slots of R lanes");
+__device__ __forceinline__ void improve_stage(ImproveLds<B> &L, int boff, int s, int r,
+                                              const int32_t (&ri)[PU], const float (&vv)[PU],
+                                              const float (&zb)[PU], const float (&yb)[PU]) {
 #pragma unroll
   for (int q = 0; q < PU; ++q) {
-    const int e = q * R + r;
+    const int e = boff + q * R + r;
     const bool ok = ri[q] >= 0;
     L.z[e][s] = ok ? zb[q] : 0.0f;
     if (s == 0) {
-      L.v[e] = ok ? vv[q] : 0.0f;  // padding contributes 0 * l'(1, 0)
+      L.v[e] = ok ? vv[q] : 0.0f;
       L.y[e] = ok ? yb[q] : 1.0f;
     }
   }
+}
+
+// The same steps for a column of at most NQ * R entries (one or two
+// batches, staged in LDS by the first step), without workgroup barriers
+// between steps: wave v takes the slots [v B/4, (v+1) B/4), R lanes per slot
+// and NQ entries per lane (the first step's thread shape with slots and row
+// lanes swapped), sums over its R lanes with DPP moves (every lane gets the
+// same bits) and repeats until none of its slots changed or the steps run
+// out.  The loss derivative takes the fast forms above, and 1/n and 1/c
+// are formed once.
+template <int B, int R, int NQ>
+__device__ __forceinline__ void path_improve_wave(const PathArgs &a, int s, float wj, float cj,
+                                                  float lam, float *sdel, ImproveLds<B> &L) {
+  static_assert(NQ * R <= kImproveMax, "the column fits the staging");
+  constexpr int SPW = B / (kBlock / kWave);  // slots per wave
+  static_assert(SPW * R == kWave, "a wave holds SPW slots of R lanes");
   if (int(threadIdx.x) < B) {
     L.w[s] = wj;
     L.lam[s] = lam;
     if (s == 0) L.c = cj;
   }
-  __syncthreads();
+  __syncthreads();  // the staged column and the slots' scalars are in LDS
   const int lane = int(threadIdx.x) % kWave;
   const int sl = lane / R, rl = lane % R;
   const int s2 = int(threadIdx.x) / kWave * SPW + sl;
-  float v[PU], z[PU], y[PU];
+  float v[NQ], z[NQ], y[NQ];
 #pragma unroll
-  for (int q = 0; q < PU; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int e = q * R + rl;
     v[q] = L.v[e];
     z[q] = L.z[e][s2];
@@ -259,7 +269,7 @@ __device__ __forceinline__ void path_improve_wave(const PathArgs &a, int s, int 
     float acc = 0.0f;
     if (d != 0.0f) {
 #pragma unroll
-      for (int q = 0; q < PU; ++q) acc += v[q] * dloss_fast_f32(a.loss, y[q], z[q] + d * v[q]);
+      for (int q = 0; q < NQ; ++q) acc += v[q] * dloss_fast_f32(a.loss, y[q], z[q] + d * v[q]);
     }
     acc = row_group_sum<R>(acc);
     int changed = 0;
@@ -277,12 +287,29 @@ __device__ __forceinline__ void path_improve_wave(const PathArgs &a, int s, int 
   __syncthreads();
 }
 
+// The improve steps of one column, by its length: staged columns of one or
+// two batches in waves, longer ones as a workgroup.
+template <int B, int R, int PU, int NW>
+__device__ __forceinline__ void improve_column(const PathArgs &a, int64_t cb, int64_t ce, int s,
+                                               int r, float wj, float cj, float lam,
+                                               float (&sred)[NW][B], float *sdel,
+                                               ImproveLds<B> &L) {
+  const int64_t len = ce - cb;
+  if (len <= int64_t(R) * PU)
+    path_improve_wave<B, R, PU>(a, s, wj, cj, lam, sdel, L);
+  else if (len <= int64_t(kImproveMax))
+    path_improve_wave<B, R, kImproveMax / R>(a, s, wj, cj, lam, sdel, L);
+  else
+    path_improve<B, R, PU, NW>(a, cb, ce, s, r, wj, cj, lam, sred, sdel);
+}
+
 template <int B, bool IMP>
 __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
   using SH = PathShape<B>;
   constexpr int R = SH::R, PU = SH::PU, NW = SH::NW;
   __shared__ float sred[NW][B];
   __shared__ float sdel[B];
+  __shared__ std::conditional_t<IMP, ImproveLds<B>, char> simp;
   const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
   const int64_t npos = a.win_hi - a.win_lo;
   for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
@@ -323,6 +350,9 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
 #pragma unroll
       for (int q = 0; q < PU; ++q)
         if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yb[q], zb[q]);
+      if constexpr (IMP)
+        if (ce - cb <= int64_t(kImproveMax))
+          improve_stage<B, R, PU>(simp, int(base - cb), s, r, ri, vv, zb, yb);
     }
 #pragma unroll
     for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
@@ -341,13 +371,8 @@ __global__ __launch_bounds__(kBlock) void k_path_propose(PathArgs a) {
       sdel[s] = d;
     }
     __syncthreads();
-    if constexpr (IMP) {  // uniform: the whole workgroup takes the steps
-      __shared__ ImproveLds<B> simp;
-      if (ce - cb <= int64_t(R) * PU)
-        path_improve_wave<B, R, PU>(a, s, r, ri, vv, zb, yb, wj, cj, lam, sdel, simp);
-      else
-        path_improve<B, R, PU, NW>(a, cb, ce, s, r, wj, cj, lam, sred, sdel);
-    }
+    if constexpr (IMP)  // uniform: the whole workgroup takes the steps
+      improve_column<B, R, PU, NW>(a, cb, ce, s, r, wj, cj, lam, sred, sdel, simp);
     if (int(threadIdx.x) < B) {
       const float d = sdel[s];
       if (d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
@@ -415,6 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
   constexpr int R = SH::R, PU = SH::PU, NW = SH::NW;
   __shared__ float sred[NW][B];
   __shared__ float sdel[B];
+  __shared__ std::conditional_t<IMP, ImproveLds<B>, char> simp;
   const int s = int(threadIdx.x) % B, r = int(threadIdx.x) / B;
   const bool slot_lane = int(threadIdx.x) < B;
   const int64_t npos = a.win_hi - a.win_lo;
@@ -457,6 +483,9 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
         zb[q] = zh[q] + zl[q];
         if (ri[q] >= 0) acc += vv[q] * dloss_f32(a.loss, yb[q], zb[q]);
       }
+      if constexpr (IMP)
+        if (ce - cb <= int64_t(kImproveMax))
+          improve_stage<B, R, PU>(simp, int(base - cb), s, r, ri, vv, zb, yb);
     }
 #pragma unroll
     for (int off = B; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
@@ -475,13 +504,8 @@ __global__ __launch_bounds__(kBlock) void k_path_fused(PathArgs a) {
       sdel[s] = d;
     }
     __syncthreads();
-    if constexpr (IMP) {  // uniform: the whole workgroup takes the steps
-      __shared__ ImproveLds<B> simp;
-      if (one)
-        path_improve_wave<B, R, PU>(a, s, r, ri, vv, zb, yb, wj, cj, lam, sdel, simp);
-      else
-        path_improve<B, R, PU, NW>(a, cb, ce, s, r, wj, cj, lam, sred, sdel);
-    }
+    if constexpr (IMP)  // uniform: the whole workgroup takes the steps
+      improve_column<B, R, PU, NW>(a, cb, ce, s, r, wj, cj, lam, sred, sdel, simp);
     const float d = sdel[s];
     if (slot_lane && d != 0.0f) a.W[int64_t(j) * B + s] = wj + d;
     // the next position's loads go out before this column's atomics
