@@ -46,6 +46,10 @@ def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
     prof.write_text(prof.read_text() + "- schedule = 4,128,1\n")
     assert bench.measured_traffic("k_update", schedule="4,128,1") == 777.0
     assert bench.measured_traffic("k_update", schedule="8,256,0") is None
+    # kernel instances named with their options (the path's improve steps)
+    prof.write_text(prof.read_text() + "- traffic_bytes_per_launch.k_path_fused<16> improve10 = 42\n")
+    assert bench.measured_traffic("k_path_fused<16> improve10", str(prof)) == 42.0
+    assert bench.measured_traffic("k_path_fused<16>", str(prof)) is None
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda sources=None: "def")
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
