@@ -701,7 +701,8 @@ def bench_path(args):
             "bound": "hbm",
             "kernel": f"k_path_fused<{B}> (the whole epoch in one launch: every slot's gradient, "
                       f"step and scatter; 12 + 16*{B} B per nonzero + 20 + 8*{B} B per column)"
-                      + (f", up to {imp} improve-delta steps per slot and column (not counted)"
+                      + (f", up to {imp} improve-delta steps per slot and column (not counted; "
+                         f"they make the launch arithmetic-bound, so the HBM fraction understates it)"
                          if imp else ""),
             "achieved": round(bpl / us / 1e3, 3), "peak": 8000.0, "unit": "GB/s",
             "frac": round(bpl / us / 1e3 / 8000.0, 6),
