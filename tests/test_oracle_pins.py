@@ -965,3 +965,32 @@ def test_curvature_bound_is_the_largest_second_derivative(kind, beta):
                  np.array(vals, dtype=np.float64))
     np.testing.assert_allclose(O.curvature(X, kind), beta * (A ** 2).sum(axis=0) / n,
                                rtol=1e-14, atol=0)
+
+
+def test_path_optima_follow_the_envelope():
+    """The oracle's 64-lambda optima (golden file) against the mathematics of
+    the path of Eq. (1).  P*(lambda) = min_w f(w) + lambda ||w||_1 is a
+    minimum of functions affine in lambda: concave and nondecreasing, with
+    slope ||w*(lambda)||_1 (envelope theorem), so the secant slope between
+    neighbouring grid points lies between their two l1 norms, and ||w*||_1
+    does not grow with lambda.  Each stored objective may exceed the optimum
+    by at most KKT * (||w||_1 + ||w*||_1) (convexity), taken with the stored
+    norm on both sides, which widens the bracket.  At lambda_max the optimum
+    is w = 0 with the logistic objective log 2 (z = 0)."""
+    r = np.loadtxt(os.path.join(GOLDEN, "c4_path_optima.txt"), comments="#")
+    t, lam, obj, kkt, nnz, l1 = (r[:, c] for c in range(6))
+    assert np.array_equal(t, np.arange(64))
+    np.testing.assert_allclose(lam, 2.7e-4 * 1e-3 ** (t / 63), rtol=1e-14)
+    assert nnz[0] == 0 and l1[0] == 0.0
+    assert abs(obj[0] - np.log(2.0)) <= 50000 * np.finfo(float).eps
+    assert np.all(kkt <= 1e-10) and np.all(r[:, 7] == 1)
+    assert np.all(np.diff(obj) < 0) and np.all(np.diff(l1) >= 0)
+    slope = (obj[:-1] - obj[1:]) / (lam[:-1] - lam[1:])
+    err = 2.0 * kkt * l1
+    allow = (err[:-1] + err[1:]) / (lam[:-1] - lam[1:])
+    assert np.all(slope >= l1[:-1] - allow)
+    assert np.all(slope <= l1[1:] + allow)
+    # where the stored points are tight enough the bracket is strict
+    tight = allow < 1e-3 * (l1[1:] - l1[:-1])
+    assert tight.sum() >= 10
+    assert np.all((slope > l1[:-1]) & (slope < l1[1:]) | ~tight)
